@@ -1,0 +1,190 @@
+"""CPU oracle for spatially weighted local histograms (SWIH).
+
+TEST INFRASTRUCTURE ONLY -- only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the GPU path.
+
+The brute-force part (``liboracle.so``, from ``swih_oracle.c``) evaluates every
+window pixel by pixel: the convolution-style weighted histogram of Sec. 2 of the
+paper, which the paper's SWIH method reproduces exactly (Sec. 3, Sec. 5).
+``separable`` holds a second, independent route (per-bin separable
+correlation) used only to cross-check the first.
+
+Kernel kinds: 0 uniform, 1 Manhattan, 2 Euclidean (paraboloid), 3 Gaussian
+(true Gaussian with sigma = window side / 4 unless given).  See the C file's
+header for the readings of the paper these fix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN = 0, 1, 2, 3
+KIND_NAMES = {UNIFORM: "uniform", MANHATTAN: "manhattan", EUCLIDEAN: "euclidean", GAUSSIAN: "gaussian"}
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.build()
+        lib = C.CDLL(path)
+        i32, i64p, f64p, u8p, i32p = C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), \
+            C.POINTER(C.c_uint8), C.POINTER(C.c_int32)
+        lib.oracle_quantise.argtypes = [i32, i32]
+        lib.oracle_kernel_table_int.argtypes = [i32, i32, i32, i64p]
+        lib.oracle_kernel_table_gauss.argtypes = [i32, i32, C.c_double, C.c_double, f64p]
+        lib.oracle_hist_i64.argtypes = [u8p, i32, i32, i32, i32, i64p, i32, i32, i32p, i32, i64p]
+        lib.oracle_hist_f64.argtypes = [u8p, i32, i32, i32, i32, f64p, i32, i32, i32p, i32, f64p]
+        lib.oracle_bc_i64.argtypes = [u8p, i32, i32, i32, i32, i64p, i32, i32, i64p, i32p, i32, f64p]
+        lib.oracle_bc_f64.argtypes = [u8p, i32, i32, i32, i32, f64p, i32, i32, f64p, i32p, i32, f64p]
+        lib.oracle_map_i64.argtypes = [u8p, i32, i32, i32, i32, i64p, i32, i32, i64p,
+                                       i32, i32, i32, i32, f64p]
+        lib.oracle_map_f64.argtypes = [u8p, i32, i32, i32, i32, f64p, i32, i32, f64p,
+                                       i32, i32, i32, i32, f64p]
+        _lib = lib
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def set_threads(n: int | None):
+    """Limit the OpenMP threads the oracle uses (None = library default)."""
+    if n is None:
+        os.environ.pop("OMP_NUM_THREADS", None)
+    else:
+        os.environ["OMP_NUM_THREADS"] = str(int(n))
+
+
+def quantise(v, nbins: int):
+    lib = _load()
+    return lib.oracle_quantise(int(v), int(nbins))
+
+
+def default_sigma(w: int, h: int):
+    """Gaussian widths used throughout: sigma = side / 4 along each axis."""
+    return w / 4.0, h / 4.0
+
+
+def kernel_table(kind: int, w: int, h: int, sigma=None) -> np.ndarray:
+    """Spatial kernel k[dy + ry, dx + rx] (int64, or float64 for the Gaussian)."""
+    lib = _load()
+    if kind == GAUSSIAN:
+        sx, sy = sigma if sigma is not None else default_sigma(w, h)
+        out = np.empty((h, w), np.float64)
+        if lib.oracle_kernel_table_gauss(w, h, float(sx), float(sy), _p(out, C.c_double)):
+            raise ValueError("bad Gaussian window %dx%d" % (w, h))
+        return out
+    out = np.empty((h, w), np.int64)
+    if lib.oracle_kernel_table_int(int(kind), w, h, _p(out, C.c_int64)):
+        raise ValueError("bad kernel %r or window %dx%d" % (kind, w, h))
+    return out
+
+
+def mass(kind: int, w: int, h: int, sigma=None):
+    """Kernel mass S = sum of the kernel table (int for integer kernels)."""
+    t = kernel_table(kind, w, h, sigma)
+    return int(t.sum()) if t.dtype == np.int64 else float(t.sum())
+
+
+def _img(img):
+    a = np.ascontiguousarray(img, dtype=np.uint8)
+    if a.ndim != 2:
+        raise ValueError("image must be 2-D")
+    return a
+
+
+def hist(img, nbins: int, kind: int, w: int, h: int, centres, sigma=None, table=None) -> np.ndarray:
+    """Raw weighted histograms H_b at the given centres ([n, 2] of (xc, yc)).
+
+    int64 [n, nbins] for integer kernels, float64 for the Gaussian.
+    ``table`` overrides the kernel (any int64 or float64 h x w table).
+    """
+    lib = _load()
+    a = _img(img)
+    H, W = a.shape
+    c = np.ascontiguousarray(np.asarray(centres, dtype=np.int32).reshape(-1, 2))
+    tab = table if table is not None else kernel_table(kind, w, h, sigma)
+    tab = np.ascontiguousarray(tab)
+    n = c.shape[0]
+    if tab.dtype == np.int64:
+        out = np.empty((n, nbins), np.int64)
+        rc = lib.oracle_hist_i64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_int64), w, h,
+                                 _p(c, C.c_int32), n, _p(out, C.c_int64))
+    else:
+        tab = tab.astype(np.float64)
+        out = np.empty((n, nbins), np.float64)
+        rc = lib.oracle_hist_f64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_double), w, h,
+                                 _p(c, C.c_int32), n, _p(out, C.c_double))
+    if rc:
+        raise ValueError("a centre puts the window outside the image")
+    return out
+
+
+def normalised(raw, kind: int, w: int, h: int, sigma=None) -> np.ndarray:
+    """p_b = H_b / S (float64)."""
+    return np.asarray(raw, np.float64) / float(mass(kind, w, h, sigma))
+
+
+def template(img, nbins: int, kind: int, w: int, h: int, centre, sigma=None):
+    """Template histogram at ``centre``: (raw, normalised)."""
+    raw = hist(img, nbins, kind, w, h, [centre], sigma)[0]
+    return raw, normalised(raw, kind, w, h, sigma)
+
+
+def bc_at(img, nbins: int, kind: int, w: int, h: int, centres, tmpl, sigma=None) -> np.ndarray:
+    """Bhattacharyya coefficient at listed centres against template ``tmpl``.
+
+    Integer kernels take the raw integer template; the Gaussian takes the
+    normalised one.
+    """
+    lib = _load()
+    a = _img(img)
+    H, W = a.shape
+    c = np.ascontiguousarray(np.asarray(centres, dtype=np.int32).reshape(-1, 2))
+    n = c.shape[0]
+    out = np.empty(n, np.float64)
+    tab = np.ascontiguousarray(kernel_table(kind, w, h, sigma))
+    if tab.dtype == np.int64:
+        t = np.ascontiguousarray(np.asarray(tmpl, np.int64))
+        rc = lib.oracle_bc_i64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_int64), w, h,
+                               _p(t, C.c_int64), _p(c, C.c_int32), n, _p(out, C.c_double))
+    else:
+        t = np.ascontiguousarray(np.asarray(tmpl, np.float64))
+        rc = lib.oracle_bc_f64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_double), w, h,
+                               _p(t, C.c_double), _p(c, C.c_int32), n, _p(out, C.c_double))
+    if rc:
+        raise ValueError("a centre puts the window outside the image")
+    return out
+
+
+def bc_map(img, nbins: int, kind: int, w: int, h: int, tmpl, rect=None, sigma=None) -> np.ndarray:
+    """Dense likelihood map over the inclusive centre rectangle (x0, y0, x1, y1).
+
+    Defaults to every valid centre.  Returns float64 [y1 - y0 + 1, x1 - x0 + 1].
+    """
+    lib = _load()
+    a = _img(img)
+    H, W = a.shape
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    x0, y0, x1, y1 = rect if rect is not None else (rx, ry, W - 1 - rx, H - 1 - ry)
+    out = np.empty((max(0, y1 - y0 + 1), max(0, x1 - x0 + 1)), np.float64)
+    tab = np.ascontiguousarray(kernel_table(kind, w, h, sigma))
+    if tab.dtype == np.int64:
+        t = np.ascontiguousarray(np.asarray(tmpl, np.int64))
+        rc = lib.oracle_map_i64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_int64), w, h,
+                                _p(t, C.c_int64), x0, y0, x1, y1, _p(out, C.c_double))
+    else:
+        t = np.ascontiguousarray(np.asarray(tmpl, np.float64))
+        rc = lib.oracle_map_f64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_double), w, h,
+                                _p(t, C.c_double), x0, y0, x1, y1, _p(out, C.c_double))
+    if rc:
+        raise ValueError("centre rectangle outside the valid region")
+    return out

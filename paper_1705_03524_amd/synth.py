@@ -1,0 +1,199 @@
+"""Seeded synthetic inputs for the SWIH hot path.
+
+This module only draws images, regions and request streams.  It contains none
+of the method's arithmetic (no quantiser, no spatial kernel, no integral
+histogram, no similarity), so the CPU oracle and the HIP path can both be fed
+from it without sharing any computation.
+
+Every generator takes an explicit seed and uses numpy's PCG64 generator.
+
+Workload recipes (the paper's own images -- the VOT2016 frame of its Fig. 5 and
+the aerial imagery of its Fig. 7 -- are not available; these stand in for them):
+
+* ``uniform_noise``: i.i.d. uniform intensities 0..255 (the 64x64 check image).
+* ``smooth_noise``: uniform noise, blurred by a separable Gaussian FIR
+  (radius 4 sigma, mirrored border), then stretched min..max onto 0..255 and
+  rounded.  Without the stretch the blurred values crowd into a narrow band and
+  most histogram bins stay empty.
+* ``rect_scene``: ``smooth_noise`` plus axis-aligned bright (235) or dark (20)
+  rectangles with sides drawn from 20..60, the synthetic stand-in for the
+  paper's cluttered tracking scenes (Sec. 2, Fig. 3; Sec. 3, Fig. 5).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "rng",
+    "uniform_noise",
+    "smooth_noise",
+    "rect_scene",
+    "sample_centres",
+    "odd",
+    "batch_frames",
+    "serving_requests",
+]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def uniform_noise(seed: int, height: int, width: int) -> np.ndarray:
+    """i.i.d. uniform uint8 intensities in [0, 255], shape (height, width)."""
+    return rng(seed).integers(0, 256, size=(height, width), dtype=np.uint8)
+
+
+def _blur_axis(a: np.ndarray, taps: np.ndarray, axis: int) -> np.ndarray:
+    r = (len(taps) - 1) // 2
+    pad = [(0, 0), (0, 0)]
+    pad[axis] = (r, r)
+    p = np.pad(a, pad, mode="symmetric")
+    out = np.zeros_like(a)
+    n = a.shape[axis]
+    for k, t in enumerate(taps):
+        sl = [slice(None), slice(None)]
+        sl[axis] = slice(k, k + n)
+        out += t * p[tuple(sl)]
+    return out
+
+
+def smooth_noise(seed: int, height: int, width: int, sigma: float = 3.0) -> np.ndarray:
+    """Blurred uniform noise stretched onto the full 0..255 range (uint8)."""
+    g = rng(seed)
+    a = g.uniform(0.0, 256.0, size=(height, width))
+    r = int(np.ceil(4.0 * sigma))
+    t = np.arange(-r, r + 1, dtype=np.float64)
+    taps = np.exp(-0.5 * (t / sigma) ** 2)
+    taps /= taps.sum()
+    a = _blur_axis(a, taps, 1)
+    a = _blur_axis(a, taps, 0)
+    lo, hi = a.min(), a.max()
+    a = (a - lo) * (255.0 / max(hi - lo, 1e-12))
+    return np.clip(np.rint(a), 0, 255).astype(np.uint8)
+
+
+def rect_scene(seed: int, height: int, width: int, nrect: int = 6,
+               side_lo: int = 20, side_hi: int = 60, sigma: float = 3.0):
+    """Smooth noise plus ``nrect`` bright/dark rectangles drawn in order.
+
+    Returns ``(image, rects)`` with ``rects`` a list of ``(x0, y0, w, h, value)``.
+    """
+    img = smooth_noise(seed, height, width, sigma)
+    g = rng(seed + 7919)
+    rects = []
+    for _ in range(nrect):
+        rw = int(g.integers(side_lo, side_hi + 1))
+        rh = int(g.integers(side_lo, side_hi + 1))
+        x0 = int(g.integers(0, max(1, width - rw + 1)))
+        y0 = int(g.integers(0, max(1, height - rh + 1)))
+        val = 235 if g.random() < 0.5 else 20
+        img[y0:y0 + rh, x0:x0 + rw] = val
+        rects.append((x0, y0, rw, rh, val))
+    return img, rects
+
+
+def odd(n: int) -> int:
+    """Map a side length to the odd window size used for it (n -> n + 1 if even)."""
+    n = int(n)
+    return n if n % 2 == 1 else n + 1
+
+
+def sample_centres(seed: int, height: int, width: int, w: int, h: int, n: int) -> np.ndarray:
+    """``n`` seeded valid window centres (int32 [n, 2] as (xc, yc)).
+
+    The four corners of the valid region and points on its four edges are
+    always included, the rest is uniform over the valid region.
+    """
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    x_lo, x_hi, y_lo, y_hi = rx, width - 1 - rx, ry, height - 1 - ry
+    if x_hi < x_lo or y_hi < y_lo:
+        return np.zeros((0, 2), np.int32)
+    g = rng(seed)
+    fixed = [(x_lo, y_lo), (x_hi, y_lo), (x_lo, y_hi), (x_hi, y_hi)]
+    for _ in range(4):
+        fixed.append((x_lo, int(g.integers(y_lo, y_hi + 1))))
+        fixed.append((x_hi, int(g.integers(y_lo, y_hi + 1))))
+        fixed.append((int(g.integers(x_lo, x_hi + 1)), y_lo))
+        fixed.append((int(g.integers(x_lo, x_hi + 1)), y_hi))
+    rest = max(0, n - len(fixed))
+    xs = g.integers(x_lo, x_hi + 1, size=rest)
+    ys = g.integers(y_lo, y_hi + 1, size=rest)
+    pts = np.array(fixed + list(zip(xs.tolist(), ys.tolist())), dtype=np.int32)
+    return pts[:max(n, 0)] if n < len(fixed) else pts
+
+
+def batch_frames(seed: int, nframes: int = 64, w_range=(256, 1920), h_range=(256, 1080),
+                 roi_range=(1, 8), side_range=(16, 128), scale_factors=(0.8, 1.0, 1.25)):
+    """Uneven frame batch: frames of independent uniform sizes with target ROIs.
+
+    Each frame is ``smooth_noise`` content.  Each ROI is a square of side
+    ``s`` (made odd), centred uniformly so the window fits; its scales are
+    ``odd(round(s * f))`` for ``f`` in ``scale_factors`` (clipped to the frame),
+    and its search region is the 3s x 3s square around it, clipped to the
+    frame.  Returns a list of dicts with ``image`` and ``rois``; each ROI is a
+    dict with ``centre`` (x, y), ``scales`` [(w, h)], and ``search`` (x0, y0, x1, y1)
+    as an inclusive pixel rectangle.
+    """
+    g = rng(seed)
+    frames = []
+    for f in range(nframes):
+        W = int(g.integers(w_range[0], w_range[1] + 1))
+        H = int(g.integers(h_range[0], h_range[1] + 1))
+        img = smooth_noise(seed * 1000 + f + 1, H, W)
+        nroi = int(g.integers(roi_range[0], roi_range[1] + 1))
+        rois = []
+        for _ in range(nroi):
+            s = odd(int(g.integers(side_range[0], side_range[1] + 1)))
+            scales = []
+            for fac in scale_factors:
+                m = min(W, H)
+                largest_odd = m if m % 2 == 1 else m - 1
+                sw = min(odd(max(3, int(round(s * fac)))), largest_odd)
+                scales.append((sw, sw))
+            smax = max(sc[0] for sc in scales)
+            r = (smax - 1) // 2
+            cx = int(g.integers(r, W - r))
+            cy = int(g.integers(r, H - r))
+            half = (3 * s) // 2
+            search = (max(0, cx - half), max(0, cy - half), min(W - 1, cx + half), min(H - 1, cy + half))
+            rois.append({"centre": (cx, cy), "scales": scales, "search": search})
+        frames.append({"image": img, "rois": rois})
+    return frames
+
+
+FRAME_SIZES = ((640, 480), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160), (4096, 2160))
+
+
+def serving_requests(seed: int, rate: float, n: int, nstreams: int = 16,
+                     roi_range=(24, 96), search_mult=(2.0, 4.0),
+                     scale_factors=(0.8, 1.0, 1.25), sizes=FRAME_SIZES):
+    """Poisson stream of tracking requests.
+
+    Inter-arrival times are exponential with mean ``1/rate`` seconds.  Each
+    request names a stream (round-robin), a frame size drawn uniformly from
+    ``sizes``, a target ROI side (odd), its three window scales, and a search
+    region ``ROI * U[search_mult]`` centred on the target and clipped to the
+    frame.  Pixel content is drawn separately (``smooth_noise``) by the caller
+    from ``pixel_seed`` so a pool of frames can be reused.
+    """
+    g = rng(seed)
+    t = 0.0
+    reqs = []
+    for k in range(n):
+        t += float(g.exponential(1.0 / rate))
+        W, H = sizes[int(g.integers(0, len(sizes)))]
+        s = odd(int(g.integers(roi_range[0], roi_range[1] + 1)))
+        scales = [(odd(max(3, int(round(s * f)))),) * 2 for f in scale_factors]
+        smax = max(sc[0] for sc in scales)
+        mult = float(g.uniform(*search_mult))
+        side = odd(max(smax, int(round(s * mult))))
+        r = (smax - 1) // 2
+        cx = int(g.integers(r, W - r))
+        cy = int(g.integers(r, H - r))
+        half = (side - 1) // 2
+        search = (max(r, cx - half), max(r, cy - half), min(W - 1 - r, cx + half), min(H - 1 - r, cy + half))
+        reqs.append({"id": k, "t_arrive": t, "stream": k % nstreams, "frame_hw": (H, W),
+                     "centre": (cx, cy), "scales": scales, "search": search,
+                     "pixel_seed": int(g.integers(0, 2**31 - 1))})
+    return reqs
