@@ -1,0 +1,193 @@
+/*
+ * swih.h -- C ABI of the MI355X (gfx950) spatially weighted local histogram
+ * library (libswih.so).
+ *
+ * Method: "Multi-Scale Spatially Weighted Local Histograms in O(1)"
+ * (Poostchi, Shafiekhani, Palaniappan, Seetharaman), SWIH.
+ *
+ *   swih_build  -- Sec. 2.1, Eq. 2 and steps (1)-(2) of Sec. 1: quantise the
+ *                  image (Q of Eq. 2), decompose the spatial kernel into weight
+ *                  terms, and build one weighted integral histogram per
+ *                  (weight term, bin).
+ *   swih_query  -- Sec. 2.1 and steps (3)-(5) of Sec. 1: the weighted local
+ *                  histogram of a window from O(1) corner lookups translated
+ *                  from the window centre, normalised by the kernel mass.
+ *   swih_match  -- Sec. 2 (Fig. 3), Sec. 3 (Fig. 5) and Sec. 4: the
+ *                  sliding-window histogram-matching likelihood map, one value
+ *                  per window centre.  The similarity is the Bhattacharyya
+ *                  coefficient sum_b sqrt(p_b t_b).
+ *
+ * Conventions
+ *   - Image: H x W uint8, row-major with a row pitch in bytes; x = column,
+ *     y = row, 0-based.
+ *   - Quantiser: bin(v) = floor(v * nbins / 256), uniform bins over [0, 256).
+ *   - Windows are odd, w x h, rx = (w-1)/2, ry = (h-1)/2, centred on (xc, yc).
+ *     Only windows wholly inside the image are valid:
+ *     rx <= xc <= W-1-rx and ry <= yc <= H-1-ry.
+ *   - Kernels (weight at offset (dx, dy) from the centre):
+ *       SWIH_UNIFORM    1                                (plain histogram)
+ *       SWIH_MANHATTAN  (rx+ry+1) - |dx| - |dy|          (Eq. 1, Fig. 4b)
+ *       SWIH_EUCLIDEAN  (rx^2+ry^2+1) - dx^2 - dy^2      (Fig. 1b, paraboloid)
+ *       SWIH_GAUSSIAN   exp(-dx^2/(2 sx^2) - dy^2/(2 sy^2)), sx = w/4,
+ *                       sy = h/4 (Fig. 1c), evaluated through a K-term cosine
+ *                       series per axis (see swih_gauss_terms).
+ *     The first three are exact: raw histograms are integers, computed modulo
+ *     2^32 and exact whenever the true value is below 2^32.
+ *   - Normalised histogram p_b = H_b / S, with S the kernel mass (the same at
+ *     every location, Sec. 2.1).
+ *
+ * Memory and streams
+ *   - Every pointer named d_* is a device pointer owned by the caller; the
+ *     library never allocates, frees or keeps device memory between calls.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued asynchronously on it; no call synchronises
+ *     the device or reads device memory on the host.
+ *   - The workspace written by swih_build is read by swih_query/swih_match;
+ *     the caller must pass the same configuration and image size to all three,
+ *     and must order them on streams.
+ *
+ * Errors
+ *   - Every entry point returns an int status: SWIH_OK (0) or a negative code.
+ *     Arguments are checked on the host before anything is enqueued; nothing
+ *     is enqueued on error.  Device faults surface at the caller's next
+ *     synchronisation of the stream.
+ */
+#ifndef SWIH_H_
+#define SWIH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWIH_OK 0
+#define SWIH_ERR_INVALID (-1)     /* bad size, window, bin count, rectangle or NULL */
+#define SWIH_ERR_WORKSPACE (-2)   /* workspace smaller than swih_workspace_bytes */
+#define SWIH_ERR_UNSUPPORTED (-3) /* valid request this kernel cannot serve */
+#define SWIH_ERR_HIP (-4)         /* a HIP launch or runtime call failed */
+
+typedef enum {
+  SWIH_UNIFORM = 0,
+  SWIH_MANHATTAN = 1,
+  SWIH_EUCLIDEAN = 2,
+  SWIH_GAUSSIAN = 3
+} swih_kernel;
+
+/* One window scale: odd width and height, 1 <= w <= W, 1 <= h <= H. */
+typedef struct {
+  int32_t w, h;
+} swih_scale;
+
+typedef struct {
+  int32_t nbins;            /* 1..256 */
+  int32_t kernel;           /* swih_kernel */
+  int32_t nscales;          /* >= 1 */
+  const swih_scale* scales; /* host array of nscales entries */
+  int32_t gauss_terms;      /* K of the cosine series, 1..8; 0 = default (4) */
+  uint32_t flags;           /* reserved, must be 0 */
+} swih_config;
+
+/* Inclusive rectangle of window CENTRES. */
+typedef struct {
+  int32_t x0, y0, x1, y1;
+} swih_rect;
+
+/*
+ * Bytes of device workspace a build of an H x W image needs under `cfg`.
+ * Integer kernels keep one set of planes for every scale; the Gaussian keeps
+ * one set per scale (its weight terms depend on the window size, Sec. 2.1
+ * "multi-scale").  Returns the size (> 0), or a negative status.
+ */
+int64_t swih_workspace_bytes(const swih_config* cfg, int32_t height, int32_t width);
+
+/*
+ * Build the weighted integral histograms (Eq. 2) of the image into d_ws.
+ *   d_img   device, height rows of `pitch` bytes, width <= pitch.
+ *   d_ws    device workspace of at least swih_workspace_bytes(cfg, H, W) bytes,
+ *           256-byte aligned; its previous contents are irrelevant.
+ * Errors: SWIH_ERR_INVALID (cfg, sizes, NULL), SWIH_ERR_WORKSPACE, SWIH_ERR_HIP.
+ */
+int swih_build(const swih_config* cfg, const uint8_t* d_img, int32_t height, int32_t width,
+               int32_t pitch, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * The build in two phases, for callers that schedule or time them apart.
+ * swih_build is swih_build_carries followed by swih_build_planes for every
+ * plane set.
+ *   swih_build_carries  reads the image and computes the carries every tile
+ *                       needs: the integral-histogram row above each band, the
+ *                       row prefix left of each tile and the value at each tile
+ *                       origin (plus, for the Gaussian, the weight-term tables
+ *                       of the scale).  Several kernel launches, small output.
+ *   swih_build_planes   writes the planes of one set from the image and those
+ *                       carries: exactly one kernel launch.
+ *   set     0 for integer kernels; the scale index for the Gaussian, whose
+ *           planes are per scale.
+ * The carries live in a scratch region shared by all sets, so a set's planes
+ * must follow its own carries on the stream with no other set's carries in
+ * between.  Errors as swih_build, plus SWIH_ERR_INVALID for a bad set.
+ */
+int swih_build_carries(const swih_config* cfg, const uint8_t* d_img, int32_t height,
+                       int32_t width, int32_t pitch, int32_t set, void* d_ws, size_t ws_bytes,
+                       void* stream);
+int swih_build_planes(const swih_config* cfg, const uint8_t* d_img, int32_t height,
+                      int32_t width, int32_t pitch, int32_t set, void* d_ws, size_t ws_bytes,
+                      void* stream);
+
+/*
+ * Weighted local histograms at n window centres of scale `scale_idx`.
+ *   d_centres   device int32 [n][2] = (xc, yc); every centre must be valid for
+ *               the scale (a host check is not possible; out-of-range centres
+ *               are clamped on the device and give unspecified histograms).
+ *   d_hist      device float [n][nbins], p_b = H_b / S; may be NULL.
+ *   d_hist_raw  device uint32 [n][nbins], exact H_b; integer kernels only
+ *               (SWIH_ERR_UNSUPPORTED for the Gaussian); may be NULL.
+ * n == 0 is valid and enqueues nothing.
+ */
+int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+               int32_t width, int32_t scale_idx, const int32_t* d_centres, int32_t n,
+               float* d_hist, uint32_t* d_hist_raw, void* stream);
+
+/*
+ * Likelihood map: Bhattacharyya coefficient of every window centre in
+ * `centres` (inclusive, must lie in the valid range of the scale) against a
+ * template histogram of the same scale.
+ *   d_template      device float [nbins], normalised template t_b; or NULL.
+ *   d_template_raw  device uint32 [nbins], exact template T_b (integer kernels
+ *                   only); or NULL.  Exactly one of the two must be given.
+ *                   With the raw template the value is
+ *                   (sum_b sqrt(H_b T_b)) / S evaluated in double with bins in
+ *                   order 0..nbins-1, then rounded to float.
+ *   d_map           device float [(y1-y0+1)][(x1-x0+1)], row-major.
+ * An empty rectangle (x1 < x0 or y1 < y0) is valid and enqueues nothing.
+ */
+int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+               int32_t width, int32_t scale_idx, const float* d_template,
+               const uint32_t* d_template_raw, swih_rect centres, float* d_map, void* stream);
+
+/*
+ * The cosine series that stands in for one axis of the Gaussian kernel:
+ *   g(t) ~= sum_{k=0..K} a_k cos(2 pi k t / P),  t in [-r, r], r = (n-1)/2,
+ * least-squares fitted to exp(-t^2 / (2 (n/4)^2)) at the integer offsets,
+ * with the integer period P >= n chosen to minimise the worst normalised
+ * 2-D histogram error of the separable product.  Each cosine term splits into
+ * cos/sin products of the absolute coordinates and the window centre, which is
+ * what makes the Gaussian decomposable into 2K+1 weight terms per axis.
+ *   n      odd window side, 1..4095
+ *   K      1..8
+ *   a_out  host double [K+1] (may be NULL); period_out host int32 (may be NULL)
+ *   err_out host double: the worst normalised histogram error of the square
+ *          n x n window with this series (may be NULL)
+ */
+int swih_gauss_terms(int32_t n, int32_t K, double* a_out, int32_t* period_out, double* err_out);
+
+/* Static text for a status code. */
+const char* swih_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWIH_H_ */

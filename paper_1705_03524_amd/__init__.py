@@ -1,0 +1,18 @@
+"""MI355X-native spatially weighted local histograms (SWIH) in O(1).
+
+HIP kernels for gfx950 behind the C ABI declared in ``include/swih.h``
+(libswih.so); this package is its Python binding.
+"""
+from ._swih import (EUCLIDEAN, GAUSSIAN, KERNELS, MANHATTAN, UNIFORM, Config, SwihError,
+                    build, build_phase, gauss_terms, load, match, query, status_string, workspace_bytes)
+
+__all__ = ["Config", "SwihError", "build", "build_phase", "query", "match", "workspace_bytes", "gauss_terms",
+           "load", "status_string", "UNIFORM", "MANHATTAN", "EUCLIDEAN", "GAUSSIAN", "KERNELS",
+           "Plan"]
+
+
+def __getattr__(name):
+    if name == "Plan":
+        from .plan import Plan
+        return Plan
+    raise AttributeError(name)

@@ -1,0 +1,182 @@
+"""ctypes binding of libswih.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels.  PyTorch is used
+for device buffers (``tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing or the GPU is absent the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libswih.so")
+
+UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN = 0, 1, 2, 3
+KERNELS = {"uniform": UNIFORM, "manhattan": MANHATTAN, "euclidean": EUCLIDEAN, "gaussian": GAUSSIAN}
+
+OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
+
+EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_build_planes",
+            "swih_query", "swih_match", "swih_gauss_terms", "swih_status_string")
+
+
+class SwihError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, status_string(status), status))
+        self.status = status
+
+
+class _Scale(C.Structure):
+    _fields_ = [("w", C.c_int32), ("h", C.c_int32)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("nbins", C.c_int32), ("kernel", C.c_int32), ("nscales", C.c_int32),
+                ("scales", C.POINTER(_Scale)), ("gauss_terms", C.c_int32), ("flags", C.c_uint32)]
+
+
+class _Rect(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libswih.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libswih.so not built: run `python -m paper_1705_03524_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    cfgp = C.POINTER(_Config)
+    lib.swih_workspace_bytes.argtypes = [cfgp, i32, i32]
+    lib.swih_workspace_bytes.restype = C.c_int64
+    lib.swih_build.argtypes = [cfgp, vp, i32, i32, i32, vp, sz, vp]
+    lib.swih_build.restype = C.c_int
+    for name in ("swih_build_carries", "swih_build_planes"):
+        f = getattr(lib, name)
+        f.argtypes = [cfgp, vp, i32, i32, i32, i32, vp, sz, vp]
+        f.restype = C.c_int
+    lib.swih_query.argtypes = [cfgp, vp, sz, i32, i32, i32, vp, i32, vp, vp, vp]
+    lib.swih_query.restype = C.c_int
+    lib.swih_match.argtypes = [cfgp, vp, sz, i32, i32, i32, vp, vp, _Rect, vp, vp]
+    lib.swih_match.restype = C.c_int
+    lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double)]
+    lib.swih_gauss_terms.restype = C.c_int
+    lib.swih_status_string.argtypes = [C.c_int]
+    lib.swih_status_string.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().swih_status_string(int(status)).decode()
+
+
+@dataclass
+class Config:
+    """Python mirror of ``swih_config``."""
+    nbins: int
+    kernel: int
+    scales: Sequence[tuple] = ((15, 15),)
+    gauss_terms: int = 0
+    flags: int = 0
+    _c: _Config = field(default=None, init=False, repr=False)
+    _arr: object = field(default=None, init=False, repr=False)
+
+    def __post_init__(self):
+        if isinstance(self.kernel, str):
+            self.kernel = KERNELS[self.kernel]
+        self.scales = tuple((int(w), int(h)) for w, h in self.scales)
+
+    def c(self) -> _Config:
+        arr = (_Scale * max(1, len(self.scales)))(*[_Scale(w, h) for w, h in self.scales])
+        self._arr = arr
+        self._c = _Config(int(self.nbins), int(self.kernel), len(self.scales),
+                          C.cast(arr, C.POINTER(_Scale)), int(self.gauss_terms), int(self.flags))
+        return self._c
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def workspace_bytes(cfg: Config, height: int, width: int) -> int:
+    n = load().swih_workspace_bytes(C.byref(cfg.c()), int(height), int(width))
+    if n < 0:
+        raise SwihError(int(n), "swih_workspace_bytes")
+    return int(n)
+
+
+def build(cfg: Config, img, ws, height=None, width=None, pitch=None, stream=None):
+    """swih_build on a uint8 device tensor ``img`` (rows x pitch) into ``ws`` (uint8)."""
+    H = int(height if height is not None else img.shape[0])
+    W = int(width if width is not None else img.shape[1])
+    P = int(pitch if pitch is not None else img.stride(0))
+    st = load().swih_build(C.byref(cfg.c()), _ptr(img), H, W, P, _ptr(ws), ws.numel() * ws.element_size(),
+                           _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_build")
+
+
+def build_phase(cfg: Config, img, ws, phase: str, set_idx: int = 0, height=None, width=None,
+                pitch=None, stream=None):
+    """One build phase: ``phase`` = "carries" or "planes" (see swih_build_carries)."""
+    H = int(height if height is not None else img.shape[0])
+    W = int(width if width is not None else img.shape[1])
+    P = int(pitch if pitch is not None else img.stride(0))
+    fn = {"carries": load().swih_build_carries, "planes": load().swih_build_planes}[phase]
+    st = fn(C.byref(cfg.c()), _ptr(img), H, W, P, int(set_idx), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_build_" + phase)
+
+
+def query(cfg: Config, ws, height: int, width: int, scale_idx: int, centres, hist=None,
+          hist_raw=None, stream=None):
+    """swih_query at int32 [n, 2] device ``centres``."""
+    n = int(centres.shape[0]) if centres is not None else 0
+    st = load().swih_query(C.byref(cfg.c()), _ptr(ws), ws.numel() * ws.element_size(), int(height),
+                           int(width), int(scale_idx), _ptr(centres), n, _ptr(hist), _ptr(hist_raw),
+                           _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_query")
+
+
+def match(cfg: Config, ws, height: int, width: int, scale_idx: int, rect, out, template=None,
+          template_raw=None, stream=None):
+    """swih_match over the inclusive centre rectangle ``rect`` = (x0, y0, x1, y1)."""
+    r = _Rect(*[int(v) for v in rect])
+    st = load().swih_match(C.byref(cfg.c()), _ptr(ws), ws.numel() * ws.element_size(), int(height),
+                           int(width), int(scale_idx), _ptr(template), _ptr(template_raw), r,
+                           _ptr(out), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_match")
+
+
+def gauss_terms(n: int, K: int = 4):
+    """(coefficients a_0..a_K, period P, worst normalised 2-D error) of the series."""
+    a = (C.c_double * (K + 1))()
+    P = C.c_int32()
+    e = C.c_double()
+    st = load().swih_gauss_terms(int(n), int(K), a, C.byref(P), C.byref(e))
+    if st != OK:
+        raise SwihError(st, "swih_gauss_terms")
+    return list(a), int(P.value), float(e.value)

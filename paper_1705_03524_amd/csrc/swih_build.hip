@@ -1,0 +1,487 @@
+// Weighted integral histogram build for gfx950 (Sec. 2.1, Eq. 2).
+//
+// One plane per (weight term p = (i, j), bin b):
+//   P[Y][X] = sum_{x < X, y < Y} [Q(f(x, y)) = b] u_i(x) v_j(y).
+// Every u_i v_j product is a weight image w_dir of Eq. 2; the window-centre
+// translation of Sec. 2.1 is applied later, at query time, through per-centre
+// coefficients (see swih_query.hip).
+//
+// The 2-D prefix is computed in three launches over a grid of 64-column tiles
+// (one wave64 lane per pixel column) and TY-row bands:
+//   1. aggregate: per (band, tile, bin) wave, the band's column sums
+//      z_j(x) = sum_y v_j(y) m(x, y), the row-segment sums
+//      T_i(y, tile) = sum_x u_i(x) m(x, y), and each plane's tile total.
+//   2. scan: exclusive prefix of z over bands (the carry row above a band),
+//      of T over tiles (the carry column left of a tile), and a 2-D exclusive
+//      prefix of the tile totals (the value at each tile's origin corner).
+//   3. emit: per (band, tile, bin[, i]) wave, rows top to bottom: a wave64 DPP
+//      inclusive scan of u_i m gives the row prefix inside the tile, the carries
+//      complete it, and v_j(y) times it accumulates into each plane's column
+//      running sum, stored once per element with coalesced 256-byte rows.
+// Integer kernels accumulate modulo 2^32.  The Gaussian runs its horizontal
+// scans in int32 fixed point (exact), accumulates in double, and stores each
+// tile relative to its own origin (float) with double carries.
+#include "swih_internal.h"
+#include "wave64.h"
+
+namespace swih {
+namespace {
+
+constexpr int WG = 256;
+constexpr int WPB = WG / 64;  // waves per block
+
+// Integer kernels' weight terms: plane p -> (i, j) with u/v in {1, t, t^2}.
+template <int KIND> struct IntTerms;
+template <> struct IntTerms<0> { static constexpr int nI = 1, nJ = 1, nP = 1; };
+template <> struct IntTerms<1> { static constexpr int nI = 2, nJ = 2, nP = 3; };
+template <> struct IntTerms<2> { static constexpr int nI = 3, nJ = 3, nP = 5; };
+__host__ __device__ constexpr int plane_i(int p) { return p == 1 ? 1 : (p == 3 ? 2 : 0); }
+__host__ __device__ constexpr int plane_j(int p) { return p == 2 ? 1 : (p == 4 ? 2 : 0); }
+__device__ __forceinline__ uint32_t poly_term(int i, uint32_t t) {
+  return i == 0 ? 1u : (i == 1 ? t : t * t);
+}
+
+__device__ __forceinline__ bool in_bin(uint32_t v, int B, int b) {
+  return ((v * (uint32_t)B) >> 8) == (uint32_t)b;
+}
+
+struct WaveTile {
+  int b, tx, ty, x, y0, nrows;
+  bool valid;
+};
+
+__device__ __forceinline__ bool wave_tile(const SwihGeom& g, long wid, int extra, WaveTile& t,
+                                          int& e) {
+  const long nw = (long)g.NTY * g.NTX * g.B * extra;
+  if (wid >= nw) return false;
+  e = (int)(wid % extra);
+  long r = wid / extra;
+  t.b = (int)(r % g.B);
+  r /= g.B;
+  t.tx = (int)(r % g.NTX);
+  t.ty = (int)(r / g.NTX);
+  t.x = t.tx * SWIH_TX + lane_id();
+  t.valid = t.x < g.W;
+  t.y0 = t.ty * g.TY;
+  t.nrows = min(g.TY, g.H - t.y0);
+  return true;
+}
+
+__device__ __forceinline__ long wave_index() {
+  return (long)blockIdx.x * WPB + (long)(threadIdx.x >> 6);
+}
+
+// ---------------------------------------------------------------- integer kernels
+template <int KIND>
+__global__ __launch_bounds__(WG) void k_aggregate_int(const uint8_t* __restrict__ img,
+                                                      int ipitch, SwihGeom g,
+                                                      uint32_t* __restrict__ z,
+                                                      uint32_t* __restrict__ T,
+                                                      uint32_t* __restrict__ BT) {
+  using TT = IntTerms<KIND>;
+  WaveTile t;
+  int e;
+  if (!wave_tile(g, wave_index(), 1, t, e)) return;
+  const int lane = lane_id();
+  const int NXP = g.NTX * SWIH_TX;
+  uint32_t zacc[TT::nJ], treg[TT::nI], u[TT::nI];
+#pragma unroll
+  for (int j = 0; j < TT::nJ; ++j) zacc[j] = 0;
+#pragma unroll
+  for (int i = 0; i < TT::nI; ++i) {
+    treg[i] = 0;
+    u[i] = poly_term(i, (uint32_t)t.x);
+  }
+  const uint8_t* col = img + (t.valid ? t.x : 0);
+  for (int k = 0; k < t.nrows; ++k) {
+    const uint32_t y = (uint32_t)(t.y0 + k);
+    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
+    const uint32_t m = (t.valid && in_bin(v, g.B, t.b)) ? 1u : 0u;
+#pragma unroll
+    for (int j = 0; j < TT::nJ; ++j) zacc[j] += m * poly_term(j, y);
+#pragma unroll
+    for (int i = 0; i < TT::nI; ++i) {
+      const uint32_t s = wave_sum(m * u[i]);
+      treg[i] = put_lane(treg[i], s, k);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TT::nJ; ++j)
+    z[((size_t)(j * g.B + t.b) * g.NTY + t.ty) * NXP + t.x] = zacc[j];
+  if (lane < t.nrows) {
+#pragma unroll
+    for (int i = 0; i < TT::nI; ++i)
+      T[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] = treg[i];
+  }
+  const uint32_t yl = (uint32_t)(t.y0 + lane);
+#pragma unroll
+  for (int p = 0; p < TT::nP; ++p) {
+    const uint32_t val = lane < t.nrows ? poly_term(plane_j(p), yl) * treg[plane_i(p)] : 0u;
+    const uint32_t s = wave_sum(val);
+    if (lane == 0) BT[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] = s;
+  }
+}
+
+// Exclusive prefixes of the aggregates (all three roles in one launch).
+template <typename ZT, typename TTy, typename BTy>
+__global__ __launch_bounds__(WG) void k_scan(SwihGeom g, ZT* __restrict__ z,
+                                             TTy* __restrict__ T, BTy* __restrict__ BT) {
+  long t = (long)blockIdx.x * WG + threadIdx.x;
+  const int NXP = g.NTX * SWIH_TX;
+  const long n1 = (long)g.nJ * g.B * NXP;
+  const long n2 = (long)g.nI * g.B * g.H;
+  const long n3 = (long)g.nP * g.B;
+  if (t < n1) {  // carry row above each band: exclusive over bands
+    const long col = t % NXP, jb = t / NXP;
+    ZT* base = z + (size_t)jb * g.NTY * NXP + col;
+    ZT run = 0;
+    for (int ty = 0; ty < g.NTY; ++ty) {
+      const ZT v = base[(size_t)ty * NXP];
+      base[(size_t)ty * NXP] = run;
+      run += v;
+    }
+    return;
+  }
+  t -= n1;
+  if (t < n2) {  // carry column left of each tile: exclusive over tiles
+    const long y = t % g.H, ib = t / g.H;
+    TTy* base = T + (size_t)ib * g.NTX * g.H + y;
+    TTy run = 0;
+    for (int tx = 0; tx < g.NTX; ++tx) {
+      const TTy v = base[(size_t)tx * g.H];
+      base[(size_t)tx * g.H] = run;
+      run += v;
+    }
+    return;
+  }
+  t -= n2;
+  if (t < n3) {  // value at each tile's origin corner: 2-D exclusive prefix
+    BTy* base = BT + (size_t)t * g.NTY * g.NTX;
+    for (int tx = 0; tx < g.NTX; ++tx) {
+      BTy run = 0;
+      for (int ty = 0; ty < g.NTY; ++ty) {
+        const BTy v = base[(size_t)ty * g.NTX + tx];
+        base[(size_t)ty * g.NTX + tx] = run;
+        run += v;
+      }
+    }
+    for (int ty = 0; ty < g.NTY; ++ty) {
+      BTy run = 0;
+      for (int tx = 0; tx < g.NTX; ++tx) {
+        const BTy v = base[(size_t)ty * g.NTX + tx];
+        base[(size_t)ty * g.NTX + tx] = run;
+        run += v;
+      }
+    }
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img, int ipitch,
+                                                 SwihGeom g, uint32_t* __restrict__ planes,
+                                                 const uint32_t* __restrict__ zc,
+                                                 const uint32_t* __restrict__ E,
+                                                 const uint32_t* __restrict__ CTc) {
+  using TT = IntTerms<KIND>;
+  WaveTile t;
+  int e;
+  if (!wave_tile(g, wave_index(), 1, t, e)) return;
+  const int lane = lane_id();
+  const int NXP = g.NTX * SWIH_TX;
+  uint32_t u[TT::nI], ereg[TT::nI], acc[TT::nP];
+  size_t pbase[TT::nP];
+#pragma unroll
+  for (int i = 0; i < TT::nI; ++i) {
+    u[i] = poly_term(i, (uint32_t)t.x);
+    ereg[i] = lane < t.nrows ? E[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane]
+                             : 0u;
+  }
+  // carry row: P[y0][x + 1] = tile-origin value + prefix of u_i * (column sums above)
+#pragma unroll
+  for (int p = 0; p < TT::nP; ++p) {
+    const uint32_t zv = zc[((size_t)(plane_j(p) * g.B + t.b) * g.NTY + t.ty) * NXP + t.x];
+    acc[p] = CTc[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] +
+             wave_incl_scan(u[plane_i(p)] * zv);
+    pbase[p] = (size_t)(p * g.B + t.b) * g.plane_elems + 64 + t.x;
+  }
+  if (t.ty == 0) {
+#pragma unroll
+    for (int p = 0; p < TT::nP; ++p) {
+      if (t.valid) planes[pbase[p]] = 0u;
+      if (t.tx == 0 && lane == 0) planes[pbase[p] - 1] = 0u;
+    }
+  }
+  const uint8_t* col = img + (t.valid ? t.x : 0);
+  for (int k = 0; k < t.nrows; ++k) {
+    const uint32_t y = (uint32_t)(t.y0 + k);
+    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
+    const uint32_t m = (t.valid && in_bin(v, g.B, t.b)) ? 1u : 0u;
+    uint32_t s[TT::nI];
+#pragma unroll
+    for (int i = 0; i < TT::nI; ++i) s[i] = wave_incl_scan(m * u[i]) + readlane(ereg[i], k);
+#pragma unroll
+    for (int p = 0; p < TT::nP; ++p) acc[p] += poly_term(plane_j(p), y) * s[plane_i(p)];
+    if (t.valid) {
+      const size_t row = (size_t)(y + 1) * g.pitch;
+#pragma unroll
+      for (int p = 0; p < TT::nP; ++p) planes[pbase[p] + row] = acc[p];
+    }
+  }
+  if (t.tx == 0 && lane < t.nrows) {
+#pragma unroll
+    for (int p = 0; p < TT::nP; ++p)
+      planes[(size_t)(p * g.B + t.b) * g.plane_elems + (size_t)(t.y0 + 1 + lane) * g.pitch + 63] =
+          0u;
+  }
+}
+
+// ---------------------------------------------------------------- Gaussian
+// Fixed-point weight terms: uq[i][x] (x < NTX*64, zero beyond W), vq[y][j],
+// and vqd[y][j] = vq * 2^-48 as double (scales the u*v product to real units).
+__global__ __launch_bounds__(WG) void k_basis(SwihGeom g, GaussAxis ax, GaussAxis ay,
+                                              int32_t* __restrict__ uq, int32_t* __restrict__ vq,
+                                              double* __restrict__ vqd) {
+  const long t = (long)blockIdx.x * WG + threadIdx.x;
+  const int NXP = g.NTX * SWIH_TX;
+  const long nu = (long)g.nI * NXP, nv = (long)g.nJ * g.H;
+  const double fix = (double)(1 << SWIH_FIX_BITS);
+  if (t < nu) {
+    const int i = (int)(t / NXP), x = (int)(t % NXP);
+    double val = 0.0;
+    if (x < g.W) {
+      if (i == 0) {
+        val = 1.0;
+      } else {
+        const int k = (i + 1) / 2;
+        const long ph = ((long)k * x) % ax.P;
+        const double ang = 2.0 * M_PI * (double)ph / (double)ax.P;
+        val = (i & 1) ? cos(ang) : sin(ang);
+      }
+    }
+    uq[(size_t)i * NXP + x] = (int32_t)rint(val * fix);
+  } else if (t < nu + nv) {
+    const long r = t - nu;
+    const int y = (int)(r / g.nJ), j = (int)(r % g.nJ);
+    double val;
+    if (j == 0) {
+      val = 1.0;
+    } else {
+      const int k = (j + 1) / 2;
+      const long ph = ((long)k * y) % ay.P;
+      const double ang = 2.0 * M_PI * (double)ph / (double)ay.P;
+      val = (j & 1) ? cos(ang) : sin(ang);
+    }
+    const int32_t q = (int32_t)rint(val * fix);
+    vq[(size_t)y * g.nJ + j] = q;
+    vqd[(size_t)y * g.nJ + j] = ldexp((double)q, -2 * SWIH_FIX_BITS);
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restrict__ img,
+                                                        int ipitch, SwihGeom g,
+                                                        const int32_t* __restrict__ uq,
+                                                        const int32_t* __restrict__ vq,
+                                                        int64_t* __restrict__ z,
+                                                        int64_t* __restrict__ T,
+                                                        double* __restrict__ BT) {
+  WaveTile t;
+  int e;
+  if (!wave_tile(g, wave_index(), 1, t, e)) return;
+  const int lane = lane_id();
+  const int NXP = g.NTX * SWIH_TX;
+  int32_t uqx[NT], zacc[NT], treg[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    uqx[i] = uq[(size_t)i * NXP + t.x];
+    zacc[i] = 0;
+    treg[i] = 0;
+  }
+  const uint8_t* col = img + (t.valid ? t.x : 0);
+  for (int k = 0; k < t.nrows; ++k) {
+    const int y = t.y0 + k;
+    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
+    const bool m = t.valid && in_bin(v, g.B, t.b);
+    const int32_t* vrow = vq + (size_t)y * NT;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) zacc[j] += m ? vrow[j] : 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int32_t s = wave_sum(m ? uqx[i] : 0);
+      treg[i] = put_lane(treg[i], s, k);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NT; ++j)
+    z[((size_t)(j * g.B + t.b) * g.NTY + t.ty) * NXP + t.x] = (int64_t)zacc[j];
+  if (lane < t.nrows) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+      T[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] = (int64_t)treg[i];
+  }
+  // tile totals of every plane: sum over the band's rows of v_j(y) T_i(y), exact in int64
+  const int yl = t.y0 + (lane < t.nrows ? lane : 0);
+  for (int j = 0; j < NT; ++j) {
+    const int64_t vj = lane < t.nrows ? (int64_t)vq[(size_t)yl * NT + j] : 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int64_t s = wave_sum(vj * (int64_t)treg[i]);
+      if (lane == 0)
+        BT[((size_t)((i * NT + j) * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] = (double)s;
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ img, int ipitch,
+                                                   SwihGeom g, const int32_t* __restrict__ uq,
+                                                   const int32_t* __restrict__ vq,
+                                                   const double* __restrict__ vqd,
+                                                   const int64_t* __restrict__ zc,
+                                                   const int64_t* __restrict__ E,
+                                                   const double* __restrict__ CTc,
+                                                   float* __restrict__ Lp,
+                                                   double* __restrict__ Kp,
+                                                   double* __restrict__ RCp) {
+  WaveTile t;
+  int i;
+  if (!wave_tile(g, wave_index(), NT, t, i)) return;
+  const int lane = lane_id();
+  const int NXP = g.NTX * SWIH_TX;
+  const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
+  const int32_t uqi = uq[(size_t)i * NXP + t.x];
+  const int64_t ereg =
+      lane < t.nrows ? E[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] : 0;
+  size_t lbase[NT];
+  double L[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int p = i * NT + j;
+    const size_t pb = (size_t)(p * g.B + t.b);
+    lbase[j] = pb * g.plane_elems + 64 + t.x;
+    L[j] = 0.0;
+    // carry row relative to the tile origin: K[ty][x + 1] = P[y0][x + 1] - P[y0][Xo]
+    const double zv = (double)zc[((size_t)(j * g.B + t.b) * g.NTY + t.ty) * NXP + t.x];
+    const double kv = wave_incl_scan((double)uqi * zv) * sc48;
+    double* krow = Kp + (pb * g.NTY + t.ty) * (size_t)g.pitch;
+    if (t.valid) krow[64 + t.x] = kv;
+    if (t.tx == 0 && lane == 0) krow[63] = 0.0;
+    if (t.ty == 0) {
+      if (t.valid) Lp[lbase[j]] = 0.0f;
+      if (t.tx == 0 && lane == 0) Lp[lbase[j] - 1] = 0.0f;
+      if (lane == 0) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1)] = 0.0;
+    }
+  }
+  const uint8_t* col = img + (t.valid ? t.x : 0);
+  for (int k = 0; k < t.nrows; ++k) {
+    const int y = t.y0 + k;
+    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
+    const bool m = t.valid && in_bin(v, g.B, t.b);
+    const double R = (double)wave_incl_scan(m ? uqi : 0);
+    const double* vrow = vqd + (size_t)y * NT;
+    const size_t row = (size_t)(y + 1) * g.pitch;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      L[j] = fma(vrow[j], R, L[j]);
+      if (t.valid) Lp[lbase[j] + row] = (float)L[j];
+    }
+  }
+  // row carries at the tile origin column: RC[tx][y + 1] = P[y + 1][Xo], one lane per row
+  const int yl = t.y0 + (lane < t.nrows ? lane : 0);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int p = i * NT + j;
+    const size_t pb = (size_t)(p * g.B + t.b);
+    const double term = lane < t.nrows ? (double)vq[(size_t)yl * NT + j] * (double)ereg : 0.0;
+    const double rc =
+        (CTc[(pb * g.NTY + t.ty) * g.NTX + t.tx] + wave_incl_scan(term)) * sc48;
+    if (lane < t.nrows) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1) + t.y0 + 1 + lane] = rc;
+    if (t.tx == 0 && lane < t.nrows)
+      Lp[pb * g.plane_elems + (size_t)(t.y0 + 1 + lane) * g.pitch + 63] = 0.0f;
+  }
+}
+
+inline unsigned blocks_for_waves(long waves) { return (unsigned)((waves + WPB - 1) / WPB); }
+inline unsigned blocks_for_threads(long n) { return (unsigned)((n + WG - 1) / WG); }
+
+template <int KIND>
+hipError_t build_int(const SwihLayout& L, const uint8_t* img, int ipitch, char* ws,
+                     hipStream_t s, int phases) {
+  const SwihGeom& g = L.g;
+  uint32_t* planes = (uint32_t*)(ws + L.off_planes);
+  uint32_t* z = (uint32_t*)(ws + L.off_z);
+  uint32_t* T = (uint32_t*)(ws + L.off_T);
+  uint32_t* BT = (uint32_t*)(ws + L.off_CT);
+  const long waves = (long)g.NTY * g.NTX * g.B;
+  if (phases & 1) {
+    hipLaunchKernelGGL(k_aggregate_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
+                       ipitch, g, z, T, BT);
+    const long nscan = (long)g.nJ * g.B * g.NTX * SWIH_TX + (long)g.nI * g.B * g.H +
+                       (long)g.nP * g.B;
+    hipLaunchKernelGGL((k_scan<uint32_t, uint32_t, uint32_t>), dim3(blocks_for_threads(nscan)),
+                       dim3(WG), 0, s, g, z, T, BT);
+  }
+  if (phases & 2)
+    hipLaunchKernelGGL(k_emit_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
+                       ipitch, g, planes, z, T, BT);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t build_gauss(const SwihLayout& L, int set, const GaussAxis& ax, const GaussAxis& ay,
+                       const uint8_t* img, int ipitch, char* ws, hipStream_t s, int phases) {
+  const SwihGeom& g = L.g;
+  char* sb = ws + (size_t)set * L.set_bytes;
+  float* Lp = (float*)(sb + L.off_planes);
+  double* Kp = (double*)(sb + L.off_K);
+  double* RCp = (double*)(sb + L.off_RC);
+  int32_t* uq = (int32_t*)(sb + L.off_uq);
+  int32_t* vq = (int32_t*)(sb + L.off_vq);
+  double* vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
+  int64_t* z = (int64_t*)(ws + L.off_z);
+  int64_t* T = (int64_t*)(ws + L.off_T);
+  double* BT = (double*)(ws + L.off_CT);
+  const long waves = (long)g.NTY * g.NTX * g.B;
+  if (phases & 1) {
+    const long nbasis = (long)g.nI * g.NTX * SWIH_TX + (long)g.nJ * g.H;
+    hipLaunchKernelGGL(k_basis, dim3(blocks_for_threads(nbasis)), dim3(WG), 0, s, g, ax, ay, uq,
+                       vq, vqd);
+    hipLaunchKernelGGL(k_aggregate_gauss<NT>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s,
+                       img, ipitch, g, uq, vq, z, T, BT);
+    const long nscan = (long)g.nJ * g.B * g.NTX * SWIH_TX + (long)g.nI * g.B * g.H +
+                       (long)g.nP * g.B;
+    hipLaunchKernelGGL((k_scan<int64_t, int64_t, double>), dim3(blocks_for_threads(nscan)),
+                       dim3(WG), 0, s, g, z, T, BT);
+  }
+  if (phases & 2)
+    hipLaunchKernelGGL(k_emit_gauss<NT>, dim3(blocks_for_waves(waves * NT)), dim3(WG), 0, s,
+                       img, ipitch, g, uq, vq, vqd, z, T, BT, Lp, Kp, RCp);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,
+                        const GaussAxis* ay, const uint8_t* img, int32_t img_pitch, char* ws,
+                        hipStream_t stream, int phases) {
+  switch (kind) {
+    case 0: return build_int<0>(L, img, img_pitch, ws, stream, phases);
+    case 1: return build_int<1>(L, img, img_pitch, ws, stream, phases);
+    case 2: return build_int<2>(L, img, img_pitch, ws, stream, phases);
+    case 3:
+      switch (L.g.nI) {
+        case 3: return build_gauss<3>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 5: return build_gauss<5>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 7: return build_gauss<7>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 9: return build_gauss<9>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 11: return build_gauss<11>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 13: return build_gauss<13>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 15: return build_gauss<15>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        case 17: return build_gauss<17>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
+        default: return hipErrorInvalidValue;
+      }
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace swih

@@ -1,0 +1,68 @@
+// Workspace layout of the weighted integral histograms and the build's carries.
+//
+// Geometry.  Pixel columns are cut into tiles of 64 (one wave64 lane per
+// column) and pixel rows into bands of TY rows.  The integral histogram of
+// plane p = (i, j) and bin b is the padded prefix
+//   P[Y][X] = sum_{x < X, y < Y} [Q(f(x, y)) = b] u_i(x) v_j(y),
+// X in [0, W], Y in [0, H]; row 0 and column 0 are zero.  Pixel column x
+// feeds column X = x + 1, so tile tx owns columns X in [64 tx + 1, 64 tx + 64]
+// and band ty owns rows Y in [TY ty + 1, TY ty + TY].
+//
+// Element (Y, X) of a plane sits at Y * pitch + 63 + X with pitch a multiple
+// of 64 elements, so every tile's 64 columns start on a 256-byte boundary.
+//
+// Weight terms (u_i(x) v_j(y)):
+//   uniform    {1}
+//   Manhattan  {1, x, y}                 (i, j) = (0,0) (1,0) (0,1)
+//   Euclidean  {1, x, y, x^2, y^2}       (0,0) (1,0) (0,1) (2,0) (0,2)
+//   Gaussian   all products of {1, cos(2 pi k x / Px), sin(2 pi k x / Px)}_k
+//              and the same in y: (2K+1)^2 terms, p = i * (2K+1) + j.
+//
+// Integer kernels store P itself as uint32 (arithmetic modulo 2^32).  The
+// Gaussian stores it split per tile (tile origin Xo = 64 tx, Yo = TY ty):
+//   P[Y][X] = RC[tx][Y] + K[ty][X] + L[Y][X]
+//   RC[tx][Y] = P[Y][Xo]                       (double, per row and tile column)
+//   K[ty][X]  = P[Yo][X] - P[Yo][Xo]           (double, per band and column)
+//   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X (float, bounded by the tile)
+// with tx = tile of column X, ty = band of row Y, and zeros at row/column 0.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#define SWIH_TX 64
+#define SWIH_TY_MAX 64
+
+struct SwihGeom {
+  int32_t H, W, B;       // image size, bins
+  int32_t TY;            // band height (<= 64)
+  int32_t NTX, NTY;      // tiles across, bands down
+  int32_t pitch;         // plane row pitch in elements (multiple of 64)
+  int32_t nP, nI, nJ;    // planes, x terms, y terms
+  int32_t gauss;         // 1 for the split Gaussian storage
+  int64_t plane_elems;   // (H + 1) * pitch
+};
+
+// Byte offsets inside one workspace.  All regions are 256-byte aligned.
+struct SwihLayout {
+  SwihGeom g;
+  int32_t nsets;         // plane sets: 1, or nscales for the Gaussian
+  int64_t set_bytes;     // bytes of one plane set (planes [+ K + RC + tables])
+  // inside a set
+  int64_t off_planes;    // uint32 or float [nP][B][H+1][pitch]
+  int64_t off_K;         // double [nP][B][NTY][pitch]            (Gaussian)
+  int64_t off_RC;        // double [nP][B][NTX][H+1]              (Gaussian)
+  int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
+  int64_t off_vq;        // int32 [nJ][H]       fixed-point y terms (Gaussian)
+  // build scratch, shared by all sets (after the sets)
+  int64_t off_scratch;
+  int64_t off_z;         // [nJ][B][NTY][NTX*64] band column sums -> carries
+  int64_t off_T;         // [nI][B][NTX][H]      row-segment sums -> row carries
+  int64_t off_CT;        // [nP][B][NTY][NTX]    tile carries
+  int64_t total;
+};
+
+static inline int64_t swih_align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+// Fixed-point scale of the Gaussian weight terms: u, v stored as round(t * 2^24).
+#define SWIH_FIX_BITS 24

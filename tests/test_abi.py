@@ -1,0 +1,109 @@
+"""The C ABI loads, exports every symbol include/swih.h declares, and its host-only
+paths (sizes, argument checks, the Gaussian series) behave -- no GPU needed."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1705_03524_amd as swih
+from paper_1705_03524_amd import _swih
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "swih.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(swih_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_declared_symbols():
+    lib = swih.load()
+    names = declared_functions()
+    assert len(names) >= 6
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_swih.EXPORTED)
+
+
+def test_status_strings():
+    assert swih.status_string(0) == "ok"
+    for s in (-1, -2, -3, -4):
+        assert swih.status_string(s) != "unknown status"
+
+
+def test_workspace_bytes_and_validation():
+    cfg = swih.Config(16, swih.MANHATTAN, [(31, 31)])
+    n = swih.workspace_bytes(cfg, 512, 512)
+    planes = 3 * 16 * 513 * 576 * 4
+    assert planes <= n < planes * 1.1
+    bad = [swih.Config(0, swih.MANHATTAN, [(3, 3)]), swih.Config(257, swih.MANHATTAN, [(3, 3)]),
+           swih.Config(8, 9, [(3, 3)]), swih.Config(8, swih.MANHATTAN, [(4, 3)]),
+           swih.Config(8, swih.MANHATTAN, [(3, 3)], flags=1),
+           swih.Config(8, swih.GAUSSIAN, [(3, 3)], gauss_terms=9),
+           swih.Config(8, swih.MANHATTAN, [(601, 3)])]
+    for c in bad:
+        with pytest.raises(swih.SwihError) as e:
+            swih.workspace_bytes(c, 512, 512)
+        assert e.value.status == _swih.ERR_INVALID
+    with pytest.raises(swih.SwihError):
+        swih.workspace_bytes(cfg, 0, 10)
+    # Gaussian keeps one plane set per scale
+    g1 = swih.workspace_bytes(swih.Config(16, swih.GAUSSIAN, [(31, 31)]), 256, 256)
+    g2 = swih.workspace_bytes(swih.Config(16, swih.GAUSSIAN, [(31, 31), (21, 21)]), 256, 256)
+    assert g2 > 1.9 * g1 - 2e6
+
+
+def test_host_checks_before_launch():
+    # rejected on the host: nothing reaches the device, so no GPU is needed
+    import ctypes as C
+    lib = swih.load()
+    cfg = swih.Config(8, swih.MANHATTAN, [(5, 5)])
+    st = lib.swih_build(C.byref(cfg.c()), None, 64, 64, 64, None, 0, None)
+    assert st == _swih.ERR_INVALID
+    st = lib.swih_build(C.byref(cfg.c()), C.c_void_p(256), 64, 64, 32, C.c_void_p(256), 1 << 30, None)
+    assert st == _swih.ERR_INVALID          # pitch < width
+    st = lib.swih_build(C.byref(cfg.c()), C.c_void_p(256), 64, 64, 64, C.c_void_p(256), 16, None)
+    assert st == _swih.ERR_WORKSPACE
+    st = lib.swih_build(C.byref(cfg.c()), C.c_void_p(256), 64, 64, 64, C.c_void_p(300), 1 << 30, None)
+    assert st == _swih.ERR_INVALID          # misaligned workspace
+    r = _swih._Rect(1, 2, 10, 10)           # x0 < rx
+    st = lib.swih_match(C.byref(cfg.c()), C.c_void_p(256), 1 << 30, 64, 64, 0, C.c_void_p(256), None, r,
+                        C.c_void_p(256), None)
+    assert st == _swih.ERR_INVALID
+    r = _swih._Rect(2, 2, 10, 10)
+    st = lib.swih_match(C.byref(cfg.c()), C.c_void_p(256), 1 << 30, 64, 64, 0, C.c_void_p(256),
+                        C.c_void_p(256), r, C.c_void_p(256), None)
+    assert st == _swih.ERR_INVALID          # both templates given
+    g = swih.Config(8, swih.GAUSSIAN, [(5, 5)])
+    st = lib.swih_query(C.byref(g.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, C.c_void_p(256), 4,
+                        None, C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # exact raw histograms are for integer kernels
+    big = swih.Config(8, swih.EUCLIDEAN, [(2001, 2001)])
+    st = lib.swih_build(C.byref(big.c()), C.c_void_p(256), 4000, 4000, 4000, C.c_void_p(256), 1 << 40, None)
+    assert st == _swih.ERR_UNSUPPORTED      # kernel mass beyond 2^32
+    st = lib.swih_query(C.byref(cfg.c()), C.c_void_p(256), 1 << 30, 64, 64, 0, None, 0, None, None, None)
+    assert st == 0                          # n == 0 is a no-op
+
+
+@pytest.mark.parametrize("n", [3, 5, 15, 21, 31, 45, 63, 81, 121])
+def test_gauss_series_fidelity(n):
+    # The series stands in for exp(-t^2 / (2 (n/4)^2)) on t in [-r, r]: check its
+    # worst normalised 2-D histogram error from the coefficients alone.
+    a, P, err = swih.gauss_terms(n, 4)
+    r = (n - 1) // 2
+    t = np.arange(-r, r + 1)
+    g = np.exp(-t.astype(float) ** 2 / (2 * (n / 4.0) ** 2))
+    gt = sum(a[k] * np.cos(2 * math.pi * k * t / P) for k in range(5))
+    k2 = np.outer(gt, gt) / gt.sum() ** 2 - np.outer(g, g) / g.sum() ** 2
+    worst = max(k2[k2 > 0].sum(), -k2[k2 < 0].sum()) if n > 1 else 0.0
+    assert worst == pytest.approx(err, rel=1e-6, abs=1e-15)
+    assert err < 1e-6
+    assert P >= n
+
+
+def test_gauss_series_orders():
+    e = [swih.gauss_terms(31, K)[2] for K in (2, 3, 4, 5)]
+    assert e[0] > e[1] > e[2] > e[3]
