@@ -45,6 +45,30 @@ __device__ __forceinline__ bool in_bin(uint32_t v, int B, int b) {
   return ((v * (uint32_t)B) >> 8) == (uint32_t)b;
 }
 
+// Bit k = [pixel (x, y0 + k) falls in bin b] for the band's rows.  All the
+// band's pixel loads of a lane are issued together (row index clamped, so no
+// branch separates them) and masked afterwards.
+__device__ __forceinline__ uint64_t band_mask(const uint8_t* __restrict__ img, int ipitch, int W,
+                                              int x, int y0, int nrows, int B, int b) {
+  const uint8_t* col = img + (size_t)y0 * ipitch + (x < W ? x : W - 1);
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int kk = k < nrows ? k : nrows - 1;
+    lo |= (uint32_t)in_bin(col[(size_t)kk * ipitch], B, b) << k;
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int kk = k + 32 < nrows ? k + 32 : nrows - 1;
+    hi |= (uint32_t)in_bin(col[(size_t)kk * ipitch], B, b) << k;
+  }
+  uint64_t m = ((uint64_t)hi << 32) | lo;
+  if (nrows < 64) m &= ((uint64_t)1 << nrows) - 1;
+  return x < W ? m : 0;
+}
+
+__device__ __forceinline__ uint32_t bit_of(uint64_t m, int k) { return (uint32_t)(m >> k) & 1u; }
+
 struct WaveTile {
   int b, tx, ty, x, y0, nrows;
   bool valid;
@@ -67,8 +91,10 @@ __device__ __forceinline__ bool wave_tile(const SwihGeom& g, long wid, int extra
   return true;
 }
 
+// Wave-uniform by construction; readfirstlane tells the compiler so, which keeps
+// every index derived from it (and the loads they address) scalar.
 __device__ __forceinline__ long wave_index() {
-  return (long)blockIdx.x * WPB + (long)(threadIdx.x >> 6);
+  return (long)blockIdx.x * WPB + (long)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------- integer kernels
@@ -92,11 +118,10 @@ __global__ __launch_bounds__(WG) void k_aggregate_int(const uint8_t* __restrict_
     treg[i] = 0;
     u[i] = poly_term(i, (uint32_t)t.x);
   }
-  const uint8_t* col = img + (t.valid ? t.x : 0);
+  const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
     const uint32_t y = (uint32_t)(t.y0 + k);
-    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
-    const uint32_t m = (t.valid && in_bin(v, g.B, t.b)) ? 1u : 0u;
+    const uint32_t m = bit_of(mask, k);
 #pragma unroll
     for (int j = 0; j < TT::nJ; ++j) zacc[j] += m * poly_term(j, y);
 #pragma unroll
@@ -211,11 +236,10 @@ __global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img
       if (t.tx == 0 && lane == 0) planes[pbase[p] - 1] = 0u;
     }
   }
-  const uint8_t* col = img + (t.valid ? t.x : 0);
+  const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
     const uint32_t y = (uint32_t)(t.y0 + k);
-    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
-    const uint32_t m = (t.valid && in_bin(v, g.B, t.b)) ? 1u : 0u;
+    const uint32_t m = bit_of(mask, k);
     uint32_t s[TT::nI];
 #pragma unroll
     for (int i = 0; i < TT::nI; ++i) s[i] = wave_incl_scan(m * u[i]) + readlane(ereg[i], k);
@@ -297,11 +321,10 @@ __global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restric
     zacc[i] = 0;
     treg[i] = 0;
   }
-  const uint8_t* col = img + (t.valid ? t.x : 0);
+  const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
     const int y = t.y0 + k;
-    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
-    const bool m = t.valid && in_bin(v, g.B, t.b);
+    const bool m = bit_of(mask, k) != 0;
     const int32_t* vrow = vq + (size_t)y * NT;
 #pragma unroll
     for (int j = 0; j < NT; ++j) zacc[j] += m ? vrow[j] : 0;
@@ -372,18 +395,25 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
       if (lane == 0) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1)] = 0.0;
     }
   }
-  const uint8_t* col = img + (t.valid ? t.x : 0);
+  const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
     const int y = t.y0 + k;
-    const uint32_t v = t.valid ? (uint32_t)col[(size_t)y * ipitch] : 0u;
-    const bool m = t.valid && in_bin(v, g.B, t.b);
+    const bool m = bit_of(mask, k) != 0;
     const double R = (double)wave_incl_scan(m ? uqi : 0);
     const double* vrow = vqd + (size_t)y * NT;
-    const size_t row = (size_t)(y + 1) * g.pitch;
+    double vr[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) vr[j] = vrow[j];
+    float out[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      L[j] = fma(vrow[j], R, L[j]);
-      if (t.valid) Lp[lbase[j] + row] = (float)L[j];
+      L[j] = fma(vr[j], R, L[j]);
+      out[j] = (float)L[j];
+    }
+    if (t.valid) {
+      const size_t row = (size_t)(y + 1) * g.pitch;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) Lp[lbase[j] + row] = out[j];
     }
   }
   // row carries at the tile origin column: RC[tx][y + 1] = P[y + 1][Xo], one lane per row

@@ -150,91 +150,146 @@ __device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double
   }
 }
 
+// One block per centre; threads over (bin, x term i) pairs compute
+// alpha_i sum_j beta_j B_ij into LDS, then one thread per bin adds the terms
+// in order i = 0..NT-1.
 template <int NT>
 __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
-                                                     const int32_t* __restrict__ centres, int n,
+                                                     const int32_t* __restrict__ centres,
                                                      float* __restrict__ hist) {
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long)n * g.B) return;
-  const int k = (int)(t / g.B), b = (int)(t % g.B);
+  extern __shared__ double part[];  // [B][NT]
+  const int k = blockIdx.x;
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
   double al[NT], be[NT];
   series_coeffs<NT>(sp.ax, xc, al);
   series_coeffs<NT>(sp.ay, yc, be);
   const int xa = xc - sp.rx, xb = xc + sp.rx + 1, ya = yc - sp.ry, yb = yc + sp.ry + 1;
-  double h = 0.0;
-  for (int i = 0; i < NT; ++i) {
+  for (int it = threadIdx.x; it < g.B * NT; it += blockDim.x) {
+    const int b = it / NT, i = it - (it / NT) * NT;
     double hi = 0.0;
+#pragma unroll
     for (int j = 0; j < NT; ++j) {
       const size_t pb = (size_t)((i * NT + j) * g.B + b);
       const double bx = at_g(gp, g, pb, yb, xb) - at_g(gp, g, pb, ya, xb) -
                         at_g(gp, g, pb, yb, xa) + at_g(gp, g, pb, ya, xa);
-      hi += be[j] * bx;
+      hi = fma(be[j], bx, hi);
     }
-    h += al[i] * hi;
+    part[it] = al[i] * hi;
   }
-  hist[t] = (float)(h / sp.mass);
+  __syncthreads();
+  for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
+    double h = 0.0;
+    for (int i = 0; i < NT; ++i) h += part[b * NT + i];
+    hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
+  }
 }
 
-// Dense map, one block per (row of centres, chunk of 256 centres).  For each
-// bin the block first contracts the y terms of every plane pair of rows
-// (ya, yb) into V_i(X) = sum_j beta_j (P_ij[yb][X] - P_ij[ya][X]) for the
-// columns the chunk's windows touch, then each window reads two entries per i.
+// V_i(X) for one bin: loads of all j for one i are issued together (no
+// branch between them), then contracted with beta.
+template <int NT, bool KDIFF>
+__device__ __forceinline__ void contract_rows(const GaussPlanes& gp, const SwihGeom& g, int b,
+                                              const double (&be)[NT], size_t offA, size_t offB,
+                                              size_t kA, size_t kB, double* V, int stride) {
+#pragma unroll 1
+  for (int i = 0; i < NT; ++i) {
+    float la[NT], lb[NT];
+    double ka[NT], kb[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const size_t pb = (size_t)((i * NT + j) * g.B + b);
+      const float* lp = gp.L + pb * g.plane_elems;
+      la[j] = lp[offA];
+      lb[j] = lp[offB];
+      if (KDIFF) {
+        const double* kp = gp.K + pb * g.NTY * (size_t)g.pitch;
+        ka[j] = kp[kA];
+        kb[j] = kp[kB];
+      }
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      double d = (double)lb[j] - (double)la[j];
+      if (KDIFF) d += kb[j] - ka[j];
+      v = fma(be[j], d, v);
+    }
+    V[i * stride] = v;
+  }
+}
+
+// Dense map, one block per (row of centres yc, chunk of cw centres); one thread
+// per plane column X the chunk's windows touch (X = xc - rx and xc + rx + 1).
+// For each bin the block contracts the y terms of every plane between the two
+// rows ya = yc - ry and yb = yc + ry + 1:
+//   V_i(X)  = sum_j beta_j(yc) ([L + K]_ij[yb][X] - [L + K]_ij[ya][X])
+//   R_i(tx) = sum_j beta_j(yc) (RC_ij[yb][tx] - RC_ij[ya][tx])   (per tile column)
+// into LDS (double-buffered across bins, one barrier per bin); each window then
+// needs H_b = sum_i alpha_i(xc) ((V_i + R_i)(xc + rx + 1) - (V_i + R_i)(xc - rx)).
 template <int NT>
 __global__ __launch_bounds__(256) void k_match_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
                                                      const float* __restrict__ tmpl, int x0,
-                                                     int y0, int x1, float* __restrict__ map) {
-  __shared__ double V[NT][512];
+                                                     int y0, int x1, int cw, int ntl_max,
+                                                     float* __restrict__ map) {
+  extern __shared__ double sm[];
+  const int nthr = blockDim.x;
+  double* Vbuf = sm;                   // [2][NT][nthr]
+  double* Rbuf = sm + 2 * NT * nthr;   // [2][NT][ntl_max]
   const int yc = y0 + blockIdx.y;
-  const int xa = x0 + blockIdx.x * 256;
-  const int cw = min(256, x1 - xa + 1);
+  const int xa = x0 + blockIdx.x * cw;
+  const int cwc = min(cw, x1 - xa + 1);
   const int rx = sp.rx, ry = sp.ry;
-  const bool contig = 2 * rx + 1 <= cw;
-  const int nV = contig ? cw + 2 * rx + 1 : 2 * cw;
+  const bool contig = 2 * rx + 1 <= cwc;
+  const int nV = contig ? cwc + 2 * rx + 1 : 2 * cwc;
   const int Ya = yc - ry, Yb = yc + ry + 1;
   const int tya = band_of(Ya, g.TY), tyb = band_of(Yb, g.TY);
-  double be[NT], al[NT];
+  const bool kdiff = tya != tyb;
+  double be[NT];
   series_coeffs<NT>(sp.ay, yc, be);
   const int tid = threadIdx.x;
-  const bool win = tid < cw;
+  const bool has_x = tid < nV;
+  const int X = !has_x ? xa : (contig ? xa - rx + tid
+                                      : (tid < cwc ? xa - rx + tid : xa + rx + 1 + tid - cwc));
+  const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
+  const bool win = tid < cwc;
   const int xc = xa + tid;
+  double al[NT];
   series_coeffs<NT>(sp.ax, win ? xc : xa, al);
-  const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cw + tid;
+  const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
+  const int t1 = win ? tile_of(xc - rx) - tlo : 0, t2 = win ? tile_of(xc + rx + 1) - tlo : 0;
+  const size_t offA = (size_t)Ya * g.pitch + 63 + X, offB = (size_t)Yb * g.pitch + 63 + X;
+  const size_t kA = (size_t)tya * g.pitch + 63 + X, kB = (size_t)tyb * g.pitch + 63 + X;
   const double inv_mass = 1.0 / sp.mass;
   double bc = 0.0;
   for (int b = 0; b < g.B; ++b) {
-    for (int idx = tid; idx < nV; idx += 256) {
-      const int X = contig ? xa - rx + idx : (idx < cw ? xa - rx + idx : xa + rx + 1 + idx - cw);
-      const int tx = tile_of(X);
-#pragma unroll 1
-      for (int i = 0; i < NT; ++i) {
-        double v = 0.0;
+    double* V = Vbuf + (b & 1) * NT * nthr;
+    double* R = Rbuf + (b & 1) * NT * ntl_max;
+    if (has_x) {
+      if (kdiff)
+        contract_rows<NT, true>(gp, g, b, be, offA, offB, kA, kB, V + tid, nthr);
+      else
+        contract_rows<NT, false>(gp, g, b, be, offA, offB, kA, kB, V + tid, nthr);
+    }
+    for (int it = tid; it < NT * ntl; it += nthr) {
+      const int i = it / ntl, t = it - (it / ntl) * ntl;
+      double r = 0.0;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const size_t pb = (size_t)((i * NT + j) * g.B + b);
-          const float* lp = gp.L + pb * g.plane_elems + 63 + X;
-          double d = (double)lp[(size_t)Yb * g.pitch] - (double)lp[(size_t)Ya * g.pitch];
-          const double* rcp = gp.RC + (pb * g.NTX + tx) * (size_t)(g.H + 1);
-          d += rcp[Yb] - rcp[Ya];
-          if (tya != tyb) {
-            const double* kp = gp.K + pb * g.NTY * (size_t)g.pitch + 63 + X;
-            d += kp[(size_t)tyb * g.pitch] - kp[(size_t)tya * g.pitch];
-          }
-          v = fma(be[j], d, v);
-        }
-        V[i][idx] = v;
+      for (int j = 0; j < NT; ++j) {
+        const size_t pb = (size_t)((i * NT + j) * g.B + b);
+        const double* rcp = gp.RC + (pb * g.NTX + tlo + t) * (size_t)(g.H + 1);
+        r = fma(be[j], rcp[Yb] - rcp[Ya], r);
       }
+      R[i * ntl_max + t] = r;
     }
     __syncthreads();
     if (win) {
       double h = 0.0;
 #pragma unroll
-      for (int i = 0; i < NT; ++i) h = fma(al[i], V[i][i2] - V[i][i1], h);
-      const double p = h * inv_mass;
-      bc += sqrt(fmax(p, 0.0) * fmax((double)tmpl[b], 0.0));
+      for (int i = 0; i < NT; ++i)
+        h = fma(al[i], (V[i * nthr + i2] + R[i * ntl_max + t2]) - (V[i * nthr + i1] + R[i * ntl_max + t1]),
+                h);
+      bc += sqrt(fmax(h * inv_mass, 0.0) * fmax((double)tmpl[b], 0.0));
     }
-    __syncthreads();
   }
   if (win) map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)bc;
 }
@@ -248,9 +303,9 @@ inline GaussPlanes gauss_planes(const SwihLayout& L, int set, const char* ws) {
 template <int NT>
 hipError_t query_gauss(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                        const int32_t* centres, int32_t n, float* hist, hipStream_t s) {
-  const long nt = (long)n * L.g.B;
-  hipLaunchKernelGGL(k_query_gauss<NT>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, L.g,
-                     sp, gauss_planes(L, set, ws), centres, n, hist);
+  const size_t lds = sizeof(double) * (size_t)L.g.B * NT;
+  hipLaunchKernelGGL(k_query_gauss<NT>, dim3((unsigned)n), dim3(256), lds, s, L.g, sp,
+                     gauss_planes(L, set, ws), centres, hist);
   return hipGetLastError();
 }
 
@@ -259,8 +314,24 @@ hipError_t match_gauss(const SwihLayout& L, const ScaleParams& sp, int set, cons
                        const float* tmpl, int x0, int y0, int x1, int y1, float* map,
                        hipStream_t s) {
   const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
-  hipLaunchKernelGGL(k_match_gauss<NT>, dim3((unsigned)((nx + 255) / 256), (unsigned)ny),
-                     dim3(256), 0, s, L.g, sp, gauss_planes(L, set, ws), tmpl, x0, y0, x1, map);
+  const int span = 2 * sp.rx + 1;
+  int cw, nthr;
+  if (span <= 128) {  // contiguous columns: nV = cw + span <= 256
+    const int cwmax = 256 - span;
+    const int nch = (nx + cwmax - 1) / cwmax;
+    cw = (nx + nch - 1) / nch;
+    nthr = cw + span;
+  } else {            // two column segments of cw each
+    cw = nx < 128 ? nx : 128;
+    nthr = 2 * cw;
+  }
+  nthr = (nthr + 63) / 64 * 64;
+  // tile columns one block can touch
+  const int ntl_max = (cw + span + 63) / 64 + 2;
+  const size_t lds = sizeof(double) * (size_t)2 * NT * (nthr + ntl_max);
+  const unsigned nch = (unsigned)((nx + cw - 1) / cw);
+  hipLaunchKernelGGL(k_match_gauss<NT>, dim3(nch, (unsigned)ny), dim3(nthr), lds, s, L.g, sp,
+                     gauss_planes(L, set, ws), tmpl, x0, y0, x1, cw, ntl_max, map);
   return hipGetLastError();
 }
 
