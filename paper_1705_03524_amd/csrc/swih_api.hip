@@ -69,8 +69,6 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   L.off_planes = off;
   off += swih_align256(PB * g.plane_elems * 4);
   if (gauss) {
-    L.off_K = off;
-    off += swih_align256(PB * g.NTY * g.pitch * 8);
     L.off_RC = off;
     off += swih_align256(PB * g.NTX * (int64_t)(H + 1) * 8);
     L.off_uq = off;
@@ -84,7 +82,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   off = L.set_bytes * L.nsets;
   L.off_scratch = off;
   L.off_z = off;
-  off += swih_align256((int64_t)g.nJ * g.B * g.NTY * NXP * esz);
+  if (!gauss) off += swih_align256((int64_t)g.nJ * g.B * g.NTY * NXP * esz);
   L.off_T = off;
   off += swih_align256((int64_t)g.nI * g.B * g.NTX * (int64_t)H * esz);
   L.off_CT = off;

@@ -150,10 +150,11 @@ __global__ __launch_bounds__(WG) void k_aggregate_int(const uint8_t* __restrict_
 // Exclusive prefixes of the aggregates (all three roles in one launch).
 template <typename ZT, typename TTy, typename BTy>
 __global__ __launch_bounds__(WG) void k_scan(SwihGeom g, ZT* __restrict__ z,
-                                             TTy* __restrict__ T, BTy* __restrict__ BT) {
+                                             TTy* __restrict__ T, BTy* __restrict__ BT,
+                                             int with_z) {
   long t = (long)blockIdx.x * WG + threadIdx.x;
   const int NXP = g.NTX * SWIH_TX;
-  const long n1 = (long)g.nJ * g.B * NXP;
+  const long n1 = with_z ? (long)g.nJ * g.B * NXP : 0;
   const long n2 = (long)g.nI * g.B * g.H;
   const long n3 = (long)g.nP * g.B;
   if (t < n1) {  // carry row above each band: exclusive over bands
@@ -306,7 +307,6 @@ __global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restric
                                                         int ipitch, SwihGeom g,
                                                         const int32_t* __restrict__ uq,
                                                         const int32_t* __restrict__ vq,
-                                                        int64_t* __restrict__ z,
                                                         int64_t* __restrict__ T,
                                                         double* __restrict__ BT) {
   WaveTile t;
@@ -314,29 +314,21 @@ __global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restric
   if (!wave_tile(g, wave_index(), 1, t, e)) return;
   const int lane = lane_id();
   const int NXP = g.NTX * SWIH_TX;
-  int32_t uqx[NT], zacc[NT], treg[NT];
+  int32_t uqx[NT], treg[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
     uqx[i] = uq[(size_t)i * NXP + t.x];
-    zacc[i] = 0;
     treg[i] = 0;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
-    const int y = t.y0 + k;
     const bool m = bit_of(mask, k) != 0;
-    const int32_t* vrow = vq + (size_t)y * NT;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) zacc[j] += m ? vrow[j] : 0;
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
       const int32_t s = wave_sum(m ? uqx[i] : 0);
       treg[i] = put_lane(treg[i], s, k);
     }
   }
-#pragma unroll
-  for (int j = 0; j < NT; ++j)
-    z[((size_t)(j * g.B + t.b) * g.NTY + t.ty) * NXP + t.x] = (int64_t)zacc[j];
   if (lane < t.nrows) {
 #pragma unroll
     for (int i = 0; i < NT; ++i)
@@ -360,11 +352,9 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
                                                    SwihGeom g, const int32_t* __restrict__ uq,
                                                    const int32_t* __restrict__ vq,
                                                    const double* __restrict__ vqd,
-                                                   const int64_t* __restrict__ zc,
                                                    const int64_t* __restrict__ E,
                                                    const double* __restrict__ CTc,
                                                    float* __restrict__ Lp,
-                                                   double* __restrict__ Kp,
                                                    double* __restrict__ RCp) {
   WaveTile t;
   int i;
@@ -383,12 +373,6 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
     const size_t pb = (size_t)(p * g.B + t.b);
     lbase[j] = pb * g.plane_elems + 64 + t.x;
     L[j] = 0.0;
-    // carry row relative to the tile origin: K[ty][x + 1] = P[y0][x + 1] - P[y0][Xo]
-    const double zv = (double)zc[((size_t)(j * g.B + t.b) * g.NTY + t.ty) * NXP + t.x];
-    const double kv = wave_incl_scan((double)uqi * zv) * sc48;
-    double* krow = Kp + (pb * g.NTY + t.ty) * (size_t)g.pitch;
-    if (t.valid) krow[64 + t.x] = kv;
-    if (t.tx == 0 && lane == 0) krow[63] = 0.0;
     if (t.ty == 0) {
       if (t.valid) Lp[lbase[j]] = 0.0f;
       if (t.tx == 0 && lane == 0) Lp[lbase[j] - 1] = 0.0f;
@@ -449,7 +433,7 @@ hipError_t build_int(const SwihLayout& L, const uint8_t* img, int ipitch, char* 
     const long nscan = (long)g.nJ * g.B * g.NTX * SWIH_TX + (long)g.nI * g.B * g.H +
                        (long)g.nP * g.B;
     hipLaunchKernelGGL((k_scan<uint32_t, uint32_t, uint32_t>), dim3(blocks_for_threads(nscan)),
-                       dim3(WG), 0, s, g, z, T, BT);
+                       dim3(WG), 0, s, g, z, T, BT, 1);
   }
   if (phases & 2)
     hipLaunchKernelGGL(k_emit_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
@@ -463,12 +447,10 @@ hipError_t build_gauss(const SwihLayout& L, int set, const GaussAxis& ax, const 
   const SwihGeom& g = L.g;
   char* sb = ws + (size_t)set * L.set_bytes;
   float* Lp = (float*)(sb + L.off_planes);
-  double* Kp = (double*)(sb + L.off_K);
   double* RCp = (double*)(sb + L.off_RC);
   int32_t* uq = (int32_t*)(sb + L.off_uq);
   int32_t* vq = (int32_t*)(sb + L.off_vq);
   double* vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
-  int64_t* z = (int64_t*)(ws + L.off_z);
   int64_t* T = (int64_t*)(ws + L.off_T);
   double* BT = (double*)(ws + L.off_CT);
   const long waves = (long)g.NTY * g.NTX * g.B;
@@ -477,15 +459,14 @@ hipError_t build_gauss(const SwihLayout& L, int set, const GaussAxis& ax, const 
     hipLaunchKernelGGL(k_basis, dim3(blocks_for_threads(nbasis)), dim3(WG), 0, s, g, ax, ay, uq,
                        vq, vqd);
     hipLaunchKernelGGL(k_aggregate_gauss<NT>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s,
-                       img, ipitch, g, uq, vq, z, T, BT);
-    const long nscan = (long)g.nJ * g.B * g.NTX * SWIH_TX + (long)g.nI * g.B * g.H +
-                       (long)g.nP * g.B;
+                       img, ipitch, g, uq, vq, T, BT);
+    const long nscan = (long)g.nI * g.B * g.H + (long)g.nP * g.B;
     hipLaunchKernelGGL((k_scan<int64_t, int64_t, double>), dim3(blocks_for_threads(nscan)),
-                       dim3(WG), 0, s, g, z, T, BT);
+                       dim3(WG), 0, s, g, (int64_t*)nullptr, T, BT, 0);
   }
   if (phases & 2)
     hipLaunchKernelGGL(k_emit_gauss<NT>, dim3(blocks_for_waves(waves * NT)), dim3(WG), 0, s,
-                       img, ipitch, g, uq, vq, vqd, z, T, BT, Lp, Kp, RCp);
+                       img, ipitch, g, uq, vq, vqd, T, BT, Lp, RCp);
   return hipGetLastError();
 }
 

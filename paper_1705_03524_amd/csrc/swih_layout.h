@@ -20,11 +20,16 @@
 //
 // Integer kernels store P itself as uint32 (arithmetic modulo 2^32).  The
 // Gaussian stores it split per tile (tile origin Xo = 64 tx, Yo = TY ty):
-//   P[Y][X] = RC[tx][Y] + K[ty][X] + L[Y][X]
-//   RC[tx][Y] = P[Y][Xo]                       (double, per row and tile column)
-//   K[ty][X]  = P[Yo][X] - P[Yo][Xo]           (double, per band and column)
-//   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X (float, bounded by the tile)
+//   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X  (float, bounded by the tile)
+//   RC[tx][Y] = P[Y][Xo]                          (double, per row and tile column)
 // with tx = tile of column X, ty = band of row Y, and zeros at row/column 0.
+// Only window boxes are ever needed, and they follow from vertical
+// differences at fixed X:
+//   P[yb][X] - P[ya][X] = L[yb][X] - L[ya][X] + sum_{c} L[c][X]
+//                         + RC[tx][yb] - RC[tx][ya]
+// where c runs over the band-boundary rows (multiples of TY) in [ya, yb): the
+// last row of a band holds the band's whole tile-local column sum, which is
+// exactly what the band-top carry grows by from one band to the next.
 #pragma once
 
 #include <stddef.h>
@@ -47,16 +52,15 @@ struct SwihGeom {
 struct SwihLayout {
   SwihGeom g;
   int32_t nsets;         // plane sets: 1, or nscales for the Gaussian
-  int64_t set_bytes;     // bytes of one plane set (planes [+ K + RC + tables])
+  int64_t set_bytes;     // bytes of one plane set (planes [+ RC + tables])
   // inside a set
   int64_t off_planes;    // uint32 or float [nP][B][H+1][pitch]
-  int64_t off_K;         // double [nP][B][NTY][pitch]            (Gaussian)
   int64_t off_RC;        // double [nP][B][NTX][H+1]              (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
-  int64_t off_vq;        // int32 [nJ][H]       fixed-point y terms (Gaussian)
+  int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
   // build scratch, shared by all sets (after the sets)
   int64_t off_scratch;
-  int64_t off_z;         // [nJ][B][NTY][NTX*64] band column sums -> carries
+  int64_t off_z;         // [nJ][B][NTY][NTX*64] band column sums -> carries (integer)
   int64_t off_T;         // [nI][B][NTX][H]      row-segment sums -> row carries
   int64_t off_CT;        // [nP][B][NTY][NTX]    tile carries
   int64_t total;

@@ -120,20 +120,26 @@ __global__ __launch_bounds__(256) void k_match_int(SwihGeom g, ScaleParams sp,
 // ---------------------------------------------------------------- Gaussian
 struct GaussPlanes {
   const float* L;
-  const double* K;
   const double* RC;
 };
 
 __device__ __forceinline__ int tile_of(int X) { return (X > 0 ? X - 1 : 0) >> 6; }
-__device__ __forceinline__ int band_of(int Y, int TY) { return (Y > 0 ? Y - 1 : 0) / TY; }
 
-// P[Y][X] of plane-bin pb from its tile-local split.
-__device__ __forceinline__ double at_g(const GaussPlanes& gp, const SwihGeom& g, size_t pb, int Y,
-                                       int X) {
-  const double l = (double)gp.L[pb * g.plane_elems + (size_t)Y * g.pitch + 63 + X];
-  const double k = gp.K[(pb * g.NTY + band_of(Y, g.TY)) * g.pitch + 63 + X];
-  const double rc = gp.RC[(pb * g.NTX + tile_of(X)) * (size_t)(g.H + 1) + Y];
-  return rc + k + l;
+// First band-boundary row (a positive multiple of TY) at or after ya.
+__device__ __forceinline__ int first_cross(int ya, int TY) {
+  const int c = (ya + TY - 1) / TY * TY;
+  return c == 0 ? TY : c;
+}
+
+// P[yb][X] - P[ya][X] of plane-bin pb from the tile-local split: the two L rows,
+// the L rows that close each band in between, and the row carries of X's tile.
+__device__ __forceinline__ double vdiff_g(const GaussPlanes& gp, const SwihGeom& g, size_t pb,
+                                          int ya, int yb, int X) {
+  const float* lp = gp.L + pb * g.plane_elems + 63 + X;
+  double d = (double)lp[(size_t)yb * g.pitch] - (double)lp[(size_t)ya * g.pitch];
+  for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) d += (double)lp[(size_t)c * g.pitch];
+  const double* rcp = gp.RC + (pb * g.NTX + tile_of(X)) * (size_t)(g.H + 1);
+  return d + (rcp[yb] - rcp[ya]);
 }
 
 template <int NT>
@@ -171,9 +177,7 @@ __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp,
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const size_t pb = (size_t)((i * NT + j) * g.B + b);
-      const double bx = at_g(gp, g, pb, yb, xb) - at_g(gp, g, pb, ya, xb) -
-                        at_g(gp, g, pb, yb, xa) + at_g(gp, g, pb, ya, xa);
-      hi = fma(be[j], bx, hi);
+      hi = fma(be[j], vdiff_g(gp, g, pb, ya, yb, xb) - vdiff_g(gp, g, pb, ya, yb, xa), hi);
     }
     part[it] = al[i] * hi;
   }
@@ -185,56 +189,57 @@ __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp,
   }
 }
 
-// V_i(X) for one bin: loads of all j for one i are issued together (no
-// branch between them), then contracted with beta.
-template <int NT, bool KDIFF>
+// V_i(X) = sum_j beta_j (L_ij[yb][X] - L_ij[ya][X] + sum_c L_ij[c][X]) for the
+// x terms i = grp, grp + NG, ... of one bin; NC band-boundary rows c (NC < 0:
+// any number, looped).  All loads of one i are issued before any use.
+template <int NT, int NG, int NC>
 __device__ __forceinline__ void contract_rows(const GaussPlanes& gp, const SwihGeom& g, int b,
-                                              const double (&be)[NT], size_t offA, size_t offB,
-                                              size_t kA, size_t kB, double* V, int stride) {
-#pragma unroll 1
-  for (int i = 0; i < NT; ++i) {
-    float la[NT], lb[NT];
-    double ka[NT], kb[NT];
+                                              int grp, const double (&be)[NT], size_t offA,
+                                              size_t offB, size_t offC, int ncross, double* V,
+                                              int stride) {
+#pragma unroll
+  for (int ii = 0; ii < (NT + NG - 1) / NG; ++ii) {
+    const int i = grp + ii * NG;
+    if (i >= NT) break;
+    float la[NT], lb[NT], lc[NT > 0 ? NT : 1];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const size_t pb = (size_t)((i * NT + j) * g.B + b);
-      const float* lp = gp.L + pb * g.plane_elems;
+      const float* lp = gp.L + (size_t)((i * NT + j) * g.B + b) * g.plane_elems;
       la[j] = lp[offA];
       lb[j] = lp[offB];
-      if (KDIFF) {
-        const double* kp = gp.K + pb * g.NTY * (size_t)g.pitch;
-        ka[j] = kp[kA];
-        kb[j] = kp[kB];
-      }
+      if (NC >= 1) lc[j] = lp[offC];
     }
     double v = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       double d = (double)lb[j] - (double)la[j];
-      if (KDIFF) d += kb[j] - ka[j];
+      if (NC >= 1) d += (double)lc[j];
+      if (NC < 0) {
+        const float* lp = gp.L + (size_t)((i * NT + j) * g.B + b) * g.plane_elems;
+        for (int c = 0; c < ncross; ++c) d += (double)lp[offC + (size_t)c * g.TY * g.pitch];
+      }
       v = fma(be[j], d, v);
     }
     V[i * stride] = v;
   }
 }
 
-// Dense map, one block per (row of centres yc, chunk of cw centres); one thread
-// per plane column X the chunk's windows touch (X = xc - rx and xc + rx + 1).
-// For each bin the block contracts the y terms of every plane between the two
-// rows ya = yc - ry and yb = yc + ry + 1:
-//   V_i(X)  = sum_j beta_j(yc) ([L + K]_ij[yb][X] - [L + K]_ij[ya][X])
-//   R_i(tx) = sum_j beta_j(yc) (RC_ij[yb][tx] - RC_ij[ya][tx])   (per tile column)
+// Dense map, one block per (row of centres yc, chunk of cw centres).  NG groups
+// of threads, one thread per (group, plane column X the chunk's windows touch:
+// X = xc - rx and xc + rx + 1).  For each bin the block contracts the y terms
+// of every plane between rows ya = yc - ry and yb = yc + ry + 1:
+//   V_i(X)  = sum_j beta_j(yc) (P_ij[yb][X] - P_ij[ya][X]) without the row carries
+//   R_i(tx) = sum_j beta_j(yc) (RC_ij[tx][yb] - RC_ij[tx][ya])   (per tile column)
 // into LDS (double-buffered across bins, one barrier per bin); each window then
 // needs H_b = sum_i alpha_i(xc) ((V_i + R_i)(xc + rx + 1) - (V_i + R_i)(xc - rx)).
-template <int NT>
-__global__ __launch_bounds__(256) void k_match_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
-                                                     const float* __restrict__ tmpl, int x0,
-                                                     int y0, int x1, int cw, int ntl_max,
-                                                     float* __restrict__ map) {
+template <int NT, int NG>
+__global__ __launch_bounds__(1024) void k_match_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
+                                                      const float* __restrict__ tmpl, int x0,
+                                                      int y0, int x1, int cw, int nvpad,
+                                                      int ntl_max, float* __restrict__ map) {
   extern __shared__ double sm[];
-  const int nthr = blockDim.x;
-  double* Vbuf = sm;                   // [2][NT][nthr]
-  double* Rbuf = sm + 2 * NT * nthr;   // [2][NT][ntl_max]
+  double* Vbuf = sm;                    // [2][NT][nvpad]
+  double* Rbuf = sm + 2 * NT * nvpad;   // [2][NT][ntl_max]
   const int yc = y0 + blockIdx.y;
   const int xa = x0 + blockIdx.x * cw;
   const int cwc = min(cw, x1 - xa + 1);
@@ -242,14 +247,16 @@ __global__ __launch_bounds__(256) void k_match_gauss(SwihGeom g, ScaleParams sp,
   const bool contig = 2 * rx + 1 <= cwc;
   const int nV = contig ? cwc + 2 * rx + 1 : 2 * cwc;
   const int Ya = yc - ry, Yb = yc + ry + 1;
-  const int tya = band_of(Ya, g.TY), tyb = band_of(Yb, g.TY);
-  const bool kdiff = tya != tyb;
+  const int c0 = first_cross(Ya, g.TY);
+  const int ncross = c0 < Yb ? (Yb - 1 - c0) / g.TY + 1 : 0;
   double be[NT];
   series_coeffs<NT>(sp.ay, yc, be);
   const int tid = threadIdx.x;
-  const bool has_x = tid < nV;
-  const int X = !has_x ? xa : (contig ? xa - rx + tid
-                                      : (tid < cwc ? xa - rx + tid : xa + rx + 1 + tid - cwc));
+  const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
+  const int xi = tid - grp * nvpad;
+  const bool has_x = xi < nV;
+  const int X = !has_x ? xa : (contig ? xa - rx + xi
+                                      : (xi < cwc ? xa - rx + xi : xa + rx + 1 + xi - cwc));
   const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
   const bool win = tid < cwc;
   const int xc = xa + tid;
@@ -258,19 +265,21 @@ __global__ __launch_bounds__(256) void k_match_gauss(SwihGeom g, ScaleParams sp,
   const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
   const int t1 = win ? tile_of(xc - rx) - tlo : 0, t2 = win ? tile_of(xc + rx + 1) - tlo : 0;
   const size_t offA = (size_t)Ya * g.pitch + 63 + X, offB = (size_t)Yb * g.pitch + 63 + X;
-  const size_t kA = (size_t)tya * g.pitch + 63 + X, kB = (size_t)tyb * g.pitch + 63 + X;
+  const size_t offC = (size_t)c0 * g.pitch + 63 + X;
   const double inv_mass = 1.0 / sp.mass;
   double bc = 0.0;
   for (int b = 0; b < g.B; ++b) {
-    double* V = Vbuf + (b & 1) * NT * nthr;
+    double* V = Vbuf + (b & 1) * NT * nvpad;
     double* R = Rbuf + (b & 1) * NT * ntl_max;
     if (has_x) {
-      if (kdiff)
-        contract_rows<NT, true>(gp, g, b, be, offA, offB, kA, kB, V + tid, nthr);
+      if (ncross == 0)
+        contract_rows<NT, NG, 0>(gp, g, b, grp, be, offA, offB, offC, 0, V + xi, nvpad);
+      else if (ncross == 1)
+        contract_rows<NT, NG, 1>(gp, g, b, grp, be, offA, offB, offC, 1, V + xi, nvpad);
       else
-        contract_rows<NT, false>(gp, g, b, be, offA, offB, kA, kB, V + tid, nthr);
+        contract_rows<NT, NG, -1>(gp, g, b, grp, be, offA, offB, offC, ncross, V + xi, nvpad);
     }
-    for (int it = tid; it < NT * ntl; it += nthr) {
+    for (int it = tid; it < NT * ntl; it += blockDim.x) {
       const int i = it / ntl, t = it - (it / ntl) * ntl;
       double r = 0.0;
 #pragma unroll
@@ -286,7 +295,8 @@ __global__ __launch_bounds__(256) void k_match_gauss(SwihGeom g, ScaleParams sp,
       double h = 0.0;
 #pragma unroll
       for (int i = 0; i < NT; ++i)
-        h = fma(al[i], (V[i * nthr + i2] + R[i * ntl_max + t2]) - (V[i * nthr + i1] + R[i * ntl_max + t1]),
+        h = fma(al[i],
+                (V[i * nvpad + i2] + R[i * ntl_max + t2]) - (V[i * nvpad + i1] + R[i * ntl_max + t1]),
                 h);
       bc += sqrt(fmax(h * inv_mass, 0.0) * fmax((double)tmpl[b], 0.0));
     }
@@ -296,8 +306,7 @@ __global__ __launch_bounds__(256) void k_match_gauss(SwihGeom g, ScaleParams sp,
 
 inline GaussPlanes gauss_planes(const SwihLayout& L, int set, const char* ws) {
   const char* sb = ws + (size_t)set * L.set_bytes;
-  return GaussPlanes{(const float*)(sb + L.off_planes), (const double*)(sb + L.off_K),
-                     (const double*)(sb + L.off_RC)};
+  return GaussPlanes{(const float*)(sb + L.off_planes), (const double*)(sb + L.off_RC)};
 }
 
 template <int NT>
@@ -313,25 +322,30 @@ template <int NT>
 hipError_t match_gauss(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                        const float* tmpl, int x0, int y0, int x1, int y1, float* map,
                        hipStream_t s) {
+  constexpr int NG = 3;
   const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
   const int span = 2 * sp.rx + 1;
-  int cw, nthr;
-  if (span <= 128) {  // contiguous columns: nV = cw + span <= 256
-    const int cwmax = 256 - span;
+  // columns per group: NG * maxV threads <= 1024 and the double-buffered V
+  // table within 60 KB of LDS
+  int maxV = (60000 / (16 * NT)) / 64 * 64;
+  if (maxV > 320) maxV = 320;
+  int cw, nV;
+  if (span <= maxV / 2) {  // one contiguous column range: nV = cw + span
+    const int cwmax = maxV - span;
     const int nch = (nx + cwmax - 1) / cwmax;
     cw = (nx + nch - 1) / nch;
-    nthr = cw + span;
-  } else {            // two column segments of cw each
-    cw = nx < 128 ? nx : 128;
-    nthr = 2 * cw;
+    nV = cw + span;
+  } else {                 // two column segments of cw each
+    cw = nx < maxV / 2 ? nx : maxV / 2;
+    nV = 2 * cw;
   }
-  nthr = (nthr + 63) / 64 * 64;
-  // tile columns one block can touch
-  const int ntl_max = (cw + span + 63) / 64 + 2;
-  const size_t lds = sizeof(double) * (size_t)2 * NT * (nthr + ntl_max);
+  const int nvpad = (nV + 63) / 64 * 64;
+  const int ntl_max = (cw + span + 63) / 64 + 2;  // tile columns one block can touch
+  const size_t lds = sizeof(double) * (size_t)2 * NT * (nvpad + ntl_max);
   const unsigned nch = (unsigned)((nx + cw - 1) / cw);
-  hipLaunchKernelGGL(k_match_gauss<NT>, dim3(nch, (unsigned)ny), dim3(nthr), lds, s, L.g, sp,
-                     gauss_planes(L, set, ws), tmpl, x0, y0, x1, cw, ntl_max, map);
+  hipLaunchKernelGGL((k_match_gauss<NT, NG>), dim3(nch, (unsigned)ny), dim3(NG * nvpad), lds, s,
+                     L.g, sp, gauss_planes(L, set, ws), tmpl, x0, y0, x1, cw, nvpad, ntl_max,
+                     map);
   return hipGetLastError();
 }
 
