@@ -58,11 +58,14 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   if (gauss) {
     g.nI = g.nJ = 2 * gauss_K(c) + 1;
     g.nP = g.nI * g.nJ;
+    g.ppg = g.nJ;
   } else {
     static const int nI[3] = {1, 2, 3}, nP[3] = {1, 3, 5};
     g.nI = g.nJ = nI[c->kernel];
     g.nP = nP[c->kernel];
+    g.ppg = g.nP;
   }
+  g.row_stride = (int64_t)g.ppg * g.pitch;
   const int64_t PB = (int64_t)g.nP * g.B;
   const int64_t NXP = (int64_t)g.NTX * SWIH_TX;
   int64_t off = 0;

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img
     const uint32_t zv = zc[((size_t)(plane_j(p) * g.B + t.b) * g.NTY + t.ty) * NXP + t.x];
     acc[p] = CTc[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] +
              wave_incl_scan(u[plane_i(p)] * zv);
-    pbase[p] = (size_t)(p * g.B + t.b) * g.plane_elems + 64 + t.x;
+    pbase[p] = (size_t)swih_elem(g, p, t.b, 0, t.x + 1);
   }
   if (t.ty == 0) {
 #pragma unroll
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img
 #pragma unroll
     for (int p = 0; p < TT::nP; ++p) acc[p] += poly_term(plane_j(p), y) * s[plane_i(p)];
     if (t.valid) {
-      const size_t row = (size_t)(y + 1) * g.pitch;
+      const size_t row = (size_t)(y + 1) * g.row_stride;
 #pragma unroll
       for (int p = 0; p < TT::nP; ++p) planes[pbase[p] + row] = acc[p];
     }
@@ -255,8 +255,7 @@ __global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img
   if (t.tx == 0 && lane < t.nrows) {
 #pragma unroll
     for (int p = 0; p < TT::nP; ++p)
-      planes[(size_t)(p * g.B + t.b) * g.plane_elems + (size_t)(t.y0 + 1 + lane) * g.pitch + 63] =
-          0u;
+      planes[swih_elem(g, p, t.b, t.y0 + 1 + lane, 0)] = 0u;
   }
 }
 
@@ -371,7 +370,7 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
   for (int j = 0; j < NT; ++j) {
     const int p = i * NT + j;
     const size_t pb = (size_t)(p * g.B + t.b);
-    lbase[j] = pb * g.plane_elems + 64 + t.x;
+    lbase[j] = (size_t)swih_elem(g, p, t.b, 0, t.x + 1);
     L[j] = 0.0;
     if (t.ty == 0) {
       if (t.valid) Lp[lbase[j]] = 0.0f;
@@ -395,7 +394,7 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
       out[j] = (float)L[j];
     }
     if (t.valid) {
-      const size_t row = (size_t)(y + 1) * g.pitch;
+      const size_t row = (size_t)(y + 1) * g.row_stride;
 #pragma unroll
       for (int j = 0; j < NT; ++j) Lp[lbase[j] + row] = out[j];
     }
@@ -411,7 +410,7 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
         (CTc[(pb * g.NTY + t.ty) * g.NTX + t.tx] + wave_incl_scan(term)) * sc48;
     if (lane < t.nrows) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1) + t.y0 + 1 + lane] = rc;
     if (t.tx == 0 && lane < t.nrows)
-      Lp[pb * g.plane_elems + (size_t)(t.y0 + 1 + lane) * g.pitch + 63] = 0.0f;
+      Lp[swih_elem(g, p, t.b, t.y0 + 1 + lane, 0)] = 0.0f;
   }
 }
 

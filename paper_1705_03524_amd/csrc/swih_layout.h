@@ -8,8 +8,13 @@
 // feeds column X = x + 1, so tile tx owns columns X in [64 tx + 1, 64 tx + 64]
 // and band ty owns rows Y in [TY ty + 1, TY ty + TY].
 //
-// Element (Y, X) of a plane sits at Y * pitch + 63 + X with pitch a multiple
-// of 64 elements, so every tile's 64 columns start on a 256-byte boundary.
+// Planes come in groups of ppg: the y terms of one x term for the Gaussian,
+// all terms for the integer kernels.  The rows of a group's planes (for one
+// bin) are interleaved: row Y of plane p sits at
+//   ((((p / ppg) * B + b) * (H + 1) + Y) * ppg + p % ppg) * pitch
+// so a window corner's values of all terms of a group lie within ppg * pitch
+// elements.  Element X of a row sits at 63 + X, pitch a multiple of 64
+// elements, so every tile's 64 columns start on a 256-byte boundary.
 //
 // Weight terms (u_i(x) v_j(y)):
 //   uniform    {1}
@@ -32,6 +37,7 @@
 // exactly what the band-top carry grows by from one band to the next.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -45,8 +51,16 @@ struct SwihGeom {
   int32_t pitch;         // plane row pitch in elements (multiple of 64)
   int32_t nP, nI, nJ;    // planes, x terms, y terms
   int32_t gauss;         // 1 for the split Gaussian storage
+  int32_t ppg;           // planes per interleaved group
   int64_t plane_elems;   // (H + 1) * pitch
+  int64_t row_stride;    // ppg * pitch: from row Y to row Y + 1 of one plane
 };
+
+// Element offset of P[Y][X] of plane p, bin b.
+__host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, int Y, int X) {
+  const int grp = p / g.ppg, pj = p - grp * g.ppg;
+  return (((int64_t)(grp * g.B + b) * (g.H + 1) + Y) * g.ppg + pj) * g.pitch + 63 + X;
+}
 
 // Byte offsets inside one workspace.  All regions are 256-byte aligned.
 struct SwihLayout {

@@ -24,8 +24,9 @@
 namespace swih {
 namespace {
 
-__device__ __forceinline__ uint32_t at_u(const uint32_t* __restrict__ pl, int pitch, int Y, int X) {
-  return pl[(size_t)Y * pitch + 63 + X];
+// pl points at row 0, column 0 of a plane; rs is the plane's row stride.
+__device__ __forceinline__ uint32_t at_u(const uint32_t* __restrict__ pl, int64_t rs, int Y, int X) {
+  return pl[(size_t)Y * rs + X];
 }
 
 // Exact H_b of an integer kernel at (xc, yc) (uint32 arithmetic modulo 2^32).
@@ -33,16 +34,15 @@ template <int KIND>
 __device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes,
                                              const SwihGeom& g, int b, int xc, int yc,
                                              const ScaleParams& sp) {
-  const size_t pstride = (size_t)g.B * g.plane_elems;
-  const uint32_t* p0 = planes + (size_t)b * g.plane_elems;
+  const uint32_t* p0 = planes + swih_elem(g, 0, b, 0, 0);
   const int xa = xc - sp.rx, xb = xc + sp.rx + 1, ya = yc - sp.ry, yb = yc + sp.ry + 1;
   if (KIND == 0) {
-    return at_u(p0, g.pitch, yb, xb) - at_u(p0, g.pitch, ya, xb) - at_u(p0, g.pitch, yb, xa) +
-           at_u(p0, g.pitch, ya, xa);
+    return at_u(p0, g.row_stride, yb, xb) - at_u(p0, g.row_stride, ya, xb) - at_u(p0, g.row_stride, yb, xa) +
+           at_u(p0, g.row_stride, ya, xa);
   } else if (KIND == 1) {
     const int xm = xc + 1, ym = yc + 1;
-    const uint32_t* px = p0 + pstride;
-    const uint32_t* py = p0 + 2 * pstride;
+    const uint32_t* px = planes + swih_elem(g, 1, b, 0, 0);
+    const uint32_t* py = planes + swih_elem(g, 2, b, 0, 0);
     // 3 x 3 corner grid per plane
     uint32_t c1[3][3], cx[3][3], cy[3][3];
     const int Ys[3] = {ya, ym, yb}, Xs[3] = {xa, xm, xb};
@@ -50,9 +50,9 @@ __device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        c1[r][c] = at_u(p0, g.pitch, Ys[r], Xs[c]);
-        cx[r][c] = at_u(px, g.pitch, Ys[r], Xs[c]);
-        cy[r][c] = at_u(py, g.pitch, Ys[r], Xs[c]);
+        c1[r][c] = at_u(p0, g.row_stride, Ys[r], Xs[c]);
+        cx[r][c] = at_u(px, g.row_stride, Ys[r], Xs[c]);
+        cy[r][c] = at_u(py, g.row_stride, Ys[r], Xs[c]);
       }
     auto box = [](const uint32_t (&a)[3][3], int r, int c) {
       return a[r + 1][c + 1] - a[r][c + 1] - a[r + 1][c] + a[r][c];
@@ -67,9 +67,9 @@ __device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes
     uint32_t bx[5];
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
-      const uint32_t* pl = p0 + p * pstride;
-      bx[p] = at_u(pl, g.pitch, yb, xb) - at_u(pl, g.pitch, ya, xb) - at_u(pl, g.pitch, yb, xa) +
-              at_u(pl, g.pitch, ya, xa);
+      const uint32_t* pl = planes + swih_elem(g, p, b, 0, 0);
+      bx[p] = at_u(pl, g.row_stride, yb, xb) - at_u(pl, g.row_stride, ya, xb) - at_u(pl, g.row_stride, yb, xa) +
+              at_u(pl, g.row_stride, ya, xa);
     }
     const uint32_t X = (uint32_t)xc, Y = (uint32_t)yc;
     return (sp.c_int - X * X - Y * Y) * bx[0] + 2u * X * bx[1] + 2u * Y * bx[2] - bx[3] - bx[4];
@@ -133,11 +133,13 @@ __device__ __forceinline__ int first_cross(int ya, int TY) {
 
 // P[yb][X] - P[ya][X] of plane-bin pb from the tile-local split: the two L rows,
 // the L rows that close each band in between, and the row carries of X's tile.
-__device__ __forceinline__ double vdiff_g(const GaussPlanes& gp, const SwihGeom& g, size_t pb,
+__device__ __forceinline__ double vdiff_g(const GaussPlanes& gp, const SwihGeom& g, int p, int b,
                                           int ya, int yb, int X) {
-  const float* lp = gp.L + pb * g.plane_elems + 63 + X;
-  double d = (double)lp[(size_t)yb * g.pitch] - (double)lp[(size_t)ya * g.pitch];
-  for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) d += (double)lp[(size_t)c * g.pitch];
+  const float* lp = gp.L + swih_elem(g, p, b, 0, X);
+  const int64_t rs = g.row_stride;
+  double d = (double)lp[(size_t)yb * rs] - (double)lp[(size_t)ya * rs];
+  for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) d += (double)lp[(size_t)c * rs];
+  const size_t pb = (size_t)p * g.B + b;
   const double* rcp = gp.RC + (pb * g.NTX + tile_of(X)) * (size_t)(g.H + 1);
   return d + (rcp[yb] - rcp[ya]);
 }
@@ -176,8 +178,8 @@ __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp,
     double hi = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const size_t pb = (size_t)((i * NT + j) * g.B + b);
-      hi = fma(be[j], vdiff_g(gp, g, pb, ya, yb, xb) - vdiff_g(gp, g, pb, ya, yb, xa), hi);
+      const int p = i * NT + j;
+      hi = fma(be[j], vdiff_g(gp, g, p, b, ya, yb, xb) - vdiff_g(gp, g, p, b, ya, yb, xa), hi);
     }
     part[it] = al[i] * hi;
   }
@@ -189,57 +191,46 @@ __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp,
   }
 }
 
-// V_i(X) = sum_j beta_j (L_ij[yb][X] - L_ij[ya][X] + sum_c L_ij[c][X]) for the
-// x terms i = grp, grp + NG, ... of one bin; NC band-boundary rows c (NC < 0:
-// any number, looped).  All loads of one i are issued before any use.
-template <int NT, int NG, int NC>
-__device__ __forceinline__ void contract_rows(const GaussPlanes& gp, const SwihGeom& g, int b,
-                                              int grp, const double (&be)[NT], size_t offA,
-                                              size_t offB, size_t offC, int ncross, double* V,
-                                              int stride) {
-#pragma unroll
-  for (int ii = 0; ii < (NT + NG - 1) / NG; ++ii) {
-    const int i = grp + ii * NG;
-    if (i >= NT) break;
-    float la[NT], lb[NT], lc[NT > 0 ? NT : 1];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const float* lp = gp.L + (size_t)((i * NT + j) * g.B + b) * g.plane_elems;
-      la[j] = lp[offA];
-      lb[j] = lp[offB];
-      if (NC >= 1) lc[j] = lp[offC];
-    }
-    double v = 0.0;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      double d = (double)lb[j] - (double)la[j];
-      if (NC >= 1) d += (double)lc[j];
-      if (NC < 0) {
-        const float* lp = gp.L + (size_t)((i * NT + j) * g.B + b) * g.plane_elems;
-        for (int c = 0; c < ncross; ++c) d += (double)lp[offC + (size_t)c * g.TY * g.pitch];
-      }
-      v = fma(be[j], d, v);
-    }
-    V[i * stride] = v;
-  }
+// A block-uniform double made visibly uniform (kept in scalar registers).
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Dense map, one block per (row of centres yc, chunk of cw centres).  NG groups
-// of threads, one thread per (group, plane column X the chunk's windows touch:
-// X = xc - rx and xc + rx + 1).  For each bin the block contracts the y terms
-// of every plane between rows ya = yc - ry and yb = yc + ry + 1:
-//   V_i(X)  = sum_j beta_j(yc) (P_ij[yb][X] - P_ij[ya][X]) without the row carries
-//   R_i(tx) = sum_j beta_j(yc) (RC_ij[tx][yb] - RC_ij[tx][ya])   (per tile column)
-// into LDS (double-buffered across bins, one barrier per bin); each window then
-// needs H_b = sum_i alpha_i(xc) ((V_i + R_i)(xc + rx + 1) - (V_i + R_i)(xc - rx)).
+// One coefficient of the series at centre coordinate c: index 0 -> a_0,
+// 2k-1 -> a_k cos(2 pi k c / P), 2k -> a_k sin(2 pi k c / P).
+__device__ __forceinline__ double series_coeff(const GaussAxis& ax, int c, int idx) {
+  if (idx == 0) return ax.a[0];
+  const int k = (idx + 1) / 2;
+  const long ph = ((long)k * c) % ax.P;
+  const double ang = 2.0 * M_PI * (double)ph / (double)ax.P;
+  return ax.a[k] * ((idx & 1) ? cos(ang) : sin(ang));
+}
+
+// Dense map.  One block per (row of centres yc, chunk of cw centres); NG
+// groups of threads, one thread per (group, plane column X the chunk's windows
+// touch: X = xc - rx and xc + rx + 1).  With the y terms contracted,
+//   V_i(X) = sum_j beta_j(yc) (P_ij[yb][X] - P_ij[ya][X]),
+// the window histogram is H_b(xc) = sum_i alpha_i(xc) (V_i(xc+rx+1) - V_i(xc-rx)).
+// Each column therefore folds its own V_i into the two quantities the windows
+// need from it,
+//   G+(X) = sum_i alpha_i(X - rx - 1) V_i(X)   (X is a right edge)
+//   G-(X) = sum_i alpha_i(X + rx) V_i(X)       (X is a left edge),
+// and only those cross LDS: H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).  The row
+// carries of V_i depend on X only through its tile column and are tabulated
+// for every bin once per block.  Per bin: the column threads load their
+// L rows (all j of one i together), one barrier (LDS double-buffered by bin
+// parity), the window threads accumulate sqrt(p_b t_b).
 template <int NT, int NG>
 __global__ __launch_bounds__(1024) void k_match_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
                                                       const float* __restrict__ tmpl, int x0,
                                                       int y0, int x1, int cw, int nvpad,
                                                       int ntl_max, float* __restrict__ map) {
   extern __shared__ double sm[];
-  double* Vbuf = sm;                    // [2][NT][nvpad]
-  double* Rbuf = sm + 2 * NT * nvpad;   // [2][NT][ntl_max]
+  double* Gb = sm;                                  // [2][NG][2][nvpad]
+  double* R = sm + 2 * NG * 2 * nvpad;              // [B][NT][ntl_max]
   const int yc = y0 + blockIdx.y;
   const int xa = x0 + blockIdx.x * cw;
   const int cwc = min(cw, x1 - xa + 1);
@@ -251,54 +242,84 @@ __global__ __launch_bounds__(1024) void k_match_gauss(SwihGeom g, ScaleParams sp
   const int ncross = c0 < Yb ? (Yb - 1 - c0) / g.TY + 1 : 0;
   double be[NT];
   series_coeffs<NT>(sp.ay, yc, be);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) be[j] = uniform(be[j]);
   const int tid = threadIdx.x;
+  const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
+  // row-carry table of every bin: R[b][i][t] = sum_j beta_j (RC_ij[yb] - RC_ij[ya])
+  for (int it = tid; it < g.B * NT * ntl; it += blockDim.x) {
+    const int b = it / (NT * ntl);
+    const int rem = it - b * (NT * ntl);
+    const int i = rem / ntl, t = rem - (rem / ntl) * ntl;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const size_t pb = (size_t)((i * NT + j) * g.B + b);
+      const double* rcp = gp.RC + (pb * g.NTX + tlo + t) * (size_t)(g.H + 1);
+      acc = fma(be[j], rcp[Yb] - rcp[Ya], acc);
+    }
+    R[(b * NT + i) * ntl_max + t] = acc;
+  }
   const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
   const int xi = tid - grp * nvpad;
   const bool has_x = xi < nV;
   const int X = !has_x ? xa : (contig ? xa - rx + xi
                                       : (xi < cwc ? xa - rx + xi : xa + rx + 1 + xi - cwc));
-  const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
+  const int tX = tile_of(X) - tlo;
+  // alpha at the two windows this column serves, for this group's x terms
+  constexpr int NI = (NT + NG - 1) / NG;
+  double ap[NI], am[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int i = grp + ii * NG;
+    ap[ii] = i < NT ? series_coeff(sp.ax, max(X - rx - 1, 0), i) : 0.0;
+    am[ii] = i < NT ? series_coeff(sp.ax, X + rx, i) : 0.0;
+  }
+  const int64_t rs = g.row_stride;
+  const size_t offA = (size_t)Ya * rs + X, offB = (size_t)Yb * rs + X, offC = (size_t)c0 * rs + X;
   const bool win = tid < cwc;
   const int xc = xa + tid;
-  double al[NT];
-  series_coeffs<NT>(sp.ax, win ? xc : xa, al);
   const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
-  const int t1 = win ? tile_of(xc - rx) - tlo : 0, t2 = win ? tile_of(xc + rx + 1) - tlo : 0;
-  const size_t offA = (size_t)Ya * g.pitch + 63 + X, offB = (size_t)Yb * g.pitch + 63 + X;
-  const size_t offC = (size_t)c0 * g.pitch + 63 + X;
   const double inv_mass = 1.0 / sp.mass;
   double bc = 0.0;
+  __syncthreads();
   for (int b = 0; b < g.B; ++b) {
-    double* V = Vbuf + (b & 1) * NT * nvpad;
-    double* R = Rbuf + (b & 1) * NT * ntl_max;
+    double* Gp = Gb + (b & 1) * NG * 2 * nvpad;
     if (has_x) {
-      if (ncross == 0)
-        contract_rows<NT, NG, 0>(gp, g, b, grp, be, offA, offB, offC, 0, V + xi, nvpad);
-      else if (ncross == 1)
-        contract_rows<NT, NG, 1>(gp, g, b, grp, be, offA, offB, offC, 1, V + xi, nvpad);
-      else
-        contract_rows<NT, NG, -1>(gp, g, b, grp, be, offA, offB, offC, ncross, V + xi, nvpad);
-    }
-    for (int it = tid; it < NT * ntl; it += blockDim.x) {
-      const int i = it / ntl, t = it - (it / ntl) * ntl;
-      double r = 0.0;
+      double gplus = 0.0, gminus = 0.0;
+#pragma unroll 1
+      for (int ii = 0; ii < NI; ++ii) {
+        const int i = grp + ii * NG;
+        if (i >= NT) break;
+        const float* lp = gp.L + swih_elem(g, i * NT, b, 0, 0);
+        float la[NT], lb[NT];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const size_t pb = (size_t)((i * NT + j) * g.B + b);
-        const double* rcp = gp.RC + (pb * g.NTX + tlo + t) * (size_t)(g.H + 1);
-        r = fma(be[j], rcp[Yb] - rcp[Ya], r);
+        for (int j = 0; j < NT; ++j) {
+          la[j] = lp[offA + (size_t)j * g.pitch];
+          lb[j] = lp[offB + (size_t)j * g.pitch];
+        }
+        double v = R[(b * NT + i) * ntl_max + tX];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) v = fma(be[j], (double)lb[j] - (double)la[j], v);
+        for (int c = 0; c < ncross; ++c) {
+          float lc[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) lc[j] = lp[offC + (size_t)c * g.TY * rs + (size_t)j * g.pitch];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) v = fma(be[j], (double)lc[j], v);
+        }
+        gplus = fma(ap[ii], v, gplus);
+        gminus = fma(am[ii], v, gminus);
       }
-      R[i * ntl_max + t] = r;
+      Gp[(grp * 2 + 0) * nvpad + xi] = gplus;
+      Gp[(grp * 2 + 1) * nvpad + xi] = gminus;
     }
     __syncthreads();
     if (win) {
-      double h = 0.0;
+      double hh = 0.0;
 #pragma unroll
-      for (int i = 0; i < NT; ++i)
-        h = fma(al[i],
-                (V[i * nvpad + i2] + R[i * ntl_max + t2]) - (V[i * nvpad + i1] + R[i * ntl_max + t1]),
-                h);
-      bc += sqrt(fmax(h * inv_mass, 0.0) * fmax((double)tmpl[b], 0.0));
+      for (int q = 0; q < NG; ++q) hh += Gp[(q * 2 + 0) * nvpad + i2] - Gp[(q * 2 + 1) * nvpad + i1];
+      bc += sqrt(fmax(hh * inv_mass, 0.0) * fmax((double)tmpl[b], 0.0));
     }
   }
   if (win) map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)bc;
@@ -325,10 +346,7 @@ hipError_t match_gauss(const SwihLayout& L, const ScaleParams& sp, int set, cons
   constexpr int NG = 3;
   const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
   const int span = 2 * sp.rx + 1;
-  // columns per group: NG * maxV threads <= 1024 and the double-buffered V
-  // table within 60 KB of LDS
-  int maxV = (60000 / (16 * NT)) / 64 * 64;
-  if (maxV > 320) maxV = 320;
+  const int maxV = 320;  // NG * maxV threads <= 1024
   int cw, nV;
   if (span <= maxV / 2) {  // one contiguous column range: nV = cw + span
     const int cwmax = maxV - span;
@@ -341,11 +359,12 @@ hipError_t match_gauss(const SwihLayout& L, const ScaleParams& sp, int set, cons
   }
   const int nvpad = (nV + 63) / 64 * 64;
   const int ntl_max = (cw + span + 63) / 64 + 2;  // tile columns one block can touch
-  const size_t lds = sizeof(double) * (size_t)2 * NT * (nvpad + ntl_max);
+  const size_t lds =
+      sizeof(double) * ((size_t)2 * NG * 2 * nvpad + (size_t)L.g.B * NT * ntl_max);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   const unsigned nch = (unsigned)((nx + cw - 1) / cw);
   hipLaunchKernelGGL((k_match_gauss<NT, NG>), dim3(nch, (unsigned)ny), dim3(NG * nvpad), lds, s,
-                     L.g, sp, gauss_planes(L, set, ws), tmpl, x0, y0, x1, cw, nvpad, ntl_max,
-                     map);
+                     L.g, sp, gauss_planes(L, set, ws), tmpl, x0, y0, x1, cw, nvpad, ntl_max, map);
   return hipGetLastError();
 }
 
