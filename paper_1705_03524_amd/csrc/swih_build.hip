@@ -110,25 +110,27 @@ __global__ __launch_bounds__(WG) void k_aggregate_int(const uint8_t* __restrict_
   if (!wave_tile(g, wave_index(), 1, t, e)) return;
   const int lane = lane_id();
   const int NXP = g.NTX * SWIH_TX;
-  uint32_t zacc[TT::nJ], treg[TT::nI], u[TT::nI];
+  uint32_t zacc[TT::nJ], treg[TT::nI];
 #pragma unroll
   for (int j = 0; j < TT::nJ; ++j) zacc[j] = 0;
 #pragma unroll
-  for (int i = 0; i < TT::nI; ++i) {
-    treg[i] = 0;
-    u[i] = poly_term(i, (uint32_t)t.x);
-  }
+  for (int i = 0; i < TT::nI; ++i) treg[i] = 0;
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
+  // column sums of this lane's column over the band's rows
   for (int k = 0; k < t.nrows; ++k) {
     const uint32_t y = (uint32_t)(t.y0 + k);
     const uint32_t m = bit_of(mask, k);
 #pragma unroll
     for (int j = 0; j < TT::nJ; ++j) zacc[j] += m * poly_term(j, y);
+  }
+  // row sums, transposed: lane k gathers row y0 + k over the tile's 64 columns
+  for (int l = 0; l < 64; ++l) {
+    const uint64_t ml = ((uint64_t)readlane((uint32_t)(mask >> 32), l) << 32) |
+                        readlane((uint32_t)mask, l);
+    const uint32_t bit = bit_of(ml, lane);
+    const uint32_t xl = (uint32_t)(t.tx * SWIH_TX + l);
 #pragma unroll
-    for (int i = 0; i < TT::nI; ++i) {
-      const uint32_t s = wave_sum(m * u[i]);
-      treg[i] = put_lane(treg[i], s, k);
-    }
+    for (int i = 0; i < TT::nI; ++i) treg[i] += bit * poly_term(i, xl);
   }
 #pragma unroll
   for (int j = 0; j < TT::nJ; ++j)
@@ -147,57 +149,73 @@ __global__ __launch_bounds__(WG) void k_aggregate_int(const uint8_t* __restrict_
   }
 }
 
-// Exclusive prefixes of the aggregates (all three roles in one launch).
+// Exclusive prefixes of the aggregates, three roles in one launch:
+//   blocks [0, nb1)          thread per column: carry row above each band
+//                            (exclusive prefix of z over bands; integer kernels)
+//   blocks [nb1, nb1 + nb2)  thread per row: carry left of each tile
+//                            (exclusive prefix of T over tiles)
+//   remaining blocks         wave per (plane, bin): value at each tile origin,
+//                            the 2-D exclusive prefix of the tile totals.
+// Each serial walk loads its next 8 values before storing, so the loads of a
+// thread overlap.
+template <typename V>
+__device__ __forceinline__ void excl_walk(V* p, long stride, int n) {
+  V run = 0;
+  int k = 0;
+  for (; k + 8 <= n; k += 8) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(k + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      p[(k + u) * stride] = run;
+      run += v[u];
+    }
+  }
+  for (; k < n; ++k) {
+    const V v = p[k * stride];
+    p[k * stride] = run;
+    run += v;
+  }
+}
+
 template <typename ZT, typename TTy, typename BTy>
 __global__ __launch_bounds__(WG) void k_scan(SwihGeom g, ZT* __restrict__ z,
                                              TTy* __restrict__ T, BTy* __restrict__ BT,
-                                             int with_z) {
-  long t = (long)blockIdx.x * WG + threadIdx.x;
+                                             int nb1, int nb2) {
+  __shared__ BTy rowcarry[WPB][128];
   const int NXP = g.NTX * SWIH_TX;
-  const long n1 = with_z ? (long)g.nJ * g.B * NXP : 0;
-  const long n2 = (long)g.nI * g.B * g.H;
-  const long n3 = (long)g.nP * g.B;
-  if (t < n1) {  // carry row above each band: exclusive over bands
+  if ((int)blockIdx.x < nb1) {
+    const long t = (long)blockIdx.x * WG + threadIdx.x;
+    if (t >= (long)g.nJ * g.B * NXP) return;
     const long col = t % NXP, jb = t / NXP;
-    ZT* base = z + (size_t)jb * g.NTY * NXP + col;
-    ZT run = 0;
-    for (int ty = 0; ty < g.NTY; ++ty) {
-      const ZT v = base[(size_t)ty * NXP];
-      base[(size_t)ty * NXP] = run;
-      run += v;
-    }
+    excl_walk(z + (size_t)jb * g.NTY * NXP + col, NXP, g.NTY);
     return;
   }
-  t -= n1;
-  if (t < n2) {  // carry column left of each tile: exclusive over tiles
+  if ((int)blockIdx.x < nb1 + nb2) {
+    const long t = (long)(blockIdx.x - nb1) * WG + threadIdx.x;
+    if (t >= (long)g.nI * g.B * g.H) return;
     const long y = t % g.H, ib = t / g.H;
-    TTy* base = T + (size_t)ib * g.NTX * g.H + y;
-    TTy run = 0;
-    for (int tx = 0; tx < g.NTX; ++tx) {
-      const TTy v = base[(size_t)tx * g.H];
-      base[(size_t)tx * g.H] = run;
-      run += v;
-    }
+    excl_walk(T + (size_t)ib * g.NTX * g.H + y, g.H, g.NTX);
     return;
   }
-  t -= n2;
-  if (t < n3) {  // value at each tile's origin corner: 2-D exclusive prefix
-    BTy* base = BT + (size_t)t * g.NTY * g.NTX;
-    for (int tx = 0; tx < g.NTX; ++tx) {
-      BTy run = 0;
-      for (int ty = 0; ty < g.NTY; ++ty) {
-        const BTy v = base[(size_t)ty * g.NTX + tx];
-        base[(size_t)ty * g.NTX + tx] = run;
-        run += v;
-      }
-    }
+  const int w = (int)(threadIdx.x >> 6);
+  const long pbi = (long)(blockIdx.x - nb1 - nb2) * WPB + __builtin_amdgcn_readfirstlane(w);
+  if (pbi >= (long)g.nP * g.B) return;
+  BTy* base = BT + (size_t)pbi * g.NTY * g.NTX;
+  const int lane = lane_id();
+  for (int ty = lane; ty < g.NTY; ty += 64) rowcarry[w][ty] = 0;
+  for (int c0 = 0; c0 < g.NTX; c0 += 64) {
+    const int tx = c0 + lane;
+    const bool ok = tx < g.NTX;
+    BTy run = 0;
     for (int ty = 0; ty < g.NTY; ++ty) {
-      BTy run = 0;
-      for (int tx = 0; tx < g.NTX; ++tx) {
-        const BTy v = base[(size_t)ty * g.NTX + tx];
-        base[(size_t)ty * g.NTX + tx] = run;
-        run += v;
-      }
+      const BTy v = ok ? base[(size_t)ty * g.NTX + tx] : (BTy)0;
+      const BTy inc = wave_incl_scan(run);
+      const BTy carry = rowcarry[w][ty];
+      if (ok) base[(size_t)ty * g.NTX + tx] = carry + inc - run;
+      rowcarry[w][ty] = carry + readlane(inc, 63);
+      run += v;
     }
   }
 }
@@ -260,7 +278,7 @@ __global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img
 }
 
 // ---------------------------------------------------------------- Gaussian
-// Fixed-point weight terms: uq[i][x] (x < NTX*64, zero beyond W), vq[y][j],
+// Fixed-point weight terms: uq[x][i] (x < NTX*64, zero beyond W), vq[y][j],
 // and vqd[y][j] = vq * 2^-48 as double (scales the u*v product to real units).
 __global__ __launch_bounds__(WG) void k_basis(SwihGeom g, GaussAxis ax, GaussAxis ay,
                                               int32_t* __restrict__ uq, int32_t* __restrict__ vq,
@@ -282,7 +300,7 @@ __global__ __launch_bounds__(WG) void k_basis(SwihGeom g, GaussAxis ax, GaussAxi
         val = (i & 1) ? cos(ang) : sin(ang);
       }
     }
-    uq[(size_t)i * NXP + x] = (int32_t)rint(val * fix);
+    uq[(size_t)x * g.nI + i] = (int32_t)rint(val * fix);
   } else if (t < nu + nv) {
     const long r = t - nu;
     const int y = (int)(r / g.nJ), j = (int)(r % g.nJ);
@@ -312,21 +330,19 @@ __global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restric
   int e;
   if (!wave_tile(g, wave_index(), 1, t, e)) return;
   const int lane = lane_id();
-  const int NXP = g.NTX * SWIH_TX;
-  int32_t uqx[NT], treg[NT];
+    int32_t treg[NT];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    uqx[i] = uq[(size_t)i * NXP + t.x];
-    treg[i] = 0;
-  }
+  for (int i = 0; i < NT; ++i) treg[i] = 0;
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
-  for (int k = 0; k < t.nrows; ++k) {
-    const bool m = bit_of(mask, k) != 0;
+  // row sums, transposed: lane k gathers row y0 + k over the tile's 64 columns
+  const int32_t* ucol = uq + (size_t)t.tx * SWIH_TX * NT;
+  for (int l = 0; l < 64; ++l) {
+    const uint64_t ml = ((uint64_t)readlane((uint32_t)(mask >> 32), l) << 32) |
+                        readlane((uint32_t)mask, l);
+    const bool bit = bit_of(ml, lane) != 0;
+    const int32_t* ul = ucol + l * NT;
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const int32_t s = wave_sum(m ? uqx[i] : 0);
-      treg[i] = put_lane(treg[i], s, k);
-    }
+    for (int i = 0; i < NT; ++i) treg[i] += bit ? ul[i] : 0;
   }
   if (lane < t.nrows) {
 #pragma unroll
@@ -359,9 +375,8 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
   int i;
   if (!wave_tile(g, wave_index(), NT, t, i)) return;
   const int lane = lane_id();
-  const int NXP = g.NTX * SWIH_TX;
-  const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
-  const int32_t uqi = uq[(size_t)i * NXP + t.x];
+    const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
+  const int32_t uqi = uq[(size_t)t.x * NT + i];
   const int64_t ereg =
       lane < t.nrows ? E[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] : 0;
   size_t lbase[NT];
@@ -429,10 +444,11 @@ hipError_t build_int(const SwihLayout& L, const uint8_t* img, int ipitch, char* 
   if (phases & 1) {
     hipLaunchKernelGGL(k_aggregate_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
                        ipitch, g, z, T, BT);
-    const long nscan = (long)g.nJ * g.B * g.NTX * SWIH_TX + (long)g.nI * g.B * g.H +
-                       (long)g.nP * g.B;
-    hipLaunchKernelGGL((k_scan<uint32_t, uint32_t, uint32_t>), dim3(blocks_for_threads(nscan)),
-                       dim3(WG), 0, s, g, z, T, BT, 1);
+    const int nb1 = (int)blocks_for_threads((long)g.nJ * g.B * g.NTX * SWIH_TX);
+    const int nb2 = (int)blocks_for_threads((long)g.nI * g.B * g.H);
+    const int nb3 = (int)blocks_for_waves((long)g.nP * g.B);
+    hipLaunchKernelGGL((k_scan<uint32_t, uint32_t, uint32_t>), dim3(nb1 + nb2 + nb3), dim3(WG), 0,
+                       s, g, z, T, BT, nb1, nb2);
   }
   if (phases & 2)
     hipLaunchKernelGGL(k_emit_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
@@ -459,9 +475,10 @@ hipError_t build_gauss(const SwihLayout& L, int set, const GaussAxis& ax, const 
                        vq, vqd);
     hipLaunchKernelGGL(k_aggregate_gauss<NT>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s,
                        img, ipitch, g, uq, vq, T, BT);
-    const long nscan = (long)g.nI * g.B * g.H + (long)g.nP * g.B;
-    hipLaunchKernelGGL((k_scan<int64_t, int64_t, double>), dim3(blocks_for_threads(nscan)),
-                       dim3(WG), 0, s, g, (int64_t*)nullptr, T, BT, 0);
+    const int nb2 = (int)blocks_for_threads((long)g.nI * g.B * g.H);
+    const int nb3 = (int)blocks_for_waves((long)g.nP * g.B);
+    hipLaunchKernelGGL((k_scan<int64_t, int64_t, double>), dim3(nb2 + nb3), dim3(WG), 0, s, g,
+                       (int64_t*)nullptr, T, BT, 0, nb2);
   }
   if (phases & 2)
     hipLaunchKernelGGL(k_emit_gauss<NT>, dim3(blocks_for_waves(waves * NT)), dim3(WG), 0, s,

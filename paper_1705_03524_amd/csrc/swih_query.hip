@@ -131,19 +131,6 @@ __device__ __forceinline__ int first_cross(int ya, int TY) {
   return c == 0 ? TY : c;
 }
 
-// P[yb][X] - P[ya][X] of plane-bin pb from the tile-local split: the two L rows,
-// the L rows that close each band in between, and the row carries of X's tile.
-__device__ __forceinline__ double vdiff_g(const GaussPlanes& gp, const SwihGeom& g, int p, int b,
-                                          int ya, int yb, int X) {
-  const float* lp = gp.L + swih_elem(g, p, b, 0, X);
-  const int64_t rs = g.row_stride;
-  double d = (double)lp[(size_t)yb * rs] - (double)lp[(size_t)ya * rs];
-  for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) d += (double)lp[(size_t)c * rs];
-  const size_t pb = (size_t)p * g.B + b;
-  const double* rcp = gp.RC + (pb * g.NTX + tile_of(X)) * (size_t)(g.H + 1);
-  return d + (rcp[yb] - rcp[ya]);
-}
-
 template <int NT>
 __device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double (&out)[NT]) {
   out[0] = ax.a[0];
@@ -173,13 +160,40 @@ __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp,
   series_coeffs<NT>(sp.ax, xc, al);
   series_coeffs<NT>(sp.ay, yc, be);
   const int xa = xc - sp.rx, xb = xc + sp.rx + 1, ya = yc - sp.ry, yb = yc + sp.ry + 1;
+  const int64_t rs = g.row_stride;
+  const int txa = tile_of(xa), txb = tile_of(xb);
   for (int it = threadIdx.x; it < g.B * NT; it += blockDim.x) {
     const int b = it / NT, i = it - (it / NT) * NT;
+    // the NT y-term planes of x term i are row-interleaved: plane j at + j * pitch
+    const float* lp = gp.L + swih_elem(g, i * NT, b, 0, 0);
+    float aA[NT], bA[NT], aB[NT], bB[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const float* q = lp + (size_t)j * g.pitch;
+      aA[j] = q[(size_t)ya * rs + xa];
+      bA[j] = q[(size_t)yb * rs + xa];
+      aB[j] = q[(size_t)ya * rs + xb];
+      bB[j] = q[(size_t)yb * rs + xb];
+    }
+    double d[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      d[j] = ((double)bB[j] - (double)aB[j]) - ((double)bA[j] - (double)aA[j]);
+    for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const float* q = lp + (size_t)j * g.pitch + (size_t)c * rs;
+        d[j] += (double)q[xb] - (double)q[xa];
+      }
+    }
     double hi = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const int p = i * NT + j;
-      hi = fma(be[j], vdiff_g(gp, g, p, b, ya, yb, xb) - vdiff_g(gp, g, p, b, ya, yb, xa), hi);
+      const size_t pb = (size_t)((i * NT + j) * g.B + b);
+      const double* rA = gp.RC + (pb * g.NTX + txa) * (size_t)(g.H + 1);
+      const double* rB = gp.RC + (pb * g.NTX + txb) * (size_t)(g.H + 1);
+      d[j] += (rB[yb] - rB[ya]) - (rA[yb] - rA[ya]);
+      hi = fma(be[j], d[j], hi);
     }
     part[it] = al[i] * hi;
   }
