@@ -20,6 +20,14 @@ class Plan:
         self.device = self.ws.device
 
     @property
+    def nplanes(self) -> int:
+        """Weight terms per bin: 1 uniform, 3 Manhattan, 5 Euclidean, (2K+1)^2 Gaussian."""
+        if self.cfg.kernel == S.GAUSSIAN:
+            k = self.cfg.gauss_terms or 4
+            return (2 * k + 1) ** 2
+        return {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5}[self.cfg.kernel]
+
+    @property
     def integer(self) -> bool:
         return self.cfg.kernel != S.GAUSSIAN
 
