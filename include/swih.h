@@ -125,9 +125,9 @@ int swih_build(const swih_config* cfg, const uint8_t* d_img, int32_t height, int
  *                       carries: exactly one kernel launch.
  *   set     0 for integer kernels; the scale index for the Gaussian, whose
  *           planes are per scale.
- * The carries live in a scratch region shared by all sets, so a set's planes
- * must follow its own carries on the stream with no other set's carries in
- * between.  Errors as swih_build, plus SWIH_ERR_INVALID for a bad set.
+ * Each set keeps its own carries, so a set's planes need only follow its own
+ * carries on the stream.  Errors as swih_build, plus SWIH_ERR_INVALID for a
+ * bad set.
  */
 int swih_build_carries(const swih_config* cfg, const uint8_t* d_img, int32_t height,
                        int32_t width, int32_t pitch, int32_t set, void* d_ws, size_t ws_bytes,
@@ -166,6 +166,66 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
 int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
                int32_t width, int32_t scale_idx, const float* d_template,
                const uint32_t* d_template_raw, swih_rect centres, float* d_map, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form.  Sec. 4 applies the likelihood maps to many targets over the
+ * frames of a tracking sequence; a batch builds many frames (or search-region
+ * crops) of different sizes, queries their templates and computes their maps
+ * with one grid-stride launch per stage, so uneven work fills the GPU and the
+ * whole batch can be captured once in a HIP graph and replayed.
+ *
+ * The plan is pure host work: swih_batch_plan checks every descriptor and
+ * writes a table that names all device buffers and launch sizes.  The caller
+ * copies the table byte for byte to device memory (256-byte aligned) and
+ * passes both copies to the launches, which read the host copy for launch
+ * sizes and the device copy in the kernels.  The device copy must stay valid
+ * while the launches run.  Every frame's result is a function of that frame
+ * alone: the same as a single swih_build / swih_query / swih_match of it,
+ * whatever else is in the batch.
+ */
+typedef struct {
+  const uint8_t* d_img;      /* device: frame or crop origin, height rows of pitch bytes */
+  int32_t height, width, pitch;
+  int32_t nscales;           /* 0: the configuration's scales; else this frame's own */
+  const swih_scale* scales;  /* host, nscales entries (read by swih_batch_plan only) */
+  void* d_ws;                /* device workspace of this frame, 256-byte aligned */
+  size_t ws_bytes;           /* >= swih_workspace_bytes of the frame's configuration */
+} swih_frame_desc;
+
+typedef struct {
+  int32_t frame, scale_idx;  /* frame index and the frame's scale */
+  const int32_t* d_centres;  /* device int32 [n][2] */
+  int32_t n;
+  float* d_hist;             /* device float [n][nbins] or NULL */
+  uint32_t* d_hist_raw;      /* device uint32 [n][nbins] or NULL (integer kernels) */
+} swih_query_desc;
+
+typedef struct {
+  int32_t frame, scale_idx;
+  swih_rect centres;         /* inclusive, within the scale's valid range */
+  const float* d_template;   /* exactly one of the two templates, as swih_match */
+  const uint32_t* d_template_raw;
+  float* d_map;              /* device float, rectangle-sized, row-major */
+} swih_match_desc;
+
+/* Bytes of the table for this batch (or a negative status). */
+int64_t swih_batch_table_bytes(const swih_config* cfg, const swih_frame_desc* frames,
+                               int32_t nframes, int32_t nqueries, int32_t nmatches);
+
+/*
+ * Check the batch and write its table into h_table (host, table_bytes).
+ * Errors as the single-frame calls; SWIH_ERR_WORKSPACE if a frame's workspace
+ * or the table is too small.  Queries and maps name a frame and one of its scales.
+ */
+int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32_t nframes,
+                    const swih_query_desc* queries, int32_t nqueries,
+                    const swih_match_desc* matches, int32_t nmatches, void* h_table,
+                    size_t table_bytes);
+
+/* Launch the batch's builds (4 launches), queries (1) or maps (1) on `stream`. */
+int swih_build_batch(const void* h_table, const void* d_table, void* stream);
+int swih_query_batch(const void* h_table, const void* d_table, void* stream);
+int swih_match_batch(const void* h_table, const void* d_table, void* stream);
 
 /*
  * The cosine series that stands in for one axis of the Gaussian kernel:

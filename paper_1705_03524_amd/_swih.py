@@ -21,7 +21,9 @@ KERNELS = {"uniform": UNIFORM, "manhattan": MANHATTAN, "euclidean": EUCLIDEAN, "
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
 
 EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_build_planes",
-            "swih_query", "swih_match", "swih_gauss_terms", "swih_status_string")
+            "swih_query", "swih_match", "swih_batch_table_bytes", "swih_batch_plan",
+            "swih_build_batch", "swih_query_batch", "swih_match_batch", "swih_gauss_terms",
+            "swih_status_string")
 
 
 class SwihError(RuntimeError):
@@ -41,6 +43,22 @@ class _Config(C.Structure):
 
 class _Rect(C.Structure):
     _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32)]
+
+
+class _FrameDesc(C.Structure):
+    _fields_ = [("d_img", C.c_void_p), ("height", C.c_int32), ("width", C.c_int32),
+                ("pitch", C.c_int32), ("nscales", C.c_int32), ("scales", C.POINTER(_Scale)),
+                ("d_ws", C.c_void_p), ("ws_bytes", C.c_size_t)]
+
+
+class _QueryDesc(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("scale_idx", C.c_int32), ("d_centres", C.c_void_p),
+                ("n", C.c_int32), ("d_hist", C.c_void_p), ("d_hist_raw", C.c_void_p)]
+
+
+class _MatchDesc(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("scale_idx", C.c_int32), ("centres", _Rect),
+                ("d_template", C.c_void_p), ("d_template_raw", C.c_void_p), ("d_map", C.c_void_p)]
 
 
 _lib = None
@@ -68,6 +86,15 @@ def load():
     lib.swih_query.restype = C.c_int
     lib.swih_match.argtypes = [cfgp, vp, sz, i32, i32, i32, vp, vp, _Rect, vp, vp]
     lib.swih_match.restype = C.c_int
+    lib.swih_batch_table_bytes.argtypes = [cfgp, C.POINTER(_FrameDesc), i32, i32, i32]
+    lib.swih_batch_table_bytes.restype = C.c_int64
+    lib.swih_batch_plan.argtypes = [cfgp, C.POINTER(_FrameDesc), i32, C.POINTER(_QueryDesc), i32,
+                                    C.POINTER(_MatchDesc), i32, vp, sz]
+    lib.swih_batch_plan.restype = C.c_int
+    for name in ("swih_build_batch", "swih_query_batch", "swih_match_batch"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp]
+        f.restype = C.c_int
     lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
     lib.swih_gauss_terms.restype = C.c_int
@@ -180,3 +207,60 @@ def gauss_terms(n: int, K: int = 4):
     if st != OK:
         raise SwihError(st, "swih_gauss_terms")
     return list(a), int(P.value), float(e.value)
+
+
+def batch_plan(cfg: Config, frames, queries, matches):
+    """Plan a batch (host work only).
+
+    frames: list of dicts with ``img`` (2-D uint8 device tensor, possibly a
+    strided crop view), ``ws`` (uint8 device tensor), optional ``scales``.
+    queries: dicts with ``frame``, ``scale_idx``, ``centres`` (int32 [n, 2]
+    device), ``hist`` and/or ``hist_raw`` outputs.  matches: dicts with
+    ``frame``, ``scale_idx``, ``rect``, ``template`` or ``template_raw``,
+    ``out``.  Returns the host table as a numpy uint8 array.
+    """
+    import numpy as np
+    lib = load()
+    keep = []
+    fd = (_FrameDesc * max(1, len(frames)))()
+    for k, f in enumerate(frames):
+        img = f["img"]
+        sc = f.get("scales")
+        arr = None
+        if sc:
+            arr = (_Scale * len(sc))(*[_Scale(int(w), int(h)) for w, h in sc])
+            keep.append(arr)
+        fd[k] = _FrameDesc(img.data_ptr(), int(img.shape[0]), int(img.shape[1]), int(img.stride(0)),
+                           len(sc) if sc else 0, C.cast(arr, C.POINTER(_Scale)) if arr else None,
+                           f["ws"].data_ptr(), f["ws"].numel())
+    qd = (_QueryDesc * max(1, len(queries)))()
+    for k, q in enumerate(queries):
+        c = q["centres"]
+        qd[k] = _QueryDesc(int(q["frame"]), int(q.get("scale_idx", 0)), c.data_ptr() if c.numel() else None,
+                           int(c.shape[0]), q["hist"].data_ptr() if q.get("hist") is not None else None,
+                           q["hist_raw"].data_ptr() if q.get("hist_raw") is not None else None)
+    md = (_MatchDesc * max(1, len(matches)))()
+    for k, m in enumerate(matches):
+        md[k] = _MatchDesc(int(m["frame"]), int(m.get("scale_idx", 0)), _Rect(*[int(v) for v in m["rect"]]),
+                           m["template"].data_ptr() if m.get("template") is not None else None,
+                           m["template_raw"].data_ptr() if m.get("template_raw") is not None else None,
+                           m["out"].data_ptr())
+    c = cfg.c()
+    n = lib.swih_batch_table_bytes(C.byref(c), fd, len(frames), len(queries), len(matches))
+    if n < 0:
+        raise SwihError(int(n), "swih_batch_table_bytes")
+    table = np.zeros(int(n), np.uint8)
+    st = lib.swih_batch_plan(C.byref(c), fd, len(frames), qd, len(queries), md, len(matches),
+                             table.ctypes.data_as(C.c_void_p), table.nbytes)
+    if st != OK:
+        raise SwihError(st, "swih_batch_plan")
+    return table
+
+
+def batch_launch(which: str, h_table, d_table, stream=None):
+    """``which`` = "build", "query" or "match": launch that part of a planned batch."""
+    fn = {"build": load().swih_build_batch, "query": load().swih_query_batch,
+          "match": load().swih_match_batch}[which]
+    st = fn(h_table.ctypes.data_as(C.c_void_p), C.c_void_p(d_table.data_ptr()), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_%s_batch" % which)

@@ -1,6 +1,8 @@
 // C ABI of libswih.so: argument checks, workspace layout and launches.
 #include <string.h>
 
+#include <vector>
+
 #include "swih.h"
 #include "swih_internal.h"
 
@@ -79,10 +81,8 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     L.off_vq = off;  // int32 [H][nJ], then double [H][nJ]
     off += swih_align256((int64_t)g.nJ * H * 4) + swih_align256((int64_t)g.nJ * H * 8);
   }
-  L.set_bytes = off;
-  L.nsets = gauss ? c->nscales : 1;
+  // build scratch (carries), inside the set so that sets never share it
   const int64_t esz = gauss ? 8 : 4;
-  off = L.set_bytes * L.nsets;
   L.off_scratch = off;
   L.off_z = off;
   if (!gauss) off += swih_align256((int64_t)g.nJ * g.B * g.NTY * NXP * esz);
@@ -90,6 +90,9 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   off += swih_align256((int64_t)g.nI * g.B * g.NTX * (int64_t)H * esz);
   L.off_CT = off;
   off += swih_align256(PB * g.NTY * g.NTX * esz);
+  L.set_bytes = off;
+  L.nsets = gauss ? c->nscales : 1;
+  off = L.set_bytes * L.nsets;
   L.total = off;
   return SWIH_OK;
 }
@@ -243,6 +246,225 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
   return launch_match(L, sp, set, (const char*)d_ws, d_template, d_template_raw, r.x0, r.y0, r.x1,
                       r.y1, d_map, (hipStream_t)stream) == hipSuccess
+             ? SWIH_OK
+             : SWIH_ERR_HIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+namespace {
+
+constexpr uint32_t kBatchMagic = 0x53574842u;  // "SWHB"
+constexpr int kBatchGrid = 4096;               // blocks per grid-stride launch
+
+struct BatchHeader {
+  uint32_t magic;
+  int32_t kind, nt, nbins;
+  int32_t nunits, nq, nm;
+  int32_t total[4];   // build-stage virtual blocks
+  Launch ql, ml;      // query / map launch shapes (blocks = total virtual blocks)
+  int64_t off_units, off_uprefix, off_q, off_qprefix, off_m, off_mprefix, bytes;
+};
+
+int32_t frame_units(const swih_config* cfg, const swih_frame_desc& f) {
+  if (cfg->kernel != SWIH_GAUSSIAN) return 1;
+  return f.nscales > 0 ? f.nscales : cfg->nscales;
+}
+
+// Offsets of every table section for the given counts.
+BatchHeader table_layout(int32_t nunits, int32_t nq, int32_t nm) {
+  BatchHeader h;
+  memset(&h, 0, sizeof(h));
+  int64_t off = swih_align256(sizeof(BatchHeader));
+  h.off_units = off;
+  off += swih_align256((int64_t)nunits * sizeof(BuildArgs));
+  h.off_uprefix = off;
+  off += swih_align256((int64_t)4 * (nunits + 1) * sizeof(int32_t));
+  h.off_q = off;
+  off += swih_align256((int64_t)nq * sizeof(QueryArgs));
+  h.off_qprefix = off;
+  off += swih_align256((int64_t)(nq + 1) * sizeof(int32_t));
+  h.off_m = off;
+  off += swih_align256((int64_t)nm * sizeof(MatchArgs));
+  h.off_mprefix = off;
+  off += swih_align256((int64_t)(nm + 1) * sizeof(int32_t));
+  h.bytes = off;
+  h.nunits = nunits;
+  h.nq = nq;
+  h.nm = nm;
+  return h;
+}
+
+// The frame's own configuration: the batch configuration with its scales.
+swih_config frame_config(const swih_config* cfg, const swih_frame_desc& f) {
+  swih_config c = *cfg;
+  if (f.nscales > 0) {
+    c.nscales = f.nscales;
+    c.scales = f.scales;
+  }
+  return c;
+}
+
+const BatchHeader* header_of(const void* h_table) {
+  const BatchHeader* h = (const BatchHeader*)h_table;
+  return (h && h->magic == kBatchMagic) ? h : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t swih_batch_table_bytes(const swih_config* cfg, const swih_frame_desc* frames,
+                               int32_t nframes, int32_t nqueries, int32_t nmatches) {
+  if (!cfg || nframes < 0 || nqueries < 0 || nmatches < 0 || (nframes > 0 && !frames))
+    return SWIH_ERR_INVALID;
+  int64_t nunits = 0;
+  for (int f = 0; f < nframes; ++f) nunits += frame_units(cfg, frames[f]);
+  if (nunits > (1 << 24)) return SWIH_ERR_INVALID;
+  return table_layout((int32_t)nunits, nqueries, nmatches).bytes;
+}
+
+int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32_t nframes,
+                    const swih_query_desc* queries, int32_t nqueries,
+                    const swih_match_desc* matches, int32_t nmatches, void* h_table,
+                    size_t table_bytes) {
+  if (!cfg || !h_table || nframes < 0 || nqueries < 0 || nmatches < 0) return SWIH_ERR_INVALID;
+  if ((nframes > 0 && !frames) || (nqueries > 0 && !queries) || (nmatches > 0 && !matches))
+    return SWIH_ERR_INVALID;
+  const int64_t need = swih_batch_table_bytes(cfg, frames, nframes, nqueries, nmatches);
+  if (need < 0) return (int)need;
+  if ((int64_t)table_bytes < need) return SWIH_ERR_WORKSPACE;
+  const bool gauss = cfg->kernel == SWIH_GAUSSIAN;
+  // frames: check, lay out, and fill one build unit per plane set
+  std::vector<SwihLayout> layouts(nframes);
+  std::vector<int32_t> ubase(nframes + 1, 0);
+  for (int f = 0; f < nframes; ++f) {
+    const swih_frame_desc& fd = frames[f];
+    const swih_config fc = frame_config(cfg, fd);
+    int st = check_config(&fc, fd.height, fd.width);
+    if (st != SWIH_OK) return st;
+    if (!fd.d_img || !fd.d_ws || fd.pitch < fd.width || !aligned256(fd.d_ws)) return SWIH_ERR_INVALID;
+    if (fd.nscales > 0 && !fd.scales) return SWIH_ERR_INVALID;
+    make_layout(&fc, fd.height, fd.width, layouts[f]);
+    if ((int64_t)fd.ws_bytes < layouts[f].total) return SWIH_ERR_WORKSPACE;
+    for (int k = 0; k < fc.nscales; ++k) {
+      ScaleParams sp;
+      st = scale_params(&fc, k, sp);
+      if (st != SWIH_OK) return st;
+    }
+    ubase[f + 1] = ubase[f] + frame_units(cfg, fd);
+  }
+  const int32_t nunits = ubase[nframes];
+  BatchHeader h = table_layout(nunits, nqueries, nmatches);
+  h.magic = kBatchMagic;
+  h.kind = cfg->kernel;
+  h.nt = gauss ? 2 * gauss_K(cfg) + 1 : 0;
+  h.nbins = cfg->nbins;
+  char* tb = (char*)h_table;
+  memset(tb, 0, (size_t)h.bytes);
+  BuildArgs* units = (BuildArgs*)(tb + h.off_units);
+  int32_t* upre = (int32_t*)(tb + h.off_uprefix);
+  for (int f = 0; f < nframes; ++f) {
+    const swih_frame_desc& fd = frames[f];
+    const swih_config fc = frame_config(cfg, fd);
+    for (int k = 0; k < ubase[f + 1] - ubase[f]; ++k) {
+      const int u = ubase[f] + k;
+      ScaleParams sp;
+      scale_params(&fc, gauss ? k : 0, sp);
+      int32_t nb[4];
+      build_args(layouts[f], k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, fd.d_img,
+                 fd.pitch, (char*)fd.d_ws, units[u], nb);
+      for (int s = 0; s < 4; ++s) upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + nb[s];
+    }
+  }
+  for (int s = 0; s < 4; ++s) h.total[s] = upre[s * (nunits + 1) + nunits];
+  // queries
+  QueryArgs* qa = (QueryArgs*)(tb + h.off_q);
+  int32_t* qpre = (int32_t*)(tb + h.off_qprefix);
+  h.ql.threads = 256;
+  for (int q = 0; q < nqueries; ++q) {
+    const swih_query_desc& qd = queries[q];
+    if (qd.frame < 0 || qd.frame >= nframes || qd.n < 0) return SWIH_ERR_INVALID;
+    const swih_config fc = frame_config(cfg, frames[qd.frame]);
+    if (qd.scale_idx < 0 || qd.scale_idx >= fc.nscales) return SWIH_ERR_INVALID;
+    if (gauss && qd.d_hist_raw) return SWIH_ERR_UNSUPPORTED;
+    if (qd.n > 0 && (!qd.d_centres || (!qd.d_hist && !qd.d_hist_raw))) return SWIH_ERR_INVALID;
+    ScaleParams sp;
+    scale_params(&fc, qd.scale_idx, sp);
+    Launch ql;
+    query_args(layouts[qd.frame], sp, gauss ? qd.scale_idx : 0, (const char*)frames[qd.frame].d_ws,
+               qd.d_centres, qd.n, qd.d_hist, qd.d_hist_raw, qa[q], ql);
+    qpre[q + 1] = qpre[q] + (qd.n > 0 ? ql.blocks : 0);
+    if (ql.lds > h.ql.lds) h.ql.lds = ql.lds;
+  }
+  h.ql.blocks = qpre[nqueries];
+  // maps
+  MatchArgs* ma = (MatchArgs*)(tb + h.off_m);
+  int32_t* mpre = (int32_t*)(tb + h.off_mprefix);
+  for (int m = 0; m < nmatches; ++m) {
+    const swih_match_desc& md = matches[m];
+    if (md.frame < 0 || md.frame >= nframes) return SWIH_ERR_INVALID;
+    const swih_frame_desc& fd = frames[md.frame];
+    const swih_config fc = frame_config(cfg, fd);
+    if (md.scale_idx < 0 || md.scale_idx >= fc.nscales) return SWIH_ERR_INVALID;
+    if ((md.d_template == nullptr) == (md.d_template_raw == nullptr)) return SWIH_ERR_INVALID;
+    if (gauss && md.d_template_raw) return SWIH_ERR_UNSUPPORTED;
+    const swih_rect r = md.centres;
+    const bool empty = r.x1 < r.x0 || r.y1 < r.y0;
+    if (!empty) {
+      const swih_scale sc = fc.scales[md.scale_idx];
+      const int32_t rx = (sc.w - 1) / 2, ry = (sc.h - 1) / 2;
+      if (r.x0 < rx || r.y0 < ry || r.x1 > fd.width - 1 - rx || r.y1 > fd.height - 1 - ry || !md.d_map)
+        return SWIH_ERR_INVALID;
+    }
+    ScaleParams sp;
+    scale_params(&fc, md.scale_idx, sp);
+    Launch ml;
+    memset(&ml, 0, sizeof(ml));
+    if (!empty)
+      match_args(layouts[md.frame], sp, gauss ? md.scale_idx : 0, (const char*)fd.d_ws,
+                 md.d_template, md.d_template_raw, r.x0, r.y0, r.x1, r.y1, md.d_map, ma[m], ml);
+    mpre[m + 1] = mpre[m] + (empty ? 0 : ml.blocks);
+    if (ml.threads > h.ml.threads) h.ml.threads = ml.threads;
+    if (ml.lds > h.ml.lds) h.ml.lds = ml.lds;
+  }
+  h.ml.blocks = mpre[nmatches];
+  if (h.ml.threads == 0) h.ml.threads = 256;
+  if (h.ml.lds > 160 * 1024) return SWIH_ERR_UNSUPPORTED;
+  memcpy(tb, &h, sizeof(h));
+  return SWIH_OK;
+}
+
+int swih_build_batch(const void* h_table, const void* d_table, void* stream) {
+  const BatchHeader* h = header_of(h_table);
+  if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
+  const char* db = (const char*)d_table;
+  return launch_build_batch(h->kind, h->nt, (const BuildArgs*)(db + h->off_units),
+                            (const int32_t*)(db + h->off_uprefix), h->nunits, h->total, kBatchGrid,
+                            (hipStream_t)stream) == hipSuccess
+             ? SWIH_OK
+             : SWIH_ERR_HIP;
+}
+
+int swih_query_batch(const void* h_table, const void* d_table, void* stream) {
+  const BatchHeader* h = header_of(h_table);
+  if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
+  const char* db = (const char*)d_table;
+  return launch_query_batch(h->kind, h->nt, (const QueryArgs*)(db + h->off_q),
+                            (const int32_t*)(db + h->off_qprefix), h->nq, h->ql, kBatchGrid,
+                            (hipStream_t)stream) == hipSuccess
+             ? SWIH_OK
+             : SWIH_ERR_HIP;
+}
+
+int swih_match_batch(const void* h_table, const void* d_table, void* stream) {
+  const BatchHeader* h = header_of(h_table);
+  if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
+  const char* db = (const char*)d_table;
+  return launch_match_batch(h->kind, h->nt, (const MatchArgs*)(db + h->off_m),
+                            (const int32_t*)(db + h->off_mprefix), h->nm, h->ml, kBatchGrid,
+                            (hipStream_t)stream) == hipSuccess
              ? SWIH_OK
              : SWIH_ERR_HIP;
 }

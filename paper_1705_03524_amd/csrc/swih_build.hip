@@ -21,6 +21,8 @@
 // Integer kernels accumulate modulo 2^32.  The Gaussian runs its horizontal
 // scans in int32 fixed point (exact), accumulates in double, and stores each
 // tile relative to its own origin (float) with double carries.
+#include <string.h>
+
 #include "swih_internal.h"
 #include "wave64.h"
 
@@ -93,21 +95,23 @@ __device__ __forceinline__ bool wave_tile(const SwihGeom& g, long wid, int extra
 
 // Wave-uniform by construction; readfirstlane tells the compiler so, which keeps
 // every index derived from it (and the loads they address) scalar.
-__device__ __forceinline__ long wave_index() {
-  return (long)blockIdx.x * WPB + (long)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+__device__ __forceinline__ long wave_index(int vb) {
+  return (long)vb * WPB + (long)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------- integer kernels
 template <int KIND>
-__global__ __launch_bounds__(WG) void k_aggregate_int(const uint8_t* __restrict__ img,
-                                                      int ipitch, SwihGeom g,
-                                                      uint32_t* __restrict__ z,
-                                                      uint32_t* __restrict__ T,
-                                                      uint32_t* __restrict__ BT) {
+__device__ __forceinline__ void aggregate_int(const BuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const uint8_t* __restrict__ img = a.img;
+  const int ipitch = a.ipitch;
+  uint32_t* __restrict__ z = (uint32_t*)a.z;
+  uint32_t* __restrict__ T = (uint32_t*)a.T;
+  uint32_t* __restrict__ BT = (uint32_t*)a.BT;
   using TT = IntTerms<KIND>;
   WaveTile t;
   int e;
-  if (!wave_tile(g, wave_index(), 1, t, e)) return;
+  if (!wave_tile(g, wave_index(vb), 1, t, e)) return;
   const int lane = lane_id();
   const int NXP = g.NTX * SWIH_TX;
   uint32_t zacc[TT::nJ], treg[TT::nI];
@@ -180,27 +184,30 @@ __device__ __forceinline__ void excl_walk(V* p, long stride, int n) {
 }
 
 template <typename ZT, typename TTy, typename BTy>
-__global__ __launch_bounds__(WG) void k_scan(SwihGeom g, ZT* __restrict__ z,
-                                             TTy* __restrict__ T, BTy* __restrict__ BT,
-                                             int nb1, int nb2) {
+__device__ __forceinline__ void scan_carries(const BuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  ZT* __restrict__ z = (ZT*)a.z;
+  TTy* __restrict__ T = (TTy*)a.T;
+  BTy* __restrict__ BT = (BTy*)a.BT;
+  const int nb1 = a.nb1, nb2 = a.nb2;
   __shared__ BTy rowcarry[WPB][128];
   const int NXP = g.NTX * SWIH_TX;
-  if ((int)blockIdx.x < nb1) {
-    const long t = (long)blockIdx.x * WG + threadIdx.x;
+  if (vb < nb1) {
+    const long t = (long)vb * WG + threadIdx.x;
     if (t >= (long)g.nJ * g.B * NXP) return;
     const long col = t % NXP, jb = t / NXP;
     excl_walk(z + (size_t)jb * g.NTY * NXP + col, NXP, g.NTY);
     return;
   }
-  if ((int)blockIdx.x < nb1 + nb2) {
-    const long t = (long)(blockIdx.x - nb1) * WG + threadIdx.x;
+  if (vb < nb1 + nb2) {
+    const long t = (long)(vb - nb1) * WG + threadIdx.x;
     if (t >= (long)g.nI * g.B * g.H) return;
     const long y = t % g.H, ib = t / g.H;
     excl_walk(T + (size_t)ib * g.NTX * g.H + y, g.H, g.NTX);
     return;
   }
   const int w = (int)(threadIdx.x >> 6);
-  const long pbi = (long)(blockIdx.x - nb1 - nb2) * WPB + __builtin_amdgcn_readfirstlane(w);
+  const long pbi = (long)(vb - nb1 - nb2) * WPB + __builtin_amdgcn_readfirstlane(w);
   if (pbi >= (long)g.nP * g.B) return;
   BTy* base = BT + (size_t)pbi * g.NTY * g.NTX;
   const int lane = lane_id();
@@ -221,15 +228,18 @@ __global__ __launch_bounds__(WG) void k_scan(SwihGeom g, ZT* __restrict__ z,
 }
 
 template <int KIND>
-__global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img, int ipitch,
-                                                 SwihGeom g, uint32_t* __restrict__ planes,
-                                                 const uint32_t* __restrict__ zc,
-                                                 const uint32_t* __restrict__ E,
-                                                 const uint32_t* __restrict__ CTc) {
+__device__ __forceinline__ void emit_int(const BuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const uint8_t* __restrict__ img = a.img;
+  const int ipitch = a.ipitch;
+  uint32_t* __restrict__ planes = (uint32_t*)a.planes;
+  const uint32_t* __restrict__ zc = (const uint32_t*)a.z;
+  const uint32_t* __restrict__ E = (const uint32_t*)a.T;
+  const uint32_t* __restrict__ CTc = (const uint32_t*)a.BT;
   using TT = IntTerms<KIND>;
   WaveTile t;
   int e;
-  if (!wave_tile(g, wave_index(), 1, t, e)) return;
+  if (!wave_tile(g, wave_index(vb), 1, t, e)) return;
   const int lane = lane_id();
   const int NXP = g.NTX * SWIH_TX;
   uint32_t u[TT::nI], ereg[TT::nI], acc[TT::nP];
@@ -280,10 +290,14 @@ __global__ __launch_bounds__(WG) void k_emit_int(const uint8_t* __restrict__ img
 // ---------------------------------------------------------------- Gaussian
 // Fixed-point weight terms: uq[x][i] (x < NTX*64, zero beyond W), vq[y][j],
 // and vqd[y][j] = vq * 2^-48 as double (scales the u*v product to real units).
-__global__ __launch_bounds__(WG) void k_basis(SwihGeom g, GaussAxis ax, GaussAxis ay,
-                                              int32_t* __restrict__ uq, int32_t* __restrict__ vq,
-                                              double* __restrict__ vqd) {
-  const long t = (long)blockIdx.x * WG + threadIdx.x;
+__device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const GaussAxis& ax = a.ax;
+  const GaussAxis& ay = a.ay;
+  int32_t* __restrict__ uq = a.uq;
+  int32_t* __restrict__ vq = a.vq;
+  double* __restrict__ vqd = a.vqd;
+  const long t = (long)vb * WG + threadIdx.x;
   const int NXP = g.NTX * SWIH_TX;
   const long nu = (long)g.nI * NXP, nv = (long)g.nJ * g.H;
   const double fix = (double)(1 << SWIH_FIX_BITS);
@@ -320,15 +334,17 @@ __global__ __launch_bounds__(WG) void k_basis(SwihGeom g, GaussAxis ax, GaussAxi
 }
 
 template <int NT>
-__global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restrict__ img,
-                                                        int ipitch, SwihGeom g,
-                                                        const int32_t* __restrict__ uq,
-                                                        const int32_t* __restrict__ vq,
-                                                        int64_t* __restrict__ T,
-                                                        double* __restrict__ BT) {
+__device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const uint8_t* __restrict__ img = a.img;
+  const int ipitch = a.ipitch;
+  const int32_t* __restrict__ uq = a.uq;
+  const int32_t* __restrict__ vq = a.vq;
+  int64_t* __restrict__ T = (int64_t*)a.T;
+  double* __restrict__ BT = (double*)a.BT;
   WaveTile t;
   int e;
-  if (!wave_tile(g, wave_index(), 1, t, e)) return;
+  if (!wave_tile(g, wave_index(vb), 1, t, e)) return;
   const int lane = lane_id();
     int32_t treg[NT];
 #pragma unroll
@@ -363,17 +379,20 @@ __global__ __launch_bounds__(WG) void k_aggregate_gauss(const uint8_t* __restric
 }
 
 template <int NT>
-__global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ img, int ipitch,
-                                                   SwihGeom g, const int32_t* __restrict__ uq,
-                                                   const int32_t* __restrict__ vq,
-                                                   const double* __restrict__ vqd,
-                                                   const int64_t* __restrict__ E,
-                                                   const double* __restrict__ CTc,
-                                                   float* __restrict__ Lp,
-                                                   double* __restrict__ RCp) {
+__device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const uint8_t* __restrict__ img = a.img;
+  const int ipitch = a.ipitch;
+  const int32_t* __restrict__ uq = a.uq;
+  const int32_t* __restrict__ vq = a.vq;
+  const double* __restrict__ vqd = a.vqd;
+  const int64_t* __restrict__ E = (const int64_t*)a.T;
+  const double* __restrict__ CTc = (const double*)a.BT;
+  float* __restrict__ Lp = (float*)a.planes;
+  double* __restrict__ RCp = a.RC;
   WaveTile t;
   int i;
-  if (!wave_tile(g, wave_index(), NT, t, i)) return;
+  if (!wave_tile(g, wave_index(vb), NT, t, i)) return;
   const int lane = lane_id();
     const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
   const int32_t uqi = uq[(size_t)t.x * NT + i];
@@ -429,86 +448,143 @@ __global__ __launch_bounds__(WG) void k_emit_gauss(const uint8_t* __restrict__ i
   }
 }
 
-inline unsigned blocks_for_waves(long waves) { return (unsigned)((waves + WPB - 1) / WPB); }
-inline unsigned blocks_for_threads(long n) { return (unsigned)((n + WG - 1) / WG); }
+inline int blocks_for_waves(long waves) { return (int)((waves + WPB - 1) / WPB); }
+inline int blocks_for_threads(long n) { return (int)((n + WG - 1) / WG); }
 
-template <int KIND>
-hipError_t build_int(const SwihLayout& L, const uint8_t* img, int ipitch, char* ws,
-                     hipStream_t s, int phases) {
-  const SwihGeom& g = L.g;
-  uint32_t* planes = (uint32_t*)(ws + L.off_planes);
-  uint32_t* z = (uint32_t*)(ws + L.off_z);
-  uint32_t* T = (uint32_t*)(ws + L.off_T);
-  uint32_t* BT = (uint32_t*)(ws + L.off_CT);
-  const long waves = (long)g.NTY * g.NTX * g.B;
-  if (phases & 1) {
-    hipLaunchKernelGGL(k_aggregate_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
-                       ipitch, g, z, T, BT);
-    const int nb1 = (int)blocks_for_threads((long)g.nJ * g.B * g.NTX * SWIH_TX);
-    const int nb2 = (int)blocks_for_threads((long)g.nI * g.B * g.H);
-    const int nb3 = (int)blocks_for_waves((long)g.nP * g.B);
-    hipLaunchKernelGGL((k_scan<uint32_t, uint32_t, uint32_t>), dim3(nb1 + nb2 + nb3), dim3(WG), 0,
-                       s, g, z, T, BT, nb1, nb2);
+// Every stage is a device body over (arguments, virtual block).  One plane set
+// launches it with one block per virtual block; a batch runs all units'
+// virtual blocks in one grid-stride launch, each block finding its unit by
+// binary search over the prefix of block counts.
+using Body = void (*)(const BuildArgs&, int);
+
+template <Body BODY>
+__global__ __launch_bounds__(WG) void k_single(BuildArgs a) {
+  BODY(a, (int)blockIdx.x);
+}
+
+template <Body BODY>
+__global__ __launch_bounds__(WG) void k_batch(const BuildArgs* __restrict__ units,
+                                              const int32_t* __restrict__ prefix, int nunits) {
+  const int total = prefix[nunits];
+  for (int vb = (int)blockIdx.x; vb < total; vb += (int)gridDim.x) {
+    int lo = 0, hi = nunits - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= vb) lo = mid; else hi = mid - 1;
+    }
+    BODY(units[lo], vb - prefix[lo]);
   }
-  if (phases & 2)
-    hipLaunchKernelGGL(k_emit_int<KIND>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s, img,
-                       ipitch, g, planes, z, T, BT);
+}
+
+template <int KIND> struct IntStages {
+  static constexpr Body basis = nullptr;
+  static constexpr Body agg = aggregate_int<KIND>;
+  static constexpr Body scan = scan_carries<uint32_t, uint32_t, uint32_t>;
+  static constexpr Body emit = emit_int<KIND>;
+};
+template <int NT> struct GaussStages {
+  static constexpr Body basis = ::swih::basis;
+  static constexpr Body agg = aggregate_gauss<NT>;
+  static constexpr Body scan = scan_carries<int64_t, int64_t, double>;
+  static constexpr Body emit = emit_gauss<NT>;
+};
+
+template <class ST>
+hipError_t run_single(const BuildArgs& a, const int32_t (&nb)[4], int phases, hipStream_t s) {
+  if (phases & 1) {
+    if constexpr (ST::basis != nullptr)
+      hipLaunchKernelGGL(k_single<ST::basis>, dim3(nb[0]), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_single<ST::agg>, dim3(nb[1]), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_single<ST::scan>, dim3(nb[2]), dim3(WG), 0, s, a);
+  }
+  if (phases & 2) hipLaunchKernelGGL(k_single<ST::emit>, dim3(nb[3]), dim3(WG), 0, s, a);
   return hipGetLastError();
 }
 
-template <int NT>
-hipError_t build_gauss(const SwihLayout& L, int set, const GaussAxis& ax, const GaussAxis& ay,
-                       const uint8_t* img, int ipitch, char* ws, hipStream_t s, int phases) {
-  const SwihGeom& g = L.g;
-  char* sb = ws + (size_t)set * L.set_bytes;
-  float* Lp = (float*)(sb + L.off_planes);
-  double* RCp = (double*)(sb + L.off_RC);
-  int32_t* uq = (int32_t*)(sb + L.off_uq);
-  int32_t* vq = (int32_t*)(sb + L.off_vq);
-  double* vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
-  int64_t* T = (int64_t*)(ws + L.off_T);
-  double* BT = (double*)(ws + L.off_CT);
-  const long waves = (long)g.NTY * g.NTX * g.B;
-  if (phases & 1) {
-    const long nbasis = (long)g.nI * g.NTX * SWIH_TX + (long)g.nJ * g.H;
-    hipLaunchKernelGGL(k_basis, dim3(blocks_for_threads(nbasis)), dim3(WG), 0, s, g, ax, ay, uq,
-                       vq, vqd);
-    hipLaunchKernelGGL(k_aggregate_gauss<NT>, dim3(blocks_for_waves(waves)), dim3(WG), 0, s,
-                       img, ipitch, g, uq, vq, T, BT);
-    const int nb2 = (int)blocks_for_threads((long)g.nI * g.B * g.H);
-    const int nb3 = (int)blocks_for_waves((long)g.nP * g.B);
-    hipLaunchKernelGGL((k_scan<int64_t, int64_t, double>), dim3(nb2 + nb3), dim3(WG), 0, s, g,
-                       (int64_t*)nullptr, T, BT, 0, nb2);
-  }
-  if (phases & 2)
-    hipLaunchKernelGGL(k_emit_gauss<NT>, dim3(blocks_for_waves(waves * NT)), dim3(WG), 0, s,
-                       img, ipitch, g, uq, vq, vqd, T, BT, Lp, RCp);
+template <class ST>
+hipError_t run_batch(const BuildArgs* units, const int32_t* prefix, int nunits, const int32_t (&total)[4],
+                     int grid, hipStream_t s) {
+  const int32_t* pre[4];
+  for (int k = 0; k < 4; ++k) pre[k] = prefix + (size_t)k * (nunits + 1);
+  auto g = [&](int k) { return dim3((unsigned)(total[k] < grid ? (total[k] > 0 ? total[k] : 1) : grid)); };
+  if constexpr (ST::basis != nullptr)
+    hipLaunchKernelGGL(k_batch<ST::basis>, g(0), dim3(WG), 0, s, units, pre[0], nunits);
+  hipLaunchKernelGGL(k_batch<ST::agg>, g(1), dim3(WG), 0, s, units, pre[1], nunits);
+  hipLaunchKernelGGL(k_batch<ST::scan>, g(2), dim3(WG), 0, s, units, pre[2], nunits);
+  hipLaunchKernelGGL(k_batch<ST::emit>, g(3), dim3(WG), 0, s, units, pre[3], nunits);
   return hipGetLastError();
 }
+
+#define SWIH_STAGE_DISPATCH(KIND, NTV, CALL)       \
+  switch (KIND) {                                  \
+    case 0: return CALL(IntStages<0>);             \
+    case 1: return CALL(IntStages<1>);             \
+    case 2: return CALL(IntStages<2>);             \
+    case 3:                                        \
+      switch (NTV) {                               \
+        case 3: return CALL(GaussStages<3>);       \
+        case 5: return CALL(GaussStages<5>);       \
+        case 7: return CALL(GaussStages<7>);       \
+        case 9: return CALL(GaussStages<9>);       \
+        case 11: return CALL(GaussStages<11>);     \
+        case 13: return CALL(GaussStages<13>);     \
+        case 15: return CALL(GaussStages<15>);     \
+        case 17: return CALL(GaussStages<17>);     \
+        default: return hipErrorInvalidValue;      \
+      }                                            \
+    default: return hipErrorInvalidValue;          \
+  }
 
 }  // namespace
+
+void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay,
+                const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4]) {
+  const SwihGeom& g = L.g;
+  memset(&a, 0, sizeof(a));
+  a.g = g;
+  a.img = img;
+  a.ipitch = img_pitch;
+  char* sb = ws + (size_t)set * L.set_bytes;
+  a.planes = sb + L.off_planes;
+  if (g.gauss) {
+    a.RC = (double*)(sb + L.off_RC);
+    a.uq = (int32_t*)(sb + L.off_uq);
+    a.vq = (int32_t*)(sb + L.off_vq);
+    a.vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
+    a.ax = *ax;
+    a.ay = *ay;
+  }
+  a.z = sb + L.off_z;
+  a.T = sb + L.off_T;
+  a.BT = sb + L.off_CT;
+  const int NXP = g.NTX * SWIH_TX;
+  a.nb1 = g.gauss ? 0 : blocks_for_threads((long)g.nJ * g.B * NXP);
+  a.nb2 = blocks_for_threads((long)g.nI * g.B * g.H);
+  const int nb3 = blocks_for_waves((long)g.nP * g.B);
+  const long waves = (long)g.NTY * g.NTX * g.B;
+  nb[0] = g.gauss ? blocks_for_threads((long)g.nI * NXP + (long)g.nJ * g.H) : 0;
+  nb[1] = blocks_for_waves(waves);
+  nb[2] = a.nb1 + a.nb2 + nb3;
+  nb[3] = blocks_for_waves(waves * (g.gauss ? g.nI : 1));
+}
 
 hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,
                         const GaussAxis* ay, const uint8_t* img, int32_t img_pitch, char* ws,
                         hipStream_t stream, int phases) {
-  switch (kind) {
-    case 0: return build_int<0>(L, img, img_pitch, ws, stream, phases);
-    case 1: return build_int<1>(L, img, img_pitch, ws, stream, phases);
-    case 2: return build_int<2>(L, img, img_pitch, ws, stream, phases);
-    case 3:
-      switch (L.g.nI) {
-        case 3: return build_gauss<3>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 5: return build_gauss<5>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 7: return build_gauss<7>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 9: return build_gauss<9>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 11: return build_gauss<11>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 13: return build_gauss<13>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 15: return build_gauss<15>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        case 17: return build_gauss<17>(L, set, *ax, *ay, img, img_pitch, ws, stream, phases);
-        default: return hipErrorInvalidValue;
-      }
-    default: return hipErrorInvalidValue;
-  }
+  BuildArgs a;
+  int32_t nb[4];
+  build_args(L, set, ax, ay, img, img_pitch, ws, a, nb);
+#define SWIH_RUN1(ST) run_single<ST>(a, nb, phases, stream)
+  SWIH_STAGE_DISPATCH(kind, L.g.nI, SWIH_RUN1)
+#undef SWIH_RUN1
+}
+
+hipError_t launch_build_batch(int kind, int nt, const BuildArgs* units, const int32_t* prefix,
+                              int nunits, const int32_t (&total)[4], int grid, hipStream_t stream) {
+  if (nunits <= 0) return hipSuccess;
+#define SWIH_RUNB(ST) run_batch<ST>(units, prefix, nunits, total, grid, stream)
+  SWIH_STAGE_DISPATCH(kind, nt, SWIH_RUNB)
+#undef SWIH_RUNB
 }
 
 }  // namespace swih

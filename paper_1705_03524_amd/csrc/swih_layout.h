@@ -72,7 +72,7 @@ struct SwihLayout {
   int64_t off_RC;        // double [nP][B][NTX][H+1]              (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
-  // build scratch, shared by all sets (after the sets)
+  // build scratch (carries) of the set
   int64_t off_scratch;
   int64_t off_z;         // [nJ][B][NTY][NTX*64] band column sums -> carries (integer)
   int64_t off_T;         // [nI][B][NTX][H]      row-segment sums -> row carries

@@ -18,6 +18,8 @@
 // Integer coefficients are applied modulo 2^32; the true histogram is below
 // 2^32, so the result is exact.  Normalisation divides by the kernel mass S
 // (the same at every location, Sec. 2.1).
+#include <string.h>
+
 #include "swih_internal.h"
 #include "wave64.h"
 
@@ -79,30 +81,32 @@ __device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 template <int KIND>
-__global__ __launch_bounds__(256) void k_query_int(SwihGeom g, ScaleParams sp,
-                                                   const uint32_t* __restrict__ planes,
-                                                   const int32_t* __restrict__ centres, int n,
-                                                   float* __restrict__ hist,
-                                                   uint32_t* __restrict__ hist_raw) {
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long)n * g.B) return;
+__device__ __forceinline__ void query_int(const QueryArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const uint32_t* __restrict__ planes = (const uint32_t*)a.planes;
+  const int32_t* __restrict__ centres = a.centres;
+  const long t = (long)vb * 256 + threadIdx.x;
+  if (t >= (long)a.n * g.B) return;
   const int k = (int)(t / g.B), b = (int)(t % g.B);
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
   const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp);
-  if (hist_raw) hist_raw[t] = h;
-  if (hist) hist[t] = (float)((double)h / sp.mass);
+  if (a.hist_raw) a.hist_raw[t] = h;
+  if (a.hist) a.hist[t] = (float)((double)h / sp.mass);
 }
 
 template <int KIND>
-__global__ __launch_bounds__(256) void k_match_int(SwihGeom g, ScaleParams sp,
-                                                   const uint32_t* __restrict__ planes,
-                                                   const float* __restrict__ tmpl,
-                                                   const uint32_t* __restrict__ tmpl_raw, int x0,
-                                                   int y0, int x1, int y1,
-                                                   float* __restrict__ map) {
-  const int xc = x0 + blockIdx.x * 64 + threadIdx.x;
-  const int yc = y0 + blockIdx.y * 4 + threadIdx.y;
+__device__ __forceinline__ void match_int(const MatchArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const uint32_t* __restrict__ planes = (const uint32_t*)a.planes;
+  const float* __restrict__ tmpl = a.tmpl;
+  const uint32_t* __restrict__ tmpl_raw = a.tmpl_raw;
+  const int x0 = a.x0, y0 = a.y0, x1 = a.x1, y1 = a.y1;
+  const int bx = vb % a.nbx, by = vb / a.nbx;
+  const int xc = x0 + bx * 64 + (int)(threadIdx.x & 63);
+  const int yc = y0 + by * 4 + (int)(threadIdx.x >> 6);
   if (xc > x1 || yc > y1) return;
   double acc = 0.0;
   for (int b = 0; b < g.B; ++b) {
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256) void k_match_int(SwihGeom g, ScaleParams sp,
     }
   }
   if (tmpl_raw) acc = acc / sp.mass;
-  map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)acc;
+  a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)acc;
 }
 
 // ---------------------------------------------------------------- Gaussian
@@ -149,11 +153,14 @@ __device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double
 // alpha_i sum_j beta_j B_ij into LDS, then one thread per bin adds the terms
 // in order i = 0..NT-1.
 template <int NT>
-__global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
-                                                     const int32_t* __restrict__ centres,
-                                                     float* __restrict__ hist) {
+__device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const GaussPlanes gp{(const float*)a.planes, a.RC};
+  const int32_t* __restrict__ centres = a.centres;
+  __syncthreads();  // LDS reuse across virtual blocks of one block
   extern __shared__ double part[];  // [B][NT]
-  const int k = blockIdx.x;
+  const int k = vb;
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
   double al[NT], be[NT];
@@ -201,7 +208,7 @@ __global__ __launch_bounds__(256) void k_query_gauss(SwihGeom g, ScaleParams sp,
   for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
     double h = 0.0;
     for (int i = 0; i < NT; ++i) h += part[b * NT + i];
-    hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
+    a.hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
   }
 }
 
@@ -238,15 +245,21 @@ __device__ __forceinline__ double series_coeff(const GaussAxis& ax, int c, int i
 // L rows (all j of one i together), one barrier (LDS double-buffered by bin
 // parity), the window threads accumulate sqrt(p_b t_b).
 template <int NT, int NG>
-__global__ __launch_bounds__(1024) void k_match_gauss(SwihGeom g, ScaleParams sp, GaussPlanes gp,
-                                                      const float* __restrict__ tmpl, int x0,
-                                                      int y0, int x1, int cw, int nvpad,
-                                                      int ntl_max, float* __restrict__ map) {
+__device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const GaussPlanes gp{(const float*)a.planes, a.RC};
+  const float* __restrict__ tmpl = a.tmpl;
+  const int x0 = a.x0, y0 = a.y0, x1 = a.x1;
+  const int cw = a.cw, nvpad = a.nvpad, ntl_max = a.ntl_max;
+  // a block may run several virtual blocks one after another: the previous
+  // one's window threads must be done with LDS before it is overwritten
+  __syncthreads();
   extern __shared__ double sm[];
   double* Gb = sm;                                  // [2][NG][2][nvpad]
   double* R = sm + 2 * NG * 2 * nvpad;              // [B][NT][ntl_max]
-  const int yc = y0 + blockIdx.y;
-  const int xa = x0 + blockIdx.x * cw;
+  const int yc = y0 + vb / a.nbx;
+  const int xa = x0 + (vb % a.nbx) * cw;
   const int cwc = min(cw, x1 - xa + 1);
   const int rx = sp.rx, ry = sp.ry;
   const bool contig = 2 * rx + 1 <= cwc;
@@ -276,7 +289,7 @@ __global__ __launch_bounds__(1024) void k_match_gauss(SwihGeom g, ScaleParams sp
   }
   const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
   const int xi = tid - grp * nvpad;
-  const bool has_x = xi < nV;
+  const bool has_x = grp < NG && xi < nV;
   const int X = !has_x ? xa : (contig ? xa - rx + xi
                                       : (xi < cwc ? xa - rx + xi : xa + rx + 1 + xi - cwc));
   const int tX = tile_of(X) - tlo;
@@ -336,29 +349,150 @@ __global__ __launch_bounds__(1024) void k_match_gauss(SwihGeom g, ScaleParams sp
       bc += sqrt(fmax(hh * inv_mass, 0.0) * fmax((double)tmpl[b], 0.0));
     }
   }
-  if (win) map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)bc;
+  if (win) a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)bc;
 }
 
-inline GaussPlanes gauss_planes(const SwihLayout& L, int set, const char* ws) {
-  const char* sb = ws + (size_t)set * L.set_bytes;
-  return GaussPlanes{(const float*)(sb + L.off_planes), (const double*)(sb + L.off_RC)};
+
+
+}  // namespace
+
+// Every map and query is a device body over (arguments, virtual block).  A
+// single request launches one block per virtual block; a batch runs all
+// requests' virtual blocks in one grid-stride launch, each block finding its
+// request by binary search over the prefix of block counts.
+template <class A, void (*BODY)(const A&, int)>
+__global__ __launch_bounds__(1024) void k_one(A a) {
+  BODY(a, (int)blockIdx.x);
 }
 
-template <int NT>
-hipError_t query_gauss(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
-                       const int32_t* centres, int32_t n, float* hist, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)L.g.B * NT;
-  hipLaunchKernelGGL(k_query_gauss<NT>, dim3((unsigned)n), dim3(256), lds, s, L.g, sp,
-                     gauss_planes(L, set, ws), centres, hist);
+template <class A, void (*BODY)(const A&, int)>
+__global__ __launch_bounds__(1024) void k_many(const A* __restrict__ items,
+                                               const int32_t* __restrict__ prefix, int n) {
+  const int total = prefix[n];
+  for (int vb = (int)blockIdx.x; vb < total; vb += (int)gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= vb) lo = mid; else hi = mid - 1;
+    }
+    BODY(items[lo], vb - prefix[lo]);
+  }
+}
+
+namespace {
+
+template <class A, void (*BODY)(const A&, int)>
+hipError_t run_one(const A& a, const Launch& ml, hipStream_t s) {
+  hipLaunchKernelGGL((k_one<A, BODY>), dim3((unsigned)ml.blocks), dim3((unsigned)ml.threads),
+                     ml.lds, s, a);
   return hipGetLastError();
 }
 
-template <int NT>
-hipError_t match_gauss(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
-                       const float* tmpl, int x0, int y0, int x1, int y1, float* map,
-                       hipStream_t s) {
-  constexpr int NG = 3;
+template <class A, void (*BODY)(const A&, int)>
+hipError_t run_many(const A* items, const int32_t* prefix, int n, unsigned grid, const Launch& ml,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((k_many<A, BODY>), dim3(grid), dim3((unsigned)ml.threads), ml.lds, s, items,
+                     prefix, n);
+  return hipGetLastError();
+}
+
+template <int K> constexpr void (*int_match)(const MatchArgs&, int) = match_int<K>;
+template <int K> constexpr void (*int_query)(const QueryArgs&, int) = query_int<K>;
+template <int NT> constexpr void (*gauss_match)(const MatchArgs&, int) = match_gauss<NT, 3>;
+template <int NT> constexpr void (*gauss_query)(const QueryArgs&, int) = query_gauss<NT>;
+
+// switch over kernel kind (and Gaussian term count) calling CALL(body)
+#define SWIH_BODY_CASES(CALL)                 \
+  switch (kind) {                             \
+    case 0: return CALL(SWIH_I(0));           \
+    case 1: return CALL(SWIH_I(1));           \
+    case 2: return CALL(SWIH_I(2));           \
+    case 3:                                   \
+      switch (nt) {                           \
+        case 3: return CALL(SWIH_G(3));       \
+        case 5: return CALL(SWIH_G(5));       \
+        case 7: return CALL(SWIH_G(7));       \
+        case 9: return CALL(SWIH_G(9));       \
+        case 11: return CALL(SWIH_G(11));     \
+        case 13: return CALL(SWIH_G(13));     \
+        case 15: return CALL(SWIH_G(15));     \
+        case 17: return CALL(SWIH_G(17));     \
+        default: return hipErrorInvalidValue; \
+      }                                       \
+    default: return hipErrorInvalidValue;     \
+  }
+
+hipError_t match_one(int kind, int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
+#define SWIH_I(K) int_match<K>
+#define SWIH_G(NT) gauss_match<NT>
+#define SWIH_C(B) run_one<MatchArgs, B>(a, ml, s)
+  SWIH_BODY_CASES(SWIH_C)
+#undef SWIH_C
+#undef SWIH_G
+#undef SWIH_I
+}
+
+hipError_t match_many(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix, int n,
+                      unsigned grid, const Launch& ml, hipStream_t s) {
+#define SWIH_I(K) int_match<K>
+#define SWIH_G(NT) gauss_match<NT>
+#define SWIH_C(B) run_many<MatchArgs, B>(jobs, prefix, n, grid, ml, s)
+  SWIH_BODY_CASES(SWIH_C)
+#undef SWIH_C
+#undef SWIH_G
+#undef SWIH_I
+}
+
+hipError_t query_one(int kind, int nt, const QueryArgs& a, const Launch& ql, hipStream_t s) {
+#define SWIH_I(K) int_query<K>
+#define SWIH_G(NT) gauss_query<NT>
+#define SWIH_C(B) run_one<QueryArgs, B>(a, ql, s)
+  SWIH_BODY_CASES(SWIH_C)
+#undef SWIH_C
+#undef SWIH_G
+#undef SWIH_I
+}
+
+hipError_t query_many(int kind, int nt, const QueryArgs* jobs, const int32_t* prefix, int n,
+                      unsigned grid, const Launch& ql, hipStream_t s) {
+#define SWIH_I(K) int_query<K>
+#define SWIH_G(NT) gauss_query<NT>
+#define SWIH_C(B) run_many<QueryArgs, B>(jobs, prefix, n, grid, ql, s)
+  SWIH_BODY_CASES(SWIH_C)
+#undef SWIH_C
+#undef SWIH_G
+#undef SWIH_I
+}
+
+}  // namespace
+
+void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
+                const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0, int32_t x1,
+                int32_t y1, float* map, MatchArgs& a, Launch& ml) {
+  memset(&a, 0, sizeof(a));
+  a.g = L.g;
+  a.sp = sp;
+  const char* sb = ws + (size_t)set * L.set_bytes;
+  a.planes = sb + L.off_planes;
+  a.RC = L.g.gauss ? (const double*)(sb + L.off_RC) : nullptr;
+  a.tmpl = tmpl;
+  a.tmpl_raw = tmpl_raw;
+  a.map = map;
+  a.x0 = x0;
+  a.y0 = y0;
+  a.x1 = x1;
+  a.y1 = y1;
   const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
+  if (!L.g.gauss) {
+    a.nbx = (nx + 63) / 64;
+    ml.blocks = a.nbx * ((ny + 3) / 4);
+    ml.threads = 256;
+    ml.lds = 0;
+    return;
+  }
+  // Gaussian: NG = 3 groups of nvpad column threads; cw centres per block
+  constexpr int NG = 3;
+  const int NT = L.g.nI;
   const int span = 2 * sp.rx + 1;
   const int maxV = 320;  // NG * maxV threads <= 1024
   int cw, nV;
@@ -371,88 +505,72 @@ hipError_t match_gauss(const SwihLayout& L, const ScaleParams& sp, int set, cons
     cw = nx < maxV / 2 ? nx : maxV / 2;
     nV = 2 * cw;
   }
-  const int nvpad = (nV + 63) / 64 * 64;
-  const int ntl_max = (cw + span + 63) / 64 + 2;  // tile columns one block can touch
-  const size_t lds =
-      sizeof(double) * ((size_t)2 * NG * 2 * nvpad + (size_t)L.g.B * NT * ntl_max);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const unsigned nch = (unsigned)((nx + cw - 1) / cw);
-  hipLaunchKernelGGL((k_match_gauss<NT, NG>), dim3(nch, (unsigned)ny), dim3(NG * nvpad), lds, s,
-                     L.g, sp, gauss_planes(L, set, ws), tmpl, x0, y0, x1, cw, nvpad, ntl_max, map);
-  return hipGetLastError();
+  a.cw = cw;
+  a.nvpad = (nV + 63) / 64 * 64;
+  a.ntl_max = (cw + span + 63) / 64 + 2;  // tile columns one block can touch
+  a.nbx = (nx + cw - 1) / cw;
+  ml.blocks = a.nbx * ny;
+  ml.threads = NG * a.nvpad;
+  ml.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)L.g.B * NT * a.ntl_max);
 }
 
-}  // namespace
-
-#define SWIH_NT_DISPATCH(NTV, CALL) \
-  switch (NTV) {                    \
-    case 3: return CALL(3);         \
-    case 5: return CALL(5);         \
-    case 7: return CALL(7);         \
-    case 9: return CALL(9);         \
-    case 11: return CALL(11);       \
-    case 13: return CALL(13);       \
-    case 15: return CALL(15);       \
-    case 17: return CALL(17);       \
-    default: return hipErrorInvalidValue; \
+void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
+                const int32_t* centres, int32_t n, float* hist, uint32_t* hist_raw, QueryArgs& a,
+                Launch& ql) {
+  memset(&a, 0, sizeof(a));
+  a.g = L.g;
+  a.sp = sp;
+  const char* sb = ws + (size_t)set * L.set_bytes;
+  a.planes = sb + L.off_planes;
+  a.RC = L.g.gauss ? (const double*)(sb + L.off_RC) : nullptr;
+  a.centres = centres;
+  a.n = n;
+  a.hist = hist;
+  a.hist_raw = hist_raw;
+  ql.threads = 256;
+  if (L.g.gauss) {
+    ql.blocks = n;
+    ql.lds = sizeof(double) * (size_t)L.g.B * L.g.nI;
+  } else {
+    ql.blocks = (int32_t)(((long)n * L.g.B + 255) / 256);
+    ql.lds = 0;
   }
+}
 
 hipError_t launch_query(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const int32_t* centres, int32_t n, float* hist, uint32_t* hist_raw,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const long nt = (long)n * L.g.B;
-  const dim3 grid((unsigned)((nt + 255) / 256));
-  const uint32_t* planes = (const uint32_t*)(ws + L.off_planes);
-  switch (sp.kind) {
-    case 0:
-      hipLaunchKernelGGL(k_query_int<0>, grid, dim3(256), 0, s, L.g, sp, planes, centres, n, hist,
-                         hist_raw);
-      return hipGetLastError();
-    case 1:
-      hipLaunchKernelGGL(k_query_int<1>, grid, dim3(256), 0, s, L.g, sp, planes, centres, n, hist,
-                         hist_raw);
-      return hipGetLastError();
-    case 2:
-      hipLaunchKernelGGL(k_query_int<2>, grid, dim3(256), 0, s, L.g, sp, planes, centres, n, hist,
-                         hist_raw);
-      return hipGetLastError();
-    case 3: {
-#define SWIH_Q(NT) query_gauss<NT>(L, sp, set, ws, centres, n, hist, s)
-      SWIH_NT_DISPATCH(L.g.nI, SWIH_Q)
-#undef SWIH_Q
-    }
-    default: return hipErrorInvalidValue;
-  }
+  QueryArgs a;
+  Launch ql;
+  query_args(L, sp, set, ws, centres, n, hist, hist_raw, a, ql);
+  return query_one(sp.kind, L.g.nI, a, ql, s);
+}
+
+hipError_t launch_query_batch(int kind, int nt, const QueryArgs* jobs, const int32_t* prefix,
+                              int njobs, const Launch& ql, int grid, hipStream_t s) {
+  if (njobs <= 0 || ql.blocks <= 0) return hipSuccess;
+  const unsigned gb = (unsigned)(ql.blocks < grid ? ql.blocks : grid);
+  return query_many(kind, nt, jobs, prefix, njobs, gb, ql, s);
 }
 
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
                         int32_t x1, int32_t y1, float* map, hipStream_t s) {
   if (x1 < x0 || y1 < y0) return hipSuccess;
-  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
-  const uint32_t* planes = (const uint32_t*)(ws + L.off_planes);
-  const dim3 gi((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4)), bi(64, 4);
-  switch (sp.kind) {
-    case 0:
-      hipLaunchKernelGGL(k_match_int<0>, gi, bi, 0, s, L.g, sp, planes, tmpl, tmpl_raw, x0, y0,
-                         x1, y1, map);
-      return hipGetLastError();
-    case 1:
-      hipLaunchKernelGGL(k_match_int<1>, gi, bi, 0, s, L.g, sp, planes, tmpl, tmpl_raw, x0, y0,
-                         x1, y1, map);
-      return hipGetLastError();
-    case 2:
-      hipLaunchKernelGGL(k_match_int<2>, gi, bi, 0, s, L.g, sp, planes, tmpl, tmpl_raw, x0, y0,
-                         x1, y1, map);
-      return hipGetLastError();
-    case 3: {
-#define SWIH_M(NT) match_gauss<NT>(L, sp, set, ws, tmpl, x0, y0, x1, y1, map, s)
-      SWIH_NT_DISPATCH(L.g.nI, SWIH_M)
-#undef SWIH_M
-    }
-    default: return hipErrorInvalidValue;
-  }
+  MatchArgs a;
+  Launch ml;
+  match_args(L, sp, set, ws, tmpl, tmpl_raw, x0, y0, x1, y1, map, a, ml);
+  if (ml.lds > 160 * 1024) return hipErrorInvalidValue;
+  return match_one(sp.kind, L.g.nI, a, ml, s);
+}
+
+hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix,
+                              int njobs, const Launch& ml, int grid, hipStream_t s) {
+  if (njobs <= 0 || ml.blocks <= 0) return hipSuccess;
+  if (ml.lds > 160 * 1024) return hipErrorInvalidValue;
+  const unsigned gb = (unsigned)(ml.blocks < grid ? ml.blocks : grid);
+  return match_many(kind, nt, jobs, prefix, njobs, gb, ml, s);
 }
 
 }  // namespace swih
