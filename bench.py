@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--workload", choices=("frame", "batch"), default="frame",
+                    help="frame: the 512x512 single-frame path (default); batch: 64 uneven "
+                         "frames with 1-8 targets x 3 scales, batched vs per-frame")
+    ap.add_argument("--budget-gb", type=float, default=64.0,
+                    help="batch workload: workspace budget of one Gaussian sub-batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (known bytes) so HBM "
                          "counters of a profiling run can be scaled")
@@ -113,12 +118,91 @@ def measured_traffic(kernel_prefix):
     return None
 
 
+def bench_batch(args):
+    """64 uneven frames (256..1920 x 256..1080), 1-8 targets of side 16..128,
+    3 scales each, search region 3s x 3s, 16 bins; Manhattan (one build per
+    frame) and Gaussian K=4 (one build per target-scale search crop).  Times
+    the plain per-frame loop of single calls, the batched form, and the batched
+    form replayed from one HIP graph; checks batched == per-frame bit for bit."""
+    import torch
+    import paper_1705_03524_amd as swih
+    from paper_1705_03524_amd import workloads as WL
+
+    frames = WL.batch_config_frames(4, 64)
+    out = {}
+    total_windows = 0
+    total_ms = {"per_frame": 0.0, "batched": 0.0, "graph": 0.0}
+    for name in ("manhattan", "gaussian"):
+        cfg = swih.Config(16, name, [(15, 15)])
+        units = WL.tracking_units(cfg, frames)
+        budget = int(args.budget_gb * 2**30)
+        per = WL.PerFrameRunner(cfg, units, budget)
+        bat = WL.BatchedRunner(cfg, units, budget)
+        # correctness: batched results equal the per-frame ones bit for bit
+        per.run()
+        torch.cuda.synchronize()
+        ref = [j.out.clone() for u in units for j in u.jobs]
+        for u in units:
+            for j in u.jobs:
+                j.out.fill_(-1)
+        bat.run()
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, j.out) for a, j in zip(ref, (j for u in units for j in u.jobs)))
+        bat.capture()
+
+        def timed(fn, steps):
+            for _ in range(max(1, args.warmup // 2)):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / steps
+
+        steps = max(1, args.steps // 4)
+        t_per = timed(per.run, steps)
+        t_bat = timed(bat.run, steps)
+        t_gra = timed(bat.replay, steps)
+        nw = WL.total_windows(units)
+        total_windows += nw
+        total_ms["per_frame"] += t_per
+        total_ms["batched"] += t_bat
+        total_ms["graph"] += t_gra
+        out[name] = {"units": len(units), "jobs": sum(len(u.jobs) for u in units),
+                     "sub_batches": bat.nbatches, "windows": nw,
+                     "plane_gb": WL.plane_bytes(cfg, units) / 1e9,
+                     "ms_per_frame_loop": t_per, "ms_batched": t_bat, "ms_graph": t_gra,
+                     "windows_per_s_graph": nw / (t_gra / 1e3), "batched_equals_per_frame": same}
+        del per, bat, units
+        torch.cuda.empty_cache()
+    best = min(total_ms["batched"], total_ms["graph"])
+    line = {
+        "metric": METRIC, "value": total_windows / (best / 1e3), "unit": "windows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": best,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
+        "data": "synthetic",
+        "config": {"workload": "batch: 64 uneven frames 256..1920 x 256..1080, 1-8 targets side "
+                               "16..128 x 3 scales, search 3s x 3s, 16 bins, Manhattan + Gaussian K=4",
+                   "global_batch": 64, "seq_len": None, "parallelism": "none"},
+        "per_frame_windows_per_s": total_windows / (total_ms["per_frame"] / 1e3),
+        "speedup_vs_per_frame": total_ms["per_frame"] / best,
+        "detail": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     import torch
     import paper_1705_03524_amd as swih
     from paper_1705_03524_amd.plan import Plan
