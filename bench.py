@@ -41,9 +41,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("frame", "batch"), default="frame",
+    ap.add_argument("--workload", choices=("frame", "batch", "serve"), default="frame",
                     help="frame: the 512x512 single-frame path (default); batch: 64 uneven "
-                         "frames with 1-8 targets x 3 scales, batched vs per-frame")
+                         "frames with 1-8 targets x 3 scales, batched vs per-frame; serve: "
+                         "Poisson tracking requests, continuous batching vs one at a time")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000",
+                    help="serve workload: request rates (req/s) to sweep")
+    ap.add_argument("--seconds", type=float, default=1.0,
+                    help="serve workload: arrival span per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0,
                     help="batch workload: workspace budget of one Gaussian sub-batch")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -194,6 +199,51 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args):
+    """Poisson tracking requests from 16 streams (frames 640x480..4096x2160,
+    target 24..96 px, 3 scales, search 2-4x target, 16 bins, Gaussian K=4);
+    continuous batching (3 in-flight micro-batches, 24 GiB workspace each) vs
+    one request at a time, swept over arrival rates."""
+    import torch
+    import paper_1705_03524_amd as swih
+    from paper_1705_03524_amd import serving, synth
+
+    cfg = swih.Config(16, "gaussian", [(15, 15)])
+    pool = serving.FramePool(synth.FRAME_SIZES, lambda H, W: synth.smooth_noise(H * 7 + W, H, W))
+    cont = serving.ContinuousServer(cfg, pool, budget=24 << 30, max_inflight=3)
+    ser = serving.SerialServer(cfg, pool, budget=8 << 30)
+    # warm up both paths (library load, kernels, allocator, and the weight-term
+    # fits of every stream's window sizes: the same seed gives the same streams)
+    warm = synth.serving_requests(7, 1000.0, 32)
+    cont.serve(warm)
+    ser.serve(warm)
+    torch.cuda.synchronize()
+    sweep = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        n = max(32, int(rate * args.seconds))
+        reqs = synth.serving_requests(7, rate, n)
+        cont.templates = serving._Templates(cfg.nbins, "cuda")
+        rc = serving.latency_stats(cont.serve(reqs))
+        ser.templates = serving._Templates(cfg.nbins, "cuda")
+        rs = serving.latency_stats(ser.serve(reqs))
+        sweep.append({"rate": rate, "continuous": rc, "serial": rs})
+        print(json.dumps({"rate": rate, "continuous_p50_ms": rc["p50_ms"], "continuous_p99_ms": rc["p99_ms"],
+                          "serial_p50_ms": rs["p50_ms"], "serial_p99_ms": rs["p99_ms"]}), file=sys.stderr,
+              flush=True)
+    top = sweep[-1]["continuous"]
+    line = {
+        "metric": METRIC, "value": top["windows_per_s"], "unit": "windows/s", "n_gpus": 1,
+        "steps": len(sweep), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve: Poisson tracking requests, 16 streams, frames 640x480..4096x2160, "
+                               "target 24..96, 3 scales, search 2-4x, 16 bins, Gaussian K=4",
+                   "global_batch": None, "seq_len": None, "parallelism": "none"},
+        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "rate": sweep[-1]["rate"],
+        "sweep": sweep,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -202,6 +252,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
     import torch
     import paper_1705_03524_amd as swih

@@ -9,9 +9,11 @@
 // whose translates do: cos(w (x - xc)) = cos(w x) cos(w xc) + sin(w x) sin(w xc).
 // The coefficients are least-squares fitted at the integer offsets of the
 // window, t in [-r, r], to exp(-t^2 / (2 sigma^2)) with sigma = n / 4, and the
-// integer period P is searched for the smallest worst-case error of the
+// integer period P is chosen for the smallest worst-case error of the
 // normalised 2-D histogram (max over all pixel subsets of the difference in
-// normalised weight, i.e. the larger of the positive and negative parts).
+// normalised weight, i.e. the larger of the positive and negative parts)
+// among the periods with the smallest 1-D maximum error.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -119,30 +121,41 @@ static double worst_error_1d(const std::vector<double>& g, const std::vector<dou
 static Fit compute(int n, int K) {
   const int r = (n - 1) / 2;
   const double sigma = n / 4.0;
-  Fit best;
-  best.err = INFINITY;
-  // The 2-D criterion costs n^2 per candidate; beyond 255 the 1-D maximum
-  // error picks the period and the 2-D figure is evaluated once at the end.
-  const bool full2d = n <= 255;
-  const int Pmax = 6 * n;
   // A window with r + 1 <= K distinct |offsets| is interpolated exactly by its
   // first r + 1 terms; the remaining coefficients are zero.
   const int Ke = K < r ? K : r;
+  // Every integer period in [n, 6n] is fitted and ranked by the cheap 1-D
+  // maximum error; the best few are then ranked by the 2-D criterion, which
+  // costs n^2 each.
+  constexpr int kFinalists = 8;
+  struct Cand {
+    double e1;
+    int P;
+  };
+  std::vector<Cand> cands;
   std::vector<double> a, g, gt;
-  for (int P = n; P <= Pmax; ++P) {
+  for (int P = n; P <= 6 * n; ++P) {
     if (!lsq_fit(r, sigma, Ke, P, a)) continue;
     a.resize(K + 1, 0.0);
     profiles(r, sigma, P, a, g, gt);
-    const double e = full2d ? worst_error_2d(g, gt) : worst_error_1d(g, gt);
-    if (e < best.err) {
+    cands.push_back({worst_error_1d(g, gt), P});
+  }
+  std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) {
+    return x.e1 < y.e1 || (x.e1 == y.e1 && x.P < y.P);
+  });
+  if (cands.size() > kFinalists) cands.resize(kFinalists);
+  Fit best;
+  best.err = INFINITY;
+  for (const Cand& c : cands) {
+    lsq_fit(r, sigma, Ke, c.P, a);
+    a.resize(K + 1, 0.0);
+    profiles(r, sigma, c.P, a, g, gt);
+    const double e = worst_error_2d(g, gt);
+    if (e < best.err || (e == best.err && c.P < best.P)) {
       best.err = e;
-      best.P = P;
+      best.P = c.P;
       best.a = a;
     }
-  }
-  if (!full2d && best.P > 0) {
-    profiles(r, sigma, best.P, best.a, g, gt);
-    best.err = worst_error_2d(g, gt);
   }
   return best;
 }

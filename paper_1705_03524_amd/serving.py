@@ -1,0 +1,300 @@
+"""Serving: continuous batching of tracking requests on one GPU.
+
+A request names a tracking stream, a frame, a target centre, three window
+scales and a search region (Sec. 4: likelihood maps of a target in the next
+frame).  Per request and scale the server builds the Gaussian weighted
+integral histograms of the search-region crop, takes the stream's template
+histogram (computed on the stream's first request and kept resident on the
+device), and computes the Bhattacharyya likelihood map of the search region;
+the maps are copied to pinned host memory.  Latency runs from the request's
+arrival to its maps being on the host.
+
+``ContinuousServer``: requests that arrive while earlier ones are on the GPU
+join the next micro-batch as soon as an in-flight slot and the HBM budget
+allow; each micro-batch (crops uploaded, one batched build + query + map
+launch sequence, maps downloaded) runs on its own stream, so micro-batches
+overlap on the device.  ``SerialServer``: the plain path, one request at a
+time with single-frame calls and a synchronisation per request.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import _swih as S
+from .batch import ALIGN, Batch
+from .plan import Plan
+
+
+class FramePool:
+    """Host frames per frame size, shared by all requests of that size."""
+
+    def __init__(self, sizes, make_image):
+        self.frames = {}
+        for (W, H) in sizes:
+            self.frames[(H, W)] = np.ascontiguousarray(make_image(H, W))
+
+    def get(self, hw) -> np.ndarray:
+        return self.frames[tuple(hw)]
+
+
+class Request:
+    __slots__ = ("id", "t_arrive", "stream", "hw", "centre", "scales", "search", "crop_box",
+                 "units", "maps", "host_maps", "t_done", "windows")
+
+    def __init__(self, r):
+        self.id, self.t_arrive, self.stream = r["id"], r["t_arrive"], r["stream"]
+        self.hw, self.centre, self.scales, self.search = r["frame_hw"], r["centre"], r["scales"], r["search"]
+        self.t_done = None
+        H, W = self.hw
+        cx, cy = self.centre
+        x0, y0, x1, y1 = self.search
+        rmx = max((w - 1) // 2 for w, h in self.scales)
+        rmy = max((h - 1) // 2 for w, h in self.scales)
+        # the uploaded crop: search centres and the template centre plus the largest margin
+        self.crop_box = (max(0, min(x0, cx) - rmx), max(0, min(y0, cy) - rmy),
+                         min(W - 1, max(x1, cx) + rmx), min(H - 1, max(y1, cy) + rmy))
+        ox, oy = self.crop_box[0], self.crop_box[1]
+        self.units = []
+        self.windows = 0
+        for (w, h) in self.scales:
+            rx, ry = (w - 1) // 2, (h - 1) // 2
+            vx0, vy0 = max(x0, rx), max(y0, ry)
+            vx1, vy1 = min(x1, W - 1 - rx), min(y1, H - 1 - ry)
+            ux0, uy0 = min(vx0, cx) - rx - ox, min(vy0, cy) - ry - oy
+            ux1, uy1 = max(vx1, cx) + rx - ox, max(vy1, cy) + ry - oy
+            # (crop view box, template centre, map rectangle), all in the view's coordinates
+            self.units.append(((ux0, uy0, ux1, uy1), (cx - ox - ux0, cy - oy - uy0),
+                               (vx0 - ox - ux0, vy0 - oy - uy0, vx1 - ox - ux0, vy1 - oy - uy0)))
+            self.windows += (vx1 - vx0 + 1) * (vy1 - vy0 + 1)
+
+
+def unit_bytes(cfg, w, h, uh, uw):
+    c = S.Config(cfg.nbins, cfg.kernel, [(w, h)], cfg.gauss_terms)
+    nb = S.workspace_bytes(c, uh, uw)
+    return (nb + ALIGN - 1) // ALIGN * ALIGN
+
+
+def request_io(req: Request):
+    """(crop bytes uploaded, map floats downloaded) of a request."""
+    x0, y0, x1, y1 = req.crop_box
+    return (x1 - x0 + 1) * (y1 - y0 + 1), req.windows
+
+
+def request_bytes(cfg, req: Request) -> int:
+    tot = 0
+    for (w, h), (box, _, _) in zip(req.scales, req.units):
+        tot += unit_bytes(cfg, w, h, box[3] - box[1] + 1, box[2] - box[0] + 1)
+    return tot
+
+
+class _Templates:
+    """Per tracking stream and scale: the template histogram, resident on the device,
+    with the event of the launch that wrote it."""
+
+    def __init__(self, nbins, device):
+        self.t = {}
+        self.ready = {}
+        self.nbins, self.device = nbins, device
+
+    def get(self, stream, scale):
+        key = (stream, scale)
+        new = key not in self.t
+        if new:
+            self.t[key] = torch.empty((1, self.nbins), dtype=torch.float32, device=self.device)
+        return self.t[key], new
+
+    def produced(self, stream, scale, event):
+        self.ready[(stream, scale)] = event
+
+    def event(self, stream, scale):
+        return self.ready.get((stream, scale))
+
+
+class _Slot:
+    """One in-flight micro-batch's memory: workspace, pinned host staging for
+    crops / template centres / maps and their device counterparts, a stream."""
+
+    def __init__(self, budget, in_bytes, out_floats, device):
+        self.ws = torch.empty(budget, dtype=torch.uint8, device=device)
+        self.h_in = torch.empty(in_bytes, dtype=torch.uint8, pin_memory=True)
+        self.d_in = torch.empty(in_bytes, dtype=torch.uint8, device=device)
+        self.h_cen = torch.empty(4096, dtype=torch.int32, pin_memory=True)
+        self.d_cen = torch.empty(4096, dtype=torch.int32, device=device)
+        self.h_out = torch.empty(out_floats, dtype=torch.float32, pin_memory=True)
+        self.d_out = torch.empty(out_floats, dtype=torch.float32, device=device)
+        self.stream = torch.cuda.Stream()
+
+
+class _MicroBatch:
+    def __init__(self, reqs, stream, event):
+        self.reqs, self.stream, self.event = reqs, stream, event
+
+
+class ContinuousServer:
+    def __init__(self, cfg: S.Config, pool: FramePool, budget: int, max_inflight: int = 3,
+                 max_batch: int = 64, in_bytes: int = 64 << 20, out_floats: int = 32 << 20,
+                 device="cuda"):
+        self.cfg, self.pool, self.budget = cfg, pool, budget
+        self.max_inflight, self.max_batch, self.device = max_inflight, max_batch, device
+        self.in_bytes, self.out_floats = in_bytes, out_floats
+        self.slots = [_Slot(budget, in_bytes, out_floats, device) for _ in range(max_inflight)]
+        self.free = deque(range(max_inflight))
+        self.templates = _Templates(cfg.nbins, device)
+
+    def _launch(self, reqs, slot_id):
+        cfg, dev = self.cfg, self.device
+        sl = self.slots[slot_id]
+        st = sl.stream
+        frames, queries, matches = [], [], []
+        produced, waits = [], []
+        hin = sl.h_in.numpy()
+        hcen = sl.h_cen.numpy()
+        ioff, coff, ooff = 0, 0, 0
+        crops, cens = [], []
+        for r in reqs:  # stage crops and template centres in pinned memory
+            x0, y0, x1, y1 = r.crop_box
+            h, w = y1 - y0 + 1, x1 - x0 + 1
+            np.copyto(hin[ioff:ioff + h * w].reshape(h, w), self.pool.get(r.hw)[y0:y1 + 1, x0:x1 + 1])
+            crops.append((ioff, h, w))
+            ioff += h * w
+            cl = []
+            for (_, tc, _) in r.units:
+                hcen[coff:coff + 2] = tc
+                cl.append(coff)
+                coff += 2
+            cens.append(cl)
+        with torch.cuda.stream(st):
+            sl.d_in[:ioff].copy_(sl.h_in[:ioff], non_blocking=True)
+            sl.d_cen[:coff].copy_(sl.h_cen[:coff], non_blocking=True)
+            for r, (io, h, w), cl in zip(reqs, crops, cens):
+                crop = sl.d_in[io:io + h * w].view(h, w)
+                r.maps = []
+                for (sw, sh), (box, tc, rect), co in zip(r.scales, r.units, cl):
+                    ux0, uy0, ux1, uy1 = box
+                    fi = len(frames)
+                    frames.append({"img": crop[uy0:uy1 + 1, ux0:ux1 + 1], "scales": [(sw, sh)]})
+                    tmpl, new = self.templates.get(r.stream, (sw, sh))
+                    if new:
+                        queries.append({"frame": fi, "scale_idx": 0,
+                                        "centres": sl.d_cen[co:co + 2].view(1, 2), "hist": tmpl})
+                        produced.append((r.stream, (sw, sh)))
+                    else:
+                        ev = self.templates.event(r.stream, (sw, sh))
+                        if ev is not None:
+                            waits.append(ev)
+                    rows, cols = rect[3] - rect[1] + 1, rect[2] - rect[0] + 1
+                    m = sl.d_out[ooff:ooff + rows * cols].view(rows, cols)
+                    r.maps.append((ooff, rows, cols))
+                    ooff += rows * cols
+                    matches.append({"frame": fi, "scale_idx": 0, "rect": rect, "template": tmpl[0],
+                                    "out": m})
+            b = Batch(cfg, frames, queries, matches, ws=sl.ws)
+            for ev in waits:  # templates written by a batch on another stream
+                st.wait_event(ev)
+            b.build()
+            b.query()
+            if produced:
+                tev = torch.cuda.Event()
+                tev.record(st)
+                for key in produced:
+                    self.templates.produced(key[0], key[1], tev)
+            b.match()
+            sl.h_out[:ooff].copy_(sl.d_out[:ooff], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        mb = _MicroBatch(reqs, slot_id, ev)
+        mb.batch = b  # keep the plan table alive until done
+        return mb
+
+    def _finish(self, mb):
+        h_out = self.slots[mb.stream].h_out
+        for r in mb.reqs:
+            r.host_maps = [h_out[o:o + rows * cols].view(rows, cols).clone() for o, rows, cols in r.maps]
+
+    def serve(self, requests, clock=time.perf_counter, keep_maps=False):
+        """Run the arrival schedule in real time; returns the requests with t_done set."""
+        reqs = [Request(r) for r in requests]
+        for r in reqs:
+            ib, of = request_io(r)
+            if request_bytes(self.cfg, r) > self.budget or ib > self.in_bytes or of > self.out_floats:
+                raise ValueError("request %d exceeds a slot's capacity" % r.id)
+        pending, inflight = deque(), deque()
+        i, done, n = 0, 0, len(reqs)
+        t0 = clock()
+        while done < n:
+            now = clock() - t0
+            while i < n and reqs[i].t_arrive <= now:
+                pending.append(reqs[i])
+                i += 1
+            while inflight and inflight[0].event.query():
+                mb = inflight.popleft()
+                t = clock() - t0
+                if keep_maps:
+                    self._finish(mb)
+                for r in mb.reqs:
+                    r.t_done = t
+                done += len(mb.reqs)
+                self.free.append(mb.stream)
+            if pending and self.free:
+                take, used, uin, uout = [], 0, 0, 0
+                while pending and len(take) < self.max_batch:
+                    nb = request_bytes(self.cfg, pending[0])
+                    ib, of = request_io(pending[0])
+                    if used + nb > self.budget or uin + ib > self.in_bytes or uout + of > self.out_floats:
+                        break
+                    take.append(pending.popleft())
+                    used, uin, uout = used + nb, uin + ib, uout + of
+                inflight.append(self._launch(take, self.free.popleft()))
+            elif not pending and i < n and not inflight:
+                time.sleep(max(0.0, min(0.0005, reqs[i].t_arrive - (clock() - t0))))
+        return reqs
+
+
+class SerialServer:
+    """One request at a time with the single-frame calls; synchronises per request."""
+
+    def __init__(self, cfg: S.Config, pool: FramePool, budget: int, device="cuda"):
+        self.cfg, self.pool, self.device = cfg, pool, device
+        self.ws = torch.empty(budget, dtype=torch.uint8, device=device)
+        self.templates = _Templates(cfg.nbins, device)
+
+    def serve(self, requests, clock=time.perf_counter, keep_maps=False):
+        reqs = [Request(r) for r in requests]
+        cfg, dev = self.cfg, self.device
+        t0 = clock()
+        for r in reqs:
+            wait = r.t_arrive - (clock() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            x0, y0, x1, y1 = r.crop_box
+            crop = torch.from_numpy(np.ascontiguousarray(self.pool.get(r.hw)[y0:y1 + 1, x0:x1 + 1])).to(dev)
+            maps = []
+            for (w, h), (box, tc, rect) in zip(r.scales, r.units):
+                ux0, uy0, ux1, uy1 = box
+                view = crop[uy0:uy1 + 1, ux0:ux1 + 1]
+                uc = S.Config(cfg.nbins, cfg.kernel, [(w, h)], cfg.gauss_terms)
+                nb = S.workspace_bytes(uc, view.shape[0], view.shape[1])
+                p = Plan(uc, view.shape[0], view.shape[1], ws=self.ws[:nb])
+                p.build(view)
+                tmpl, new = self.templates.get(r.stream, (w, h))
+                if new:
+                    S.query(uc, p.ws, p.H, p.W, 0, torch.tensor([tc], dtype=torch.int32, device=dev), tmpl)
+                maps.append(p.match(0, template=tmpl[0], rect=rect))
+            host = [m.cpu() for m in maps]  # synchronises
+            if keep_maps:
+                r.host_maps = host
+            r.t_done = clock() - t0
+        return reqs
+
+
+def latency_stats(reqs):
+    lat = np.array([r.t_done - r.t_arrive for r in reqs]) * 1e3
+    span = max(r.t_done for r in reqs) - min(r.t_arrive for r in reqs)
+    wins = sum(r.windows for r in reqs)
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "windows_per_s": wins / span, "requests": len(reqs),
+            "achieved_req_per_s": len(reqs) / span}

@@ -168,23 +168,30 @@ FRAME_SIZES = ((640, 480), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)
 def serving_requests(seed: int, rate: float, n: int, nstreams: int = 16,
                      roi_range=(24, 96), search_mult=(2.0, 4.0),
                      scale_factors=(0.8, 1.0, 1.25), sizes=FRAME_SIZES):
-    """Poisson stream of tracking requests.
+    """Poisson stream of tracking requests from ``nstreams`` tracking streams.
 
-    Inter-arrival times are exponential with mean ``1/rate`` seconds.  Each
-    request names a stream (round-robin), a frame size drawn uniformly from
-    ``sizes``, a target ROI side (odd), its three window scales, and a search
-    region ``ROI * U[search_mult]`` centred on the target and clipped to the
-    frame.  Pixel content is drawn separately (``smooth_noise``) by the caller
-    from ``pixel_seed`` so a pool of frames can be reused.
+    Inter-arrival times are exponential with mean ``1/rate`` seconds and
+    requests go to the streams round-robin.  Each stream is one camera and
+    one target: its frame size is drawn uniformly from ``sizes`` and its
+    target side (made odd) from ``roi_range`` once, so its three window
+    scales ``odd(round(s * f))`` stay fixed.  Per request the target centre is
+    drawn uniformly where the largest window fits, and the search region is
+    the square of side ``s * U[search_mult]`` (odd, at least the largest
+    window) around it, clipped to the valid centres.
     """
     g = rng(seed)
+    streams = []
+    for _ in range(nstreams):
+        W, H = sizes[int(g.integers(0, len(sizes)))]
+        s = odd(int(g.integers(roi_range[0], roi_range[1] + 1)))
+        scales = [(odd(max(3, int(round(s * f)))),) * 2 for f in scale_factors]
+        streams.append(((H, W), s, scales))
     t = 0.0
     reqs = []
     for k in range(n):
         t += float(g.exponential(1.0 / rate))
-        W, H = sizes[int(g.integers(0, len(sizes)))]
-        s = odd(int(g.integers(roi_range[0], roi_range[1] + 1)))
-        scales = [(odd(max(3, int(round(s * f)))),) * 2 for f in scale_factors]
+        st = k % nstreams
+        (H, W), s, scales = streams[st]
         smax = max(sc[0] for sc in scales)
         mult = float(g.uniform(*search_mult))
         side = odd(max(smax, int(round(s * mult))))
@@ -193,7 +200,6 @@ def serving_requests(seed: int, rate: float, n: int, nstreams: int = 16,
         cy = int(g.integers(r, H - r))
         half = (side - 1) // 2
         search = (max(r, cx - half), max(r, cy - half), min(W - 1 - r, cx + half), min(H - 1 - r, cy + half))
-        reqs.append({"id": k, "t_arrive": t, "stream": k % nstreams, "frame_hw": (H, W),
-                     "centre": (cx, cy), "scales": scales, "search": search,
-                     "pixel_seed": int(g.integers(0, 2**31 - 1))})
+        reqs.append({"id": k, "t_arrive": t, "stream": st, "frame_hw": (H, W),
+                     "centre": (cx, cy), "scales": scales, "search": search})
     return reqs
