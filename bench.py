@@ -272,34 +272,41 @@ def main():
             for k in KERNELS}
     tmpl = {k: torch.empty(NBINS, dtype=torch.float32, device="cuda") for k in KERNELS}
     traw = {k: torch.empty(NBINS, dtype=torch.uint32, device="cuda") for k in KERNELS}
-    evs = []
 
-    def ev():
-        return torch.cuda.Event(enable_timing=True)
-
-    def step(timed):
-        for k in KERNELS:
-            p = plans[k]
-            e0, e1, e2, e3 = ev(), ev(), ev(), ev()
-            e0.record()
-            swih.build_phase(p.cfg, d_img, p.ws, "carries", 0)
-            e1.record()
-            swih.build_phase(p.cfg, d_img, p.ws, "planes", 0)
-            e2.record()
+    def phase(k, name):
+        """One launch of a hot-path phase of kernel k (all on the current stream)."""
+        p = plans[k]
+        if name in ("carries", "planes"):
+            swih.build_phase(p.cfg, d_img, p.ws, name, 0)
+        elif name == "query":
             if p.integer:
                 swih.query(p.cfg, p.ws, H, W, 0, d_tc, None, traw[k].view(1, NBINS))
-                e3.record()
-                swih.match(p.cfg, p.ws, H, W, 0, p.valid_rect(0), maps[k], template_raw=traw[k])
             else:
                 swih.query(p.cfg, p.ws, H, W, 0, d_tc, tmpl[k].view(1, NBINS), None)
-                e3.record()
-                swih.match(p.cfg, p.ws, H, W, 0, p.valid_rect(0), maps[k], template=tmpl[k])
-            e4 = ev()
-            e4.record()
-            if timed:
-                evs.append(("build_" + k, e0, e2))
-                evs.append(("planes_" + k, e1, e2))
-                evs.append(("match_" + k, e3, e4))
+        elif p.integer:
+            swih.match(p.cfg, p.ws, H, W, 0, p.valid_rect(0), maps[k], template_raw=traw[k])
+        else:
+            swih.match(p.cfg, p.ws, H, W, 0, p.valid_rect(0), maps[k], template=tmpl[k])
+
+    PHASES = ("carries", "planes", "query", "match")
+
+    def step():
+        for k in KERNELS:
+            for ph in PHASES:
+                phase(k, ph)
+
+    def capture(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        return g
 
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -308,20 +315,46 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
+    eager = {k: maps[k].clone() for k in KERNELS}
+    # The step (3 kernels x 4 launches) is replayed from one captured HIP graph,
+    # so host-side launch cost never starves the device.
+    g_step = capture(step)
+    for k in KERNELS:
+        maps[k].fill_(-1.0)
+    g_step.replay()
+    torch.cuda.synchronize()
+    for k in KERNELS:
+        if not torch.equal(maps[k], eager[k]):
+            raise RuntimeError("graph replay of the %s step differs from the eager step" % k)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
     for _ in range(args.steps):
-        step(True)
+        g_step.replay()
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
+    # Per-kernel launch durations: ROCm graphs carry no timing events, so each
+    # phase is captured as its own graph of REP back-to-back launches and timed
+    # with events around its replays on the same stream.
+    REP = 10
     per = {}
-    for name, a, b in evs:
-        per.setdefault(name, []).append(a.elapsed_time(b))
-    per = {k: float(np.mean(v)) for k, v in per.items()}
+    for k in KERNELS:
+        for ph in PHASES:
+            g = capture(lambda: [phase(k, ph) for _ in range(REP)])
+            g.replay()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            per[ph + "_" + k] = a.elapsed_time(b) / (3 * REP)
+            del g
+    for k in KERNELS:
+        per["build_" + k] = per["carries_" + k] + per["planes_" + k]
 
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)

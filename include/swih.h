@@ -31,6 +31,13 @@
  *       SWIH_GAUSSIAN   exp(-dx^2/(2 sx^2) - dy^2/(2 sy^2)), sx = w/4,
  *                       sy = h/4 (Fig. 1c), evaluated through a K-term cosine
  *                       series per axis (see swih_gauss_terms).
+ *       SWIH_GAUSSIAN_SEP  the same series kernel in separable form: one
+ *                       1-D weighted integral histogram along x with the
+ *                       translated lookups (Sec. 2.1, Eq. 2 per axis) giving
+ *                       row results per valid centre column, then one along y
+ *                       over those row results.  Same values as SWIH_GAUSSIAN
+ *                       up to rounding; the workspace holds H x (W-w+1) x
+ *                       nbins floats per scale instead of (2K+1)^2 planes.
  *     The first three are exact: raw histograms are integers, computed modulo
  *     2^32 and exact whenever the true value is below 2^32.
  *   - Normalised histogram p_b = H_b / S, with S the kernel mass (the same at
@@ -72,7 +79,8 @@ typedef enum {
   SWIH_UNIFORM = 0,
   SWIH_MANHATTAN = 1,
   SWIH_EUCLIDEAN = 2,
-  SWIH_GAUSSIAN = 3
+  SWIH_GAUSSIAN = 3,
+  SWIH_GAUSSIAN_SEP = 4
 } swih_kernel;
 
 /* One window scale: odd width and height, 1 <= w <= W, 1 <= h <= H. */
@@ -96,9 +104,9 @@ typedef struct {
 
 /*
  * Bytes of device workspace a build of an H x W image needs under `cfg`.
- * Integer kernels keep one set of planes for every scale; the Gaussian keeps
- * one set per scale (its weight terms depend on the window size, Sec. 2.1
- * "multi-scale").  Returns the size (> 0), or a negative status.
+ * Integer kernels keep one set of planes for every scale; both Gaussian forms
+ * keep one set per scale (their weight terms depend on the window size,
+ * Sec. 2.1 "multi-scale").  Returns the size (> 0), or a negative status.
  */
 int64_t swih_workspace_bytes(const swih_config* cfg, int32_t height, int32_t width);
 
@@ -125,6 +133,8 @@ int swih_build(const swih_config* cfg, const uint8_t* d_img, int32_t height, int
  *                       carries: exactly one kernel launch.
  *   set     0 for integer kernels; the scale index for the Gaussian, whose
  *           planes are per scale.
+ * For SWIH_GAUSSIAN_SEP the first phase writes the scale's term and
+ * coefficient tables and the second the row results (one launch each).
  * Each set keeps its own carries, so a set's planes need only follow its own
  * carries on the stream.  Errors as swih_build, plus SWIH_ERR_INVALID for a
  * bad set.
@@ -143,7 +153,7 @@ int swih_build_planes(const swih_config* cfg, const uint8_t* d_img, int32_t heig
  *               are clamped on the device and give unspecified histograms).
  *   d_hist      device float [n][nbins], p_b = H_b / S; may be NULL.
  *   d_hist_raw  device uint32 [n][nbins], exact H_b; integer kernels only
- *               (SWIH_ERR_UNSUPPORTED for the Gaussian); may be NULL.
+ *               (SWIH_ERR_UNSUPPORTED for both Gaussian forms); may be NULL.
  * n == 0 is valid and enqueues nothing.
  */
 int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,

@@ -15,8 +15,10 @@ from typing import Sequence
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libswih.so")
 
-UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN = 0, 1, 2, 3
-KERNELS = {"uniform": UNIFORM, "manhattan": MANHATTAN, "euclidean": EUCLIDEAN, "gaussian": GAUSSIAN}
+UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN, GAUSSIAN_SEP = 0, 1, 2, 3, 4
+KERNELS = {"uniform": UNIFORM, "manhattan": MANHATTAN, "euclidean": EUCLIDEAN, "gaussian": GAUSSIAN,
+           "gaussian_sep": GAUSSIAN_SEP}
+SERIES_KINDS = (GAUSSIAN, GAUSSIAN_SEP)
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
 

@@ -12,7 +12,10 @@ namespace {
 constexpr int32_t kMaxSide = 8192;
 constexpr int32_t kDefaultTY = 64;
 
-bool kind_ok(int32_t k) { return k >= SWIH_UNIFORM && k <= SWIH_GAUSSIAN; }
+bool kind_ok(int32_t k) { return k >= SWIH_UNIFORM && k <= SWIH_GAUSSIAN_SEP; }
+
+// Kernels built from the cosine series, with one workspace set per scale.
+bool series_kind(int32_t k) { return k == SWIH_GAUSSIAN || k == SWIH_GAUSSIAN_SEP; }
 
 int32_t gauss_K(const swih_config* c) { return c->gauss_terms == 0 ? 4 : c->gauss_terms; }
 
@@ -22,7 +25,7 @@ int check_config(const swih_config* c, int32_t H, int32_t W) {
   if (c->nbins < 1 || c->nbins > 256 || !kind_ok(c->kernel) || c->flags != 0)
     return SWIH_ERR_INVALID;
   if (c->nscales < 1 || !c->scales) return SWIH_ERR_INVALID;
-  if (c->kernel == SWIH_GAUSSIAN) {
+  if (series_kind(c->kernel)) {
     const int32_t K = gauss_K(c);
     if (K < 1 || K > SWIH_MAX_K) return SWIH_ERR_INVALID;
   }
@@ -50,6 +53,13 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   g.H = H;
   g.W = W;
   g.B = c->nbins;
+  if (c->kernel == SWIH_GAUSSIAN_SEP) {  // row results + tables per scale (swih_sep.hip)
+    g.nI = g.nJ = 2 * gauss_K(c) + 1;
+    L.set_bytes = sep_layout(H, W, g.B, g.nI).set_bytes;
+    L.nsets = c->nscales;
+    L.total = L.set_bytes * L.nsets;
+    return SWIH_OK;
+  }
   g.TY = kDefaultTY;
   g.NTX = (W + SWIH_TX - 1) / SWIH_TX;
   g.NTY = (H + g.TY - 1) / g.TY;
@@ -114,7 +124,7 @@ int scale_params(const swih_config* c, int32_t scale_idx, ScaleParams& sp) {
   sp.rx = (sc.w - 1) / 2;
   sp.ry = (sc.h - 1) / 2;
   sp.kind = c->kernel;
-  if (c->kernel == SWIH_GAUSSIAN) {
+  if (series_kind(c->kernel)) {
     const int32_t K = gauss_K(c);
     if (fill_axis(sc.w, K, sp.ax) || fill_axis(sc.h, K, sp.ay)) return SWIH_ERR_INVALID;
     sp.mass = gauss_axis_mass(sc.w, K, sp.ax.a, sp.ax.P) * gauss_axis_mass(sc.h, K, sp.ay.a, sp.ay.P);
@@ -168,6 +178,20 @@ int build_phases(const swih_config* cfg, const uint8_t* d_img, int32_t height, i
   const bool gauss = cfg->kernel == SWIH_GAUSSIAN;
   const int first = set < 0 ? 0 : set, last = set < 0 ? L.nsets - 1 : set;
   if (first >= L.nsets || last >= L.nsets) return SWIH_ERR_INVALID;
+  if (cfg->kernel == SWIH_GAUSSIAN_SEP) {
+    const SepLayout SL = sep_layout(height, width, cfg->nbins, L.g.nI);
+    for (int k = first; k <= last; ++k) {
+      ScaleParams sp;
+      scale_params(cfg, k, sp);
+      const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, L.g.nI);
+      SepBuildArgs a;
+      int32_t nb[2];
+      sep_build_args(sg, SL, sp.ax, sp.ay, d_img, pitch, (char*)d_ws + (size_t)k * L.set_bytes, a,
+                     nb);
+      if (sep_launch_build(a, nb, phases, s) != hipSuccess) return SWIH_ERR_HIP;
+    }
+    return SWIH_OK;
+  }
   for (int k = first; k <= last; ++k) {
     ScaleParams sp;
     scale_params(cfg, gauss ? k : 0, sp);
@@ -207,7 +231,7 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   int st = check_config(cfg, height, width);
   if (st != SWIH_OK) return st;
   if (scale_idx < 0 || scale_idx >= cfg->nscales || n < 0 || !d_ws) return SWIH_ERR_INVALID;
-  if (cfg->kernel == SWIH_GAUSSIAN && d_hist_raw) return SWIH_ERR_UNSUPPORTED;
+  if (series_kind(cfg->kernel) && d_hist_raw) return SWIH_ERR_UNSUPPORTED;
   if (n == 0) return SWIH_OK;
   if (!d_centres || (!d_hist && !d_hist_raw)) return SWIH_ERR_INVALID;
   SwihLayout L;
@@ -216,6 +240,14 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   ScaleParams sp;
   st = scale_params(cfg, scale_idx, sp);
   if (st != SWIH_OK) return st;
+  if (cfg->kernel == SWIH_GAUSSIAN_SEP) {
+    const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, L.g.nI);
+    SepQueryArgs a;
+    int32_t nb;
+    sep_query_args(sg, sep_layout(height, width, cfg->nbins, L.g.nI), sp.mass,
+                   (const char*)d_ws + (size_t)scale_idx * L.set_bytes, d_centres, n, d_hist, a, nb);
+    return sep_launch_query(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+  }
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
   return launch_query(L, sp, set, (const char*)d_ws, d_centres, n, d_hist, d_hist_raw,
                       (hipStream_t)stream) == hipSuccess
@@ -230,7 +262,7 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   if (st != SWIH_OK) return st;
   if (scale_idx < 0 || scale_idx >= cfg->nscales || !d_ws) return SWIH_ERR_INVALID;
   if ((d_template == nullptr) == (d_template_raw == nullptr)) return SWIH_ERR_INVALID;
-  if (cfg->kernel == SWIH_GAUSSIAN && d_template_raw) return SWIH_ERR_UNSUPPORTED;
+  if (series_kind(cfg->kernel) && d_template_raw) return SWIH_ERR_UNSUPPORTED;
   if (r.x1 < r.x0 || r.y1 < r.y0) return SWIH_OK;
   const swih_scale sc = cfg->scales[scale_idx];
   const int32_t rx = (sc.w - 1) / 2, ry = (sc.h - 1) / 2;
@@ -243,6 +275,15 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   ScaleParams sp;
   st = scale_params(cfg, scale_idx, sp);
   if (st != SWIH_OK) return st;
+  if (cfg->kernel == SWIH_GAUSSIAN_SEP) {
+    const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, L.g.nI);
+    SepMatchArgs a;
+    int32_t nb;
+    sep_match_args(sg, sep_layout(height, width, cfg->nbins, L.g.nI), sp.mass,
+                   (const char*)d_ws + (size_t)scale_idx * L.set_bytes, d_template, r.x0, r.y0,
+                   r.x1, r.y1, d_map, a, nb);
+    return sep_launch_match(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+  }
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
   return launch_match(L, sp, set, (const char*)d_ws, d_template, d_template_raw, r.x0, r.y0, r.x1,
                       r.y1, d_map, (hipStream_t)stream) == hipSuccess
@@ -268,25 +309,27 @@ struct BatchHeader {
 };
 
 int32_t frame_units(const swih_config* cfg, const swih_frame_desc& f) {
-  if (cfg->kernel != SWIH_GAUSSIAN) return 1;
+  if (!series_kind(cfg->kernel)) return 1;
   return f.nscales > 0 ? f.nscales : cfg->nscales;
 }
 
-// Offsets of every table section for the given counts.
-BatchHeader table_layout(int32_t nunits, int32_t nq, int32_t nm) {
+// Offsets of every table section for the given counts (item records of the
+// separable kind are its own argument structs).
+BatchHeader table_layout(int32_t kind, int32_t nunits, int32_t nq, int32_t nm) {
   BatchHeader h;
   memset(&h, 0, sizeof(h));
+  const bool sep = kind == SWIH_GAUSSIAN_SEP;
   int64_t off = swih_align256(sizeof(BatchHeader));
   h.off_units = off;
-  off += swih_align256((int64_t)nunits * sizeof(BuildArgs));
+  off += swih_align256((int64_t)nunits * (sep ? sizeof(SepBuildArgs) : sizeof(BuildArgs)));
   h.off_uprefix = off;
   off += swih_align256((int64_t)4 * (nunits + 1) * sizeof(int32_t));
   h.off_q = off;
-  off += swih_align256((int64_t)nq * sizeof(QueryArgs));
+  off += swih_align256((int64_t)nq * (sep ? sizeof(SepQueryArgs) : sizeof(QueryArgs)));
   h.off_qprefix = off;
   off += swih_align256((int64_t)(nq + 1) * sizeof(int32_t));
   h.off_m = off;
-  off += swih_align256((int64_t)nm * sizeof(MatchArgs));
+  off += swih_align256((int64_t)nm * (sep ? sizeof(SepMatchArgs) : sizeof(MatchArgs)));
   h.off_mprefix = off;
   off += swih_align256((int64_t)(nm + 1) * sizeof(int32_t));
   h.bytes = off;
@@ -322,7 +365,7 @@ int64_t swih_batch_table_bytes(const swih_config* cfg, const swih_frame_desc* fr
   int64_t nunits = 0;
   for (int f = 0; f < nframes; ++f) nunits += frame_units(cfg, frames[f]);
   if (nunits > (1 << 24)) return SWIH_ERR_INVALID;
-  return table_layout((int32_t)nunits, nqueries, nmatches).bytes;
+  return table_layout(cfg->kernel, (int32_t)nunits, nqueries, nmatches).bytes;
 }
 
 int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32_t nframes,
@@ -336,6 +379,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
   if (need < 0) return (int)need;
   if ((int64_t)table_bytes < need) return SWIH_ERR_WORKSPACE;
   const bool gauss = cfg->kernel == SWIH_GAUSSIAN;
+  const bool sep = cfg->kernel == SWIH_GAUSSIAN_SEP;
   // frames: check, lay out, and fill one build unit per plane set
   std::vector<SwihLayout> layouts(nframes);
   std::vector<int32_t> ubase(nframes + 1, 0);
@@ -356,16 +400,34 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     ubase[f + 1] = ubase[f] + frame_units(cfg, fd);
   }
   const int32_t nunits = ubase[nframes];
-  BatchHeader h = table_layout(nunits, nqueries, nmatches);
+  BatchHeader h = table_layout(cfg->kernel, nunits, nqueries, nmatches);
   h.magic = kBatchMagic;
   h.kind = cfg->kernel;
-  h.nt = gauss ? 2 * gauss_K(cfg) + 1 : 0;
+  h.nt = series_kind(cfg->kernel) ? 2 * gauss_K(cfg) + 1 : 0;
   h.nbins = cfg->nbins;
   char* tb = (char*)h_table;
   memset(tb, 0, (size_t)h.bytes);
   BuildArgs* units = (BuildArgs*)(tb + h.off_units);
+  SepBuildArgs* sunits = (SepBuildArgs*)(tb + h.off_units);
   int32_t* upre = (int32_t*)(tb + h.off_uprefix);
   for (int f = 0; f < nframes; ++f) {
+    if (sep) {
+      const swih_frame_desc& fd = frames[f];
+      const swih_config fc = frame_config(cfg, fd);
+      const SepLayout SL = sep_layout(fd.height, fd.width, cfg->nbins, h.nt);
+      for (int k = 0; k < ubase[f + 1] - ubase[f]; ++k) {
+        const int u = ubase[f] + k;
+        ScaleParams sp;
+        scale_params(&fc, k, sp);
+        const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, h.nt);
+        int32_t nb[2];
+        sep_build_args(sg, SL, sp.ax, sp.ay, fd.d_img, fd.pitch,
+                       (char*)fd.d_ws + (size_t)k * layouts[f].set_bytes, sunits[u], nb);
+        for (int s = 0; s < 4; ++s)
+          upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + (s < 2 ? nb[s] : 0);
+      }
+      continue;
+    }
     const swih_frame_desc& fd = frames[f];
     const swih_config fc = frame_config(cfg, fd);
     for (int k = 0; k < ubase[f + 1] - ubase[f]; ++k) {
@@ -388,10 +450,20 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     if (qd.frame < 0 || qd.frame >= nframes || qd.n < 0) return SWIH_ERR_INVALID;
     const swih_config fc = frame_config(cfg, frames[qd.frame]);
     if (qd.scale_idx < 0 || qd.scale_idx >= fc.nscales) return SWIH_ERR_INVALID;
-    if (gauss && qd.d_hist_raw) return SWIH_ERR_UNSUPPORTED;
+    if ((gauss || sep) && qd.d_hist_raw) return SWIH_ERR_UNSUPPORTED;
     if (qd.n > 0 && (!qd.d_centres || (!qd.d_hist && !qd.d_hist_raw))) return SWIH_ERR_INVALID;
     ScaleParams sp;
     scale_params(&fc, qd.scale_idx, sp);
+    if (sep) {
+      const swih_frame_desc& fd = frames[qd.frame];
+      const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, h.nt);
+      int32_t nb = 0;
+      sep_query_args(sg, sep_layout(fd.height, fd.width, cfg->nbins, h.nt), sp.mass,
+                     (const char*)fd.d_ws + (size_t)qd.scale_idx * layouts[qd.frame].set_bytes,
+                     qd.d_centres, qd.n, qd.d_hist, ((SepQueryArgs*)(tb + h.off_q))[q], nb);
+      qpre[q + 1] = qpre[q] + (qd.n > 0 ? nb : 0);
+      continue;
+    }
     Launch ql;
     query_args(layouts[qd.frame], sp, gauss ? qd.scale_idx : 0, (const char*)frames[qd.frame].d_ws,
                qd.d_centres, qd.n, qd.d_hist, qd.d_hist_raw, qa[q], ql);
@@ -409,7 +481,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     const swih_config fc = frame_config(cfg, fd);
     if (md.scale_idx < 0 || md.scale_idx >= fc.nscales) return SWIH_ERR_INVALID;
     if ((md.d_template == nullptr) == (md.d_template_raw == nullptr)) return SWIH_ERR_INVALID;
-    if (gauss && md.d_template_raw) return SWIH_ERR_UNSUPPORTED;
+    if ((gauss || sep) && md.d_template_raw) return SWIH_ERR_UNSUPPORTED;
     const swih_rect r = md.centres;
     const bool empty = r.x1 < r.x0 || r.y1 < r.y0;
     if (!empty) {
@@ -420,6 +492,18 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     }
     ScaleParams sp;
     scale_params(&fc, md.scale_idx, sp);
+    if (sep) {
+      int32_t nb = 0;
+      if (!empty) {
+        const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, h.nt);
+        sep_match_args(sg, sep_layout(fd.height, fd.width, cfg->nbins, h.nt), sp.mass,
+                       (const char*)fd.d_ws + (size_t)md.scale_idx * layouts[md.frame].set_bytes,
+                       md.d_template, r.x0, r.y0, r.x1, r.y1, md.d_map,
+                       ((SepMatchArgs*)(tb + h.off_m))[m], nb);
+      }
+      mpre[m + 1] = mpre[m] + nb;
+      continue;
+    }
     Launch ml;
     memset(&ml, 0, sizeof(ml));
     if (!empty)
@@ -440,6 +524,14 @@ int swih_build_batch(const void* h_table, const void* d_table, void* stream) {
   const BatchHeader* h = header_of(h_table);
   if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
   const char* db = (const char*)d_table;
+  if (h->kind == SWIH_GAUSSIAN_SEP) {
+    const int32_t tot[2] = {h->total[0], h->total[1]};
+    return sep_launch_build_batch(h->nt, h->nbins, (const SepBuildArgs*)(db + h->off_units),
+                                  (const int32_t*)(db + h->off_uprefix), h->nunits, tot,
+                                  kBatchGrid, (hipStream_t)stream) == hipSuccess
+               ? SWIH_OK
+               : SWIH_ERR_HIP;
+  }
   return launch_build_batch(h->kind, h->nt, (const BuildArgs*)(db + h->off_units),
                             (const int32_t*)(db + h->off_uprefix), h->nunits, h->total, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess
@@ -451,6 +543,12 @@ int swih_query_batch(const void* h_table, const void* d_table, void* stream) {
   const BatchHeader* h = header_of(h_table);
   if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
   const char* db = (const char*)d_table;
+  if (h->kind == SWIH_GAUSSIAN_SEP)
+    return sep_launch_query_batch(h->nt, h->nbins, (const SepQueryArgs*)(db + h->off_q),
+                                  (const int32_t*)(db + h->off_qprefix), h->nq, h->ql.blocks,
+                                  kBatchGrid, (hipStream_t)stream) == hipSuccess
+               ? SWIH_OK
+               : SWIH_ERR_HIP;
   return launch_query_batch(h->kind, h->nt, (const QueryArgs*)(db + h->off_q),
                             (const int32_t*)(db + h->off_qprefix), h->nq, h->ql, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess
@@ -462,6 +560,12 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream) {
   const BatchHeader* h = header_of(h_table);
   if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
   const char* db = (const char*)d_table;
+  if (h->kind == SWIH_GAUSSIAN_SEP)
+    return sep_launch_match_batch(h->nt, h->nbins, (const SepMatchArgs*)(db + h->off_m),
+                                  (const int32_t*)(db + h->off_mprefix), h->nm, h->ml.blocks,
+                                  kBatchGrid, (hipStream_t)stream) == hipSuccess
+               ? SWIH_OK
+               : SWIH_ERR_HIP;
   return launch_match_batch(h->kind, h->nt, (const MatchArgs*)(db + h->off_m),
                             (const int32_t*)(db + h->off_mprefix), h->nm, h->ml, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess

@@ -121,4 +121,100 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
                         int32_t x1, int32_t y1, float* map, hipStream_t stream);
 
+// ------------------------------------------------------------------------
+// Separable two-pass form of the Gaussian series (kernel SWIH_GAUSSIAN_SEP).
+//
+// The 2-D weight terms u_i(x) v_j(y) of the Gaussian are products of two 1-D
+// families, so the window histogram factors into two 1-D weighted integral
+// histograms with translation (Sec. 2.1, Eq. 2, applied per axis):
+//   row pass:    h_b(xc; y) = sum_i alpha_i(xc) sum_{|x - xc| <= rx} [Q(x, y) = b] u_i(x)
+//   column pass: H_b(xc, yc) = sum_j beta_j(yc) sum_{|y - yc| <= ry} h_b(xc; y) v_j(y)
+// The row results h (one float per row, valid centre column and bin) are the
+// only large buffer; nothing of size terms x bins x pixels is ever stored.
+
+struct SepGeom {
+  int32_t H, W, B;      // image size, bins
+  int32_t w, h, rx, ry; // window
+  int32_t Wv, Hv;       // valid centre columns / rows: W - w + 1, H - h + 1
+  int32_t nT;           // terms per axis, 2K + 1
+  int32_t SX;           // row pass: centre columns per wave
+  int32_t SY;           // column pass: centre rows per segment (segments start at multiples of SY)
+};
+
+// Workspace of one scale (set-relative byte offsets, 256-byte aligned).
+struct SepLayout {
+  int64_t off_hr;   // float  [H][W - w + 1][B]   row results (sized for W)
+  int64_t off_ux;   // double [W][nT]  x terms, fixed point round(u * 2^24) (integer valued)
+  int64_t off_al;   // double [W][nT]  alpha_i at centre column rx + v, times 2^-24
+  int64_t off_vy;   // double [H][nT]  y terms, round(v * 2^24) * 2^-24
+  int64_t off_be;   // double [H][nT]  beta_j at centre row ry + u
+  int64_t set_bytes;
+};
+
+SepLayout sep_layout(int32_t H, int32_t W, int32_t B, int32_t nT);
+SepGeom sep_geom(int32_t H, int32_t W, int32_t B, int32_t w, int32_t h, int32_t nT);
+
+struct SepBuildArgs {
+  SepGeom g;
+  const uint8_t* img;
+  int32_t ipitch;
+  float* hr;
+  double* ux;
+  double* al;
+  double* vy;
+  double* be;
+  GaussAxis ax, ay;
+};
+
+struct SepQueryArgs {
+  SepGeom g;
+  const float* hr;
+  const double* vy;
+  const double* be;
+  double inv_mass;
+  const int32_t* centres;  // [n][2]
+  int32_t n;
+  float* hist;             // [n][B]
+};
+
+struct SepMatchArgs {
+  SepGeom g;
+  const float* hr;
+  const double* vy;
+  const double* be;
+  double inv_mass;
+  const float* tmpl;       // [B] normalised template
+  float* map;
+  int32_t x0, y0, x1, y1;  // inclusive centre rectangle
+  int32_t nwx;             // waves across the rectangle
+  int32_t seg0, nseg;      // first segment (absolute) and segment count
+};
+
+// Blocks (of 256 threads) of the two build stages: tables, row pass.
+void sep_build_args(const SepGeom& g, const SepLayout& L, const GaussAxis& ax,
+                    const GaussAxis& ay, const uint8_t* img, int32_t img_pitch, char* set_base,
+                    SepBuildArgs& a, int32_t (&nb)[2]);
+void sep_query_args(const SepGeom& g, const SepLayout& L, double mass, const char* set_base,
+                    const int32_t* centres, int32_t n, float* hist, SepQueryArgs& a, int32_t& nb);
+void sep_match_args(const SepGeom& g, const SepLayout& L, double mass, const char* set_base,
+                    const float* tmpl, int32_t x0, int32_t y0, int32_t x1, int32_t y1, float* map,
+                    SepMatchArgs& a, int32_t& nb);
+
+// phases: bit 1 = tables, bit 2 = row pass.
+hipError_t sep_launch_build(const SepBuildArgs& a, const int32_t (&nb)[2], int phases,
+                            hipStream_t s);
+hipError_t sep_launch_query(const SepQueryArgs& a, int32_t nb, hipStream_t s);
+hipError_t sep_launch_match(const SepMatchArgs& a, int32_t nb, hipStream_t s);
+// Batched forms: grid-stride launches over the items' virtual blocks
+// (prefix: exclusive block prefixes in device memory; build: 2 arrays).
+hipError_t sep_launch_build_batch(int nt, int nbins, const SepBuildArgs* units,
+                                  const int32_t* prefix, int nunits, const int32_t (&total)[2],
+                                  int grid, hipStream_t s);
+hipError_t sep_launch_query_batch(int nt, int nbins, const SepQueryArgs* items,
+                                  const int32_t* prefix, int n, int32_t total, int grid,
+                                  hipStream_t s);
+hipError_t sep_launch_match_batch(int nt, int nbins, const SepMatchArgs* items,
+                                  const int32_t* prefix, int n, int32_t total, int grid,
+                                  hipStream_t s);
+
 }  // namespace swih

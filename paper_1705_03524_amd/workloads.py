@@ -61,7 +61,7 @@ def tracking_units(cfg: S.Config, frames, device="cuda"):
     """Units and jobs for ``synth.batch_frames``-style frames (dicts with
     ``image`` and ``rois`` of ``centre``, ``scales``, ``search``)."""
     units = []
-    integer = cfg.kernel != S.GAUSSIAN
+    integer = cfg.kernel not in S.SERIES_KINDS
     for fr in frames:
         img = torch.from_numpy(fr["image"]).to(device)
         H, W = fr["image"].shape
@@ -125,7 +125,7 @@ class BatchedRunner:
             groups.append(cur)
         self.ws = torch.empty(max(ALIGN, max(sum(unit_bytes(cfg, u) for u in g) for g in groups)),
                               dtype=torch.uint8, device=device)
-        integer = cfg.kernel != S.GAUSSIAN
+        integer = cfg.kernel not in S.SERIES_KINDS
         self.batches = []
         for g in groups:
             frames, queries, matches = [], [], []
@@ -178,7 +178,7 @@ class PerFrameRunner:
         self.cfg, self.units = cfg, units
         self.ws = torch.empty(max(ALIGN, max(unit_bytes(cfg, u) for u in units)), dtype=torch.uint8,
                               device=device)
-        self.integer = cfg.kernel != S.GAUSSIAN
+        self.integer = cfg.kernel not in S.SERIES_KINDS
         self.plans = []
         for u in units:
             uc = unit_config(cfg, u)

@@ -4,8 +4,19 @@ from __future__ import annotations
 import numpy as np
 
 
+# Gaussian normalised histograms: max |p' - p| over bins and windows against the
+# FP64 true-Gaussian oracle (the series' own error is below 1e-6 of the mass).
+GAUSS_TOL = 1e-5
+
+
 def to_dev(a, torch):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def all_centres(H, W, w, h):
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    ys, xs = np.mgrid[ry:H - ry, rx:W - rx]
+    return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
 
 
 def map_tolerance(p_oracle: np.ndarray, t_oracle: np.ndarray, eps: float,
@@ -30,3 +41,43 @@ def map_tolerance(p_oracle: np.ndarray, t_oracle: np.ndarray, eps: float,
         return (dp * st).sum(1)
     dt = d(t_oracle)[None, :]
     return (dp * (st + dt) + np.sqrt(np.maximum(p_oracle, 0.0)) * dt).sum(1)
+
+
+def gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=None, kind=None):
+    """Histograms at ``centres``, the template at ``tcentre`` and (optionally) the
+    map over ``map_rect`` of a series-Gaussian kind against the FP64 oracle."""
+    import torch
+
+    import oracle
+    import paper_1705_03524_amd as swih
+    from paper_1705_03524_amd.plan import Plan
+    H, W = img.shape
+    cfg = swih.Config(nb, swih.GAUSSIAN if kind is None else kind, [(w, h)])
+    plan = Plan(cfg, H, W)
+    plan.build(to_dev(img, torch))
+    hist, _ = plan.query(0, to_dev(centres, torch))
+    thist, _ = plan.query(0, to_dev(np.array([tcentre], np.int32), torch))
+    got = hist.cpu().numpy().astype(np.float64)
+    ref = oracle.normalised(oracle.hist(img, nb, oracle.GAUSSIAN, w, h, centres), oracle.GAUSSIAN, w, h)
+    herr = np.abs(got - ref).max()
+    _, tref = oracle.template(img, nb, oracle.GAUSSIAN, w, h, tcentre)
+    terr = np.abs(thist.cpu().numpy()[0] - tref).max()
+    out = {"hist_err": float(herr), "template_err": float(terr)}
+    if map_rect is not None:
+        m = plan.match(0, template=thist[0].contiguous(), rect=map_rect).cpu().numpy()
+        m_or = plan.match(0, template=to_dev(tref.astype(np.float32), torch), rect=map_rect).cpu().numpy()
+        mref = oracle.bc_map(img, nb, oracle.GAUSSIAN, w, h, tref, rect=map_rect)
+        x0, y0, x1, y1 = map_rect
+        ys, xs = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        cc = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+        pref = oracle.normalised(oracle.hist(img, nb, oracle.GAUSSIAN, w, h, cc), oracle.GAUSSIAN, w, h)
+        tol = map_tolerance(pref, tref, GAUSS_TOL).reshape(mref.shape) + 1e-6
+        tol_or = map_tolerance(pref, tref, GAUSS_TOL, template_exact=True).reshape(mref.shape) + 1e-6
+        out["map_err"] = float(np.abs(m - mref).max())
+        out["map_err_oracle_template"] = float(np.abs(m_or - mref).max())
+        assert np.all(np.abs(m - mref) <= tol), label
+        assert np.all(np.abs(m_or - mref) <= tol_or), label
+    print(label, out, flush=True)
+    assert herr <= GAUSS_TOL, (label, herr)
+    assert terr <= GAUSS_TOL, (label, terr)
+    return out

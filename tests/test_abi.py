@@ -56,6 +56,46 @@ def test_workspace_bytes_and_validation():
     assert g2 > 1.9 * g1 - 2e6
 
 
+def test_separable_workspace_and_validation():
+    # one set per scale: H x W x B floats of row results (sized for the smallest
+    # window) plus four tables of (2K+1) doubles per column / row
+    def a256(v):
+        return (v + 255) // 256 * 256
+    H, W, B, nT = 480, 640, 16, 9
+    per_set = a256(H * W * B * 4) + 2 * a256(W * nT * 8) + 2 * a256(H * nT * 8)
+    for scales in ([(31, 31)], [(31, 31), (9, 21), (101, 1)]):
+        n = swih.workspace_bytes(swih.Config(B, swih.GAUSSIAN_SEP, scales), H, W)
+        assert n == len(scales) * per_set
+    two_d = swih.workspace_bytes(swih.Config(B, swih.GAUSSIAN, [(31, 31)]), H, W)
+    assert two_d > 60 * per_set                         # 81 planes + carries vs row results
+    for c in (swih.Config(8, swih.GAUSSIAN_SEP, [(3, 3)], gauss_terms=9),
+              swih.Config(8, swih.GAUSSIAN_SEP, [(3, 3)], gauss_terms=-1),
+              swih.Config(8, swih.GAUSSIAN_SEP, [(2, 3)]),
+              swih.Config(8, 5, [(3, 3)])):
+        with pytest.raises(swih.SwihError) as e:
+            swih.workspace_bytes(c, 64, 64)
+        assert e.value.status == _swih.ERR_INVALID
+
+
+def test_separable_host_checks():
+    import ctypes as C
+    lib = swih.load()
+    g = swih.Config(8, swih.GAUSSIAN_SEP, [(5, 5)])
+    st = lib.swih_query(C.byref(g.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, C.c_void_p(256), 4,
+                        None, C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # no exact raw histograms
+    r = _swih._Rect(2, 2, 10, 10)
+    st = lib.swih_match(C.byref(g.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, None, C.c_void_p(256), r,
+                        C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # raw template
+    st = lib.swih_match(C.byref(g.c()), C.c_void_p(256), 16, 64, 64, 0, C.c_void_p(256), None, r,
+                        C.c_void_p(256), None)
+    assert st == _swih.ERR_WORKSPACE
+    st = lib.swih_build_carries(C.byref(g.c()), C.c_void_p(256), 64, 64, 64, 1, C.c_void_p(256),
+                                1 << 30, None)
+    assert st == _swih.ERR_INVALID          # only set 0 exists
+
+
 def test_host_checks_before_launch():
     # rejected on the host: nothing reaches the device, so no GPU is needed
     import ctypes as C

@@ -102,12 +102,13 @@ def test_batch_equals_single_integer(kind):
             checked += 1
 
 
-def test_batch_equals_single_gaussian_crops():
-    print("case: batch gaussian crops with per-frame scales", flush=True)
+@pytest.mark.parametrize("kind", [swih.GAUSSIAN, swih.GAUSSIAN_SEP])
+def test_batch_equals_single_gaussian_crops(kind):
+    print("case: batch gaussian (kind %d) crops with per-frame scales" % kind, flush=True)
     big = to_dev(synth.smooth_noise(77, 600, 700), torch)
     crops = [big[10:210, 20:300], big[300:420, 100:260], big[50:131, 400:690], big[500:560, 0:90]]
     scales = [[(21, 21), (31, 15)], [(15, 15)], [(9, 9), (25, 31), (41, 41)], [(11, 13)]]
-    cfg = swih.Config(16, swih.GAUSSIAN, [(15, 15)])
+    cfg = swih.Config(16, kind, [(15, 15)])
     b, outs = make_batch(cfg, crops, scales, False, list(range(len(crops))))
     b.run()
     torch.cuda.synchronize()
@@ -150,13 +151,13 @@ def test_mix_invariance():
             assert torch.equal(gres[0][k][0], r[k][0]) and torch.equal(gres[0][k][1], r[k][1])
 
 
-@pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.GAUSSIAN])
+@pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.GAUSSIAN, swih.GAUSSIAN_SEP])
 def test_graph_replay(kind):
     print("case: graph replay kind %d" % kind, flush=True)
     cfg = swih.Config(16, kind, SCALES)
     imgs = [to_dev(synth.smooth_noise(50 + k, H, W), torch) for k, (H, W) in enumerate(SIZES)]
     scales = [[s for s in SCALES if s[0] <= W and s[1] <= H] for (H, W) in SIZES]
-    integer = kind != swih.GAUSSIAN
+    integer = kind not in (swih.GAUSSIAN, swih.GAUSSIAN_SEP)
     b, outs = make_batch(cfg, imgs, scales, integer, list(range(len(imgs))))
     b.run()
     torch.cuda.synchronize()

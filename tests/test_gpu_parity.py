@@ -22,16 +22,10 @@ pytestmark = pytest.mark.gpu
 import paper_1705_03524_amd as swih  # noqa: E402
 from paper_1705_03524_amd.plan import Plan  # noqa: E402
 
-from gpu_util import map_tolerance, to_dev  # noqa: E402
+from gpu_util import GAUSS_TOL, all_centres, gauss_check, to_dev  # noqa: E402
 
 INT_KINDS = (swih.UNIFORM, swih.MANHATTAN, swih.EUCLIDEAN)
-GAUSS_TOL = 1e-5
-
-
-def all_centres(H, W, w, h):
-    rx, ry = (w - 1) // 2, (h - 1) // 2
-    ys, xs = np.mgrid[ry:H - ry, rx:W - rx]
-    return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+GAUSS_KINDS = (swih.GAUSSIAN, swih.GAUSSIAN_SEP)
 
 
 def run_int(img, nb, kind, w, h, tcentre, centres=None, rect=None):
@@ -196,55 +190,25 @@ def test_empty_inputs_are_noops():
 
 
 # ---------------------------------------------------------------- Gaussian
-def gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=None):
-    H, W = img.shape
-    cfg = swih.Config(nb, swih.GAUSSIAN, [(w, h)])
-    plan = Plan(cfg, H, W)
-    plan.build(to_dev(img, torch))
-    hist, _ = plan.query(0, to_dev(centres, torch))
-    thist, _ = plan.query(0, to_dev(np.array([tcentre], np.int32), torch))
-    got = hist.cpu().numpy().astype(np.float64)
-    ref = oracle.normalised(oracle.hist(img, nb, oracle.GAUSSIAN, w, h, centres), oracle.GAUSSIAN, w, h)
-    herr = np.abs(got - ref).max()
-    _, tref = oracle.template(img, nb, oracle.GAUSSIAN, w, h, tcentre)
-    terr = np.abs(thist.cpu().numpy()[0] - tref).max()
-    out = {"hist_err": float(herr), "template_err": float(terr)}
-    if map_rect is not None:
-        m = plan.match(0, template=thist[0].contiguous(), rect=map_rect).cpu().numpy()
-        m_or = plan.match(0, template=to_dev(tref.astype(np.float32), torch), rect=map_rect).cpu().numpy()
-        mref = oracle.bc_map(img, nb, oracle.GAUSSIAN, w, h, tref, rect=map_rect)
-        x0, y0, x1, y1 = map_rect
-        ys, xs = np.mgrid[y0:y1 + 1, x0:x1 + 1]
-        cc = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
-        pref = oracle.normalised(oracle.hist(img, nb, oracle.GAUSSIAN, w, h, cc), oracle.GAUSSIAN, w, h)
-        tol = map_tolerance(pref, tref, GAUSS_TOL).reshape(mref.shape) + 1e-6
-        tol_or = map_tolerance(pref, tref, GAUSS_TOL, template_exact=True).reshape(mref.shape) + 1e-6
-        out["map_err"] = float(np.abs(m - mref).max())
-        out["map_err_oracle_template"] = float(np.abs(m_or - mref).max())
-        assert np.all(np.abs(m - mref) <= tol), label
-        assert np.all(np.abs(m_or - mref) <= tol_or), label
-    print(label, out, flush=True)
-    assert herr <= GAUSS_TOL, (label, herr)
-    assert terr <= GAUSS_TOL, (label, terr)
-    return out
-
-
-def test_gaussian_scene512(scene512):
+@pytest.mark.parametrize("kind", GAUSS_KINDS)
+def test_gaussian_scene512(scene512, kind):
     img, tc = scene512
     c = all_centres(512, 512, 31, 31)
-    gauss_check(img, 16, 31, 31, c, tc, "gaussian 512x512 31x31", map_rect=(15, 15, 496, 496))
+    gauss_check(img, 16, 31, 31, c, tc, "gaussian(%d) 512x512 31x31" % kind, map_rect=(15, 15, 496, 496),
+                kind=kind)
 
 
+@pytest.mark.parametrize("kind", GAUSS_KINDS)
 @pytest.mark.parametrize("HW,nb,wh", [((100, 77), 3, (5, 9)), ((65, 129), 16, (15, 21)),
                                       ((33, 33), 7, (33, 33)), ((20, 31), 5, (1, 1))])
-def test_gaussian_ragged(HW, nb, wh):
+def test_gaussian_ragged(HW, nb, wh, kind):
     H, W = HW
     w, h = wh
     img = synth.uniform_noise(H * 7 + W, H, W)
     c = all_centres(H, W, w, h)
     rx, ry = (w - 1) // 2, (h - 1) // 2
-    gauss_check(img, nb, w, h, c, tuple(c[len(c) // 2]), "gaussian ragged %s %s" % (HW, wh),
-                map_rect=(rx, ry, W - 1 - rx, H - 1 - ry))
+    gauss_check(img, nb, w, h, c, tuple(c[len(c) // 2]), "gaussian(%d) ragged %s %s" % (kind, HW, wh),
+                map_rect=(rx, ry, W - 1 - rx, H - 1 - ry), kind=kind)
 
 
 @pytest.mark.parametrize("w", [21, 31, 45, 63, 81])
