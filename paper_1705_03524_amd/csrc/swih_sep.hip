@@ -89,18 +89,87 @@ int32_t table_blocks(const SepGeom& g) {
   return (int32_t)((n + WG - 1) / WG);
 }
 
+// ---------------------------------------------------------------- walks
+// Both passes walk a line of elements (pixels of a row, or rows of h) with a
+// window of L elements: step s adds element s; once the window is complete
+// (s >= L - 1) it is evaluated for centre c = s - (L - 1), and element c
+// leaves.  The per-element table rows a step needs are wave-uniform; each
+// wave stages them in its own LDS slice a chunk of CH steps at a time (rows
+// of the element entering, and of the centre), together with its lanes' data
+// for the chunk in registers, so a chunk costs one memory latency instead of
+// one per step.  LDS traffic of one wave is ordered, so the stage-then-read
+// sequence only needs the compiler fence.
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over aligned groups of BP lanes (BP a power of two <= 64); every lane of
+// a group gets the same value.  Within a 16-lane row: quad_perm [1,0,3,2] and
+// [2,3,0,1], then row_half_mirror and row_mirror pair the quads and halves.
+__device__ __forceinline__ double group_sum(double v, int BP) {
+  if (BP >= 2) v += dpp_f64<0xB1>(v);
+  if (BP >= 4) v += dpp_f64<0x4E>(v);
+  if (BP >= 8) v += dpp_f64<0x141>(v);
+  if (BP >= 16) v += dpp_f64<0x140>(v);
+  if (BP >= 32) v += __shfl_xor(v, 16, 64);
+  if (BP >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Table rows [max(r0, lo), min(r0 + N, hi)) of a [rows][NT] double table, held
+// in registers between load() (all loads issued back to back) and store()
+// into LDS as dst[(r - r0) * NT + i].
+template <int NT, int N>
+struct StageRows {
+  static constexpr int PER = (N * NT + 63) / 64;
+  double v[PER];
+  int a, b;
+  __device__ __forceinline__ void load(const double* __restrict__ tab, int r0, int lo, int hi,
+                                       int lane) {
+    a = (max(r0, lo) - r0) * NT;
+    b = (min(r0 + N, hi) - r0) * NT;
+    if (b <= a) return;  // uniform
+    const double* src = tab + (long)r0 * NT;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) v[k] = src[min(max(lane + 64 * k, a), b - 1)];
+  }
+  __device__ __forceinline__ void store(double* dst, int lane) const {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int t = lane + 64 * k;
+      if (t >= a && t < b) dst[t] = v[k];
+    }
+  }
+};
+
 // ---------------------------------------------------------------- row pass
 // A wave owns RPW = 64 / BP image rows (BP lanes per row, one bin per lane and
 // chunk of 64 bins) and SX consecutive centre columns; it walks the centres
-// left to right with NT running window sums per bin.
+// left to right with NT running window sums per bin.  Chunks are software
+// pipelined: the pixels and table rows of chunk k + 1 are in flight while
+// chunk k is computed from registers and LDS.
 template <int NT, int NCH>
 __device__ void sep_rows(const SepBuildArgs& a, int vb) {
+  constexpr int CH = 16;
+  __shared__ double stage[WPB][3][CH * NT];
   const SepGeom& g = a.g;
   const int B = g.B;
   const int BP = NCH > 1 ? 64 : bin_lanes(B);
   const int RPW = 64 / BP;
   const int lane = (int)(threadIdx.x & 63);
-  const int wv = rfl(vb * WPB + (int)(threadIdx.x >> 6));
+  const int wid = (int)(threadIdx.x >> 6);
+  const int wv = rfl(vb * WPB + wid);
   const int nsx = (g.Wv + g.SX - 1) / g.SX;
   const int rg = wv / nsx;
   if (rg * RPW >= g.H) return;  // padding waves of the last block (uniform per wave)
@@ -109,9 +178,10 @@ __device__ void sep_rows(const SepBuildArgs& a, int vb) {
   const int y = rg * RPW + lane / BP;
   const bool row_ok = y < g.H;
   const uint8_t* __restrict__ row = a.img + (size_t)(row_ok ? y : g.H - 1) * a.ipitch;
-  const double* __restrict__ ux = a.ux;
-  const double* __restrict__ al = a.al;
   float* __restrict__ hr = a.hr;
+  double* s_in = stage[wid][0];
+  double* s_out = stage[wid][1];
+  double* s_al = stage[wid][2];
   int bin[NCH];
   bool bok[NCH];
 #pragma unroll
@@ -125,64 +195,69 @@ __device__ void sep_rows(const SepBuildArgs& a, int vb) {
 #pragma unroll
     for (int i = 0; i < NT; ++i) win[c][i] = 0.0;
   // The window sums only ever add or remove integer terms (masks 0 or 1 times
-  // round(u 2^24)), so they are exact.  Pixels are loaded a chunk of U steps
-  // ahead; the tables are wave-uniform (scalar loads).
-  constexpr int U = 8;
-  // the first w - 1 pixels of the first window
-  for (int x0 = v0; x0 < v0 + g.w - 1; x0 += U) {
-    int q[U];
+  // round(u 2^24)), so they are exact.
+  const int L = g.w, nc = v1 - v0, nsteps = L - 1 + nc;
+  int qi[CH], qo[CH];
+  StageRows<NT, CH> t_in, t_out, t_al;
+  auto fetch = [&](int s0, int (&pi)[CH], int (&po)[CH]) {
+    const int c0 = s0 - (L - 1);
 #pragma unroll
-    for (int u = 0; u < U; ++u) q[u] = ((int)row[min(x0 + u, v0 + g.w - 2)] * B) >> 8;
+    for (int u = 0; u < CH; ++u) {
+      pi[u] = row[v0 + min(s0 + u, nsteps - 1)];
+      po[u] = row[v0 + min(max(c0 + u, 0), nc - 1)];
+    }
+    t_in.load(a.ux, v0 + s0, v0, v0 + nsteps, lane);
+    t_out.load(a.ux, v0 + c0, v0, v1, lane);
+    t_al.load(a.al, v0 + c0, v0, v1, lane);
+  };
+  auto put = [&]() {
+    wave_fence();  // reads of the previous chunk are issued (LDS is in order per wave)
+    t_in.store(s_in, lane);
+    t_out.store(s_out, lane);
+    t_al.store(s_al, lane);
+    wave_fence();
+  };
+  fetch(0, qi, qo);
+  put();
+  for (int s0 = 0; s0 < nsteps; s0 += CH) {
+    const int c0 = s0 - (L - 1);  // centre of the chunk's first step
+    const bool more = s0 + CH < nsteps;
+    int ni[CH], no[CH];
+    if (more) fetch(s0 + CH, ni, no);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (x0 + u >= v0 + g.w - 1) break;
-      const double* up = ux + (size_t)(x0 + u) * NT;
-      double uv[NT];
+    for (int u = 0; u < CH; ++u) {
+      if (s0 + u < nsteps) {
+        const double* ui = s_in + u * NT;
+        const int q = (qi[u] * B) >> 8;
 #pragma unroll
-      for (int i = 0; i < NT; ++i) uv[i] = up[i];
+        for (int c = 0; c < NCH; ++c) {
+          const double m = q == bin[c] ? 1.0 : 0.0;
+#pragma unroll
+          for (int i = 0; i < NT; ++i) win[c][i] = fma(m, ui[i], win[c][i]);
+        }
+      }
+      if (s0 + u >= nsteps || c0 + u < 0) continue;
+      const int v = v0 + c0 + u;
+      const double* uo = s_out + u * NT;
+      const double* av = s_al + u * NT;
+      const int q = (qo[u] * B) >> 8;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        const double m = q[u] == bin[c] ? 1.0 : 0.0;
-#pragma unroll
-        for (int i = 0; i < NT; ++i) win[c][i] = fma(m, uv[i], win[c][i]);
-      }
-    }
-  }
-  for (int vs = v0; vs < v1; vs += U) {
-    int qi[U], qo[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int v = min(vs + u, v1 - 1);
-      qi[u] = ((int)row[v + g.w - 1] * B) >> 8;
-      qo[u] = ((int)row[v] * B) >> 8;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int v = vs + u;
-      if (v >= v1) break;
-      const double* ui = ux + (size_t)(v + g.w - 1) * NT;
-      const double* uo = ux + (size_t)v * NT;
-      const double* av = al + (size_t)v * NT;
-      double uiv[NT], uov[NT], avv[NT];
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        uiv[i] = ui[i];
-        uov[i] = uo[i];
-        avv[i] = av[i];
-      }
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const double mi = qi[u] == bin[c] ? 1.0 : 0.0;
-        const double mo = qo[u] == bin[c] ? -1.0 : 0.0;
         double hv = 0.0;
 #pragma unroll
-        for (int i = 0; i < NT; ++i) {
-          win[c][i] = fma(mi, uiv[i], win[c][i]);
-          hv = fma(avv[i], win[c][i], hv);
-        }
+        for (int i = 0; i < NT; ++i) hv = fma(av[i], win[c][i], hv);
         if (bok[c]) hr[((size_t)y * g.Wv + v) * B + bin[c]] = (float)hv;
+        const double m = q == bin[c] ? -1.0 : 0.0;
 #pragma unroll
-        for (int i = 0; i < NT; ++i) win[c][i] = fma(mo, uov[i], win[c][i]);
+        for (int i = 0; i < NT; ++i) win[c][i] = fma(m, uo[i], win[c][i]);
+      }
+    }
+    if (more) {
+      put();
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        qi[u] = ni[u];
+        qo[u] = no[u];
       }
     }
   }
@@ -199,8 +274,11 @@ int32_t row_blocks(const SepGeom& g) {
 // window sums of h v_j are taken directly over the h rows of the window.
 template <int NT, int NCH>
 __device__ void sep_query(const SepQueryArgs& a, int vb) {
+  constexpr int CH = 16 / NCH;
+  __shared__ double stage[WPB][CH * NT];
   const SepGeom& g = a.g;
-  const int n = rfl(vb * WPB + (int)(threadIdx.x >> 6));
+  const int wid = (int)(threadIdx.x >> 6);
+  const int n = rfl(vb * WPB + wid);
   if (n >= a.n) return;
   const int lane = (int)(threadIdx.x & 63);
   const int xc = min(max(a.centres[2 * n], g.rx), g.W - 1 - g.rx);
@@ -208,19 +286,53 @@ __device__ void sep_query(const SepQueryArgs& a, int vb) {
   const int B = g.B;
   const float* __restrict__ hcol = a.hr + (size_t)(xc - g.rx) * B;
   const size_t rstride = (size_t)g.Wv * B;
+  double* s_v = stage[wid];
   double win[NCH][NT];
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int j = 0; j < NT; ++j) win[c][j] = 0.0;
-  for (int y = yc - g.ry; y <= yc + g.ry; ++y) {
-    const double* vv = a.vy + (size_t)y * NT;
+  const int y0 = yc - g.ry;
+  float hv[CH][NCH];
+  StageRows<NT, CH> t_v;
+  auto fetch = [&](int s0, float (&p)[CH][NCH]) {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int b = lane + 64 * c;
-      const double hv = b < B ? (double)hcol[(size_t)y * rstride + b] : 0.0;
+    for (int u = 0; u < CH; ++u)
 #pragma unroll
-      for (int j = 0; j < NT; ++j) win[c][j] = fma(hv, vv[j], win[c][j]);
+      for (int c = 0; c < NCH; ++c) {
+        const int b = min(lane + 64 * c, B - 1);
+        p[u][c] = hcol[(size_t)(y0 + min(s0 + u, g.h - 1)) * rstride + b];
+      }
+    t_v.load(a.vy, y0 + s0, y0, y0 + g.h, lane);
+  };
+  auto put = [&]() {
+    wave_fence();
+    t_v.store(s_v, lane);
+    wave_fence();
+  };
+  fetch(0, hv);
+  put();
+  for (int s0 = 0; s0 < g.h; s0 += CH) {
+    const bool more = s0 + CH < g.h;
+    float nv[CH][NCH];
+    if (more) fetch(s0 + CH, nv);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (s0 + u >= g.h) continue;
+      const double* vv = s_v + u * NT;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double h = lane + 64 * c < B ? (double)hv[u][c] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) win[c][j] = fma(h, vv[j], win[c][j]);
+      }
+    }
+    if (more) {
+      put();
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) hv[u][c] = nv[u][c];
     }
   }
   const double* bb = a.be + (size_t)(yc - g.ry) * NT;
@@ -236,19 +348,21 @@ __device__ void sep_query(const SepQueryArgs& a, int vb) {
 
 // ---------------------------------------------------------------- dense map
 // A wave owns XPW = 64 / BP consecutive centres of one segment of SY centre
-// rows (BP lanes per centre, one bin per lane and chunk).  It starts the
-// column window sums with a direct sum at the segment's first row and walks
-// down: per row, H_b from the NT sums, the Bhattacharyya terms summed over the
-// centre's lanes, then the h row that enters is added and the one that leaves
-// subtracted.
+// rows (BP lanes per centre, one bin per lane and chunk).  It walks the h
+// rows down the segment: per centre row, H_b from the NT column window sums
+// and the translation coefficients beta(yc), the Bhattacharyya terms summed
+// over the centre's lanes, then the h row that leaves is removed.
 template <int NT, int NCH>
 __device__ void sep_match(const SepMatchArgs& a, int vb) {
+  constexpr int CH = 16 / NCH;
+  __shared__ double stage[WPB][3][CH * NT];
   const SepGeom& g = a.g;
   const int B = g.B;
   const int BP = NCH > 1 ? 64 : bin_lanes(B);
   const int XPW = 64 / BP;
   const int lane = (int)(threadIdx.x & 63);
-  const int wv = rfl(vb * WPB + (int)(threadIdx.x >> 6));
+  const int wid = (int)(threadIdx.x >> 6);
+  const int wv = rfl(vb * WPB + wid);
   const int seg = wv / a.nwx;
   if (seg >= a.nseg) return;  // padding waves of the last block (uniform per wave)
   const int wx = wv - seg * a.nwx;
@@ -259,15 +373,17 @@ __device__ void sep_match(const SepMatchArgs& a, int vb) {
   const int yi = max(k * g.SY, g.ry);
   const float* __restrict__ hcol = a.hr + (size_t)((x_ok ? xc : a.x0) - g.rx) * B;
   const size_t rstride = (size_t)g.Wv * B;
-  const double* __restrict__ vy = a.vy;
-  const double* __restrict__ be = a.be;
-  int bin[NCH];
+  double* s_in = stage[wid][0];
+  double* s_out = stage[wid][1];
+  double* s_be = stage[wid][2];
+  int bin[NCH], bcl[NCH];
   bool bok[NCH];
   double tv[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     bin[c] = lane % BP + 64 * c;
     bok[c] = bin[c] < B;
+    bcl[c] = min(bin[c], B - 1);
     tv[c] = bok[c] ? fmax((double)a.tmpl[bin[c]], 0.0) : 0.0;
   }
   double win[NCH][NT];
@@ -275,44 +391,84 @@ __device__ void sep_match(const SepMatchArgs& a, int vb) {
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int j = 0; j < NT; ++j) win[c][j] = 0.0;
-  for (int y = yi - g.ry; y <= yi + g.ry; ++y) {
-    const double* vv = vy + (size_t)y * NT;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const double hv = bok[c] ? (double)hcol[(size_t)y * rstride + bin[c]] : 0.0;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) win[c][j] = fma(hv, vv[j], win[c][j]);
-    }
-  }
   const int mw = a.x1 - a.x0 + 1;
-  for (int yc = yi; yc <= ye; ++yc) {
-    if (yc >= ys) {
-      const double* bb = be + (size_t)(yc - g.ry) * NT;
-      double s = 0.0;
+  const int L = g.h, nc = ye - yi + 1, nsteps = L - 1 + nc;
+  const int e0 = yi - g.ry;  // h row of element 0; centre c sits at row yi + c
+  float hi[CH][NCH], ho[CH][NCH];
+  StageRows<NT, CH> t_in, t_out, t_be;
+  auto fetch = [&](int s0, float (&pi)[CH][NCH], float (&po)[CH][NCH]) {
+    const int c0 = s0 - (L - 1);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const size_t ri = (size_t)(e0 + min(s0 + u, nsteps - 1)) * rstride;
+      const size_t ro = (size_t)(e0 + min(max(c0 + u, 0), nc - 1)) * rstride;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        double hb = 0.0;
-#pragma unroll
-        for (int j = 0; j < NT; ++j) hb = fma(bb[j], win[c][j], hb);
-        s += sqrt(fmax(hb * a.inv_mass, 0.0) * tv[c]);
+        pi[u][c] = hcol[ri + bcl[c]];
+        po[u][c] = hcol[ro + bcl[c]];
       }
-      for (int m = 1; m < BP; m <<= 1) s += __shfl_xor(s, m, 64);
-      if (x_ok && lane % BP == 0) a.map[(size_t)(yc - a.y0) * mw + (xc - a.x0)] = (float)s;
     }
-    if (yc < ye) {
-      const int yin = yc + g.ry + 1, yout = yc - g.ry;
-      const double* vi = vy + (size_t)yin * NT;
-      const double* vo = vy + (size_t)yout * NT;
+    t_in.load(a.vy, e0 + s0, e0, e0 + nsteps, lane);
+    t_out.load(a.vy, e0 + c0, e0, e0 + nc, lane);
+    t_be.load(a.be, e0 + c0, e0, e0 + nc, lane);  // beta row of centre yc is yc - ry
+  };
+  auto put = [&]() {
+    wave_fence();
+    t_in.store(s_in, lane);
+    t_out.store(s_out, lane);
+    t_be.store(s_be, lane);
+    wave_fence();
+  };
+  fetch(0, hi, ho);
+  put();
+  for (int s0 = 0; s0 < nsteps; s0 += CH) {
+    const int c0 = s0 - (L - 1);
+    const bool more = s0 + CH < nsteps;
+    float ni[CH][NCH], no[CH][NCH];
+    if (more) fetch(s0 + CH, ni, no);
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const double hi = bok[c] ? (double)hcol[(size_t)yin * rstride + bin[c]] : 0.0;
-        const double ho = bok[c] ? (double)hcol[(size_t)yout * rstride + bin[c]] : 0.0;
+    for (int u = 0; u < CH; ++u) {
+      if (s0 + u < nsteps) {
+        const double* vi = s_in + u * NT;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          win[c][j] = fma(hi, vi[j], win[c][j]);
-          win[c][j] = fma(-ho, vo[j], win[c][j]);
+        for (int c = 0; c < NCH; ++c) {
+          const double h = bok[c] ? (double)hi[u][c] : 0.0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) win[c][j] = fma(h, vi[j], win[c][j]);
         }
       }
+      if (s0 + u >= nsteps || c0 + u < 0) continue;
+      const int yc = yi + c0 + u;
+      if (yc >= ys) {
+        const double* bb = s_be + u * NT;
+        double sb = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          double hb = 0.0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) hb = fma(bb[j], win[c][j], hb);
+          sb += (double)sqrtf((float)(fmax(hb * a.inv_mass, 0.0) * tv[c]));
+        }
+        sb = group_sum(sb, BP);
+        if (x_ok && lane % BP == 0) a.map[(size_t)(yc - a.y0) * mw + (xc - a.x0)] = (float)sb;
+      }
+      const double* vo = s_out + u * NT;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double h = bok[c] ? -(double)ho[u][c] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) win[c][j] = fma(h, vo[j], win[c][j]);
+      }
+    }
+    if (more) {
+      put();
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          hi[u][c] = ni[u][c];
+          ho[u][c] = no[u][c];
+        }
     }
   }
 }
@@ -453,10 +609,10 @@ SepGeom sep_geom(int32_t H, int32_t W, int32_t B, int32_t w, int32_t h, int32_t 
   g.Wv = W - w + 1;
   g.Hv = H - h + 1;
   g.nT = nT;
-  // segment lengths at least the window, so that a segment's start-up sum
-  // costs no more than its walk
-  g.SX = 64 * (1 > (w + 62) / 64 ? 1 : (w + 62) / 64);
-  g.SY = 32 * (2 > (h + 30) / 32 ? 2 : (h + 30) / 32);
+  // segment lengths: multiples of 32, at least the window less one, so a
+  // segment's start-up walk costs no more than its output walk
+  g.SX = 32 * (1 > (w + 30) / 32 ? 1 : (w + 30) / 32);
+  g.SY = 32 * (1 > (h + 30) / 32 ? 1 : (h + 30) / 32);
   return g;
 }
 
