@@ -49,6 +49,9 @@ def parse():
                     help="serve workload: request rates (req/s) to sweep")
     ap.add_argument("--seconds", type=float, default=1.0,
                     help="serve workload: arrival span per rate")
+    ap.add_argument("--gaussian", choices=("2d", "separable"), default="2d",
+                    help="batch / serve workloads: the Gaussian as 2-D planes (81 weight terms) "
+                         "or in separable form")
     ap.add_argument("--budget-gb", type=float, default=64.0,
                     help="batch workload: workspace budget of one Gaussian sub-batch")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -137,7 +140,8 @@ def bench_batch(args):
     out = {}
     total_windows = 0
     total_ms = {"per_frame": 0.0, "batched": 0.0, "graph": 0.0}
-    for name in ("manhattan", "gaussian"):
+    gname = "gaussian_sep" if args.gaussian == "separable" else "gaussian"
+    for name in ("manhattan", gname):
         cfg = swih.Config(16, name, [(15, 15)])
         units = WL.tracking_units(cfg, frames)
         budget = int(args.budget_gb * 2**30)
@@ -190,7 +194,8 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
         "data": "synthetic",
         "config": {"workload": "batch: 64 uneven frames 256..1920 x 256..1080, 1-8 targets side "
-                               "16..128 x 3 scales, search 3s x 3s, 16 bins, Manhattan + Gaussian K=4",
+                               "16..128 x 3 scales, search 3s x 3s, 16 bins, Manhattan + Gaussian K=4 "
+                               "(%s)" % ("separable" if args.gaussian == "separable" else "2-D planes"),
                    "global_batch": 64, "seq_len": None, "parallelism": "none"},
         "per_frame_windows_per_s": total_windows / (total_ms["per_frame"] / 1e3),
         "speedup_vs_per_frame": total_ms["per_frame"] / best,
@@ -208,7 +213,7 @@ def bench_serve(args):
     import paper_1705_03524_amd as swih
     from paper_1705_03524_amd import serving, synth
 
-    cfg = swih.Config(16, "gaussian", [(15, 15)])
+    cfg = swih.Config(16, "gaussian_sep" if args.gaussian == "separable" else "gaussian", [(15, 15)])
     pool = serving.FramePool(synth.FRAME_SIZES, lambda H, W: synth.smooth_noise(H * 7 + W, H, W))
     cont = serving.ContinuousServer(cfg, pool, budget=24 << 30, max_inflight=3)
     ser = serving.SerialServer(cfg, pool, budget=8 << 30)
@@ -236,7 +241,8 @@ def bench_serve(args):
         "steps": len(sweep), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve: Poisson tracking requests, 16 streams, frames 640x480..4096x2160, "
-                               "target 24..96, 3 scales, search 2-4x, 16 bins, Gaussian K=4",
+                               "target 24..96, 3 scales, search 2-4x, 16 bins, Gaussian K=4 (%s)"
+                               % ("separable" if args.gaussian == "separable" else "2-D planes"),
                    "global_batch": None, "seq_len": None, "parallelism": "none"},
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "rate": sweep[-1]["rate"],
         "sweep": sweep,
@@ -356,6 +362,38 @@ def main():
     for k in KERNELS:
         per["build_" + k] = per["carries_" + k] + per["planes_" + k]
 
+    # The same Gaussian in separable form (row pass, then a column walk over
+    # the row results): reported beside the step, not part of it.
+    sp = Plan(swih.Config(NBINS, "gaussian_sep", [(WIN, WIN)]), H, W)
+    smap = torch.empty_like(maps["gaussian"])
+    stm = torch.empty(NBINS, dtype=torch.float32, device="cuda")
+
+    def sep_phase(name):
+        if name in ("carries", "planes"):
+            swih.build_phase(sp.cfg, d_img, sp.ws, name, 0)
+        elif name == "query":
+            swih.query(sp.cfg, sp.ws, H, W, 0, d_tc, stm.view(1, NBINS), None)
+        else:
+            swih.match(sp.cfg, sp.ws, H, W, 0, sp.valid_rect(0), smap, template=stm)
+
+    sep_ms = {}
+    for ph in PHASES:
+        sep_phase(ph)
+    torch.cuda.synchronize()
+    for ph in ("planes", "query", "match"):
+        g = capture(lambda: [sep_phase(ph) for _ in range(REP)])
+        g.replay()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        sep_ms[ph] = a.elapsed_time(b) / (3 * REP)
+        del g
+    sep_total = sum(sep_ms.values())
+    sep_diff = float((smap - maps["gaussian"]).abs().max())
+
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)
     # Algorithmic bytes of the two Gaussian kernels (81 weight terms x 16 bins):
@@ -401,6 +439,11 @@ def main():
         # IH build (carries + planes) in algorithmic GB/s: image read + planes written
         "ih_build_gbs": {k: (H * W + 4 * plans[k].nplanes * NBINS * (H + 1) * (W + 1)) /
                             (per["build_" + k] / 1e3) / 1e9 for k in KERNELS},
+        "gaussian_separable": {
+            "ms": sep_ms, "ms_total": sep_total, "windows_per_s": nwin / (sep_total / 1e3),
+            "speedup_vs_2d_gaussian": (per["build_gaussian"] + per["query_gaussian"] +
+                                       per["match_gaussian"]) / sep_total,
+            "max_abs_map_diff_vs_2d": sep_diff},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img, tc, args.cpu_seconds)

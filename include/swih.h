@@ -133,8 +133,8 @@ int swih_build(const swih_config* cfg, const uint8_t* d_img, int32_t height, int
  *                       carries: exactly one kernel launch.
  *   set     0 for integer kernels; the scale index for the Gaussian, whose
  *           planes are per scale.
- * For SWIH_GAUSSIAN_SEP the first phase writes the scale's term and
- * coefficient tables and the second the row results (one launch each).
+ * For SWIH_GAUSSIAN_SEP the first phase has nothing to do (it enqueues
+ * nothing) and the second writes the row results in one launch.
  * Each set keeps its own carries, so a set's planes need only follow its own
  * carries on the stream.  Errors as swih_build, plus SWIH_ERR_INVALID for a
  * bad set.

@@ -55,7 +55,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   g.B = c->nbins;
   if (c->kernel == SWIH_GAUSSIAN_SEP) {  // row results + tables per scale (swih_sep.hip)
     g.nI = g.nJ = 2 * gauss_K(c) + 1;
-    L.set_bytes = sep_layout(H, W, g.B, g.nI).set_bytes;
+    L.set_bytes = sep_layout(H, W, g.B).set_bytes;
     L.nsets = c->nscales;
     L.total = L.set_bytes * L.nsets;
     return SWIH_OK;
@@ -179,15 +179,14 @@ int build_phases(const swih_config* cfg, const uint8_t* d_img, int32_t height, i
   const int first = set < 0 ? 0 : set, last = set < 0 ? L.nsets - 1 : set;
   if (first >= L.nsets || last >= L.nsets) return SWIH_ERR_INVALID;
   if (cfg->kernel == SWIH_GAUSSIAN_SEP) {
-    const SepLayout SL = sep_layout(height, width, cfg->nbins, L.g.nI);
+    const SepLayout SL = sep_layout(height, width, cfg->nbins);
     for (int k = first; k <= last; ++k) {
       ScaleParams sp;
       scale_params(cfg, k, sp);
-      const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, L.g.nI);
+      const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, gauss_K(cfg));
       SepBuildArgs a;
       int32_t nb[2];
-      sep_build_args(sg, SL, sp.ax, sp.ay, d_img, pitch, (char*)d_ws + (size_t)k * L.set_bytes, a,
-                     nb);
+      sep_build_args(sg, SL, sp.ax, d_img, pitch, (char*)d_ws + (size_t)k * L.set_bytes, a, nb);
       if (sep_launch_build(a, nb, phases, s) != hipSuccess) return SWIH_ERR_HIP;
     }
     return SWIH_OK;
@@ -241,10 +240,10 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   st = scale_params(cfg, scale_idx, sp);
   if (st != SWIH_OK) return st;
   if (cfg->kernel == SWIH_GAUSSIAN_SEP) {
-    const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, L.g.nI);
+    const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, gauss_K(cfg));
     SepQueryArgs a;
     int32_t nb;
-    sep_query_args(sg, sep_layout(height, width, cfg->nbins, L.g.nI), sp.mass,
+    sep_query_args(sg, sep_layout(height, width, cfg->nbins), sp.ay, sp.mass,
                    (const char*)d_ws + (size_t)scale_idx * L.set_bytes, d_centres, n, d_hist, a, nb);
     return sep_launch_query(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
   }
@@ -276,10 +275,10 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   st = scale_params(cfg, scale_idx, sp);
   if (st != SWIH_OK) return st;
   if (cfg->kernel == SWIH_GAUSSIAN_SEP) {
-    const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, L.g.nI);
+    const SepGeom sg = sep_geom(height, width, cfg->nbins, sp.w, sp.h, gauss_K(cfg));
     SepMatchArgs a;
     int32_t nb;
-    sep_match_args(sg, sep_layout(height, width, cfg->nbins, L.g.nI), sp.mass,
+    sep_match_args(sg, sep_layout(height, width, cfg->nbins), sp.ay, sp.mass,
                    (const char*)d_ws + (size_t)scale_idx * L.set_bytes, d_template, r.x0, r.y0,
                    r.x1, r.y1, d_map, a, nb);
     return sep_launch_match(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
@@ -414,14 +413,14 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     if (sep) {
       const swih_frame_desc& fd = frames[f];
       const swih_config fc = frame_config(cfg, fd);
-      const SepLayout SL = sep_layout(fd.height, fd.width, cfg->nbins, h.nt);
+      const SepLayout SL = sep_layout(fd.height, fd.width, cfg->nbins);
       for (int k = 0; k < ubase[f + 1] - ubase[f]; ++k) {
         const int u = ubase[f] + k;
         ScaleParams sp;
         scale_params(&fc, k, sp);
-        const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, h.nt);
+        const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, (h.nt - 1) / 2);
         int32_t nb[2];
-        sep_build_args(sg, SL, sp.ax, sp.ay, fd.d_img, fd.pitch,
+        sep_build_args(sg, SL, sp.ax, fd.d_img, fd.pitch,
                        (char*)fd.d_ws + (size_t)k * layouts[f].set_bytes, sunits[u], nb);
         for (int s = 0; s < 4; ++s)
           upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + (s < 2 ? nb[s] : 0);
@@ -456,9 +455,9 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     scale_params(&fc, qd.scale_idx, sp);
     if (sep) {
       const swih_frame_desc& fd = frames[qd.frame];
-      const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, h.nt);
+      const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, (h.nt - 1) / 2);
       int32_t nb = 0;
-      sep_query_args(sg, sep_layout(fd.height, fd.width, cfg->nbins, h.nt), sp.mass,
+      sep_query_args(sg, sep_layout(fd.height, fd.width, cfg->nbins), sp.ay, sp.mass,
                      (const char*)fd.d_ws + (size_t)qd.scale_idx * layouts[qd.frame].set_bytes,
                      qd.d_centres, qd.n, qd.d_hist, ((SepQueryArgs*)(tb + h.off_q))[q], nb);
       qpre[q + 1] = qpre[q] + (qd.n > 0 ? nb : 0);
@@ -495,8 +494,8 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     if (sep) {
       int32_t nb = 0;
       if (!empty) {
-        const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, h.nt);
-        sep_match_args(sg, sep_layout(fd.height, fd.width, cfg->nbins, h.nt), sp.mass,
+        const SepGeom sg = sep_geom(fd.height, fd.width, cfg->nbins, sp.w, sp.h, (h.nt - 1) / 2);
+        sep_match_args(sg, sep_layout(fd.height, fd.width, cfg->nbins), sp.ay, sp.mass,
                        (const char*)fd.d_ws + (size_t)md.scale_idx * layouts[md.frame].set_bytes,
                        md.d_template, r.x0, r.y0, r.x1, r.y1, md.d_map,
                        ((SepMatchArgs*)(tb + h.off_m))[m], nb);

@@ -127,50 +127,56 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
 // The 2-D weight terms u_i(x) v_j(y) of the Gaussian are products of two 1-D
 // families, so the window histogram factors into two 1-D weighted integral
 // histograms with translation (Sec. 2.1, Eq. 2, applied per axis):
-//   row pass:    h_b(xc; y) = sum_i alpha_i(xc) sum_{|x - xc| <= rx} [Q(x, y) = b] u_i(x)
-//   column pass: H_b(xc, yc) = sum_j beta_j(yc) sum_{|y - yc| <= ry} h_b(xc; y) v_j(y)
-// The row results h (one float per row, valid centre column and bin) are the
-// only large buffer; nothing of size terms x bins x pixels is ever stored.
+//   row pass:    h_b(xc; y) = sum_{|x - xc| <= rx} [Q(x, y) = b] g_x(x - xc)
+//   column pass: H_b(xc, yc) = sum_{|y - yc| <= ry} h_b(xc; y) g_y(y - yc)
+// with g the cosine series of the axis.  The row results h (one float per
+// row, valid centre column and bin) are the only buffer; nothing of size
+// terms x bins x pixels is ever stored.
 
 struct SepGeom {
   int32_t H, W, B;      // image size, bins
   int32_t w, h, rx, ry; // window
   int32_t Wv, Hv;       // valid centre columns / rows: W - w + 1, H - h + 1
-  int32_t nT;           // terms per axis, 2K + 1
+  int32_t K;            // series terms per axis beyond the constant
   int32_t SX;           // row pass: centre columns per wave
   int32_t SY;           // column pass: centre rows per segment (segments start at multiples of SY)
 };
 
+// One axis of the series g(t) = sum_k a_k cos(w k t), w = 2 pi / P, for walks
+// along it: the window sum of term k translated to the current centre is the
+// complex number Z_k = sum_t e(t) exp(i w k t) over the window's offsets t.
+struct SepAxis {
+  double a[SWIH_MAX_K + 1];   // a_0 .. a_K
+  double ec[SWIH_MAX_K + 1];  // cos(w k r), r the half width: the entering offset +r
+  double es[SWIH_MAX_K + 1];  // sin(w k r)  (the leaving offset -r is the conjugate)
+  double rc[SWIH_MAX_K + 1];  // cos(w k), sin(w k): moving the centre one step on
+  double rs[SWIH_MAX_K + 1];  //   multiplies Z_k by (rc - i rs)
+  double g_in;                // g(r) = a_0 + sum_k a_k ec_k
+};
+
+void sep_axis(const GaussAxis& ax, int32_t r, SepAxis& s);
+
 // Workspace of one scale (set-relative byte offsets, 256-byte aligned).
 struct SepLayout {
-  int64_t off_hr;   // float  [H][W - w + 1][B]   row results (sized for W)
-  int64_t off_ux;   // double [W][nT]  x terms, fixed point round(u * 2^24) (integer valued)
-  int64_t off_al;   // double [W][nT]  alpha_i at centre column rx + v, times 2^-24
-  int64_t off_vy;   // double [H][nT]  y terms, round(v * 2^24) * 2^-24
-  int64_t off_be;   // double [H][nT]  beta_j at centre row ry + u
+  int64_t off_hr;   // float [H][W - w + 1][B] row results (sized for W)
   int64_t set_bytes;
 };
 
-SepLayout sep_layout(int32_t H, int32_t W, int32_t B, int32_t nT);
-SepGeom sep_geom(int32_t H, int32_t W, int32_t B, int32_t w, int32_t h, int32_t nT);
+SepLayout sep_layout(int32_t H, int32_t W, int32_t B);
+SepGeom sep_geom(int32_t H, int32_t W, int32_t B, int32_t w, int32_t h, int32_t K);
 
 struct SepBuildArgs {
   SepGeom g;
   const uint8_t* img;
   int32_t ipitch;
   float* hr;
-  double* ux;
-  double* al;
-  double* vy;
-  double* be;
-  GaussAxis ax, ay;
+  SepAxis ax;
 };
 
 struct SepQueryArgs {
   SepGeom g;
   const float* hr;
-  const double* vy;
-  const double* be;
+  SepAxis ay;
   double inv_mass;
   const int32_t* centres;  // [n][2]
   int32_t n;
@@ -180,8 +186,7 @@ struct SepQueryArgs {
 struct SepMatchArgs {
   SepGeom g;
   const float* hr;
-  const double* vy;
-  const double* be;
+  SepAxis ay;
   double inv_mass;
   const float* tmpl;       // [B] normalised template
   float* map;
@@ -190,17 +195,18 @@ struct SepMatchArgs {
   int32_t seg0, nseg;      // first segment (absolute) and segment count
 };
 
-// Blocks (of 256 threads) of the two build stages: tables, row pass.
-void sep_build_args(const SepGeom& g, const SepLayout& L, const GaussAxis& ax,
-                    const GaussAxis& ay, const uint8_t* img, int32_t img_pitch, char* set_base,
-                    SepBuildArgs& a, int32_t (&nb)[2]);
-void sep_query_args(const SepGeom& g, const SepLayout& L, double mass, const char* set_base,
-                    const int32_t* centres, int32_t n, float* hist, SepQueryArgs& a, int32_t& nb);
-void sep_match_args(const SepGeom& g, const SepLayout& L, double mass, const char* set_base,
-                    const float* tmpl, int32_t x0, int32_t y0, int32_t x1, int32_t y1, float* map,
-                    SepMatchArgs& a, int32_t& nb);
+// Blocks (of 256 threads) of the build stages: nb[0] = 0 (the separable form
+// needs no carries), nb[1] = the row pass.
+void sep_build_args(const SepGeom& g, const SepLayout& L, const GaussAxis& ax, const uint8_t* img,
+                    int32_t img_pitch, char* set_base, SepBuildArgs& a, int32_t (&nb)[2]);
+void sep_query_args(const SepGeom& g, const SepLayout& L, const GaussAxis& ay, double mass,
+                    const char* set_base, const int32_t* centres, int32_t n, float* hist,
+                    SepQueryArgs& a, int32_t& nb);
+void sep_match_args(const SepGeom& g, const SepLayout& L, const GaussAxis& ay, double mass,
+                    const char* set_base, const float* tmpl, int32_t x0, int32_t y0, int32_t x1,
+                    int32_t y1, float* map, SepMatchArgs& a, int32_t& nb);
 
-// phases: bit 1 = tables, bit 2 = row pass.
+// phases: bit 2 = row pass (bit 1, the carries, launches nothing).
 hipError_t sep_launch_build(const SepBuildArgs& a, const int32_t (&nb)[2], int phases,
                             hipStream_t s);
 hipError_t sep_launch_query(const SepQueryArgs& a, int32_t nb, hipStream_t s);

@@ -205,12 +205,16 @@ def total_windows(units) -> int:
 
 
 def plane_bytes(cfg: S.Config, units) -> int:
-    """Algorithmic plane bytes written by all builds: 4 T B (H+1)(W+1) per plane set."""
+    """Algorithmic bytes the builds write: 4 T B (H+1)(W+1) per plane set, or for
+    the separable Gaussian 4 B H (W - w + 1) of row results per scale."""
     K = cfg.gauss_terms or 4
-    T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5}.get(cfg.kernel, (2 * K + 1) ** 2)
     tot = 0
     for u in units:
         H, W = u.img.shape
+        if cfg.kernel == S.GAUSSIAN_SEP:
+            tot += sum(4 * cfg.nbins * H * (W - w + 1) for w, _ in u.scales)
+            continue
+        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5}.get(cfg.kernel, (2 * K + 1) ** 2)
         nsets = len(u.scales) if cfg.kernel == S.GAUSSIAN else 1
         tot += nsets * 4 * T * cfg.nbins * (H + 1) * (W + 1)
     return tot

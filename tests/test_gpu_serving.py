@@ -13,9 +13,10 @@ import paper_1705_03524_amd as swih  # noqa: E402
 from paper_1705_03524_amd import serving  # noqa: E402
 
 
-def test_served_maps_equal_serial():
+@pytest.mark.parametrize("kind", ["gaussian", "gaussian_sep"])
+def test_served_maps_equal_serial(kind):
     print("case: serving 48 requests at 400 req/s vs serial", flush=True)
-    cfg = swih.Config(16, "gaussian", [(15, 15)])
+    cfg = swih.Config(16, kind, [(15, 15)])
     sizes = ((640, 480), (1280, 720))
     pool = serving.FramePool(sizes, lambda H, W: synth.smooth_noise(H + W, H, W))
     reqs = synth.serving_requests(3, 400.0, 48, nstreams=5, sizes=sizes)
