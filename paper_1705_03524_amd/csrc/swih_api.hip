@@ -63,8 +63,6 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   g.TY = kDefaultTY;
   g.NTX = (W + SWIH_TX - 1) / SWIH_TX;
   g.NTY = (H + g.TY - 1) / g.TY;
-  g.pitch = SWIH_TX * (g.NTX + 1);
-  g.plane_elems = (int64_t)(H + 1) * g.pitch;
   const bool gauss = c->kernel == SWIH_GAUSSIAN;
   g.gauss = gauss ? 1 : 0;
   if (gauss) {
@@ -77,12 +75,13 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     g.nP = nP[c->kernel];
     g.ppg = g.nP;
   }
-  g.row_stride = (int64_t)g.ppg * g.pitch;
+  g.row_stride = (int64_t)g.ppg * SWIH_TX;
+  g.tile_stride = (int64_t)(H + 1) * g.row_stride;
   const int64_t PB = (int64_t)g.nP * g.B;
   const int64_t NXP = (int64_t)g.NTX * SWIH_TX;
   int64_t off = 0;
   L.off_planes = off;
-  off += swih_align256(PB * g.plane_elems * 4);
+  off += swih_align256(PB * g.NTX * (int64_t)(H + 1) * SWIH_TX * 4);
   if (gauss) {
     L.off_RC = off;
     off += swih_align256(PB * g.NTX * (int64_t)(H + 1) * 8);

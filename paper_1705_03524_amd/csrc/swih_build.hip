@@ -256,14 +256,13 @@ __device__ __forceinline__ void emit_int(const BuildArgs& a, int vb) {
     const uint32_t zv = zc[((size_t)(plane_j(p) * g.B + t.b) * g.NTY + t.ty) * NXP + t.x];
     acc[p] = CTc[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] +
              wave_incl_scan(u[plane_i(p)] * zv);
-    pbase[p] = (size_t)swih_elem(g, p, t.b, 0, t.x + 1);
+    // lanes past the image's last column write too (their values are never
+    // read), so every store is a whole 256-byte run
+    pbase[p] = (size_t)(swih_base(g, p, t.b) + t.tx * g.tile_stride + lane);
   }
   if (t.ty == 0) {
 #pragma unroll
-    for (int p = 0; p < TT::nP; ++p) {
-      if (t.valid) planes[pbase[p]] = 0u;
-      if (t.tx == 0 && lane == 0) planes[pbase[p] - 1] = 0u;
-    }
+    for (int p = 0; p < TT::nP; ++p) planes[pbase[p]] = 0u;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
@@ -274,16 +273,9 @@ __device__ __forceinline__ void emit_int(const BuildArgs& a, int vb) {
     for (int i = 0; i < TT::nI; ++i) s[i] = wave_incl_scan(m * u[i]) + readlane(ereg[i], k);
 #pragma unroll
     for (int p = 0; p < TT::nP; ++p) acc[p] += poly_term(plane_j(p), y) * s[plane_i(p)];
-    if (t.valid) {
-      const size_t row = (size_t)(y + 1) * g.row_stride;
+    const size_t row = (size_t)(y + 1) * g.row_stride;
 #pragma unroll
-      for (int p = 0; p < TT::nP; ++p) planes[pbase[p] + row] = acc[p];
-    }
-  }
-  if (t.tx == 0 && lane < t.nrows) {
-#pragma unroll
-    for (int p = 0; p < TT::nP; ++p)
-      planes[swih_elem(g, p, t.b, t.y0 + 1 + lane, 0)] = 0u;
+    for (int p = 0; p < TT::nP; ++p) planes[pbase[p] + row] = acc[p];
   }
 }
 
@@ -404,11 +396,10 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   for (int j = 0; j < NT; ++j) {
     const int p = i * NT + j;
     const size_t pb = (size_t)(p * g.B + t.b);
-    lbase[j] = (size_t)swih_elem(g, p, t.b, 0, t.x + 1);
+    lbase[j] = (size_t)(swih_base(g, p, t.b) + t.tx * g.tile_stride + lane);
     L[j] = 0.0;
     if (t.ty == 0) {
-      if (t.valid) Lp[lbase[j]] = 0.0f;
-      if (t.tx == 0 && lane == 0) Lp[lbase[j] - 1] = 0.0f;
+      Lp[lbase[j]] = 0.0f;
       if (lane == 0) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1)] = 0.0;
     }
   }
@@ -427,11 +418,10 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
       L[j] = fma(vr[j], R, L[j]);
       out[j] = (float)L[j];
     }
-    if (t.valid) {
-      const size_t row = (size_t)(y + 1) * g.row_stride;
+    // whole 256-byte runs: lanes past the last column write values never read
+    const size_t row = (size_t)(y + 1) * g.row_stride;
 #pragma unroll
-      for (int j = 0; j < NT; ++j) Lp[lbase[j] + row] = out[j];
-    }
+    for (int j = 0; j < NT; ++j) Lp[lbase[j] + row] = out[j];
   }
   // row carries at the tile origin column: RC[tx][y + 1] = P[y + 1][Xo], one lane per row
   const int yl = t.y0 + (lane < t.nrows ? lane : 0);
@@ -443,8 +433,6 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     const double rc =
         (CTc[(pb * g.NTY + t.ty) * g.NTX + t.tx] + wave_incl_scan(term)) * sc48;
     if (lane < t.nrows) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1) + t.y0 + 1 + lane] = rc;
-    if (t.tx == 0 && lane < t.nrows)
-      Lp[swih_elem(g, p, t.b, t.y0 + 1 + lane, 0)] = 0.0f;
   }
 }
 

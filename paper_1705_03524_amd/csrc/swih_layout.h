@@ -9,12 +9,16 @@
 // and band ty owns rows Y in [TY ty + 1, TY ty + TY].
 //
 // Planes come in groups of ppg: the y terms of one x term for the Gaussian,
-// all terms for the integer kernels.  The rows of a group's planes (for one
-// bin) are interleaved: row Y of plane p sits at
-//   ((((p / ppg) * B + b) * (H + 1) + Y) * ppg + p % ppg) * pitch
-// so a window corner's values of all terms of a group lie within ppg * pitch
-// elements.  Element X of a row sits at 63 + X, pitch a multiple of 64
-// elements, so every tile's 64 columns start on a 256-byte boundary.
+// all terms for the integer kernels.  Storage is tile-major: for one (group,
+// bin) the tile columns follow one another, each holding rows Y = 0..H, and a
+// row holds the group's ppg planes as consecutive runs of 64 elements:
+//   elem(p, b, Y, X) = ((grp B + b) NTX + tx) tile_stride + Y row_stride
+//                      + (p % ppg) 64 + lane,   grp = p / ppg,
+// with tx = (X - 1) / 64, lane = (X - 1) % 64 (the column of pixel x = X - 1),
+// row_stride = 64 ppg and tile_stride = (H + 1) row_stride.  The wave that
+// builds a tile of a band writes one contiguous run of memory; a window
+// corner's values of all terms of a group lie in 64 ppg elements.  Column
+// X = 0 is zero by definition and is not stored: readers use 0 for it.
 //
 // Weight terms (u_i(x) v_j(y)):
 //   uniform    {1}
@@ -48,18 +52,27 @@ struct SwihGeom {
   int32_t H, W, B;       // image size, bins
   int32_t TY;            // band height (<= 64)
   int32_t NTX, NTY;      // tiles across, bands down
-  int32_t pitch;         // plane row pitch in elements (multiple of 64)
   int32_t nP, nI, nJ;    // planes, x terms, y terms
   int32_t gauss;         // 1 for the split Gaussian storage
   int32_t ppg;           // planes per interleaved group
-  int64_t plane_elems;   // (H + 1) * pitch
-  int64_t row_stride;    // ppg * pitch: from row Y to row Y + 1 of one plane
+  int64_t row_stride;    // 64 ppg: from row Y to row Y + 1 of one plane
+  int64_t tile_stride;   // (H + 1) row_stride: from tile column tx to tx + 1
 };
 
-// Element offset of P[Y][X] of plane p, bin b.
-__host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, int Y, int X) {
+// Offset of plane p, bin b at row 0 of tile 0, lane 0.
+__host__ __device__ inline int64_t swih_base(const SwihGeom& g, int p, int b) {
   const int grp = p / g.ppg, pj = p - grp * g.ppg;
-  return (((int64_t)(grp * g.B + b) * (g.H + 1) + Y) * g.ppg + pj) * g.pitch + 63 + X;
+  return (int64_t)(grp * g.B + b) * g.NTX * g.tile_stride + pj * 64;
+}
+
+// Column part of the offset of X >= 1.
+__host__ __device__ inline int64_t swih_xoff(const SwihGeom& g, int X) {
+  return (int64_t)((X - 1) >> 6) * g.tile_stride + ((X - 1) & 63);
+}
+
+// Element offset of P[Y][X] of plane p, bin b, for X >= 1.
+__host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, int Y, int X) {
+  return swih_base(g, p, b) + (int64_t)Y * g.row_stride + swih_xoff(g, X);
 }
 
 // Byte offsets inside one workspace.  All regions are 256-byte aligned.
@@ -68,7 +81,7 @@ struct SwihLayout {
   int32_t nsets;         // plane sets: 1, or nscales for the Gaussian
   int64_t set_bytes;     // bytes of one plane set (planes [+ RC + tables])
   // inside a set
-  int64_t off_planes;    // uint32 or float [nP][B][H+1][pitch]
+  int64_t off_planes;    // uint32 or float planes, tile-major (above)
   int64_t off_RC;        // double [nP][B][NTX][H+1]              (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)

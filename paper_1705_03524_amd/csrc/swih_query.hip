@@ -26,35 +26,58 @@
 namespace swih {
 namespace {
 
-// pl points at row 0, column 0 of a plane; rs is the plane's row stride.
-__device__ __forceinline__ uint32_t at_u(const uint32_t* __restrict__ pl, int64_t rs, int Y, int X) {
-  return pl[(size_t)Y * rs + X];
+// Offsets of a window's corner lookups, the same for every plane and bin:
+// rows {ya, ym, yb} x columns {xa, xm, xb}, ym = yc + 1, xm = xc + 1 (the
+// Manhattan quadrant split; the other kernels use the outer four).  Column
+// X = 0 is not stored and reads as 0: its offset points at column 1 and the
+// value is dropped.
+struct IntCorners {
+  int64_t o[3][3];
+  bool xa0;
+};
+
+__device__ __forceinline__ IntCorners int_corners(const SwihGeom& g, int xc, int yc,
+                                                  const ScaleParams& sp) {
+  IntCorners k;
+  const int xa = xc - sp.rx;
+  const int Ys[3] = {yc - sp.ry, yc + 1, yc + sp.ry + 1};
+  const int64_t Xo[3] = {swih_xoff(g, xa > 0 ? xa : 1), swih_xoff(g, xc + 1),
+                         swih_xoff(g, xc + sp.rx + 1)};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k.o[r][c] = (int64_t)Ys[r] * g.row_stride + Xo[c];
+  k.xa0 = xa == 0;
+  return k;
 }
 
-// Exact H_b of an integer kernel at (xc, yc) (uint32 arithmetic modulo 2^32).
+// P at corner (r, c) of the plane whose base (swih_base) is pl.
+__device__ __forceinline__ uint32_t at_u(const uint32_t* __restrict__ pl, const IntCorners& k,
+                                         int r, int c) {
+  const uint32_t v = pl[k.o[r][c]];
+  return c == 0 && k.xa0 ? 0u : v;
+}
+
+// Exact H_b of an integer kernel at the window of k (uint32 arithmetic modulo 2^32).
 template <int KIND>
 __device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes,
                                              const SwihGeom& g, int b, int xc, int yc,
-                                             const ScaleParams& sp) {
-  const uint32_t* p0 = planes + swih_elem(g, 0, b, 0, 0);
-  const int xa = xc - sp.rx, xb = xc + sp.rx + 1, ya = yc - sp.ry, yb = yc + sp.ry + 1;
+                                             const ScaleParams& sp, const IntCorners& k) {
+  const uint32_t* p0 = planes + swih_base(g, 0, b);
   if (KIND == 0) {
-    return at_u(p0, g.row_stride, yb, xb) - at_u(p0, g.row_stride, ya, xb) - at_u(p0, g.row_stride, yb, xa) +
-           at_u(p0, g.row_stride, ya, xa);
+    return at_u(p0, k, 2, 2) - at_u(p0, k, 0, 2) - at_u(p0, k, 2, 0) + at_u(p0, k, 0, 0);
   } else if (KIND == 1) {
-    const int xm = xc + 1, ym = yc + 1;
-    const uint32_t* px = planes + swih_elem(g, 1, b, 0, 0);
-    const uint32_t* py = planes + swih_elem(g, 2, b, 0, 0);
+    const uint32_t* px = planes + swih_base(g, 1, b);
+    const uint32_t* py = planes + swih_base(g, 2, b);
     // 3 x 3 corner grid per plane
     uint32_t c1[3][3], cx[3][3], cy[3][3];
-    const int Ys[3] = {ya, ym, yb}, Xs[3] = {xa, xm, xb};
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        c1[r][c] = at_u(p0, g.row_stride, Ys[r], Xs[c]);
-        cx[r][c] = at_u(px, g.row_stride, Ys[r], Xs[c]);
-        cy[r][c] = at_u(py, g.row_stride, Ys[r], Xs[c]);
+        c1[r][c] = at_u(p0, k, r, c);
+        cx[r][c] = at_u(px, k, r, c);
+        cy[r][c] = at_u(py, k, r, c);
       }
     auto box = [](const uint32_t (&a)[3][3], int r, int c) {
       return a[r + 1][c + 1] - a[r][c + 1] - a[r + 1][c] + a[r][c];
@@ -69,9 +92,8 @@ __device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes
     uint32_t bx[5];
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
-      const uint32_t* pl = planes + swih_elem(g, p, b, 0, 0);
-      bx[p] = at_u(pl, g.row_stride, yb, xb) - at_u(pl, g.row_stride, ya, xb) - at_u(pl, g.row_stride, yb, xa) +
-              at_u(pl, g.row_stride, ya, xa);
+      const uint32_t* pl = planes + swih_base(g, p, b);
+      bx[p] = at_u(pl, k, 2, 2) - at_u(pl, k, 0, 2) - at_u(pl, k, 2, 0) + at_u(pl, k, 0, 0);
     }
     const uint32_t X = (uint32_t)xc, Y = (uint32_t)yc;
     return (sp.c_int - X * X - Y * Y) * bx[0] + 2u * X * bx[1] + 2u * Y * bx[2] - bx[3] - bx[4];
@@ -91,7 +113,7 @@ __device__ __forceinline__ void query_int(const QueryArgs& a, int vb) {
   const int k = (int)(t / g.B), b = (int)(t % g.B);
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
-  const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp);
+  const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp, int_corners(g, xc, yc, sp));
   if (a.hist_raw) a.hist_raw[t] = h;
   if (a.hist) a.hist[t] = (float)((double)h / sp.mass);
 }
@@ -108,9 +130,10 @@ __device__ __forceinline__ void match_int(const MatchArgs& a, int vb) {
   const int xc = x0 + bx * 64 + (int)(threadIdx.x & 63);
   const int yc = y0 + by * 4 + (int)(threadIdx.x >> 6);
   if (xc > x1 || yc > y1) return;
+  const IntCorners k = int_corners(g, xc, yc, sp);
   double acc = 0.0;
   for (int b = 0; b < g.B; ++b) {
-    const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp);
+    const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp, k);
     if (tmpl_raw) {
       acc += sqrt((double)h * (double)tmpl_raw[b]);
     } else {
@@ -169,18 +192,21 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const int xa = xc - sp.rx, xb = xc + sp.rx + 1, ya = yc - sp.ry, yb = yc + sp.ry + 1;
   const int64_t rs = g.row_stride;
   const int txa = tile_of(xa), txb = tile_of(xb);
+  // column X = 0 is not stored (it is zero): its loads go to column 1 and are dropped
+  const bool xa0 = xa == 0;
+  const int64_t oa = swih_xoff(g, xa0 ? 1 : xa), ob = swih_xoff(g, xb);
   for (int it = threadIdx.x; it < g.B * NT; it += blockDim.x) {
     const int b = it / NT, i = it - (it / NT) * NT;
-    // the NT y-term planes of x term i are row-interleaved: plane j at + j * pitch
-    const float* lp = gp.L + swih_elem(g, i * NT, b, 0, 0);
+    // the NT y-term planes of x term i sit 64 elements apart within a row
+    const float* lp = gp.L + swih_base(g, i * NT, b);
     float aA[NT], bA[NT], aB[NT], bB[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const float* q = lp + (size_t)j * g.pitch;
-      aA[j] = q[(size_t)ya * rs + xa];
-      bA[j] = q[(size_t)yb * rs + xa];
-      aB[j] = q[(size_t)ya * rs + xb];
-      bB[j] = q[(size_t)yb * rs + xb];
+      const float* q = lp + (size_t)j * 64;
+      aA[j] = xa0 ? 0.0f : q[(size_t)ya * rs + oa];
+      bA[j] = xa0 ? 0.0f : q[(size_t)yb * rs + oa];
+      aB[j] = q[(size_t)ya * rs + ob];
+      bB[j] = q[(size_t)yb * rs + ob];
     }
     double d[NT];
 #pragma unroll
@@ -189,8 +215,8 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
     for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) {
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        const float* q = lp + (size_t)j * g.pitch + (size_t)c * rs;
-        d[j] += (double)q[xb] - (double)q[xa];
+        const float* q = lp + (size_t)j * 64 + (size_t)c * rs;
+        d[j] += (double)q[ob] - (xa0 ? 0.0 : (double)q[oa]);
       }
     }
     double hi = 0.0;
@@ -303,7 +329,10 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
     am[ii] = i < NT ? series_coeff(sp.ax, X + rx, i) : 0.0;
   }
   const int64_t rs = g.row_stride;
-  const size_t offA = (size_t)Ya * rs + X, offB = (size_t)Yb * rs + X, offC = (size_t)c0 * rs + X;
+  // column X = 0 is not stored (it is zero): its thread loads column 1 and drops it
+  const bool x0col = X == 0;
+  const int64_t xo = swih_xoff(g, x0col ? 1 : X);
+  const size_t offA = (size_t)Ya * rs + xo, offB = (size_t)Yb * rs + xo, offC = (size_t)c0 * rs + xo;
   const bool win = tid < cwc;
   const int xc = xa + tid;
   const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
@@ -318,23 +347,24 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
       for (int ii = 0; ii < NI; ++ii) {
         const int i = grp + ii * NG;
         if (i >= NT) break;
-        const float* lp = gp.L + swih_elem(g, i * NT, b, 0, 0);
+        const float* lp = gp.L + swih_base(g, i * NT, b);
         float la[NT], lb[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-          la[j] = lp[offA + (size_t)j * g.pitch];
-          lb[j] = lp[offB + (size_t)j * g.pitch];
+          la[j] = lp[offA + (size_t)j * 64];
+          lb[j] = lp[offB + (size_t)j * 64];
         }
-        double v = R[(b * NT + i) * ntl_max + tX];
+        double vl = 0.0;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) v = fma(be[j], (double)lb[j] - (double)la[j], v);
+        for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lb[j] - (double)la[j], vl);
         for (int c = 0; c < ncross; ++c) {
           float lc[NT];
 #pragma unroll
-          for (int j = 0; j < NT; ++j) lc[j] = lp[offC + (size_t)c * g.TY * rs + (size_t)j * g.pitch];
+          for (int j = 0; j < NT; ++j) lc[j] = lp[offC + (size_t)c * g.TY * rs + (size_t)j * 64];
 #pragma unroll
-          for (int j = 0; j < NT; ++j) v = fma(be[j], (double)lc[j], v);
+          for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
         }
+        const double v = R[(b * NT + i) * ntl_max + tX] + (x0col ? 0.0 : vl);
         gplus = fma(ap[ii], v, gplus);
         gminus = fma(am[ii], v, gminus);
       }

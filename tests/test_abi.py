@@ -37,7 +37,7 @@ def test_status_strings():
 def test_workspace_bytes_and_validation():
     cfg = swih.Config(16, swih.MANHATTAN, [(31, 31)])
     n = swih.workspace_bytes(cfg, 512, 512)
-    planes = 3 * 16 * 513 * 576 * 4
+    planes = 3 * 16 * 513 * 512 * 4   # tile-major: 8 tiles of 64 columns, rows 0..512
     assert planes <= n < planes * 1.1
     bad = [swih.Config(0, swih.MANHATTAN, [(3, 3)]), swih.Config(257, swih.MANHATTAN, [(3, 3)]),
            swih.Config(8, 9, [(3, 3)]), swih.Config(8, swih.MANHATTAN, [(4, 3)]),
