@@ -89,6 +89,8 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     off += swih_align256((int64_t)g.nI * NXP * 4);
     L.off_vq = off;  // int32 [H][nJ], then double [H][nJ]
     off += swih_align256((int64_t)g.nJ * H * 4) + swih_align256((int64_t)g.nJ * H * 8);
+    L.off_acc = off;
+    off += swih_align256((int64_t)H * W * 8);
   }
   // build scratch (carries), inside the set so that sets never share it
   const int64_t esz = gauss ? 8 : 4;

@@ -322,6 +322,8 @@ __device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
     const int32_t q = (int32_t)rint(val * fix);
     vq[(size_t)y * g.nJ + j] = q;
     vqd[(size_t)y * g.nJ + j] = ldexp((double)q, -2 * SWIH_FIX_BITS);
+  } else if (t < nu + nv + a.nacc) {
+    a.acc[t - nu - nv] = 0;  // the map accumulator starts at zero
   }
 }
 
@@ -539,6 +541,8 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.uq = (int32_t*)(sb + L.off_uq);
     a.vq = (int32_t*)(sb + L.off_vq);
     a.vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
+    a.acc = (int64_t*)(sb + L.off_acc);
+    a.nacc = (int64_t)g.H * g.W;
     a.ax = *ax;
     a.ay = *ay;
   }
@@ -550,7 +554,7 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
   a.nb2 = blocks_for_threads((long)g.nI * g.B * g.H);
   const int nb3 = blocks_for_waves((long)g.nP * g.B);
   const long waves = (long)g.NTY * g.NTX * g.B;
-  nb[0] = g.gauss ? blocks_for_threads((long)g.nI * NXP + (long)g.nJ * g.H) : 0;
+  nb[0] = g.gauss ? blocks_for_threads((long)g.nI * NXP + (long)g.nJ * g.H + a.nacc) : 0;
   nb[1] = blocks_for_waves(waves);
   nb[2] = a.nb1 + a.nb2 + nb3;
   nb[3] = blocks_for_waves(waves * (g.gauss ? g.nI : 1));

@@ -44,6 +44,8 @@ struct BuildArgs {
   void* z;            // band column sums -> carry rows (integer kernels)
   void* T;            // row-segment sums -> row carries
   void* BT;           // tile totals -> tile-origin values
+  int64_t* acc;       // Gaussian: the map accumulator of the set, cleared by the build
+  int64_t nacc;
   GaussAxis ax, ay;
 };
 
@@ -81,6 +83,9 @@ struct MatchArgs {
   int32_t x0, y0, x1, y1;  // inclusive centre rectangle
   int32_t nbx;             // virtual blocks per row of blocks
   int32_t cw, nvpad, ntl_max;  // Gaussian: centres per block, columns per group, tile columns
+  int64_t* acc;            // Gaussian, comb form: per-centre integer accumulator (zero between maps)
+  int32_t comb_steps;      // comb form: centre rows per segment
+  int32_t comb_segs;       // comb form: segments per comb
 };
 
 struct Launch {

@@ -256,6 +256,19 @@ __device__ __forceinline__ double series_coeff(const GaussAxis& ax, int c, int i
   return ax.a[k] * ((idx & 1) ? cos(ang) : sin(ang));
 }
 
+// A Gaussian map value is sum_b sqrt(p_b t_b).  Each bin's term is rounded to
+// a multiple of 2^-40 and the terms are added as integers: exact, so the sum
+// is the same whatever the order in which bins arrive (one block per bin and
+// integer atomics, or all bins in one thread); 2^-41 is far below the float
+// resolution of the result.
+constexpr double kBcScale = 1099511627776.0;  // 2^40
+
+__device__ __forceinline__ int64_t bc_term(double p, float t) {
+  return (int64_t)__builtin_rint(sqrt(fmax(p, 0.0) * fmax((double)t, 0.0)) * kBcScale);
+}
+
+__device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q / kBcScale); }
+
 // Dense map.  One block per (row of centres yc, chunk of cw centres); NG
 // groups of threads, one thread per (group, plane column X the chunk's windows
 // touch: X = xc - rx and xc + rx + 1).  With the y terms contracted,
@@ -337,7 +350,7 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
   const int xc = xa + tid;
   const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
   const double inv_mass = 1.0 / sp.mass;
-  double bc = 0.0;
+  int64_t bc = 0;
   __syncthreads();
   for (int b = 0; b < g.B; ++b) {
     double* Gp = Gb + (b & 1) * NG * 2 * nvpad;
@@ -376,12 +389,175 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
       double hh = 0.0;
 #pragma unroll
       for (int q = 0; q < NG; ++q) hh += Gp[(q * 2 + 0) * nvpad + i2] - Gp[(q * 2 + 1) * nvpad + i1];
-      bc += sqrt(fmax(hh * inv_mass, 0.0) * fmax((double)tmpl[b], 0.0));
+      bc += bc_term(hh * inv_mass, tmpl[b]);
     }
   }
-  if (win) a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)bc;
+  if (win) a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = bc_value(bc);
 }
 
+
+// Dense map for large rectangles: one block per (bin, chunk of centres, comb
+// segment).  A comb is the set of centre rows yc = y0 + q + m h (h the window
+// height): the bottom row of one comb member's windows is the top row of the
+// next, so a block walks its comb segment reading each boundary row once and
+// keeping the previous one in registers (S + 1 rows for S centre rows, against
+// 2 S for one row per block).  Per centre row the column threads form G+/G-
+// exactly as match_gauss does (same operations in the same order), the window
+// threads form the bin's term and add it, as an integer, into the map's
+// accumulator.  match_gauss_fin turns the accumulator into the map and clears
+// it.  The result equals match_gauss bit for bit.
+template <int NT, int NG>
+__device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const GaussPlanes gp{(const float*)a.planes, a.RC};
+  const int x0 = a.x0, y0 = a.y0, x1 = a.x1, y1 = a.y1;
+  const int cw = a.cw, nvpad = a.nvpad, ntl_max = a.ntl_max;
+  const int S = a.comb_steps, nsegc = a.comb_segs;
+  const int rx = sp.rx, ry = sp.ry, h = 2 * ry + 1;
+  const int q = vb % h;
+  int r = vb / h;
+  const int sg = r % nsegc;
+  r /= nsegc;
+  const int chunk = r % a.nbx;
+  const int b = r / a.nbx;
+  const int ny = y1 - y0 + 1;
+  const int Mq = q < ny ? (ny - q + h - 1) / h : 0;  // centre rows of comb q
+  const int m0 = sg * S;
+  if (m0 >= Mq) return;  // uniform over the block
+  const int cnt = min(S, Mq - m0);
+  __syncthreads();  // LDS reuse across virtual blocks of one block
+  extern __shared__ double sm[];
+  double* Gb = sm;                          // [2][NG][2][nvpad]
+  double* R = sm + 2 * NG * 2 * nvpad;      // [S][NT][ntl_max]
+  double* BE = R + (size_t)S * NT * ntl_max;  // [S][NT]
+  const int xa = x0 + chunk * cw;
+  const int cwc = min(cw, x1 - xa + 1);
+  const bool contig = 2 * rx + 1 <= cwc;
+  const int nV = contig ? cwc + 2 * rx + 1 : 2 * cwc;
+  const int tid = threadIdx.x;
+  const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
+  const int ycb = y0 + q + m0 * h;  // first centre row of the segment
+  // beta of every centre row of the segment
+  for (int mm = tid; mm < cnt; mm += blockDim.x) {
+    double be[NT];
+    series_coeffs<NT>(sp.ay, ycb + mm * h, be);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) BE[mm * NT + j] = be[j];
+  }
+  __syncthreads();
+  // row carries: R[mm][i][t] = sum_j beta_j (RC_ij[yb] - RC_ij[ya]) for this bin
+  for (int it = tid; it < cnt * NT * ntl; it += blockDim.x) {
+    const int mm = it / (NT * ntl);
+    const int rem = it - mm * (NT * ntl);
+    const int i = rem / ntl, t = rem - (rem / ntl) * ntl;
+    const int ya = ycb + mm * h - ry, yb = ya + h;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const size_t pb = (size_t)((i * NT + j) * g.B + b);
+      const double* rcp = gp.RC + (pb * g.NTX + tlo + t) * (size_t)(g.H + 1);
+      acc = fma(BE[mm * NT + j], rcp[yb] - rcp[ya], acc);
+    }
+    R[(mm * NT + i) * ntl_max + t] = acc;
+  }
+  const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
+  const int xi = tid - grp * nvpad;
+  const bool has_x = grp < NG && xi < nV;
+  const int X = !has_x ? xa : (contig ? xa - rx + xi
+                                      : (xi < cwc ? xa - rx + xi : xa + rx + 1 + xi - cwc));
+  const int tX = tile_of(X) - tlo;
+  constexpr int NI = (NT + NG - 1) / NG;
+  double ap[NI], am[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int i = grp + ii * NG;
+    ap[ii] = i < NT ? series_coeff(sp.ax, max(X - rx - 1, 0), i) : 0.0;
+    am[ii] = i < NT ? series_coeff(sp.ax, X + rx, i) : 0.0;
+  }
+  const int64_t rs = g.row_stride;
+  const bool x0col = X == 0;  // column X = 0 is not stored (zero)
+  const int64_t xo = swih_xoff(g, x0col ? 1 : X);
+  const float* lpi[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int i = grp + ii * NG;
+    lpi[ii] = gp.L + swih_base(g, (i < NT ? i : 0) * NT, b) + xo;
+  }
+  // the segment's first top row
+  float prev[NI][NT];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      prev[ii][j] = has_x && grp + ii * NG < NT
+                        ? lpi[ii][(size_t)(ycb - ry) * rs + (size_t)j * 64] : 0.0f;
+  const bool win = tid < cwc;
+  const int xc = xa + tid;
+  const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
+  const double inv_mass = 1.0 / sp.mass;
+  const float tb = a.tmpl[b];
+  const int mw = x1 - x0 + 1;
+  __syncthreads();
+  for (int mm = 0; mm < cnt; ++mm) {
+    const int yc = ycb + mm * h;
+    const int Ya = yc - ry, Yb = Ya + h;
+    const int c0 = first_cross(Ya, g.TY);
+    const int ncross = c0 < Yb ? (Yb - 1 - c0) / g.TY + 1 : 0;
+    double* Gp = Gb + (mm & 1) * NG * 2 * nvpad;
+    double be[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) be[j] = uniform(BE[mm * NT + j]);
+    if (has_x) {
+      double gplus = 0.0, gminus = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii) {
+        const int i = grp + ii * NG;
+        if (i >= NT) break;
+        float lb[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) lb[j] = lpi[ii][(size_t)Yb * rs + (size_t)j * 64];
+        double vl = 0.0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lb[j] - (double)prev[ii][j], vl);
+        for (int c = 0; c < ncross; ++c) {
+          float lc[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            lc[j] = lpi[ii][(size_t)(c0 + c * g.TY) * rs + (size_t)j * 64];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
+        }
+        const double v = R[(mm * NT + i) * ntl_max + tX] + (x0col ? 0.0 : vl);
+        gplus = fma(ap[ii], v, gplus);
+        gminus = fma(am[ii], v, gminus);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) prev[ii][j] = lb[j];
+      }
+      Gp[(grp * 2 + 0) * nvpad + xi] = gplus;
+      Gp[(grp * 2 + 1) * nvpad + xi] = gminus;
+    }
+    __syncthreads();
+    if (win) {
+      double hh = 0.0;
+#pragma unroll
+      for (int qg = 0; qg < NG; ++qg)
+        hh += Gp[(qg * 2 + 0) * nvpad + i2] - Gp[(qg * 2 + 1) * nvpad + i1];
+      atomicAdd((unsigned long long*)&a.acc[(size_t)(yc - y0) * mw + (xc - x0)],
+                (unsigned long long)bc_term(hh * inv_mass, tb));
+    }
+  }
+}
+
+// Map from the accumulator of match_gauss_comb; the accumulator is left zero.
+__device__ __forceinline__ void match_gauss_fin(const MatchArgs& a, int vb) {
+  const int mw = a.x1 - a.x0 + 1;
+  const long n = (long)mw * (a.y1 - a.y0 + 1);
+  const long t = (long)vb * 256 + threadIdx.x;
+  if (t >= n) return;
+  a.map[t] = bc_value(a.acc[t]);
+  a.acc[t] = 0;
+}
 
 
 }  // namespace
@@ -584,6 +760,30 @@ hipError_t launch_query_batch(int kind, int nt, const QueryArgs* jobs, const int
   return query_many(kind, nt, jobs, prefix, njobs, gb, ql, s);
 }
 
+namespace {
+
+template <int NT> constexpr void (*gauss_comb)(const MatchArgs&, int) = match_gauss_comb<NT, 3>;
+constexpr void (*gauss_fin)(const MatchArgs&, int) = match_gauss_fin;
+
+hipError_t comb_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
+  switch (nt) {
+    case 3: return run_one<MatchArgs, gauss_comb<3>>(a, ml, s);
+    case 5: return run_one<MatchArgs, gauss_comb<5>>(a, ml, s);
+    case 7: return run_one<MatchArgs, gauss_comb<7>>(a, ml, s);
+    case 9: return run_one<MatchArgs, gauss_comb<9>>(a, ml, s);
+    case 11: return run_one<MatchArgs, gauss_comb<11>>(a, ml, s);
+    case 13: return run_one<MatchArgs, gauss_comb<13>>(a, ml, s);
+    case 15: return run_one<MatchArgs, gauss_comb<15>>(a, ml, s);
+    case 17: return run_one<MatchArgs, gauss_comb<17>>(a, ml, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Comb segments of kCombSteps centre rows: S + 1 boundary rows per S rows.
+constexpr int kCombSteps = 8;
+
+}  // namespace
+
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
                         int32_t x1, int32_t y1, float* map, hipStream_t s) {
@@ -592,7 +792,29 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   Launch ml;
   match_args(L, sp, set, ws, tmpl, tmpl_raw, x0, y0, x1, y1, map, a, ml);
   if (ml.lds > 160 * 1024) return hipErrorInvalidValue;
-  return match_one(sp.kind, L.g.nI, a, ml, s);
+  const int h = 2 * sp.ry + 1, ny = y1 - y0 + 1;
+  if (!L.g.gauss || ny < 2 * h) return match_one(sp.kind, L.g.nI, a, ml, s);
+  // Gaussian over many centre rows: the comb form (same values, fewer plane
+  // reads), then the accumulator to the map.
+  const int NT = L.g.nI, NG = 3;
+  const int S = kCombSteps;
+  const int mmax = (ny + h - 1) / h;
+  a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
+  a.comb_steps = S;
+  a.comb_segs = (mmax + S - 1) / S;
+  Launch cl;
+  cl.threads = ml.threads;
+  cl.blocks = L.g.B * a.nbx * a.comb_segs * h;
+  cl.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)S * NT * a.ntl_max +
+                             (size_t)S * NT);
+  if (cl.lds > 160 * 1024) return match_one(sp.kind, L.g.nI, a, ml, s);
+  hipError_t e = comb_one(NT, a, cl, s);
+  if (e != hipSuccess) return e;
+  Launch fl;
+  fl.threads = 256;
+  fl.blocks = (int32_t)(((long)(x1 - x0 + 1) * ny + 255) / 256);
+  fl.lds = 0;
+  return run_one<MatchArgs, gauss_fin>(a, fl, s);
 }
 
 hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix,
