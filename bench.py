@@ -119,11 +119,12 @@ def measured_traffic(kernel_prefix):
         return None
     if kernel_source_hash() not in txt:
         return None
-    for line in txt.splitlines():
+    total = None
+    for line in txt.splitlines():  # every kernel of the phase (same dispatch count)
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cells) == 6 and cells[0].startswith(kernel_prefix):
-            return (float(cells[4]) + float(cells[5])) * 1e6
-    return None
+            total = (total or 0.0) + (float(cells[4]) + float(cells[5])) * 1e6
+    return total
 
 
 def bench_batch(args):
@@ -404,9 +405,10 @@ def main():
     plane_bytes = 4 * T * NBINS * (H + 1) * (W + 1)
     kernels = {
         "build": {"kernel": "k_emit_gauss (Gaussian plane build, 81 terms x 16 bins)",
-                  "alg": H * W + plane_bytes, "ms": per["planes_gaussian"], "prefix": "k_emit_gauss"},
-        "match": {"kernel": "k_match_gauss (Gaussian dense likelihood map, 482x482 centres)",
-                  "alg": plane_bytes + 4 * nwin, "ms": per["match_gaussian"], "prefix": "k_match_gauss"},
+                  "alg": H * W + plane_bytes, "ms": per["planes_gaussian"], "prefix": "k_emit_gauss<"},
+        "match": {"kernel": "k_match_gauss_comb + k_match_gauss_fin (Gaussian dense likelihood map, "
+                            "482x482 centres; the finalising pass is ~1% of the phase)",
+                  "alg": plane_bytes + 4 * nwin, "ms": per["match_gaussian"], "prefix": "k_match_gauss_"},
     }
 
     def roof(k):

@@ -172,6 +172,10 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
  *                   order 0..nbins-1, then rounded to float.
  *   d_map           device float [(y1-y0+1)][(x1-x0+1)], row-major.
  * An empty rectangle (x1 < x0 or y1 < y0) is valid and enqueues nothing.
+ * SWIH_GAUSSIAN maps use a per-scale accumulator inside d_ws (cleared by the
+ * build, left cleared by every map): Gaussian maps of one scale of one
+ * workspace must not run concurrently (order them on one stream).  Maps of
+ * the other kernels only read d_ws.
  */
 int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
                int32_t width, int32_t scale_idx, const float* d_template,
