@@ -349,10 +349,15 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
   for (int l = 0; l < 64; ++l) {
     const uint64_t ml = ((uint64_t)readlane((uint32_t)(mask >> 32), l) << 32) |
                         readlane((uint32_t)mask, l);
-    const bool bit = bit_of(ml, lane) != 0;
+    const int32_t bit = (int32_t)bit_of(ml, lane);
+    // the column's terms are loaded unconditionally (one scalar load batch)
+    // and masked by multiplication, so no lane-dependent branch guards a load
     const int32_t* ul = ucol + l * NT;
+    int32_t uv[NT];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) treg[i] += bit ? ul[i] : 0;
+    for (int i = 0; i < NT; ++i) uv[i] = ul[i];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) treg[i] += bit * uv[i];
   }
   if (lane < t.nrows) {
 #pragma unroll
@@ -360,9 +365,10 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
       T[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] = (int64_t)treg[i];
   }
   // tile totals of every plane: sum over the band's rows of v_j(y) T_i(y), exact in int64
+  // (lanes past the band's last row hold T_i = 0, so their v_j needs no mask)
   const int yl = t.y0 + (lane < t.nrows ? lane : 0);
   for (int j = 0; j < NT; ++j) {
-    const int64_t vj = lane < t.nrows ? (int64_t)vq[(size_t)yl * NT + j] : 0;
+    const int64_t vj = (int64_t)vq[(size_t)yl * NT + j];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
       const int64_t s = wave_sum(vj * (int64_t)treg[i]);
@@ -431,7 +437,8 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   for (int j = 0; j < NT; ++j) {
     const int p = i * NT + j;
     const size_t pb = (size_t)(p * g.B + t.b);
-    const double term = lane < t.nrows ? (double)vq[(size_t)yl * NT + j] * (double)ereg : 0.0;
+    // ereg is 0 on lanes past the band's last row
+    const double term = (double)vq[(size_t)yl * NT + j] * (double)ereg;
     const double rc =
         (CTc[(pb * g.NTY + t.ty) * g.NTX + t.tx] + wave_incl_scan(term)) * sc48;
     if (lane < t.nrows) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1) + t.y0 + 1 + lane] = rc;
