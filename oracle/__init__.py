@@ -11,8 +11,11 @@ paper, which the paper's SWIH method reproduces exactly (Sec. 3, Sec. 5).
 correlation) used only to cross-check the first.
 
 Kernel kinds: 0 uniform, 1 Manhattan, 2 Euclidean (paraboloid), 3 Gaussian
-(true Gaussian with sigma = window side / 4 unless given).  See the C file's
-header for the readings of the paper these fix.
+(true Gaussian with sigma = window side / 4 unless given), 5 exponential
+(exp(-|dx|/tx - |dy|/ty), tau = window side / 4 unless given).  See the C
+file's header for the readings of the paper these fix.  For the two real-valued
+kernels the ``sigma`` argument of every function is the pair of widths
+(sigma or tau per axis).
 """
 from __future__ import annotations
 
@@ -23,8 +26,10 @@ import numpy as np
 
 from . import build as _build
 
-UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN = 0, 1, 2, 3
-KIND_NAMES = {UNIFORM: "uniform", MANHATTAN: "manhattan", EUCLIDEAN: "euclidean", GAUSSIAN: "gaussian"}
+UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN, EXPONENTIAL = 0, 1, 2, 3, 5
+KIND_NAMES = {UNIFORM: "uniform", MANHATTAN: "manhattan", EUCLIDEAN: "euclidean", GAUSSIAN: "gaussian",
+              EXPONENTIAL: "exponential"}
+REAL_KINDS = (GAUSSIAN, EXPONENTIAL)
 
 _lib = None
 
@@ -39,6 +44,7 @@ def _load():
         lib.oracle_quantise.argtypes = [i32, i32]
         lib.oracle_kernel_table_int.argtypes = [i32, i32, i32, i64p]
         lib.oracle_kernel_table_gauss.argtypes = [i32, i32, C.c_double, C.c_double, f64p]
+        lib.oracle_kernel_table_exp.argtypes = [i32, i32, C.c_double, C.c_double, f64p]
         lib.oracle_hist_i64.argtypes = [u8p, i32, i32, i32, i32, i64p, i32, i32, i32p, i32, i64p]
         lib.oracle_hist_f64.argtypes = [u8p, i32, i32, i32, i32, f64p, i32, i32, i32p, i32, f64p]
         lib.oracle_bc_i64.argtypes = [u8p, i32, i32, i32, i32, i64p, i32, i32, i64p, i32p, i32, f64p]
@@ -69,18 +75,19 @@ def quantise(v, nbins: int):
 
 
 def default_sigma(w: int, h: int):
-    """Gaussian widths used throughout: sigma = side / 4 along each axis."""
+    """Widths used throughout (Gaussian sigma, exponential tau): side / 4 per axis."""
     return w / 4.0, h / 4.0
 
 
 def kernel_table(kind: int, w: int, h: int, sigma=None) -> np.ndarray:
-    """Spatial kernel k[dy + ry, dx + rx] (int64, or float64 for the Gaussian)."""
+    """Spatial kernel k[dy + ry, dx + rx] (int64, or float64 for the real-valued kernels)."""
     lib = _load()
-    if kind == GAUSSIAN:
+    if kind in REAL_KINDS:
         sx, sy = sigma if sigma is not None else default_sigma(w, h)
         out = np.empty((h, w), np.float64)
-        if lib.oracle_kernel_table_gauss(w, h, float(sx), float(sy), _p(out, C.c_double)):
-            raise ValueError("bad Gaussian window %dx%d" % (w, h))
+        fn = lib.oracle_kernel_table_gauss if kind == GAUSSIAN else lib.oracle_kernel_table_exp
+        if fn(w, h, float(sx), float(sy), _p(out, C.c_double)):
+            raise ValueError("bad window %dx%d for kernel %d" % (w, h, kind))
         return out
     out = np.empty((h, w), np.int64)
     if lib.oracle_kernel_table_int(int(kind), w, h, _p(out, C.c_int64)):
@@ -104,7 +111,7 @@ def _img(img):
 def hist(img, nbins: int, kind: int, w: int, h: int, centres, sigma=None, table=None) -> np.ndarray:
     """Raw weighted histograms H_b at the given centres ([n, 2] of (xc, yc)).
 
-    int64 [n, nbins] for integer kernels, float64 for the Gaussian.
+    int64 [n, nbins] for integer kernels, float64 for the real-valued ones.
     ``table`` overrides the kernel (any int64 or float64 h x w table).
     """
     lib = _load()
@@ -142,8 +149,8 @@ def template(img, nbins: int, kind: int, w: int, h: int, centre, sigma=None):
 def bc_at(img, nbins: int, kind: int, w: int, h: int, centres, tmpl, sigma=None) -> np.ndarray:
     """Bhattacharyya coefficient at listed centres against template ``tmpl``.
 
-    Integer kernels take the raw integer template; the Gaussian takes the
-    normalised one.
+    Integer kernels take the raw integer template; the real-valued kernels take
+    the normalised one.
     """
     lib = _load()
     a = _img(img)

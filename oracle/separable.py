@@ -10,6 +10,7 @@ k(dx, dy) = sum_r a_r(dx) * c_r(dy):
 * Manhattan: (rx + ry + 1) * 1 * 1  -  |dx| * 1  -  1 * |dy|
 * Euclidean: (rx^2 + ry^2 + 1) * 1 * 1  -  dx^2 * 1  -  1 * dy^2
 * Gaussian:  exp(-dx^2 / 2 sx^2) * exp(-dy^2 / 2 sy^2)
+* exponential: exp(-|dx| / tx) * exp(-|dy| / ty)
 
 For every bin b the indicator image [Q(f) = b] is correlated along rows with
 a_r and then along columns with c_r (numpy sliding windows and integer or
@@ -20,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 from numpy.lib.stride_tricks import sliding_window_view
 
-UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN = 0, 1, 2, 3
+UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN, EXPONENTIAL = 0, 1, 2, 3, 5
 
 
 def profiles(kind: int, w: int, h: int, sigma=None):
@@ -41,19 +42,22 @@ def profiles(kind: int, w: int, h: int, sigma=None):
         gx = np.exp(-(dx.astype(np.float64) ** 2) / (2 * sx * sx))
         gy = np.exp(-(dy.astype(np.float64) ** 2) / (2 * sy * sy))
         return [(gx, gy)]
+    if kind == EXPONENTIAL:
+        tx, ty = sigma if sigma is not None else (w / 4.0, h / 4.0)
+        return [(np.exp(-np.abs(dx) / tx), np.exp(-np.abs(dy) / ty))]
     raise ValueError(kind)
 
 
 def hist_maps(img: np.ndarray, nbins: int, kind: int, w: int, h: int, sigma=None) -> np.ndarray:
     """H_b at every valid centre: array [nbins, H - h + 1, W - w + 1].
 
-    int64 for integer kernels (exact), float64 for the Gaussian.
+    int64 for integer kernels (exact), float64 for the real-valued ones.
     """
     img = np.asarray(img, np.uint8)
     H, W = img.shape
     q = (img.astype(np.int64) * nbins) // 256
     prof = profiles(kind, w, h, sigma)
-    dt = np.int64 if kind != GAUSSIAN else np.float64
+    dt = np.float64 if kind in (GAUSSIAN, EXPONENTIAL) else np.int64
     out = np.zeros((nbins, H - h + 1, W - w + 1), dt)
     for b in range(nbins):
         m = (q == b).astype(dt)

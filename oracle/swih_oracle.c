@@ -22,6 +22,10 @@
  *    k = (rx^2 + ry^2 + 1) - dx^2 - dy^2.
  *  - Gaussian kernel (Fig. 1c, no formula): the true Gaussian
  *    exp(-dx^2 / (2 sx^2) - dy^2 / (2 sy^2)).
+ *  - Exponential kernel (named among the weighting functions of Sec. 2, no
+ *    formula): the Laplacian of the city-block distance,
+ *    exp(-|dx| / tx - |dy| / ty), widths tx = w / 4, ty = h / 4 as for the
+ *    Gaussian.
  *  - Uniform kernel: k = 1, the plain local histogram (Sec. 1, integral
  *    histogram of Porikli).
  *  - Normalisation (Sec. 1 steps (4)-(5); Sec. 2.1): by the total kernel mass
@@ -38,7 +42,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OR_UNIFORM = 0, OR_MANHATTAN = 1, OR_EUCLIDEAN = 2, OR_GAUSSIAN = 3 };
+enum { OR_UNIFORM = 0, OR_MANHATTAN = 1, OR_EUCLIDEAN = 2, OR_GAUSSIAN = 3, OR_EXPONENTIAL = 5 };
 
 /* Quantiser Q of Eq. 2: uniform bins over [0, 256). */
 int oracle_quantise(int v, int nbins) { return (v * nbins) / 256; }
@@ -80,6 +84,20 @@ int oracle_kernel_table_gauss(int w, int h, double sigma_x, double sigma_y, doub
     for (int dx = -rx; dx <= rx; ++dx) {
       const double e = (double)dx * dx / (2.0 * sigma_x * sigma_x) +
                        (double)dy * dy / (2.0 * sigma_y * sigma_y);
+      out[(dy + ry) * w + (dx + rx)] = exp(-e);
+    }
+  }
+  return 0;
+}
+
+/* Exponential (Laplacian) table exp(-|dx| / tau_x - |dy| / tau_y), same indexing. */
+int oracle_kernel_table_exp(int w, int h, double tau_x, double tau_y, double* out) {
+  if (w < 1 || h < 1 || (w % 2) == 0 || (h % 2) == 0) return -1;
+  if (!(tau_x > 0.0) || !(tau_y > 0.0)) return -1;
+  const int rx = (w - 1) / 2, ry = (h - 1) / 2;
+  for (int dy = -ry; dy <= ry; ++dy) {
+    for (int dx = -rx; dx <= rx; ++dx) {
+      const double e = fabs((double)dx) / tau_x + fabs((double)dy) / tau_y;
       out[(dy + ry) * w + (dx + rx)] = exp(-e);
     }
   }

@@ -4,7 +4,10 @@ None of these retypes the oracle's own loop.  Each test is chosen so that a
 plausible slip in the oracle (a dropped kernel term, a wrong sign, a swapped
 dx/dy, an off-by-one window edge, a wrong normaliser) fails at least one:
 
-* closed-form kernel masses (golden file, worked by hand from sum formulas);
+* closed-form kernel masses (golden file, worked by hand from sum formulas;
+  geometric series for the exponential kernel);
+* the exponential table is the product of two 1-D profiles with a constant
+  ratio between neighbouring weights (the defining property of exp(-|d|/tau));
 * sum_b H_b = S at every centre (normalisation independent of location,
   Sec. 2.1 of the paper);
 * a constant image puts all mass in one bin; the likelihood map is 1;
@@ -32,7 +35,7 @@ from paper_1705_03524_amd import synth
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 INT_KINDS = (oracle.UNIFORM, oracle.MANHATTAN, oracle.EUCLIDEAN)
-ALL_KINDS = INT_KINDS + (oracle.GAUSSIAN,)
+ALL_KINDS = INT_KINDS + (oracle.GAUSSIAN, oracle.EXPONENTIAL)
 NAMES = {"uniform": oracle.UNIFORM, "manhattan": oracle.MANHATTAN, "euclidean": oracle.EUCLIDEAN}
 
 
@@ -83,6 +86,36 @@ def test_masses_closed_form(w, h):
     gx = sum(math.exp(-d * d / (2 * sx * sx)) for d in range(-rx, rx + 1))
     gy = sum(math.exp(-d * d / (2 * sy * sy)) for d in range(-ry, ry + 1))
     assert oracle.mass(oracle.GAUSSIAN, w, h) == pytest.approx(gx * gy, rel=1e-13)
+    # exponential: 1 + 2 (q + q^2 + ... + q^r) = 1 + 2 q (1 - q^r) / (1 - q), q = exp(-1 / tau)
+    geo = lambda r, tau: 1 + 2 * math.exp(-1 / tau) * (1 - math.exp(-r / tau)) / (1 - math.exp(-1 / tau))
+    assert oracle.mass(oracle.EXPONENTIAL, w, h) == pytest.approx(geo(rx, w / 4.0) * geo(ry, h / 4.0), rel=1e-13)
+
+
+@pytest.mark.parametrize("w,h", [(3, 3), (7, 5), (5, 11), (31, 31), (61, 91)])
+def test_exponential_table_structure(w, h):
+    t = oracle.kernel_table(oracle.EXPONENTIAL, w, h)
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    assert t[ry, rx] == 1.0
+    np.testing.assert_allclose(t, t[::-1, :], rtol=0, atol=0)
+    np.testing.assert_allclose(t, t[:, ::-1], rtol=0, atol=0)
+    # rank one: k(dx, dy) = k(dx, 0) k(0, dy)
+    np.testing.assert_allclose(t, np.outer(t[:, rx], t[ry, :]), rtol=1e-14)
+    # a constant ratio between neighbouring weights moving out from the centre,
+    # the x ratio set by w alone and the y ratio by h alone
+    qx = t[ry, rx + 1:] / t[ry, rx:-1] if rx else np.array([])
+    qy = t[ry + 1:, rx] / t[ry:-1, rx] if ry else np.array([])
+    if rx:
+        np.testing.assert_allclose(qx, qx[0], rtol=1e-13)
+        assert 0 < qx[0] < 1
+        tt = oracle.kernel_table(oracle.EXPONENTIAL, h, w)
+        np.testing.assert_allclose(tt.T, t, rtol=1e-15)   # widths follow the sides, not the axes
+    if ry:
+        np.testing.assert_allclose(qy, qy[0], rtol=1e-13)
+    if rx and ry and w != h:
+        assert qx[0] != pytest.approx(qy[0])
+    # widths side / 4: the weight at distance d along x is q^d with q^(w/4) = 1/e
+    if rx:
+        assert qx[0] ** (w / 4.0) == pytest.approx(math.exp(-1), rel=1e-13)
 
 
 def test_manhattan_table_follows_eq1_distance():
@@ -104,7 +137,7 @@ def test_mass_invariant_every_centre(kind):
     c = valid_centres(40, 37, w, h)
     hb = oracle.hist(img, 5, kind, w, h, c)
     S = oracle.mass(kind, w, h)
-    if kind == oracle.GAUSSIAN:
+    if kind in oracle.REAL_KINDS:
         np.testing.assert_allclose(hb.sum(1), S, rtol=1e-13)
     else:
         assert np.all(hb.sum(1) == S)
@@ -124,7 +157,7 @@ def test_constant_image(kind, v):
     expect[b] = S
     np.testing.assert_allclose(hb, np.broadcast_to(expect, hb.shape), rtol=1e-14)
     raw, p = oracle.template(img, nb, kind, w, h, (15, 12))
-    m = oracle.bc_map(img, nb, kind, w, h, raw if kind != oracle.GAUSSIAN else p)
+    m = oracle.bc_map(img, nb, kind, w, h, raw if kind not in oracle.REAL_KINDS else p)
     np.testing.assert_allclose(m, 1.0, rtol=0, atol=1e-15)
 
 
@@ -212,7 +245,7 @@ def test_bc_self_match_and_bounds(kind):
     img, _ = synth.rect_scene(2, 64, 64, nrect=3)
     nb, w, h = 16, 15, 15
     raw, p = oracle.template(img, nb, kind, w, h, (30, 33))
-    m = oracle.bc_map(img, nb, kind, w, h, raw if kind != oracle.GAUSSIAN else p)
+    m = oracle.bc_map(img, nb, kind, w, h, raw if kind not in oracle.REAL_KINDS else p)
     assert m[33 - 7, 30 - 7] == pytest.approx(1.0, abs=2e-15)
     assert m.min() >= 0.0 and m.max() <= 1.0 + 2e-15
 
@@ -249,8 +282,10 @@ def naive_hist(img, nb, kind, w, h, xc, yc):
                 k = rx + ry + 1 - dx - dy
             elif kind == oracle.EUCLIDEAN:
                 k = rx * rx + ry * ry + 1 - dx * dx - dy * dy
-            else:
+            elif kind == oracle.GAUSSIAN:
                 k = math.exp(-dx * dx / (2 * (w / 4) ** 2)) * math.exp(-dy * dy / (2 * (h / 4) ** 2))
+            else:
+                k = math.exp(-dx / (w / 4)) * math.exp(-dy / (h / 4))
             out[int(img[y, x]) * nb // 256] += k
     return out
 
@@ -276,7 +311,7 @@ def test_brute_force_vs_separable(kind, nb, wh):
     hb = oracle.hist(img, nb, kind, w, h, c)
     sm = sep.hist_maps(img, nb, kind, w, h)
     got = sm.transpose(1, 2, 0).reshape(-1, nb)
-    if kind == oracle.GAUSSIAN:
+    if kind in oracle.REAL_KINDS:
         np.testing.assert_allclose(hb, got, rtol=1e-12, atol=1e-12)
     else:
         assert np.array_equal(hb, got)
