@@ -38,6 +38,13 @@
  *                       over those row results.  Same values as SWIH_GAUSSIAN
  *                       up to rounding; the workspace holds H x (W-w+1) x
  *                       nbins floats per scale instead of (2K+1)^2 planes.
+ *       SWIH_EXPONENTIAL  exp(-|dx|/tx - |dy|/ty), tx = w/4, ty = h/4 (the
+ *                       exponential weighting of Sec. 2): four direction-
+ *                       weighted integral histograms per bin, one per window
+ *                       quadrant (Sec. 2.1), each built in its own direction
+ *                       and stored rescaled to its own corner, so values stay
+ *                       bounded at any image size.  Exact up to rounding
+ *                       (float planes, double lookups).
  *     The first three are exact: raw histograms are integers, computed modulo
  *     2^32 and exact whenever the true value is below 2^32.
  *   - Normalised histogram p_b = H_b / S, with S the kernel mass (the same at
@@ -80,7 +87,8 @@ typedef enum {
   SWIH_MANHATTAN = 1,
   SWIH_EUCLIDEAN = 2,
   SWIH_GAUSSIAN = 3,
-  SWIH_GAUSSIAN_SEP = 4
+  SWIH_GAUSSIAN_SEP = 4,
+  SWIH_EXPONENTIAL = 5
 } swih_kernel;
 
 /* One window scale: odd width and height, 1 <= w <= W, 1 <= h <= H. */
@@ -105,8 +113,8 @@ typedef struct {
 /*
  * Bytes of device workspace a build of an H x W image needs under `cfg`.
  * Integer kernels keep one set of planes for every scale; both Gaussian forms
- * keep one set per scale (their weight terms depend on the window size,
- * Sec. 2.1 "multi-scale").  Returns the size (> 0), or a negative status.
+ * and the exponential keep one set per scale (their weight terms depend on
+ * the window size, Sec. 2.1 "multi-scale").  Returns the size (> 0), or a negative status.
  */
 int64_t swih_workspace_bytes(const swih_config* cfg, int32_t height, int32_t width);
 
@@ -131,8 +139,8 @@ int swih_build(const swih_config* cfg, const uint8_t* d_img, int32_t height, int
  *                       of the scale).  Several kernel launches, small output.
  *   swih_build_planes   writes the planes of one set from the image and those
  *                       carries: exactly one kernel launch.
- *   set     0 for integer kernels; the scale index for the Gaussian, whose
- *           planes are per scale.
+ *   set     0 for integer kernels; the scale index for the Gaussian and the
+ *           exponential, whose planes are per scale.
  * For SWIH_GAUSSIAN_SEP the first phase has nothing to do (it enqueues
  * nothing) and the second writes the row results in one launch.
  * Each set keeps its own carries, so a set's planes need only follow its own
@@ -153,7 +161,8 @@ int swih_build_planes(const swih_config* cfg, const uint8_t* d_img, int32_t heig
  *               are clamped on the device and give unspecified histograms).
  *   d_hist      device float [n][nbins], p_b = H_b / S; may be NULL.
  *   d_hist_raw  device uint32 [n][nbins], exact H_b; integer kernels only
- *               (SWIH_ERR_UNSUPPORTED for both Gaussian forms); may be NULL.
+ *               (SWIH_ERR_UNSUPPORTED for both Gaussian forms and the
+ *               exponential); may be NULL.
  * n == 0 is valid and enqueues nothing.
  */
 int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
@@ -167,6 +176,9 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
  *   d_template      device float [nbins], normalised template t_b; or NULL.
  *   d_template_raw  device uint32 [nbins], exact template T_b (integer kernels
  *                   only); or NULL.  Exactly one of the two must be given.
+ *                   With the float template the value is sum_b sqrt(p_b t_b)
+ *                   over bins in order (double for the integer kernels and
+ *                   the exponential), rounded to float.
  *                   With the raw template the value is
  *                   (sum_b sqrt(H_b T_b)) / S evaluated in double with bins in
  *                   order 0..nbins-1, then rounded to float.

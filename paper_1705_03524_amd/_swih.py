@@ -15,10 +15,12 @@ from typing import Sequence
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libswih.so")
 
-UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN, GAUSSIAN_SEP = 0, 1, 2, 3, 4
+UNIFORM, MANHATTAN, EUCLIDEAN, GAUSSIAN, GAUSSIAN_SEP, EXPONENTIAL = 0, 1, 2, 3, 4, 5
 KERNELS = {"uniform": UNIFORM, "manhattan": MANHATTAN, "euclidean": EUCLIDEAN, "gaussian": GAUSSIAN,
-           "gaussian_sep": GAUSSIAN_SEP}
+           "gaussian_sep": GAUSSIAN_SEP, "exponential": EXPONENTIAL}
 SERIES_KINDS = (GAUSSIAN, GAUSSIAN_SEP)
+# real-valued histograms (no exact integer outputs), one plane set per scale
+REAL_KINDS = (GAUSSIAN, GAUSSIAN_SEP, EXPONENTIAL)
 
 OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
 

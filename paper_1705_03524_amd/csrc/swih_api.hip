@@ -12,10 +12,16 @@ namespace {
 constexpr int32_t kMaxSide = 8192;
 constexpr int32_t kDefaultTY = 64;
 
-bool kind_ok(int32_t k) { return k >= SWIH_UNIFORM && k <= SWIH_GAUSSIAN_SEP; }
+bool kind_ok(int32_t k) { return k >= SWIH_UNIFORM && k <= SWIH_EXPONENTIAL; }
 
-// Kernels built from the cosine series, with one workspace set per scale.
+// Kernels built from the cosine series.
 bool series_kind(int32_t k) { return k == SWIH_GAUSSIAN || k == SWIH_GAUSSIAN_SEP; }
+
+// Kernels with one workspace set per scale (weight terms depend on the window).
+bool per_scale(int32_t k) { return series_kind(k) || k == SWIH_EXPONENTIAL; }
+
+// Kernels whose histograms are real-valued: no exact integer outputs.
+bool real_kind(int32_t k) { return per_scale(k); }
 
 int32_t gauss_K(const swih_config* c) { return c->gauss_terms == 0 ? 4 : c->gauss_terms; }
 
@@ -63,6 +69,27 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   g.TY = kDefaultTY;
   g.NTX = (W + SWIH_TX - 1) / SWIH_TX;
   g.NTY = (H + g.TY - 1) / g.TY;
+  if (c->kernel == SWIH_EXPONENTIAL) {  // four direction planes per bin (swih_exp.hip)
+    g.nP = 4;
+    g.ppg = 1;
+    g.row_stride = SWIH_TX;
+    g.tile_stride = (int64_t)(H + 1) * g.row_stride;
+    const int64_t DB = 4LL * g.B;
+    int64_t off = 0;
+    L.off_planes = off;
+    off += swih_align256(DB * g.NTX * (int64_t)(H + 1) * SWIH_TX * 4);
+    L.off_scratch = off;
+    L.off_z = off;
+    off += swih_align256(DB * g.NTY * (int64_t)g.NTX * SWIH_TX * 8);
+    L.off_T = off;
+    off += swih_align256(DB * g.NTX * (int64_t)H * 8);
+    L.off_CT = off;
+    off += swih_align256(DB * g.NTY * (int64_t)g.NTX * 8);
+    L.set_bytes = off;
+    L.nsets = c->nscales;
+    L.total = L.set_bytes * L.nsets;
+    return SWIH_OK;
+  }
   const bool gauss = c->kernel == SWIH_GAUSSIAN;
   g.gauss = gauss ? 1 : 0;
   if (gauss) {
@@ -131,6 +158,12 @@ int scale_params(const swih_config* c, int32_t scale_idx, ScaleParams& sp) {
     sp.mass = gauss_axis_mass(sc.w, K, sp.ax.a, sp.ax.P) * gauss_axis_mass(sc.h, K, sp.ay.a, sp.ay.P);
     return SWIH_OK;
   }
+  if (c->kernel == SWIH_EXPONENTIAL) {
+    ExpScale es;
+    exp_scale(sc.w, sc.h, es);
+    sp.mass = es.mass;
+    return SWIH_OK;
+  }
   sp.mass = int_mass(c->kernel, sc.w, sc.h);
   if (sp.mass >= 4294967296.0) return SWIH_ERR_UNSUPPORTED;  // H_b must stay below 2^32
   if (c->kernel == SWIH_MANHATTAN) sp.c_int = (uint32_t)(sp.rx + sp.ry + 1);
@@ -192,6 +225,18 @@ int build_phases(const swih_config* cfg, const uint8_t* d_img, int32_t height, i
     }
     return SWIH_OK;
   }
+  if (cfg->kernel == SWIH_EXPONENTIAL) {
+    for (int k = first; k <= last; ++k) {
+      const swih_scale sc = cfg->scales[k];
+      ExpScale es;
+      exp_scale(sc.w, sc.h, es);
+      ExpBuildArgs a;
+      int32_t nb[4];
+      exp_build_args(L, es, k, d_img, pitch, (char*)d_ws, a, nb);
+      if (exp_launch_build(a, nb, phases, s) != hipSuccess) return SWIH_ERR_HIP;
+    }
+    return SWIH_OK;
+  }
   for (int k = first; k <= last; ++k) {
     ScaleParams sp;
     scale_params(cfg, gauss ? k : 0, sp);
@@ -231,7 +276,7 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   int st = check_config(cfg, height, width);
   if (st != SWIH_OK) return st;
   if (scale_idx < 0 || scale_idx >= cfg->nscales || n < 0 || !d_ws) return SWIH_ERR_INVALID;
-  if (series_kind(cfg->kernel) && d_hist_raw) return SWIH_ERR_UNSUPPORTED;
+  if (real_kind(cfg->kernel) && d_hist_raw) return SWIH_ERR_UNSUPPORTED;
   if (n == 0) return SWIH_OK;
   if (!d_centres || (!d_hist && !d_hist_raw)) return SWIH_ERR_INVALID;
   SwihLayout L;
@@ -248,6 +293,15 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
                    (const char*)d_ws + (size_t)scale_idx * L.set_bytes, d_centres, n, d_hist, a, nb);
     return sep_launch_query(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
   }
+  if (cfg->kernel == SWIH_EXPONENTIAL) {
+    const swih_scale sc = cfg->scales[scale_idx];
+    ExpScale es;
+    exp_scale(sc.w, sc.h, es);
+    ExpQueryArgs a;
+    int32_t nb;
+    exp_query_args(L, es, scale_idx, (const char*)d_ws, d_centres, n, d_hist, a, nb);
+    return exp_launch_query(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+  }
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
   return launch_query(L, sp, set, (const char*)d_ws, d_centres, n, d_hist, d_hist_raw,
                       (hipStream_t)stream) == hipSuccess
@@ -262,7 +316,7 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   if (st != SWIH_OK) return st;
   if (scale_idx < 0 || scale_idx >= cfg->nscales || !d_ws) return SWIH_ERR_INVALID;
   if ((d_template == nullptr) == (d_template_raw == nullptr)) return SWIH_ERR_INVALID;
-  if (series_kind(cfg->kernel) && d_template_raw) return SWIH_ERR_UNSUPPORTED;
+  if (real_kind(cfg->kernel) && d_template_raw) return SWIH_ERR_UNSUPPORTED;
   if (r.x1 < r.x0 || r.y1 < r.y0) return SWIH_OK;
   const swih_scale sc = cfg->scales[scale_idx];
   const int32_t rx = (sc.w - 1) / 2, ry = (sc.h - 1) / 2;
@@ -283,6 +337,15 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
                    (const char*)d_ws + (size_t)scale_idx * L.set_bytes, d_template, r.x0, r.y0,
                    r.x1, r.y1, d_map, a, nb);
     return sep_launch_match(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+  }
+  if (cfg->kernel == SWIH_EXPONENTIAL) {
+    ExpScale es;
+    exp_scale(sc.w, sc.h, es);
+    ExpMatchArgs a;
+    int32_t nb;
+    exp_match_args(L, es, scale_idx, (const char*)d_ws, d_template, r.x0, r.y0, r.x1, r.y1, d_map,
+                   a, nb);
+    return exp_launch_match(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
   }
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
   return launch_match(L, sp, set, (const char*)d_ws, d_template, d_template_raw, r.x0, r.y0, r.x1,
@@ -309,27 +372,30 @@ struct BatchHeader {
 };
 
 int32_t frame_units(const swih_config* cfg, const swih_frame_desc& f) {
-  if (!series_kind(cfg->kernel)) return 1;
+  if (!per_scale(cfg->kernel)) return 1;
   return f.nscales > 0 ? f.nscales : cfg->nscales;
 }
 
 // Offsets of every table section for the given counts (item records of the
-// separable kind are its own argument structs).
+// separable and exponential kinds are their own argument structs).
 BatchHeader table_layout(int32_t kind, int32_t nunits, int32_t nq, int32_t nm) {
   BatchHeader h;
   memset(&h, 0, sizeof(h));
-  const bool sep = kind == SWIH_GAUSSIAN_SEP;
+  const bool sep = kind == SWIH_GAUSSIAN_SEP, ex = kind == SWIH_EXPONENTIAL;
+  const size_t ub = sep ? sizeof(SepBuildArgs) : (ex ? sizeof(ExpBuildArgs) : sizeof(BuildArgs));
+  const size_t qb = sep ? sizeof(SepQueryArgs) : (ex ? sizeof(ExpQueryArgs) : sizeof(QueryArgs));
+  const size_t mb = sep ? sizeof(SepMatchArgs) : (ex ? sizeof(ExpMatchArgs) : sizeof(MatchArgs));
   int64_t off = swih_align256(sizeof(BatchHeader));
   h.off_units = off;
-  off += swih_align256((int64_t)nunits * (sep ? sizeof(SepBuildArgs) : sizeof(BuildArgs)));
+  off += swih_align256((int64_t)nunits * ub);
   h.off_uprefix = off;
   off += swih_align256((int64_t)4 * (nunits + 1) * sizeof(int32_t));
   h.off_q = off;
-  off += swih_align256((int64_t)nq * (sep ? sizeof(SepQueryArgs) : sizeof(QueryArgs)));
+  off += swih_align256((int64_t)nq * qb);
   h.off_qprefix = off;
   off += swih_align256((int64_t)(nq + 1) * sizeof(int32_t));
   h.off_m = off;
-  off += swih_align256((int64_t)nm * (sep ? sizeof(SepMatchArgs) : sizeof(MatchArgs)));
+  off += swih_align256((int64_t)nm * mb);
   h.off_mprefix = off;
   off += swih_align256((int64_t)(nm + 1) * sizeof(int32_t));
   h.bytes = off;
@@ -380,6 +446,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
   if ((int64_t)table_bytes < need) return SWIH_ERR_WORKSPACE;
   const bool gauss = cfg->kernel == SWIH_GAUSSIAN;
   const bool sep = cfg->kernel == SWIH_GAUSSIAN_SEP;
+  const bool ex = cfg->kernel == SWIH_EXPONENTIAL;
   // frames: check, lay out, and fill one build unit per plane set
   std::vector<SwihLayout> layouts(nframes);
   std::vector<int32_t> ubase(nframes + 1, 0);
@@ -409,8 +476,22 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
   memset(tb, 0, (size_t)h.bytes);
   BuildArgs* units = (BuildArgs*)(tb + h.off_units);
   SepBuildArgs* sunits = (SepBuildArgs*)(tb + h.off_units);
+  ExpBuildArgs* eunits = (ExpBuildArgs*)(tb + h.off_units);
   int32_t* upre = (int32_t*)(tb + h.off_uprefix);
   for (int f = 0; f < nframes; ++f) {
+    if (ex) {
+      const swih_frame_desc& fd = frames[f];
+      const swih_config fc = frame_config(cfg, fd);
+      for (int k = 0; k < ubase[f + 1] - ubase[f]; ++k) {
+        const int u = ubase[f] + k;
+        ExpScale es;
+        exp_scale(fc.scales[k].w, fc.scales[k].h, es);
+        int32_t nb[4];
+        exp_build_args(layouts[f], es, k, fd.d_img, fd.pitch, (char*)fd.d_ws, eunits[u], nb);
+        for (int s = 0; s < 4; ++s) upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + nb[s];
+      }
+      continue;
+    }
     if (sep) {
       const swih_frame_desc& fd = frames[f];
       const swih_config fc = frame_config(cfg, fd);
@@ -450,8 +531,17 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     if (qd.frame < 0 || qd.frame >= nframes || qd.n < 0) return SWIH_ERR_INVALID;
     const swih_config fc = frame_config(cfg, frames[qd.frame]);
     if (qd.scale_idx < 0 || qd.scale_idx >= fc.nscales) return SWIH_ERR_INVALID;
-    if ((gauss || sep) && qd.d_hist_raw) return SWIH_ERR_UNSUPPORTED;
+    if (real_kind(cfg->kernel) && qd.d_hist_raw) return SWIH_ERR_UNSUPPORTED;
     if (qd.n > 0 && (!qd.d_centres || (!qd.d_hist && !qd.d_hist_raw))) return SWIH_ERR_INVALID;
+    if (ex) {
+      ExpScale es;
+      exp_scale(fc.scales[qd.scale_idx].w, fc.scales[qd.scale_idx].h, es);
+      int32_t nb = 0;
+      exp_query_args(layouts[qd.frame], es, qd.scale_idx, (const char*)frames[qd.frame].d_ws,
+                     qd.d_centres, qd.n, qd.d_hist, ((ExpQueryArgs*)(tb + h.off_q))[q], nb);
+      qpre[q + 1] = qpre[q] + (qd.n > 0 ? nb : 0);
+      continue;
+    }
     ScaleParams sp;
     scale_params(&fc, qd.scale_idx, sp);
     if (sep) {
@@ -481,7 +571,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     const swih_config fc = frame_config(cfg, fd);
     if (md.scale_idx < 0 || md.scale_idx >= fc.nscales) return SWIH_ERR_INVALID;
     if ((md.d_template == nullptr) == (md.d_template_raw == nullptr)) return SWIH_ERR_INVALID;
-    if ((gauss || sep) && md.d_template_raw) return SWIH_ERR_UNSUPPORTED;
+    if (real_kind(cfg->kernel) && md.d_template_raw) return SWIH_ERR_UNSUPPORTED;
     const swih_rect r = md.centres;
     const bool empty = r.x1 < r.x0 || r.y1 < r.y0;
     if (!empty) {
@@ -489,6 +579,17 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
       const int32_t rx = (sc.w - 1) / 2, ry = (sc.h - 1) / 2;
       if (r.x0 < rx || r.y0 < ry || r.x1 > fd.width - 1 - rx || r.y1 > fd.height - 1 - ry || !md.d_map)
         return SWIH_ERR_INVALID;
+    }
+    if (ex) {
+      int32_t nb = 0;
+      if (!empty) {
+        ExpScale es;
+        exp_scale(fc.scales[md.scale_idx].w, fc.scales[md.scale_idx].h, es);
+        exp_match_args(layouts[md.frame], es, md.scale_idx, (const char*)fd.d_ws, md.d_template,
+                       r.x0, r.y0, r.x1, r.y1, md.d_map, ((ExpMatchArgs*)(tb + h.off_m))[m], nb);
+      }
+      mpre[m + 1] = mpre[m] + nb;
+      continue;
     }
     ScaleParams sp;
     scale_params(&fc, md.scale_idx, sp);
@@ -532,6 +633,12 @@ int swih_build_batch(const void* h_table, const void* d_table, void* stream) {
                ? SWIH_OK
                : SWIH_ERR_HIP;
   }
+  if (h->kind == SWIH_EXPONENTIAL)
+    return exp_launch_build_batch((const ExpBuildArgs*)(db + h->off_units),
+                                  (const int32_t*)(db + h->off_uprefix), h->nunits, h->total,
+                                  kBatchGrid, (hipStream_t)stream) == hipSuccess
+               ? SWIH_OK
+               : SWIH_ERR_HIP;
   return launch_build_batch(h->kind, h->nt, (const BuildArgs*)(db + h->off_units),
                             (const int32_t*)(db + h->off_uprefix), h->nunits, h->total, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess
@@ -549,6 +656,12 @@ int swih_query_batch(const void* h_table, const void* d_table, void* stream) {
                                   kBatchGrid, (hipStream_t)stream) == hipSuccess
                ? SWIH_OK
                : SWIH_ERR_HIP;
+  if (h->kind == SWIH_EXPONENTIAL)
+    return exp_launch_query_batch((const ExpQueryArgs*)(db + h->off_q),
+                                  (const int32_t*)(db + h->off_qprefix), h->nq, h->ql.blocks,
+                                  kBatchGrid, (hipStream_t)stream) == hipSuccess
+               ? SWIH_OK
+               : SWIH_ERR_HIP;
   return launch_query_batch(h->kind, h->nt, (const QueryArgs*)(db + h->off_q),
                             (const int32_t*)(db + h->off_qprefix), h->nq, h->ql, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess
@@ -562,6 +675,12 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream) {
   const char* db = (const char*)d_table;
   if (h->kind == SWIH_GAUSSIAN_SEP)
     return sep_launch_match_batch(h->nt, h->nbins, (const SepMatchArgs*)(db + h->off_m),
+                                  (const int32_t*)(db + h->off_mprefix), h->nm, h->ml.blocks,
+                                  kBatchGrid, (hipStream_t)stream) == hipSuccess
+               ? SWIH_OK
+               : SWIH_ERR_HIP;
+  if (h->kind == SWIH_EXPONENTIAL)
+    return exp_launch_match_batch((const ExpMatchArgs*)(db + h->off_m),
                                   (const int32_t*)(db + h->off_mprefix), h->nm, h->ml.blocks,
                                   kBatchGrid, (hipStream_t)stream) == hipSuccess
                ? SWIH_OK

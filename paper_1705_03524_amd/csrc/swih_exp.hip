@@ -1,0 +1,489 @@
+// Exponential (Laplacian) spatial kernel, k(dx, dy) = exp(-|dx| / tx - |dy| / ty)
+// (kernel SWIH_EXPONENTIAL).
+//
+// Over each of the four disjoint quadrants of a window (Sec. 2.1) the weight
+// is a product of two exponentials that grow toward the window centre, so a
+// quadrant is one box of an integral histogram weighted by exp(+x/tx)exp(+y/ty)
+// in that quadrant's direction, translated to the centre by a constant factor:
+// the four direction-weighted integral histograms of Sec. 2.1, one per
+// quadrant.  Direction d = (mx, my) = (d & 1, d >> 1) is built in mirrored
+// coordinates x' = mx ? W - 1 - x : x, y' = my ? H - 1 - y : y, in which every
+// direction is "weights growing toward +x', +y'".
+//
+// A prefix of exp(x / t) leaves every float format within a few hundred
+// pixels, so each plane holds the prefix rescaled to its own corner,
+//   E(X, Y) = sum_{x < X, y < Y} [Q(f) = b] qx^(X - x) qy^(Y - y),   q = exp(-1 / t),
+// a sum of positive terms bounded by 1 / ((1 - qx)(1 - qy)) at any image size.
+// The window box of a quadrant with mirrored centre (cx, cy) is
+//   sum_corners +- qx^(cx - X) qy^(cy - Y) E(X, Y),
+// where the factors are exp(1/t) (near corner of the centre's own quadrant),
+// 1 (near corner of the opposite one) or exp(-r/t) (far corner).  E obeys
+//   E(X, Y + 1) = qy (E(X, Y) + R(X, Y)),   R(X, y) = sum_{x < X} [Q = b] qx^(X - x),
+// which the build runs down each 64-column tile of a 64-row band in double,
+// with three carries made exactly like the integer kernels' (aggregate, scan,
+// emit): the band-top column values, the row values at the tile's left edge
+// and the tile-origin values E(64 tx, 64 ty), each a chain with the decay of
+// one tile or band.  The planes are stored as float (relative error 2^-24).
+#include <math.h>
+#include <string.h>
+
+#include "swih_internal.h"
+#include "wave64.h"
+
+namespace swih {
+namespace {
+
+constexpr int WG = 256;
+constexpr int WPB = WG / 64;
+constexpr int TY = 64;  // band height of the exponential build
+
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ long exp_wave(int vb) {
+  return (long)vb * WPB + (long)rfl((int)(threadIdx.x >> 6));
+}
+
+// Leaky inclusive scan over the 64 lanes, s_l = sum_{k <= l} g^(l - k) v_k,
+// with g = exp(-step): the DPP steps of wave_incl_scan, each source scaled by
+// g to the power of the lane distance it spans (uniform for the row_shr
+// steps, per lane for the two broadcasts).
+struct Leaky {
+  double g1, g2, g4, g8;
+  double f15;  // g^((l & 15) + 1): distance from lane 15 (47) to lane l of row 1 (3)
+  double f31;  // g^(l - 31) for rows 2 and 3
+};
+
+__device__ __forceinline__ Leaky make_leaky(double step) {
+  const int l = lane_id();
+  Leaky L;
+  L.g1 = exp(-step);
+  L.g2 = exp(-2.0 * step);
+  L.g4 = exp(-4.0 * step);
+  L.g8 = exp(-8.0 * step);
+  L.f15 = exp(-step * (double)((l & 15) + 1));
+  L.f31 = l >= 32 ? exp(-step * (double)(l - 31)) : 0.0;
+  return L;
+}
+
+__device__ __forceinline__ double leaky_scan(double v, const Leaky& L) {
+  v = fma(L.g1, dpp_f64<0x111>(v), v);       // row_shr:1
+  v = fma(L.g2, dpp_f64<0x112>(v), v);       // row_shr:2
+  v = fma(L.g4, dpp_f64<0x114>(v), v);       // row_shr:4
+  v = fma(L.g8, dpp_f64<0x118>(v), v);       // row_shr:8
+  v = fma(L.f15, dpp_f64<0x142, 0xa>(v), v); // row_bcast:15 into rows 1 and 3
+  v = fma(L.f31, dpp_f64<0x143, 0xc>(v), v); // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+struct ExpTile {
+  int d, b, tx, ty, y0, nrows;
+};
+
+// Wave -> (direction, bin, band, tile); tile fastest.
+__device__ __forceinline__ bool exp_tile(const SwihGeom& g, long wid, ExpTile& t) {
+  const long nw = 4L * g.B * g.NTY * g.NTX;
+  if (wid >= nw) return false;
+  t.tx = (int)(wid % g.NTX);
+  long r = wid / g.NTX;
+  t.ty = (int)(r % g.NTY);
+  r /= g.NTY;
+  t.b = (int)(r % g.B);
+  t.d = (int)(r / g.B);
+  t.y0 = t.ty * TY;
+  t.nrows = min(TY, g.H - t.y0);
+  return true;
+}
+
+// Bit k = [Q(f) = b] at mirrored column 64 tx + lane, mirrored row y0 + k
+// (k < nrows); zero for columns past the image.
+__device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const ExpTile& t) {
+  const SwihGeom& g = a.g;
+  const int xm = t.tx * 64 + lane_id();
+  const bool valid = xm < g.W;
+  const int xo = valid ? ((t.d & 1) ? g.W - 1 - xm : xm) : 0;
+  const bool my = (t.d & 2) != 0;
+  const long step = my ? -(long)a.ipitch : (long)a.ipitch;
+  const uint8_t* col = a.img + (long)(my ? g.H - 1 - t.y0 : t.y0) * a.ipitch + xo;
+  const int B = g.B, b = t.b;
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int kk = k < t.nrows ? k : t.nrows - 1;
+    lo |= (uint32_t)((((int)col[kk * step] * B) >> 8) == b) << k;
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int kk = k + 32 < t.nrows ? k + 32 : t.nrows - 1;
+    hi |= (uint32_t)((((int)col[kk * step] * B) >> 8) == b) << k;
+  }
+  uint64_t m = ((uint64_t)hi << 32) | lo;
+  if (t.nrows < 64) m &= ((uint64_t)1 << t.nrows) - 1;
+  return valid ? m : 0;
+}
+
+__device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)((m >> k) & 1); }
+
+// ---------------------------------------------------------------- build
+// Aggregate: per (direction, bin, band, tile) wave
+//   z  [X]  = sum_{X0 <= x < X, y in band} [Q = b] qx^(X - x) qy^(Y0 + 64 - y)
+//   CT      = the same at X = X0 + 64 (the tile total)
+//   T  [y]  = sum_{x in tile} [Q = b] qx^(X0 + 64 - x)      (lane = row)
+__device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  ExpTile t;
+  if (!exp_tile(g, exp_wave(vb), t)) return;
+  const int lane = lane_id();
+  const long NXP = (long)g.NTX * 64;
+  const uint64_t mask = exp_band_mask(a, t);
+  const double qy = exp(-a.ity), qx = exp(-a.itx);
+  double c = 0.0;  // this column's band sum, relative to row Y0 + 64
+#pragma unroll
+  for (int k = 0; k < 64; ++k) c = (c + mbit(mask, k)) * qy;
+  const double zl = qx * leaky_scan(c, make_leaky(a.itx));
+  const long db = (long)t.d * g.B + t.b;
+  a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane] = zl;
+  if (lane == 63) a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx] = zl;
+  // row sums across the tile, transposed: lane k reads bit k of every column's mask
+  const uint32_t mlo = (uint32_t)mask, mhi = (uint32_t)(mask >> 32);
+  double tr = 0.0, wgt = qx;  // qx^(64 - l) for l = 63, 62, ..., 0
+#pragma unroll 8
+  for (int l = 63; l >= 0; --l) {
+    const uint64_t ml = ((uint64_t)readlane(mhi, l) << 32) | readlane(mlo, l);
+    tr = fma(mbit(ml, lane), wgt, tr);
+    wgt *= qx;
+  }
+  if (lane < t.nrows) a.T[(db * g.NTX + t.tx) * g.H + t.y0 + lane] = tr;
+}
+
+// Scan: three independent chains.
+//   role 1, one thread per (direction, bin, column): z over bands becomes the
+//     band-top value Zc (exclusive), Zc' = qy^64 Zc + z;
+//   role 2, one thread per (direction, bin, row): T over tiles becomes the row
+//     value at the tile's left edge (exclusive), C' = qx^64 C + T;
+//   role 3, one wave per (direction, bin): CT becomes E(64 tx, 64 ty), with an
+//     exclusive leaky scan over the tiles of each band (decay qx^64).
+__device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const long NXP = (long)g.NTX * 64;
+  if (vb < a.nb1) {
+    const long t = (long)vb * WG + threadIdx.x;
+    if (t >= 4L * g.B * NXP) return;
+    const long db = t / NXP, col = t - db * NXP;
+    const double qT = exp(-a.ity * TY);
+    double* z = a.z + db * g.NTY * NXP + col;
+    double carry = 0.0;
+    for (int ty = 0; ty < g.NTY; ++ty) {
+      const double v = z[ty * NXP];
+      z[ty * NXP] = carry;
+      carry = fma(qT, carry, v);
+    }
+    return;
+  }
+  vb -= a.nb1;
+  if (vb < a.nb2) {
+    const long t = (long)vb * WG + threadIdx.x;
+    if (t >= 4L * g.B * g.H) return;
+    const long db = t / g.H;
+    const int y = (int)(t - db * g.H);
+    const double qT = exp(-a.itx * 64.0);
+    double* T = a.T + db * g.NTX * g.H + y;
+    double carry = 0.0;
+    for (int tx = 0; tx < g.NTX; ++tx) {
+      const double v = T[(long)tx * g.H];
+      T[(long)tx * g.H] = carry;
+      carry = fma(qT, carry, v);
+    }
+    return;
+  }
+  vb -= a.nb2;
+  const long wid = exp_wave(vb);
+  if (wid >= 4L * g.B) return;
+  const int lane = lane_id();
+  double* CT = a.CT + wid * g.NTY * g.NTX;
+  const double qyT = exp(-a.ity * TY);
+  const double gx = a.itx * 64.0;
+  const Leaky Lt = make_leaky(gx);
+  const double up = exp(-gx * (double)(lane + 1));  // decay from tile 63 of the first chunk
+  const bool v0 = lane < g.NTX, v1 = 64 + lane < g.NTX;  // NTX <= 128
+  double k0 = 0.0, k1 = 0.0;
+  for (int ty = 0; ty < g.NTY; ++ty) {
+    double* row = CT + (long)ty * g.NTX;
+    const double t0 = v0 ? row[lane] : 0.0;
+    const double t1 = v1 ? row[64 + lane] : 0.0;
+    if (v0) row[lane] = k0;
+    if (v1) row[64 + lane] = k1;
+    const double s0 = leaky_scan(t0, Lt);
+    const double last0 = readlane(s0, 63);
+    const double s1 = fma(up, last0, leaky_scan(t1, Lt));
+    const double p0 = __shfl_up(s0, 1, 64);
+    const double p1 = __shfl_up(s1, 1, 64);
+    const double a0 = lane == 0 ? 0.0 : p0;
+    const double a1 = lane == 0 ? last0 : p1;
+    k0 = fma(qyT, k0, a0);
+    k1 = fma(qyT, k1, a1);
+  }
+}
+
+// Emit: per (direction, bin, band, tile) wave, rows top to bottom,
+//   E(X, Y0) = Zc(X) + qx^(X - X0) E(X0, Y0),
+//   E(X, y + 1) = qy (E(X, y) + qx s_l + qx^(l + 1) C(y)),
+// s the leaky scan of the row's [Q = b] across the tile and C(y) the row value
+// at the tile's left edge.  Every lane stores, so a wave writes whole 256-byte
+// rows (lanes past the last column hold values never read).
+__device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  ExpTile t;
+  if (!exp_tile(g, exp_wave(vb), t)) return;
+  const int lane = lane_id();
+  const long NXP = (long)g.NTX * 64;
+  const uint64_t mask = exp_band_mask(a, t);
+  const double qx = exp(-a.itx), qy = exp(-a.ity);
+  const double pw = exp(-a.itx * (double)(lane + 1));
+  const Leaky Lx = make_leaky(a.itx);
+  const long db = (long)t.d * g.B + t.b;
+  const double K = a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx];
+  double e = fma(pw, K, a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane]);
+  const double creg = a.T[(db * g.NTX + t.tx) * g.H + t.y0 + (lane < t.nrows ? lane : 0)];
+  float* P = a.planes + swih_base(g, t.d, t.b) + (long)t.tx * g.tile_stride + lane;
+  if (t.ty == 0) P[0] = 0.0f;
+  for (int k = 0; k < t.nrows; ++k) {
+    const double s = leaky_scan(mbit(mask, k), Lx);
+    const double R = fma(qx, s, pw * readlane(creg, k));
+    e = qy * (e + R);
+    P[(long)(t.y0 + k + 1) * g.row_stride] = (float)e;
+  }
+}
+
+// ---------------------------------------------------------------- lookups
+__device__ __forceinline__ double e_at(const SwihGeom& g, const float* __restrict__ pl, int64_t base,
+                                       int Y, int X) {
+  const int Xc = X > 0 ? X : 1;
+  const float v = pl[base + (int64_t)Y * g.row_stride + swih_xoff(g, Xc)];
+  return X > 0 ? (double)v : 0.0;
+}
+
+// H_b at centre (xc, yc): the four quadrant boxes, each from its direction's plane.
+__device__ __forceinline__ double exp_hist(const SwihGeom& g, const ExpScale& s,
+                                           const float* __restrict__ pl, int b, int xc, int yc) {
+  // corners (far, near) and their factors per side
+  const int XL0 = xc - s.rx, XL1 = xc + 1;
+  const int XR0 = g.W - 1 - xc - s.rx, XR1 = g.W - 1 - xc;
+  const int YT0 = yc - s.ry, YT1 = yc + 1;
+  const int YB0 = g.H - 1 - yc - s.ry, YB1 = g.H - 1 - yc;
+  double h = 0.0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const bool mx = d & 1, my = d & 2;
+    const int X0 = mx ? XR0 : XL0, X1 = mx ? XR1 : XL1;
+    const int Y0 = my ? YB0 : YT0, Y1 = my ? YB1 : YT1;
+    const double f0x = s.fxlo, f1x = mx ? 1.0 : s.fxin;
+    const double f0y = s.fylo, f1y = my ? 1.0 : s.fyin;
+    const int64_t base = swih_base(g, d, b);
+    const double e11 = e_at(g, pl, base, Y1, X1), e01 = e_at(g, pl, base, Y1, X0);
+    const double e10 = e_at(g, pl, base, Y0, X1), e00 = e_at(g, pl, base, Y0, X0);
+    h += f1y * (f1x * e11 - f0x * e01) - f0y * (f1x * e10 - f0x * e00);
+  }
+  return h;
+}
+
+// One thread per (centre, bin).
+__device__ __forceinline__ void exp_query(const ExpQueryArgs& a, int vb) {
+  const long t = (long)vb * WG + threadIdx.x;
+  const int B = a.g.B;
+  if (t >= (long)a.n * B) return;
+  const long i = t / B;
+  const int b = (int)(t - i * B);
+  // centres outside the valid range are clamped into it
+  const int xc = min(max(a.centres[2 * i], a.s.rx), a.g.W - 1 - a.s.rx);
+  const int yc = min(max(a.centres[2 * i + 1], a.s.ry), a.g.H - 1 - a.s.ry);
+  const double h = exp_hist(a.g, a.s, a.planes, b, xc, yc);
+  a.hist[t] = (float)(h * a.s.inv_mass);
+}
+
+// One thread per centre: sum_b sqrt(p_b t_b) in double, bins in order.  A wave
+// covers 64 consecutive centres of one row.
+__device__ __forceinline__ void exp_match(const ExpMatchArgs& a, int vb) {
+  const long w = exp_wave(vb);
+  const int nx = a.x1 - a.x0 + 1, ny = a.y1 - a.y0 + 1;
+  const int row = (int)(w / a.nbx), wc = (int)(w - (long)row * a.nbx);
+  if (row >= ny) return;
+  const int xc = a.x0 + wc * 64 + lane_id();
+  if (xc > a.x1) return;
+  const int yc = a.y0 + row;
+  double acc = 0.0;
+  for (int b = 0; b < a.g.B; ++b) {
+    const double p = exp_hist(a.g, a.s, a.planes, b, xc, yc) * a.s.inv_mass;
+    acc += sqrt(fmax(p, 0.0) * fmax((double)a.tmpl[b], 0.0));
+  }
+  a.map[(long)row * nx + (xc - a.x0)] = (float)acc;
+}
+
+}  // namespace
+
+// Single launch: one block per virtual block.  Batched: a grid-stride loop
+// over every item's virtual blocks, each block finding its item by binary
+// search over the prefix of block counts.
+template <class A, void (*BODY)(const A&, int)>
+__global__ __launch_bounds__(WG) void k_exp_one(A a) {
+  BODY(a, (int)blockIdx.x);
+}
+
+template <class A, void (*BODY)(const A&, int)>
+__global__ __launch_bounds__(WG) void k_exp_many(const A* __restrict__ items,
+                                                 const int32_t* __restrict__ prefix, int n) {
+  const int total = prefix[n];
+  for (int vb = (int)blockIdx.x; vb < total; vb += (int)gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= vb) lo = mid; else hi = mid - 1;
+    }
+    BODY(items[lo], vb - prefix[lo]);
+  }
+}
+
+namespace {
+
+template <class A, void (*BODY)(const A&, int)>
+hipError_t one(const A& a, int32_t nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_exp_one<A, BODY>), dim3((unsigned)nb), dim3(WG), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class A, void (*BODY)(const A&, int)>
+hipError_t many(const A* items, const int32_t* prefix, int n, int32_t total, int grid,
+                hipStream_t s) {
+  if (n <= 0 || total <= 0) return hipSuccess;
+  const unsigned gb = (unsigned)(total < grid ? total : grid);
+  hipLaunchKernelGGL((k_exp_many<A, BODY>), dim3(gb), dim3(WG), 0, s, items, prefix, n);
+  return hipGetLastError();
+}
+
+inline int32_t blocks_of_waves(long w) { return (int32_t)((w + WPB - 1) / WPB); }
+inline int32_t blocks_of_threads(long n) { return (int32_t)((n + WG - 1) / WG); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+void exp_scale(int32_t w, int32_t h, ExpScale& s) {
+  memset(&s, 0, sizeof(s));
+  s.w = w;
+  s.h = h;
+  s.rx = (w - 1) / 2;
+  s.ry = (h - 1) / 2;
+  const double tx = w / 4.0, ty = h / 4.0;
+  s.itx = 1.0 / tx;
+  s.ity = 1.0 / ty;
+  s.fxlo = exp(-s.rx / tx);
+  s.fylo = exp(-s.ry / ty);
+  s.fxin = exp(1.0 / tx);
+  s.fyin = exp(1.0 / ty);
+  double sx = 0.0, sy = 0.0;  // axis masses, summed outward from the rim
+  for (int d = s.rx; d >= 1; --d) sx += 2.0 * exp(-d / tx);
+  for (int d = s.ry; d >= 1; --d) sy += 2.0 * exp(-d / ty);
+  s.mass = (1.0 + sx) * (1.0 + sy);
+  s.inv_mass = 1.0 / s.mass;
+}
+
+void exp_build_args(const SwihLayout& L, const ExpScale& s, int set, const uint8_t* img,
+                    int32_t img_pitch, char* ws, ExpBuildArgs& a, int32_t (&nb)[4]) {
+  const SwihGeom& g = L.g;
+  memset(&a, 0, sizeof(a));
+  a.g = g;
+  a.img = img;
+  a.ipitch = img_pitch;
+  char* sb = ws + (size_t)set * L.set_bytes;
+  a.planes = (float*)(sb + L.off_planes);
+  a.z = (double*)(sb + L.off_z);
+  a.T = (double*)(sb + L.off_T);
+  a.CT = (double*)(sb + L.off_CT);
+  a.itx = s.itx;
+  a.ity = s.ity;
+  const long waves = 4L * g.B * g.NTY * g.NTX;
+  a.nb1 = blocks_of_threads(4L * g.B * g.NTX * 64);
+  a.nb2 = blocks_of_threads(4L * g.B * g.H);
+  nb[0] = 0;
+  nb[1] = blocks_of_waves(waves);
+  nb[2] = a.nb1 + a.nb2 + blocks_of_waves(4L * g.B);
+  nb[3] = blocks_of_waves(waves);
+}
+
+void exp_query_args(const SwihLayout& L, const ExpScale& s, int set, const char* ws,
+                    const int32_t* centres, int32_t n, float* hist, ExpQueryArgs& a, int32_t& nb) {
+  memset(&a, 0, sizeof(a));
+  a.g = L.g;
+  a.s = s;
+  a.planes = (const float*)(ws + (size_t)set * L.set_bytes + L.off_planes);
+  a.centres = centres;
+  a.n = n;
+  a.hist = hist;
+  nb = blocks_of_threads((long)n * L.g.B);
+}
+
+void exp_match_args(const SwihLayout& L, const ExpScale& s, int set, const char* ws,
+                    const float* tmpl, int32_t x0, int32_t y0, int32_t x1, int32_t y1, float* map,
+                    ExpMatchArgs& a, int32_t& nb) {
+  memset(&a, 0, sizeof(a));
+  a.g = L.g;
+  a.s = s;
+  a.planes = (const float*)(ws + (size_t)set * L.set_bytes + L.off_planes);
+  a.tmpl = tmpl;
+  a.map = map;
+  a.x0 = x0;
+  a.y0 = y0;
+  a.x1 = x1;
+  a.y1 = y1;
+  a.nbx = (x1 - x0 + 1 + 63) / 64;
+  nb = blocks_of_waves((long)a.nbx * (y1 - y0 + 1));
+}
+
+namespace {
+constexpr void (*agg_body)(const ExpBuildArgs&, int) = exp_aggregate;
+constexpr void (*scan_body)(const ExpBuildArgs&, int) = exp_scan;
+constexpr void (*emit_body)(const ExpBuildArgs&, int) = exp_emit;
+constexpr void (*query_body)(const ExpQueryArgs&, int) = exp_query;
+constexpr void (*match_body)(const ExpMatchArgs&, int) = exp_match;
+}  // namespace
+
+hipError_t exp_launch_build(const ExpBuildArgs& a, const int32_t (&nb)[4], int phases,
+                            hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (phases & 1) {
+    e = one<ExpBuildArgs, agg_body>(a, nb[1], s);
+    if (e == hipSuccess) e = one<ExpBuildArgs, scan_body>(a, nb[2], s);
+  }
+  if (e == hipSuccess && (phases & 2)) e = one<ExpBuildArgs, emit_body>(a, nb[3], s);
+  return e;
+}
+
+hipError_t exp_launch_query(const ExpQueryArgs& a, int32_t nb, hipStream_t s) {
+  return one<ExpQueryArgs, query_body>(a, nb, s);
+}
+
+hipError_t exp_launch_match(const ExpMatchArgs& a, int32_t nb, hipStream_t s) {
+  return one<ExpMatchArgs, match_body>(a, nb, s);
+}
+
+hipError_t exp_launch_build_batch(const ExpBuildArgs* units, const int32_t* prefix, int nunits,
+                                  const int32_t (&total)[4], int grid, hipStream_t s) {
+  if (nunits <= 0) return hipSuccess;
+  const int32_t* pre[4];
+  for (int k = 0; k < 4; ++k) pre[k] = prefix + (size_t)k * (nunits + 1);
+  hipError_t e = many<ExpBuildArgs, agg_body>(units, pre[1], nunits, total[1], grid, s);
+  if (e == hipSuccess) e = many<ExpBuildArgs, scan_body>(units, pre[2], nunits, total[2], grid, s);
+  if (e == hipSuccess) e = many<ExpBuildArgs, emit_body>(units, pre[3], nunits, total[3], grid, s);
+  return e;
+}
+
+hipError_t exp_launch_query_batch(const ExpQueryArgs* items, const int32_t* prefix, int n,
+                                  int32_t total, int grid, hipStream_t s) {
+  return many<ExpQueryArgs, query_body>(items, prefix, n, total, grid, s);
+}
+
+hipError_t exp_launch_match_batch(const ExpMatchArgs* items, const int32_t* prefix, int n,
+                                  int32_t total, int grid, hipStream_t s) {
+  return many<ExpMatchArgs, match_body>(items, prefix, n, total, grid, s);
+}
+
+}  // namespace swih

@@ -228,4 +228,76 @@ hipError_t sep_launch_match_batch(int nt, int nbins, const SepMatchArgs* items,
                                   const int32_t* prefix, int n, int32_t total, int grid,
                                   hipStream_t s);
 
+// ------------------------------------------------------------------------
+// Exponential (Laplacian) kernel (SWIH_EXPONENTIAL), swih_exp.hip.
+//
+// k(dx, dy) = exp(-|dx| / tx - |dy| / ty), tx = w / 4, ty = h / 4.  Four
+// direction-weighted planes per bin (one per window quadrant, Sec. 2.1), each
+// stored rescaled to its own corner so that it stays bounded; one plane set
+// per scale.  The planes use the tile-major layout of SwihGeom with nP = 4
+// (direction d = mirrored x (bit 0), mirrored y (bit 1)) and ppg = 1.
+
+struct ExpScale {
+  int32_t w, h, rx, ry;
+  double itx, ity;     // 1 / tx, 1 / ty
+  double fxlo, fylo;   // exp(-rx / tx), exp(-ry / ty): far corners
+  double fxin, fyin;   // exp(1 / tx), exp(1 / ty): near corner of the centre's quadrant
+  double mass, inv_mass;
+};
+
+void exp_scale(int32_t w, int32_t h, ExpScale& s);
+
+struct ExpBuildArgs {
+  SwihGeom g;
+  const uint8_t* img;
+  int32_t ipitch;
+  int32_t nb1, nb2;    // scan: blocks of the band-chain and row-chain roles
+  float* planes;
+  double* z;           // [4 B][NTY][NTX 64] band sums -> band-top values
+  double* T;           // [4 B][NTX][H]      row sums  -> left-edge row values
+  double* CT;          // [4 B][NTY][NTX]    tile sums -> tile-origin values
+  double itx, ity;
+};
+
+struct ExpQueryArgs {
+  SwihGeom g;
+  ExpScale s;
+  const float* planes;
+  const int32_t* centres;  // [n][2]
+  int32_t n;
+  float* hist;             // [n][B]
+};
+
+struct ExpMatchArgs {
+  SwihGeom g;
+  ExpScale s;
+  const float* planes;
+  const float* tmpl;       // [B] normalised template
+  float* map;
+  int32_t x0, y0, x1, y1;  // inclusive centre rectangle
+  int32_t nbx;             // waves across the rectangle (64 centres each)
+};
+
+// nb: blocks of the build stages (0 = none, aggregate, scan, emit).
+void exp_build_args(const SwihLayout& L, const ExpScale& s, int set, const uint8_t* img,
+                    int32_t img_pitch, char* ws, ExpBuildArgs& a, int32_t (&nb)[4]);
+void exp_query_args(const SwihLayout& L, const ExpScale& s, int set, const char* ws,
+                    const int32_t* centres, int32_t n, float* hist, ExpQueryArgs& a, int32_t& nb);
+void exp_match_args(const SwihLayout& L, const ExpScale& s, int set, const char* ws,
+                    const float* tmpl, int32_t x0, int32_t y0, int32_t x1, int32_t y1, float* map,
+                    ExpMatchArgs& a, int32_t& nb);
+
+// phases: bit 1 = carries (aggregate + scan), bit 2 = planes (emit).
+hipError_t exp_launch_build(const ExpBuildArgs& a, const int32_t (&nb)[4], int phases,
+                            hipStream_t s);
+hipError_t exp_launch_query(const ExpQueryArgs& a, int32_t nb, hipStream_t s);
+hipError_t exp_launch_match(const ExpMatchArgs& a, int32_t nb, hipStream_t s);
+hipError_t exp_launch_build_batch(const ExpBuildArgs* units, const int32_t* prefix, int nunits,
+                                  const int32_t (&total)[4], int grid, hipStream_t s);
+hipError_t exp_launch_query_batch(const ExpQueryArgs* items, const int32_t* prefix, int n,
+                                  int32_t total, int grid, hipStream_t s);
+hipError_t exp_launch_match_batch(const ExpMatchArgs* items, const int32_t* prefix, int n,
+                                  int32_t total, int grid, hipStream_t s);
+
+
 }  // namespace swih

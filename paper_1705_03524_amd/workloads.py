@@ -61,7 +61,7 @@ def tracking_units(cfg: S.Config, frames, device="cuda"):
     """Units and jobs for ``synth.batch_frames``-style frames (dicts with
     ``image`` and ``rois`` of ``centre``, ``scales``, ``search``)."""
     units = []
-    integer = cfg.kernel not in S.SERIES_KINDS
+    integer = cfg.kernel not in S.REAL_KINDS
     for fr in frames:
         img = torch.from_numpy(fr["image"]).to(device)
         H, W = fr["image"].shape
@@ -125,7 +125,7 @@ class BatchedRunner:
             groups.append(cur)
         self.ws = torch.empty(max(ALIGN, max(sum(unit_bytes(cfg, u) for u in g) for g in groups)),
                               dtype=torch.uint8, device=device)
-        integer = cfg.kernel not in S.SERIES_KINDS
+        integer = cfg.kernel not in S.REAL_KINDS
         self.batches = []
         for g in groups:
             frames, queries, matches = [], [], []
@@ -178,7 +178,7 @@ class PerFrameRunner:
         self.cfg, self.units = cfg, units
         self.ws = torch.empty(max(ALIGN, max(unit_bytes(cfg, u) for u in units)), dtype=torch.uint8,
                               device=device)
-        self.integer = cfg.kernel not in S.SERIES_KINDS
+        self.integer = cfg.kernel not in S.REAL_KINDS
         self.plans = []
         for u in units:
             uc = unit_config(cfg, u)
@@ -206,7 +206,8 @@ def total_windows(units) -> int:
 
 def plane_bytes(cfg: S.Config, units) -> int:
     """Algorithmic bytes the builds write: 4 T B (H+1)(W+1) per plane set, or for
-    the separable Gaussian 4 B H (W - w + 1) of row results per scale."""
+    the separable Gaussian 4 B H (W - w + 1) of row results per scale.  The
+    Gaussian and the exponential keep one plane set per scale."""
     K = cfg.gauss_terms or 4
     tot = 0
     for u in units:
@@ -214,8 +215,8 @@ def plane_bytes(cfg: S.Config, units) -> int:
         if cfg.kernel == S.GAUSSIAN_SEP:
             tot += sum(4 * cfg.nbins * H * (W - w + 1) for w, _ in u.scales)
             continue
-        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5}.get(cfg.kernel, (2 * K + 1) ** 2)
-        nsets = len(u.scales) if cfg.kernel == S.GAUSSIAN else 1
+        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4}.get(cfg.kernel, (2 * K + 1) ** 2)
+        nsets = len(u.scales) if cfg.kernel in (S.GAUSSIAN, S.EXPONENTIAL) else 1
         tot += nsets * 4 * T * cfg.nbins * (H + 1) * (W + 1)
     return tot
 

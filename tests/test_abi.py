@@ -70,10 +70,38 @@ def test_separable_workspace_and_validation():
     for c in (swih.Config(8, swih.GAUSSIAN_SEP, [(3, 3)], gauss_terms=9),
               swih.Config(8, swih.GAUSSIAN_SEP, [(3, 3)], gauss_terms=-1),
               swih.Config(8, swih.GAUSSIAN_SEP, [(2, 3)]),
-              swih.Config(8, 5, [(3, 3)])):
+              swih.Config(8, 6, [(3, 3)])):
         with pytest.raises(swih.SwihError) as e:
             swih.workspace_bytes(c, 64, 64)
         assert e.value.status == _swih.ERR_INVALID
+
+
+def test_exponential_workspace_and_host_checks():
+    # per scale: 4 direction planes per bin (tile-major float) + double carries
+    import ctypes as C
+
+    def a256(v):
+        return (v + 255) // 256 * 256
+    H, W, B = 300, 200, 16
+    NTX, NTY = (W + 63) // 64, (H + 63) // 64
+    per_set = (a256(4 * B * NTX * (H + 1) * 64 * 4) + a256(4 * B * NTY * NTX * 64 * 8)
+               + a256(4 * B * NTX * H * 8) + a256(4 * B * NTY * NTX * 8))
+    for scales in ([(31, 31)], [(31, 31), (9, 21), (101, 1)]):
+        assert swih.workspace_bytes(swih.Config(B, swih.EXPONENTIAL, scales), H, W) == len(scales) * per_set
+    lib = swih.load()
+    e = swih.Config(8, swih.EXPONENTIAL, [(5, 5)])
+    st = lib.swih_query(C.byref(e.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, C.c_void_p(256), 4,
+                        None, C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # no exact raw histograms
+    r = _swih._Rect(2, 2, 10, 10)
+    st = lib.swih_match(C.byref(e.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, None, C.c_void_p(256), r,
+                        C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # raw template
+    st = lib.swih_build_planes(C.byref(e.c()), C.c_void_p(256), 64, 64, 64, 1, C.c_void_p(256),
+                               1 << 30, None)
+    assert st == _swih.ERR_INVALID          # one set per scale: only set 0 exists
+    st = lib.swih_build(C.byref(e.c()), C.c_void_p(256), 64, 64, 64, C.c_void_p(256), 16, None)
+    assert st == _swih.ERR_WORKSPACE
 
 
 def test_separable_host_checks():
