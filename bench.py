@@ -363,37 +363,46 @@ def main():
     for k in KERNELS:
         per["build_" + k] = per["carries_" + k] + per["planes_" + k]
 
-    # The same Gaussian in separable form (row pass, then a column walk over
-    # the row results): reported beside the step, not part of it.
-    sp = Plan(swih.Config(NBINS, "gaussian_sep", [(WIN, WIN)]), H, W)
-    smap = torch.empty_like(maps["gaussian"])
-    stm = torch.empty(NBINS, dtype=torch.float32, device="cuda")
+    # Kernels reported beside the step, not part of it: the same Gaussian in
+    # separable form (row pass, then a column walk over the row results) and
+    # the exponential kernel (four direction-weighted planes per bin).
+    def side_kind(kname, timed):
+        sp = Plan(swih.Config(NBINS, kname, [(WIN, WIN)]), H, W)
+        smap = torch.empty_like(maps["gaussian"])
+        stm = torch.empty(NBINS, dtype=torch.float32, device="cuda")
 
-    def sep_phase(name):
-        if name in ("carries", "planes"):
-            swih.build_phase(sp.cfg, d_img, sp.ws, name, 0)
-        elif name == "query":
-            swih.query(sp.cfg, sp.ws, H, W, 0, d_tc, stm.view(1, NBINS), None)
-        else:
-            swih.match(sp.cfg, sp.ws, H, W, 0, sp.valid_rect(0), smap, template=stm)
+        def side_phase(name):
+            if name in ("carries", "planes"):
+                swih.build_phase(sp.cfg, d_img, sp.ws, name, 0)
+            elif name == "query":
+                swih.query(sp.cfg, sp.ws, H, W, 0, d_tc, stm.view(1, NBINS), None)
+            else:
+                swih.match(sp.cfg, sp.ws, H, W, 0, sp.valid_rect(0), smap, template=stm)
 
-    sep_ms = {}
-    for ph in PHASES:
-        sep_phase(ph)
-    torch.cuda.synchronize()
-    for ph in ("planes", "query", "match"):
-        g = capture(lambda: [sep_phase(ph) for _ in range(REP)])
-        g.replay()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(3):
-            g.replay()
-        b.record()
+        ms_ = {}
+        for ph in PHASES:
+            side_phase(ph)
         torch.cuda.synchronize()
-        sep_ms[ph] = a.elapsed_time(b) / (3 * REP)
-        del g
+        for ph in timed:
+            g = capture(lambda: [side_phase(ph) for _ in range(REP)])
+            g.replay()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            ms_[ph] = a.elapsed_time(b) / (3 * REP)
+            del g
+        return sp, smap, ms_
+
+    # (the separable form's carries phase launches nothing)
+    _, smap, sep_ms = side_kind("gaussian_sep", ("planes", "query", "match"))
     sep_total = sum(sep_ms.values())
     sep_diff = float((smap - maps["gaussian"]).abs().max())
+    ep, _, exp_ms = side_kind("exponential", PHASES)
+    exp_total = sum(exp_ms.values())
+    exp_build = exp_ms["carries"] + exp_ms["planes"]
 
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)
@@ -446,6 +455,10 @@ def main():
             "speedup_vs_2d_gaussian": (per["build_gaussian"] + per["query_gaussian"] +
                                        per["match_gaussian"]) / sep_total,
             "max_abs_map_diff_vs_2d": sep_diff},
+        "exponential": {
+            "ms": exp_ms, "ms_total": exp_total, "windows_per_s": nwin / (exp_total / 1e3),
+            "ih_build_gbs": (H * W + 4 * ep.nplanes * NBINS * (H + 1) * (W + 1)) / (exp_build / 1e3) / 1e9,
+            "planes_gbs": 4 * ep.nplanes * NBINS * (H + 1) * (W + 1) / (exp_ms["planes"] / 1e3) / 1e9},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img, tc, args.cpu_seconds)

@@ -43,8 +43,12 @@ __device__ __forceinline__ uint32_t poly_term(int i, uint32_t t) {
   return i == 0 ? 1u : (i == 1 ? t : t * t);
 }
 
+// [Q(v) = b] for 8-bit v: Q(v) = floor(v B / 256) = b exactly when
+// ceil(256 b / B) <= v < ceil(256 (b + 1) / B), one unsigned range test.
 __device__ __forceinline__ bool in_bin(uint32_t v, int B, int b) {
-  return ((v * (uint32_t)B) >> 8) == (uint32_t)b;
+  const uint32_t lo = (256u * (uint32_t)b + (uint32_t)B - 1) / (uint32_t)B;
+  const uint32_t hi = (256u * (uint32_t)(b + 1) + (uint32_t)B - 1) / (uint32_t)B;
+  return v - lo < hi - lo;
 }
 
 // Bit k = [pixel (x, y0 + k) falls in bin b] for the band's rows.  All the

@@ -46,11 +46,14 @@ __device__ __forceinline__ long exp_wave(int vb) {
 // Leaky inclusive scan over the 64 lanes, s_l = sum_{k <= l} g^(l - k) v_k,
 // with g = exp(-step): the DPP steps of wave_incl_scan, each source scaled by
 // g to the power of the lane distance it spans (uniform for the row_shr
-// steps, per lane for the two broadcasts).
+// steps, per lane for the two broadcasts).  Every DPP move writes all lanes
+// with bound_ctrl (a lane without a source reads 0), so no destination needs
+// clearing first; the broadcasts' factor is 0 on the rows they must not
+// change, whatever those rows read.
 struct Leaky {
   double g1, g2, g4, g8;
-  double f15;  // g^((l & 15) + 1): distance from lane 15 (47) to lane l of row 1 (3)
-  double f31;  // g^(l - 31) for rows 2 and 3
+  double f15;  // rows 1 and 3: g^((l & 15) + 1), the distance from lane 15 (47); else 0
+  double f31;  // rows 2 and 3: g^(l - 31); else 0
 };
 
 __device__ __forceinline__ Leaky make_leaky(double step) {
@@ -60,18 +63,26 @@ __device__ __forceinline__ Leaky make_leaky(double step) {
   L.g2 = exp(-2.0 * step);
   L.g4 = exp(-4.0 * step);
   L.g8 = exp(-8.0 * step);
-  L.f15 = exp(-step * (double)((l & 15) + 1));
+  L.f15 = (l & 16) ? exp(-step * (double)((l & 15) + 1)) : 0.0;
   L.f31 = l >= 32 ? exp(-step * (double)(l - 31)) : 0.0;
   return L;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_all(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double leaky_scan(double v, const Leaky& L) {
-  v = fma(L.g1, dpp_f64<0x111>(v), v);       // row_shr:1
-  v = fma(L.g2, dpp_f64<0x112>(v), v);       // row_shr:2
-  v = fma(L.g4, dpp_f64<0x114>(v), v);       // row_shr:4
-  v = fma(L.g8, dpp_f64<0x118>(v), v);       // row_shr:8
-  v = fma(L.f15, dpp_f64<0x142, 0xa>(v), v); // row_bcast:15 into rows 1 and 3
-  v = fma(L.f31, dpp_f64<0x143, 0xc>(v), v); // row_bcast:31 into rows 2 and 3
+  v = fma(L.g1, dpp_all<0x111>(v), v);   // row_shr:1
+  v = fma(L.g2, dpp_all<0x112>(v), v);   // row_shr:2
+  v = fma(L.g4, dpp_all<0x114>(v), v);   // row_shr:4
+  v = fma(L.g8, dpp_all<0x118>(v), v);   // row_shr:8
+  v = fma(L.f15, dpp_all<0x142>(v), v);  // row_bcast:15 (used by rows 1 and 3)
+  v = fma(L.f31, dpp_all<0x143>(v), v);  // row_bcast:31 (used by rows 2 and 3)
   return v;
 }
 
@@ -104,24 +115,26 @@ __device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const E
   const bool my = (t.d & 2) != 0;
   const long step = my ? -(long)a.ipitch : (long)a.ipitch;
   const uint8_t* col = a.img + (long)(my ? g.H - 1 - t.y0 : t.y0) * a.ipitch + xo;
-  const int B = g.B, b = t.b;
+  // [Q(v) = b] exactly when ceil(256 b / B) <= v < ceil(256 (b + 1) / B)
+  const uint32_t B = (uint32_t)g.B, b = (uint32_t)t.b;
+  const uint32_t vlo = (256u * b + B - 1) / B, span = (256u * (b + 1) + B - 1) / B - vlo;
   uint32_t lo = 0, hi = 0;
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int kk = k < t.nrows ? k : t.nrows - 1;
-    lo |= (uint32_t)((((int)col[kk * step] * B) >> 8) == b) << k;
+    lo |= (uint32_t)((uint32_t)col[kk * step] - vlo < span) << k;
   }
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int kk = k + 32 < t.nrows ? k + 32 : t.nrows - 1;
-    hi |= (uint32_t)((((int)col[kk * step] * B) >> 8) == b) << k;
+    hi |= (uint32_t)((uint32_t)col[kk * step] - vlo < span) << k;
   }
   uint64_t m = ((uint64_t)hi << 32) | lo;
   if (t.nrows < 64) m &= ((uint64_t)1 << t.nrows) - 1;
   return valid ? m : 0;
 }
 
-__device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)((m >> k) & 1); }
+__device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)(uint32_t)((m >> k) & 1); }
 
 // ---------------------------------------------------------------- build
 // Aggregate: per (direction, bin, band, tile) wave

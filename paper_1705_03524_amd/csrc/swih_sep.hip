@@ -141,8 +141,9 @@ __device__ void sep_rows(const SepBuildArgs& a, int vb) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int u = 4 * u4 + j;
-        const uint32_t bi = ((uint32_t)row[v0 + min(s0 + u, nsteps - 1)] * (uint32_t)B) >> 8;
-        const uint32_t bo = ((uint32_t)row[v0 + min(max(c0 + u, 0), nc - 1)] * (uint32_t)B) >> 8;
+        // 8-bit pixel times B <= 256 fits the 24-bit multiplier
+        const uint32_t bi = __umul24((uint32_t)row[v0 + min(s0 + u, nsteps - 1)], (uint32_t)B) >> 8;
+        const uint32_t bo = __umul24((uint32_t)row[v0 + min(max(c0 + u, 0), nc - 1)], (uint32_t)B) >> 8;
         wi |= bi << (8 * j);
         wo |= bo << (8 * j);
       }

@@ -102,9 +102,9 @@ def test_batch_equals_single_integer(kind):
             checked += 1
 
 
-@pytest.mark.parametrize("kind", [swih.GAUSSIAN, swih.GAUSSIAN_SEP])
+@pytest.mark.parametrize("kind", [swih.GAUSSIAN, swih.GAUSSIAN_SEP, swih.EXPONENTIAL])
 def test_batch_equals_single_gaussian_crops(kind):
-    print("case: batch gaussian (kind %d) crops with per-frame scales" % kind, flush=True)
+    print("case: batch real-valued kind %d: crops with per-frame scales" % kind, flush=True)
     big = to_dev(synth.smooth_noise(77, 600, 700), torch)
     crops = [big[10:210, 20:300], big[300:420, 100:260], big[50:131, 400:690], big[500:560, 0:90]]
     scales = [[(21, 21), (31, 15)], [(15, 15)], [(9, 9), (25, 31), (41, 41)], [(11, 13)]]
@@ -120,7 +120,8 @@ def test_batch_equals_single_gaussian_crops(kind):
     c, rect, hist, _, out = outs[(fi, si)]
     img = crops[fi].cpu().numpy()
     w, h = scales[fi][si]
-    _, tp = oracle.template(img, 16, oracle.GAUSSIAN, w, h, c)
+    ok = oracle.EXPONENTIAL if kind == swih.EXPONENTIAL else oracle.GAUSSIAN
+    _, tp = oracle.template(img, 16, ok, w, h, c)
     assert np.abs(hist.cpu().numpy()[0] - tp).max() <= 1e-5
 
 
@@ -151,13 +152,13 @@ def test_mix_invariance():
             assert torch.equal(gres[0][k][0], r[k][0]) and torch.equal(gres[0][k][1], r[k][1])
 
 
-@pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.GAUSSIAN, swih.GAUSSIAN_SEP])
+@pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.GAUSSIAN, swih.GAUSSIAN_SEP, swih.EXPONENTIAL])
 def test_graph_replay(kind):
     print("case: graph replay kind %d" % kind, flush=True)
     cfg = swih.Config(16, kind, SCALES)
     imgs = [to_dev(synth.smooth_noise(50 + k, H, W), torch) for k, (H, W) in enumerate(SIZES)]
     scales = [[s for s in SCALES if s[0] <= W and s[1] <= H] for (H, W) in SIZES]
-    integer = kind not in (swih.GAUSSIAN, swih.GAUSSIAN_SEP)
+    integer = kind not in swih._swih.REAL_KINDS
     b, outs = make_batch(cfg, imgs, scales, integer, list(range(len(imgs))))
     b.run()
     torch.cuda.synchronize()

@@ -13,7 +13,7 @@ import paper_1705_03524_amd as swih  # noqa: E402
 from paper_1705_03524_amd import serving  # noqa: E402
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "gaussian_sep"])
+@pytest.mark.parametrize("kind", ["gaussian", "gaussian_sep", "exponential"])
 def test_served_maps_equal_serial(kind):
     print("case: serving 48 requests at 400 req/s vs serial", flush=True)
     cfg = swih.Config(16, kind, [(15, 15)])
