@@ -69,6 +69,11 @@ def scene():
     return img, tc
 
 
+def synth_smooth(n):
+    from paper_1705_03524_amd import synth
+    return synth.smooth_noise(33, n, n)
+
+
 def cpu_baseline(img, tc, budget_s):
     """The oracle (brute force, OpenMP over centres) on a bounded sample: rows of
     centres of the same map, all three kernels, until ~budget_s of wall time
@@ -404,6 +409,39 @@ def main():
     exp_total = sum(exp_ms.values())
     exp_build = exp_ms["carries"] + exp_ms["planes"]
 
+    # The build at the multi-scale configuration's size (2048 x 2048 smooth
+    # noise, 32 bins, one 31 x 31 scale): algorithmic bytes = image read +
+    # every plane element written once.
+    W3 = 2048
+    w3_img = torch.from_numpy(synth_smooth(W3)).cuda()
+    w3 = {}
+    for kname in ("manhattan", "exponential", "gaussian"):
+        bp = Plan(swih.Config(32, kname, [(WIN, WIN)]), W3, W3)
+        swih.build(bp.cfg, w3_img, bp.ws, W3, W3, W3)
+        torch.cuda.synchronize()
+        rep = 2 if kname == "gaussian" else REP
+        t = {}
+        for ph in ("carries", "planes"):
+            g = capture(lambda: [swih.build_phase(bp.cfg, w3_img, bp.ws, ph, 0) for _ in range(rep)])
+            g.replay()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            t[ph] = a.elapsed_time(b) / (3 * rep)
+            del g
+        planes = 4 * bp.nplanes * 32 * (W3 + 1) * (W3 + 1)
+        build_ms = t["carries"] + t["planes"]
+        w3[kname] = {"ms": t, "plane_bytes": planes,
+                     "build_gbs": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9,
+                     "build_frac": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "planes_gbs": planes / (t["planes"] / 1e3) / 1e9}
+        del bp
+        torch.cuda.empty_cache()
+    del w3_img
+
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)
     # Algorithmic bytes of the two Gaussian kernels (81 weight terms x 16 bins):
@@ -455,6 +493,7 @@ def main():
             "speedup_vs_2d_gaussian": (per["build_gaussian"] + per["query_gaussian"] +
                                        per["match_gaussian"]) / sep_total,
             "max_abs_map_diff_vs_2d": sep_diff},
+        "ih_build_2048x2048_32bins": w3,
         "exponential": {
             "ms": exp_ms, "ms_total": exp_total, "windows_per_s": nwin / (exp_total / 1e3),
             "ih_build_gbs": (H * W + 4 * ep.nplanes * NBINS * (H + 1) * (W + 1)) / (exp_build / 1e3) / 1e9,
