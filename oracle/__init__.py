@@ -95,10 +95,56 @@ def kernel_table(kind: int, w: int, h: int, sigma=None) -> np.ndarray:
     return out
 
 
-def mass(kind: int, w: int, h: int, sigma=None):
+def mass(kind: int, w: int, h: int, sigma=None, table=None):
     """Kernel mass S = sum of the kernel table (int for integer kernels)."""
-    t = kernel_table(kind, w, h, sigma)
+    t = table if table is not None else kernel_table(kind, w, h, sigma)
     return int(t.sum()) if t.dtype == np.int64 else float(t.sum())
+
+
+# ---------------------------------------------------------------- wedding cake
+# The discrete approximation of Sec. 2 ("Wedding-Cake Approach", Fig. 4a): the
+# window is cut into n nested windows R_0 (the whole window) > R_1 > ... >
+# R_{n-1} around the centre; the rings R_i minus R_{i+1} get one weight each
+# and the weighted ring histograms are summed.  Readings (the paper fixes
+# neither): per axis the r + 1 distances 0..r from the centre are split into n
+# equal runs, r_i = floor((r + 1)(n - i) / n) - 1 (so n = r + 1 gives one ring
+# per distance; a negative half-size is an empty window), and each ring is
+# weighted by the mean of the kernel over its own pixels, which keeps the
+# total mass S.  The approximation is then a piecewise-constant kernel table,
+# evaluated by the same brute force.
+
+def cake_rings(w: int, h: int, n: int):
+    """Half-sizes (rx_i, ry_i), i = 0..n-1, of the nested windows."""
+    if n < 1:
+        raise ValueError("ring count must be >= 1")
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    return [((rx + 1) * (n - i) // n - 1, (ry + 1) * (n - i) // n - 1) for i in range(n)]
+
+
+def cake_ring_index(w: int, h: int, n: int) -> np.ndarray:
+    """ring[dy + ry, dx + rx] = the largest i with |dx| <= rx_i and |dy| <= ry_i."""
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    ring = np.zeros((h, w), np.int64)
+    for i, (ax, ay) in enumerate(cake_rings(w, h, n)):
+        if ax < 0 or ay < 0:
+            continue
+        for dy in range(-ay, ay + 1):
+            for dx in range(-ax, ax + 1):
+                ring[dy + ry, dx + rx] = i
+    return ring
+
+
+def cake_table(kind: int, w: int, h: int, n: int, sigma=None) -> np.ndarray:
+    """The wedding-cake kernel: every pixel of ring i weighted by the mean of the
+    kernel over ring i (float64 [h, w])."""
+    k = kernel_table(kind, w, h, sigma).astype(np.float64)
+    ring = cake_ring_index(w, h, n)
+    out = np.zeros((h, w), np.float64)
+    for i in range(n):
+        sel = ring == i
+        if sel.any():
+            out[sel] = k[sel].sum() / sel.sum()
+    return out
 
 
 def _img(img):
@@ -135,18 +181,18 @@ def hist(img, nbins: int, kind: int, w: int, h: int, centres, sigma=None, table=
     return out
 
 
-def normalised(raw, kind: int, w: int, h: int, sigma=None) -> np.ndarray:
+def normalised(raw, kind: int, w: int, h: int, sigma=None, table=None) -> np.ndarray:
     """p_b = H_b / S (float64)."""
-    return np.asarray(raw, np.float64) / float(mass(kind, w, h, sigma))
+    return np.asarray(raw, np.float64) / float(mass(kind, w, h, sigma, table))
 
 
-def template(img, nbins: int, kind: int, w: int, h: int, centre, sigma=None):
+def template(img, nbins: int, kind: int, w: int, h: int, centre, sigma=None, table=None):
     """Template histogram at ``centre``: (raw, normalised)."""
-    raw = hist(img, nbins, kind, w, h, [centre], sigma)[0]
-    return raw, normalised(raw, kind, w, h, sigma)
+    raw = hist(img, nbins, kind, w, h, [centre], sigma, table)[0]
+    return raw, normalised(raw, kind, w, h, sigma, table)
 
 
-def bc_at(img, nbins: int, kind: int, w: int, h: int, centres, tmpl, sigma=None) -> np.ndarray:
+def bc_at(img, nbins: int, kind: int, w: int, h: int, centres, tmpl, sigma=None, table=None) -> np.ndarray:
     """Bhattacharyya coefficient at listed centres against template ``tmpl``.
 
     Integer kernels take the raw integer template; the real-valued kernels take
@@ -158,7 +204,7 @@ def bc_at(img, nbins: int, kind: int, w: int, h: int, centres, tmpl, sigma=None)
     c = np.ascontiguousarray(np.asarray(centres, dtype=np.int32).reshape(-1, 2))
     n = c.shape[0]
     out = np.empty(n, np.float64)
-    tab = np.ascontiguousarray(kernel_table(kind, w, h, sigma))
+    tab = np.ascontiguousarray(table if table is not None else kernel_table(kind, w, h, sigma))
     if tab.dtype == np.int64:
         t = np.ascontiguousarray(np.asarray(tmpl, np.int64))
         rc = lib.oracle_bc_i64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_int64), w, h,
@@ -172,10 +218,11 @@ def bc_at(img, nbins: int, kind: int, w: int, h: int, centres, tmpl, sigma=None)
     return out
 
 
-def bc_map(img, nbins: int, kind: int, w: int, h: int, tmpl, rect=None, sigma=None) -> np.ndarray:
+def bc_map(img, nbins: int, kind: int, w: int, h: int, tmpl, rect=None, sigma=None, table=None) -> np.ndarray:
     """Dense likelihood map over the inclusive centre rectangle (x0, y0, x1, y1).
 
     Defaults to every valid centre.  Returns float64 [y1 - y0 + 1, x1 - x0 + 1].
+    ``table`` overrides the kernel (a float64 table takes the normalised template).
     """
     lib = _load()
     a = _img(img)
@@ -183,7 +230,7 @@ def bc_map(img, nbins: int, kind: int, w: int, h: int, tmpl, rect=None, sigma=No
     rx, ry = (w - 1) // 2, (h - 1) // 2
     x0, y0, x1, y1 = rect if rect is not None else (rx, ry, W - 1 - rx, H - 1 - ry)
     out = np.empty((max(0, y1 - y0 + 1), max(0, x1 - x0 + 1)), np.float64)
-    tab = np.ascontiguousarray(kernel_table(kind, w, h, sigma))
+    tab = np.ascontiguousarray(table if table is not None else kernel_table(kind, w, h, sigma))
     if tab.dtype == np.int64:
         t = np.ascontiguousarray(np.asarray(tmpl, np.int64))
         rc = lib.oracle_map_i64(_p(a, C.c_uint8), H, W, W, nbins, _p(tab, C.c_int64), w, h,

@@ -335,3 +335,80 @@ def test_generators_are_seeded():
     assert cs.shape == (100, 2)
     assert cs[:, 0].min() == 7 and cs[:, 0].max() == 80 - 8
     assert cs[:, 1].min() == 4 and cs[:, 1].max() == 100 - 5
+
+
+# ---------------------------------------------------------------- wedding cake
+# Sec. 2 (Fig. 4a): nested windows, one weight per ring.  Pins: the ring
+# geometry, the one-ring case (a scaled plain histogram), mass preservation, a
+# ring-constant kernel reproduced exactly, and convergence toward the kernel.
+@pytest.mark.parametrize("w,h,n", [(31, 31, 1), (31, 31, 4), (15, 9, 3), (61, 91, 8), (5, 5, 7), (1, 9, 2)])
+def test_cake_ring_geometry(w, h, n):
+    rings = oracle.cake_rings(w, h, n)
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    assert rings[0] == (rx, ry)
+    for (ax, ay), (bx, by) in zip(rings, rings[1:]):
+        assert bx <= ax and by <= ay
+    ring = oracle.cake_ring_index(w, h, n)
+    sizes = [(2 * ax + 1) * (2 * ay + 1) if ax >= 0 and ay >= 0 else 0 for ax, ay in rings] + [0]
+    for i in range(n):
+        assert (ring == i).sum() == sizes[i] - sizes[i + 1]
+    assert ring[ry, rx] == max(i for i, (ax, ay) in enumerate(rings) if ax >= 0 and ay >= 0)
+    if n <= min(rx, ry) + 1:    # equal runs of distance: every ring is non-empty
+        assert all(sizes[i] > sizes[i + 1] for i in range(n))
+    assert ring[0, 0] == max(i for i, r in enumerate(rings) if r == rings[0])  # outermost non-empty ring
+
+
+@pytest.mark.parametrize("kind", (oracle.MANHATTAN, oracle.EUCLIDEAN, oracle.GAUSSIAN))
+def test_cake_one_ring_is_scaled_plain_histogram(kind):
+    img = synth.uniform_noise(21, 30, 34)
+    w, h, nb = 9, 7, 5
+    c = valid_centres(30, 34, w, h)
+    cake = oracle.hist(img, nb, kind, w, h, c, table=oracle.cake_table(kind, w, h, 1))
+    plain = oracle.hist(img, nb, oracle.UNIFORM, w, h, c)
+    S = oracle.mass(kind, w, h)
+    np.testing.assert_allclose(cake, plain * (S / (w * h)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("kind", (oracle.MANHATTAN, oracle.EUCLIDEAN, oracle.EXPONENTIAL))
+@pytest.mark.parametrize("n", [2, 5, 16])
+def test_cake_keeps_mass(kind, n):
+    w, h = 21, 15
+    t = oracle.cake_table(kind, w, h, n)
+    assert t.sum() == pytest.approx(oracle.mass(kind, w, h), rel=1e-13)
+    img = synth.smooth_noise(3, 40, 40)
+    hb = oracle.hist(img, 8, kind, w, h, valid_centres(40, 40, w, h)[::13], table=t)
+    np.testing.assert_allclose(hb.sum(1), oracle.mass(kind, w, h), rtol=1e-12)
+
+
+@pytest.mark.parametrize("w,h,n", [(15, 15, 4), (21, 9, 3), (31, 31, 8)])
+def test_cake_reproduces_ring_constant_kernel(w, h, n):
+    # k = number of nested windows holding the pixel: constant on every ring
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    k = np.zeros((h, w), np.int64)
+    for ax, ay in oracle.cake_rings(w, h, n):
+        if ax >= 0 and ay >= 0:
+            k[ry - ay:ry + ay + 1, rx - ax:rx + ax + 1] += 1
+    img = synth.uniform_noise(9, 45, 50)
+    c = valid_centres(45, 50, w, h)[::5]
+    exact = oracle.hist(img, 6, oracle.MANHATTAN, w, h, c, table=k)
+    # the cake of k (ring means of k) must be k itself
+    ring = oracle.cake_ring_index(w, h, n)
+    means = np.array([k[ring == i].mean() for i in range(n)])
+    cake = oracle.hist(img, 6, oracle.MANHATTAN, w, h, c, table=means[ring])
+    np.testing.assert_allclose(cake, exact, rtol=1e-14)
+
+
+def test_cake_error_falls_with_rings_but_stays_for_the_diamond():
+    # square rings approach the kernel as they multiply, but the Manhattan
+    # pyramid varies inside a square shell (corner vs edge), so even one ring
+    # per shell leaves an error: the point of Sec. 2.1's exact method
+    w = h = 31
+    k = oracle.kernel_table(oracle.MANHATTAN, w, h).astype(np.float64)
+    err = [np.abs(oracle.cake_table(oracle.MANHATTAN, w, h, n) - k).sum() / k.sum() for n in (1, 2, 4, 8, 16)]
+    assert all(b < a for a, b in zip(err, err[1:]))
+    shells = oracle.cake_table(oracle.MANHATTAN, w, h, 16)   # 16 rings = every shell of a 31 x 31
+    assert len(set(oracle.cake_rings(w, h, 16))) == 16
+    dist = np.maximum.outer(np.abs(np.arange(-15, 16)), np.abs(np.arange(-15, 16)))
+    for d in range(16):                                       # shell mean of the pyramid
+        assert np.allclose(shells[dist == d], k[dist == d].mean())
+    assert err[-1] > 0.1
