@@ -194,6 +194,49 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
                const uint32_t* d_template_raw, swih_rect centres, float* d_map, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Baselines the paper compares SWIH with (Sec. 3, Figs. 5 and 6).
+ *
+ * Wedding cake (Sec. 2, "Wedding-Cake Approach", Fig. 4a): the window is cut
+ * into `rings` nested windows around the centre, per axis half-sizes
+ * r_i = floor((r+1)(rings-i)/rings) - 1, i = 0..rings-1 (equal runs of the
+ * distances 0..r from the centre; a negative half-size is an empty window).
+ * Each ring (a window minus the next one) is weighted by the mean of the
+ * configured kernel over the ring's pixels, so the total mass stays S, and the
+ * ring counts come from the plain count plane of the workspace: O(rings)
+ * lookups per window whatever its size.  cfg must be an integer kernel
+ * (SWIH_UNIFORM, SWIH_MANHATTAN, SWIH_EUCLIDEAN; SWIH_ERR_UNSUPPORTED
+ * otherwise) and d_ws a workspace swih_build wrote for it.
+ *   rings       1..32 (SWIH_ERR_INVALID otherwise).
+ *   d_hist      device float [n][nbins], the normalised approximate histogram.
+ *   d_template  device float [nbins], normalised template (normally the
+ *               swih_cake_query result at the template centre).
+ *   d_map       device float [(y1-y0+1)][(x1-x0+1)]: sum_b sqrt(p_b t_b) in
+ *               double, bins in order, rounded to float.
+ * Other arguments, rules and errors as swih_query / swih_match.
+ */
+int swih_cake_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+                    int32_t width, int32_t scale_idx, int32_t rings, const int32_t* d_centres,
+                    int32_t n, float* d_hist, void* stream);
+int swih_cake_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+                    int32_t width, int32_t scale_idx, int32_t rings, const float* d_template,
+                    swih_rect centres, float* d_map, void* stream);
+
+/*
+ * Brute force (Sec. 2, the convolution-style weighted histogram): every pixel
+ * of every window adds its kernel weight to its bin, straight from the image;
+ * O(w h) per window.  Integer kernels only (SWIH_ERR_UNSUPPORTED otherwise);
+ * the histograms are exact, and the map is (sum_b sqrt(H_b T_b)) / S as in
+ * swih_match with the raw template, so the two maps are equal bit for bit.
+ *   d_img            device image, as swih_build; no workspace is used.
+ *   d_template_raw   device uint32 [nbins], exact template T_b.
+ *   d_map            device float [(y1-y0+1)][(x1-x0+1)], row-major.
+ * nbins up to 256 (each thread keeps its histogram in LDS).
+ */
+int swih_brute_match(const swih_config* cfg, const uint8_t* d_img, int32_t height, int32_t width,
+                     int32_t pitch, int32_t scale_idx, const uint32_t* d_template_raw,
+                     swih_rect centres, float* d_map, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form.  Sec. 4 applies the likelihood maps to many targets over the
  * frames of a tracking sequence; a batch builds many frames (or search-region
  * crops) of different sizes, queries their templates and computes their maps

@@ -27,7 +27,7 @@ OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
 EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_build_planes",
             "swih_query", "swih_match", "swih_batch_table_bytes", "swih_batch_plan",
             "swih_build_batch", "swih_query_batch", "swih_match_batch", "swih_gauss_terms",
-            "swih_status_string")
+            "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match")
 
 
 class SwihError(RuntimeError):
@@ -99,6 +99,12 @@ def load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp]
         f.restype = C.c_int
+    lib.swih_cake_query.argtypes = [cfgp, vp, sz, i32, i32, i32, i32, vp, i32, vp, vp]
+    lib.swih_cake_query.restype = C.c_int
+    lib.swih_cake_match.argtypes = [cfgp, vp, sz, i32, i32, i32, i32, vp, _Rect, vp, vp]
+    lib.swih_cake_match.restype = C.c_int
+    lib.swih_brute_match.argtypes = [cfgp, vp, i32, i32, i32, i32, vp, _Rect, vp, vp]
+    lib.swih_brute_match.restype = C.c_int
     lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
     lib.swih_gauss_terms.restype = C.c_int
@@ -200,6 +206,41 @@ def match(cfg: Config, ws, height: int, width: int, scale_idx: int, rect, out, t
                            _ptr(out), _stream(stream))
     if st != OK:
         raise SwihError(st, "swih_match")
+
+
+def cake_query(cfg: Config, ws, height: int, width: int, scale_idx: int, rings: int, centres, hist,
+               stream=None):
+    """swih_cake_query: wedding-cake histograms at int32 [n, 2] device ``centres``."""
+    n = int(centres.shape[0])
+    st = load().swih_cake_query(C.byref(cfg.c()), _ptr(ws), ws.numel() * ws.element_size(), int(height),
+                                int(width), int(scale_idx), int(rings), _ptr(centres), n, _ptr(hist),
+                                _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_cake_query")
+
+
+def cake_match(cfg: Config, ws, height: int, width: int, scale_idx: int, rings: int, rect, out, template,
+               stream=None):
+    """swih_cake_match over the inclusive centre rectangle ``rect``."""
+    r = _Rect(*[int(v) for v in rect])
+    st = load().swih_cake_match(C.byref(cfg.c()), _ptr(ws), ws.numel() * ws.element_size(), int(height),
+                                int(width), int(scale_idx), int(rings), _ptr(template), r, _ptr(out),
+                                _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_cake_match")
+
+
+def brute_match(cfg: Config, img, scale_idx: int, rect, out, template_raw, height=None, width=None,
+                pitch=None, stream=None):
+    """swih_brute_match: the brute-force map straight from the image."""
+    H = int(height if height is not None else img.shape[0])
+    W = int(width if width is not None else img.shape[1])
+    P = int(pitch if pitch is not None else img.stride(0))
+    r = _Rect(*[int(v) for v in rect])
+    st = load().swih_brute_match(C.byref(cfg.c()), _ptr(img), H, W, P, int(scale_idx), _ptr(template_raw), r,
+                                 _ptr(out), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_brute_match")
 
 
 def gauss_terms(n: int, K: int = 4):

@@ -356,6 +356,109 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- baselines
+namespace {
+
+// Shared checks of the wedding-cake calls: an integer kernel, a valid scale
+// and ring count, a workspace built for cfg.
+int cake_setup(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+               int32_t width, int32_t scale_idx, int32_t rings, CakeArgs& a) {
+  int st = check_config(cfg, height, width);
+  if (st != SWIH_OK) return st;
+  if (scale_idx < 0 || scale_idx >= cfg->nscales || !d_ws) return SWIH_ERR_INVALID;
+  if (real_kind(cfg->kernel)) return SWIH_ERR_UNSUPPORTED;  // needs the count plane
+  if (rings < 1 || rings > SWIH_MAX_RINGS) return SWIH_ERR_INVALID;
+  SwihLayout L;
+  make_layout(cfg, height, width, L);
+  if ((int64_t)ws_bytes < L.total) return SWIH_ERR_WORKSPACE;
+  ScaleParams sp;
+  st = scale_params(cfg, scale_idx, sp);
+  if (st != SWIH_OK) return st;
+  if (cake_args(cfg->kernel, L.g, sp.w, sp.h, rings, sp.mass, sp.c_int,
+                (const char*)d_ws + L.off_planes, a))
+    return SWIH_ERR_INVALID;
+  return SWIH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swih_cake_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+                    int32_t width, int32_t scale_idx, int32_t rings, const int32_t* d_centres,
+                    int32_t n, float* d_hist, void* stream) {
+  CakeArgs a;
+  int st = cake_setup(cfg, d_ws, ws_bytes, height, width, scale_idx, rings, a);
+  if (st != SWIH_OK) return st;
+  if (n < 0) return SWIH_ERR_INVALID;
+  if (n == 0) return SWIH_OK;
+  if (!d_centres || !d_hist) return SWIH_ERR_INVALID;
+  a.centres = d_centres;
+  a.n = n;
+  a.hist = d_hist;
+  return cake_launch_query(a, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+}
+
+int swih_cake_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+                    int32_t width, int32_t scale_idx, int32_t rings, const float* d_template,
+                    swih_rect r, float* d_map, void* stream) {
+  CakeArgs a;
+  int st = cake_setup(cfg, d_ws, ws_bytes, height, width, scale_idx, rings, a);
+  if (st != SWIH_OK) return st;
+  if (!d_template) return SWIH_ERR_INVALID;
+  if (r.x1 < r.x0 || r.y1 < r.y0) return SWIH_OK;
+  const swih_scale sc = cfg->scales[scale_idx];
+  const int32_t rx = (sc.w - 1) / 2, ry = (sc.h - 1) / 2;
+  if (r.x0 < rx || r.y0 < ry || r.x1 > width - 1 - rx || r.y1 > height - 1 - ry || !d_map)
+    return SWIH_ERR_INVALID;
+  a.tmpl = d_template;
+  a.map = d_map;
+  a.x0 = r.x0;
+  a.y0 = r.y0;
+  a.x1 = r.x1;
+  a.y1 = r.y1;
+  a.nbx = (r.x1 - r.x0 + 1 + 63) / 64;
+  return cake_launch_match(a, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+}
+
+int swih_brute_match(const swih_config* cfg, const uint8_t* d_img, int32_t height, int32_t width,
+                     int32_t pitch, int32_t scale_idx, const uint32_t* d_template_raw, swih_rect r,
+                     float* d_map, void* stream) {
+  int st = check_config(cfg, height, width);
+  if (st != SWIH_OK) return st;
+  if (scale_idx < 0 || scale_idx >= cfg->nscales || !d_img || pitch < width || !d_template_raw)
+    return SWIH_ERR_INVALID;
+  if (real_kind(cfg->kernel)) return SWIH_ERR_UNSUPPORTED;  // exact integer kernels only
+  if (r.x1 < r.x0 || r.y1 < r.y0) return SWIH_OK;
+  ScaleParams sp;
+  st = scale_params(cfg, scale_idx, sp);
+  if (st != SWIH_OK) return st;
+  if (r.x0 < sp.rx || r.y0 < sp.ry || r.x1 > width - 1 - sp.rx || r.y1 > height - 1 - sp.ry || !d_map)
+    return SWIH_ERR_INVALID;
+  BruteArgs a;
+  memset(&a, 0, sizeof(a));
+  a.img = d_img;
+  a.ipitch = pitch;
+  a.H = height;
+  a.W = width;
+  a.B = cfg->nbins;
+  a.kind = cfg->kernel;
+  a.rx = sp.rx;
+  a.ry = sp.ry;
+  a.c_int = sp.c_int;
+  a.mass = sp.mass;
+  a.tmpl_raw = d_template_raw;
+  a.map = d_map;
+  a.x0 = r.x0;
+  a.y0 = r.y0;
+  a.x1 = r.x1;
+  a.y1 = r.y1;
+  a.nbx = (r.x1 - r.x0 + 1 + 63) / 64;
+  return brute_launch_match(a, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- batches
 namespace {
 

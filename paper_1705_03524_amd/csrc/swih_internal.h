@@ -300,4 +300,50 @@ hipError_t exp_launch_match_batch(const ExpMatchArgs* items, const int32_t* pref
                                   int32_t total, int grid, hipStream_t s);
 
 
+// ------------------------------------------------------------------------
+// Baselines (swih_cake.hip): the wedding-cake approximation over the count
+// plane of an integer-kernel workspace, and the brute-force weighted
+// histogram straight from the image.
+
+#define SWIH_MAX_RINGS 32
+
+struct CakeArgs {
+  SwihGeom g;
+  const void* planes;        // uint32 planes of an integer kernel; plane 0 counts pixels
+  int32_t nrings;
+  int32_t rx[SWIH_MAX_RINGS], ry[SWIH_MAX_RINGS];  // nested half-sizes (negative = empty)
+  double dw[SWIH_MAX_RINGS];  // w_i - w_{i-1}: weight steps from ring to ring
+  double mass;
+  const int32_t* centres;    // query: [n][2]
+  int32_t n;
+  float* hist;               // query: [n][B]
+  const float* tmpl;         // map: [B] normalised template
+  float* map;
+  int32_t x0, y0, x1, y1;    // map: inclusive centre rectangle
+  int32_t nbx;               // map: waves across the rectangle (64 centres each)
+};
+
+// Rings and weights for kernel `kind` (uniform, Manhattan, Euclidean) of a
+// w x h window; returns 0, or -1 for a ring count outside 1..SWIH_MAX_RINGS.
+int cake_args(int kind, const SwihGeom& g, int32_t w, int32_t h, int32_t rings, double mass,
+              uint32_t c_int, const void* planes, CakeArgs& a);
+hipError_t cake_launch_query(const CakeArgs& a, hipStream_t s);
+hipError_t cake_launch_match(const CakeArgs& a, hipStream_t s);
+
+struct BruteArgs {
+  const uint8_t* img;
+  int32_t ipitch;
+  int32_t H, W, B;
+  int32_t kind;              // uniform, Manhattan or Euclidean
+  int32_t rx, ry;
+  uint32_t c_int;            // kernel constant (rx + ry + 1, or rx^2 + ry^2 + 1)
+  double mass;
+  const uint32_t* tmpl_raw;  // [B] exact template
+  float* map;
+  int32_t x0, y0, x1, y1;
+  int32_t nbx;               // blocks across the rectangle (64 centres each)
+};
+
+hipError_t brute_launch_match(const BruteArgs& a, hipStream_t s);
+
 }  // namespace swih

@@ -174,3 +174,28 @@ def test_gauss_series_fidelity(n):
 def test_gauss_series_orders():
     e = [swih.gauss_terms(31, K)[2] for K in (2, 3, 4, 5)]
     assert e[0] > e[1] > e[2] > e[3]
+
+
+def test_baseline_host_checks():
+    import ctypes as C
+    lib = swih.load()
+    r = _swih._Rect(2, 2, 10, 10)
+    g = swih.Config(8, swih.GAUSSIAN, [(5, 5)])
+    st = lib.swih_cake_query(C.byref(g.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, 4, C.c_void_p(256), 4,
+                             C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # the wedding cake needs an integer kernel's count plane
+    m = swih.Config(8, swih.MANHATTAN, [(5, 5)])
+    for rings in (0, 33):
+        st = lib.swih_cake_match(C.byref(m.c()), C.c_void_p(256), 1 << 34, 64, 64, 0, rings, C.c_void_p(256),
+                                 r, C.c_void_p(256), None)
+        assert st == _swih.ERR_INVALID
+    st = lib.swih_cake_match(C.byref(m.c()), C.c_void_p(256), 16, 64, 64, 0, 4, C.c_void_p(256), r,
+                             C.c_void_p(256), None)
+    assert st == _swih.ERR_WORKSPACE
+    st = lib.swih_brute_match(C.byref(g.c()), C.c_void_p(256), 64, 64, 64, 0, C.c_void_p(256), r,
+                              C.c_void_p(256), None)
+    assert st == _swih.ERR_UNSUPPORTED      # exact integer kernels only
+    bad = _swih._Rect(1, 2, 10, 10)         # x0 < rx
+    st = lib.swih_brute_match(C.byref(m.c()), C.c_void_p(256), 64, 64, 64, 0, C.c_void_p(256), bad,
+                              C.c_void_p(256), None)
+    assert st == _swih.ERR_INVALID
