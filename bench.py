@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("frame", "batch", "serve"), default="frame",
+    ap.add_argument("--workload", choices=("frame", "batch", "serve", "sweep"), default="frame",
                     help="frame: the 512x512 single-frame path (default); batch: 64 uneven "
                          "frames with 1-8 targets x 3 scales, batched vs per-frame; serve: "
                          "Poisson tracking requests, continuous batching vs one at a time")
@@ -256,6 +256,143 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_sweep(args):
+    """The comparison of Sec. 3 on synthetic images: time of the likelihood map
+    against window size (Fig. 6: 640x480 and 1024x1024, Manhattan, 16 bins) for
+    SWIH (one build serves every window size, then the map), the wedding cake
+    (4 rings over the same build's count plane), brute force on the GPU and the
+    oracle's brute force on the host (a bounded sample, extrapolated); the
+    wedding cake's map error against ring count (Fig. 5) on the 512x512 scene;
+    and the paper's one timed shape (a 345x460 region, 61x91 window)."""
+    import torch
+    import paper_1705_03524_amd as swih
+    from paper_1705_03524_amd import synth
+    from paper_1705_03524_amd.plan import Plan
+    import oracle
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def cpu_brute_ms(img, w, h, traw, budget_s):
+        """Oracle brute force over whole rows of centres for ~budget_s; the full-map
+        time extrapolated from its rate."""
+        H_, W_ = img.shape
+        r, ry = (w - 1) // 2, (h - 1) // 2
+        oracle.bc_map(img, NBINS, oracle.MANHATTAN, w, h, traw, rect=(r, ry, r, ry))  # threads up
+        t0 = time.perf_counter()
+        y, n = ry, 0
+        while time.perf_counter() - t0 < budget_s and y <= H_ - 1 - ry:
+            oracle.bc_map(img, NBINS, oracle.MANHATTAN, w, h, traw, rect=(r, y, W_ - 1 - r, y))
+            n += W_ - 2 * r
+            y += 1
+        dt = time.perf_counter() - t0
+        return dt / n * (W_ - w + 1) * (H_ - h + 1) * 1e3, n
+
+    cfg_all = None
+    sizes = ((480, 640), (1024, 1024))
+    wins = (11, 21, 31, 41, 61, 81, 101, 151, 201)
+    curves = {}
+    for (Hs, Ws) in sizes:
+        img = synth.rect_scene(5, Hs, Ws)[0]
+        d_img = torch.from_numpy(img).cuda()
+        cfg_all = swih.Config(NBINS, swih.MANHATTAN, [(w, w) for w in wins])
+        plan = Plan(cfg_all, Hs, Ws)
+        build_ms = timed(lambda: plan.build(d_img), 5)
+        rows = []
+        for si, w in enumerate(wins):
+            r = (w - 1) // 2
+            tc = np.array([[Ws // 2, Hs // 2]], np.int32)
+            d_tc = torch.from_numpy(tc).cuda()
+            hist, raw = plan.query(si, d_tc)
+            traw = raw[0].contiguous()
+            rect = plan.valid_rect(si)
+            out = torch.empty((Hs - w + 1, Ws - w + 1), dtype=torch.float32, device="cuda")
+            map_ms = timed(lambda: plan.match(si, template_raw=traw, rect=rect, out=out), 10)
+            ctm = torch.empty((1, NBINS), dtype=torch.float32, device="cuda")
+            swih.cake_query(plan.cfg, plan.ws, Hs, Ws, si, 4, d_tc, ctm)
+            cout = torch.empty_like(out)
+            cake_ms = timed(lambda: swih.cake_match(plan.cfg, plan.ws, Hs, Ws, si, 4, rect, cout, ctm[0]), 10)
+            bout = torch.empty_like(out)
+            brute_ms = timed(lambda: swih.brute_match(plan.cfg, d_img, si, rect, bout, traw),
+                             1 if w >= 101 else 3)
+            same = bool(torch.equal(bout, out))
+            cpu_ms, cpu_n = cpu_brute_ms(img, w, w, raw[0].cpu().numpy().astype(np.int64),
+                                         args.cpu_seconds / len(wins) / len(sizes))
+            rows.append({"w": w, "windows": (Hs - w + 1) * (Ws - w + 1), "swih_map_ms": map_ms,
+                         "swih_ms": build_ms + map_ms, "cake4_ms": cake_ms, "brute_gpu_ms": brute_ms,
+                         "brute_gpu_equals_swih": same, "cpu_oracle_brute_ms_extrapolated": cpu_ms,
+                         "cpu_sample_windows": cpu_n})
+            print("sweep %dx%d w=%d: swih %.3f ms, cake %.3f ms, brute gpu %.3f ms, cpu %.0f ms" %
+                  (Ws, Hs, w, build_ms + map_ms, cake_ms, brute_ms, cpu_ms), file=sys.stderr, flush=True)
+        curves["%dx%d" % (Ws, Hs)] = {"swih_build_ms": build_ms, "rows": rows}
+        del plan
+        torch.cuda.empty_cache()
+
+    # Fig. 5: likelihood-map error of the approximations against the exact map
+    img, rects = synth.rect_scene(1, H, W)
+    x0, y0, rw, rh, _ = rects[0]
+    r = (WIN - 1) // 2
+    tc = np.array([[min(max(x0 + rw // 2, r), W - 1 - r), min(max(y0 + rh // 2, r), H - 1 - r)]], np.int32)
+    d_img = torch.from_numpy(img).cuda()
+    d_tc = torch.from_numpy(tc).cuda()
+    plan = Plan(swih.Config(NBINS, swih.MANHATTAN, [(WIN, WIN)]), H, W)
+    plan.build(d_img)
+    _, raw = plan.query(0, d_tc)
+    exact = plan.match(0, template_raw=raw[0].contiguous())
+    acc = []
+    for n in (1, 2, 3, 4, 6, 8, 12, 16):
+        ctm = torch.empty((1, NBINS), dtype=torch.float32, device="cuda")
+        swih.cake_query(plan.cfg, plan.ws, H, W, 0, n, d_tc, ctm)
+        cm = torch.empty_like(exact)
+        swih.cake_match(plan.cfg, plan.ws, H, W, 0, n, plan.valid_rect(0), cm, ctm[0])
+        d = (cm - exact).abs()
+        acc.append({"rings": n, "max_abs_map_err": float(d.max()), "mean_abs_map_err": float(d.mean())})
+    up = Plan(swih.Config(NBINS, swih.UNIFORM, [(WIN, WIN)]), H, W)
+    up.build(d_img)
+    uh, _ = up.query(0, d_tc)
+    um = up.match(0, template=uh[0].contiguous())
+    plain = {"max_abs_map_err": float((um - exact).abs().max()), "mean_abs_map_err": float((um - exact).abs().mean())}
+
+    # the paper's timed shape: a 345 x 460 region, 61 x 91 window (Sec. 3)
+    PW, PH, pw, ph = 345, 460, 61, 91
+    pimg = synth.rect_scene(6, PH, PW)[0]
+    d_p = torch.from_numpy(pimg).cuda()
+    pp = Plan(swih.Config(NBINS, swih.MANHATTAN, [(pw, ph)]), PH, PW)
+    pc = torch.tensor([[PW // 2, PH // 2]], dtype=torch.int32, device="cuda")
+    pp.build(d_p)
+    _, praw = pp.query(0, pc)
+    praw = praw[0].contiguous()
+    pout = torch.empty((PH - ph + 1, PW - pw + 1), dtype=torch.float32, device="cuda")
+    swih_ms = timed(lambda: (pp.build(d_p), pp.match(0, template_raw=praw, out=pout)), 10)
+    bout = torch.empty_like(pout)
+    brute_ms = timed(lambda: swih.brute_match(pp.cfg, d_p, 0, pp.valid_rect(0), bout, praw), 3)
+    cpu_ms, cpu_n = cpu_brute_ms(pimg, pw, ph, praw.cpu().numpy().astype(np.int64), 2.0)
+    line = {
+        "metric": "likelihood-map time vs window size (SWIH, wedding cake, brute force)",
+        "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "u32+f64", "data": "synthetic",
+        "config": {"workload": "Fig. 6 shape: 640x480 and 1024x1024 scenes, 16 bins, Manhattan, square "
+                               "windows 11..201, full map; wedding cake with 4 rings",
+                   "parallelism": "none"},
+        "curves": curves,
+        "cake_accuracy_512_scene_31x31": {"wedding_cake": acc, "plain_histogram": plain},
+        "paper_shape_345x460_61x91": {
+            "swih_ms": swih_ms, "brute_gpu_ms": brute_ms, "brute_gpu_over_swih": brute_ms / swih_ms,
+            "brute_gpu_equals_swih": bool(torch.equal(bout, pout)),
+            "cpu_oracle_brute_ms_extrapolated": cpu_ms, "cpu_sample_windows": cpu_n,
+            "cpu_cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "paper_reported_speedup_over_brute_force": 4.5},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -267,6 +404,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
     import torch
     import paper_1705_03524_amd as swih
