@@ -196,7 +196,7 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
 /* ------------------------------------------------------------------------
  * Baselines the paper compares SWIH with (Sec. 3, Figs. 5 and 6).
  *
- * Wedding cake (Sec. 2, "Wedding-Cake Approach", Fig. 4a): the window is cut
+ * Wedding cake (Sec. 2, the wedding-cake approach, Fig. 4a): the window is cut
  * into `rings` nested windows around the centre, per axis half-sizes
  * r_i = floor((r+1)(rings-i)/rings) - 1, i = 0..rings-1 (equal runs of the
  * distances 0..r from the centre; a negative half-size is an empty window).

@@ -102,7 +102,7 @@ def mass(kind: int, w: int, h: int, sigma=None, table=None):
 
 
 # ---------------------------------------------------------------- wedding cake
-# The discrete approximation of Sec. 2 ("Wedding-Cake Approach", Fig. 4a): the
+# The discrete approximation of Sec. 2 (the wedding-cake approach, Fig. 4a): the
 # window is cut into n nested windows R_0 (the whole window) > R_1 > ... >
 # R_{n-1} around the centre; the rings R_i minus R_{i+1} get one weight each
 # and the weighted ring histograms are summed.  Readings (the paper fixes
