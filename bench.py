@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("frame", "batch", "serve", "sweep"), default="frame",
+    ap.add_argument("--workload", choices=("frame", "batch", "serve", "sweep", "track"), default="frame",
                     help="frame: the 512x512 single-frame path (default); batch: 64 uneven "
                          "frames with 1-8 targets x 3 scales, batched vs per-frame; serve: "
                          "Poisson tracking requests, continuous batching vs one at a time")
@@ -393,6 +393,41 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_track(args):
+    """The tracking loop of Sec. 4 on synthetic sequences (640x480, a 31x31 target
+    and 3 distractors holding the target's pixel values in reverse spatial order,
+    60 frames each, 16 sequences): localisation error and frames per second for
+    the plain histogram and the spatially weighted kernels, 3 scales per frame."""
+    import torch
+    from paper_1705_03524_amd import synth, tracking
+
+    seqs = [synth.track_sequence(100 + s, 60, ndistract=3) for s in range(16)]
+    out = {}
+    for k in ("uniform", "manhattan", "euclidean", "gaussian_sep", "exponential"):
+        errs, succ, frames = [], [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for fr, gt, side in seqs:
+            r = tracking.run_sequence(k, fr, gt, side, scales=(0.9, 1.0, 1.1))
+            errs.append(r["errors"])
+            succ.append(r["success"])
+            frames += len(fr) - 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e = np.concatenate(errs)
+        out[k] = {"mean_error_px": float(e.mean()), "median_error_px": float(np.median(e)),
+                  "success_rate": float(np.mean(succ)), "frames_per_s": frames / dt}
+        print("track %s: mean %.2f px, success %.3f, %.0f frames/s" %
+              (k, e.mean(), np.mean(succ), frames / dt), file=sys.stderr, flush=True)
+    line = {"metric": "tracking localisation error and frames/s (plain vs spatially weighted histograms)",
+            "unit": "px", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": "16 sequences x 60 frames of 640x480, 31x31 target, 3 distractors with the "
+                                   "target's values in reverse spatial order, 16 bins, 3 scales, search 1.5 sides",
+                       "parallelism": "none"},
+            "kernels": out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -407,6 +442,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "track":
+        bench_track(args)
         return
     import torch
     import paper_1705_03524_amd as swih

@@ -236,6 +236,16 @@ int swih_brute_match(const swih_config* cfg, const uint8_t* d_img, int32_t heigh
                      int32_t pitch, int32_t scale_idx, const uint32_t* d_template_raw,
                      swih_rect centres, float* d_map, void* stream);
 
+/*
+ * The best window of a likelihood map, as a tracker's localisation step takes
+ * it (Sec. 4): the first maximum of d_map[0..n-1] in row-major order.
+ *   d_map   device float [n], every value >= 0 (likelihoods are).
+ *   d_key   device uint64 [1], written with (bits of the maximum << 32) |
+ *           (2^32 - 1 - index): index = 0xffffffff - (key & 0xffffffff).
+ * 1 <= n < 2^32 (SWIH_ERR_INVALID otherwise).  Two launches on `stream`.
+ */
+int swih_argmax(const float* d_map, int64_t n, uint64_t* d_key, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form.  Sec. 4 applies the likelihood maps to many targets over the
  * frames of a tracking sequence; a batch builds many frames (or search-region

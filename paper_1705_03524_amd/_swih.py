@@ -27,7 +27,7 @@ OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
 EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_build_planes",
             "swih_query", "swih_match", "swih_batch_table_bytes", "swih_batch_plan",
             "swih_build_batch", "swih_query_batch", "swih_match_batch", "swih_gauss_terms",
-            "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match")
+            "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match", "swih_argmax")
 
 
 class SwihError(RuntimeError):
@@ -105,6 +105,8 @@ def load():
     lib.swih_cake_match.restype = C.c_int
     lib.swih_brute_match.argtypes = [cfgp, vp, i32, i32, i32, i32, vp, _Rect, vp, vp]
     lib.swih_brute_match.restype = C.c_int
+    lib.swih_argmax.argtypes = [vp, C.c_int64, vp, vp]
+    lib.swih_argmax.restype = C.c_int
     lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
     lib.swih_gauss_terms.restype = C.c_int
@@ -241,6 +243,22 @@ def brute_match(cfg: Config, img, scale_idx: int, rect, out, template_raw, heigh
                                  _ptr(out), _stream(stream))
     if st != OK:
         raise SwihError(st, "swih_brute_match")
+
+
+def argmax(values, key, stream=None):
+    """swih_argmax of a float device tensor into ``key`` (a 1-element int64 device
+    tensor read as uint64).  Decode with ``argmax_decode``."""
+    st = load().swih_argmax(_ptr(values), int(values.numel()), _ptr(key), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_argmax")
+
+
+def argmax_decode(key: int):
+    """(index, value) from a swih_argmax key."""
+    import struct
+    k = int(key) & 0xFFFFFFFFFFFFFFFF
+    value = struct.unpack("<f", struct.pack("<I", k >> 32))[0]
+    return 0xFFFFFFFF - (k & 0xFFFFFFFF), value
 
 
 def gauss_terms(n: int, K: int = 4):

@@ -18,6 +18,11 @@ the aerial imagery of its Fig. 7 -- are not available; these stand in for them):
 * ``rect_scene``: ``smooth_noise`` plus axis-aligned bright (235) or dark (20)
   rectangles with sides drawn from 20..60, the synthetic stand-in for the
   paper's cluttered tracking scenes (Sec. 2, Fig. 3; Sec. 3, Fig. 5).
+* ``track_sequence``: a moving target over a static ``smooth_noise``
+  background, with distractors that carry exactly the target's pixel values in
+  a different spatial arrangement (the target's values sorted by distance from
+  its centre, handed out in reverse), so a plain histogram cannot tell them
+  apart; the stand-in for the tracking imagery of Sec. 4 (Fig. 7).
 """
 from __future__ import annotations
 
@@ -32,6 +37,7 @@ __all__ = [
     "odd",
     "batch_frames",
     "serving_requests",
+    "track_sequence",
 ]
 
 
@@ -203,3 +209,69 @@ def serving_requests(seed: int, rate: float, n: int, nstreams: int = 16,
         reqs.append({"id": k, "t_arrive": t, "stream": st, "frame_hw": (H, W),
                      "centre": (cx, cy), "scales": scales, "search": search})
     return reqs
+
+
+def _patch_pair(g: np.random.Generator, side: int):
+    """A side x side target whose values rise toward its centre, and a distractor
+    holding the same values (the same multiset) in reverse distance order."""
+    r = (side - 1) // 2
+    yy, xx = np.mgrid[-r:r + 1, -r:r + 1]
+    dist = np.maximum(np.abs(xx), np.abs(yy)) + 0.01 * (np.abs(xx) + np.abs(yy))
+    order = np.argsort(dist.ravel(), kind="stable")            # centre first
+    vals = np.sort(g.integers(20, 256, size=side * side))[::-1]  # brightest first
+    target = np.empty(side * side, np.int64)
+    target[order] = vals
+    distract = np.empty(side * side, np.int64)
+    distract[order] = vals[::-1]
+    return target.reshape(side, side).astype(np.uint8), distract.reshape(side, side).astype(np.uint8)
+
+
+def track_sequence(seed: int, nframes: int = 60, height: int = 480, width: int = 640, side: int = 31,
+                   ndistract: int = 2, speed: float = 4.0):
+    """A synthetic tracking sequence.
+
+    Returns ``(frames, truth, side)``: ``frames`` a list of uint8 (height,
+    width) arrays, ``truth`` an int array [nframes, 2] of the target centre
+    (x, y) per frame.  The target moves along a smooth curve (constant velocity
+    plus a slow sway); each distractor follows its own curve and is drawn
+    under the target where they overlap.
+    """
+    g = rng(seed)
+    bg = smooth_noise(seed + 1, height, width, sigma=4.0) // 2 + 40   # low-contrast clutter
+    target, distract = _patch_pair(g, side)
+    r = (side - 1) // 2
+    margin = r + 2
+
+    def path(start, vel, amp, period):
+        t = np.arange(nframes, dtype=np.float64)
+        p = start[None, :] + vel[None, :] * t[:, None] + amp[None, :] * np.sin(2 * np.pi * t / period)[:, None]
+        lo = np.array([margin, margin])
+        hi = np.array([width - 1 - margin, height - 1 - margin])
+        # fold the curve back into the frame
+        span = hi - lo
+        q = np.mod(p - lo, 2 * span)
+        q = np.where(q > span, 2 * span - q, q)
+        return np.rint(q + lo).astype(np.int64)
+
+    def draw_dir():
+        a = g.uniform(0, 2 * np.pi)
+        return np.array([np.cos(a), np.sin(a)]) * speed
+
+    start = np.array([g.uniform(width * 0.3, width * 0.7), g.uniform(height * 0.3, height * 0.7)])
+    truth = path(start, draw_dir(), g.uniform(5, 15, size=2), g.uniform(20, 40))
+    others = []
+    for _ in range(ndistract):
+        # distractors start a few sides away and cross the target's neighbourhood
+        off = g.uniform(2.5, 4.0) * side * np.array([np.cos(g.uniform(0, 2 * np.pi)),
+                                                     np.sin(g.uniform(0, 2 * np.pi))])
+        others.append(path(start + off, draw_dir() * 0.8, g.uniform(5, 15, size=2), g.uniform(20, 40)))
+    frames = []
+    for f in range(nframes):
+        img = bg.copy()
+        for o in others:
+            x, y = o[f]
+            img[y - r:y + r + 1, x - r:x + r + 1] = distract
+        x, y = truth[f]
+        img[y - r:y + r + 1, x - r:x + r + 1] = target
+        frames.append(img)
+    return frames, truth, side
