@@ -104,6 +104,66 @@ __device__ __forceinline__ long wave_index(int vb) {
 }
 
 // ---------------------------------------------------------------- integer kernels
+// Sums over the set bits of a 64-bit mask of the bit index k and of k^2,
+// from popcounts: k = sum_m 2^m k_m with k_m its bit m, so
+//   sum k   = sum_m 2^m popc(mask & K_m),
+//   sum k^2 = sum_{m,n} 2^(m+n) popc(mask & K_m & K_n),
+// K_m the positions whose bit m is set.  Arithmetic modulo 2^32 like the planes.
+__device__ __constant__ const uint64_t kBitOfIndex[6] = {
+    0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+    0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+__device__ __forceinline__ uint32_t index_sum(uint64_t m) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) s += popc64(m & kBitOfIndex[b]) << b;
+  return s;
+}
+
+__device__ __forceinline__ uint32_t index_sq_sum(uint64_t m) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const uint64_t mb = m & kBitOfIndex[b];
+    s += popc64(mb) << (2 * b);
+#pragma unroll
+    for (int c = b + 1; c < 6; ++c) s += popc64(mb & kBitOfIndex[c]) << (b + c + 1);
+  }
+  return s;
+}
+
+// sum over set bits k of u_i(t0 + k) for the terms {1, t, t^2}
+template <int NI>
+__device__ __forceinline__ void term_sums(uint64_t m, uint32_t t0, uint32_t (&out)[NI]) {
+  const uint32_t c = popc64(m);
+  out[0] = c;
+  if constexpr (NI > 1) {
+    const uint32_t sk = index_sum(m);
+    out[1] = t0 * c + sk;
+    if constexpr (NI > 2) out[2] = t0 * t0 * c + 2u * t0 * sk + index_sq_sum(m);
+  }
+}
+
+// 64 x 64 bit transpose across the wave: lane l holds bits A[l][k]; afterwards
+// lane k holds A[l][k] at bit l.  Each stage swaps bit s of the lane index with
+// bit s of the bit index (the off-diagonal s x s blocks of every 2s x 2s block).
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t m) {
+  const int lane = lane_id();
+  const uint64_t low[6] = {0x5555555555555555ull, 0x3333333333333333ull, 0x0F0F0F0F0F0F0F0Full,
+                           0x00FF00FF00FF00FFull, 0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
+#pragma unroll
+  for (int b = 5; b >= 0; --b) {
+    const int s = 1 << b;
+    const uint32_t plo = (uint32_t)__shfl_xor((int)(uint32_t)m, s, 64);
+    const uint32_t phi = (uint32_t)__shfl_xor((int)(uint32_t)(m >> 32), s, 64);
+    const uint64_t t = ((uint64_t)phi << 32) | plo;
+    m = (lane & s) ? (m & ~low[b]) | ((t & ~low[b]) >> s) : (m & low[b]) | ((t & low[b]) << s);
+  }
+  return m;
+}
+
 template <int KIND>
 __device__ __forceinline__ void aggregate_int(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
@@ -118,28 +178,13 @@ __device__ __forceinline__ void aggregate_int(const BuildArgs& a, int vb) {
   if (!wave_tile(g, wave_index(vb), 1, t, e)) return;
   const int lane = lane_id();
   const int NXP = g.NTX * SWIH_TX;
-  uint32_t zacc[TT::nJ], treg[TT::nI];
-#pragma unroll
-  for (int j = 0; j < TT::nJ; ++j) zacc[j] = 0;
-#pragma unroll
-  for (int i = 0; i < TT::nI; ++i) treg[i] = 0;
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
-  // column sums of this lane's column over the band's rows
-  for (int k = 0; k < t.nrows; ++k) {
-    const uint32_t y = (uint32_t)(t.y0 + k);
-    const uint32_t m = bit_of(mask, k);
-#pragma unroll
-    for (int j = 0; j < TT::nJ; ++j) zacc[j] += m * poly_term(j, y);
-  }
-  // row sums, transposed: lane k gathers row y0 + k over the tile's 64 columns
-  for (int l = 0; l < 64; ++l) {
-    const uint64_t ml = ((uint64_t)readlane((uint32_t)(mask >> 32), l) << 32) |
-                        readlane((uint32_t)mask, l);
-    const uint32_t bit = bit_of(ml, lane);
-    const uint32_t xl = (uint32_t)(t.tx * SWIH_TX + l);
-#pragma unroll
-    for (int i = 0; i < TT::nI; ++i) treg[i] += bit * poly_term(i, xl);
-  }
+  // column sums of this lane's column over the band's rows: v_j(y0 + k) over set bits k
+  uint32_t zacc[TT::nJ];
+  term_sums<TT::nJ>(mask, (uint32_t)t.y0, zacc);
+  // row sums: after the transpose lane k holds row y0 + k over the tile's 64 columns
+  uint32_t treg[TT::nI];
+  term_sums<TT::nI>(wave_transpose64(mask), (uint32_t)(t.tx * SWIH_TX), treg);
 #pragma unroll
   for (int j = 0; j < TT::nJ; ++j)
     z[((size_t)(j * g.B + t.b) * g.NTY + t.ty) * NXP + t.x] = zacc[j];
