@@ -103,6 +103,12 @@ typedef struct {
   const swih_scale* scales; /* host array of nscales entries */
   int32_t gauss_terms;      /* K of the cosine series, 1..8; 0 = default (4) */
   uint32_t flags;           /* reserved, must be 0 */
+  int32_t band_rows;        /* rows of a scan tile, the build's band height: 0 = 64,
+                               else 16, 32 or 64.  Tiles are 64 columns wide (one lane
+                               per column).  Results do not depend on it; speed does
+                               (more, shorter bands fill the GPU on small frames, at
+                               the price of more carries).  Ignored by
+                               SWIH_GAUSSIAN_SEP, which has no tiles. */
 } swih_config;
 
 /* Inclusive rectangle of window CENTRES. */
@@ -269,6 +275,8 @@ typedef struct {
   const swih_scale* scales;  /* host, nscales entries (read by swih_batch_plan only) */
   void* d_ws;                /* device workspace of this frame, 256-byte aligned */
   size_t ws_bytes;           /* >= swih_workspace_bytes of the frame's configuration */
+  int32_t band_rows;         /* 0: the configuration's; else this frame's own scan-tile
+                                rows (16, 32 or 64), e.g. as an autotuner picks per size */
 } swih_frame_desc;
 
 typedef struct {

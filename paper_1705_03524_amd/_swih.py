@@ -42,7 +42,8 @@ class _Scale(C.Structure):
 
 class _Config(C.Structure):
     _fields_ = [("nbins", C.c_int32), ("kernel", C.c_int32), ("nscales", C.c_int32),
-                ("scales", C.POINTER(_Scale)), ("gauss_terms", C.c_int32), ("flags", C.c_uint32)]
+                ("scales", C.POINTER(_Scale)), ("gauss_terms", C.c_int32), ("flags", C.c_uint32),
+                ("band_rows", C.c_int32)]
 
 
 class _Rect(C.Structure):
@@ -52,7 +53,7 @@ class _Rect(C.Structure):
 class _FrameDesc(C.Structure):
     _fields_ = [("d_img", C.c_void_p), ("height", C.c_int32), ("width", C.c_int32),
                 ("pitch", C.c_int32), ("nscales", C.c_int32), ("scales", C.POINTER(_Scale)),
-                ("d_ws", C.c_void_p), ("ws_bytes", C.c_size_t)]
+                ("d_ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("band_rows", C.c_int32)]
 
 
 class _QueryDesc(C.Structure):
@@ -128,6 +129,7 @@ class Config:
     scales: Sequence[tuple] = ((15, 15),)
     gauss_terms: int = 0
     flags: int = 0
+    band_rows: int = 0      # scan-tile rows: 0 = 64, else 16, 32 or 64 (see autotune)
     _c: _Config = field(default=None, init=False, repr=False)
     _arr: object = field(default=None, init=False, repr=False)
 
@@ -140,7 +142,8 @@ class Config:
         arr = (_Scale * max(1, len(self.scales)))(*[_Scale(w, h) for w, h in self.scales])
         self._arr = arr
         self._c = _Config(int(self.nbins), int(self.kernel), len(self.scales),
-                          C.cast(arr, C.POINTER(_Scale)), int(self.gauss_terms), int(self.flags))
+                          C.cast(arr, C.POINTER(_Scale)), int(self.gauss_terms), int(self.flags),
+                          int(self.band_rows))
         return self._c
 
 
@@ -295,7 +298,7 @@ def batch_plan(cfg: Config, frames, queries, matches):
             keep.append(arr)
         fd[k] = _FrameDesc(img.data_ptr(), int(img.shape[0]), int(img.shape[1]), int(img.stride(0)),
                            len(sc) if sc else 0, C.cast(arr, C.POINTER(_Scale)) if arr else None,
-                           f["ws"].data_ptr(), f["ws"].numel())
+                           f["ws"].data_ptr(), f["ws"].numel(), int(f.get("band_rows", 0)))
     qd = (_QueryDesc * max(1, len(queries)))()
     for k, q in enumerate(queries):
         c = q["centres"]

@@ -16,12 +16,14 @@ ALIGN = 256
 class Batch:
     def __init__(self, cfg: S.Config, frames, queries=(), matches=(), device="cuda", ws=None):
         """frames: dicts with ``img`` (2-D uint8 device tensor or crop view) and
-        optional ``scales``; queries / matches as in ``_swih.batch_plan`` (their
-        ``frame`` indexes ``frames``).  ``ws`` may supply the workspace buffer."""
+        optional ``scales`` and ``band_rows``; queries / matches as in
+        ``_swih.batch_plan`` (their ``frame`` indexes ``frames``).  ``ws`` may
+        supply the workspace buffer."""
         self.cfg = cfg
         offs, total = [], 0
         for f in frames:
-            fc = S.Config(cfg.nbins, cfg.kernel, f.get("scales") or cfg.scales, cfg.gauss_terms)
+            fc = S.Config(cfg.nbins, cfg.kernel, f.get("scales") or cfg.scales, cfg.gauss_terms,
+                          band_rows=f.get("band_rows") or cfg.band_rows)
             nb = S.workspace_bytes(fc, f["img"].shape[0], f["img"].shape[1])
             offs.append((total, nb))
             total += (nb + ALIGN - 1) // ALIGN * ALIGN

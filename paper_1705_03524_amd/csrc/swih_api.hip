@@ -30,6 +30,8 @@ int check_config(const swih_config* c, int32_t H, int32_t W) {
   if (!c || H < 1 || W < 1 || H > kMaxSide || W > kMaxSide) return SWIH_ERR_INVALID;
   if (c->nbins < 1 || c->nbins > 256 || !kind_ok(c->kernel) || c->flags != 0)
     return SWIH_ERR_INVALID;
+  if (c->band_rows != 0 && c->band_rows != 16 && c->band_rows != 32 && c->band_rows != 64)
+    return SWIH_ERR_INVALID;
   if (c->nscales < 1 || !c->scales) return SWIH_ERR_INVALID;
   if (series_kind(c->kernel)) {
     const int32_t K = gauss_K(c);
@@ -66,7 +68,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     L.total = L.set_bytes * L.nsets;
     return SWIH_OK;
   }
-  g.TY = kDefaultTY;
+  g.TY = c->band_rows ? c->band_rows : kDefaultTY;
   g.NTX = (W + SWIH_TX - 1) / SWIH_TX;
   g.NTY = (H + g.TY - 1) / g.TY;
   if (c->kernel == SWIH_EXPONENTIAL) {  // four direction planes per bin (swih_exp.hip)
@@ -508,13 +510,15 @@ BatchHeader table_layout(int32_t kind, int32_t nunits, int32_t nq, int32_t nm) {
   return h;
 }
 
-// The frame's own configuration: the batch configuration with its scales.
+// The frame's own configuration: the batch configuration with its scales and
+// scan-tile rows.
 swih_config frame_config(const swih_config* cfg, const swih_frame_desc& f) {
   swih_config c = *cfg;
   if (f.nscales > 0) {
     c.nscales = f.nscales;
     c.scales = f.scales;
   }
+  if (f.band_rows != 0) c.band_rows = f.band_rows;
   return c;
 }
 

@@ -22,7 +22,7 @@
 // which the build runs down each 64-column tile of a 64-row band in double,
 // with three carries made exactly like the integer kernels' (aggregate, scan,
 // emit): the band-top column values, the row values at the tile's left edge
-// and the tile-origin values E(64 tx, 64 ty), each a chain with the decay of
+// and the tile-origin values E(64 tx, TY ty), each a chain with the decay of
 // one tile or band.  The planes are stored as float (relative error 2^-24).
 #include <math.h>
 #include <string.h>
@@ -35,7 +35,6 @@ namespace {
 
 constexpr int WG = 256;
 constexpr int WPB = WG / 64;
-constexpr int TY = 64;  // band height of the exponential build
 
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -100,8 +99,8 @@ __device__ __forceinline__ bool exp_tile(const SwihGeom& g, long wid, ExpTile& t
   r /= g.NTY;
   t.b = (int)(r % g.B);
   t.d = (int)(r / g.B);
-  t.y0 = t.ty * TY;
-  t.nrows = min(TY, g.H - t.y0);
+  t.y0 = t.ty * g.TY;
+  t.nrows = min(g.TY, g.H - t.y0);
   return true;
 }
 
@@ -137,8 +136,8 @@ __device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const E
 __device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)(uint32_t)((m >> k) & 1); }
 
 // ---------------------------------------------------------------- build
-// Aggregate: per (direction, bin, band, tile) wave
-//   z  [X]  = sum_{X0 <= x < X, y in band} [Q = b] qx^(X - x) qy^(Y0 + 64 - y)
+// Aggregate: per (direction, bin, band, tile) wave (band of TY rows)
+//   z  [X]  = sum_{X0 <= x < X, y in band} [Q = b] qx^(X - x) qy^(Y0 + TY - y)
 //   CT      = the same at X = X0 + 64 (the tile total)
 //   T  [y]  = sum_{x in tile} [Q = b] qx^(X0 + 64 - x)      (lane = row)
 __device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
@@ -149,9 +148,8 @@ __device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
   const long NXP = (long)g.NTX * 64;
   const uint64_t mask = exp_band_mask(a, t);
   const double qy = exp(-a.ity), qx = exp(-a.itx);
-  double c = 0.0;  // this column's band sum, relative to row Y0 + 64
-#pragma unroll
-  for (int k = 0; k < 64; ++k) c = (c + mbit(mask, k)) * qy;
+  double c = 0.0;  // this column's band sum, relative to row Y0 + TY
+  for (int k = 0; k < g.TY; ++k) c = (c + mbit(mask, k)) * qy;
   const double zl = qx * leaky_scan(c, make_leaky(a.itx));
   const long db = (long)t.d * g.B + t.b;
   a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane] = zl;
@@ -170,7 +168,7 @@ __device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
 
 // Scan: three independent chains.
 //   role 1, one thread per (direction, bin, column): z over bands becomes the
-//     band-top value Zc (exclusive), Zc' = qy^64 Zc + z;
+//     band-top value Zc (exclusive), Zc' = qy^TY Zc + z;
 //   role 2, one thread per (direction, bin, row): T over tiles becomes the row
 //     value at the tile's left edge (exclusive), C' = qx^64 C + T;
 //   role 3, one wave per (direction, bin): CT becomes E(64 tx, 64 ty), with an
@@ -182,7 +180,7 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
     const long t = (long)vb * WG + threadIdx.x;
     if (t >= 4L * g.B * NXP) return;
     const long db = t / NXP, col = t - db * NXP;
-    const double qT = exp(-a.ity * TY);
+    const double qT = exp(-a.ity * g.TY);
     double* z = a.z + db * g.NTY * NXP + col;
     double carry = 0.0;
     for (int ty = 0; ty < g.NTY; ++ty) {
@@ -213,7 +211,7 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
   if (wid >= 4L * g.B) return;
   const int lane = lane_id();
   double* CT = a.CT + wid * g.NTY * g.NTX;
-  const double qyT = exp(-a.ity * TY);
+  const double qyT = exp(-a.ity * g.TY);
   const double gx = a.itx * 64.0;
   const Leaky Lt = make_leaky(gx);
   const double up = exp(-gx * (double)(lane + 1));  // decay from tile 63 of the first chunk

@@ -73,7 +73,7 @@ class Request:
 
 
 def unit_bytes(cfg, w, h, uh, uw):
-    c = S.Config(cfg.nbins, cfg.kernel, [(w, h)], cfg.gauss_terms)
+    c = S.Config(cfg.nbins, cfg.kernel, [(w, h)], cfg.gauss_terms, band_rows=cfg.band_rows)
     nb = S.workspace_bytes(c, uh, uw)
     return (nb + ALIGN - 1) // ALIGN * ALIGN
 
@@ -276,7 +276,7 @@ class SerialServer:
             for (w, h), (box, tc, rect) in zip(r.scales, r.units):
                 ux0, uy0, ux1, uy1 = box
                 view = crop[uy0:uy1 + 1, ux0:ux1 + 1]
-                uc = S.Config(cfg.nbins, cfg.kernel, [(w, h)], cfg.gauss_terms)
+                uc = S.Config(cfg.nbins, cfg.kernel, [(w, h)], cfg.gauss_terms, band_rows=cfg.band_rows)
                 nb = S.workspace_bytes(uc, view.shape[0], view.shape[1])
                 p = Plan(uc, view.shape[0], view.shape[1], ws=self.ws[:nb])
                 p.build(view)

@@ -49,6 +49,7 @@ class Unit:
     img: torch.Tensor       # 2-D uint8 device view (frame or crop)
     scales: list
     jobs: list = field(default_factory=list)
+    band_rows: int = 0      # scan-tile rows of this unit's build (0: the configuration's)
 
 
 def _valid(rect, w, h, H, W):
@@ -98,7 +99,17 @@ def tracking_units(cfg: S.Config, frames, device="cuda"):
 
 
 def unit_config(cfg: S.Config, u: Unit) -> S.Config:
-    return S.Config(cfg.nbins, cfg.kernel, u.scales, cfg.gauss_terms)
+    return S.Config(cfg.nbins, cfg.kernel, u.scales, cfg.gauss_terms, band_rows=u.band_rows or cfg.band_rows)
+
+
+def tune_units(cfg: S.Config, units, tuner) -> dict:
+    """Set every unit's scan-tile rows from the autotuner; returns the choice per size class."""
+    chosen = {}
+    for u in units:
+        H, W = u.img.shape
+        u.band_rows = tuner.best(unit_config(cfg, u), H, W)
+        chosen[tuner.size_class(H, W)] = u.band_rows
+    return chosen
 
 
 def unit_bytes(cfg: S.Config, u: Unit) -> int:
@@ -130,7 +141,7 @@ class BatchedRunner:
         for g in groups:
             frames, queries, matches = [], [], []
             for fi, u in enumerate(g):
-                frames.append({"img": u.img, "scales": u.scales})
+                frames.append({"img": u.img, "scales": u.scales, "band_rows": u.band_rows})
                 for j in u.jobs:
                     si = u.scales.index(j.scale)
                     cen = torch.tensor([j.centre], dtype=torch.int32, device=device)

@@ -199,3 +199,14 @@ def test_baseline_host_checks():
     st = lib.swih_brute_match(C.byref(m.c()), C.c_void_p(256), 64, 64, 64, 0, C.c_void_p(256), bad,
                               C.c_void_p(256), None)
     assert st == _swih.ERR_INVALID
+
+
+def test_band_rows_validation_and_layout():
+    base = swih.Config(16, swih.MANHATTAN, [(31, 31)])
+    n64 = swih.workspace_bytes(base, 512, 512)
+    for rows in (16, 32, 64):
+        n = swih.workspace_bytes(swih.Config(16, swih.MANHATTAN, [(31, 31)], band_rows=rows), 512, 512)
+        assert n >= n64 if rows < 64 else n == n64        # more bands, more carries; planes unchanged
+    for rows in (8, 48, 128, -1):
+        with pytest.raises(swih.SwihError):
+            swih.workspace_bytes(swih.Config(16, swih.MANHATTAN, [(31, 31)], band_rows=rows), 512, 512)

@@ -1,0 +1,110 @@
+"""Scan-tile rows (band_rows) on the GPU: results hold for every choice, a batch
+may mix choices per frame, and the autotuner picks and caches one.
+
+* integer kernels: histograms and maps bit-exact against the oracle for 16 and
+  32 rows (as for the default 64);
+* the 2-D Gaussian and the exponential: within their oracle bars;
+* a batch whose frames use different rows equals the single-frame calls.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_03524_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1705_03524_amd as swih  # noqa: E402
+from paper_1705_03524_amd.autotune import Autotuner  # noqa: E402
+from paper_1705_03524_amd.batch import Batch  # noqa: E402
+from paper_1705_03524_amd.plan import Plan  # noqa: E402
+
+from gpu_util import EXP_TOL, GAUSS_TOL, all_centres, map_tolerance, to_dev  # noqa: E402
+
+
+@pytest.mark.parametrize("rows", [16, 32])
+@pytest.mark.parametrize("kind", [swih.UNIFORM, swih.MANHATTAN, swih.EUCLIDEAN])
+@pytest.mark.parametrize("HW,nb,wh", [((100, 77), 3, (5, 9)), ((130, 200), 16, (31, 21)), ((33, 40), 7, (33, 33))])
+def test_integer_exact_for_every_band_height(rows, kind, HW, nb, wh):
+    H, W = HW
+    w, h = wh
+    print("case: band rows %d kind %d %dx%d" % (rows, kind, H, W), flush=True)
+    img = synth.uniform_noise(H + 5 * W + rows, H, W)
+    plan = Plan(swih.Config(nb, kind, [(w, h)], band_rows=rows), H, W)
+    plan.build(to_dev(img, torch))
+    c = all_centres(H, W, w, h)
+    _, raw = plan.query(0, to_dev(c, torch))
+    assert np.array_equal(raw.cpu().numpy().astype(np.int64), oracle.hist(img, nb, kind, w, h, c))
+    tc = tuple(c[len(c) // 2])
+    tref, _ = oracle.template(img, nb, kind, w, h, tc)
+    m = plan.match(0, template_raw=torch.tensor(tref.astype(np.uint32), device="cuda"))
+    assert np.array_equal(m.cpu().numpy(), oracle.bc_map(img, nb, kind, w, h, tref).astype(np.float32))
+
+
+@pytest.mark.parametrize("rows", [16, 32])
+@pytest.mark.parametrize("kind,okind,tol", [(swih.GAUSSIAN, oracle.GAUSSIAN, GAUSS_TOL),
+                                            (swih.EXPONENTIAL, oracle.EXPONENTIAL, EXP_TOL)])
+def test_real_kernels_for_every_band_height(rows, kind, okind, tol):
+    H, W = 200, 170
+    print("case: band rows %d kind %d" % (rows, kind), flush=True)
+    img = synth.smooth_noise(rows + kind, H, W)
+    plan = Plan(swih.Config(16, kind, [(31, 21)], band_rows=rows), H, W)
+    plan.build(to_dev(img, torch))
+    c = all_centres(H, W, 31, 21)
+    got = plan.query(0, to_dev(c, torch))[0].cpu().numpy().astype(np.float64)
+    ref = oracle.normalised(oracle.hist(img, 16, okind, 31, 21, c), okind, 31, 21)
+    assert np.abs(got - ref).max() <= tol
+    # the map against the oracle's, within the bound the histogram bar implies (oracle template)
+    _, tref = oracle.template(img, 16, okind, 31, 21, tuple(c[0]))
+    rect = (15, 10, 60, 40)
+    m = plan.match(0, template=to_dev(tref.astype(np.float32), torch), rect=rect).cpu().numpy()
+    mref = oracle.bc_map(img, 16, okind, 31, 21, tref, rect=rect)
+    ys, xs = np.mgrid[rect[1]:rect[3] + 1, rect[0]:rect[2] + 1]
+    cc = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+    pref = oracle.normalised(oracle.hist(img, 16, okind, 31, 21, cc), okind, 31, 21)
+    bound = map_tolerance(pref, tref, tol, template_exact=True).reshape(mref.shape) + 1e-6
+    assert np.all(np.abs(m - mref) <= bound)
+
+
+@pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.GAUSSIAN, swih.EXPONENTIAL])
+def test_batch_mixes_band_heights(kind):
+    print("case: batch with mixed band rows, kind %d" % kind, flush=True)
+    sizes = [(97, 131), (256, 300), (64, 64), (150, 90)]
+    rows = [16, 64, 32, 16]
+    imgs = [to_dev(synth.smooth_noise(60 + k, H, W), torch) for k, (H, W) in enumerate(sizes)]
+    cfg = swih.Config(16, kind, [(15, 15)])
+    integer = kind == swih.MANHATTAN
+    frames, queries, matches, outs = [], [], [], []
+    for fi, (img, r) in enumerate(zip(imgs, rows)):
+        H, W = img.shape
+        frames.append({"img": img, "band_rows": r})
+        cen = torch.tensor([[W // 2, H // 2]], dtype=torch.int32, device="cuda")
+        hist = torch.empty((1, 16), dtype=torch.float32, device="cuda")
+        raw = torch.empty((1, 16), dtype=torch.uint32, device="cuda") if integer else None
+        queries.append({"frame": fi, "centres": cen, "hist": hist, "hist_raw": raw})
+        out = torch.empty((H - 14, W - 14), dtype=torch.float32, device="cuda")
+        m = {"frame": fi, "rect": (7, 7, W - 8, H - 8), "out": out}
+        m["template_raw" if integer else "template"] = raw[0] if integer else hist[0]
+        matches.append(m)
+        outs.append((cen, hist, raw, out))
+    b = Batch(cfg, frames, queries, matches)
+    b.run()
+    torch.cuda.synchronize()
+    for (img, r), (cen, hist, raw, out) in zip(zip(imgs, rows), outs):
+        p = Plan(swih.Config(16, kind, [(15, 15)], band_rows=r), img.shape[0], img.shape[1])
+        p.build(img)
+        h, rw = p.query(0, cen)
+        assert torch.equal(h, hist)
+        o = p.match(0, template_raw=rw[0].contiguous()) if integer else p.match(0, template=h[0].contiguous())
+        assert torch.equal(o, out)
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    t = Autotuner(str(tmp_path / "tune.json"), reps=2)
+    for kind in (swih.MANHATTAN, swih.GAUSSIAN):
+        cfg = swih.Config(16, kind, [(31, 31)])
+        r = t.best(cfg, 300, 400)
+        print("autotune kind %d ->" % kind, r, t.timings, flush=True)
+        assert r in (16, 32, 64)
+        assert Autotuner(str(tmp_path / "tune.json")).best(cfg, 300, 400) == r
