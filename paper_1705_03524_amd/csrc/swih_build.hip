@@ -452,12 +452,11 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int p = i * NT + j;
-    const size_t pb = (size_t)(p * g.B + t.b);
     lbase[j] = (size_t)(swih_base(g, p, t.b) + t.tx * g.tile_stride + lane);
     L[j] = 0.0;
     if (t.ty == 0) {
       Lp[lbase[j]] = 0.0f;
-      if (lane == 0) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1)] = 0.0;
+      if (lane == 0) RCp[swih_rc(g, p, t.b, t.tx, 0)] = 0.0;
     }
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
@@ -490,7 +489,7 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     const double term = (double)vq[(size_t)yl * NT + j] * (double)ereg;
     const double rc =
         (CTc[(pb * g.NTY + t.ty) * g.NTX + t.tx] + wave_incl_scan(term)) * sc48;
-    if (lane < t.nrows) RCp[(pb * g.NTX + t.tx) * (size_t)(g.H + 1) + t.y0 + 1 + lane] = rc;
+    if (lane < t.nrows) RCp[swih_rc(g, p, t.b, t.tx, t.y0 + 1 + lane)] = rc;
   }
 }
 

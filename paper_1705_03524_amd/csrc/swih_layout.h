@@ -31,6 +31,8 @@
 // Gaussian stores it split per tile (tile origin Xo = 64 tx, Yo = TY ty):
 //   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X  (float, bounded by the tile)
 //   RC[tx][Y] = P[Y][Xo]                          (double, per row and tile column)
+// RC is stored [bin][Y][tx][plane] (planes fastest): a lookup needs every plane of
+// a few tiles at one row, which is then one contiguous run.
 // with tx = tile of column X, ty = band of row Y, and zeros at row/column 0.
 // Only window boxes are ever needed, and they follow from vertical
 // differences at fixed X:
@@ -75,6 +77,11 @@ __host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, in
   return swih_base(g, p, b) + (int64_t)Y * g.row_stride + swih_xoff(g, X);
 }
 
+// Element offset of the Gaussian row carry RC[tx][Y] of plane p, bin b.
+__host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int p, int b, int tx, int Y) {
+  return (((int64_t)b * (g.H + 1) + Y) * g.NTX + tx) * g.nP + p;
+}
+
 // Byte offsets inside one workspace.  All regions are 256-byte aligned.
 struct SwihLayout {
   SwihGeom g;
@@ -82,7 +89,7 @@ struct SwihLayout {
   int64_t set_bytes;     // bytes of one plane set (planes [+ RC + tables])
   // inside a set
   int64_t off_planes;    // uint32 or float planes, tile-major (above)
-  int64_t off_RC;        // double [nP][B][NTX][H+1]              (Gaussian)
+  int64_t off_RC;        // double [B][H+1][NTX][nP], swih_rc     (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
   int64_t off_acc;       // int64 [H * W] map accumulator of the comb-form map (Gaussian)

@@ -222,10 +222,9 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
     double hi = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const size_t pb = (size_t)((i * NT + j) * g.B + b);
-      const double* rA = gp.RC + (pb * g.NTX + txa) * (size_t)(g.H + 1);
-      const double* rB = gp.RC + (pb * g.NTX + txb) * (size_t)(g.H + 1);
-      d[j] += (rB[yb] - rB[ya]) - (rA[yb] - rA[ya]);
+      const int p = i * NT + j;
+      d[j] += (gp.RC[swih_rc(g, p, b, txb, yb)] - gp.RC[swih_rc(g, p, b, txb, ya)]) -
+              (gp.RC[swih_rc(g, p, b, txa, yb)] - gp.RC[swih_rc(g, p, b, txa, ya)]);
       hi = fma(be[j], d[j], hi);
     }
     part[it] = al[i] * hi;
@@ -320,9 +319,8 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const size_t pb = (size_t)((i * NT + j) * g.B + b);
-      const double* rcp = gp.RC + (pb * g.NTX + tlo + t) * (size_t)(g.H + 1);
-      acc = fma(be[j], rcp[Yb] - rcp[Ya], acc);
+      const int p = i * NT + j;
+      acc = fma(be[j], gp.RC[swih_rc(g, p, b, tlo + t, Yb)] - gp.RC[swih_rc(g, p, b, tlo + t, Ya)], acc);
     }
     R[(b * NT + i) * ntl_max + t] = acc;
   }
@@ -455,9 +453,9 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const size_t pb = (size_t)((i * NT + j) * g.B + b);
-      const double* rcp = gp.RC + (pb * g.NTX + tlo + t) * (size_t)(g.H + 1);
-      acc = fma(BE[mm * NT + j], rcp[yb] - rcp[ya], acc);
+      const int p = i * NT + j;
+      acc = fma(BE[mm * NT + j], gp.RC[swih_rc(g, p, b, tlo + t, yb)] - gp.RC[swih_rc(g, p, b, tlo + t, ya)],
+                acc);
     }
     R[(mm * NT + i) * ntl_max + t] = acc;
   }
