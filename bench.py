@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("frame", "batch", "serve", "sweep", "track"), default="frame",
+    ap.add_argument("--workload", choices=("frame", "batch", "serve", "sweep", "track", "builds"),
+                    default="frame",
                     help="frame: the 512x512 single-frame path (default); batch: 64 uneven "
                          "frames with 1-8 targets x 3 scales, batched vs per-frame; serve: "
                          "Poisson tracking requests, continuous batching vs one at a time")
@@ -54,6 +55,9 @@ def parse():
                          "or in separable form")
     ap.add_argument("--budget-gb", type=float, default=64.0,
                     help="batch workload: workspace budget of one Gaussian sub-batch")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the measurements reported beside the step (separable Gaussian, exponential, "
+                         "2048x2048 builds), so a profile of the run covers the step's launches only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (known bytes) so HBM "
                          "counters of a profiling run can be scaled")
@@ -277,6 +281,73 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def w3_builds(rep_small=10):
+    """The build at the multi-scale configuration's size (2048 x 2048 smooth
+    noise, 32 bins, one 31 x 31 scale) for Manhattan, exponential and Gaussian:
+    carries and planes timed as graphs of back-to-back launches; algorithmic
+    bytes = image read + every plane element written once."""
+    import torch
+    import paper_1705_03524_amd as swih
+    from paper_1705_03524_amd.plan import Plan
+
+    def capture(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        return g
+
+    W3 = 2048
+    w3 = {}
+    w3_img = torch.from_numpy(synth_smooth(W3)).cuda()
+    for i, kname in enumerate(("manhattan", "exponential", "gaussian")):
+        bp = Plan(swih.Config(32, kname, [(WIN, WIN)]), W3, W3)
+        # the first timed kernel of a fresh process runs before the clocks have
+        # ramped up: ~50 ms of builds beforehand
+        for _ in range(150 if i == 0 else 1):
+            swih.build(bp.cfg, w3_img, bp.ws, W3, W3, W3)
+        torch.cuda.synchronize()
+        rep = 2 if kname == "gaussian" else rep_small
+        t = {}
+        for ph in ("carries", "planes"):
+            g = capture(lambda: [swih.build_phase(bp.cfg, w3_img, bp.ws, ph, 0) for _ in range(rep)])
+            g.replay()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            t[ph] = a.elapsed_time(b) / (3 * rep)
+            del g
+        planes = 4 * bp.nplanes * 32 * (W3 + 1) * (W3 + 1)
+        build_ms = t["carries"] + t["planes"]
+        w3[kname] = {"ms": t, "plane_bytes": planes,
+                     "build_gbs": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9,
+                     "build_frac": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "planes_gbs": planes / (t["planes"] / 1e3) / 1e9}
+        del bp
+        torch.cuda.empty_cache()
+    return w3
+
+
+def bench_builds(args):
+    """The 2048 x 2048, 32-bin builds alone (the headline build-bandwidth measurement)."""
+    w3 = w3_builds()
+    line = {"metric": "IH-build HBM GB/s", "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
+            "data": "synthetic", "dtype": "u32/f32/f64",
+            "config": {"workload": "2048x2048 smooth noise, 32 bins, 31x31 scale: Manhattan, exponential, "
+                                   "Gaussian K=4 builds (carries + planes)", "parallelism": "none"},
+            "value": w3["manhattan"]["build_gbs"], "builds": w3}
+    print(json.dumps(line), flush=True)
+
+
 def bench_sweep(args):
     """The comparison of Sec. 3 on synthetic images: time of the likelihood map
     against window size (Fig. 6: 640x480 and 1024x1024, Manhattan, 16 bins) for
@@ -467,6 +538,9 @@ def main():
     if args.workload == "track":
         bench_track(args)
         return
+    if args.workload == "builds":
+        bench_builds(args)
+        return
     import torch
     import paper_1705_03524_amd as swih
     from paper_1705_03524_amd.plan import Plan
@@ -600,46 +674,28 @@ def main():
             del g
         return sp, smap, ms_
 
-    # (the separable form's carries phase launches nothing)
-    _, smap, sep_ms = side_kind("gaussian_sep", ("planes", "query", "match"))
-    sep_total = sum(sep_ms.values())
-    sep_diff = float((smap - maps["gaussian"]).abs().max())
-    ep, _, exp_ms = side_kind("exponential", PHASES)
-    exp_total = sum(exp_ms.values())
-    exp_build = exp_ms["carries"] + exp_ms["planes"]
+    extras = {}
+    if not args.no_extras:
+        # (the separable form's carries phase launches nothing)
+        _, smap, sep_ms = side_kind("gaussian_sep", ("planes", "query", "match"))
+        sep_total = sum(sep_ms.values())
+        ep, _, exp_ms = side_kind("exponential", PHASES)
+        exp_total = sum(exp_ms.values())
+        exp_build = exp_ms["carries"] + exp_ms["planes"]
+        nwin_ = (H - WIN + 1) * (W - WIN + 1)
+        extras["gaussian_separable"] = {
+            "ms": sep_ms, "ms_total": sep_total, "windows_per_s": nwin_ / (sep_total / 1e3),
+            "speedup_vs_2d_gaussian": (per["build_gaussian"] + per["query_gaussian"] +
+                                       per["match_gaussian"]) / sep_total,
+            "max_abs_map_diff_vs_2d": float((smap - maps["gaussian"]).abs().max())}
+        extras["exponential"] = {
+            "ms": exp_ms, "ms_total": exp_total, "windows_per_s": nwin_ / (exp_total / 1e3),
+            "ih_build_gbs": (H * W + 4 * ep.nplanes * NBINS * (H + 1) * (W + 1)) / (exp_build / 1e3) / 1e9,
+            "planes_gbs": 4 * ep.nplanes * NBINS * (H + 1) * (W + 1) / (exp_ms["planes"] / 1e3) / 1e9}
 
-    # The build at the multi-scale configuration's size (2048 x 2048 smooth
-    # noise, 32 bins, one 31 x 31 scale): algorithmic bytes = image read +
-    # every plane element written once.
-    W3 = 2048
-    w3_img = torch.from_numpy(synth_smooth(W3)).cuda()
-    w3 = {}
-    for kname in ("manhattan", "exponential", "gaussian"):
-        bp = Plan(swih.Config(32, kname, [(WIN, WIN)]), W3, W3)
-        swih.build(bp.cfg, w3_img, bp.ws, W3, W3, W3)
-        torch.cuda.synchronize()
-        rep = 2 if kname == "gaussian" else REP
-        t = {}
-        for ph in ("carries", "planes"):
-            g = capture(lambda: [swih.build_phase(bp.cfg, w3_img, bp.ws, ph, 0) for _ in range(rep)])
-            g.replay()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(3):
-                g.replay()
-            b.record()
-            torch.cuda.synchronize()
-            t[ph] = a.elapsed_time(b) / (3 * rep)
-            del g
-        planes = 4 * bp.nplanes * 32 * (W3 + 1) * (W3 + 1)
-        build_ms = t["carries"] + t["planes"]
-        w3[kname] = {"ms": t, "plane_bytes": planes,
-                     "build_gbs": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9,
-                     "build_frac": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "planes_gbs": planes / (t["planes"] / 1e3) / 1e9}
-        del bp
-        torch.cuda.empty_cache()
-    del w3_img
+    w3 = {} if args.no_extras else w3_builds(REP)
+    if w3:
+        extras["ih_build_2048x2048_32bins"] = w3
 
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)
@@ -687,17 +743,8 @@ def main():
         # IH build (carries + planes) in algorithmic GB/s: image read + planes written
         "ih_build_gbs": {k: (H * W + 4 * plans[k].nplanes * NBINS * (H + 1) * (W + 1)) /
                             (per["build_" + k] / 1e3) / 1e9 for k in KERNELS},
-        "gaussian_separable": {
-            "ms": sep_ms, "ms_total": sep_total, "windows_per_s": nwin / (sep_total / 1e3),
-            "speedup_vs_2d_gaussian": (per["build_gaussian"] + per["query_gaussian"] +
-                                       per["match_gaussian"]) / sep_total,
-            "max_abs_map_diff_vs_2d": sep_diff},
-        "ih_build_2048x2048_32bins": w3,
-        "exponential": {
-            "ms": exp_ms, "ms_total": exp_total, "windows_per_s": nwin / (exp_total / 1e3),
-            "ih_build_gbs": (H * W + 4 * ep.nplanes * NBINS * (H + 1) * (W + 1)) / (exp_build / 1e3) / 1e9,
-            "planes_gbs": 4 * ep.nplanes * NBINS * (H + 1) * (W + 1) / (exp_ms["planes"] / 1e3) / 1e9},
     }
+    line.update(extras)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(img, tc, args.cpu_seconds)
     print(json.dumps(line), flush=True)
