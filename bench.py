@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--seconds", type=float, default=1.0,
                     help="serve workload: arrival span per rate")
     ap.add_argument("--gaussian", choices=("2d", "separable"), default="2d",
-                    help="batch / serve workloads: the Gaussian as 2-D planes (81 weight terms) "
+                    help="batch / serve workloads: the Gaussian as 2-D planes (49 weight terms) "
                          "or in separable form")
     ap.add_argument("--budget-gb", type=float, default=64.0,
                     help="batch workload: workspace budget of one Gaussian sub-batch")
@@ -139,7 +139,7 @@ def measured_traffic(kernel_prefix):
 def bench_batch(args):
     """64 uneven frames (256..1920 x 256..1080), 1-8 targets of side 16..128,
     3 scales each, search region 3s x 3s, 16 bins; Manhattan (one build per
-    frame) and Gaussian K=4 (one build per target-scale search crop).  Times
+    frame) and Gaussian K=3 (one build per target-scale search crop).  Times
     the plain per-frame loop of single calls, the batched form, and the batched
     form replayed from one HIP graph; checks batched == per-frame bit for bit."""
     import torch
@@ -224,7 +224,7 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
         "data": "synthetic",
         "config": {"workload": "batch: 64 uneven frames 256..1920 x 256..1080, 1-8 targets side "
-                               "16..128 x 3 scales, search 3s x 3s, 16 bins, Manhattan + Gaussian K=4 "
+                               "16..128 x 3 scales, search 3s x 3s, 16 bins, Manhattan + Gaussian K=3 "
                                "(%s)" % ("separable" if args.gaussian == "separable" else "2-D planes"),
                    "global_batch": 64, "seq_len": None, "parallelism": "none"},
         "per_frame_windows_per_s": total_windows / (total_ms["per_frame"] / 1e3),
@@ -237,7 +237,7 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Poisson tracking requests from 16 streams (frames 640x480..4096x2160,
-    target 24..96 px, 3 scales, search 2-4x target, 16 bins, Gaussian K=4);
+    target 24..96 px, 3 scales, search 2-4x target, 16 bins, Gaussian K=3);
     continuous batching (3 in-flight micro-batches, 24 GiB workspace each) vs
     one request at a time, swept over arrival rates."""
     import torch
@@ -272,7 +272,7 @@ def bench_serve(args):
         "steps": len(sweep), "warmup": 1, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve: Poisson tracking requests, 16 streams, frames 640x480..4096x2160, "
-                               "target 24..96, 3 scales, search 2-4x, 16 bins, Gaussian K=4 (%s)"
+                               "target 24..96, 3 scales, search 2-4x, 16 bins, Gaussian K=3 (%s)"
                                % ("separable" if args.gaussian == "separable" else "2-D planes"),
                    "global_batch": None, "seq_len": None, "parallelism": "none"},
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "rate": sweep[-1]["rate"],
@@ -343,7 +343,7 @@ def bench_builds(args):
     line = {"metric": "IH-build HBM GB/s", "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
             "data": "synthetic", "dtype": "u32/f32/f64",
             "config": {"workload": "2048x2048 smooth noise, 32 bins, 31x31 scale: Manhattan, exponential, "
-                                   "Gaussian K=4 builds (carries + planes)", "parallelism": "none"},
+                                   "Gaussian K=3 builds (carries + planes)", "parallelism": "none"},
             "value": w3["manhattan"]["build_gbs"], "builds": w3}
     print(json.dumps(line), flush=True)
 
@@ -699,14 +699,14 @@ def main():
 
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)
-    # Algorithmic bytes of the two Gaussian kernels (81 weight terms x 16 bins):
+    # Algorithmic bytes of the two Gaussian kernels ((2K+1)^2 weight terms x 16 bins):
     # the plane build reads the image once and writes every plane element once;
     # the dense map reads every plane element once and writes one float per centre.
-    K = 4
+    K = plans["gaussian"].cfg.K
     T = (2 * K + 1) ** 2
     plane_bytes = 4 * T * NBINS * (H + 1) * (W + 1)
     kernels = {
-        "build": {"kernel": "k_emit_gauss (Gaussian plane build, 81 terms x 16 bins)",
+        "build": {"kernel": "k_emit_gauss (Gaussian plane build, %d terms x 16 bins)" % T,
                   "alg": H * W + plane_bytes, "ms": per["planes_gaussian"], "prefix": "k_emit_gauss<"},
         "match": {"kernel": "k_match_gauss_comb + k_match_gauss_fin (Gaussian dense likelihood map, "
                             "482x482 centres; the finalising pass is ~1% of the phase)",
@@ -735,7 +735,7 @@ def main():
         "dtype": "u32+f32",
         "data": "synthetic",
         "config": {"workload": "512x512 scene, 16 bins, 31x31 windows, Manhattan+Euclidean+Gaussian "
-                               "(sigma=w/4, K=4), full Bhattacharyya map of 482x482 centres per kernel",
+                               "(sigma=w/4, K=3), full Bhattacharyya map of 482x482 centres per kernel",
                    "global_batch": 1, "seq_len": None, "parallelism": "none"},
         "roofline": roof(kernels[dominant]),
         "roofline_" + other: roof(kernels[other]),

@@ -101,7 +101,7 @@ typedef struct {
   int32_t kernel;           /* swih_kernel */
   int32_t nscales;          /* >= 1 */
   const swih_scale* scales; /* host array of nscales entries */
-  int32_t gauss_terms;      /* K of the cosine series, 1..8; 0 = default (4) */
+  int32_t gauss_terms;      /* K of the cosine series, 1..8; 0 = default (3) */
   uint32_t flags;           /* reserved, must be 0 */
   int32_t band_rows;        /* rows of a scan tile, the build's band height: 0 = 64,
                                else 16, 32 or 64.  Tiles are 64 columns wide (one lane
@@ -316,19 +316,24 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream);
 
 /*
  * The cosine series that stands in for one axis of the Gaussian kernel:
- *   g(t) ~= sum_{k=0..K} a_k cos(2 pi k t / P),  t in [-r, r], r = (n-1)/2,
- * least-squares fitted to exp(-t^2 / (2 (n/4)^2)) at the integer offsets,
- * with the integer period P >= n chosen to minimise the worst normalised
- * 2-D histogram error of the separable product.  Each cosine term splits into
- * cos/sin products of the absolute coordinates and the window centre, which is
- * what makes the Gaussian decomposable into 2K+1 weight terms per axis.
- *   n      odd window side, 1..4095
- *   K      1..8
- *   a_out  host double [K+1] (may be NULL); period_out host int32 (may be NULL)
- *   err_out host double: the worst normalised histogram error of the square
- *          n x n window with this series (may be NULL)
+ *   g(t) ~= sum_{k=0..K} a_k cos(w_k t),  t in [-r, r], r = (n-1)/2,
+ * with w_0 = 0 < w_1 < ... < w_K, fitted to exp(-t^2 / (2 (n/4)^2)) at the
+ * integer offsets: coefficients by least squares, frequencies refined from
+ * harmonic starts by Levenberg-Marquardt, the candidate with the smallest
+ * worst normalised 2-D histogram error of the separable product kept.  Each
+ * cosine term splits into cos/sin products of the absolute coordinate and the
+ * window centre, which is what makes the Gaussian decomposable into 2K+1
+ * weight terms per axis.  K = 3 reaches a worst 2-D error of ~4e-8.
+ *   n         odd window side, 1..4095
+ *   K         1..8
+ *   a_out     host double [K+1] (may be NULL)
+ *   omega_out host double [K+1], the frequencies w_k in radians per pixel
+ *             (may be NULL)
+ *   err_out   host double: the worst normalised histogram error of the square
+ *             n x n window with this series (may be NULL)
+ * Host only; the fit runs once per (n, K) per process and is cached.
  */
-int swih_gauss_terms(int32_t n, int32_t K, double* a_out, int32_t* period_out, double* err_out);
+int swih_gauss_terms(int32_t n, int32_t K, double* a_out, double* omega_out, double* err_out);
 
 /* Static text for a status code. */
 const char* swih_status_string(int status);

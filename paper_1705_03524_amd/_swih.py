@@ -108,7 +108,7 @@ def load():
     lib.swih_brute_match.restype = C.c_int
     lib.swih_argmax.argtypes = [vp, C.c_int64, vp, vp]
     lib.swih_argmax.restype = C.c_int
-    lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+    lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
     lib.swih_gauss_terms.restype = C.c_int
     lib.swih_status_string.argtypes = [C.c_int]
@@ -119,6 +119,9 @@ def load():
 
 def status_string(status: int) -> str:
     return load().swih_status_string(int(status)).decode()
+
+
+DEFAULT_GAUSS_TERMS = 3     # K used when a config's gauss_terms is 0
 
 
 @dataclass
@@ -145,6 +148,11 @@ class Config:
                           C.cast(arr, C.POINTER(_Scale)), int(self.gauss_terms), int(self.flags),
                           int(self.band_rows))
         return self._c
+
+    @property
+    def K(self) -> int:
+        """Terms of the Gaussian series per axis (the default when gauss_terms is 0)."""
+        return int(self.gauss_terms) or DEFAULT_GAUSS_TERMS
 
 
 def _ptr(t):
@@ -264,15 +272,18 @@ def argmax_decode(key: int):
     return 0xFFFFFFFF - (k & 0xFFFFFFFF), value
 
 
-def gauss_terms(n: int, K: int = 4):
-    """(coefficients a_0..a_K, period P, worst normalised 2-D error) of the series."""
+def gauss_terms(n: int, K: int = 0):
+    """(coefficients a_0..a_K, frequencies w_0..w_K in radians per pixel, worst
+    normalised 2-D error) of the series g(t) = sum_k a_k cos(w_k t); K = 0 is
+    the default."""
+    K = int(K) or DEFAULT_GAUSS_TERMS
     a = (C.c_double * (K + 1))()
-    P = C.c_int32()
+    om = (C.c_double * (K + 1))()
     e = C.c_double()
-    st = load().swih_gauss_terms(int(n), int(K), a, C.byref(P), C.byref(e))
+    st = load().swih_gauss_terms(int(n), K, a, om, C.byref(e))
     if st != OK:
         raise SwihError(st, "swih_gauss_terms")
-    return list(a), int(P.value), float(e.value)
+    return list(a), list(om), float(e.value)
 
 
 def batch_plan(cfg: Config, frames, queries, matches):

@@ -69,7 +69,7 @@ class Autotuner:
         ch, cw = self.size_class(H, W)
         w, h = cfg.scales[0]
         return "%s|k%d|b%d|K%d|%dx%d|w%dx%d" % (self._device_name(), cfg.kernel, cfg.nbins,
-                                               cfg.gauss_terms or 4, cw, ch, w, h)
+                                               cfg.K, cw, ch, w, h)
 
     def best(self, cfg: S.Config, H: int, W: int) -> int:
         if cfg.kernel == S.GAUSSIAN_SEP:

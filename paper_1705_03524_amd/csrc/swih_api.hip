@@ -23,7 +23,7 @@ bool per_scale(int32_t k) { return series_kind(k) || k == SWIH_EXPONENTIAL; }
 // Kernels whose histograms are real-valued: no exact integer outputs.
 bool real_kind(int32_t k) { return per_scale(k); }
 
-int32_t gauss_K(const swih_config* c) { return c->gauss_terms == 0 ? 4 : c->gauss_terms; }
+int32_t gauss_K(const swih_config* c) { return c->gauss_terms == 0 ? SWIH_DEFAULT_K : c->gauss_terms; }
 
 // Checks the configuration against an image size; returns a status.
 int check_config(const swih_config* c, int32_t H, int32_t W) {
@@ -140,9 +140,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
 int fill_axis(int32_t n, int32_t K, GaussAxis& ax) {
   memset(&ax, 0, sizeof(ax));
   ax.K = K;
-  int P = 0;
-  if (gauss_fit(n, K, ax.a, &P, nullptr)) return SWIH_ERR_INVALID;
-  ax.P = P;
+  if (gauss_fit(n, K, ax.a, ax.om, nullptr)) return SWIH_ERR_INVALID;
   return SWIH_OK;
 }
 
@@ -157,7 +155,7 @@ int scale_params(const swih_config* c, int32_t scale_idx, ScaleParams& sp) {
   if (series_kind(c->kernel)) {
     const int32_t K = gauss_K(c);
     if (fill_axis(sc.w, K, sp.ax) || fill_axis(sc.h, K, sp.ay)) return SWIH_ERR_INVALID;
-    sp.mass = gauss_axis_mass(sc.w, K, sp.ax.a, sp.ax.P) * gauss_axis_mass(sc.h, K, sp.ay.a, sp.ay.P);
+    sp.mass = gauss_axis_mass(sc.w, K, sp.ax.a, sp.ax.om) * gauss_axis_mass(sc.h, K, sp.ay.a, sp.ay.om);
     return SWIH_OK;
   }
   if (c->kernel == SWIH_EXPONENTIAL) {
@@ -799,15 +797,15 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream) {
              : SWIH_ERR_HIP;
 }
 
-int swih_gauss_terms(int32_t n, int32_t K, double* a_out, int32_t* period_out, double* err_out) {
-  double a[SWIH_MAX_K + 1];
-  int P = 0;
+int swih_gauss_terms(int32_t n, int32_t K, double* a_out, double* omega_out, double* err_out) {
+  double a[SWIH_MAX_K + 1], om[SWIH_MAX_K + 1];
   double e = 0.0;
   if (K < 1 || K > SWIH_MAX_K) return SWIH_ERR_INVALID;
-  if (gauss_fit(n, K, a, &P, &e)) return SWIH_ERR_INVALID;
-  if (a_out)
-    for (int k = 0; k <= K; ++k) a_out[k] = a[k];
-  if (period_out) *period_out = P;
+  if (gauss_fit(n, K, a, om, &e)) return SWIH_ERR_INVALID;
+  for (int k = 0; k <= K; ++k) {
+    if (a_out) a_out[k] = a[k];
+    if (omega_out) omega_out[k] = om[k];
+  }
   if (err_out) *err_out = e;
   return SWIH_OK;
 }

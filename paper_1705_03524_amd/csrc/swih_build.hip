@@ -349,9 +349,7 @@ __device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
       if (i == 0) {
         val = 1.0;
       } else {
-        const int k = (i + 1) / 2;
-        const long ph = ((long)k * x) % ax.P;
-        const double ang = 2.0 * M_PI * (double)ph / (double)ax.P;
+        const double ang = ax.om[(i + 1) / 2] * (double)x;
         val = (i & 1) ? cos(ang) : sin(ang);
       }
     }
@@ -363,9 +361,7 @@ __device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
     if (j == 0) {
       val = 1.0;
     } else {
-      const int k = (j + 1) / 2;
-      const long ph = ((long)k * y) % ay.P;
-      const double ang = 2.0 * M_PI * (double)ph / (double)ay.P;
+      const double ang = ay.om[(j + 1) / 2] * (double)y;
       val = (j & 1) ? cos(ang) : sin(ang);
     }
     const int32_t q = (int32_t)rint(val * fix);

@@ -7,18 +7,20 @@
 #include "swih_layout.h"
 
 #define SWIH_MAX_K 8
+#define SWIH_DEFAULT_K 3  // free-frequency fit: worst 2-D histogram error ~4e-8
 
 namespace swih {
 
 // Host-side cosine-series fit (gauss_terms.cpp).
-int gauss_fit(int n, int K, double* a_out, int* P_out, double* err_out);
-double gauss_axis_mass(int n, int K, const double* a, int P);
+int gauss_fit(int n, int K, double* a_out, double* om_out, double* err_out);
+double gauss_axis_mass(int n, int K, const double* a, const double* om);
 
-// One axis of the Gaussian stand-in: g(t) = sum_k a[k] cos(2 pi k t / P).
+// One axis of the Gaussian stand-in: g(t) = sum_k a[k] cos(om[k] t), om[0] = 0.
 struct GaussAxis {
-  int32_t P;
   int32_t K;
+  int32_t pad;
   double a[SWIH_MAX_K + 1];
+  double om[SWIH_MAX_K + 1];
 };
 
 // Per-scale constants shared by query and match.
@@ -147,14 +149,14 @@ struct SepGeom {
   int32_t SY;           // column pass: centre rows per segment (segments start at multiples of SY)
 };
 
-// One axis of the series g(t) = sum_k a_k cos(w k t), w = 2 pi / P, for walks
-// along it: the window sum of term k translated to the current centre is the
-// complex number Z_k = sum_t e(t) exp(i w k t) over the window's offsets t.
+// One axis of the series g(t) = sum_k a_k cos(w_k t) for walks along it: the
+// window sum of term k translated to the current centre is the complex number
+// Z_k = sum_t e(t) exp(i w_k t) over the window's offsets t.
 struct SepAxis {
   double a[SWIH_MAX_K + 1];   // a_0 .. a_K
-  double ec[SWIH_MAX_K + 1];  // cos(w k r), r the half width: the entering offset +r
-  double es[SWIH_MAX_K + 1];  // sin(w k r)  (the leaving offset -r is the conjugate)
-  double rc[SWIH_MAX_K + 1];  // cos(w k), sin(w k): moving the centre one step on
+  double ec[SWIH_MAX_K + 1];  // cos(w_k r), r the half width: the entering offset +r
+  double es[SWIH_MAX_K + 1];  // sin(w_k r)  (the leaving offset -r is the conjugate)
+  double rc[SWIH_MAX_K + 1];  // cos(w_k), sin(w_k): moving the centre one step on
   double rs[SWIH_MAX_K + 1];  //   multiplies Z_k by (rc - i rs)
   double g_in;                // g(r) = a_0 + sum_k a_k ec_k
 };

@@ -24,7 +24,7 @@
 //   uniform    {1}
 //   Manhattan  {1, x, y}                 (i, j) = (0,0) (1,0) (0,1)
 //   Euclidean  {1, x, y, x^2, y^2}       (0,0) (1,0) (0,1) (2,0) (0,2)
-//   Gaussian   all products of {1, cos(2 pi k x / Px), sin(2 pi k x / Px)}_k
+//   Gaussian   all products of {1, cos(w_k x), sin(w_k x)}_{k=1..K}
 //              and the same in y: (2K+1)^2 terms, p = i * (2K+1) + j.
 //
 // Integer kernels store P itself as uint32 (arithmetic modulo 2^32).  The

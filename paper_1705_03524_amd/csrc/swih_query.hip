@@ -14,7 +14,7 @@
 //   Euclidean paraboloid, one box, c = rx^2 + ry^2 + 1:
 //     (c - xc^2 - yc^2) B_1 + 2 xc B_x + 2 yc B_y - B_xx - B_yy
 //   Gaussian, one box: sum_ij alpha_i(xc) beta_j(yc) B_ij with
-//     alpha = (a_0, a_k cos(w_k xc), a_k sin(w_k xc)), w_k = 2 pi k / P.
+//     alpha = (a_0, a_k cos(w_k xc), a_k sin(w_k xc)), w_k the series' frequencies.
 // Integer coefficients are applied modulo 2^32; the true histogram is below
 // 2^32, so the result is exact.  Normalisation divides by the kernel mass S
 // (the same at every location, Sec. 2.1).
@@ -163,10 +163,8 @@ __device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double
   out[0] = ax.a[0];
 #pragma unroll
   for (int k = 1; k <= (NT - 1) / 2; ++k) {
-    const long ph = ((long)k * c) % ax.P;
-    const double ang = 2.0 * M_PI * (double)ph / (double)ax.P;
     double s, co;
-    sincos(ang, &s, &co);
+    sincos(ax.om[k] * (double)c, &s, &co);
     out[2 * k - 1] = ax.a[k] * co;
     out[2 * k] = ax.a[k] * s;
   }
@@ -246,12 +244,11 @@ __device__ __forceinline__ double uniform(double v) {
 }
 
 // One coefficient of the series at centre coordinate c: index 0 -> a_0,
-// 2k-1 -> a_k cos(2 pi k c / P), 2k -> a_k sin(2 pi k c / P).
+// 2k-1 -> a_k cos(w_k c), 2k -> a_k sin(w_k c).
 __device__ __forceinline__ double series_coeff(const GaussAxis& ax, int c, int idx) {
   if (idx == 0) return ax.a[0];
   const int k = (idx + 1) / 2;
-  const long ph = ((long)k * c) % ax.P;
-  const double ang = 2.0 * M_PI * (double)ph / (double)ax.P;
+  const double ang = ax.om[k] * (double)c;
   return ax.a[k] * ((idx & 1) ? cos(ang) : sin(ang));
 }
 
@@ -268,9 +265,93 @@ __device__ __forceinline__ int64_t bc_term(double p, float t) {
 
 __device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q / kBcScale); }
 
-// Dense map.  One block per (row of centres yc, chunk of cw centres); NG
-// groups of threads, one thread per (group, plane column X the chunk's windows
-// touch: X = xc - rx and xc + rx + 1).  With the y terms contracted,
+// Column work of the Gaussian maps.  A block covers nV plane columns X (the
+// left and right window edges of its chunk of centres).  The x terms i of a
+// column are split over NG slots; each thread sums the terms of its items in
+// item order and writes its slot's partial G+/G- to LDS, and the window
+// threads add the slots in slot order.  Both map kernels use this split, so
+// their maps agree bit for bit.
+//  * strided (NT != 2 NG - 1): slot s holds terms s, s + NG, s + 2 NG, ...;
+//    one thread per (slot, column) and NG * nvpad threads, so a wave never
+//    spans two slots.
+//  * paired (NT == 2 NG - 1): slot s < NG - 1 holds terms s and s + NG, one
+//    thread per (slot, column); the last slot holds term NG - 1 alone, one
+//    thread per two columns (xi and xi + ceil(nV / 2)).  Every thread has two
+//    items: for NT = 7 the seven terms cost two item times per step instead of
+//    three with a strided split over three slots.
+__host__ __device__ constexpr int gauss_slots(int NT) { return NT <= 7 ? (NT + 1) / 2 : 3; }
+
+template <int NT, int NG>
+struct ColItems {
+  static constexpr bool kPaired = NT == 2 * NG - 1;
+  static constexpr int NI = kPaired ? 2 : (NT + NG - 1) / NG;
+  int slot;      // LDS slot of this thread's sums, -1 for none
+  bool single;   // paired split, last slot: the two items are two columns of one term
+  int i[NI], xi[NI], X[NI];
+  bool ok[NI];
+
+  __device__ __forceinline__ void init(int tid, int nV, int nvpad, int xa, int rx, int cwc,
+                                       bool contig) {
+    auto colX = [&](int c) {
+      return contig ? xa - rx + c : (c < cwc ? xa - rx + c : xa + rx + 1 + c - cwc);
+    };
+    single = false;
+    if constexpr (kPaired) {
+      const int base = (NG - 1) * nV, nvh = (nV + 1) / 2;
+      if (tid < base) {
+        slot = tid / nV;
+        const int c = tid - slot * nV;
+        i[0] = slot;
+        i[1] = slot + NG;
+        xi[0] = xi[1] = c;
+        ok[0] = ok[1] = true;
+      } else if (tid < base + nvh) {
+        slot = NG - 1;
+        single = true;
+        i[0] = i[1] = NG - 1;
+        xi[0] = tid - base;
+        xi[1] = xi[0] + nvh;
+        ok[0] = true;
+        ok[1] = xi[1] < nV;
+      } else {
+        slot = -1;
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+          i[ii] = 0;
+          xi[ii] = 0;
+          ok[ii] = false;
+        }
+      }
+    } else {
+      const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
+      const int c = tid - grp * nvpad;
+      const bool has = grp < NG && c < nV;
+      slot = has ? grp : -1;
+#pragma unroll
+      for (int ii = 0; ii < NI; ++ii) {
+        i[ii] = grp + ii * NG;
+        xi[ii] = c;
+        ok[ii] = has && i[ii] < NT;
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      X[ii] = ok[ii] ? colX(xi[ii]) : xa;
+      if (!ok[ii]) i[ii] = 0;
+    }
+  }
+};
+
+// Threads of a map block over nV columns with the split of NT terms.
+__host__ __device__ constexpr int gauss_map_threads(int NT, int nV) {
+  return gauss_slots(NT) * 2 - 1 == NT
+             ? ((gauss_slots(NT) - 1) * nV + (nV + 1) / 2 + 63) / 64 * 64
+             : gauss_slots(NT) * ((nV + 63) / 64 * 64);
+}
+
+// Dense map.  One block per (row of centres yc, chunk of cw centres), threads
+// over (slot, plane column X the chunk's windows touch: X = xc - rx and
+// xc + rx + 1).  With the y terms contracted,
 //   V_i(X) = sum_j beta_j(yc) (P_ij[yb][X] - P_ij[ya][X]),
 // the window histogram is H_b(xc) = sum_i alpha_i(xc) (V_i(xc+rx+1) - V_i(xc-rx)).
 // Each column therefore folds its own V_i into the two quantities the windows
@@ -280,10 +361,12 @@ __device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q 
 // and only those cross LDS: H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).  The row
 // carries of V_i depend on X only through its tile column and are tabulated
 // for every bin once per block.  Per bin: the column threads load their
-// L rows (all j of one i together), one barrier (LDS double-buffered by bin
+// L rows (all j of one item together), one barrier (LDS double-buffered by bin
 // parity), the window threads accumulate sqrt(p_b t_b).
 template <int NT, int NG>
 __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
+  using CI = ColItems<NT, NG>;
+  constexpr int NI = CI::NI;
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
   const GaussPlanes gp{(const float*)a.planes, a.RC};
@@ -324,26 +407,27 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
     }
     R[(b * NT + i) * ntl_max + t] = acc;
   }
-  const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
-  const int xi = tid - grp * nvpad;
-  const bool has_x = grp < NG && xi < nV;
-  const int X = !has_x ? xa : (contig ? xa - rx + xi
-                                      : (xi < cwc ? xa - rx + xi : xa + rx + 1 + xi - cwc));
-  const int tX = tile_of(X) - tlo;
-  // alpha at the two windows this column serves, for this group's x terms
-  constexpr int NI = (NT + NG - 1) / NG;
+  CI ci;
+  ci.init(tid, nV, nvpad, xa, rx, cwc, contig);
+  // alpha at the two windows each item's column serves, for the item's x term
   double ap[NI], am[NI];
+  int tX[NI];
+  bool x0col[NI];
+  size_t offA[NI], offB[NI], offC[NI];
+  const int64_t rs = g.row_stride;
 #pragma unroll
   for (int ii = 0; ii < NI; ++ii) {
-    const int i = grp + ii * NG;
-    ap[ii] = i < NT ? series_coeff(sp.ax, max(X - rx - 1, 0), i) : 0.0;
-    am[ii] = i < NT ? series_coeff(sp.ax, X + rx, i) : 0.0;
+    const int X = ci.X[ii];
+    ap[ii] = series_coeff(sp.ax, max(X - rx - 1, 0), ci.i[ii]);
+    am[ii] = series_coeff(sp.ax, X + rx, ci.i[ii]);
+    tX[ii] = tile_of(X) - tlo;
+    // column X = 0 is not stored (it is zero): its thread loads column 1 and drops it
+    x0col[ii] = X == 0;
+    const int64_t xo = swih_xoff(g, x0col[ii] ? 1 : X);
+    offA[ii] = (size_t)Ya * rs + xo;
+    offB[ii] = (size_t)Yb * rs + xo;
+    offC[ii] = (size_t)c0 * rs + xo;
   }
-  const int64_t rs = g.row_stride;
-  // column X = 0 is not stored (it is zero): its thread loads column 1 and drops it
-  const bool x0col = X == 0;
-  const int64_t xo = swih_xoff(g, x0col ? 1 : X);
-  const size_t offA = (size_t)Ya * rs + xo, offB = (size_t)Yb * rs + xo, offC = (size_t)c0 * rs + xo;
   const bool win = tid < cwc;
   const int xc = xa + tid;
   const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
@@ -352,18 +436,18 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
   __syncthreads();
   for (int b = 0; b < g.B; ++b) {
     double* Gp = Gb + (b & 1) * NG * 2 * nvpad;
-    if (has_x) {
+    if (ci.slot >= 0) {
       double gplus = 0.0, gminus = 0.0;
-#pragma unroll 1
+#pragma unroll
       for (int ii = 0; ii < NI; ++ii) {
-        const int i = grp + ii * NG;
-        if (i >= NT) break;
+        if (!ci.ok[ii]) break;
+        const int i = ci.i[ii];
         const float* lp = gp.L + swih_base(g, i * NT, b);
         float la[NT], lb[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-          la[j] = lp[offA + (size_t)j * 64];
-          lb[j] = lp[offB + (size_t)j * 64];
+          la[j] = lp[offA[ii] + (size_t)j * 64];
+          lb[j] = lp[offB[ii] + (size_t)j * 64];
         }
         double vl = 0.0;
 #pragma unroll
@@ -371,16 +455,23 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
         for (int c = 0; c < ncross; ++c) {
           float lc[NT];
 #pragma unroll
-          for (int j = 0; j < NT; ++j) lc[j] = lp[offC + (size_t)c * g.TY * rs + (size_t)j * 64];
+          for (int j = 0; j < NT; ++j) lc[j] = lp[offC[ii] + (size_t)c * g.TY * rs + (size_t)j * 64];
 #pragma unroll
           for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
         }
-        const double v = R[(b * NT + i) * ntl_max + tX] + (x0col ? 0.0 : vl);
-        gplus = fma(ap[ii], v, gplus);
-        gminus = fma(am[ii], v, gminus);
+        const double v = R[(b * NT + i) * ntl_max + tX[ii]] + (x0col[ii] ? 0.0 : vl);
+        if (ci.single) {
+          Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[ii]] = fma(ap[ii], v, 0.0);
+          Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[ii]] = fma(am[ii], v, 0.0);
+        } else {
+          gplus = fma(ap[ii], v, gplus);
+          gminus = fma(am[ii], v, gminus);
+        }
       }
-      Gp[(grp * 2 + 0) * nvpad + xi] = gplus;
-      Gp[(grp * 2 + 1) * nvpad + xi] = gminus;
+      if (!ci.single) {
+        Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[0]] = gplus;
+        Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[0]] = gminus;
+      }
     }
     __syncthreads();
     if (win) {
@@ -400,12 +491,14 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
 // next, so a block walks its comb segment reading each boundary row once and
 // keeping the previous one in registers (S + 1 rows for S centre rows, against
 // 2 S for one row per block).  Per centre row the column threads form G+/G-
-// exactly as match_gauss does (same operations in the same order), the window
-// threads form the bin's term and add it, as an integer, into the map's
-// accumulator.  match_gauss_fin turns the accumulator into the map and clears
-// it.  The result equals match_gauss bit for bit.
+// exactly as match_gauss does (same split, same operations in the same
+// order), the window threads form the bin's term and add it, as an integer,
+// into the map's accumulator.  match_gauss_fin turns the accumulator into the
+// map and clears it.  The result equals match_gauss bit for bit.
 template <int NT, int NG>
 __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
+  using CI = ColItems<NT, NG>;
+  constexpr int NI = CI::NI;
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
   const GaussPlanes gp{(const float*)a.planes, a.RC};
@@ -459,28 +552,21 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
     }
     R[(mm * NT + i) * ntl_max + t] = acc;
   }
-  const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
-  const int xi = tid - grp * nvpad;
-  const bool has_x = grp < NG && xi < nV;
-  const int X = !has_x ? xa : (contig ? xa - rx + xi
-                                      : (xi < cwc ? xa - rx + xi : xa + rx + 1 + xi - cwc));
-  const int tX = tile_of(X) - tlo;
-  constexpr int NI = (NT + NG - 1) / NG;
+  CI ci;
+  ci.init(tid, nV, nvpad, xa, rx, cwc, contig);
   double ap[NI], am[NI];
-#pragma unroll
-  for (int ii = 0; ii < NI; ++ii) {
-    const int i = grp + ii * NG;
-    ap[ii] = i < NT ? series_coeff(sp.ax, max(X - rx - 1, 0), i) : 0.0;
-    am[ii] = i < NT ? series_coeff(sp.ax, X + rx, i) : 0.0;
-  }
-  const int64_t rs = g.row_stride;
-  const bool x0col = X == 0;  // column X = 0 is not stored (zero)
-  const int64_t xo = swih_xoff(g, x0col ? 1 : X);
+  int tX[NI];
+  bool x0col[NI];
   const float* lpi[NI];
+  const int64_t rs = g.row_stride;
 #pragma unroll
   for (int ii = 0; ii < NI; ++ii) {
-    const int i = grp + ii * NG;
-    lpi[ii] = gp.L + swih_base(g, (i < NT ? i : 0) * NT, b) + xo;
+    const int X = ci.X[ii];
+    ap[ii] = series_coeff(sp.ax, max(X - rx - 1, 0), ci.i[ii]);
+    am[ii] = series_coeff(sp.ax, X + rx, ci.i[ii]);
+    tX[ii] = tile_of(X) - tlo;
+    x0col[ii] = X == 0;  // column X = 0 is not stored (zero)
+    lpi[ii] = gp.L + swih_base(g, ci.i[ii] * NT, b) + swih_xoff(g, x0col[ii] ? 1 : X);
   }
   // the segment's first top row
   float prev[NI][NT];
@@ -488,8 +574,7 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
   for (int ii = 0; ii < NI; ++ii)
 #pragma unroll
     for (int j = 0; j < NT; ++j)
-      prev[ii][j] = has_x && grp + ii * NG < NT
-                        ? lpi[ii][(size_t)(ycb - ry) * rs + (size_t)j * 64] : 0.0f;
+      prev[ii][j] = ci.ok[ii] ? lpi[ii][(size_t)(ycb - ry) * rs + (size_t)j * 64] : 0.0f;
   const bool win = tid < cwc;
   const int xc = xa + tid;
   const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
@@ -506,12 +591,12 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
     double be[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) be[j] = uniform(BE[mm * NT + j]);
-    if (has_x) {
+    if (ci.slot >= 0) {
       double gplus = 0.0, gminus = 0.0;
 #pragma unroll
       for (int ii = 0; ii < NI; ++ii) {
-        const int i = grp + ii * NG;
-        if (i >= NT) break;
+        if (!ci.ok[ii]) break;
+        const int i = ci.i[ii];
         float lb[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) lb[j] = lpi[ii][(size_t)Yb * rs + (size_t)j * 64];
@@ -526,14 +611,21 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
 #pragma unroll
           for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
         }
-        const double v = R[(mm * NT + i) * ntl_max + tX] + (x0col ? 0.0 : vl);
-        gplus = fma(ap[ii], v, gplus);
-        gminus = fma(am[ii], v, gminus);
+        const double v = R[(mm * NT + i) * ntl_max + tX[ii]] + (x0col[ii] ? 0.0 : vl);
+        if (ci.single) {
+          Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[ii]] = fma(ap[ii], v, 0.0);
+          Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[ii]] = fma(am[ii], v, 0.0);
+        } else {
+          gplus = fma(ap[ii], v, gplus);
+          gminus = fma(am[ii], v, gminus);
+        }
 #pragma unroll
         for (int j = 0; j < NT; ++j) prev[ii][j] = lb[j];
       }
-      Gp[(grp * 2 + 0) * nvpad + xi] = gplus;
-      Gp[(grp * 2 + 1) * nvpad + xi] = gminus;
+      if (!ci.single) {
+        Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[0]] = gplus;
+        Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[0]] = gminus;
+      }
     }
     __syncthreads();
     if (win) {
@@ -602,7 +694,7 @@ hipError_t run_many(const A* items, const int32_t* prefix, int n, unsigned grid,
 
 template <int K> constexpr void (*int_match)(const MatchArgs&, int) = match_int<K>;
 template <int K> constexpr void (*int_query)(const QueryArgs&, int) = query_int<K>;
-template <int NT> constexpr void (*gauss_match)(const MatchArgs&, int) = match_gauss<NT, 3>;
+template <int NT> constexpr void (*gauss_match)(const MatchArgs&, int) = match_gauss<NT, gauss_slots(NT)>;
 template <int NT> constexpr void (*gauss_query)(const QueryArgs&, int) = query_gauss<NT>;
 
 // switch over kernel kind (and Gaussian term count) calling CALL(body)
@@ -694,11 +786,12 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
     ml.lds = 0;
     return;
   }
-  // Gaussian: NG = 3 groups of nvpad column threads; cw centres per block
-  constexpr int NG = 3;
-  const int NT = L.g.nI;
+  // Gaussian: threads over (slot, plane column) (the split of ColItems); cw
+  // centres per block, as many as fit 1024 threads
+  const int NT = L.g.nI, NG = gauss_slots(NT);
   const int span = 2 * sp.rx + 1;
-  const int maxV = 320;  // NG * maxV threads <= 1024
+  int maxV = 512;
+  while (gauss_map_threads(NT, maxV) > 1024) --maxV;
   int cw, nV;
   if (span <= maxV / 2) {  // one contiguous column range: nV = cw + span
     const int cwmax = maxV - span;
@@ -714,7 +807,8 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   a.ntl_max = (cw + span + 63) / 64 + 2;  // tile columns one block can touch
   a.nbx = (nx + cw - 1) / cw;
   ml.blocks = a.nbx * ny;
-  ml.threads = NG * a.nvpad;
+  // every chunk's nV is at most the first chunk's, so its thread count serves all
+  ml.threads = gauss_map_threads(NT, nV);
   ml.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)L.g.B * NT * a.ntl_max);
 }
 
@@ -760,7 +854,7 @@ hipError_t launch_query_batch(int kind, int nt, const QueryArgs* jobs, const int
 
 namespace {
 
-template <int NT> constexpr void (*gauss_comb)(const MatchArgs&, int) = match_gauss_comb<NT, 3>;
+template <int NT> constexpr void (*gauss_comb)(const MatchArgs&, int) = match_gauss_comb<NT, gauss_slots(NT)>;
 constexpr void (*gauss_fin)(const MatchArgs&, int) = match_gauss_fin;
 
 hipError_t comb_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
@@ -795,7 +889,7 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   if (!L.g.gauss || ny < 2 * h) return match_one(sp.kind, L.g.nI, a, ml, s);
   // Gaussian over many centre rows: the comb form (same values, fewer plane
   // reads), then the accumulator to the map.
-  const int NT = L.g.nI, NG = 3;
+  const int NT = L.g.nI, NG = gauss_slots(NT);
   const int S = kCombSteps;
   const int mmax = (ny + h - 1) / h;
   a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);

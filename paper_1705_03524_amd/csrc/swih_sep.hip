@@ -2,19 +2,19 @@
 // (kernel SWIH_GAUSSIAN_SEP).
 //
 // The Gaussian's weight terms are products u_i(x) v_j(y) of two 1-D families
-// (1, cos(w k t), sin(w k t), w = 2 pi / P), so the translated window sum of
+// (1, cos(w_k t), sin(w_k t)), so the translated window sum of
 // Sec. 2.1 factors into two 1-D weighted integral histograms:
 //   row pass     h_b(xc; y)  = sum_{|x - xc| <= rx} [Q(f(x, y)) = b] g_x(x - xc)
 //   column pass  H_b(xc, yc) = sum_{|y - yc| <= ry} h_b(xc; y) g_y(y - yc)
-// with g(t) = a_0 + sum_k a_k cos(w k t).  Per term, the 1-D integral
+// with g(t) = a_0 + sum_k a_k cos(w_k t).  Per term, the 1-D integral
 // histogram's window difference translated to the centre (the product-to-sum
-// identity of Sec. 2.1) is the complex sum Z_k = sum_t e(t) exp(i w k t) over
+// identity of Sec. 2.1) is the complex sum Z_k = sum_t e(t) exp(i w_k t) over
 // the window's offsets t from the centre, and g at every offset follows as
 // a_0 Z_0 + sum_k a_k Re Z_k.  A wave walks consecutive centres of a line:
 // per step the element entering at +r and the one leaving at -r update Z_k,
-// and moving the centre one step rotates Z_k by exp(-i w k) -- O(1) per
+// and moving the centre one step rotates Z_k by exp(-i w_k) -- O(1) per
 // centre and term, whatever the window size, with no tables: the per-scale
-// constants (a_k, exp(i w k r), exp(i w k)) sit in scalar registers.
+// constants (a_k, exp(i w_k r), exp(i w_k)) sit in scalar registers.
 //
 // Walks restart from an empty window at the start of every segment (SX
 // centre columns, SY centre rows; segments start at absolute multiples of
@@ -454,9 +454,8 @@ void sep_axis(const GaussAxis& ax, int32_t r, SepAxis& s) {
   s.a[0] = ax.a[0];
   s.g_in = ax.a[0];
   for (int k = 1; k <= ax.K; ++k) {
-    // phases reduced exactly in integers before the angle is formed
-    const double tr = 2.0 * M_PI * (double)(((long)k * r) % ax.P) / (double)ax.P;
-    const double t1 = 2.0 * M_PI * (double)(k % ax.P) / (double)ax.P;
+    const double tr = ax.om[k] * (double)r;
+    const double t1 = ax.om[k];
     s.a[k] = ax.a[k];
     s.ec[k] = cos(tr);
     s.es[k] = sin(tr);

@@ -24,10 +24,9 @@ class Plan:
         """Weight terms per bin: 1 uniform, 3 Manhattan, 5 Euclidean, (2K+1)^2 Gaussian,
         2K+1 per axis for the separable Gaussian, 4 directions for the exponential."""
         if self.cfg.kernel == S.GAUSSIAN:
-            k = self.cfg.gauss_terms or 4
-            return (2 * k + 1) ** 2
+            return (2 * self.cfg.K + 1) ** 2
         if self.cfg.kernel == S.GAUSSIAN_SEP:
-            return 2 * (self.cfg.gauss_terms or 4) + 1
+            return 2 * self.cfg.K + 1
         return {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4}[self.cfg.kernel]
 
     @property

@@ -219,7 +219,7 @@ def plane_bytes(cfg: S.Config, units) -> int:
     """Algorithmic bytes the builds write: 4 T B (H+1)(W+1) per plane set, or for
     the separable Gaussian 4 B H (W - w + 1) of row results per scale.  The
     Gaussian and the exponential keep one plane set per scale."""
-    K = cfg.gauss_terms or 4
+    K = cfg.K
     tot = 0
     for u in units:
         H, W = u.img.shape

@@ -53,11 +53,12 @@ def map_tolerance(p_oracle: np.ndarray, t_oracle: np.ndarray, eps: float,
 
 
 def gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=None, kind=None, okind=None,
-                tol=GAUSS_TOL, map_slack=1e-6):
+                tol=GAUSS_TOL, map_slack=1e-6, K=0):
     """Histograms at ``centres``, the template at ``tcentre`` and (optionally) the
     map over ``map_rect`` of a real-valued kind (a series-Gaussian form by
-    default) against the FP64 oracle of kernel ``okind``, to ``tol`` per bin;
-    maps to the bound that implies, plus ``map_slack``."""
+    default, ``K`` series terms per axis, 0 = the default) against the FP64
+    oracle of kernel ``okind``, to ``tol`` per bin; maps to the bound that
+    implies, plus ``map_slack``."""
     import torch
 
     import oracle
@@ -65,7 +66,7 @@ def gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=None, kind=None
     from paper_1705_03524_amd.plan import Plan
     ok = oracle.GAUSSIAN if okind is None else okind
     H, W = img.shape
-    cfg = swih.Config(nb, swih.GAUSSIAN if kind is None else kind, [(w, h)])
+    cfg = swih.Config(nb, swih.GAUSSIAN if kind is None else kind, [(w, h)], gauss_terms=K)
     plan = Plan(cfg, H, W)
     plan.build(to_dev(img, torch))
     hist, _ = plan.query(0, to_dev(centres, torch))

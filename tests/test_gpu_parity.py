@@ -211,6 +211,18 @@ def test_gaussian_ragged(HW, nb, wh, kind):
                 map_rect=(rx, ry, W - 1 - rx, H - 1 - ry), kind=kind)
 
 
+@pytest.mark.parametrize("kind", GAUSS_KINDS)
+@pytest.mark.parametrize("K", [4, 6])
+def test_gaussian_other_series_lengths(K, kind):
+    # K is a build parameter: longer series than the default (3) are just as exact
+    H, W = 65, 129
+    img = synth.uniform_noise(17 + K, H, W)
+    c = all_centres(H, W, 15, 21)
+    print("case: gaussian(%d) K=%d 65x129 16 bins 15x21" % (kind, K), flush=True)
+    gauss_check(img, 16, 15, 21, c, tuple(c[len(c) // 3]), "gaussian(%d) K=%d" % (kind, K),
+                map_rect=(7, 10, W - 8, H - 11), kind=kind, K=K)
+
+
 @pytest.mark.parametrize("w", [21, 31, 45, 63, 81])
 def test_gaussian_multiscale_2048(w):
     # 2048 x 2048 smooth noise, 32 bins, one scale at a time (planes ~9-48 GB)
