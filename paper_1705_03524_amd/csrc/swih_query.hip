@@ -661,6 +661,13 @@ __global__ __launch_bounds__(1024) void k_one(A a) {
   BODY(a, (int)blockIdx.x);
 }
 
+// The comb map with seven or fewer series terms fits 64 registers, so two of
+// its 15-wave blocks share a compute unit: twice the loads in flight.
+template <class A, void (*BODY)(const A&, int)>
+__global__ __launch_bounds__(1024, 8) void k_one_w8(A a) {
+  BODY(a, (int)blockIdx.x);
+}
+
 template <class A, void (*BODY)(const A&, int)>
 __global__ __launch_bounds__(1024) void k_many(const A* __restrict__ items,
                                                const int32_t* __restrict__ prefix, int n) {
@@ -680,6 +687,13 @@ namespace {
 template <class A, void (*BODY)(const A&, int)>
 hipError_t run_one(const A& a, const Launch& ml, hipStream_t s) {
   hipLaunchKernelGGL((k_one<A, BODY>), dim3((unsigned)ml.blocks), dim3((unsigned)ml.threads),
+                     ml.lds, s, a);
+  return hipGetLastError();
+}
+
+template <class A, void (*BODY)(const A&, int)>
+hipError_t run_one_w8(const A& a, const Launch& ml, hipStream_t s) {
+  hipLaunchKernelGGL((k_one_w8<A, BODY>), dim3((unsigned)ml.blocks), dim3((unsigned)ml.threads),
                      ml.lds, s, a);
   return hipGetLastError();
 }
@@ -859,9 +873,9 @@ constexpr void (*gauss_fin)(const MatchArgs&, int) = match_gauss_fin;
 
 hipError_t comb_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
   switch (nt) {
-    case 3: return run_one<MatchArgs, gauss_comb<3>>(a, ml, s);
-    case 5: return run_one<MatchArgs, gauss_comb<5>>(a, ml, s);
-    case 7: return run_one<MatchArgs, gauss_comb<7>>(a, ml, s);
+    case 3: return run_one_w8<MatchArgs, gauss_comb<3>>(a, ml, s);
+    case 5: return run_one_w8<MatchArgs, gauss_comb<5>>(a, ml, s);
+    case 7: return run_one_w8<MatchArgs, gauss_comb<7>>(a, ml, s);
     case 9: return run_one<MatchArgs, gauss_comb<9>>(a, ml, s);
     case 11: return run_one<MatchArgs, gauss_comb<11>>(a, ml, s);
     case 13: return run_one<MatchArgs, gauss_comb<13>>(a, ml, s);
