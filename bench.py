@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the measurements reported beside the step (separable Gaussian, exponential, "
                          "2048x2048 builds), so a profile of the run covers the step's launches only")
+    ap.add_argument("--streams", type=int, choices=(1, 3), default=3,
+                    help="frame workload: run the three kernels' pipelines (each build -> query -> "
+                         "map in order) on 3 streams forked and joined inside the step's graph, or "
+                         "all on one stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (known bytes) so HBM "
                          "counters of a profiling run can be scaled")
@@ -575,10 +579,27 @@ def main():
 
     PHASES = ("carries", "planes", "query", "match")
 
+    # The three kernels' pipelines are independent: with --streams 3 each runs
+    # on its own stream (forked from and joined back to the current one), so
+    # the short integer pipelines overlap the Gaussian's long kernels and the
+    # launch gaps of one pipeline are covered by the others.
+    side_streams = [torch.cuda.Stream() for _ in KERNELS[1:]] if args.streams == 3 else []
+
     def step():
-        for k in KERNELS:
-            for ph in PHASES:
-                phase(k, ph)
+        if not side_streams:
+            for k in KERNELS:
+                for ph in PHASES:
+                    phase(k, ph)
+            return
+        main = torch.cuda.current_stream()
+        for st in side_streams:
+            st.wait_stream(main)
+        for k, st in zip(KERNELS, [main] + side_streams):
+            with torch.cuda.stream(st):
+                for ph in PHASES:
+                    phase(k, ph)
+        for st in side_streams:
+            main.wait_stream(st)
 
     def capture(fn):
         side = torch.cuda.Stream()
@@ -736,7 +757,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "512x512 scene, 16 bins, 31x31 windows, Manhattan+Euclidean+Gaussian "
                                "(sigma=w/4, K=3), full Bhattacharyya map of 482x482 centres per kernel",
-                   "global_batch": 1, "seq_len": None, "parallelism": "none"},
+                   "global_batch": 1, "seq_len": None, "parallelism": "none",
+                   "streams": args.streams},
         "roofline": roof(kernels[dominant]),
         "roofline_" + other: roof(kernels[other]),
         "detail_ms": per,
