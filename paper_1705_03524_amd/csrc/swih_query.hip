@@ -498,6 +498,14 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
 template <int NT, int NG>
 __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
   using CI = ColItems<NT, NG>;
+  {
+    // Workgroups go to the 8 XCDs round robin: renumber so that each XCD runs
+    // a contiguous range of virtual blocks, i.e. the combs of one (bin, chunk)
+    // together, and their shared band-closing rows stay in that XCD's L2.
+    const int n = (int)gridDim.x, base = n >> 3, rem = n & 7;
+    const int x = vb & 7, k = vb >> 3;
+    vb = x * base + (x < rem ? x : rem) + k;
+  }
   constexpr int NI = CI::NI;
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
