@@ -423,37 +423,68 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
   }
 }
 
+// Row carries at the tile origin column, RC_ij[Y] = P_ij[Y][64 tx], of every
+// plane of one (band, tile, bin): one lane per plane p = i NT + j, walking the
+// band's rows,
+//   RC[Y + 1] = RC[Y] + v_j(Y) E_i(Y),   RC[y0] = CTc
+// (CTc the tile-origin value, E_i the row carry of x term i, both in the
+// fixed-point units of the basis).  RC is stored planes fastest (swih_rc), so
+// each row's store is one contiguous run of 8 nP bytes.
+template <int NT>
+__device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) {
+  const SwihGeom& g = a.g;
+  const int32_t* __restrict__ vq = a.vq;
+  const int64_t* __restrict__ E = (const int64_t*)a.T;
+  const double* __restrict__ CTc = (const double*)a.BT;
+  double* __restrict__ RCp = a.RC;
+  constexpr int NP = NT * NT;
+  const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
+  for (int p0 = 0; p0 < NP; p0 += 64) {
+    const int p = p0 + lane_id();
+    if (p >= NP) break;
+    const int i = p / NT, j = p - (p / NT) * NT;
+    if (t.ty == 0) RCp[swih_rc(g, p, t.b, t.tx, 0)] = 0.0;
+    const int64_t* __restrict__ ei = E + ((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0;
+    const int32_t* __restrict__ vj = vq + (size_t)t.y0 * NT + j;
+    double* __restrict__ dst = RCp + swih_rc(g, p, t.b, t.tx, t.y0 + 1);
+    double acc = CTc[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx];
+#pragma unroll 8
+    for (int r = 0; r < t.nrows; ++r) {
+      acc += (double)vj[(size_t)r * NT] * (double)ei[r];
+      dst[(size_t)r * g.nP] = acc * sc48;
+    }
+  }
+}
+
+// Planes of one (band, tile, bin, x term i), rows top to bottom:
+//   L_ij[y + 1] = L_ij[y] + v_j(y) R_i(y),  R_i the row prefix of u_i [Q = b]
+// inside the tile (an exact int32 DPP scan).  The launch interleaves one
+// row-carry wave (rc_gauss) after the NT plane waves of each (band, tile,
+// bin).
 template <int NT>
 __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
   const uint8_t* __restrict__ img = a.img;
   const int ipitch = a.ipitch;
   const int32_t* __restrict__ uq = a.uq;
-  const int32_t* __restrict__ vq = a.vq;
   const double* __restrict__ vqd = a.vqd;
-  const int64_t* __restrict__ E = (const int64_t*)a.T;
-  const double* __restrict__ CTc = (const double*)a.BT;
   float* __restrict__ Lp = (float*)a.planes;
-  double* __restrict__ RCp = a.RC;
   WaveTile t;
   int i;
-  if (!wave_tile(g, wave_index(vb), NT, t, i)) return;
+  if (!wave_tile(g, wave_index(vb), NT + 1, t, i)) return;
+  if (i == NT) {
+    rc_gauss<NT>(a, t);
+    return;
+  }
   const int lane = lane_id();
-    const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
   const int32_t uqi = uq[(size_t)t.x * NT + i];
-  const int64_t ereg =
-      lane < t.nrows ? E[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] : 0;
-  size_t lbase[NT];
+  // the group's NT planes are consecutive 64-element runs of each row
+  float* lrow = Lp + swih_base(g, i * NT, t.b) + t.tx * g.tile_stride + lane;
   double L[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    const int p = i * NT + j;
-    lbase[j] = (size_t)(swih_base(g, p, t.b) + t.tx * g.tile_stride + lane);
     L[j] = 0.0;
-    if (t.ty == 0) {
-      Lp[lbase[j]] = 0.0f;
-      if (lane == 0) RCp[swih_rc(g, p, t.b, t.tx, 0)] = 0.0;
-    }
+    if (t.ty == 0) lrow[j * 64] = 0.0f;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
@@ -471,21 +502,9 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
       out[j] = (float)L[j];
     }
     // whole 256-byte runs: lanes past the last column write values never read
-    const size_t row = (size_t)(y + 1) * g.row_stride;
+    float* dst = lrow + (size_t)(y + 1) * g.row_stride;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) Lp[lbase[j] + row] = out[j];
-  }
-  // row carries at the tile origin column: RC[tx][y + 1] = P[y + 1][Xo], one lane per row
-  const int yl = t.y0 + (lane < t.nrows ? lane : 0);
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const int p = i * NT + j;
-    const size_t pb = (size_t)(p * g.B + t.b);
-    // ereg is 0 on lanes past the band's last row
-    const double term = (double)vq[(size_t)yl * NT + j] * (double)ereg;
-    const double rc =
-        (CTc[(pb * g.NTY + t.ty) * g.NTX + t.tx] + wave_incl_scan(term)) * sc48;
-    if (lane < t.nrows) RCp[swih_rc(g, p, t.b, t.tx, t.y0 + 1 + lane)] = rc;
+    for (int j = 0; j < NT; ++j) dst[j * 64] = out[j];
   }
 }
 
@@ -608,7 +627,7 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
   nb[0] = g.gauss ? blocks_for_threads((long)g.nI * NXP + (long)g.nJ * g.H + a.nacc) : 0;
   nb[1] = blocks_for_waves(waves);
   nb[2] = a.nb1 + a.nb2 + nb3;
-  nb[3] = blocks_for_waves(waves * (g.gauss ? g.nI : 1));
+  nb[3] = blocks_for_waves(waves * (g.gauss ? g.nI + 1 : 1));  // Gaussian: + a row-carry wave
 }
 
 hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,

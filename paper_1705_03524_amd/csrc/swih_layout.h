@@ -77,9 +77,11 @@ __host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, in
   return swih_base(g, p, b) + (int64_t)Y * g.row_stride + swih_xoff(g, X);
 }
 
-// Element offset of the Gaussian row carry RC[tx][Y] of plane p, bin b.
+// Element offset of the Gaussian row carry RC[tx][Y] of plane p, bin b:
+// [b][tx][Y][p], planes fastest.  A map step reads all planes of one row and
+// tile as one contiguous run, and the build writes each row of a tile as one.
 __host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int p, int b, int tx, int Y) {
-  return (((int64_t)b * (g.H + 1) + Y) * g.NTX + tx) * g.nP + p;
+  return (((int64_t)b * g.NTX + tx) * (g.H + 1) + Y) * g.nP + p;
 }
 
 // Byte offsets inside one workspace.  All regions are 256-byte aligned.
@@ -89,7 +91,7 @@ struct SwihLayout {
   int64_t set_bytes;     // bytes of one plane set (planes [+ RC + tables])
   // inside a set
   int64_t off_planes;    // uint32 or float planes, tile-major (above)
-  int64_t off_RC;        // double [B][H+1][NTX][nP], swih_rc     (Gaussian)
+  int64_t off_RC;        // double [B][NTX][H+1][nP], swih_rc     (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
   int64_t off_acc;       // int64 [H * W] map accumulator of the comb-form map (Gaussian)
