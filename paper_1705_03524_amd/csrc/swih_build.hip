@@ -381,45 +381,57 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
   const int32_t* __restrict__ vq = a.vq;
   int64_t* __restrict__ T = (int64_t*)a.T;
   double* __restrict__ BT = (double*)a.BT;
+  // per wave: the band's row sums T_i(y) and row terms v_j(y), [row][term]
+  __shared__ int32_t lds[WPB][2][64 * NT];
   WaveTile t;
   int e;
   if (!wave_tile(g, wave_index(vb), 1, t, e)) return;
   const int lane = lane_id();
-    int32_t treg[NT];
+  int32_t* sT = lds[threadIdx.x >> 6][0];
+  int32_t* sV = lds[threadIdx.x >> 6][1];
+  const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
+  // row sums: after the transpose lane k holds row y0 + k over the tile's 64
+  // columns; T_i(y) = sum over its set bits x of u_i(x), the column's terms
+  // uniform over the wave (scalar loads), added under an all-ones/zero mask
+  const uint64_t rowm = wave_transpose64(mask);
+  const uint32_t rlo = (uint32_t)rowm, rhi = (uint32_t)(rowm >> 32);
+  const int32_t* ucol = uq + (size_t)t.tx * SWIH_TX * NT;
+  int32_t treg[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) treg[i] = 0;
-  const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
-  // row sums, transposed: lane k gathers row y0 + k over the tile's 64 columns
-  const int32_t* ucol = uq + (size_t)t.tx * SWIH_TX * NT;
+#pragma unroll 4
   for (int l = 0; l < 64; ++l) {
-    const uint64_t ml = ((uint64_t)readlane((uint32_t)(mask >> 32), l) << 32) |
-                        readlane((uint32_t)mask, l);
-    const int32_t bit = (int32_t)bit_of(ml, lane);
-    // the column's terms are loaded unconditionally (one scalar load batch)
-    // and masked by multiplication, so no lane-dependent branch guards a load
+    const uint32_t half = l < 32 ? rlo : rhi;
+    const int32_t sel = -(int32_t)((half >> (l & 31)) & 1u);
     const int32_t* ul = ucol + l * NT;
-    int32_t uv[NT];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) uv[i] = ul[i];
-#pragma unroll
-    for (int i = 0; i < NT; ++i) treg[i] += bit * uv[i];
+    for (int i = 0; i < NT; ++i) treg[i] += ul[i] & sel;
   }
-  if (lane < t.nrows) {
+  const bool row = lane < t.nrows;
+  const int yl = t.y0 + (row ? lane : 0);
 #pragma unroll
-    for (int i = 0; i < NT; ++i)
-      T[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] = (int64_t)treg[i];
+  for (int i = 0; i < NT; ++i) {
+    if (row) T[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0 + lane] = (int64_t)treg[i];
+    sT[lane * NT + i] = row ? treg[i] : 0;
   }
-  // tile totals of every plane: sum over the band's rows of v_j(y) T_i(y), exact in int64
-  // (lanes past the band's last row hold T_i = 0, so their v_j needs no mask)
-  const int yl = t.y0 + (lane < t.nrows ? lane : 0);
-  for (int j = 0; j < NT; ++j) {
-    const int64_t vj = (int64_t)vq[(size_t)yl * NT + j];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const int64_t s = wave_sum(vj * (int64_t)treg[i]);
-      if (lane == 0)
-        BT[((size_t)((i * NT + j) * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] = (double)s;
-    }
+  for (int j = 0; j < NT; ++j) sV[lane * NT + j] = vq[(size_t)yl * NT + j];
+  // the wave's own LDS writes, read back by other lanes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // tile totals of every plane, one lane per plane p = i NT + j: the sum over
+  // the band's rows of v_j(y) T_i(y), exact in int64 (rows past the band's
+  // last one hold T_i = 0)
+  constexpr int NP = NT * NT;
+  for (int p0 = 0; p0 < NP; p0 += 64) {
+    const int p = p0 + lane;
+    if (p >= NP) break;
+    const int i = p / NT, j = p - (p / NT) * NT;
+    int64_t acc = 0;
+#pragma unroll 8
+    for (int y = 0; y < 64; ++y) acc += (int64_t)sT[y * NT + i] * (int64_t)sV[y * NT + j];
+    BT[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx] = (double)acc;
   }
 }
 
