@@ -55,16 +55,48 @@ struct Leaky {
   double f31;  // rows 2 and 3: g^(l - 31); else 0
 };
 
-__device__ __forceinline__ Leaky make_leaky(double step) {
+// q^n for 0 <= n < 128 (n per lane, q uniform): squarings of q and a product
+// over the bits of n, relative error a few ulps.
+__device__ __forceinline__ double dpow(double q, int n) {
+  double r = 1.0, p = q;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    r *= (n >> k) & 1 ? p : 1.0;
+    p *= p;
+  }
+  return r;
+}
+
+// The scan's factors for a decay g per lane step.
+__device__ __forceinline__ Leaky make_leaky(double g) {
   const int l = lane_id();
   Leaky L;
-  L.g1 = exp(-step);
-  L.g2 = exp(-2.0 * step);
-  L.g4 = exp(-4.0 * step);
-  L.g8 = exp(-8.0 * step);
-  L.f15 = (l & 16) ? exp(-step * (double)((l & 15) + 1)) : 0.0;
-  L.f31 = l >= 32 ? exp(-step * (double)(l - 31)) : 0.0;
+  L.g1 = g;
+  L.g2 = g * g;
+  L.g4 = L.g2 * L.g2;
+  L.g8 = L.g4 * L.g4;
+  L.f15 = (l & 16) ? dpow(g, (l & 15) + 1) : 0.0;
+  L.f31 = l >= 32 ? dpow(g, l - 31) : 0.0;
   return L;
+}
+
+// sum over the set bits k < top of m of q^(top - k), top a multiple of 8
+// (at most 64): eight independent 8-bit Horner chains, chunk c (bits 8c ..
+// 8c + 7) summing bit q^(8 - r) over its bits r, joined by powers of q^8.
+__device__ __forceinline__ double decay_sum(uint64_t m, int top, double q, double q8) {
+  double h[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v = (v + (double)(uint32_t)((m >> (8 * c + r)) & 1)) * q;
+    h[c] = v;
+  }
+  const int nch = top >> 3;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc = c < nch ? fma(acc, q8, h[c]) : acc;
+  return acc;
 }
 
 template <int CTRL>
@@ -147,22 +179,15 @@ __device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
   const int lane = lane_id();
   const long NXP = (long)g.NTX * 64;
   const uint64_t mask = exp_band_mask(a, t);
-  const double qy = exp(-a.ity), qx = exp(-a.itx);
-  double c = 0.0;  // this column's band sum, relative to row Y0 + TY
-  for (int k = 0; k < g.TY; ++k) c = (c + mbit(mask, k)) * qy;
-  const double zl = qx * leaky_scan(c, make_leaky(a.itx));
+  // this column's band sum relative to row Y0 + TY: sum_k bit_k qy^(TY - k)
+  const double c = decay_sum(mask, g.TY, a.qy, a.qy8);
+  const double zl = a.qx * leaky_scan(c, make_leaky(a.qx));
   const long db = (long)t.d * g.B + t.b;
   a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane] = zl;
   if (lane == 63) a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx] = zl;
-  // row sums across the tile, transposed: lane k reads bit k of every column's mask
-  const uint32_t mlo = (uint32_t)mask, mhi = (uint32_t)(mask >> 32);
-  double tr = 0.0, wgt = qx;  // qx^(64 - l) for l = 63, 62, ..., 0
-#pragma unroll 8
-  for (int l = 63; l >= 0; --l) {
-    const uint64_t ml = ((uint64_t)readlane(mhi, l) << 32) | readlane(mlo, l);
-    tr = fma(mbit(ml, lane), wgt, tr);
-    wgt *= qx;
-  }
+  // row sums across the tile: after the transpose lane k holds row k's
+  // columns, T(y) = sum_l bit_l qx^(64 - l)
+  const double tr = decay_sum(wave_transpose64(mask), 64, a.qx, a.qx8);
   if (lane < t.nrows) a.T[(db * g.NTX + t.tx) * g.H + t.y0 + lane] = tr;
 }
 
@@ -180,7 +205,7 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
     const long t = (long)vb * WG + threadIdx.x;
     if (t >= 4L * g.B * NXP) return;
     const long db = t / NXP, col = t - db * NXP;
-    const double qT = exp(-a.ity * g.TY);
+    const double qT = a.qyT;
     double* z = a.z + db * g.NTY * NXP + col;
     double carry = 0.0;
     for (int ty = 0; ty < g.NTY; ++ty) {
@@ -196,7 +221,7 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
     if (t >= 4L * g.B * g.H) return;
     const long db = t / g.H;
     const int y = (int)(t - db * g.H);
-    const double qT = exp(-a.itx * 64.0);
+    const double qT = a.qx64;
     double* T = a.T + db * g.NTX * g.H + y;
     double carry = 0.0;
     for (int tx = 0; tx < g.NTX; ++tx) {
@@ -211,10 +236,9 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
   if (wid >= 4L * g.B) return;
   const int lane = lane_id();
   double* CT = a.CT + wid * g.NTY * g.NTX;
-  const double qyT = exp(-a.ity * g.TY);
-  const double gx = a.itx * 64.0;
-  const Leaky Lt = make_leaky(gx);
-  const double up = exp(-gx * (double)(lane + 1));  // decay from tile 63 of the first chunk
+  const double qyT = a.qyT;
+  const Leaky Lt = make_leaky(a.qx64);
+  const double up = dpow(a.qx64, lane + 1);  // decay from tile 63 of the first chunk
   const bool v0 = lane < g.NTX, v1 = 64 + lane < g.NTX;  // NTX <= 128
   double k0 = 0.0, k1 = 0.0;
   for (int ty = 0; ty < g.NTY; ++ty) {
@@ -248,9 +272,9 @@ __device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
   const int lane = lane_id();
   const long NXP = (long)g.NTX * 64;
   const uint64_t mask = exp_band_mask(a, t);
-  const double qx = exp(-a.itx), qy = exp(-a.ity);
-  const double pw = exp(-a.itx * (double)(lane + 1));
-  const Leaky Lx = make_leaky(a.itx);
+  const double qx = a.qx, qy = a.qy;
+  const double pw = dpow(qx, lane + 1);
+  const Leaky Lx = make_leaky(qx);
   const long db = (long)t.d * g.B + t.b;
   const double K = a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx];
   double e = fma(pw, K, a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane]);
@@ -411,6 +435,12 @@ void exp_build_args(const SwihLayout& L, const ExpScale& s, int set, const uint8
   a.CT = (double*)(sb + L.off_CT);
   a.itx = s.itx;
   a.ity = s.ity;
+  a.qx = exp(-s.itx);
+  a.qy = exp(-s.ity);
+  a.qx8 = exp(-8.0 * s.itx);
+  a.qy8 = exp(-8.0 * s.ity);
+  a.qyT = exp(-s.ity * g.TY);
+  a.qx64 = exp(-64.0 * s.itx);
   const long waves = 4L * g.B * g.NTY * g.NTX;
   a.nb1 = blocks_of_threads(4L * g.B * g.NTX * 64);
   a.nb2 = blocks_of_threads(4L * g.B * g.H);

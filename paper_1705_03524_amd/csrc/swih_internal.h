@@ -259,6 +259,9 @@ struct ExpBuildArgs {
   double* T;           // [4 B][NTX][H]      row sums  -> left-edge row values
   double* CT;          // [4 B][NTY][NTX]    tile sums -> tile-origin values
   double itx, ity;
+  // decays, computed on the host: one column / row step (qx = exp(-1/tx),
+  // qy = exp(-1/ty)), eight of them, one band (qy^TY) and one tile (qx^64)
+  double qx, qy, qx8, qy8, qyT, qx64;
 };
 
 struct ExpQueryArgs {

@@ -87,6 +87,24 @@ __device__ __forceinline__ T put_lane(T reg, T val, int lane) {
   return lane_id() == lane ? val : reg;
 }
 
+// 64 x 64 bit transpose across the wave: lane l holds bits A[l][k]; afterwards
+// lane k holds A[l][k] at bit l.  Each stage swaps bit s of the lane index with
+// bit s of the bit index (the off-diagonal s x s blocks of every 2s x 2s block).
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t m) {
+  const int lane = lane_id();
+  const uint64_t low[6] = {0x5555555555555555ull, 0x3333333333333333ull, 0x0F0F0F0F0F0F0F0Full,
+                           0x00FF00FF00FF00FFull, 0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
+#pragma unroll
+  for (int b = 5; b >= 0; --b) {
+    const int s = 1 << b;
+    const uint32_t plo = (uint32_t)__shfl_xor((int)(uint32_t)m, s, 64);
+    const uint32_t phi = (uint32_t)__shfl_xor((int)(uint32_t)(m >> 32), s, 64);
+    const uint64_t t = ((uint64_t)phi << 32) | plo;
+    m = (lane & s) ? (m & ~low[b]) | ((t & ~low[b]) >> s) : (m & low[b]) | ((t & low[b]) << s);
+  }
+  return m;
+}
+
 // Wave total = lane 63 of the inclusive scan.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
