@@ -80,25 +80,6 @@ __device__ __forceinline__ Leaky make_leaky(double g) {
   return L;
 }
 
-// sum over the set bits k < top of m of q^(top - k), top a multiple of 8
-// (at most 64): eight independent 8-bit Horner chains, chunk c (bits 8c ..
-// 8c + 7) summing bit q^(8 - r) over its bits r, joined by powers of q^8.
-__device__ __forceinline__ double decay_sum(uint64_t m, int top, double q, double q8) {
-  double h[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    double v = 0.0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) v = (v + (double)(uint32_t)((m >> (8 * c + r)) & 1)) * q;
-    h[c] = v;
-  }
-  const int nch = top >> 3;
-  double acc = 0.0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc = c < nch ? fma(acc, q8, h[c]) : acc;
-  return acc;
-}
-
 template <int CTRL>
 __device__ __forceinline__ double dpp_all(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
@@ -174,21 +155,48 @@ __device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)(uint
 //   T  [y]  = sum_{x in tile} [Q = b] qx^(X0 + 64 - x)      (lane = row)
 __device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
+  // per block: byte tables F[v] = sum over the set bits r of v of q^(8 - r),
+  // for qy (band sums) and qx (row sums); every wave of the block helps build
+  // them before any returns
+  __shared__ double Fy[256], Fx[256];
+  for (int v = threadIdx.x; v < 256; v += blockDim.x) {
+    double fy = 0.0, fx = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double bit = (double)((v >> r) & 1);
+      fy = (fy + bit) * a.qy;
+      fx = (fx + bit) * a.qx;
+    }
+    Fy[v] = fy;
+    Fx[v] = fx;
+  }
+  __syncthreads();
   ExpTile t;
-  if (!exp_tile(g, exp_wave(vb), t)) return;
-  const int lane = lane_id();
-  const long NXP = (long)g.NTX * 64;
-  const uint64_t mask = exp_band_mask(a, t);
-  // this column's band sum relative to row Y0 + TY: sum_k bit_k qy^(TY - k)
-  const double c = decay_sum(mask, g.TY, a.qy, a.qy8);
-  const double zl = a.qx * leaky_scan(c, make_leaky(a.qx));
-  const long db = (long)t.d * g.B + t.b;
-  a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane] = zl;
-  if (lane == 63) a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx] = zl;
-  // row sums across the tile: after the transpose lane k holds row k's
-  // columns, T(y) = sum_l bit_l qx^(64 - l)
-  const double tr = decay_sum(wave_transpose64(mask), 64, a.qx, a.qx8);
-  if (lane < t.nrows) a.T[(db * g.NTX + t.tx) * g.H + t.y0 + lane] = tr;
+  const bool have = exp_tile(g, exp_wave(vb), t);
+  if (have) {
+    const int lane = lane_id();
+    const long NXP = (long)g.NTX * 64;
+    const uint64_t mask = exp_band_mask(a, t);
+    // this column's band sum relative to row Y0 + TY: sum_k bit_k qy^(TY - k),
+    // byte c of the mask weighing F[byte] q^(TY - 8c - 8)
+    double c = 0.0;
+    const int nch = g.TY >> 3;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c = k < nch ? fma(c, a.qy8, Fy[(mask >> (8 * k)) & 255]) : c;
+    const double zl = a.qx * leaky_scan(c, make_leaky(a.qx));
+    const long db = (long)t.d * g.B + t.b;
+    a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane] = zl;
+    if (lane == 63) a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx] = zl;
+    // row sums across the tile: after the transpose lane k holds row k's
+    // columns, T(y) = sum_l bit_l qx^(64 - l)
+    const uint64_t rowm = wave_transpose64(mask);
+    double tr = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tr = fma(tr, a.qx8, Fx[(rowm >> (8 * k)) & 255]);
+    if (lane < t.nrows) a.T[(db * g.NTX + t.tx) * g.H + t.y0 + lane] = tr;
+  }
+  // the tables are rebuilt for the next virtual block of a batched launch
+  __syncthreads();
 }
 
 // Scan: three independent chains.
