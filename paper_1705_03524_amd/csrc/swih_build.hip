@@ -247,13 +247,23 @@ __device__ __forceinline__ void scan_carries(const BuildArgs& a, int vb) {
     const int tx = c0 + lane;
     const bool ok = tx < g.NTX;
     BTy run = 0;
-    for (int ty = 0; ty < g.NTY; ++ty) {
-      const BTy v = ok ? base[(size_t)ty * g.NTX + tx] : (BTy)0;
-      const BTy inc = wave_incl_scan(run);
-      const BTy carry = rowcarry[w][ty];
-      if (ok) base[(size_t)ty * g.NTX + tx] = carry + inc - run;
-      rowcarry[w][ty] = carry + readlane(inc, 63);
-      run += v;
+    // eight bands' totals are loaded before any of them is replaced, so each
+    // group of eight costs one memory round trip
+    for (int ty0 = 0; ty0 < g.NTY; ty0 += 8) {
+      BTy v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = ok && ty0 + u < g.NTY ? base[(size_t)(ty0 + u) * g.NTX + tx] : (BTy)0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ty = ty0 + u;
+        if (ty >= g.NTY) break;
+        const BTy inc = wave_incl_scan(run);
+        const BTy carry = rowcarry[w][ty];
+        if (ok) base[(size_t)ty * g.NTX + tx] = carry + inc - run;
+        rowcarry[w][ty] = carry + readlane(inc, 63);
+        run += v[u];
+      }
     }
   }
 }

@@ -249,21 +249,33 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
   const double up = dpow(a.qx64, lane + 1);  // decay from tile 63 of the first chunk
   const bool v0 = lane < g.NTX, v1 = 64 + lane < g.NTX;  // NTX <= 128
   double k0 = 0.0, k1 = 0.0;
-  for (int ty = 0; ty < g.NTY; ++ty) {
-    double* row = CT + (long)ty * g.NTX;
-    const double t0 = v0 ? row[lane] : 0.0;
-    const double t1 = v1 ? row[64 + lane] : 0.0;
-    if (v0) row[lane] = k0;
-    if (v1) row[64 + lane] = k1;
-    const double s0 = leaky_scan(t0, Lt);
-    const double last0 = readlane(s0, 63);
-    const double s1 = fma(up, last0, leaky_scan(t1, Lt));
-    const double p0 = __shfl_up(s0, 1, 64);
-    const double p1 = __shfl_up(s1, 1, 64);
-    const double a0 = lane == 0 ? 0.0 : p0;
-    const double a1 = lane == 0 ? last0 : p1;
-    k0 = fma(qyT, k0, a0);
-    k1 = fma(qyT, k1, a1);
+  // eight bands' tile sums are loaded before any of them is replaced, so each
+  // group of eight costs one memory round trip
+  for (int ty0 = 0; ty0 < g.NTY; ty0 += 8) {
+    double t0[8], t1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* row = CT + (long)(ty0 + u) * g.NTX;
+      const bool in = ty0 + u < g.NTY;
+      t0[u] = in && v0 ? row[lane] : 0.0;
+      t1[u] = in && v1 ? row[64 + lane] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (ty0 + u >= g.NTY) break;
+      double* row = CT + (long)(ty0 + u) * g.NTX;
+      if (v0) row[lane] = k0;
+      if (v1) row[64 + lane] = k1;
+      const double s0 = leaky_scan(t0[u], Lt);
+      const double last0 = readlane(s0, 63);
+      const double s1 = fma(up, last0, leaky_scan(t1[u], Lt));
+      const double p0 = __shfl_up(s0, 1, 64);
+      const double p1 = __shfl_up(s1, 1, 64);
+      const double a0 = lane == 0 ? 0.0 : p0;
+      const double a1 = lane == 0 ? last0 : p1;
+      k0 = fma(qyT, k0, a0);
+      k1 = fma(qyT, k1, a1);
+    }
   }
 }
 
