@@ -336,24 +336,23 @@ bool cached(int n, int K, Fit& f) {
   return true;
 }
 
+// The reference side's fit, searched (and cached) on first use.
+bool reference(int K, Fit& ref) {
+  if (cached(kRefSide, K, ref)) return true;
+  ref = compute(kRefSide, K);
+  if (!ref.ok) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[{kRefSide, K}] = ref;
+  return true;
+}
+
 }  // namespace
 
 // Returns 0 on success, -1 for bad arguments or a failed fit.
 int gauss_fit(int n, int K, double* a_out, double* om_out, double* err_out) {
   if (n < 1 || n > 4095 || (n % 2) == 0 || K < 1 || K > 8) return -1;
   Fit f;
-  cached(n, K, f);
-  if (!f.ok) {
-    Fit ref;
-    if (n != kRefSide && (n - 1) / 2 > K && (cached(kRefSide, K, ref) || gauss_fit(kRefSide, K, nullptr, nullptr, nullptr) == 0) &&
-        cached(kRefSide, K, ref)) {
-      // refinement from the scaled reference, kept when it is as good as the
-      // search finds (a worst 2-D error within 2x of the reference's)
-      f = compute_scaled(n, K, ref);
-      if (f.ok && f.err > 2.0 * ref.err + 1e-15) f.ok = false;
-    }
-  }
-  if (!f.ok) {
+  if (!cached(n, K, f)) {
     if (n == 1) {
       // a single offset: g(0) = 1 exactly with a_0 = 1
       f.a.assign(K + 1, 0.0);
@@ -362,7 +361,14 @@ int gauss_fit(int n, int K, double* a_out, double* om_out, double* err_out) {
       f.err = 0.0;
       f.ok = true;
     } else {
-      f = compute(n, K);
+      Fit ref;
+      if (n != kRefSide && (n - 1) / 2 > K && reference(K, ref)) {
+        // refinement from the scaled reference, kept when it is as good as
+        // the search finds (a worst 2-D error within 2x of the reference's)
+        f = compute_scaled(n, K, ref);
+        if (f.ok && f.err > 2.0 * ref.err + 1e-15) f.ok = false;
+      }
+      if (!f.ok) f = compute(n, K);
       if (!f.ok) return -1;
     }
     std::lock_guard<std::mutex> lk(g_mu);

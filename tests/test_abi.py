@@ -180,6 +180,18 @@ def test_gauss_series_orders():
     assert e[1] > 1e-5 > 1e-7 > e[2]        # K = 2 misses the bar, K = 3 meets it with margin
 
 
+def test_gauss_series_fits_are_cached():
+    # a fit runs once per (side, K) per process: later calls are lookups
+    import time
+    for n in (23, 57, 99):
+        swih.gauss_terms(n)
+    t = time.perf_counter()
+    for _ in range(300):
+        for n in (23, 57, 99):
+            swih.gauss_terms(n)
+    assert time.perf_counter() - t < 0.1       # ~5 us a lookup; a refit costs 0.2-1 ms
+
+
 def test_gauss_series_beats_one_period():
     # free frequencies against harmonics of one integer period (the best
     # period's least-squares fit, by the same 2-D criterion): at least 100x
