@@ -260,7 +260,7 @@ def bench_serve(args):
     torch.cuda.synchronize()
     sweep = []
     for rate in [float(r) for r in args.rates.split(",")]:
-        n = max(32, int(rate * args.seconds))
+        n = max(200, int(rate * args.seconds))   # at least 200 requests, so p99 is not the maximum
         reqs = synth.serving_requests(7, rate, n)
         cont.templates = serving._Templates(cfg.nbins, "cuda")
         rc = serving.latency_stats(cont.serve(reqs))

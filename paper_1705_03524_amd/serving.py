@@ -137,9 +137,15 @@ class _MicroBatch:
 class ContinuousServer:
     def __init__(self, cfg: S.Config, pool: FramePool, budget: int, max_inflight: int = 3,
                  max_batch: int = 64, in_bytes: int = 64 << 20, out_floats: int = 32 << 20,
-                 device="cuda"):
+                 device="cuda", direct_single: bool = True):
+        """``direct_single``: while no more requests wait than there are free
+        slots, each runs alone on its own slot with the single-unit calls (no
+        batch table to plan and upload, the comb-form map); under heavier load
+        the waiting requests are batched.  The maps are the same bit for bit
+        either way."""
         self.cfg, self.pool, self.budget = cfg, pool, budget
         self.max_inflight, self.max_batch, self.device = max_inflight, max_batch, device
+        self.direct_single = direct_single
         self.in_bytes, self.out_floats = in_bytes, out_floats
         self.slots = [_Slot(budget, in_bytes, out_floats, device) for _ in range(max_inflight)]
         self.free = deque(range(max_inflight))
@@ -170,6 +176,8 @@ class ContinuousServer:
         with torch.cuda.stream(st):
             sl.d_in[:ioff].copy_(sl.h_in[:ioff], non_blocking=True)
             sl.d_cen[:coff].copy_(sl.h_cen[:coff], non_blocking=True)
+            if len(reqs) == 1 and self.direct_single:
+                return self._launch_direct(reqs[0], crops[0], cens[0], slot_id)
             for r, (io, h, w), cl in zip(reqs, crops, cens):
                 crop = sl.d_in[io:io + h * w].view(h, w)
                 r.maps = []
@@ -210,6 +218,45 @@ class ContinuousServer:
         mb.batch = b  # keep the plan table alive until done
         return mb
 
+    def _launch_direct(self, r, crop_io, cl, slot_id):
+        """One request with single-unit calls on the slot's stream (the current
+        stream here); its units run in stream order, so they share the slot's
+        workspace."""
+        cfg = self.cfg
+        sl = self.slots[slot_id]
+        st = sl.stream
+        io, h, w = crop_io
+        crop = sl.d_in[io:io + h * w].view(h, w)
+        r.maps = []
+        ooff = 0
+        for (sw, sh), (box, tc, rect), co in zip(r.scales, r.units, cl):
+            ux0, uy0, ux1, uy1 = box
+            view = crop[uy0:uy1 + 1, ux0:ux1 + 1]
+            uc = S.Config(cfg.nbins, cfg.kernel, [(sw, sh)], cfg.gauss_terms, band_rows=cfg.band_rows)
+            nb = S.workspace_bytes(uc, view.shape[0], view.shape[1])
+            p = Plan(uc, view.shape[0], view.shape[1], ws=sl.ws[:nb])
+            tmpl, new = self.templates.get(r.stream, (sw, sh))
+            if not new:
+                ev = self.templates.event(r.stream, (sw, sh))
+                if ev is not None:  # written by a batch on another stream
+                    st.wait_event(ev)
+            p.build(view)
+            if new:
+                S.query(uc, p.ws, p.H, p.W, 0, sl.d_cen[co:co + 2].view(1, 2), tmpl)
+                tev = torch.cuda.Event()
+                tev.record(st)
+                self.templates.produced(r.stream, (sw, sh), tev)
+            rows, cols = rect[3] - rect[1] + 1, rect[2] - rect[0] + 1
+            p.match(0, template=tmpl[0], rect=rect, out=sl.d_out[ooff:ooff + rows * cols].view(rows, cols))
+            r.maps.append((ooff, rows, cols))
+            ooff += rows * cols
+        sl.h_out[:ooff].copy_(sl.d_out[:ooff], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        mb = _MicroBatch([r], slot_id, ev)
+        mb.batch = None
+        return mb
+
     def _finish(self, mb):
         h_out = self.slots[mb.stream].h_out
         for r in mb.reqs:
@@ -239,7 +286,12 @@ class ContinuousServer:
                     r.t_done = t
                 done += len(mb.reqs)
                 self.free.append(mb.stream)
-            if pending and self.free:
+            if pending and self.free and self.direct_single and len(pending) <= len(self.free):
+                # light load: each waiting request alone on a free slot (the
+                # slots' streams overlap), no batching delay
+                while pending:
+                    inflight.append(self._launch([pending.popleft()], self.free.popleft()))
+            elif pending and self.free:
                 take, used, uin, uout = [], 0, 0, 0
                 while pending and len(take) < self.max_batch:
                     nb = request_bytes(self.cfg, pending[0])

@@ -13,14 +13,18 @@ import paper_1705_03524_amd as swih  # noqa: E402
 from paper_1705_03524_amd import serving  # noqa: E402
 
 
+@pytest.mark.parametrize("direct", [True, False])
 @pytest.mark.parametrize("kind", ["gaussian", "gaussian_sep", "exponential"])
-def test_served_maps_equal_serial(kind):
-    print("case: serving 48 requests at 400 req/s vs serial", flush=True)
+def test_served_maps_equal_serial(kind, direct):
+    # direct: micro-batches of one request use the single-unit calls
+    print("case: serving 48 requests at 400 req/s vs serial, %s, direct singles %s" % (kind, direct),
+          flush=True)
     cfg = swih.Config(16, kind, [(15, 15)])
     sizes = ((640, 480), (1280, 720))
     pool = serving.FramePool(sizes, lambda H, W: synth.smooth_noise(H + W, H, W))
     reqs = synth.serving_requests(3, 400.0, 48, nstreams=5, sizes=sizes)
-    cont = serving.ContinuousServer(cfg, pool, budget=8 << 30, max_inflight=3, max_batch=6)
+    cont = serving.ContinuousServer(cfg, pool, budget=8 << 30, max_inflight=3, max_batch=6,
+                                    direct_single=direct)
     got = cont.serve(reqs, keep_maps=True)
     torch.cuda.synchronize()
     ser = serving.SerialServer(cfg, pool, budget=8 << 30)
