@@ -106,8 +106,8 @@ def cpu_baseline(img, tc, budget_s):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": windows / dt, "unit": "windows/s", "cores": threads, "kind": "oracle",
-            "sample": "%d centre rows x 3 kernels (%d windows) of the 512x512 map, %.1f s" %
-                      (rows, windows, dt)}
+            "sample": "%d centre rows x 3 kernels (%d windows) of the 512x512 map, cycling through "
+                      "its %d rows, %.1f s" % (rows, windows, H - 2 * r, dt)}
 
 
 PROFILE_COUNTERS = os.path.join(HERE, "profiles", "swih_512_scene_hbm_counters.md")
