@@ -191,8 +191,7 @@ def bench_batch(args):
         t_gra = timed(bat.replay, steps)
         # the same batch with scan tiles picked by the autotuner per unit size class
         from paper_1705_03524_amd.autotune import Autotuner
-        tuner = Autotuner(os.path.join(HERE, "gpurun_out", "autotune.json") if os.path.isdir(
-            os.path.join(HERE, "gpurun_out")) else None)
+        tuner = Autotuner()  # cache: $SWIH_AUTOTUNE_CACHE, else ~/.cache/swih_autotune.json
         chosen = WL.tune_units(cfg, units, tuner)
         tun = WL.BatchedRunner(cfg, units, budget)
         for u in units:
