@@ -1,0 +1,81 @@
+"""GPU parity on seeded random configurations: image size, bins, window,
+kernel, scan-tile rows and series length drawn together, so combinations the
+hand-picked cases miss (ragged last bands and tiles at every band height, the
+paired and strided column splits of the Gaussian maps at every K, one-row and
+one-column windows) are met.  Each case is checked to the bar of its kernel:
+
+* uniform / Manhattan / Euclidean: raw histograms and maps bit for bit;
+* Gaussian (2-D and separable) and exponential: normalised histograms within
+  their oracle tolerance, maps within the bound that implies.
+
+Inputs are small enough for the oracle to compute every window.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_03524_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1705_03524_amd as swih  # noqa: E402
+from paper_1705_03524_amd.plan import Plan  # noqa: E402
+
+from gpu_util import EXP_TOL, GAUSS_TOL, all_centres, map_tolerance, to_dev  # noqa: E402
+
+OKIND = {swih.UNIFORM: oracle.UNIFORM, swih.MANHATTAN: oracle.MANHATTAN, swih.EUCLIDEAN: oracle.EUCLIDEAN,
+         swih.GAUSSIAN: oracle.GAUSSIAN, swih.GAUSSIAN_SEP: oracle.GAUSSIAN, swih.EXPONENTIAL: oracle.EXPONENTIAL}
+
+
+def draw(seed):
+    rng = np.random.default_rng(1000 + seed)
+    kind = [swih.UNIFORM, swih.MANHATTAN, swih.EUCLIDEAN, swih.GAUSSIAN, swih.GAUSSIAN_SEP,
+            swih.EXPONENTIAL][seed % 6]
+    H, W = int(rng.integers(1, 150)), int(rng.integers(1, 200))
+    K = int(rng.choice([1, 2, 3, 3, 5])) if kind in (swih.GAUSSIAN, swih.GAUSSIAN_SEP) else 0
+    # series shorter than the default are checked on windows they interpolate
+    # exactly (at most 2K + 1 offsets per axis), so the true-Gaussian oracle
+    # still holds them to the same bar
+    side = 41 if K == 0 or K >= 3 else 2 * K + 1
+    w = int(rng.integers(0, (min(W, side) + 1) // 2)) * 2 + 1
+    h = int(rng.integers(0, (min(H, side) + 1) // 2)) * 2 + 1
+    nb = int(rng.choice([1, 2, 3, 5, 8, 16, 32, 64]))
+    band = int(rng.choice([0, 16, 32, 64])) if kind != swih.GAUSSIAN_SEP else 0
+    smooth = bool(rng.integers(0, 2)) and H >= 8 and W >= 8
+    img = synth.smooth_noise(seed, H, W) if smooth else synth.uniform_noise(seed, H, W)
+    return kind, img, nb, w, h, band, K
+
+
+@pytest.mark.parametrize("seed", range(36))
+def test_random_configuration(seed):
+    kind, img, nb, w, h, band, K = draw(seed)
+    H, W = img.shape
+    print("case: seed %d kind %d %dx%d bins %d window %dx%d band_rows %d K %d"
+          % (seed, kind, H, W, nb, w, h, band, K), flush=True)
+    ok = OKIND[kind]
+    plan = Plan(swih.Config(nb, kind, [(w, h)], gauss_terms=K, band_rows=band), H, W)
+    plan.build(to_dev(img, torch))
+    c = all_centres(H, W, w, h)
+    tc = tuple(int(v) for v in c[(seed * 7919) % len(c)])
+    hist, raw = plan.query(0, to_dev(c, torch))
+    thist, traw = plan.query(0, to_dev(np.array([tc], np.int32), torch))
+    rect = plan.valid_rect(0)
+    if plan.integer:
+        ref = oracle.hist(img, nb, ok, w, h, c)
+        assert np.array_equal(raw.cpu().numpy().astype(np.int64), ref), seed
+        tref, _ = oracle.template(img, nb, ok, w, h, tc)
+        m = plan.match(0, template_raw=traw[0].contiguous()).cpu().numpy()
+        assert np.array_equal(m, oracle.bc_map(img, nb, ok, w, h, tref).astype(np.float32)), seed
+        return
+    tol = EXP_TOL if kind == swih.EXPONENTIAL else GAUSS_TOL
+    pref = oracle.normalised(oracle.hist(img, nb, ok, w, h, c), ok, w, h)
+    herr = np.abs(hist.cpu().numpy().astype(np.float64) - pref).max()
+    _, tref = oracle.template(img, nb, ok, w, h, tc)
+    m = plan.match(0, template=thist[0].contiguous()).cpu().numpy().astype(np.float64)
+    mref = oracle.bc_map(img, nb, ok, w, h, tref)
+    mtol = map_tolerance(pref, tref, tol).reshape(m.shape) + 1e-6
+    print({"hist_err": float(herr), "map_err": float(np.abs(m - mref).max())}, flush=True)
+    assert herr <= tol, (seed, herr)
+    assert np.all(np.abs(m - mref) <= mtol), seed
+    assert rect[2] - rect[0] + 1 == m.shape[1] and rect[3] - rect[1] + 1 == m.shape[0]
