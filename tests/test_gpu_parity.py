@@ -223,6 +223,21 @@ def test_gaussian_other_series_lengths(K, kind):
                 map_rect=(7, 10, W - 8, H - 11), kind=kind, K=K)
 
 
+@pytest.mark.parametrize("kind", GAUSS_KINDS)
+def test_gaussian_windows_wider_than_a_block(kind):
+    # windows whose span exceeds half a map block's columns: the 2-D map reads
+    # each chunk's left and right window edges as two column segments
+    # (a map taller than two windows, so the 2-D form takes its comb path)
+    H, W = 460, 420
+    img = synth.smooth_noise(41, H, W)
+    w, h = 161, 151
+    c = synth.sample_centres(77, H, W, w, h, 2048)
+    print("case: gaussian(%d) %dx%d window %dx%d" % (kind, H, W, w, h), flush=True)
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    gauss_check(img, 8, w, h, c, (W // 2, H // 2), "gaussian(%d) wide window" % kind,
+                map_rect=(rx, ry, rx + 40, H - 1 - ry), kind=kind)
+
+
 @pytest.mark.parametrize("w", [21, 31, 45, 63, 81])
 def test_gaussian_multiscale_2048(w):
     # 2048 x 2048 smooth noise, 32 bins, one scale at a time (planes ~9-48 GB)
