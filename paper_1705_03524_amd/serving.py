@@ -141,8 +141,9 @@ class ContinuousServer:
         """``direct_single``: while no more requests wait than there are free
         slots, each runs alone on its own slot with the single-unit calls (no
         batch table to plan and upload, the comb-form map); under heavier load
-        the waiting requests are batched.  The maps are the same bit for bit
-        either way."""
+        the waiting requests are spread over the free slots as micro-batches
+        (without it, they all go to one slot).  The maps are the same bit for
+        bit either way."""
         self.cfg, self.pool, self.budget = cfg, pool, budget
         self.max_inflight, self.max_batch, self.device = max_inflight, max_batch, device
         self.direct_single = direct_single
@@ -277,8 +278,14 @@ class ContinuousServer:
             while i < n and reqs[i].t_arrive <= now:
                 pending.append(reqs[i])
                 i += 1
-            while inflight and inflight[0].event.query():
-                mb = inflight.popleft()
+            # every in-flight micro-batch is polled, not just the oldest: the
+            # slots' streams finish out of order, and a small request must not
+            # wait behind a large one launched before it
+            running = deque()
+            for mb in inflight:
+                if not mb.event.query():
+                    running.append(mb)
+                    continue
                 t = clock() - t0
                 if keep_maps:
                     self._finish(mb)
@@ -286,21 +293,26 @@ class ContinuousServer:
                     r.t_done = t
                 done += len(mb.reqs)
                 self.free.append(mb.stream)
+            inflight = running
             if pending and self.free and self.direct_single and len(pending) <= len(self.free):
                 # light load: each waiting request alone on a free slot (the
                 # slots' streams overlap), no batching delay
                 while pending:
                     inflight.append(self._launch([pending.popleft()], self.free.popleft()))
             elif pending and self.free:
-                take, used, uin, uout = [], 0, 0, 0
-                while pending and len(take) < self.max_batch:
-                    nb = request_bytes(self.cfg, pending[0])
-                    ib, of = request_io(pending[0])
-                    if used + nb > self.budget or uin + ib > self.in_bytes or uout + of > self.out_floats:
-                        break
-                    take.append(pending.popleft())
-                    used, uin, uout = used + nb, uin + ib, uout + of
-                inflight.append(self._launch(take, self.free.popleft()))
+                # the waiting requests are spread over the free slots, a share
+                # each (at most max_batch, within the slot's budgets)
+                while pending and self.free:
+                    share = -(-len(pending) // len(self.free)) if self.direct_single else self.max_batch
+                    take, used, uin, uout = [], 0, 0, 0
+                    while pending and len(take) < min(share, self.max_batch):
+                        nb = request_bytes(self.cfg, pending[0])
+                        ib, of = request_io(pending[0])
+                        if used + nb > self.budget or uin + ib > self.in_bytes or uout + of > self.out_floats:
+                            break
+                        take.append(pending.popleft())
+                        used, uin, uout = used + nb, uin + ib, uout + of
+                    inflight.append(self._launch(take, self.free.popleft()))
             elif not pending and i < n and not inflight:
                 time.sleep(max(0.0, min(0.0005, reqs[i].t_arrive - (clock() - t0))))
         return reqs
