@@ -622,7 +622,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
       scale_params(&fc, gauss ? k : 0, sp);
       int32_t nb[4];
       build_args(layouts[f], k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, fd.d_img,
-                 fd.pitch, (char*)fd.d_ws, units[u], nb);
+                 fd.pitch, (char*)fd.d_ws, units[u], nb, true);
       for (int s = 0; s < 4; ++s) upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + nb[s];
     }
   }
@@ -744,7 +744,7 @@ int swih_build_batch(const void* h_table, const void* d_table, void* stream) {
                                   kBatchGrid, (hipStream_t)stream) == hipSuccess
                ? SWIH_OK
                : SWIH_ERR_HIP;
-  return launch_build_batch(h->kind, h->nt, (const BuildArgs*)(db + h->off_units),
+  return launch_build_batch(h->kind, h->nt, h->nbins, (const BuildArgs*)(db + h->off_units),
                             (const int32_t*)(db + h->off_uprefix), h->nunits, h->total, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess
              ? SWIH_OK

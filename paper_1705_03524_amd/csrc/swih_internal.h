@@ -48,19 +48,25 @@ struct BuildArgs {
   void* BT;           // tile totals -> tile-origin values
   int64_t* acc;       // Gaussian: the map accumulator of the set, cleared by the build
   int64_t nacc;
+  int32_t agg_hist;   // integer kernels: aggregate by LDS histograms, a block per (band, tile)
+  int32_t pad;
   GaussAxis ax, ay;
 };
 
 // Fill the arguments of one plane set; nb = blocks of the basis, aggregate,
-// scan and emit stages.
+// scan and emit stages.  `batched`: the set is one unit of a batched build
+// (its aggregate may then use the histogram form at any size).
 void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay,
-                const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4]);
+                const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4],
+                bool batched = false);
 
 // One batched build: every stage in one grid-stride launch over the units.
 // prefix: 4 arrays of nunits + 1 exclusive block prefixes (device memory, with
-// the units); total: blocks per stage; grid: blocks per launch.
-hipError_t launch_build_batch(int kind, int nt, const BuildArgs* units, const int32_t* prefix,
-                              int nunits, const int32_t (&total)[4], int grid, hipStream_t stream);
+// the units); total: blocks per stage; grid: blocks per launch; nbins: the
+// units' bin count (they share it).
+hipError_t launch_build_batch(int kind, int nt, int nbins, const BuildArgs* units,
+                              const int32_t* prefix, int nunits, const int32_t (&total)[4], int grid,
+                              hipStream_t stream);
 
 // Build: integer kernels write one global plane set; the Gaussian writes set
 // `set` with the axis series of that scale.

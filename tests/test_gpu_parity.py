@@ -108,6 +108,38 @@ def test_ragged_integer(kind, HW, nb, wh):
     assert np.array_equal(m, mref.astype(np.float32))
 
 
+# Both aggregate forms of the integer kernels: a plane set of at least 128
+# (band, tile) blocks counts all bins at once in LDS histograms (up to 64 bins,
+# 32 for the Euclidean's wider counters), smaller ones take a wave per bin.
+# Ragged last bands and tiles; the last tile's 12 columns leave three of the
+# four row-pass quarters empty.
+@pytest.mark.parametrize("kind", INT_KINDS)
+@pytest.mark.parametrize("HW,nb,band,wh", [
+    ((300, 1100), 5, 16, (7, 9)),     # 342 blocks: histogram form
+    ((300, 1100), 64, 16, (9, 5)),    # histogram form (Euclidean: per-bin, 64 bins)
+    ((300, 1100), 32, 64, (15, 15)),  # 90 blocks: per-bin form
+    ((517, 1100), 1, 32, (3, 17)),    # one bin, histogram form
+    ((700, 1300), 16, 64, (31, 31)),  # 231 blocks of 64 rows, histogram form
+])
+def test_integer_aggregate_forms(kind, HW, nb, band, wh):
+    H, W = HW
+    w, h = wh
+    print("case: aggregate forms %dx%d bins %d band %d window %dx%d kind %d" % (H, W, nb, band, w, h, kind),
+          flush=True)
+    img = synth.smooth_noise(H + W + nb, H, W) if nb >= 16 else synth.uniform_noise(H * 7 + W, H, W)
+    plan = Plan(swih.Config(nb, kind, [(w, h)], band_rows=band), H, W)
+    plan.build(to_dev(img, torch))
+    c = all_centres(H, W, w, h)
+    tc = tuple(int(v) for v in c[(len(c) * 3) // 7])
+    _, raw = plan.query(0, to_dev(c, torch))
+    _, traw = plan.query(0, to_dev(np.array([tc], np.int32), torch))
+    m = plan.match(0, template_raw=traw[0].contiguous()).cpu().numpy()
+    ref = oracle.hist(img, nb, kind, w, h, c)
+    assert np.array_equal(raw.cpu().numpy().astype(np.int64), ref)
+    tref, _ = oracle.template(img, nb, kind, w, h, tc)
+    assert np.array_equal(m, oracle.bc_map(img, nb, kind, w, h, tref).astype(np.float32))
+
+
 def test_sub_rectangle_and_pitch():
     # a crop inside a wider frame (row pitch > width) and a map over a sub-rectangle
     frame = synth.smooth_noise(4, 300, 400)
