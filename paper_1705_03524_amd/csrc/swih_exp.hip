@@ -19,8 +19,9 @@
 // where the factors are exp(1/t) (near corner of the centre's own quadrant),
 // 1 (near corner of the opposite one) or exp(-r/t) (far corner).  E obeys
 //   E(X, Y + 1) = qy (E(X, Y) + R(X, Y)),   R(X, y) = sum_{x < X} [Q = b] qx^(X - x),
-// which the build runs down each 64-column tile of a 64-row band in double,
-// with three carries made exactly like the integer kernels' (aggregate, scan,
+// which the build runs down each 64-column tile of a 64-row band in double
+// (the in-row prefix R inside the tile in float, the carried value E in
+// double), with three carries made exactly like the integer kernels' (aggregate, scan,
 // emit): the band-top column values, the row values at the tile's left edge
 // and the tile-origin values E(64 tx, TY ty), each a chain with the decay of
 // one tile or band.  The planes are stored as float (relative error 2^-24).
@@ -49,11 +50,13 @@ __device__ __forceinline__ long exp_wave(int vb) {
 // with bound_ctrl (a lane without a source reads 0), so no destination needs
 // clearing first; the broadcasts' factor is 0 on the rows they must not
 // change, whatever those rows read.
-struct Leaky {
-  double g1, g2, g4, g8;
-  double f15;  // rows 1 and 3: g^((l & 15) + 1), the distance from lane 15 (47); else 0
-  double f31;  // rows 2 and 3: g^(l - 31); else 0
+template <typename T>
+struct LeakyT {
+  T g1, g2, g4, g8;
+  T f15;  // rows 1 and 3: g^((l & 15) + 1), the distance from lane 15 (47); else 0
+  T f31;  // rows 2 and 3: g^(l - 31); else 0
 };
+using Leaky = LeakyT<double>;
 
 // q^n for 0 <= n < 128 (n per lane, q uniform): squarings of q and a product
 // over the bits of n, relative error a few ulps.
@@ -95,6 +98,28 @@ __device__ __forceinline__ double leaky_scan(double v, const Leaky& L) {
   v = fma(L.g8, dpp_all<0x118>(v), v);   // row_shr:8
   v = fma(L.f15, dpp_all<0x142>(v), v);  // row_bcast:15 (used by rows 1 and 3)
   v = fma(L.f31, dpp_all<0x143>(v), v);  // row_bcast:31 (used by rows 2 and 3)
+  return v;
+}
+
+// The same scan in FP32, for sums inside one tile row (at most 64 terms, each
+// at most 1): the emit's row prefix.  Sums that cross tiles stay in FP64.
+__device__ __forceinline__ LeakyT<float> to_float(const Leaky& L) {
+  return {(float)L.g1, (float)L.g2, (float)L.g4, (float)L.g8, (float)L.f15, (float)L.f31};
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_all(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf,
+                                                               0xf, true));
+}
+
+__device__ __forceinline__ float leaky_scan(float v, const LeakyT<float>& L) {
+  v = fmaf(L.g1, dpp_all<0x111>(v), v);
+  v = fmaf(L.g2, dpp_all<0x112>(v), v);
+  v = fmaf(L.g4, dpp_all<0x114>(v), v);
+  v = fmaf(L.g8, dpp_all<0x118>(v), v);
+  v = fmaf(L.f15, dpp_all<0x142>(v), v);
+  v = fmaf(L.f31, dpp_all<0x143>(v), v);
   return v;
 }
 
@@ -294,7 +319,7 @@ __device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
   const uint64_t mask = exp_band_mask(a, t);
   const double qx = a.qx, qy = a.qy;
   const double pw = dpow(qx, lane + 1);
-  const Leaky Lx = make_leaky(qx);
+  const LeakyT<float> Lx = to_float(make_leaky(qx));
   const long db = (long)t.d * g.B + t.b;
   const double K = a.CT[(db * g.NTY + t.ty) * g.NTX + t.tx];
   double e = fma(pw, K, a.z[(db * g.NTY + t.ty) * NXP + (long)t.tx * 64 + lane]);
@@ -302,7 +327,7 @@ __device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
   float* P = a.planes + swih_base(g, t.d, t.b) + (long)t.tx * g.tile_stride + lane;
   if (t.ty == 0) P[0] = 0.0f;
   for (int k = 0; k < t.nrows; ++k) {
-    const double s = leaky_scan(mbit(mask, k), Lx);
+    const double s = (double)leaky_scan((float)((mask >> k) & 1), Lx);
     const double R = fma(qx, s, pw * readlane(creg, k));
     e = qy * (e + R);
     P[(long)(t.y0 + k + 1) * g.row_stride] = (float)e;
