@@ -17,6 +17,9 @@ class Plan:
         self.ws = ws if ws is not None else torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         if self.ws.data_ptr() % 256:
             raise ValueError("workspace must be 256-byte aligned")
+        if self.ws.numel() * self.ws.element_size() < self.nbytes:
+            raise ValueError("workspace of %d bytes is smaller than the %d this plan needs"
+                             % (self.ws.numel() * self.ws.element_size(), self.nbytes))
         self.device = self.ws.device
 
     @property

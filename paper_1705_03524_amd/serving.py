@@ -114,6 +114,9 @@ class _Templates:
         return self.ready.get((stream, scale))
 
 
+CENTRE_INTS = 4096  # template centres staged per slot (two ints per unit)
+
+
 class _Slot:
     """One in-flight micro-batch's memory: workspace, pinned host staging for
     crops / template centres / maps and their device counterparts, a stream."""
@@ -122,8 +125,8 @@ class _Slot:
         self.ws = torch.empty(budget, dtype=torch.uint8, device=device)
         self.h_in = torch.empty(in_bytes, dtype=torch.uint8, pin_memory=True)
         self.d_in = torch.empty(in_bytes, dtype=torch.uint8, device=device)
-        self.h_cen = torch.empty(4096, dtype=torch.int32, pin_memory=True)
-        self.d_cen = torch.empty(4096, dtype=torch.int32, device=device)
+        self.h_cen = torch.empty(CENTRE_INTS, dtype=torch.int32, pin_memory=True)
+        self.d_cen = torch.empty(CENTRE_INTS, dtype=torch.int32, device=device)
         self.h_out = torch.empty(out_floats, dtype=torch.float32, pin_memory=True)
         self.d_out = torch.empty(out_floats, dtype=torch.float32, device=device)
         self.stream = torch.cuda.Stream()
@@ -268,7 +271,8 @@ class ContinuousServer:
         reqs = [Request(r) for r in requests]
         for r in reqs:
             ib, of = request_io(r)
-            if request_bytes(self.cfg, r) > self.budget or ib > self.in_bytes or of > self.out_floats:
+            if (request_bytes(self.cfg, r) > self.budget or ib > self.in_bytes or of > self.out_floats
+                    or 2 * len(r.units) > CENTRE_INTS):
                 raise ValueError("request %d exceeds a slot's capacity" % r.id)
         pending, inflight = deque(), deque()
         i, done, n = 0, 0, len(reqs)
@@ -304,14 +308,16 @@ class ContinuousServer:
                 # each (at most max_batch, within the slot's budgets)
                 while pending and self.free:
                     share = -(-len(pending) // len(self.free)) if self.direct_single else self.max_batch
-                    take, used, uin, uout = [], 0, 0, 0
+                    take, used, uin, uout, ucen = [], 0, 0, 0, 0
                     while pending and len(take) < min(share, self.max_batch):
                         nb = request_bytes(self.cfg, pending[0])
                         ib, of = request_io(pending[0])
-                        if used + nb > self.budget or uin + ib > self.in_bytes or uout + of > self.out_floats:
+                        nc = 2 * len(pending[0].units)
+                        if (used + nb > self.budget or uin + ib > self.in_bytes or uout + of > self.out_floats
+                                or ucen + nc > CENTRE_INTS):
                             break
                         take.append(pending.popleft())
-                        used, uin, uout = used + nb, uin + ib, uout + of
+                        used, uin, uout, ucen = used + nb, uin + ib, uout + of, ucen + nc
                     inflight.append(self._launch(take, self.free.popleft()))
             elif not pending and i < n and not inflight:
                 time.sleep(max(0.0, min(0.0005, reqs[i].t_arrive - (clock() - t0))))

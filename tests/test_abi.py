@@ -56,6 +56,20 @@ def test_workspace_bytes_and_validation():
     assert g2 > 1.9 * g1 - 2e6
 
 
+def test_plan_checks_a_given_workspace():
+    torch = pytest.importorskip("torch")
+    from paper_1705_03524_amd.plan import Plan
+    cfg = swih.Config(8, swih.MANHATTAN, [(15, 15)])
+    need = swih.workspace_bytes(cfg, 64, 64)
+    buf = torch.empty(need + 512, dtype=torch.uint8)
+    off = (-buf.data_ptr()) % 256
+    with pytest.raises(ValueError, match="smaller"):
+        Plan(cfg, 64, 64, ws=buf[off:off + need - 1])
+    with pytest.raises(ValueError, match="aligned"):
+        Plan(cfg, 64, 64, ws=buf[off + 1:off + 1 + need])
+    assert Plan(cfg, 64, 64, ws=buf[off:off + need]).nbytes == need
+
+
 def test_separable_workspace_and_validation():
     # one set per scale: H x W x B floats of row results (sized for any window)
     def a256(v):
