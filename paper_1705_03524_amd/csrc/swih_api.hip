@@ -740,7 +740,7 @@ int swih_build_batch(const void* h_table, const void* d_table, void* stream) {
   }
   if (h->kind == SWIH_EXPONENTIAL)
     return exp_launch_build_batch((const ExpBuildArgs*)(db + h->off_units),
-                                  (const int32_t*)(db + h->off_uprefix), h->nunits, h->total,
+                                  (const int32_t*)(db + h->off_uprefix), h->nunits, h->nbins, h->total,
                                   kBatchGrid, (hipStream_t)stream) == hipSuccess
                ? SWIH_OK
                : SWIH_ERR_HIP;

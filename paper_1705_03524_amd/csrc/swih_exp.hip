@@ -174,11 +174,106 @@ __device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const E
 __device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)(uint32_t)((m >> k) & 1); }
 
 // ---------------------------------------------------------------- build
+// Aggregate by LDS histograms (at most kExpHistMaxB bins): one block per
+// (direction, band, tile) gathers every bin at once.  Each pixel adds its
+// weight to the LDS counter of its bin: qy^(TY - k) to its column's (k = its
+// mirrored row in the band) and qx^(64 - l) to its row's (l = its mirrored
+// column in the tile).  Weights are fixed point in units of 2^-52 and a
+// counter sums at most 64 of them (each below 1), so the int64 sums are exact
+// and do not depend on the order the atomics land in.  The counters then give
+// the same z, CT and T as the per-bin form.
+constexpr int kExpHistMaxB = 32;
+constexpr int kExpHistRow = 80;  // LDS bytes per staged row (16-byte aligned, banks spread)
+
+__host__ __device__ constexpr int exp_hist_lds_bytes(int B) {
+  return 64 * kExpHistRow + 2 * 64 * 8 + 2 * B * 64 * 8;
+}
+
+extern __shared__ __align__(16) unsigned char exp_hist_lds[];
+
+__device__ __forceinline__ void exp_aggregate_hist(const ExpBuildArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const int B = g.B;
+  const int tx = vb % g.NTX, r = vb / g.NTX;
+  const int ty = r % g.NTY, d = r / g.NTY;
+  const int y0 = ty * g.TY, nrows = min(g.TY, g.H - y0);
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  unsigned char* tile = exp_hist_lds;
+  int64_t* py = (int64_t*)(exp_hist_lds + 64 * kExpHistRow);  // [64] qy^(TY - k)
+  int64_t* px = py + 64;                                        // [64] qx^(64 - l)
+  int64_t* colh = px + 64;                                      // [B][64]
+  int64_t* rowh = colh + B * 64;                                // [B][64]
+  constexpr double kFix = 4503599627370496.0;                   // 2^52
+  // wave w loads mirrored rows 16 w .. 16 w + 15 of the band at mirrored
+  // column 64 tx + lane (clamped into the image)
+  const int xm = tx * 64 + lane;
+  const bool xok = xm < g.W;
+  const int xo = xok ? ((d & 1) ? g.W - 1 - xm : xm) : 0;
+  const bool my = (d & 2) != 0;
+  const long step = my ? -(long)a.ipitch : (long)a.ipitch;
+  const uint8_t* col = a.img + (long)(my ? g.H - 1 - y0 : y0) * a.ipitch + xo;
+  uint32_t v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int k = 16 * w + i;
+    v[i] = col[(long)(k < nrows ? k : nrows - 1) * step];
+  }
+  __syncthreads();  // an earlier virtual block of this block is done with LDS
+  {
+    uint4* c4 = (uint4*)colh;
+    const int n4 = 2 * B * 64 * 8 / 16;
+    for (int i = (int)threadIdx.x; i < n4; i += WG) c4[i] = make_uint4(0u, 0u, 0u, 0u);
+    const int t = (int)threadIdx.x;
+    if (t < 64) py[t] = t < g.TY ? (int64_t)llrint(dpow(a.qy, g.TY - t) * kFix) : 0;
+    else if (t < 128) px[t - 64] = (int64_t)llrint(dpow(a.qx, 128 - t) * kFix);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int k = 16 * w + i;
+    tile[k * kExpHistRow + lane] = (unsigned char)v[i];
+    if (k < nrows && xok)
+      __hip_atomic_fetch_add(&colh[((v[i] * (uint32_t)B) >> 8) * 64 + lane], py[k], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __syncthreads();
+  {
+    // lane = mirrored row of the band, wave w counts mirrored columns 16 w .. 16 w + 15
+    const uint4 r4 = *(const uint4*)(tile + lane * kExpHistRow + 16 * w);
+    const uint32_t rw[4] = {r4.x, r4.y, r4.z, r4.w};
+    const int nx = min(16, g.W - (tx * 64 + 16 * w));
+    if (lane < nrows) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t pv = (rw[j >> 2] >> (8 * (j & 3))) & 255u;
+        if (j < nx)
+          __hip_atomic_fetch_add(&rowh[((pv * (uint32_t)B) >> 8) * 64 + lane], px[16 * w + j],
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+  __syncthreads();
+  const long NXP = (long)g.NTX * 64;
+  const Leaky Lx = make_leaky(a.qx);
+  for (int b = w; b < B; b += WPB) {
+    const long db = (long)d * B + b;
+    const double c = (double)colh[b * 64 + lane] / kFix;
+    const double zl = a.qx * leaky_scan(c, Lx);
+    a.z[(db * g.NTY + ty) * NXP + (long)tx * 64 + lane] = zl;
+    if (lane == 63) a.CT[(db * g.NTY + ty) * g.NTX + tx] = zl;
+    if (lane < nrows) a.T[(db * g.NTX + tx) * g.H + y0 + lane] = (double)rowh[b * 64 + lane] / kFix;
+  }
+}
+
 // Aggregate: per (direction, bin, band, tile) wave (band of TY rows)
 //   z  [X]  = sum_{X0 <= x < X, y in band} [Q = b] qx^(X - x) qy^(Y0 + TY - y)
 //   CT      = the same at X = X0 + 64 (the tile total)
 //   T  [y]  = sum_{x in tile} [Q = b] qx^(X0 + 64 - x)      (lane = row)
 __device__ __forceinline__ void exp_aggregate(const ExpBuildArgs& a, int vb) {
+  if (a.agg_hist) {
+    exp_aggregate_hist(a, vb);
+    return;
+  }
   const SwihGeom& g = a.g;
   // per block: byte tables F[v] = sum over the set bits r of v of q^(8 - r),
   // for qy (band sums) and qx (row sums); every wave of the block helps build
@@ -425,18 +520,18 @@ __global__ __launch_bounds__(WG) void k_exp_many(const A* __restrict__ items,
 namespace {
 
 template <class A, void (*BODY)(const A&, int)>
-hipError_t one(const A& a, int32_t nb, hipStream_t s) {
+hipError_t one(const A& a, int32_t nb, hipStream_t s, int lds = 0) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_exp_one<A, BODY>), dim3((unsigned)nb), dim3(WG), 0, s, a);
+  hipLaunchKernelGGL((k_exp_one<A, BODY>), dim3((unsigned)nb), dim3(WG), lds, s, a);
   return hipGetLastError();
 }
 
 template <class A, void (*BODY)(const A&, int)>
 hipError_t many(const A* items, const int32_t* prefix, int n, int32_t total, int grid,
-                hipStream_t s) {
+                hipStream_t s, int lds = 0) {
   if (n <= 0 || total <= 0) return hipSuccess;
   const unsigned gb = (unsigned)(total < grid ? total : grid);
-  hipLaunchKernelGGL((k_exp_many<A, BODY>), dim3(gb), dim3(WG), 0, s, items, prefix, n);
+  hipLaunchKernelGGL((k_exp_many<A, BODY>), dim3(gb), dim3(WG), lds, s, items, prefix, n);
   return hipGetLastError();
 }
 
@@ -489,8 +584,11 @@ void exp_build_args(const SwihLayout& L, const ExpScale& s, int set, const uint8
   const long waves = 4L * g.B * g.NTY * g.NTX;
   a.nb1 = blocks_of_threads(4L * g.B * g.NTX * 64);
   a.nb2 = blocks_of_threads(4L * g.B * g.H);
+  // the form depends on the bin count only, so one plane set and a batch of
+  // them round alike
+  a.agg_hist = g.B <= kExpHistMaxB;
   nb[0] = 0;
-  nb[1] = blocks_of_waves(waves);
+  nb[1] = a.agg_hist ? 4 * g.NTY * g.NTX : blocks_of_waves(waves);
   nb[2] = a.nb1 + a.nb2 + blocks_of_waves(4L * g.B);
   nb[3] = blocks_of_waves(waves);
 }
@@ -536,7 +634,7 @@ hipError_t exp_launch_build(const ExpBuildArgs& a, const int32_t (&nb)[4], int p
                             hipStream_t s) {
   hipError_t e = hipSuccess;
   if (phases & 1) {
-    e = one<ExpBuildArgs, agg_body>(a, nb[1], s);
+    e = one<ExpBuildArgs, agg_body>(a, nb[1], s, a.agg_hist ? exp_hist_lds_bytes(a.g.B) : 0);
     if (e == hipSuccess) e = one<ExpBuildArgs, scan_body>(a, nb[2], s);
   }
   if (e == hipSuccess && (phases & 2)) e = one<ExpBuildArgs, emit_body>(a, nb[3], s);
@@ -552,11 +650,12 @@ hipError_t exp_launch_match(const ExpMatchArgs& a, int32_t nb, hipStream_t s) {
 }
 
 hipError_t exp_launch_build_batch(const ExpBuildArgs* units, const int32_t* prefix, int nunits,
-                                  const int32_t (&total)[4], int grid, hipStream_t s) {
+                                  int nbins, const int32_t (&total)[4], int grid, hipStream_t s) {
   if (nunits <= 0) return hipSuccess;
   const int32_t* pre[4];
   for (int k = 0; k < 4; ++k) pre[k] = prefix + (size_t)k * (nunits + 1);
-  hipError_t e = many<ExpBuildArgs, agg_body>(units, pre[1], nunits, total[1], grid, s);
+  hipError_t e = many<ExpBuildArgs, agg_body>(units, pre[1], nunits, total[1], grid, s,
+                                              nbins <= kExpHistMaxB ? exp_hist_lds_bytes(nbins) : 0);
   if (e == hipSuccess) e = many<ExpBuildArgs, scan_body>(units, pre[2], nunits, total[2], grid, s);
   if (e == hipSuccess) e = many<ExpBuildArgs, emit_body>(units, pre[3], nunits, total[3], grid, s);
   return e;

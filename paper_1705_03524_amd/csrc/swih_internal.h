@@ -268,6 +268,8 @@ struct ExpBuildArgs {
   // decays, computed on the host: one column / row step (qx = exp(-1/tx),
   // qy = exp(-1/ty)), eight of them, one band (qy^TY) and one tile (qx^64)
   double qx, qy, qx8, qy8, qyT, qx64;
+  int32_t agg_hist;    // aggregate by LDS histograms, a block per (direction, band, tile)
+  int32_t pad;
 };
 
 struct ExpQueryArgs {
@@ -303,8 +305,9 @@ hipError_t exp_launch_build(const ExpBuildArgs& a, const int32_t (&nb)[4], int p
                             hipStream_t s);
 hipError_t exp_launch_query(const ExpQueryArgs& a, int32_t nb, hipStream_t s);
 hipError_t exp_launch_match(const ExpMatchArgs& a, int32_t nb, hipStream_t s);
+// nbins: the units' bin count (they share it).
 hipError_t exp_launch_build_batch(const ExpBuildArgs* units, const int32_t* prefix, int nunits,
-                                  const int32_t (&total)[4], int grid, hipStream_t s);
+                                  int nbins, const int32_t (&total)[4], int grid, hipStream_t s);
 hipError_t exp_launch_query_batch(const ExpQueryArgs* items, const int32_t* prefix, int n,
                                   int32_t total, int grid, hipStream_t s);
 hipError_t exp_launch_match_batch(const ExpMatchArgs* items, const int32_t* prefix, int n,
