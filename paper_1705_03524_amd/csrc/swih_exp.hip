@@ -422,7 +422,7 @@ __device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
   float* P = a.planes + swih_base(g, t.d, t.b) + (long)t.tx * g.tile_stride + lane;
   if (t.ty == 0) P[0] = 0.0f;
   for (int k = 0; k < t.nrows; ++k) {
-    const double s = (double)leaky_scan((float)((mask >> k) & 1), Lx);
+    const double s = (double)leaky_scan((float)((uint32_t)(mask >> k) & 1u), Lx);
     const double R = fma(qx, s, pw * readlane(creg, k));
     e = qy * (e + R);
     P[(long)(t.y0 + k + 1) * g.row_stride] = (float)e;
