@@ -91,6 +91,47 @@ def request_bytes(cfg, req: Request) -> int:
     return tot
 
 
+def request_needs(cfg, req: Request):
+    """What a request takes of a slot: (workspace bytes, crop bytes, map
+    floats, staged centre ints)."""
+    ib, of = request_io(req)
+    return (request_bytes(cfg, req), ib, of, 2 * len(req.units))
+
+
+def admit(needs, nfree, limits, max_batch, direct_single=True):
+    """Admission of the waiting requests (``needs`` in arrival order, each a
+    tuple of amounts) into ``nfree`` free slots whose capacities are
+    ``limits`` (one per amount).  Returns the number of requests, taken in
+    arrival order, that each successive free slot receives.
+
+    * Light load (``direct_single`` and no more waiting requests than free
+      slots): one request per slot.
+    * Otherwise the waiting requests are spread over the free slots, an even
+      share each (``ceil(waiting / free slots)``, at most ``max_batch``; every
+      request to the first free slot when ``direct_single`` is off), a slot
+      taking requests while they fit its capacities.
+    A request that fits an empty slot is always admitted to one, so the loop
+    makes progress; one that fits no slot is rejected before serving starts."""
+    out = []
+    k, n = 0, len(needs)
+    if direct_single and 0 < n <= nfree:
+        return [1] * n
+    while k < n and len(out) < nfree:
+        share = -(-(n - k) // (nfree - len(out))) if direct_single else max_batch
+        used = [0] * len(limits)
+        take = 0
+        while k < n and take < min(share, max_batch):
+            if any(u + a > c for u, a, c in zip(used, needs[k], limits)):
+                break
+            used = [u + a for u, a in zip(used, needs[k])]
+            take += 1
+            k += 1
+        if take == 0:
+            raise ValueError("request exceeds a slot's capacity")
+        out.append(take)
+    return out
+
+
 class _Templates:
     """Per tracking stream and scale: the template histogram, resident on the device,
     with the event of the launch that wrote it."""
@@ -269,10 +310,9 @@ class ContinuousServer:
     def serve(self, requests, clock=time.perf_counter, keep_maps=False):
         """Run the arrival schedule in real time; returns the requests with t_done set."""
         reqs = [Request(r) for r in requests]
+        limits = (self.budget, self.in_bytes, self.out_floats, CENTRE_INTS)
         for r in reqs:
-            ib, of = request_io(r)
-            if (request_bytes(self.cfg, r) > self.budget or ib > self.in_bytes or of > self.out_floats
-                    or 2 * len(r.units) > CENTRE_INTS):
+            if any(a > c for a, c in zip(request_needs(self.cfg, r), limits)):
                 raise ValueError("request %d exceeds a slot's capacity" % r.id)
         pending, inflight = deque(), deque()
         i, done, n = 0, 0, len(reqs)
@@ -298,27 +338,12 @@ class ContinuousServer:
                 done += len(mb.reqs)
                 self.free.append(mb.stream)
             inflight = running
-            if pending and self.free and self.direct_single and len(pending) <= len(self.free):
-                # light load: each waiting request alone on a free slot (the
-                # slots' streams overlap), no batching delay
-                while pending:
-                    inflight.append(self._launch([pending.popleft()], self.free.popleft()))
-            elif pending and self.free:
-                # the waiting requests are spread over the free slots, a share
-                # each (at most max_batch, within the slot's budgets)
-                while pending and self.free:
-                    share = -(-len(pending) // len(self.free)) if self.direct_single else self.max_batch
-                    take, used, uin, uout, ucen = [], 0, 0, 0, 0
-                    while pending and len(take) < min(share, self.max_batch):
-                        nb = request_bytes(self.cfg, pending[0])
-                        ib, of = request_io(pending[0])
-                        nc = 2 * len(pending[0].units)
-                        if (used + nb > self.budget or uin + ib > self.in_bytes or uout + of > self.out_floats
-                                or ucen + nc > CENTRE_INTS):
-                            break
-                        take.append(pending.popleft())
-                        used, uin, uout, ucen = used + nb, uin + ib, uout + of, ucen + nc
-                    inflight.append(self._launch(take, self.free.popleft()))
+            if pending and self.free:
+                needs = [request_needs(self.cfg, r) for r in pending]
+                limits = (self.budget, self.in_bytes, self.out_floats, CENTRE_INTS)
+                for count in admit(needs, len(self.free), limits, self.max_batch, self.direct_single):
+                    inflight.append(self._launch([pending.popleft() for _ in range(count)],
+                                                 self.free.popleft()))
             elif not pending and i < n and not inflight:
                 time.sleep(max(0.0, min(0.0005, reqs[i].t_arrive - (clock() - t0))))
         return reqs
