@@ -18,8 +18,10 @@ time with single-frame calls and a synchronisation per request.
 """
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
+from contextlib import contextmanager
 
 import numpy as np
 import torch
@@ -27,6 +29,21 @@ import torch
 from . import _swih as S
 from .batch import ALIGN, Batch
 from .plan import Plan
+
+
+@contextmanager
+def _no_gc_pauses():
+    """Hold Python's cyclic collector off while requests are in flight (a
+    collection of the many small objects a request loop makes can stall the
+    loop for milliseconds); it runs once afterwards."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+        gc.collect()
 
 
 class FramePool:
@@ -98,11 +115,11 @@ def request_needs(cfg, req: Request):
     return (request_bytes(cfg, req), ib, of, 2 * len(req.units))
 
 
-def admit(needs, nfree, limits, max_batch, direct_single=True):
+def admit(needs, nfree, limits, max_batch, direct_single=True, busy=0, work_cap=None):
     """Admission of the waiting requests (``needs`` in arrival order, each a
-    tuple of amounts) into ``nfree`` free slots whose capacities are
-    ``limits`` (one per amount).  Returns the number of requests, taken in
-    arrival order, that each successive free slot receives.
+    tuple of amounts, the first the workspace bytes) into ``nfree`` free slots
+    whose capacities are ``limits`` (one per amount).  Returns the number of
+    requests, taken in arrival order, that each successive free slot receives.
 
     * Light load (``direct_single`` and no more waiting requests than free
       slots): one request per slot.
@@ -110,12 +127,26 @@ def admit(needs, nfree, limits, max_batch, direct_single=True):
       share each (``ceil(waiting / free slots)``, at most ``max_batch``; every
       request to the first free slot when ``direct_single`` is off), a slot
       taking requests while they fit its capacities.
-    A request that fits an empty slot is always admitted to one, so the loop
-    makes progress; one that fits no slot is rejected before serving starts."""
+    * ``work_cap``: the workspace bytes of all micro-batches in flight
+      (``busy`` of them already) stay within it, so large requests run one
+      after another instead of sharing the memory bandwidth and all finishing
+      late; a request still starts whenever nothing is in flight.
+    A request that fits an empty slot is always admitted to one when nothing
+    is in flight, so the loop makes progress; one that fits no slot is
+    rejected before serving starts."""
     out = []
     k, n = 0, len(needs)
+    cap = float("inf") if work_cap is None else work_cap
+
+    def room(extra):
+        return busy + extra <= cap or (busy == 0 and extra == needs[k][0])
+
     if direct_single and 0 < n <= nfree:
-        return [1] * n
+        while k < n and room(needs[k][0]):
+            out.append(1)
+            busy += needs[k][0]
+            k += 1
+        return out
     while k < n and len(out) < nfree:
         share = -(-(n - k) // (nfree - len(out))) if direct_single else max_batch
         used = [0] * len(limits)
@@ -123,29 +154,40 @@ def admit(needs, nfree, limits, max_batch, direct_single=True):
         while k < n and take < min(share, max_batch):
             if any(u + a > c for u, a, c in zip(used, needs[k], limits)):
                 break
+            if not room(used[0] + needs[k][0]):
+                break
             used = [u + a for u, a in zip(used, needs[k])]
             take += 1
             k += 1
         if take == 0:
+            if busy > 0 or out:
+                break  # the rest waits for work in flight to finish
             raise ValueError("request exceeds a slot's capacity")
         out.append(take)
+        busy += used[0]
     return out
 
 
 class _Templates:
     """Per tracking stream and scale: the template histogram, resident on the device,
-    with the event of the launch that wrote it."""
+    with the event of the launch that wrote it.  All templates live in one
+    buffer allocated up front, so serving allocates no device memory (a new
+    allocation on a slot's stream can stall the device for milliseconds)."""
 
-    def __init__(self, nbins, device):
+    def __init__(self, nbins, device, capacity=4096):
         self.t = {}
         self.ready = {}
         self.nbins, self.device = nbins, device
+        self.buf = torch.zeros((capacity, nbins), dtype=torch.float32, device=device)
 
     def get(self, stream, scale):
         key = (stream, scale)
         new = key not in self.t
         if new:
-            self.t[key] = torch.empty((1, self.nbins), dtype=torch.float32, device=self.device)
+            k = len(self.t)
+            if k >= self.buf.shape[0]:
+                raise RuntimeError("more than %d (stream, scale) templates" % self.buf.shape[0])
+            self.t[key] = self.buf[k:k + 1]
         return self.t[key], new
 
     def produced(self, stream, scale, event):
@@ -176,21 +218,25 @@ class _Slot:
 class _MicroBatch:
     def __init__(self, reqs, stream, event):
         self.reqs, self.stream, self.event = reqs, stream, event
+        self.work = 0  # workspace bytes of its requests
 
 
 class ContinuousServer:
     def __init__(self, cfg: S.Config, pool: FramePool, budget: int, max_inflight: int = 3,
                  max_batch: int = 64, in_bytes: int = 64 << 20, out_floats: int = 32 << 20,
-                 device="cuda", direct_single: bool = True):
+                 device="cuda", direct_single: bool = True, work_cap: int | None = None):
         """``direct_single``: while no more requests wait than there are free
         slots, each runs alone on its own slot with the single-unit calls (no
         batch table to plan and upload, the comb-form map); under heavier load
         the waiting requests are spread over the free slots as micro-batches
         (without it, they all go to one slot).  The maps are the same bit for
-        bit either way."""
+        bit either way.  ``work_cap``: optional bound on the workspace bytes in
+        flight over all slots (see ``admit``); off by default, since at 2 GiB
+        it left the server unable to keep up with 2000 requests/s."""
         self.cfg, self.pool, self.budget = cfg, pool, budget
         self.max_inflight, self.max_batch, self.device = max_inflight, max_batch, device
         self.direct_single = direct_single
+        self.work_cap = work_cap
         self.in_bytes, self.out_floats = in_bytes, out_floats
         self.slots = [_Slot(budget, in_bytes, out_floats, device) for _ in range(max_inflight)]
         self.free = deque(range(max_inflight))
@@ -309,6 +355,10 @@ class ContinuousServer:
 
     def serve(self, requests, clock=time.perf_counter, keep_maps=False):
         """Run the arrival schedule in real time; returns the requests with t_done set."""
+        with _no_gc_pauses():
+            return self._serve(requests, clock, keep_maps)
+
+    def _serve(self, requests, clock, keep_maps):
         reqs = [Request(r) for r in requests]
         limits = (self.budget, self.in_bytes, self.out_floats, CENTRE_INTS)
         for r in reqs:
@@ -341,9 +391,14 @@ class ContinuousServer:
             if pending and self.free:
                 needs = [request_needs(self.cfg, r) for r in pending]
                 limits = (self.budget, self.in_bytes, self.out_floats, CENTRE_INTS)
-                for count in admit(needs, len(self.free), limits, self.max_batch, self.direct_single):
-                    inflight.append(self._launch([pending.popleft() for _ in range(count)],
-                                                 self.free.popleft()))
+                busy = sum(mb.work for mb in inflight)
+                k = 0
+                for count in admit(needs, len(self.free), limits, self.max_batch, self.direct_single,
+                                   busy, self.work_cap):
+                    mb = self._launch([pending.popleft() for _ in range(count)], self.free.popleft())
+                    mb.work = sum(nd[0] for nd in needs[k:k + count])
+                    k += count
+                    inflight.append(mb)
             elif not pending and i < n and not inflight:
                 time.sleep(max(0.0, min(0.0005, reqs[i].t_arrive - (clock() - t0))))
         return reqs
@@ -358,6 +413,10 @@ class SerialServer:
         self.templates = _Templates(cfg.nbins, device)
 
     def serve(self, requests, clock=time.perf_counter, keep_maps=False):
+        with _no_gc_pauses():
+            return self._serve(requests, clock, keep_maps)
+
+    def _serve(self, requests, clock, keep_maps):
         reqs = [Request(r) for r in requests]
         cfg, dev = self.cfg, self.device
         t0 = clock()

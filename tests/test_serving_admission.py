@@ -57,3 +57,24 @@ def test_counts_never_exceed_what_waits():
 def test_a_request_larger_than_a_slot_is_refused():
     with pytest.raises(ValueError):
         admit([need(ws=11)], 1, (10, 1 << 30, 1 << 30, 4096), 64, direct_single=False)
+
+
+def test_work_cap_keeps_large_requests_apart():
+    big, small = need(ws=13), need(ws=3)
+    # nothing in flight: the first large request starts, the second waits
+    assert admit([big, big], 3, ROOMY, 64, busy=0, work_cap=20) == [1]
+    # a small one may join a large one in flight; a large one may not
+    assert admit([small], 3, ROOMY, 64, busy=13, work_cap=20) == [1]
+    assert admit([big], 3, ROOMY, 64, busy=13, work_cap=20) == []
+    # a request larger than the cap still runs alone when nothing is in flight
+    assert admit([need(ws=30)], 3, ROOMY, 64, busy=0, work_cap=20) == [1]
+    # heavier load: shares stop at the cap, the rest waits
+    assert admit([small] * 9, 2, ROOMY, 64, busy=0, work_cap=20) == [5, 1]
+    assert admit([small] * 9, 2, ROOMY, 64, busy=18, work_cap=20) == []
+
+
+def test_work_cap_always_admits_when_idle():
+    for n in range(1, 9):
+        for ws in (1, 7, 25):
+            out = admit([need(ws=ws)] * n, 3, ROOMY, 64, busy=0, work_cap=20)
+            assert out and sum(out) >= 1
