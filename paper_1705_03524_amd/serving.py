@@ -361,8 +361,8 @@ class ContinuousServer:
     def _serve(self, requests, clock, keep_maps):
         reqs = [Request(r) for r in requests]
         # one small upload and download on every slot's stream before the
-        # clock starts: the first asynchronous copies of a run were measured
-        # to cost milliseconds, which no request should pay
+        # clock starts, so that setting up the asynchronous copies is not
+        # charged to the first requests
         for sl in self.slots:
             with torch.cuda.stream(sl.stream):
                 sl.d_in[:256].copy_(sl.h_in[:256], non_blocking=True)
