@@ -79,10 +79,12 @@ def single(cfg, img, scales, si, c, rect, integer):
     return hist, raw, out
 
 
+# 16 bins: the histogram aggregate in the batch; 96: the per-bin aggregate
+@pytest.mark.parametrize("nb", [16, 96])
 @pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.EUCLIDEAN])
-def test_batch_equals_single_integer(kind):
-    print("case: batch integer kind %d" % kind, flush=True)
-    cfg = swih.Config(16, kind, SCALES)
+def test_batch_equals_single_integer(kind, nb):
+    print("case: batch integer kind %d bins %d" % (kind, nb), flush=True)
+    cfg = swih.Config(nb, kind, SCALES)
     imgs = [to_dev(synth.smooth_noise(10 + k, H, W), torch) for k, (H, W) in enumerate(SIZES)]
     scales = [[s for s in SCALES if s[0] <= W and s[1] <= H] for (H, W) in SIZES]
     b, outs = make_batch(cfg, imgs, scales, True, list(range(len(imgs))))
@@ -95,20 +97,22 @@ def test_batch_equals_single_integer(kind):
         if checked < 4:  # oracle spot check
             img = imgs[fi].cpu().numpy()
             w, h = scales[fi][si]
-            tref, _ = oracle.template(img, 16, kind, w, h, c)
+            tref, _ = oracle.template(img, nb, kind, w, h, c)
             assert np.array_equal(raw.cpu().numpy()[0].astype(np.int64), tref)
-            mref = oracle.bc_map(img, 16, kind, w, h, tref, rect=rect)
+            mref = oracle.bc_map(img, nb, kind, w, h, tref, rect=rect)
             assert np.array_equal(out.cpu().numpy(), mref.astype(np.float32))
             checked += 1
 
 
+# exponential: 16 bins take the histogram aggregate, 40 the per-bin one
+@pytest.mark.parametrize("nb", [16, 40])
 @pytest.mark.parametrize("kind", [swih.GAUSSIAN, swih.GAUSSIAN_SEP, swih.EXPONENTIAL])
-def test_batch_equals_single_gaussian_crops(kind):
-    print("case: batch real-valued kind %d: crops with per-frame scales" % kind, flush=True)
+def test_batch_equals_single_gaussian_crops(kind, nb):
+    print("case: batch real-valued kind %d bins %d: crops with per-frame scales" % (kind, nb), flush=True)
     big = to_dev(synth.smooth_noise(77, 600, 700), torch)
     crops = [big[10:210, 20:300], big[300:420, 100:260], big[50:131, 400:690], big[500:560, 0:90]]
     scales = [[(21, 21), (31, 15)], [(15, 15)], [(9, 9), (25, 31), (41, 41)], [(11, 13)]]
-    cfg = swih.Config(16, kind, [(15, 15)])
+    cfg = swih.Config(nb, kind, [(15, 15)])
     b, outs = make_batch(cfg, crops, scales, False, list(range(len(crops))))
     b.run()
     torch.cuda.synchronize()
@@ -121,7 +125,7 @@ def test_batch_equals_single_gaussian_crops(kind):
     img = crops[fi].cpu().numpy()
     w, h = scales[fi][si]
     ok = oracle.EXPONENTIAL if kind == swih.EXPONENTIAL else oracle.GAUSSIAN
-    _, tp = oracle.template(img, 16, ok, w, h, c)
+    _, tp = oracle.template(img, nb, ok, w, h, c)
     assert np.abs(hist.cpu().numpy()[0] - tp).max() <= 1e-5
 
 
