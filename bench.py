@@ -1,14 +1,20 @@
 """Benchmark of the SWIH hot path on one MI355X.
 
-Workload (the single-frame configuration): a 512 x 512 uint8 scene (blurred
-uniform noise, sigma 3, stretched to 0..255, plus 6 bright/dark rectangles of
-side 20..60), 16 bins, 31 x 31 windows, the Manhattan, Euclidean and Gaussian
-(sigma = w/4) kernels, full likelihood map over every valid centre.
+Headline workload (the multi-scale configuration, the largest that the paper's
+title case puts on one GPU): a 2048 x 2048 uint8 smooth-noise image (uniform
+noise blurred with sigma 3, stretched to 0..255), 32 bins, the Gaussian kernel
+(sigma = w/4, K = 3 cosine series, 49 weight terms) at the five window scales
+21, 31, 45, 63 and 81.  One step = for every scale: build the weighted integral
+histograms of the scale (26 GB of planes, one workspace reused across the
+scales), query the template histogram at (1024, 1024) and compute the
+Bhattacharyya likelihood map of every valid centre (20.0 M windows per step).
+The image is resident in HBM before the timed region starts.
 
-One step = for each of the three kernels: build the weighted integral
-histograms, query the template histogram at the first rectangle's centre, and
-compute the Bhattacharyya likelihood map of all 482 x 482 centres.  The image
-is resident in HBM before the timed region starts.
+Reported beside it (same JSON line): the 512 x 512 single-frame step with three
+kernels, the 2048 x 2048 builds of the Manhattan, exponential and Gaussian
+kernels, the batched workload (64 uneven frames, per-frame loop against one
+batch), the measured write-only and copy ceilings of the machine's HBM, and the CPU
+oracle on sampled centres of the headline workload.
 
 Prints one JSON line (metric = weighted local histograms per second).
 """
@@ -41,11 +47,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("frame", "batch", "serve", "sweep", "track", "builds"),
-                    default="frame",
-                    help="frame: the 512x512 single-frame path (default); batch: 64 uneven "
-                         "frames with 1-8 targets x 3 scales, batched vs per-frame; serve: "
-                         "Poisson tracking requests, continuous batching vs one at a time")
+    ap.add_argument("--workload", choices=("multiscale", "frame", "batch", "serve", "sweep", "track",
+                                           "builds", "ceilings"),
+                    default="multiscale",
+                    help="multiscale: 2048x2048, 32 bins, Gaussian at 5 scales (default); frame: the "
+                         "512x512 single-frame path; batch: 64 uneven frames with 1-8 targets x 3 "
+                         "scales, batched vs per-frame; serve: Poisson tracking requests, continuous "
+                         "batching vs one at a time; ceilings: HBM write-only and copy rates")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000",
                     help="serve workload: request rates (req/s) to sweep")
     ap.add_argument("--seconds", type=float, default=1.0,
@@ -111,6 +119,63 @@ def cpu_baseline(img, tc, budget_s):
 
 
 PROFILE_COUNTERS = os.path.join(HERE, "profiles", "swih_512_scene_hbm_counters.md")
+PROFILE_COUNTERS_MS = os.path.join(HERE, "profiles", "swih_2048_multiscale_hbm_counters.md")
+
+# The multi-scale workload: 2048 x 2048 smooth noise, 32 bins, Gaussian at five
+# scales, template at the image centre.
+MS_SIDE = 2048
+MS_BINS = 32
+MS_SCALES = (21, 31, 45, 63, 81)
+MS_TEMPLATE = (1024, 1024)
+
+
+def host_info():
+    """Core count and CPU model of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline_multiscale(img, nsample=65536):
+    """The oracle (brute force per window, FP64, OpenMP over centres) on
+    ``nsample`` seeded centres per scale of the multi-scale workload (the valid
+    region's corners and edges included), on all the threads it runs with and
+    on one; windows/s is extrapolated from the sample to the full maps."""
+    import oracle
+    from paper_1705_03524_amd import synth
+    threads = oracle.threads()
+    samples, tmpl = {}, {}
+    for w in MS_SCALES:
+        samples[w] = synth.sample_centres(500 + w, MS_SIDE, MS_SIDE, w, w, nsample)
+        tmpl[w] = oracle.template(img, MS_BINS, oracle.GAUSSIAN, w, w, MS_TEMPLATE)[1]
+    out = {}
+    for label, n in (("all", threads), ("one", 1)):
+        oracle.set_threads(n)
+        oracle.bc_at(img, MS_BINS, oracle.GAUSSIAN, 21, 21, samples[21][:64], tmpl[21])  # thread pool up
+        t0 = time.perf_counter()
+        for w in MS_SCALES:
+            oracle.bc_at(img, MS_BINS, oracle.GAUSSIAN, w, w, samples[w], tmpl[w])
+        out[label] = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    nwin = nsample * len(MS_SCALES)
+    per_step = sum((MS_SIDE - w + 1) ** 2 for w in MS_SCALES)
+    return {"value": nwin / out["all"], "unit": "windows/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded centres per scale (valid-region corners and edges included) x %d scales "
+                      "of the 2048x2048 multi-scale workload, brute force per window in FP64; "
+                      "windows/s extrapolated from the sample to the full maps (%.1f s on %d threads, "
+                      "%.1f s on 1)" % (nsample, len(MS_SCALES), out["all"], threads, out["one"]),
+            "extrapolated": True,
+            "one_core": {"value": nwin / out["one"], "unit": "windows/s", "cores": 1},
+            "full_step_s_extrapolated": per_step / (nwin / out["all"]),
+            "host": host_info()}
 
 
 def kernel_source_hash():
@@ -122,12 +187,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_prefix):
-    """HBM bytes per launch of a kernel from the committed counter summary
+def measured_traffic(kernel_prefix, path=PROFILE_COUNTERS):
+    """HBM bytes per launch of a kernel from a committed counter summary
     (scaled FETCH_SIZE + WRITE_SIZE), or None if the summary is missing or was
     taken on different kernel sources."""
     try:
-        txt = open(PROFILE_COUNTERS).read()
+        txt = open(path).read()
     except OSError:
         return None
     if kernel_source_hash() not in txt:
@@ -140,7 +205,190 @@ def measured_traffic(kernel_prefix):
     return total
 
 
+def capture_graph(fn):
+    """Capture fn's launches (on the current stream) as one HIP graph, after one
+    eager run on a side stream."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def time_launches(fn, rep, replays=3):
+    """Average duration (ms) of one launch of fn: rep launches captured back to
+    back in one graph, replayed between HIP events on the launch stream."""
+    import torch
+    g = capture_graph(lambda: [fn() for _ in range(rep)])
+    g.replay()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(replays):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    del g
+    return a.elapsed_time(b) / (replays * rep)
+
+
+def ceilings():
+    """Measured HBM ceilings of the box: a write-only fill and a device copy of
+    4 GiB buffers (torch's own kernels), bytes moved per second."""
+    import torch
+    n = 4 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    fill_ms = time_launches(lambda: x.fill_(3), 5)
+    copy_ms = time_launches(lambda: y.copy_(x), 5)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"write_only_gbs": n / (fill_ms / 1e3) / 1e9, "copy_gbs": 2 * n / (copy_ms / 1e3) / 1e9,
+            "copy_bytes_counted": "read + write", "buffer_bytes": n,
+            "kernels": "torch fill_ and copy_ on uint8 tensors",
+            "write_only_frac_of_peak": n / (fill_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "copy_frac_of_peak": 2 * n / (copy_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
+def run_multiscale(args):
+    """The headline: 2048 x 2048 smooth noise, 32 bins, Gaussian at scales 21,
+    31, 45, 63, 81; per scale build + template query + full valid map, one
+    workspace reused across the scales; returns the JSON line (a dict)."""
+    import torch
+    import paper_1705_03524_amd as swih
+    from paper_1705_03524_amd.plan import Plan
+
+    N, B = MS_SIDE, MS_BINS
+    img = synth_smooth(N)
+    d_img = torch.from_numpy(img).cuda()
+    d_tc = torch.tensor([MS_TEMPLATE], dtype=torch.int32, device="cuda")
+    cfgs = [swih.Config(B, swih.GAUSSIAN, [(w, w)]) for w in MS_SCALES]
+    nbytes = max(swih.workspace_bytes(c, N, N) for c in cfgs)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    plans = [Plan(c, N, N, ws=ws) for c in cfgs]
+    maps = [torch.empty((N - w + 1, N - w + 1), dtype=torch.float32, device="cuda") for w in MS_SCALES]
+    tmpl = [torch.empty((1, B), dtype=torch.float32, device="cuda") for _ in MS_SCALES]
+    PHASES = ("carries", "planes", "query", "match")
+
+    def phase(si, name):
+        p = plans[si]
+        if name in ("carries", "planes"):
+            swih.build_phase(p.cfg, d_img, p.ws, name, 0)
+        elif name == "query":
+            swih.query(p.cfg, p.ws, N, N, 0, d_tc, tmpl[si], None)
+        else:
+            swih.match(p.cfg, p.ws, N, N, 0, p.valid_rect(0), maps[si], template=tmpl[si][0])
+
+    def step():
+        for si in range(len(MS_SCALES)):
+            for ph in PHASES:
+                phase(si, ph)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    eager = [m.clone() for m in maps]
+    g_step = capture_graph(step)
+    for m in maps:
+        m.fill_(-1.0)
+    g_step.replay()
+    torch.cuda.synchronize()
+    for si, m in enumerate(maps):
+        if not torch.equal(m, eager[si]):
+            raise RuntimeError("graph replay of scale %d differs from the eager step" % MS_SCALES[si])
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        g_step.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    del g_step
+    # Per-launch durations, scale by scale in pipeline order (each phase leaves
+    # the workspace as the next one needs it).
+    reps = {"carries": 10, "planes": 3, "query": 10, "match": 3}
+    per = {}
+    for si, w in enumerate(MS_SCALES):
+        for ph in PHASES:
+            per["%s_%d" % (ph, w)] = time_launches(lambda: phase(si, ph), reps[ph])
+    nwin = [(N - w + 1) ** 2 for w in MS_SCALES]
+    T = (2 * cfgs[0].K + 1) ** 2
+    plane_bytes = 4 * T * B * (N + 1) * (N + 1)
+    nsc = len(MS_SCALES)
+    kernels = {
+        "build": {"kernel": "k_emit_gauss (Gaussian plane build, %d terms x %d bins, 2048x2048; "
+                            "average over the 5 scales)" % (T, B),
+                  "alg": N * N + plane_bytes,
+                  "ms": sum(per["planes_%d" % w] for w in MS_SCALES) / nsc, "prefix": "k_emit_gauss<"},
+        "match": {"kernel": "k_match_gauss_comb + k_match_gauss_fin (Gaussian dense likelihood map, "
+                            "every valid centre; average over the 5 scales)",
+                  "alg": plane_bytes + 4 * sum(nwin) / nsc,
+                  "ms": sum(per["match_%d" % w] for w in MS_SCALES) / nsc, "prefix": "k_match_gauss_"},
+    }
+
+    def roof(k):
+        achieved = k["alg"] / (k["ms"] / 1e3) / 1e9
+        return {"bound": "hbm", "kernel": k["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(k["prefix"], PROFILE_COUNTERS_MS),
+                "alg_bytes_per_launch": k["alg"], "avg_launch_ms": k["ms"]}
+
+    dominant = max(kernels, key=lambda n: kernels[n]["ms"])
+    other = "build" if dominant == "match" else "match"
+    per_scale = {}
+    for si, w in enumerate(MS_SCALES):
+        build_ms = per["carries_%d" % w] + per["planes_%d" % w]
+        per_scale[str(w)] = {
+            "windows": nwin[si],
+            "ms": build_ms + per["query_%d" % w] + per["match_%d" % w],
+            "ih_build_gbs": (N * N + plane_bytes) / (build_ms / 1e3) / 1e9,
+            "ih_build_frac": (N * N + plane_bytes) / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "map_gbs": (plane_bytes + 4 * nwin[si]) / (per["match_%d" % w] / 1e3) / 1e9}
+    line = {
+        "metric": METRIC,
+        "value": sum(nwin) / (ms / 1e3),
+        "unit": "windows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "multi-scale: 2048x2048 smooth noise (seed 33), 32 bins, Gaussian kernel "
+                               "(sigma = w/4, K=3 cosine series, 49 weight terms) at scales 21,31,45,63,81; "
+                               "per scale: IH build + template query at (1024,1024) + Bhattacharyya map of "
+                               "every valid centre; one 27 GB workspace reused across scales",
+                   "windows_per_step": sum(nwin), "global_batch": 1, "seq_len": None,
+                   "parallelism": "none"},
+        "roofline": roof(kernels[dominant]),
+        "roofline_" + other: roof(kernels[other]),
+        "detail_ms": per,
+        "per_scale": per_scale,
+    }
+    del plans, ws, maps
+    torch.cuda.empty_cache()
+    return line, img
+
+
 def bench_batch(args):
+    print(json.dumps(run_batch(args)), flush=True)
+
+
+def run_batch(args):
     """64 uneven frames (256..1920 x 256..1080), 1-8 targets of side 16..128,
     3 scales each, search region 3s x 3s, 16 bins; Manhattan (one build per
     frame) and Gaussian K=3 (one build per target-scale search crop).  Times
@@ -235,7 +483,7 @@ def bench_batch(args):
         "autotuned_windows_per_s": total_windows / (total_ms["tuned"] / 1e3),
         "detail": out,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def bench_serve(args):
@@ -523,35 +771,12 @@ def bench_track(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(got --gpus %d)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batch":
-        bench_batch(args)
-        return
-    if args.workload == "serve":
-        bench_serve(args)
-        return
-    if args.workload == "sweep":
-        bench_sweep(args)
-        return
-    if args.workload == "track":
-        bench_track(args)
-        return
-    if args.workload == "builds":
-        bench_builds(args)
-        return
+def run_frame(args, side_kinds=True, builds=True, cpu=True):
+    """The 512 x 512 single-frame step (three kernels); returns the JSON line."""
     import torch
     import paper_1705_03524_amd as swih
     from paper_1705_03524_amd.plan import Plan
 
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    swih.load()
     img, tc = scene()
     d_img = torch.from_numpy(img).cuda()
     d_tc = torch.tensor([tc], dtype=torch.int32, device="cuda")
@@ -695,7 +920,7 @@ def main():
         return sp, smap, ms_
 
     extras = {}
-    if not args.no_extras:
+    if side_kinds:
         # (the separable form's carries phase launches nothing)
         _, smap, sep_ms = side_kind("gaussian_sep", ("planes", "query", "match"))
         sep_total = sum(sep_ms.values())
@@ -713,7 +938,7 @@ def main():
             "ih_build_gbs": (H * W + 4 * ep.nplanes * NBINS * (H + 1) * (W + 1)) / (exp_build / 1e3) / 1e9,
             "planes_gbs": 4 * ep.nplanes * NBINS * (H + 1) * (W + 1) / (exp_ms["planes"] / 1e3) / 1e9}
 
-    w3 = {} if args.no_extras else w3_builds(REP)
+    w3 = w3_builds(REP) if builds else {}
     if w3:
         extras["ih_build_2048x2048_32bins"] = w3
 
@@ -766,8 +991,59 @@ def main():
                             (per["build_" + k] / 1e3) / 1e9 for k in KERNELS},
     }
     line.update(extras)
-    if not args.no_cpu_baseline:
+    if cpu:
         line["cpu_baseline"] = cpu_baseline(img, tc, args.cpu_seconds)
+    for k in list(plans):
+        del plans[k]
+    torch.cuda.empty_cache()
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    simple = {"batch": bench_batch, "serve": bench_serve, "sweep": bench_sweep, "track": bench_track,
+              "builds": bench_builds}
+    if args.workload in simple:
+        simple[args.workload](args)
+        return
+    import torch
+    import paper_1705_03524_amd as swih
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    swih.load()
+    if args.workload == "ceilings":
+        print(json.dumps({"metric": "HBM ceilings", "unit": "GB/s", "n_gpus": 1, "ceilings": ceilings()}),
+              flush=True)
+        return
+    if args.workload == "frame":
+        line = run_frame(args, side_kinds=not args.no_extras, builds=not args.no_extras,
+                         cpu=not args.no_cpu_baseline)
+        print(json.dumps(line), flush=True)
+        return
+    line, img = run_multiscale(args)
+    print("multi-scale step: %.3f ms, %.3e windows/s" % (line["ms_per_step"], line["value"]),
+          file=sys.stderr, flush=True)
+    if not args.no_extras:
+        fr = run_frame(args, side_kinds=True, builds=False, cpu=False)
+        line["single_frame_512"] = {k: fr[k] for k in fr if k not in ("metric", "n_gpus", "higher_is_better",
+                                                                      "scaling", "vs_baseline", "data")}
+        print("512x512 step: %.3f ms" % fr["ms_per_step"], file=sys.stderr, flush=True)
+        line["ih_build_2048x2048_32bins"] = w3_builds()
+        print("2048x2048 builds done", file=sys.stderr, flush=True)
+        bt = run_batch(args)
+        line["batch"] = {k: bt[k] for k in ("value", "unit", "ms_per_step", "per_frame_windows_per_s",
+                                            "speedup_vs_per_frame", "autotuned_windows_per_s", "config",
+                                            "detail")}
+        print("batch done", file=sys.stderr, flush=True)
+        line["ceilings"] = ceilings()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_multiscale(img)
     print(json.dumps(line), flush=True)
 
 

@@ -42,6 +42,8 @@ def _load():
         i32, i64p, f64p, u8p, i32p = C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), \
             C.POINTER(C.c_uint8), C.POINTER(C.c_int32)
         lib.oracle_quantise.argtypes = [i32, i32]
+        lib.oracle_set_threads.argtypes = [i32]
+        lib.oracle_max_threads.restype = i32
         lib.oracle_kernel_table_int.argtypes = [i32, i32, i32, i64p]
         lib.oracle_kernel_table_gauss.argtypes = [i32, i32, C.c_double, C.c_double, f64p]
         lib.oracle_kernel_table_exp.argtypes = [i32, i32, C.c_double, C.c_double, f64p]
@@ -61,12 +63,14 @@ def _p(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
 
-def set_threads(n: int | None):
-    """Limit the OpenMP threads the oracle uses (None = library default)."""
-    if n is None:
-        os.environ.pop("OMP_NUM_THREADS", None)
-    else:
-        os.environ["OMP_NUM_THREADS"] = str(int(n))
+def set_threads(n: int):
+    """Number of OpenMP threads the oracle's parallel loops use from now on."""
+    _load().oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    """Threads the oracle's next parallel loop will use."""
+    return int(_load().oracle_max_threads())
 
 
 def quantise(v, nbins: int):

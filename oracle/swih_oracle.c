@@ -38,11 +38,17 @@
  * parallelises over window centres only; every centre is computed the same way.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 enum { OR_UNIFORM = 0, OR_MANHATTAN = 1, OR_EUCLIDEAN = 2, OR_GAUSSIAN = 3, OR_EXPONENTIAL = 5 };
+
+/* Threads of the parallel loops below (n >= 1), and the current count: lets a
+ * caller time the oracle on one core and on all of them in one process. */
+void oracle_set_threads(int n) { omp_set_num_threads(n < 1 ? 1 : n); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* Quantiser Q of Eq. 2: uniform bins over [0, 256). */
 int oracle_quantise(int v, int nbins) { return (v * nbins) / 256; }

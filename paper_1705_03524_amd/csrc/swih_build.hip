@@ -22,8 +22,8 @@
 //      running sum, stored once per element with coalesced 256-byte rows.
 // Integer kernels accumulate modulo 2^32.  The Gaussian runs its horizontal
 // scans in int32 fixed point (exact), accumulates each tile's columns in
-// float relative to the tile's own origin, and keeps the cross-tile row
-// carries in double.
+// double relative to the tile's own origin and stores them as float, and
+// keeps the cross-tile row carries in double.
 #include <string.h>
 
 #include "swih_internal.h"
@@ -616,29 +616,31 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const int32_t uqi = uq[(size_t)t.x * NT + i];
   // the group's NT planes are consecutive 64-element runs of each row
   float* lrow = Lp + swih_base(g, i * NT, t.b) + t.tx * g.tile_stride + lane;
-  // tile-local running sums in FP32 (a band holds at most 64 rows); only the
-  // cross-tile row carries are kept in FP64
-  float L[NT];
+  // tile-local running sums in FP64, each rounded once to float when stored:
+  // the row prefix R is an exact integer, so the stored value carries one
+  // half-ulp of rounding and no accumulated error (FP64 FMA issues at the
+  // FP32 rate on gfx950, and the launch is bound by its stores)
+  double L[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    L[j] = 0.0f;
+    L[j] = 0.0;
     if (t.ty == 0) lrow[j * 64] = 0.0f;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
     const int y = t.y0 + k;
     const bool m = bit_of(mask, k) != 0;
-    const float Rf = (float)wave_incl_scan(m ? uqi : 0);
+    const double Rd = (double)wave_incl_scan(m ? uqi : 0);
     const double* vrow = vqd + (size_t)y * NT;
     double vr[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) vr[j] = vrow[j];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) L[j] = fmaf((float)vr[j], Rf, L[j]);
+    for (int j = 0; j < NT; ++j) L[j] = fma(vr[j], Rd, L[j]);
     // whole 256-byte runs: lanes past the last column write values never read
     float* dst = lrow + (size_t)(y + 1) * g.row_stride;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) dst[j * 64] = L[j];
+    for (int j = 0; j < NT; ++j) dst[j * 64] = (float)L[j];
   }
 }
 

@@ -171,7 +171,6 @@ __device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const E
   return valid ? m : 0;
 }
 
-__device__ __forceinline__ double mbit(uint64_t m, int k) { return (double)(uint32_t)((m >> k) & 1); }
 
 // ---------------------------------------------------------------- build
 // Aggregate by LDS histograms (at most kExpHistMaxB bins): one block per
@@ -437,7 +436,29 @@ __device__ __forceinline__ double e_at(const SwihGeom& g, const float* __restric
   return X > 0 ? (double)v : 0.0;
 }
 
-// H_b at centre (xc, yc): the four quadrant boxes, each from its direction's plane.
+// Empty bins.  sqrt is not Lipschitz at 0, so a bin with no pixel in the
+// window must give exactly 0, not a rounding residue e (whose sqrt(e t_b) would
+// be orders of magnitude above e).  The planes hold no pixel count, but every
+// term is positive, which bounds the rounding:
+//   * the in-row prefix is an FP32 leaky scan, six FMA stages with factors
+//     rounded to float, so each of its positive terms is off by at most
+//     12 * 2^-24 relative; the FP64 chains that carry it keep that relative
+//     bound (sums of positive terms), and the float store adds 2^-24;
+//   * so each stored E is within 13 * 2^-24 of its exact value, relative, plus
+//     an absolute error far below 1e-9 from the FP64 carries' fixed-point
+//     weights (2^-52 each);
+//   * the window value is sum +- T over 16 scaled corners T = f E >= 0, hence
+//     |h' - h| <= eb = 16 * 2^-24 * sum T + 1e-9.
+// A bin with a pixel in the window has h >= wmin = exp(-rx/tx - ry/ty), the
+// kernel's smallest weight (> e^-4).  Whenever eb < wmin / 2 the test
+// h' < wmin / 2 is therefore exactly "no pixel": such bins give 0.  (eb is
+// far below that for any window up to several hundred pixels; beyond it the
+// value is kept as computed.)
+constexpr double kExpRel = 16.0 / 16777216.0;  // 16 * 2^-24
+constexpr double kExpAbs = 1e-9;
+
+// H_b at centre (xc, yc): the four quadrant boxes, each from its direction's
+// plane, with an exactly empty bin returned as 0 (above).
 __device__ __forceinline__ double exp_hist(const SwihGeom& g, const ExpScale& s,
                                            const float* __restrict__ pl, int b, int xc, int yc) {
   // corners (far, near) and their factors per side
@@ -445,7 +466,7 @@ __device__ __forceinline__ double exp_hist(const SwihGeom& g, const ExpScale& s,
   const int XR0 = g.W - 1 - xc - s.rx, XR1 = g.W - 1 - xc;
   const int YT0 = yc - s.ry, YT1 = yc + 1;
   const int YB0 = g.H - 1 - yc - s.ry, YB1 = g.H - 1 - yc;
-  double h = 0.0;
+  double h = 0.0, tsum = 0.0;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     const bool mx = d & 1, my = d & 2;
@@ -457,8 +478,10 @@ __device__ __forceinline__ double exp_hist(const SwihGeom& g, const ExpScale& s,
     const double e11 = e_at(g, pl, base, Y1, X1), e01 = e_at(g, pl, base, Y1, X0);
     const double e10 = e_at(g, pl, base, Y0, X1), e00 = e_at(g, pl, base, Y0, X0);
     h += f1y * (f1x * e11 - f0x * e01) - f0y * (f1x * e10 - f0x * e00);
+    tsum += f1y * (f1x * e11 + f0x * e01) + f0y * (f1x * e10 + f0x * e00);
   }
-  return h;
+  const double half_min = 0.5 * s.fxlo * s.fylo;
+  return fma(kExpRel, tsum, kExpAbs) < half_min && h < half_min ? 0.0 : h;
 }
 
 // One thread per (centre, bin).

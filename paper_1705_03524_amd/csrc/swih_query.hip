@@ -172,7 +172,9 @@ __device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double
 
 // One block per centre; threads over (bin, x term i) pairs compute
 // alpha_i sum_j beta_j B_ij into LDS, then one thread per bin adds the terms
-// in order i = 0..NT-1.
+// in order i = 0..NT-1.  Term (0, 0) is the plain pixel count (u_0 = v_0 = 1
+// exactly), and its box is an exact integer: a bin with no pixel in the
+// window gets p_b = 0 exactly instead of a rounding residue.
 template <int NT>
 __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const SwihGeom& g = a.g;
@@ -180,7 +182,7 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const GaussPlanes gp{(const float*)a.planes, a.RC};
   const int32_t* __restrict__ centres = a.centres;
   __syncthreads();  // LDS reuse across virtual blocks of one block
-  extern __shared__ double part[];  // [B][NT]
+  extern __shared__ double part[];  // [B][NT], then the window's pixel count per bin [B]
   const int k = vb;
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
@@ -226,11 +228,13 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
       hi = fma(be[j], d[j], hi);
     }
     part[it] = al[i] * hi;
+    if (i == 0) part[g.B * NT + b] = d[0];
   }
   __syncthreads();
   for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
     double h = 0.0;
     for (int i = 0; i < NT; ++i) h += part[b * NT + i];
+    if (part[g.B * NT + b] == 0.0) h = 0.0;
     a.hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
   }
 }
@@ -264,6 +268,13 @@ __device__ __forceinline__ int64_t bc_term(double p, float t) {
 }
 
 __device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q / kBcScale); }
+
+// Empty bins.  sqrt is not Lipschitz at 0: a bin with no pixel in the window
+// must give p_b = 0 exactly, or a rounding residue e of the float planes
+// turns into sqrt(e t_b), orders of magnitude above e.  The weight term
+// (0, 0) is the plain pixel count (u_0 = v_0 = 1 exactly), and every part of
+// its box is an integer (tile-local float values below 2^24, double carries),
+// so the count is exact and the maps drop a bin's term exactly when it is 0.
 
 // Column work of the Gaussian maps.  A block covers nV plane columns X (the
 // left and right window edges of its chunk of centres).  The x terms i of a
@@ -379,6 +390,8 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
   extern __shared__ double sm[];
   double* Gb = sm;                                  // [2][NG][2][nvpad]
   double* R = sm + 2 * NG * 2 * nvpad;              // [B][NT][ntl_max]
+  double* Nb = R + (size_t)g.B * NT * ntl_max;      // [2][nvpad] pixel counts per column
+  double* Rn = Nb + 2 * nvpad;                      // [B][ntl_max] count-plane carries
   const int yc = y0 + vb / a.nbx;
   const int xa = x0 + (vb % a.nbx) * cw;
   const int cwc = min(cw, x1 - xa + 1);
@@ -406,6 +419,8 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
       acc = fma(be[j], gp.RC[swih_rc(g, p, b, tlo + t, Yb)] - gp.RC[swih_rc(g, p, b, tlo + t, Ya)], acc);
     }
     R[(b * NT + i) * ntl_max + t] = acc;
+    if (i == 0)
+      Rn[b * ntl_max + t] = gp.RC[swih_rc(g, 0, b, tlo + t, Yb)] - gp.RC[swih_rc(g, 0, b, tlo + t, Ya)];
   }
   CI ci;
   ci.init(tid, nV, nvpad, xa, rx, cwc, contig);
@@ -436,6 +451,7 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
   __syncthreads();
   for (int b = 0; b < g.B; ++b) {
     double* Gp = Gb + (b & 1) * NG * 2 * nvpad;
+    double* Np = Nb + (b & 1) * nvpad;
     if (ci.slot >= 0) {
       double gplus = 0.0, gminus = 0.0;
 #pragma unroll
@@ -449,7 +465,7 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
           la[j] = lp[offA[ii] + (size_t)j * 64];
           lb[j] = lp[offB[ii] + (size_t)j * 64];
         }
-        double vl = 0.0;
+        double vl = 0.0, nl = (double)lb[0] - (double)la[0];
 #pragma unroll
         for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lb[j] - (double)la[j], vl);
         for (int c = 0; c < ncross; ++c) {
@@ -458,7 +474,11 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
           for (int j = 0; j < NT; ++j) lc[j] = lp[offC[ii] + (size_t)c * g.TY * rs + (size_t)j * 64];
 #pragma unroll
           for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
+          nl += (double)lc[0];
         }
+        // slot 0's first item is term 0 of its column: the column's pixel count
+        if (ii == 0 && ci.slot == 0)
+          Np[ci.xi[0]] = Rn[b * ntl_max + tX[0]] + (x0col[0] ? 0.0 : nl);
         const double v = R[(b * NT + i) * ntl_max + tX[ii]] + (x0col[ii] ? 0.0 : vl);
         if (ci.single) {
           Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[ii]] = fma(ap[ii], v, 0.0);
@@ -478,7 +498,7 @@ __device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
       double hh = 0.0;
 #pragma unroll
       for (int q = 0; q < NG; ++q) hh += Gp[(q * 2 + 0) * nvpad + i2] - Gp[(q * 2 + 1) * nvpad + i1];
-      bc += bc_term(hh * inv_mass, tmpl[b]);
+      if (Np[i2] - Np[i1] != 0.0) bc += bc_term(hh * inv_mass, tmpl[b]);
     }
   }
   if (win) a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = bc_value(bc);
@@ -530,6 +550,8 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
   double* Gb = sm;                          // [2][NG][2][nvpad]
   double* R = sm + 2 * NG * 2 * nvpad;      // [S][NT][ntl_max]
   double* BE = R + (size_t)S * NT * ntl_max;  // [S][NT]
+  double* Nb = BE + (size_t)S * NT;         // [2][nvpad] pixel counts per column
+  double* Rn = Nb + 2 * nvpad;              // [S][ntl_max] count-plane carries
   const int xa = x0 + chunk * cw;
   const int cwc = min(cw, x1 - xa + 1);
   const bool contig = 2 * rx + 1 <= cwc;
@@ -559,6 +581,8 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
                 acc);
     }
     R[(mm * NT + i) * ntl_max + t] = acc;
+    if (i == 0)
+      Rn[mm * ntl_max + t] = gp.RC[swih_rc(g, 0, b, tlo + t, yb)] - gp.RC[swih_rc(g, 0, b, tlo + t, ya)];
   }
   CI ci;
   ci.init(tid, nV, nvpad, xa, rx, cwc, contig);
@@ -596,6 +620,7 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
     const int c0 = first_cross(Ya, g.TY);
     const int ncross = c0 < Yb ? (Yb - 1 - c0) / g.TY + 1 : 0;
     double* Gp = Gb + (mm & 1) * NG * 2 * nvpad;
+    double* Np = Nb + (mm & 1) * nvpad;
     double be[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) be[j] = uniform(BE[mm * NT + j]);
@@ -608,7 +633,7 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
         float lb[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) lb[j] = lpi[ii][(size_t)Yb * rs + (size_t)j * 64];
-        double vl = 0.0;
+        double vl = 0.0, nl = (double)lb[0] - (double)prev[ii][0];
 #pragma unroll
         for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lb[j] - (double)prev[ii][j], vl);
         for (int c = 0; c < ncross; ++c) {
@@ -618,7 +643,11 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
             lc[j] = lpi[ii][(size_t)(c0 + c * g.TY) * rs + (size_t)j * 64];
 #pragma unroll
           for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
+          nl += (double)lc[0];
         }
+        // slot 0's first item is term 0 of its column: the column's pixel count
+        if (ii == 0 && ci.slot == 0)
+          Np[ci.xi[0]] = Rn[mm * ntl_max + tX[0]] + (x0col[0] ? 0.0 : nl);
         const double v = R[(mm * NT + i) * ntl_max + tX[ii]] + (x0col[ii] ? 0.0 : vl);
         if (ci.single) {
           Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[ii]] = fma(ap[ii], v, 0.0);
@@ -641,8 +670,9 @@ __device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
 #pragma unroll
       for (int qg = 0; qg < NG; ++qg)
         hh += Gp[(qg * 2 + 0) * nvpad + i2] - Gp[(qg * 2 + 1) * nvpad + i1];
-      atomicAdd((unsigned long long*)&a.acc[(size_t)(yc - y0) * mw + (xc - x0)],
-                (unsigned long long)bc_term(hh * inv_mass, tb));
+      if (Np[i2] - Np[i1] != 0.0)
+        atomicAdd((unsigned long long*)&a.acc[(size_t)(yc - y0) * mw + (xc - x0)],
+                  (unsigned long long)bc_term(hh * inv_mass, tb));
     }
   }
 }
@@ -831,7 +861,8 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   ml.blocks = a.nbx * ny;
   // every chunk's nV is at most the first chunk's, so its thread count serves all
   ml.threads = gauss_map_threads(NT, nV);
-  ml.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)L.g.B * NT * a.ntl_max);
+  ml.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)L.g.B * NT * a.ntl_max +
+                             (size_t)2 * a.nvpad + (size_t)L.g.B * a.ntl_max);
 }
 
 void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
@@ -850,7 +881,7 @@ void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   ql.threads = 256;
   if (L.g.gauss) {
     ql.blocks = n;
-    ql.lds = sizeof(double) * (size_t)L.g.B * L.g.nI;
+    ql.lds = sizeof(double) * (size_t)L.g.B * (L.g.nI + 1);
   } else {
     ql.blocks = (int32_t)(((long)n * L.g.B + 255) / 256);
     ql.lds = 0;
@@ -921,7 +952,7 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   cl.threads = ml.threads;
   cl.blocks = L.g.B * a.nbx * a.comb_segs * h;
   cl.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)S * NT * a.ntl_max +
-                             (size_t)S * NT);
+                             (size_t)S * NT + (size_t)2 * a.nvpad + (size_t)S * a.ntl_max);
   if (cl.lds > 160 * 1024) return match_one(sp.kind, L.g.nI, a, ml, s);
   hipError_t e = comb_one(NT, a, cl, s);
   if (e != hipSuccess) return e;

@@ -18,6 +18,14 @@ GAUSS_TOL = 1e-5
 # + float output rounding < 1.4e-6; the bar is 2e-6.
 EXP_TOL = 2e-6
 
+# Every real-valued likelihood map (2-D Gaussian, separable Gaussian,
+# exponential): |BC' - BC| <= MAP_TOL at every centre checked, against the
+# FP64 oracle's map of the true kernel.  A bin with no pixel in the window must
+# then contribute exactly 0 (sqrt turns a residue e into sqrt(e t)); the
+# kernels test emptiness exactly (the Gaussian's pixel-count term, the
+# exponential's rounding bound).
+MAP_TOL = 1e-5
+
 
 def to_dev(a, torch):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -54,12 +62,13 @@ def map_tolerance(p_oracle: np.ndarray, t_oracle: np.ndarray, eps: float,
 
 
 def gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=None, kind=None, okind=None,
-                tol=GAUSS_TOL, map_slack=1e-6, K=0):
+                tol=GAUSS_TOL, K=0):
     """Histograms at ``centres``, the template at ``tcentre`` and (optionally) the
     map over ``map_rect`` of a real-valued kind (a series-Gaussian form by
     default, ``K`` series terms per axis, 0 = the default) against the FP64
-    oracle of kernel ``okind``, to ``tol`` per bin; maps to the bound that
-    implies, plus ``map_slack``."""
+    oracle of kernel ``okind``, to ``tol`` per bin; maps to MAP_TOL, with the
+    GPU's own template and with the oracle's.  The bound a per-bin error of
+    ``tol`` would imply through sqrt is printed as a diagnostic only."""
     import torch
 
     import oracle
@@ -86,12 +95,12 @@ def gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=None, kind=None
         ys, xs = np.mgrid[y0:y1 + 1, x0:x1 + 1]
         cc = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
         pref = oracle.normalised(oracle.hist(img, nb, ok, w, h, cc), ok, w, h)
-        mtol = map_tolerance(pref, tref, tol).reshape(mref.shape) + map_slack
-        mtol_or = map_tolerance(pref, tref, tol, template_exact=True).reshape(mref.shape) + map_slack
+        mtol = map_tolerance(pref, tref, tol).reshape(mref.shape)
         out["map_err"] = float(np.abs(m - mref).max())
         out["map_err_oracle_template"] = float(np.abs(m_or - mref).max())
-        assert np.all(np.abs(m - mref) <= mtol), label
-        assert np.all(np.abs(m_or - mref) <= mtol_or), label
+        out["derived_bound_min"] = float(mtol.min())
+        assert out["map_err"] <= MAP_TOL, (label, out)
+        assert out["map_err_oracle_template"] <= MAP_TOL, (label, out)
     print(label, out, flush=True)
     assert herr <= tol, (label, herr)
     assert terr <= tol, (label, terr)

@@ -3,7 +3,9 @@ may mix choices per frame, and the autotuner picks and caches one.
 
 * integer kernels: histograms and maps bit-exact against the oracle for 16 and
   32 rows (as for the default 64);
-* the 2-D Gaussian and the exponential: within their oracle bars;
+* the 2-D Gaussian and the exponential: within their oracle bars, and their
+  maps for 16, 32 and 64 rows within 1e-5 of one another (rounding differs
+  with the tile-local origins, nothing else);
 * a batch whose frames use different rows equals the single-frame calls.
 """
 import numpy as np
@@ -20,7 +22,7 @@ from paper_1705_03524_amd.autotune import Autotuner  # noqa: E402
 from paper_1705_03524_amd.batch import Batch  # noqa: E402
 from paper_1705_03524_amd.plan import Plan  # noqa: E402
 
-from gpu_util import EXP_TOL, GAUSS_TOL, all_centres, map_tolerance, to_dev  # noqa: E402
+from gpu_util import EXP_TOL, GAUSS_TOL, MAP_TOL, all_centres, to_dev  # noqa: E402
 
 
 @pytest.mark.parametrize("rows", [16, 32])
@@ -55,16 +57,18 @@ def test_real_kernels_for_every_band_height(rows, kind, okind, tol):
     got = plan.query(0, to_dev(c, torch))[0].cpu().numpy().astype(np.float64)
     ref = oracle.normalised(oracle.hist(img, 16, okind, 31, 21, c), okind, 31, 21)
     assert np.abs(got - ref).max() <= tol
-    # the map against the oracle's, within the bound the histogram bar implies (oracle template)
+    # the map against the oracle's (oracle template), and against the map of
+    # the same workspace built with the default 64-row bands
     _, tref = oracle.template(img, 16, okind, 31, 21, tuple(c[0]))
-    rect = (15, 10, 60, 40)
-    m = plan.match(0, template=to_dev(tref.astype(np.float32), torch), rect=rect).cpu().numpy()
-    mref = oracle.bc_map(img, 16, okind, 31, 21, tref, rect=rect)
-    ys, xs = np.mgrid[rect[1]:rect[3] + 1, rect[0]:rect[2] + 1]
-    cc = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
-    pref = oracle.normalised(oracle.hist(img, 16, okind, 31, 21, cc), okind, 31, 21)
-    bound = map_tolerance(pref, tref, tol, template_exact=True).reshape(mref.shape) + 1e-6
-    assert np.all(np.abs(m - mref) <= bound)
+    t = to_dev(tref.astype(np.float32), torch)
+    m = plan.match(0, template=t).cpu().numpy().astype(np.float64)
+    mref = oracle.bc_map(img, 16, okind, 31, 21, tref)
+    ref64 = Plan(swih.Config(16, kind, [(31, 21)]), H, W)
+    ref64.build(to_dev(img, torch))
+    m64 = ref64.match(0, template=t).cpu().numpy().astype(np.float64)
+    print({"map_err": float(np.abs(m - mref).max()), "vs_64_rows": float(np.abs(m - m64).max())}, flush=True)
+    assert np.abs(m - mref).max() <= MAP_TOL
+    assert np.abs(m - m64).max() <= MAP_TOL
 
 
 @pytest.mark.parametrize("kind", [swih.MANHATTAN, swih.GAUSSIAN, swih.EXPONENTIAL])

@@ -2,8 +2,7 @@
 
 Bar: normalised histograms within EXP_TOL = 2e-6 of the FP64 brute-force
 oracle (the decomposition is exact; the bound on float rounding is derived in
-tests/gpu_util.py), maps within the bound that implies through sqrt plus
-float rounding of the output.  Cases:
+tests/gpu_util.py), maps within MAP_TOL = 1e-5 of the oracle's map.  Cases:
 * the 512 x 512 scene with every valid centre and the full map;
 * ragged sizes, 1 to 256 bins, windows from 1 x 1 to the whole image;
 * images far larger than exp(x / t) survives in any float format (2048^2 with
@@ -30,7 +29,7 @@ OEXP = oracle.EXPONENTIAL
 
 def check(img, nb, w, h, centres, tcentre, label, map_rect=None):
     return gauss_check(img, nb, w, h, centres, tcentre, label, map_rect=map_rect, kind=EXP,
-                       okind=OEXP, tol=EXP_TOL, map_slack=2e-7)
+                       okind=OEXP, tol=EXP_TOL)
 
 
 def test_scene512():

@@ -6,7 +6,7 @@ one-column windows) are met.  Each case is checked to the bar of its kernel:
 
 * uniform / Manhattan / Euclidean: raw histograms and maps bit for bit;
 * Gaussian (2-D and separable) and exponential: normalised histograms within
-  their oracle tolerance, maps within the bound that implies.
+  their oracle tolerance, maps within MAP_TOL = 1e-5 of the oracle's.
 
 Inputs are small enough for the oracle to compute every window.
 """
@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 import paper_1705_03524_amd as swih  # noqa: E402
 from paper_1705_03524_amd.plan import Plan  # noqa: E402
 
-from gpu_util import EXP_TOL, GAUSS_TOL, all_centres, map_tolerance, to_dev  # noqa: E402
+from gpu_util import EXP_TOL, GAUSS_TOL, MAP_TOL, all_centres, to_dev  # noqa: E402
 
 OKIND = {swih.UNIFORM: oracle.UNIFORM, swih.MANHATTAN: oracle.MANHATTAN, swih.EUCLIDEAN: oracle.EUCLIDEAN,
          swih.GAUSSIAN: oracle.GAUSSIAN, swih.GAUSSIAN_SEP: oracle.GAUSSIAN, swih.EXPONENTIAL: oracle.EXPONENTIAL}
@@ -74,8 +74,8 @@ def test_random_configuration(seed):
     _, tref = oracle.template(img, nb, ok, w, h, tc)
     m = plan.match(0, template=thist[0].contiguous()).cpu().numpy().astype(np.float64)
     mref = oracle.bc_map(img, nb, ok, w, h, tref)
-    mtol = map_tolerance(pref, tref, tol).reshape(m.shape) + 1e-6
-    print({"hist_err": float(herr), "map_err": float(np.abs(m - mref).max())}, flush=True)
+    merr = float(np.abs(m - mref).max())
+    print({"hist_err": float(herr), "map_err": merr}, flush=True)
     assert herr <= tol, (seed, herr)
-    assert np.all(np.abs(m - mref) <= mtol), seed
+    assert merr <= MAP_TOL, (seed, merr)
     assert rect[2] - rect[0] + 1 == m.shape[1] and rect[3] - rect[1] + 1 == m.shape[0]

@@ -118,6 +118,32 @@ def test_exponential_table_structure(w, h):
         assert qx[0] ** (w / 4.0) == pytest.approx(math.exp(-1), rel=1e-13)
 
 
+@pytest.mark.parametrize("w,h", [(3, 3), (7, 5), (5, 11), (31, 31), (61, 91), (81, 21)])
+def test_gaussian_table_structure(w, h):
+    # the true Gaussian with sigma = side / 4 per axis, pinned by its shape
+    # rather than by its formula: peak 1 at the centre, mirror symmetric, rank
+    # one, and log k a parabola along each axis whose second difference is
+    # -1 / sigma^2 with sigma set by that axis's own side
+    t = oracle.kernel_table(oracle.GAUSSIAN, w, h)
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    assert t[ry, rx] == 1.0
+    np.testing.assert_allclose(t, t[::-1, :], rtol=0, atol=0)
+    np.testing.assert_allclose(t, t[:, ::-1], rtol=0, atol=0)
+    np.testing.assert_allclose(t, np.outer(t[:, rx], t[ry, :]), rtol=1e-14)
+    assert np.all(t > 0) and np.all(t <= 1.0)
+    lx, ly = np.log(t[ry, :]), np.log(t[:, rx])
+    if w >= 3:
+        np.testing.assert_allclose(lx[2:] - 2 * lx[1:-1] + lx[:-2], -1.0 / (w / 4.0) ** 2, rtol=1e-9)
+    if h >= 3:
+        np.testing.assert_allclose(ly[2:] - 2 * ly[1:-1] + ly[:-2], -1.0 / (h / 4.0) ** 2, rtol=1e-9)
+    # a wrong sign of the exponent, a missing factor 1/2 or sigma from the wrong
+    # side would each move the corner weight: exp(-(rx/sx)^2/2 - (ry/sy)^2/2)
+    corner = math.exp(-0.5 * (rx / (w / 4.0)) ** 2 - 0.5 * (ry / (h / 4.0)) ** 2)
+    assert t[0, 0] == pytest.approx(corner, rel=1e-12)
+    if w != h:
+        np.testing.assert_allclose(oracle.kernel_table(oracle.GAUSSIAN, h, w).T, t, rtol=1e-15)
+
+
 def test_manhattan_table_follows_eq1_distance():
     # weights fall by one per unit of city-block distance from the centre and
     # are 1 at the window corners
