@@ -205,6 +205,17 @@ def measured_traffic(kernel_prefix, path=PROFILE_COUNTERS):
     return total
 
 
+def copy_calibration():
+    """One 1 GiB device-to-device copy (1 GiB read, 1 GiB written), so that the
+    HBM counters of a profiling run can be scaled to bytes."""
+    import torch
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def capture_graph(fn):
     """Capture fn's launches (on the current stream) as one HIP graph, after one
     eager run on a side stream."""
@@ -293,6 +304,8 @@ def run_multiscale(args):
             for ph in PHASES:
                 phase(si, ph)
 
+    if args.copy_calibration:
+        copy_calibration()
     for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
@@ -839,11 +852,7 @@ def run_frame(args, side_kinds=True, builds=True, cpu=True):
         return g
 
     if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -85,15 +85,18 @@ struct MatchArgs {
   ScaleParams sp;
   const void* planes;      // uint32 planes or float tile-local planes
   const double* RC;        // Gaussian row carries
+  double* R;               // Gaussian: row carries contracted at the centre rows (swih_rcc)
   const float* tmpl;       // normalised template, or null
   const uint32_t* tmpl_raw;  // exact template (integer kernels), or null
   float* map;
   int32_t x0, y0, x1, y1;  // inclusive centre rectangle
-  int32_t nbx;             // virtual blocks per row of blocks
-  int32_t cw, nvpad, ntl_max;  // Gaussian: centres per block, columns per group, tile columns
-  int64_t* acc;            // Gaussian, comb form: per-centre integer accumulator (zero between maps)
-  int32_t comb_steps;      // comb form: centre rows per segment
-  int32_t comb_segs;       // comb form: segments per comb
+  int32_t nbx;             // integer kernels: virtual blocks per row of blocks
+  // Gaussian comb sweep: items = ngroups x nch x nseg x ncomb
+  int32_t nch, cw, nt;     // column chunks, centres per chunk, tiles (waves) per block
+  int32_t ncomb, nseg, S;  // combs, segments per comb, members per segment
+  int32_t ngroups, bpg;    // bin groups, bins per group
+  int32_t two;             // 1: a block's waves cover the left-edge and the right-edge tiles apart
+  int64_t* acc;            // ngroups > 1: per-centre integer accumulator (zero between maps)
 };
 
 struct Launch {
@@ -124,6 +127,12 @@ hipError_t launch_query_batch(int kind, int nt, const QueryArgs* jobs, const int
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                 const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0, int32_t x1,
                 int32_t y1, float* map, MatchArgs& a, Launch& ml);
+
+// Gaussian maps: blocks of the row-carry contraction that precedes a map
+// (rc_contract), and its batched launch (prefix: exclusive block prefixes).
+int32_t rc_contract_blocks(const MatchArgs& a);
+hipError_t launch_rcc_batch(int nt, const MatchArgs* jobs, const int32_t* prefix, int njobs,
+                            int32_t total, int grid, hipStream_t stream);
 
 // One batched map launch over njobs (same kernel); ml: total virtual blocks,
 // the largest block size and LDS of any job.

@@ -20,6 +20,8 @@
 // (the same at every location, Sec. 2.1).
 #include <string.h>
 
+#include <algorithm>
+
 #include "swih_internal.h"
 #include "wave64.h"
 
@@ -247,15 +249,6 @@ __device__ __forceinline__ double uniform(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// One coefficient of the series at centre coordinate c: index 0 -> a_0,
-// 2k-1 -> a_k cos(w_k c), 2k -> a_k sin(w_k c).
-__device__ __forceinline__ double series_coeff(const GaussAxis& ax, int c, int idx) {
-  if (idx == 0) return ax.a[0];
-  const int k = (idx + 1) / 2;
-  const double ang = ax.om[k] * (double)c;
-  return ax.a[k] * ((idx & 1) ? cos(ang) : sin(ang));
-}
-
 // A Gaussian map value is sum_b sqrt(p_b t_b).  Each bin's term is rounded to
 // a multiple of 2^-40 and the terms are added as integers: exact, so the sum
 // is the same whatever the order in which bins arrive (one block per bin and
@@ -276,408 +269,342 @@ __device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q 
 // its box is an integer (tile-local float values below 2^24, double carries),
 // so the count is exact and the maps drop a bin's term exactly when it is 0.
 
-// Column work of the Gaussian maps.  A block covers nV plane columns X (the
-// left and right window edges of its chunk of centres).  The x terms i of a
-// column are split over NG slots; each thread sums the terms of its items in
-// item order and writes its slot's partial G+/G- to LDS, and the window
-// threads add the slots in slot order.  Both map kernels use this split, so
-// their maps agree bit for bit.
-//  * strided (NT != 2 NG - 1): slot s holds terms s, s + NG, s + 2 NG, ...;
-//    one thread per (slot, column) and NG * nvpad threads, so a wave never
-//    spans two slots.
-//  * paired (NT == 2 NG - 1): slot s < NG - 1 holds terms s and s + NG, one
-//    thread per (slot, column); the last slot holds term NG - 1 alone, one
-//    thread per two columns (xi and xi + ceil(nV / 2)).  Every thread has two
-//    items: for NT = 7 the seven terms cost two item times per step instead of
-//    three with a strided split over three slots.
-__host__ __device__ constexpr int gauss_slots(int NT) { return NT <= 7 ? (NT + 1) / 2 : 3; }
+// Gaussian maps: the comb sweep.
+//
+// With the y terms contracted at the centre row, V_i(X) = sum_j beta_j(yc)
+// (P_ij[Yb][X] - P_ij[Ya][X]) (Ya = yc - ry, Yb = yc + ry + 1), a window's
+// histogram is H_b(xc) = sum_i alpha_i(xc) (V_i(xc + rx + 1) - V_i(xc - rx)).
+// Each plane column therefore folds its V_i into the two values the windows
+// need from it,
+//   G+(X) = sum_i alpha_i(X - rx - 1) V_i(X)   (X is a window's right edge)
+//   G-(X) = sum_i alpha_i(X + rx) V_i(X)       (X is a window's left edge),
+// and H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).  The box difference of the
+// tile-local storage is
+//   P[Yb] - P[Ya] = L[Yb] - L[Ya] + sum_c L[c] + RC[Yb] - RC[Ya],
+// c the band-closing rows (multiples of TY) in [Ya, Yb).  When Ya itself
+// closes a band its L cancels against the crossing at c = Ya, so both drop.
+// The row-carry part does not depend on the column inside a tile: rc_contract
+// tabulates R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) per (bin, centre row,
+// tile) before the sweep (swih_rcc).  A column's V is then a sum of row
+// events, each contracted with beta(yc): the opening row Ya (minus), the
+// crossings, the boundary row Yb (plus), and R once per member.
+//
+// Combs.  The centre rows yc = y0 + q + m h (h the window height) of comb q
+// follow one another so that member m's boundary row is member m + 1's
+// opening row.  A block walks a segment of S members of one comb, reading
+// each boundary row once and contracting it twice (with beta(yc_m) for the
+// member it closes and beta(yc_m+1) for the one it opens).
+//
+// Work item = (bin group, column chunk, segment, comb); a block has one wave
+// per 64-column tile of its chunk (one thread per plane column, every weight
+// term of the column in that thread), loops over the group's bins and walks
+// the segment for each.  Rows are read in load units (IG x terms, all their
+// y terms) through two register buffers: the next unit's loads are issued
+// before the current unit is contracted, so every wave keeps a unit in
+// flight through the contraction, the barrier and the window phase.  Per
+// member, the column threads put G+, G- and the column's pixel count N (term
+// (0, 0)) into LDS (double-buffered, one barrier) and the window threads add
+// the bin's term sqrt(p_b t_b) to their (member, window) accumulator in LDS.
+// With one bin group the map is stored once at the end; with several, each
+// group adds its sums into the set's integer accumulator and
+// match_gauss_fin writes the map.  A segment of one member is the plain
+// two-row form.  All forms do the same operations in the same order for
+// every (window, bin), so their maps agree bit for bit.
+enum : int { kEvOpen = 0, kEvCross = 1, kEvBound = 2, kEvEnd = 3 };
 
-template <int NT, int NG>
-struct ColItems {
-  static constexpr bool kPaired = NT == 2 * NG - 1;
-  static constexpr int NI = kPaired ? 2 : (NT + NG - 1) / NG;
-  int slot;      // LDS slot of this thread's sums, -1 for none
-  bool single;   // paired split, last slot: the two items are two columns of one term
-  int i[NI], xi[NI], X[NI];
-  bool ok[NI];
-
-  __device__ __forceinline__ void init(int tid, int nV, int nvpad, int xa, int rx, int cwc,
-                                       bool contig) {
-    auto colX = [&](int c) {
-      return contig ? xa - rx + c : (c < cwc ? xa - rx + c : xa + rx + 1 + c - cwc);
-    };
-    single = false;
-    if constexpr (kPaired) {
-      const int base = (NG - 1) * nV, nvh = (nV + 1) / 2;
-      if (tid < base) {
-        slot = tid / nV;
-        const int c = tid - slot * nV;
-        i[0] = slot;
-        i[1] = slot + NG;
-        xi[0] = xi[1] = c;
-        ok[0] = ok[1] = true;
-      } else if (tid < base + nvh) {
-        slot = NG - 1;
-        single = true;
-        i[0] = i[1] = NG - 1;
-        xi[0] = tid - base;
-        xi[1] = xi[0] + nvh;
-        ok[0] = true;
-        ok[1] = xi[1] < nV;
-      } else {
-        slot = -1;
-#pragma unroll
-        for (int ii = 0; ii < NI; ++ii) {
-          i[ii] = 0;
-          xi[ii] = 0;
-          ok[ii] = false;
-        }
-      }
-    } else {
-      const int grp = __builtin_amdgcn_readfirstlane(tid / nvpad);
-      const int c = tid - grp * nvpad;
-      const bool has = grp < NG && c < nV;
-      slot = has ? grp : -1;
-#pragma unroll
-      for (int ii = 0; ii < NI; ++ii) {
-        i[ii] = grp + ii * NG;
-        xi[ii] = c;
-        ok[ii] = has && i[ii] < NT;
-      }
-    }
-#pragma unroll
-    for (int ii = 0; ii < NI; ++ii) {
-      X[ii] = ok[ii] ? colX(xi[ii]) : xa;
-      if (!ok[ii]) i[ii] = 0;
-    }
-  }
+struct SweepEv {
+  int b, mm, Y, type, Ya, k;  // bin, member, row, kind, the member's opening row, load unit
 };
 
-// Threads of a map block over nV columns with the split of NT terms.
-__host__ __device__ constexpr int gauss_map_threads(int NT, int nV) {
-  return gauss_slots(NT) * 2 - 1 == NT
-             ? ((gauss_slots(NT) - 1) * nV + (nV + 1) / 2 + 63) / 64 * 64
-             : gauss_slots(NT) * ((nV + 63) / 64 * 64);
+// The event after e (unit 0 of it) in the walk of a segment of cnt members
+// over bins [., b1).
+__device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1, int h, int TY,
+                                              int Ya0) {
+  SweepEv n = e;
+  n.k = 0;
+  int Ya = e.Ya, mm = e.mm, c;
+  if (e.type == kEvBound) {
+    if (mm + 1 >= cnt) {
+      if (e.b + 1 >= b1) {
+        n.type = kEvEnd;
+        return n;
+      }
+      n.b = e.b + 1;
+      n.mm = 0;
+      n.Y = n.Ya = Ya0;
+      n.type = kEvOpen;
+      return n;
+    }
+    mm += 1;
+    Ya = e.Y;
+    c = (Ya / TY + 1) * TY;
+  } else {
+    c = e.type == kEvOpen ? (Ya / TY + 1) * TY : e.Y + TY;
+  }
+  const int Yb = Ya + h;
+  n.mm = mm;
+  n.Ya = Ya;
+  n.Y = c < Yb ? c : Yb;
+  n.type = c < Yb ? kEvCross : kEvBound;
+  return n;
 }
 
-// Dense map.  One block per (row of centres yc, chunk of cw centres), threads
-// over (slot, plane column X the chunk's windows touch: X = xc - rx and
-// xc + rx + 1).  With the y terms contracted,
-//   V_i(X) = sum_j beta_j(yc) (P_ij[yb][X] - P_ij[ya][X]),
-// the window histogram is H_b(xc) = sum_i alpha_i(xc) (V_i(xc+rx+1) - V_i(xc-rx)).
-// Each column therefore folds its own V_i into the two quantities the windows
-// need from it,
-//   G+(X) = sum_i alpha_i(X - rx - 1) V_i(X)   (X is a right edge)
-//   G-(X) = sum_i alpha_i(X + rx) V_i(X)       (X is a left edge),
-// and only those cross LDS: H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).  The row
-// carries of V_i depend on X only through its tile column and are tabulated
-// for every bin once per block.  Per bin: the column threads load their
-// L rows (all j of one item together), one barrier (LDS double-buffered by bin
-// parity), the window threads accumulate sqrt(p_b t_b).
-template <int NT, int NG>
-__device__ __forceinline__ void match_gauss(const MatchArgs& a, int vb) {
-  using CI = ColItems<NT, NG>;
-  constexpr int NI = CI::NI;
-  const SwihGeom& g = a.g;
-  const ScaleParams& sp = a.sp;
-  const GaussPlanes gp{(const float*)a.planes, a.RC};
-  const float* __restrict__ tmpl = a.tmpl;
-  const int x0 = a.x0, y0 = a.y0, x1 = a.x1;
-  const int cw = a.cw, nvpad = a.nvpad, ntl_max = a.ntl_max;
-  // a block may run several virtual blocks one after another: the previous
-  // one's window threads must be done with LDS before it is overwritten
-  __syncthreads();
-  extern __shared__ double sm[];
-  double* Gb = sm;                                  // [2][NG][2][nvpad]
-  double* R = sm + 2 * NG * 2 * nvpad;              // [B][NT][ntl_max]
-  double* Nb = R + (size_t)g.B * NT * ntl_max;      // [2][nvpad] pixel counts per column
-  double* Rn = Nb + 2 * nvpad;                      // [B][ntl_max] count-plane carries
-  const int yc = y0 + vb / a.nbx;
-  const int xa = x0 + (vb % a.nbx) * cw;
-  const int cwc = min(cw, x1 - xa + 1);
-  const int rx = sp.rx, ry = sp.ry;
-  const bool contig = 2 * rx + 1 <= cwc;
-  const int nV = contig ? cwc + 2 * rx + 1 : 2 * cwc;
-  const int Ya = yc - ry, Yb = yc + ry + 1;
-  const int c0 = first_cross(Ya, g.TY);
-  const int ncross = c0 < Yb ? (Yb - 1 - c0) / g.TY + 1 : 0;
-  double be[NT];
-  series_coeffs<NT>(sp.ay, yc, be);
+// x terms per load unit: two units of IG x NT floats stay within the
+// registers of three waves per SIMD.
+template <int NT>
+__host__ __device__ constexpr int sweep_ig() {
+  return NT <= 5 ? NT : (NT <= 7 ? 4 : (NT <= 11 ? 2 : 1));
+}
+
+// One load unit's contraction: terms [i0, i0 + IG) of the row in d.
+//   kEvOpen   (op, om) += alpha+-_i sum_j beta_j L_ij (beta of the member it opens)
+//   kEvCross  (gp, gm) += alpha+-_i sum_j beta_j L_ij (beta of its member)
+//   kEvBound  the same into (gp, gm), and, if `next`, into (op, om) with bn
+//             (beta of the member it opens).
+// Rows that close a band (withL false) open a member with nothing: their L
+// cancels against the crossing at the same row.
+template <int NT, int IG>
+__device__ __forceinline__ void sweep_unit(const float (&d)[IG * NT], int type, bool next,
+                                           const double* be, const double* bn, int i0,
+                                           const double (&ap)[NT], const double (&am)[NT],
+                                           double& gp, double& gm, double& op, double& om) {
 #pragma unroll
-  for (int j = 0; j < NT; ++j) be[j] = uniform(be[j]);
-  const int tid = threadIdx.x;
-  const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
-  // row-carry table of every bin: R[b][i][t] = sum_j beta_j (RC_ij[yb] - RC_ij[ya])
-  for (int it = tid; it < g.B * NT * ntl; it += blockDim.x) {
-    const int b = it / (NT * ntl);
-    const int rem = it - b * (NT * ntl);
-    const int i = rem / ntl, t = rem - (rem / ntl) * ntl;
-    double acc = 0.0;
+  for (int ii = 0; ii < IG; ++ii) {
+    const int i = i0 + ii;
+    if (i >= NT) break;
+    double s = 0.0, sn = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const int p = i * NT + j;
-      acc = fma(be[j], gp.RC[swih_rc(g, p, b, tlo + t, Yb)] - gp.RC[swih_rc(g, p, b, tlo + t, Ya)], acc);
-    }
-    R[(b * NT + i) * ntl_max + t] = acc;
-    if (i == 0)
-      Rn[b * ntl_max + t] = gp.RC[swih_rc(g, 0, b, tlo + t, Yb)] - gp.RC[swih_rc(g, 0, b, tlo + t, Ya)];
-  }
-  CI ci;
-  ci.init(tid, nV, nvpad, xa, rx, cwc, contig);
-  // alpha at the two windows each item's column serves, for the item's x term
-  double ap[NI], am[NI];
-  int tX[NI];
-  bool x0col[NI];
-  size_t offA[NI], offB[NI], offC[NI];
-  const int64_t rs = g.row_stride;
-#pragma unroll
-  for (int ii = 0; ii < NI; ++ii) {
-    const int X = ci.X[ii];
-    ap[ii] = series_coeff(sp.ax, max(X - rx - 1, 0), ci.i[ii]);
-    am[ii] = series_coeff(sp.ax, X + rx, ci.i[ii]);
-    tX[ii] = tile_of(X) - tlo;
-    // column X = 0 is not stored (it is zero): its thread loads column 1 and drops it
-    x0col[ii] = X == 0;
-    const int64_t xo = swih_xoff(g, x0col[ii] ? 1 : X);
-    offA[ii] = (size_t)Ya * rs + xo;
-    offB[ii] = (size_t)Yb * rs + xo;
-    offC[ii] = (size_t)c0 * rs + xo;
-  }
-  const bool win = tid < cwc;
-  const int xc = xa + tid;
-  const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
-  const double inv_mass = 1.0 / sp.mass;
-  int64_t bc = 0;
-  __syncthreads();
-  for (int b = 0; b < g.B; ++b) {
-    double* Gp = Gb + (b & 1) * NG * 2 * nvpad;
-    double* Np = Nb + (b & 1) * nvpad;
-    if (ci.slot >= 0) {
-      double gplus = 0.0, gminus = 0.0;
-#pragma unroll
-      for (int ii = 0; ii < NI; ++ii) {
-        if (!ci.ok[ii]) break;
-        const int i = ci.i[ii];
-        const float* lp = gp.L + swih_base(g, i * NT, b);
-        float la[NT], lb[NT];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          la[j] = lp[offA[ii] + (size_t)j * 64];
-          lb[j] = lp[offB[ii] + (size_t)j * 64];
-        }
-        double vl = 0.0, nl = (double)lb[0] - (double)la[0];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lb[j] - (double)la[j], vl);
-        for (int c = 0; c < ncross; ++c) {
-          float lc[NT];
-#pragma unroll
-          for (int j = 0; j < NT; ++j) lc[j] = lp[offC[ii] + (size_t)c * g.TY * rs + (size_t)j * 64];
-#pragma unroll
-          for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
-          nl += (double)lc[0];
-        }
-        // slot 0's first item is term 0 of its column: the column's pixel count
-        if (ii == 0 && ci.slot == 0)
-          Np[ci.xi[0]] = Rn[b * ntl_max + tX[0]] + (x0col[0] ? 0.0 : nl);
-        const double v = R[(b * NT + i) * ntl_max + tX[ii]] + (x0col[ii] ? 0.0 : vl);
-        if (ci.single) {
-          Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[ii]] = fma(ap[ii], v, 0.0);
-          Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[ii]] = fma(am[ii], v, 0.0);
-        } else {
-          gplus = fma(ap[ii], v, gplus);
-          gminus = fma(am[ii], v, gminus);
-        }
-      }
-      if (!ci.single) {
-        Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[0]] = gplus;
-        Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[0]] = gminus;
+      const double lv = (double)d[ii * NT + j];
+      if (type == kEvOpen) {
+        sn = fma(be[j], lv, sn);
+      } else {
+        s = fma(be[j], lv, s);
+        if (next) sn = fma(bn[j], lv, sn);
       }
     }
-    __syncthreads();
-    if (win) {
-      double hh = 0.0;
-#pragma unroll
-      for (int q = 0; q < NG; ++q) hh += Gp[(q * 2 + 0) * nvpad + i2] - Gp[(q * 2 + 1) * nvpad + i1];
-      if (Np[i2] - Np[i1] != 0.0) bc += bc_term(hh * inv_mass, tmpl[b]);
+    if (type == kEvOpen || next) {
+      op = fma(ap[i], sn, op);
+      om = fma(am[i], sn, om);
+    }
+    if (type != kEvOpen) {
+      gp = fma(ap[i], s, gp);
+      gm = fma(am[i], s, gm);
     }
   }
-  if (win) a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = bc_value(bc);
 }
 
-
-// Dense map for large rectangles: one block per (bin, chunk of centres, comb
-// segment).  A comb is the set of centre rows yc = y0 + q + m h (h the window
-// height): the bottom row of one comb member's windows is the top row of the
-// next, so a block walks its comb segment reading each boundary row once and
-// keeping the previous one in registers (S + 1 rows for S centre rows, against
-// 2 S for one row per block).  Per centre row the column threads form G+/G-
-// exactly as match_gauss does (same split, same operations in the same
-// order), the window threads form the bin's term and add it, as an integer,
-// into the map's accumulator.  match_gauss_fin turns the accumulator into the
-// map and clears it.  The result equals match_gauss bit for bit.
-template <int NT, int NG>
-__device__ __forceinline__ void match_gauss_comb(const MatchArgs& a, int vb) {
-  using CI = ColItems<NT, NG>;
-  {
-    // Workgroups go to the 8 XCDs round robin: renumber so that each XCD runs
-    // a contiguous range of virtual blocks, i.e. the combs of one (bin, chunk)
-    // together, and their shared band-closing rows stay in that XCD's L2.
-    const int n = (int)gridDim.x, base = n >> 3, rem = n & 7;
-    const int x = vb & 7, k = vb >> 3;
-    vb = x * base + (x < rem ? x : rem) + k;
-  }
-  constexpr int NI = CI::NI;
+// Row carries contracted at the centre rows of a rectangle: one thread per
+// (bin, tile column, centre row), centre rows fastest (their RC rows are
+// consecutive in memory).  Writes swih_rcc entries.
+template <int NT>
+__device__ __forceinline__ void rc_contract(const MatchArgs& a, int vb) {
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
-  const GaussPlanes gp{(const float*)a.planes, a.RC};
-  const int x0 = a.x0, y0 = a.y0, x1 = a.x1, y1 = a.y1;
-  const int cw = a.cw, nvpad = a.nvpad, ntl_max = a.ntl_max;
-  const int S = a.comb_steps, nsegc = a.comb_segs;
-  const int rx = sp.rx, ry = sp.ry, h = 2 * ry + 1;
-  const int q = vb % h;
-  int r = vb / h;
-  const int sg = r % nsegc;
-  r /= nsegc;
-  const int chunk = r % a.nbx;
-  const int b = r / a.nbx;
-  const int ny = y1 - y0 + 1;
+  const int ny = a.y1 - a.y0 + 1;
+  const int tlo = (max(a.x0 - sp.rx, 1) - 1) >> 6, thi = (a.x1 + sp.rx) >> 6;
+  const int ntl = thi - tlo + 1;
+  const long n = (long)vb * 256 + threadIdx.x;
+  if (n >= (long)g.B * ntl * ny) return;
+  const int yc = a.y0 + (int)(n % ny);
+  const long r = n / ny;
+  const int t = tlo + (int)(r % ntl), b = (int)(r / ntl);
+  double be[NT];
+  series_coeffs<NT>(sp.ay, yc, be);
+  const double* __restrict__ rb = a.RC + swih_rc(g, 0, b, t, yc + sp.ry + 1);
+  const double* __restrict__ ra = a.RC + swih_rc(g, 0, b, t, yc - sp.ry);
+  double* __restrict__ out = a.R + swih_rcc(g, b, yc, t);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) s = fma(be[j], rb[i * NT + j] - ra[i * NT + j], s);
+    out[i] = s;
+  }
+  out[NT] = rb[0] - ra[0];
+}
+
+template <int NT>
+__device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
+  constexpr int IG = sweep_ig<NT>();           // x terms per load unit
+  constexpr int NU = (NT + IG - 1) / IG;       // load units per row
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const int q = vb % a.ncomb;
+  int r = vb / a.ncomb;
+  const int sg = r % a.nseg;
+  r /= a.nseg;
+  const int ch = r % a.nch;
+  const int grp = r / a.nch;
+  const int ny = a.y1 - a.y0 + 1, rx = sp.rx, ry = sp.ry, h = 2 * ry + 1;
   const int Mq = q < ny ? (ny - q + h - 1) / h : 0;  // centre rows of comb q
-  const int m0 = sg * S;
+  const int m0 = sg * a.S;
   if (m0 >= Mq) return;  // uniform over the block
-  const int cnt = min(S, Mq - m0);
+  const int cnt = min(a.S, Mq - m0);
+  const int b0 = grp * a.bpg, b1 = min(b0 + a.bpg, g.B);
+  const int xs = a.x0 + ch * a.cw, cwc = min(a.cw, a.x1 - xs + 1), xe = xs + cwc - 1;
+  // Waves over tiles: tiles ta.. (nl of them) then, in the two-range form,
+  // the right-edge tiles tr...  A column X >= 1 of tile t = (X - 1) / 64 is
+  // thread 64 w + (X - 1) % 64 of wave w.
+  const int ta = (max(xs - rx, 1) - 1) >> 6;
+  const int lastR = (xe + rx) >> 6;  // tile of the last right edge xe + rx + 1
+  const int lastL = a.two ? (max(xe - rx, 1) - 1) >> 6 : lastR;
+  const int nl = a.two ? lastL - ta + 1 : a.nt;
+  const int tr = a.two ? (xs + rx) >> 6 : ta + nl;
+  const int nV = 64 * a.nt;
+  const int tid = (int)threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tx = wv < nl ? ta + wv : tr + (wv - nl);  // the wave's tile
+  // a batch launch may have more waves than this item's tiles
+  const bool live = wv < a.nt, on = live && tx <= (wv < nl ? lastL : lastR);
+  const int X = 64 * tx + 1 + (tid & 63);
+  // LDS index of a left edge / right edge column (>= 1)
+  auto col_left = [&](int Xc) { return 64 * (((Xc - 1) >> 6) - ta) + ((Xc - 1) & 63); };
+  auto col_right = [&](int Xc) {
+    return a.two ? 64 * (nl + ((Xc - 1) >> 6) - tr) + ((Xc - 1) & 63) : col_left(Xc);
+  };
+  const int ycb = a.y0 + q + m0 * h;  // first centre row of the segment
+  const int Ya0 = ycb - ry;
+  const int TY = g.TY;
   __syncthreads();  // LDS reuse across virtual blocks of one block
   extern __shared__ double sm[];
-  double* Gb = sm;                          // [2][NG][2][nvpad]
-  double* R = sm + 2 * NG * 2 * nvpad;      // [S][NT][ntl_max]
-  double* BE = R + (size_t)S * NT * ntl_max;  // [S][NT]
-  double* Nb = BE + (size_t)S * NT;         // [2][nvpad] pixel counts per column
-  double* Rn = Nb + 2 * nvpad;              // [S][ntl_max] count-plane carries
-  const int xa = x0 + chunk * cw;
-  const int cwc = min(cw, x1 - xa + 1);
-  const bool contig = 2 * rx + 1 <= cwc;
-  const int nV = contig ? cwc + 2 * rx + 1 : 2 * cwc;
-  const int tid = threadIdx.x;
-  const int tlo = tile_of(xa - rx), ntl = tile_of(xa + cwc + rx) - tlo + 1;
-  const int ycb = y0 + q + m0 * h;  // first centre row of the segment
-  // beta of every centre row of the segment
-  for (int mm = tid; mm < cnt; mm += blockDim.x) {
+  double* Gb = sm;                                  // [2][3][nV]: G+, G-, N
+  double* BE = sm + 6 * nV;                         // [S][NT]: beta of the members
+  int64_t* acc = (int64_t*)(BE + (size_t)a.S * NT);  // [S][cw]
+  for (int mm = tid; mm < cnt; mm += (int)blockDim.x) {
     double be[NT];
     series_coeffs<NT>(sp.ay, ycb + mm * h, be);
 #pragma unroll
     for (int j = 0; j < NT; ++j) BE[mm * NT + j] = be[j];
   }
-  __syncthreads();
-  // row carries: R[mm][i][t] = sum_j beta_j (RC_ij[yb] - RC_ij[ya]) for this bin
-  for (int it = tid; it < cnt * NT * ntl; it += blockDim.x) {
-    const int mm = it / (NT * ntl);
-    const int rem = it - mm * (NT * ntl);
-    const int i = rem / ntl, t = rem - (rem / ntl) * ntl;
-    const int ya = ycb + mm * h - ry, yb = ya + h;
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int p = i * NT + j;
-      acc = fma(BE[mm * NT + j], gp.RC[swih_rc(g, p, b, tlo + t, yb)] - gp.RC[swih_rc(g, p, b, tlo + t, ya)],
-                acc);
-    }
-    R[(mm * NT + i) * ntl_max + t] = acc;
-    if (i == 0)
-      Rn[mm * ntl_max + t] = gp.RC[swih_rc(g, 0, b, tlo + t, yb)] - gp.RC[swih_rc(g, 0, b, tlo + t, ya)];
-  }
-  CI ci;
-  ci.init(tid, nV, nvpad, xa, rx, cwc, contig);
-  double ap[NI], am[NI];
-  int tX[NI];
-  bool x0col[NI];
-  const float* lpi[NI];
-  const int64_t rs = g.row_stride;
-#pragma unroll
-  for (int ii = 0; ii < NI; ++ii) {
-    const int X = ci.X[ii];
-    ap[ii] = series_coeff(sp.ax, max(X - rx - 1, 0), ci.i[ii]);
-    am[ii] = series_coeff(sp.ax, X + rx, ci.i[ii]);
-    tX[ii] = tile_of(X) - tlo;
-    x0col[ii] = X == 0;  // column X = 0 is not stored (zero)
-    lpi[ii] = gp.L + swih_base(g, ci.i[ii] * NT, b) + swih_xoff(g, x0col[ii] ? 1 : X);
-  }
-  // the segment's first top row
-  float prev[NI][NT];
-#pragma unroll
-  for (int ii = 0; ii < NI; ++ii)
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-      prev[ii][j] = ci.ok[ii] ? lpi[ii][(size_t)(ycb - ry) * rs + (size_t)j * 64] : 0.0f;
-  const bool win = tid < cwc;
-  const int xc = xa + tid;
-  const int i1 = tid, i2 = contig ? tid + 2 * rx + 1 : cwc + tid;
+  if (tid < cwc)
+    for (int mm = 0; mm < cnt; ++mm) acc[mm * a.cw + tid] = 0;
+  double ap[NT], am[NT];
+  series_coeffs<NT>(sp.ax, max(X - rx - 1, 0), ap);
+  series_coeffs<NT>(sp.ax, X + rx, am);
+  // the column's loads: plane (i, j) of bin b at row Y is at
+  // base(i, b) + Y row_stride + j 64 + the column's offset
+  const char* __restrict__ colp = (const char*)a.planes + swih_xoff(g, X) * 4;
+  const int64_t ibstride = (int64_t)g.B * g.NTX * g.tile_stride * 4;  // bytes from x term i to i + 1
   const double inv_mass = 1.0 / sp.mass;
-  const float tb = a.tmpl[b];
-  const int mw = x1 - x0 + 1;
-  __syncthreads();
-  for (int mm = 0; mm < cnt; ++mm) {
-    const int yc = ycb + mm * h;
-    const int Ya = yc - ry, Yb = Ya + h;
-    const int c0 = first_cross(Ya, g.TY);
-    const int ncross = c0 < Yb ? (Yb - 1 - c0) / g.TY + 1 : 0;
-    double* Gp = Gb + (mm & 1) * NG * 2 * nvpad;
-    double* Np = Nb + (mm & 1) * nvpad;
-    double be[NT];
+  const int xw = xs + tid;  // this thread's window centre (tid < cwc)
+  const int iXb = col_right(xw + rx + 1), iXa = xw - rx > 0 ? col_left(xw - rx) : -1;
+  // an opening row that closes a band adds nothing and is not read
+  auto reads = [&](const SweepEv& e) { return on && (e.type != kEvOpen || e.Y % TY != 0); };
+  auto load = [&](float (&d)[IG * NT], const SweepEv& e) {
+    if (!reads(e)) return;
+    const int64_t row = (int64_t)(e.k * IG) * ibstride +
+                        ((int64_t)e.b * g.NTX * g.tile_stride + (int64_t)e.Y * g.row_stride) * 4;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) be[j] = uniform(BE[mm * NT + j]);
-    if (ci.slot >= 0) {
-      double gplus = 0.0, gminus = 0.0;
+    for (int ii = 0; ii < IG; ++ii) {
+      if (e.k * IG + ii >= NT) break;
+      const char* p = colp + (row + (int64_t)ii * ibstride);
 #pragma unroll
-      for (int ii = 0; ii < NI; ++ii) {
-        if (!ci.ok[ii]) break;
-        const int i = ci.i[ii];
-        float lb[NT];
+      for (int j = 0; j < NT; ++j) d[ii * NT + j] = *(const float*)(p + j * 256);
+    }
+  };
+  auto advance = [&](const SweepEv& e) {
+    if (e.k + 1 < NU) {
+      SweepEv n = e;
+      n.k = e.k + 1;
+      return n;
+    }
+    return sweep_next(e, cnt, b1, h, TY, Ya0);
+  };
+  double gp = 0.0, gm = 0.0, gn = 0.0;   // the member's G+, G-, N
+  double op = 0.0, om = 0.0, on_ = 0.0;  // the next member's opening sums
+  int par = 0;                           // LDS buffer parity
+  // contract unit e of d; at the end of a boundary row, the member's window phase
+  auto process = [&](const float (&d)[IG * NT], const SweepEv& e) {
+    const bool next = e.type == kEvBound && e.mm + 1 < cnt;
+    const bool withL = e.Y % TY != 0;  // as an opening row
+    if (e.k == 0 && (e.type == kEvOpen || next)) op = om = on_ = 0.0;
+    if (on) {
+      double be[NT], bn[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) lb[j] = lpi[ii][(size_t)Yb * rs + (size_t)j * 64];
-        double vl = 0.0, nl = (double)lb[0] - (double)prev[ii][0];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lb[j] - (double)prev[ii][j], vl);
-        for (int c = 0; c < ncross; ++c) {
-          float lc[NT];
-#pragma unroll
-          for (int j = 0; j < NT; ++j)
-            lc[j] = lpi[ii][(size_t)(c0 + c * g.TY) * rs + (size_t)j * 64];
-#pragma unroll
-          for (int j = 0; j < NT; ++j) vl = fma(be[j], (double)lc[j], vl);
-          nl += (double)lc[0];
-        }
-        // slot 0's first item is term 0 of its column: the column's pixel count
-        if (ii == 0 && ci.slot == 0)
-          Np[ci.xi[0]] = Rn[mm * ntl_max + tX[0]] + (x0col[0] ? 0.0 : nl);
-        const double v = R[(mm * NT + i) * ntl_max + tX[ii]] + (x0col[ii] ? 0.0 : vl);
-        if (ci.single) {
-          Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[ii]] = fma(ap[ii], v, 0.0);
-          Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[ii]] = fma(am[ii], v, 0.0);
-        } else {
-          gplus = fma(ap[ii], v, gplus);
-          gminus = fma(am[ii], v, gminus);
-        }
-#pragma unroll
-        for (int j = 0; j < NT; ++j) prev[ii][j] = lb[j];
+      for (int j = 0; j < NT; ++j) {
+        be[j] = uniform(BE[e.mm * NT + j]);
+        bn[j] = next ? uniform(BE[(e.mm + 1) * NT + j]) : 0.0;
       }
-      if (!ci.single) {
-        Gp[(ci.slot * 2 + 0) * nvpad + ci.xi[0]] = gplus;
-        Gp[(ci.slot * 2 + 1) * nvpad + ci.xi[0]] = gminus;
+      if (e.type != kEvOpen || withL) {
+        sweep_unit<NT, IG>(d, e.type == kEvOpen ? kEvOpen : e.type, next && withL, be, bn, e.k * IG,
+                           ap, am, gp, gm, op, om);
+        if (e.k == 0) {
+          const double lv = (double)d[0];
+          if (e.type != kEvOpen) gn += lv;
+          if (e.type == kEvOpen || (next && withL)) on_ = lv;
+        }
       }
     }
-    __syncthreads();
-    if (win) {
-      double hh = 0.0;
+    if (e.k != NU - 1) return;
+    if (e.type == kEvOpen) {
+      gp = -op;
+      gm = -om;
+      gn = -on_;
+    } else if (e.type == kEvBound) {
+      if (on) {
+        // the member's contracted row carries (uniform over the wave)
+        const double* __restrict__ R = a.R + swih_rcc(g, e.b, ycb + e.mm * h, tx);
 #pragma unroll
-      for (int qg = 0; qg < NG; ++qg)
-        hh += Gp[(qg * 2 + 0) * nvpad + i2] - Gp[(qg * 2 + 1) * nvpad + i1];
-      if (Np[i2] - Np[i1] != 0.0)
-        atomicAdd((unsigned long long*)&a.acc[(size_t)(yc - y0) * mw + (xc - x0)],
-                  (unsigned long long)bc_term(hh * inv_mass, tb));
+        for (int i = 0; i < NT; ++i) {
+          const double ri = R[i];
+          gp = fma(ap[i], ri, gp);
+          gm = fma(am[i], ri, gm);
+        }
+        gn += R[NT];
+      }
+      double* Gp = Gb + par * 3 * nV;
+      if (live) {
+        Gp[tid] = gp;
+        Gp[nV + tid] = gm;
+        Gp[2 * nV + tid] = gn;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      if (tid < cwc) {
+        const double hp = Gp[iXb], cp = Gp[2 * nV + iXb];
+        const double hm = iXa >= 0 ? Gp[nV + iXa] : 0.0, cm = iXa >= 0 ? Gp[2 * nV + iXa] : 0.0;
+        if (cp - cm != 0.0) acc[e.mm * a.cw + tid] += bc_term((hp - hm) * inv_mass, a.tmpl[e.b]);
+      }
+      par ^= 1;
+      gp = -op;
+      gm = -om;
+      gn = -on_;
+    }
+  };
+  __syncthreads();  // BE ready
+  SweepEv e0;
+  e0.b = b0;
+  e0.mm = 0;
+  e0.Y = e0.Ya = Ya0;
+  e0.type = kEvOpen;
+  e0.k = 0;
+  float dA[IG * NT], dB[IG * NT];
+  load(dA, e0);
+  for (;;) {
+    const SweepEv e1 = advance(e0);
+    if (e1.type != kEvEnd) load(dB, e1);
+    process(dA, e0);
+    if (e1.type == kEvEnd) break;
+    e0 = advance(e1);
+    if (e0.type != kEvEnd) load(dA, e0);
+    process(dB, e1);
+    if (e0.type == kEvEnd) break;
+  }
+  if (tid < cwc) {
+    const int mw = a.x1 - a.x0 + 1;
+    for (int mm = 0; mm < cnt; ++mm) {
+      const size_t o = (size_t)(ycb + mm * h - a.y0) * mw + (xw - a.x0);
+      const int64_t v = acc[mm * a.cw + tid];
+      if (a.ngroups == 1) a.map[o] = bc_value(v);
+      else atomicAdd((unsigned long long*)&a.acc[o], (unsigned long long)v);
     }
   }
 }
 
-// Map from the accumulator of match_gauss_comb; the accumulator is left zero.
+// Map from the accumulator of a sweep with several bin groups; the
+// accumulator is left zero.
 __device__ __forceinline__ void match_gauss_fin(const MatchArgs& a, int vb) {
   const int mw = a.x1 - a.x0 + 1;
   const long n = (long)mw * (a.y1 - a.y0 + 1);
@@ -699,11 +626,31 @@ __global__ __launch_bounds__(1024) void k_one(A a) {
   BODY(a, (int)blockIdx.x);
 }
 
-// The comb map with seven or fewer series terms fits 64 registers, so two of
-// its 15-wave blocks share a compute unit: twice the loads in flight.
-template <class A, void (*BODY)(const A&, int)>
-__global__ __launch_bounds__(1024, 8) void k_one_w8(A a) {
-  BODY(a, (int)blockIdx.x);
+// A single map's sweep: one block per item, renumbered so that each XCD
+// (workgroups go to the 8 XCDs round robin) runs a contiguous range of items,
+// i.e. the combs of one (bin group, chunk, segment) together, and the band-
+// closing rows they share stay in that XCD's L2.  Up to 170 registers: three
+// waves per SIMD, one block of twelve waves per compute unit.
+template <int NT>
+__global__ __launch_bounds__(768, 3) void k_sweep(MatchArgs a) {
+  const int n = (int)gridDim.x, base = n >> 3, rem = n & 7;
+  const int x = (int)blockIdx.x & 7, k = (int)blockIdx.x >> 3;
+  match_gauss_sweep<NT>(a, x * base + (x < rem ? x : rem) + k);
+}
+
+// The batched sweep, with the register budget of k_sweep.
+template <void (*BODY)(const MatchArgs&, int)>
+__global__ __launch_bounds__(768, 3) void k_many_sweep(const MatchArgs* __restrict__ items,
+                                                       const int32_t* __restrict__ prefix, int n) {
+  const int total = prefix[n];
+  for (int vb = (int)blockIdx.x; vb < total; vb += (int)gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= vb) lo = mid; else hi = mid - 1;
+    }
+    BODY(items[lo], vb - prefix[lo]);
+  }
 }
 
 template <class A, void (*BODY)(const A&, int)>
@@ -730,13 +677,6 @@ hipError_t run_one(const A& a, const Launch& ml, hipStream_t s) {
 }
 
 template <class A, void (*BODY)(const A&, int)>
-hipError_t run_one_w8(const A& a, const Launch& ml, hipStream_t s) {
-  hipLaunchKernelGGL((k_one_w8<A, BODY>), dim3((unsigned)ml.blocks), dim3((unsigned)ml.threads),
-                     ml.lds, s, a);
-  return hipGetLastError();
-}
-
-template <class A, void (*BODY)(const A&, int)>
 hipError_t run_many(const A* items, const int32_t* prefix, int n, unsigned grid, const Launch& ml,
                     hipStream_t s) {
   hipLaunchKernelGGL((k_many<A, BODY>), dim3(grid), dim3((unsigned)ml.threads), ml.lds, s, items,
@@ -746,10 +686,24 @@ hipError_t run_many(const A* items, const int32_t* prefix, int n, unsigned grid,
 
 template <int K> constexpr void (*int_match)(const MatchArgs&, int) = match_int<K>;
 template <int K> constexpr void (*int_query)(const QueryArgs&, int) = query_int<K>;
-template <int NT> constexpr void (*gauss_match)(const MatchArgs&, int) = match_gauss<NT, gauss_slots(NT)>;
+template <int NT> constexpr void (*gauss_match)(const MatchArgs&, int) = match_gauss_sweep<NT>;
+template <int NT> constexpr void (*gauss_rcc)(const MatchArgs&, int) = rc_contract<NT>;
 template <int NT> constexpr void (*gauss_query)(const QueryArgs&, int) = query_gauss<NT>;
 
 // switch over kernel kind (and Gaussian term count) calling CALL(body)
+#define SWIH_NT_CASES(CALL)          \
+  switch (nt) {                      \
+    case 3: return CALL(3);          \
+    case 5: return CALL(5);          \
+    case 7: return CALL(7);          \
+    case 9: return CALL(9);          \
+    case 11: return CALL(11);        \
+    case 13: return CALL(13);        \
+    case 15: return CALL(15);        \
+    case 17: return CALL(17);        \
+    default: return hipErrorInvalidValue; \
+  }
+
 #define SWIH_BODY_CASES(CALL)                 \
   switch (kind) {                             \
     case 0: return CALL(SWIH_I(0));           \
@@ -770,14 +724,22 @@ template <int NT> constexpr void (*gauss_query)(const QueryArgs&, int) = query_g
     default: return hipErrorInvalidValue;     \
   }
 
-hipError_t match_one(int kind, int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
-#define SWIH_I(K) int_match<K>
-#define SWIH_G(NT) gauss_match<NT>
-#define SWIH_C(B) run_one<MatchArgs, B>(a, ml, s)
-  SWIH_BODY_CASES(SWIH_C)
-#undef SWIH_C
-#undef SWIH_G
-#undef SWIH_I
+// Integer-kernel maps; Gaussian maps go through the sweep launches.
+hipError_t match_one(int kind, const MatchArgs& a, const Launch& ml, hipStream_t s) {
+  switch (kind) {
+    case 0: return run_one<MatchArgs, int_match<0>>(a, ml, s);
+    case 1: return run_one<MatchArgs, int_match<1>>(a, ml, s);
+    case 2: return run_one<MatchArgs, int_match<2>>(a, ml, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <void (*BODY)(const MatchArgs&, int)>
+hipError_t run_many_sweep(const MatchArgs* items, const int32_t* prefix, int n, unsigned grid,
+                          const Launch& ml, hipStream_t s) {
+  hipLaunchKernelGGL(k_many_sweep<BODY>, dim3(grid), dim3((unsigned)ml.threads), ml.lds, s, items,
+                     prefix, n);
+  return hipGetLastError();
 }
 
 hipError_t match_many(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix, int n,
@@ -785,7 +747,17 @@ hipError_t match_many(int kind, int nt, const MatchArgs* jobs, const int32_t* pr
 #define SWIH_I(K) int_match<K>
 #define SWIH_G(NT) gauss_match<NT>
 #define SWIH_C(B) run_many<MatchArgs, B>(jobs, prefix, n, grid, ml, s)
-  SWIH_BODY_CASES(SWIH_C)
+#define SWIH_CG(NT) run_many_sweep<gauss_match<NT>>(jobs, prefix, n, grid, ml, s)
+  if (kind == 3) {
+    SWIH_NT_CASES(SWIH_CG)
+  }
+  switch (kind) {
+    case 0: return SWIH_C(SWIH_I(0));
+    case 1: return SWIH_C(SWIH_I(1));
+    case 2: return SWIH_C(SWIH_I(2));
+    default: return hipErrorInvalidValue;
+  }
+#undef SWIH_CG
 #undef SWIH_C
 #undef SWIH_G
 #undef SWIH_I
@@ -814,6 +786,121 @@ hipError_t query_many(int kind, int nt, const QueryArgs* jobs, const int32_t* pr
 
 }  // namespace
 
+namespace {
+
+constexpr int kSweepMaxTiles = 12;     // waves of a sweep block: 768 threads
+constexpr int kSweepBatchS = 16;       // members per segment in batches
+constexpr size_t kLdsMax = 160 * 1024;
+
+size_t sweep_lds(int nt, int S, int NT, int cw) {
+  return sizeof(double) * (6 * 64 * (size_t)nt + (size_t)S * NT) + sizeof(int64_t) * (size_t)S * cw;
+}
+
+// Tiles (waves) a chunk of window centres [xs, xe] needs: one contiguous range
+// from the first left edge to the last right edge, or (two) the left-edge
+// tiles and the right-edge tiles apart.
+int sweep_tiles(int xs, int xe, int rx, bool two) {
+  const int ta = (std::max(xs - rx, 1) - 1) >> 6, tb = (xe + rx) >> 6;
+  if (!two) return tb - ta + 1;
+  const int tla = (std::max(xe - rx, 1) - 1) >> 6, trb = (xs + rx) >> 6;
+  return (tla - ta + 1) + (tb - trb + 1);
+}
+
+// Column chunks: the split with the fewest tile reads whose chunks all fit a block.
+void sweep_chunks(int x0, int nx, int rx, MatchArgs& a, int& two) {
+  long best = -1;
+  for (int t = 0; t < 2; ++t) {
+    for (int nch = 1; nch <= nx; ++nch) {
+      const int cw = (nx + nch - 1) / nch, n = (nx + cw - 1) / cw;
+      int nt = 0;
+      for (int c = 0; c < n; ++c) {
+        const int xs = x0 + c * cw, xe = std::min(xs + cw - 1, x0 + nx - 1);
+        nt = std::max(nt, sweep_tiles(xs, xe, rx, t == 1));
+      }
+      if (nt > kSweepMaxTiles) continue;
+      const long cost = (long)n * nt;
+      if (best < 0 || cost < best) {
+        best = cost;
+        a.nch = n;
+        a.cw = cw;
+        a.nt = nt;
+        two = t;
+      }
+      break;  // more chunks only add overlap
+    }
+  }
+}
+
+int device_cus() {
+  static int cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+}  // namespace
+
+// Plan of a Gaussian comb sweep over the centre rectangle: chunks, combs,
+// segments and bin groups, and the launch shape.  cus == 0: the batch form
+// (one bin group, segments of up to kSweepBatchS members).  Otherwise the
+// split that minimises a model of the time on `cus` compute units: rounds of
+// blocks times the work of one block (bins x tiles x rows read, crossings
+// counted at a quarter since neighbouring combs share them in L2), with a
+// small charge for the accumulator pass of several bin groups.
+static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int ny, int cus,
+                       MatchArgs& a, Launch& ml) {
+  int two = 0;
+  sweep_chunks(x0, nx, sp.rx, a, two);
+  a.two = two;
+  const int h = 2 * sp.ry + 1;
+  a.ncomb = std::min(h, ny);
+  const int Mq = (ny + h - 1) / h;
+  auto smax = [&](int S) {
+    while (S > 1 && sweep_lds(a.nt, S, NT, a.cw) > kLdsMax) --S;
+    return S;
+  };
+  if (cus <= 0) {
+    a.S = smax(std::min(Mq, kSweepBatchS));
+    a.nseg = (Mq + a.S - 1) / a.S;
+    a.ngroups = 1;
+    a.bpg = B;
+  } else {
+    const int Slim = smax(Mq);
+    const int bpc0 = std::max(1, 12 / a.nt);  // three waves per SIMD (register budget)
+    double best = -1.0;
+    for (int bpg = B; bpg >= 1; bpg = bpg > 1 ? (bpg + 1) / 2 : 0) {
+      const int ng = (B + bpg - 1) / bpg;
+      for (int nseg = (Mq + Slim - 1) / Slim; nseg <= Mq; ++nseg) {
+        const int S = (Mq + nseg - 1) / nseg;
+        const size_t lds = sweep_lds(a.nt, S, NT, a.cw);
+        const int bpc = std::max(1, std::min(bpc0, (int)(kLdsMax / lds)));
+        const long items = (long)ng * a.nch * nseg * a.ncomb;
+        const long rounds = (items + (long)cus * bpc - 1) / ((long)cus * bpc);
+        const double rows = S + 1 + 0.25 * S * (double)(h - 1) / 64.0;
+        const double t = (double)rounds * bpc * bpg * a.nt * rows * (ng > 1 ? 1.05 : 1.0);
+        if (best < 0 || t < best * 0.999) {
+          best = t;
+          a.S = S;
+          a.nseg = nseg;
+          a.ngroups = ng;
+          a.bpg = bpg;
+        }
+        if (S == 1) break;
+      }
+      if (bpg == 1) break;
+    }
+  }
+  ml.blocks = a.ngroups * a.nch * a.nseg * a.ncomb;
+  ml.threads = 64 * a.nt;
+  ml.lds = sweep_lds(a.nt, a.S, NT, a.cw);
+}
+
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                 const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0, int32_t x1,
                 int32_t y1, float* map, MatchArgs& a, Launch& ml) {
@@ -838,31 +925,16 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
     ml.lds = 0;
     return;
   }
-  // Gaussian: threads over (slot, plane column) (the split of ColItems); cw
-  // centres per block, as many as fit 1024 threads
-  const int NT = L.g.nI, NG = gauss_slots(NT);
-  const int span = 2 * sp.rx + 1;
-  int maxV = 512;
-  while (gauss_map_threads(NT, maxV) > 1024) --maxV;
-  int cw, nV;
-  if (span <= maxV / 2) {  // one contiguous column range: nV = cw + span
-    const int cwmax = maxV - span;
-    const int nch = (nx + cwmax - 1) / cwmax;
-    cw = (nx + nch - 1) / nch;
-    nV = cw + span;
-  } else {                 // two column segments of cw each
-    cw = nx < maxV / 2 ? nx : maxV / 2;
-    nV = 2 * cw;
-  }
-  a.cw = cw;
-  a.nvpad = (nV + 63) / 64 * 64;
-  a.ntl_max = (cw + span + 63) / 64 + 2;  // tile columns one block can touch
-  a.nbx = (nx + cw - 1) / cw;
-  ml.blocks = a.nbx * ny;
-  // every chunk's nV is at most the first chunk's, so its thread count serves all
-  ml.threads = gauss_map_threads(NT, nV);
-  ml.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)L.g.B * NT * a.ntl_max +
-                             (size_t)2 * a.nvpad + (size_t)L.g.B * a.ntl_max);
+  // Gaussian: the comb sweep, one bin group, segments of up to kSweepBatchS
+  // members (the form batches use; a single map picks its own split).
+  a.R = (double*)(sb + L.off_R);
+  sweep_plan(sp, L.g.B, L.g.nI, x0, nx, ny, 0, a, ml);
+}
+
+int32_t rc_contract_blocks(const MatchArgs& a) {
+  const int tlo = (std::max(a.x0 - a.sp.rx, 1) - 1) >> 6, thi = (a.x1 + a.sp.rx) >> 6;
+  const long n = (long)a.g.B * (thi - tlo + 1) * (a.y1 - a.y0 + 1);
+  return (int32_t)((n + 255) / 256);
 }
 
 void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
@@ -907,26 +979,40 @@ hipError_t launch_query_batch(int kind, int nt, const QueryArgs* jobs, const int
 
 namespace {
 
-template <int NT> constexpr void (*gauss_comb)(const MatchArgs&, int) = match_gauss_comb<NT, gauss_slots(NT)>;
 constexpr void (*gauss_fin)(const MatchArgs&, int) = match_gauss_fin;
 
-hipError_t comb_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
+template <int NT>
+hipError_t run_sweep(const MatchArgs& a, const Launch& ml, hipStream_t s) {
+  hipLaunchKernelGGL(k_sweep<NT>, dim3((unsigned)ml.blocks), dim3((unsigned)ml.threads), ml.lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t rcc_one(int nt, const MatchArgs& a, const Launch& rl, hipStream_t s) {
+#define SWIH_C(NT) run_one<MatchArgs, gauss_rcc<NT>>(a, rl, s)
+  SWIH_NT_CASES(SWIH_C)
+#undef SWIH_C
+}
+
+hipError_t rcc_many(int nt, const MatchArgs* jobs, const int32_t* prefix, int n, unsigned grid,
+                    const Launch& rl, hipStream_t s) {
+#define SWIH_C(NT) run_many<MatchArgs, gauss_rcc<NT>>(jobs, prefix, n, grid, rl, s)
+  SWIH_NT_CASES(SWIH_C)
+#undef SWIH_C
+}
+
+hipError_t sweep_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
   switch (nt) {
-    case 3: return run_one_w8<MatchArgs, gauss_comb<3>>(a, ml, s);
-    case 5: return run_one_w8<MatchArgs, gauss_comb<5>>(a, ml, s);
-    case 7: return run_one_w8<MatchArgs, gauss_comb<7>>(a, ml, s);
-    case 9: return run_one<MatchArgs, gauss_comb<9>>(a, ml, s);
-    case 11: return run_one<MatchArgs, gauss_comb<11>>(a, ml, s);
-    case 13: return run_one<MatchArgs, gauss_comb<13>>(a, ml, s);
-    case 15: return run_one<MatchArgs, gauss_comb<15>>(a, ml, s);
-    case 17: return run_one<MatchArgs, gauss_comb<17>>(a, ml, s);
+    case 3: return run_sweep<3>(a, ml, s);
+    case 5: return run_sweep<5>(a, ml, s);
+    case 7: return run_sweep<7>(a, ml, s);
+    case 9: return run_sweep<9>(a, ml, s);
+    case 11: return run_sweep<11>(a, ml, s);
+    case 13: return run_sweep<13>(a, ml, s);
+    case 15: return run_sweep<15>(a, ml, s);
+    case 17: return run_sweep<17>(a, ml, s);
     default: return hipErrorInvalidValue;
   }
 }
-
-// Comb segments of kCombSteps centre rows: S + 1 boundary rows per S rows
-// (16 measured best on the 512x512 scene among 4, 8 and 16).
-constexpr int kCombSteps = 16;
 
 }  // namespace
 
@@ -937,30 +1023,35 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   MatchArgs a;
   Launch ml;
   match_args(L, sp, set, ws, tmpl, tmpl_raw, x0, y0, x1, y1, map, a, ml);
-  if (ml.lds > 160 * 1024) return hipErrorInvalidValue;
-  const int h = 2 * sp.ry + 1, ny = y1 - y0 + 1;
-  if (!L.g.gauss || ny < 2 * h) return match_one(sp.kind, L.g.nI, a, ml, s);
-  // Gaussian over many centre rows: the comb form (same values, fewer plane
-  // reads), then the accumulator to the map.
-  const int NT = L.g.nI, NG = gauss_slots(NT);
-  const int S = kCombSteps;
-  const int mmax = (ny + h - 1) / h;
+  if (!L.g.gauss) return match_one(sp.kind, a, ml, s);
+  // Gaussian: the split that fills this device; several bin groups add
+  // into the set's accumulator, which the finalising pass turns into the map.
+  sweep_plan(sp, L.g.B, L.g.nI, x0, x1 - x0 + 1, y1 - y0 + 1, device_cus(), a, ml);
+  if (ml.lds > kLdsMax) return hipErrorInvalidValue;
   a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
-  a.comb_steps = S;
-  a.comb_segs = (mmax + S - 1) / S;
-  Launch cl;
-  cl.threads = ml.threads;
-  cl.blocks = L.g.B * a.nbx * a.comb_segs * h;
-  cl.lds = sizeof(double) * ((size_t)2 * NG * 2 * a.nvpad + (size_t)S * NT * a.ntl_max +
-                             (size_t)S * NT + (size_t)2 * a.nvpad + (size_t)S * a.ntl_max);
-  if (cl.lds > 160 * 1024) return match_one(sp.kind, L.g.nI, a, ml, s);
-  hipError_t e = comb_one(NT, a, cl, s);
+  Launch rl;
+  rl.blocks = rc_contract_blocks(a);
+  rl.threads = 256;
+  rl.lds = 0;
+  hipError_t e = rcc_one(L.g.nI, a, rl, s);
   if (e != hipSuccess) return e;
+  e = sweep_one(L.g.nI, a, ml, s);
+  if (e != hipSuccess || a.ngroups == 1) return e;
   Launch fl;
   fl.threads = 256;
-  fl.blocks = (int32_t)(((long)(x1 - x0 + 1) * ny + 255) / 256);
+  fl.blocks = (int32_t)(((long)(x1 - x0 + 1) * (y1 - y0 + 1) + 255) / 256);
   fl.lds = 0;
   return run_one<MatchArgs, gauss_fin>(a, fl, s);
+}
+
+hipError_t launch_rcc_batch(int nt, const MatchArgs* jobs, const int32_t* prefix, int njobs,
+                            int32_t total, int grid, hipStream_t s) {
+  if (njobs <= 0 || total <= 0) return hipSuccess;
+  Launch rl;
+  rl.blocks = total;
+  rl.threads = 256;
+  rl.lds = 0;
+  return rcc_many(nt, jobs, prefix, njobs, (unsigned)(total < grid ? total : grid), rl, s);
 }
 
 hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix,
