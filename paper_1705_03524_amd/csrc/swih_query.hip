@@ -356,47 +356,74 @@ __host__ __device__ constexpr int sweep_ig() {
   return NT <= 5 ? NT : (NT <= 7 ? 4 : (NT <= 11 ? 2 : 1));
 }
 
-// One load unit's contraction: terms [i0, i0 + IG) of the row in d.
+// One load unit's contraction: x terms [K IG, K IG + IG) of the row in d.
 //   kEvOpen   (op, om) += alpha+-_i sum_j beta_j L_ij (beta of the member it opens)
 //   kEvCross  (gp, gm) += alpha+-_i sum_j beta_j L_ij (beta of its member)
-//   kEvBound  the same into (gp, gm), and, if `next`, into (op, om) with bn
+//   kEvBound  the same into (gp, gm), and, if NEXT, into (op, om) with bn
 //             (beta of the member it opens).
-// Rows that close a band (withL false) open a member with nothing: their L
-// cancels against the crossing at the same row.
-template <int NT, int IG>
-__device__ __forceinline__ void sweep_unit(const float (&d)[IG * NT], int type, bool next,
-                                           const double* be, const double* bn, int i0,
-                                           const double (&ap)[NT], const double (&am)[NT],
-                                           double& gp, double& gm, double& op, double& om) {
+// Rows that close a band open a member with nothing (their L cancels against
+// the crossing at the same row), so a boundary row that closes a band has
+// NEXT false and an opening row that closes one is not contracted at all.
+template <int NT, int IG, int K, int TYPE, bool NEXT>
+__device__ __forceinline__ void sweep_unit(const float (&d)[IG * NT], const double (&be)[NT],
+                                           const double (&bn)[NT], const double (&ap)[NT],
+                                           const double (&am)[NT], double& gp, double& gm,
+                                           double& op, double& om, double& gn, double& on) {
 #pragma unroll
   for (int ii = 0; ii < IG; ++ii) {
+    constexpr int i0 = K * IG;
     const int i = i0 + ii;
     if (i >= NT) break;
     double s = 0.0, sn = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const double lv = (double)d[ii * NT + j];
-      if (type == kEvOpen) {
+      if (TYPE == kEvOpen) {
         sn = fma(be[j], lv, sn);
       } else {
         s = fma(be[j], lv, s);
-        if (next) sn = fma(bn[j], lv, sn);
+        if (NEXT) sn = fma(bn[j], lv, sn);
       }
     }
-    if (type == kEvOpen || next) {
+    if (TYPE == kEvOpen || NEXT) {
       op = fma(ap[i], sn, op);
       om = fma(am[i], sn, om);
     }
-    if (type != kEvOpen) {
+    if (TYPE != kEvOpen) {
       gp = fma(ap[i], s, gp);
       gm = fma(am[i], s, gm);
     }
   }
+  if (K == 0) {  // term (0, 0): the pixel count
+    const double lv = (double)d[0];
+    if (TYPE != kEvOpen) gn += lv;
+    if (TYPE == kEvOpen || NEXT) on = lv;
+  }
 }
 
-// Row carries contracted at the centre rows of a rectangle: one thread per
-// (bin, tile column, centre row), centre rows fastest (their RC rows are
-// consecutive in memory).  Writes swih_rcc entries.
+// The contraction of unit k of an event of kind type (uniform over the block).
+template <int NT, int IG, int K>
+__device__ __forceinline__ void sweep_unit_k(const float (&d)[IG * NT], int type, bool next,
+                                             const double (&be)[NT], const double (&bn)[NT],
+                                             const double (&ap)[NT], const double (&am)[NT],
+                                             double& gp, double& gm, double& op, double& om,
+                                             double& gn, double& on) {
+  if (type == kEvOpen)
+    sweep_unit<NT, IG, K, kEvOpen, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+  else if (type == kEvCross)
+    sweep_unit<NT, IG, K, kEvCross, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+  else if (next)
+    sweep_unit<NT, IG, K, kEvBound, true>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+  else
+    sweep_unit<NT, IG, K, kEvBound, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+}
+
+// Row carries contracted at the centre rows of a rectangle (swih_rcc): eight
+// lanes per (bin, tile column, centre row), lane i < NT the x term i, lane NT
+// the count plane (terms beyond 7 handled by the same lanes in turn); centre
+// rows next to each other read neighbouring RC rows.
+constexpr int kRccLanes = 8;
+
 template <int NT>
 __device__ __forceinline__ void rc_contract(const MatchArgs& a, int vb) {
   const SwihGeom& g = a.g;
@@ -405,23 +432,42 @@ __device__ __forceinline__ void rc_contract(const MatchArgs& a, int vb) {
   const int tlo = (max(a.x0 - sp.rx, 1) - 1) >> 6, thi = (a.x1 + sp.rx) >> 6;
   const int ntl = thi - tlo + 1;
   const long n = (long)vb * 256 + threadIdx.x;
-  if (n >= (long)g.B * ntl * ny) return;
-  const int yc = a.y0 + (int)(n % ny);
-  const long r = n / ny;
+  const int li = (int)(n % kRccLanes);
+  const long w = n / kRccLanes;
+  if (w >= (long)g.B * ntl * ny) return;
+  const int yc = a.y0 + (int)(w % ny);
+  const long r = w / ny;
   const int t = tlo + (int)(r % ntl), b = (int)(r / ntl);
-  double be[NT];
-  series_coeffs<NT>(sp.ay, yc, be);
   const double* __restrict__ rb = a.RC + swih_rc(g, 0, b, t, yc + sp.ry + 1);
   const double* __restrict__ ra = a.RC + swih_rc(g, 0, b, t, yc - sp.ry);
   double* __restrict__ out = a.R + swih_rcc(g, b, yc, t);
+  double be[NT];
+  series_coeffs<NT>(sp.ay, yc, be);
+  for (int i = li; i <= NT; i += kRccLanes) {
+    if (i == NT) {
+      out[NT] = rb[0] - ra[0];
+    } else {
+      double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) s = fma(be[j], rb[i * NT + j] - ra[i * NT + j], s);
-    out[i] = s;
+      for (int j = 0; j < NT; ++j) s = fma(be[j], rb[i * NT + j] - ra[i * NT + j], s);
+      out[i] = s;
+    }
   }
-  out[NT] = rb[0] - ra[0];
+}
+
+// Unit k of a row, K from KLO up (compile-time paths for every unit).
+template <int NT, int IG, int KLO, int NU>
+__device__ __forceinline__ void sweep_dispatch(int k, const float (&d)[IG * NT], int type, bool next,
+                                               const double (&be)[NT], const double (&bn)[NT],
+                                               const double (&ap)[NT], const double (&am)[NT],
+                                               double& gp, double& gm, double& op, double& om,
+                                               double& gn, double& on) {
+  if constexpr (KLO < NU) {
+    if (k == KLO)
+      sweep_unit_k<NT, IG, KLO>(d, type, next, be, bn, ap, am, gp, gm, op, om, gn, on);
+    else
+      sweep_dispatch<NT, IG, KLO + 1, NU>(k, d, type, next, be, bn, ap, am, gp, gm, op, om, gn, on);
+  }
 }
 
 template <int NT>
@@ -513,28 +559,24 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   };
   double gp = 0.0, gm = 0.0, gn = 0.0;   // the member's G+, G-, N
   double op = 0.0, om = 0.0, on_ = 0.0;  // the next member's opening sums
+  double bcur[NT], bnxt[NT];             // beta of the current and the next member
   int par = 0;                           // LDS buffer parity
+  auto beta = [&](double (&bv)[NT], int mm) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) bv[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
+  };
   // contract unit e of d; at the end of a boundary row, the member's window phase
   auto process = [&](const float (&d)[IG * NT], const SweepEv& e) {
-    const bool next = e.type == kEvBound && e.mm + 1 < cnt;
     const bool withL = e.Y % TY != 0;  // as an opening row
-    if (e.k == 0 && (e.type == kEvOpen || next)) op = om = on_ = 0.0;
-    if (on) {
-      double be[NT], bn[NT];
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        be[j] = uniform(BE[e.mm * NT + j]);
-        bn[j] = next ? uniform(BE[(e.mm + 1) * NT + j]) : 0.0;
-      }
-      if (e.type != kEvOpen || withL) {
-        sweep_unit<NT, IG>(d, e.type == kEvOpen ? kEvOpen : e.type, next && withL, be, bn, e.k * IG,
-                           ap, am, gp, gm, op, om);
-        if (e.k == 0) {
-          const double lv = (double)d[0];
-          if (e.type != kEvOpen) gn += lv;
-          if (e.type == kEvOpen || (next && withL)) on_ = lv;
-        }
-      }
+    const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
+    if (e.k == 0 && e.type == kEvOpen) {
+      beta(bcur, 0);
+      beta(bnxt, 1);
+    }
+    if (e.k == 0 && (e.type == kEvOpen || e.type == kEvBound)) op = om = on_ = 0.0;
+    if (on && (e.type != kEvOpen || withL)) {
+      static_assert(NU <= 17, "load units");
+      sweep_dispatch<NT, IG, 0, NU>(e.k, d, e.type, next, bcur, bnxt, ap, am, gp, gm, op, om, gn, on_);
     }
     if (e.k != NU - 1) return;
     if (e.type == kEvOpen) {
@@ -571,6 +613,9 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
       gp = -op;
       gm = -om;
       gn = -on_;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bcur[j] = bnxt[j];
+      beta(bnxt, e.mm + 2);
     }
   };
   __syncthreads();  // BE ready
@@ -933,7 +978,7 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
 
 int32_t rc_contract_blocks(const MatchArgs& a) {
   const int tlo = (std::max(a.x0 - a.sp.rx, 1) - 1) >> 6, thi = (a.x1 + a.sp.rx) >> 6;
-  const long n = (long)a.g.B * (thi - tlo + 1) * (a.y1 - a.y0 + 1);
+  const long n = (long)a.g.B * (thi - tlo + 1) * (a.y1 - a.y0 + 1) * kRccLanes;
   return (int32_t)((n + 255) / 256);
 }
 
