@@ -120,8 +120,6 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     off += swih_align256((int64_t)g.nJ * H * 4) + swih_align256((int64_t)g.nJ * H * 8);
     L.off_acc = off;
     off += swih_align256((int64_t)H * W * 8);
-    L.off_R = off;
-    off += swih_align256((int64_t)g.B * H * g.NTX * (g.nI + 1) * 8);
   }
   // build scratch (carries), inside the set so that sets never share it
   const int64_t esz = gauss ? 8 : 4;
@@ -473,9 +471,7 @@ struct BatchHeader {
   int32_t nunits, nq, nm;
   int32_t total[4];   // build-stage virtual blocks
   Launch ql, ml;      // query / map launch shapes (blocks = total virtual blocks)
-  int32_t rtotal;     // Gaussian maps: blocks of the row-carry contraction
-  int32_t pad;
-  int64_t off_units, off_uprefix, off_q, off_qprefix, off_m, off_mprefix, off_rprefix, bytes;
+  int64_t off_units, off_uprefix, off_q, off_qprefix, off_m, off_mprefix, bytes;
 };
 
 int32_t frame_units(const swih_config* cfg, const swih_frame_desc& f) {
@@ -504,8 +500,6 @@ BatchHeader table_layout(int32_t kind, int32_t nunits, int32_t nq, int32_t nm) {
   h.off_m = off;
   off += swih_align256((int64_t)nm * mb);
   h.off_mprefix = off;
-  off += swih_align256((int64_t)(nm + 1) * sizeof(int32_t));
-  h.off_rprefix = off;
   off += swih_align256((int64_t)(nm + 1) * sizeof(int32_t));
   h.bytes = off;
   h.nunits = nunits;
@@ -675,7 +669,6 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
   // maps
   MatchArgs* ma = (MatchArgs*)(tb + h.off_m);
   int32_t* mpre = (int32_t*)(tb + h.off_mprefix);
-  int32_t* rpre = (int32_t*)(tb + h.off_rprefix);
   for (int m = 0; m < nmatches; ++m) {
     const swih_match_desc& md = matches[m];
     if (md.frame < 0 || md.frame >= nframes) return SWIH_ERR_INVALID;
@@ -723,12 +716,10 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
       match_args(layouts[md.frame], sp, gauss ? md.scale_idx : 0, (const char*)fd.d_ws,
                  md.d_template, md.d_template_raw, r.x0, r.y0, r.x1, r.y1, md.d_map, ma[m], ml);
     mpre[m + 1] = mpre[m] + (empty ? 0 : ml.blocks);
-    rpre[m + 1] = rpre[m] + (empty || !gauss ? 0 : rc_contract_blocks(ma[m]));
     if (ml.threads > h.ml.threads) h.ml.threads = ml.threads;
     if (ml.lds > h.ml.lds) h.ml.lds = ml.lds;
   }
   h.ml.blocks = mpre[nmatches];
-  h.rtotal = rpre[nmatches];
   if (h.ml.threads == 0) h.ml.threads = 256;
   if (h.ml.lds > 160 * 1024) return SWIH_ERR_UNSUPPORTED;
   memcpy(tb, &h, sizeof(h));
@@ -799,10 +790,6 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream) {
                                   kBatchGrid, (hipStream_t)stream) == hipSuccess
                ? SWIH_OK
                : SWIH_ERR_HIP;
-  if (h->kind == SWIH_GAUSSIAN &&
-      launch_rcc_batch(h->nt, (const MatchArgs*)(db + h->off_m), (const int32_t*)(db + h->off_rprefix),
-                       h->nm, h->rtotal, kBatchGrid, (hipStream_t)stream) != hipSuccess)
-    return SWIH_ERR_HIP;
   return launch_match_batch(h->kind, h->nt, (const MatchArgs*)(db + h->off_m),
                             (const int32_t*)(db + h->off_mprefix), h->nm, h->ml, kBatchGrid,
                             (hipStream_t)stream) == hipSuccess

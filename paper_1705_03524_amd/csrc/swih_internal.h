@@ -85,7 +85,6 @@ struct MatchArgs {
   ScaleParams sp;
   const void* planes;      // uint32 planes or float tile-local planes
   const double* RC;        // Gaussian row carries
-  double* R;               // Gaussian: row carries contracted at the centre rows (swih_rcc)
   const float* tmpl;       // normalised template, or null
   const uint32_t* tmpl_raw;  // exact template (integer kernels), or null
   float* map;
@@ -127,12 +126,6 @@ hipError_t launch_query_batch(int kind, int nt, const QueryArgs* jobs, const int
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                 const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0, int32_t x1,
                 int32_t y1, float* map, MatchArgs& a, Launch& ml);
-
-// Gaussian maps: blocks of the row-carry contraction that precedes a map
-// (rc_contract), and its batched launch (prefix: exclusive block prefixes).
-int32_t rc_contract_blocks(const MatchArgs& a);
-hipError_t launch_rcc_batch(int nt, const MatchArgs* jobs, const int32_t* prefix, int njobs,
-                            int32_t total, int grid, hipStream_t stream);
 
 // One batched map launch over njobs (same kernel); ml: total virtual blocks,
 // the largest block size and LDS of any job.

@@ -84,14 +84,6 @@ __host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int p, int b, int 
   return (((int64_t)b * g.NTX + tx) * (g.H + 1) + Y) * g.nP + p;
 }
 
-// Element offset of the contracted row carries of bin b, centre row yc and tile
-// column tx (Gaussian maps): [b][yc][tx][i], i = 0..nI-1 the x terms'
-//   R_i = sum_j beta_j(yc) (RC_ij[tx][yc + ry + 1] - RC_ij[tx][yc - ry]),
-// then i = nI the count-plane difference RC_00[tx][yc + ry + 1] - RC_00[tx][yc - ry].
-__host__ __device__ inline int64_t swih_rcc(const SwihGeom& g, int b, int yc, int tx) {
-  return (((int64_t)b * g.H + yc) * g.NTX + tx) * (g.nI + 1);
-}
-
 // Byte offsets inside one workspace.  All regions are 256-byte aligned.
 struct SwihLayout {
   SwihGeom g;
@@ -103,7 +95,6 @@ struct SwihLayout {
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
   int64_t off_acc;       // int64 [H * W] map accumulator of the map sweep (Gaussian)
-  int64_t off_R;         // double [B][H][NTX][nI + 1] row carries contracted at each centre row (Gaussian)
   // build scratch (carries) of the set
   int64_t off_scratch;
   int64_t off_z;         // [nJ][B][NTY][NTX*64] band column sums -> carries (integer)

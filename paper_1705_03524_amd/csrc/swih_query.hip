@@ -283,11 +283,11 @@ __device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q 
 //   P[Yb] - P[Ya] = L[Yb] - L[Ya] + sum_c L[c] + RC[Yb] - RC[Ya],
 // c the band-closing rows (multiples of TY) in [Ya, Yb).  When Ya itself
 // closes a band its L cancels against the crossing at c = Ya, so both drop.
-// The row-carry part does not depend on the column inside a tile: rc_contract
-// tabulates R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) per (bin, centre row,
-// tile) before the sweep (swih_rcc).  A column's V is then a sum of row
-// events, each contracted with beta(yc): the opening row Ya (minus), the
-// crossings, the boundary row Yb (plus), and R once per member.
+// A column's V is a sum of row events, each contracted with beta(yc): the
+// opening row Ya (minus), the crossings, the boundary row Yb (plus).  The
+// row-carry part R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) is the same for
+// every column of a tile: lanes 0..NT of the tile's wave contract one x term
+// each (lane NT the count plane) and the wave broadcasts the results.
 //
 // Combs.  The centre rows yc = y0 + q + m h (h the window height) of comb q
 // follow one another so that member m's boundary row is member m + 1's
@@ -418,43 +418,6 @@ __device__ __forceinline__ void sweep_unit_k(const float (&d)[IG * NT], int type
     sweep_unit<NT, IG, K, kEvBound, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
 }
 
-// Row carries contracted at the centre rows of a rectangle (swih_rcc): eight
-// lanes per (bin, tile column, centre row), lane i < NT the x term i, lane NT
-// the count plane (terms beyond 7 handled by the same lanes in turn); centre
-// rows next to each other read neighbouring RC rows.
-constexpr int kRccLanes = 8;
-
-template <int NT>
-__device__ __forceinline__ void rc_contract(const MatchArgs& a, int vb) {
-  const SwihGeom& g = a.g;
-  const ScaleParams& sp = a.sp;
-  const int ny = a.y1 - a.y0 + 1;
-  const int tlo = (max(a.x0 - sp.rx, 1) - 1) >> 6, thi = (a.x1 + sp.rx) >> 6;
-  const int ntl = thi - tlo + 1;
-  const long n = (long)vb * 256 + threadIdx.x;
-  const int li = (int)(n % kRccLanes);
-  const long w = n / kRccLanes;
-  if (w >= (long)g.B * ntl * ny) return;
-  const int yc = a.y0 + (int)(w % ny);
-  const long r = w / ny;
-  const int t = tlo + (int)(r % ntl), b = (int)(r / ntl);
-  const double* __restrict__ rb = a.RC + swih_rc(g, 0, b, t, yc + sp.ry + 1);
-  const double* __restrict__ ra = a.RC + swih_rc(g, 0, b, t, yc - sp.ry);
-  double* __restrict__ out = a.R + swih_rcc(g, b, yc, t);
-  double be[NT];
-  series_coeffs<NT>(sp.ay, yc, be);
-  for (int i = li; i <= NT; i += kRccLanes) {
-    if (i == NT) {
-      out[NT] = rb[0] - ra[0];
-    } else {
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) s = fma(be[j], rb[i * NT + j] - ra[i * NT + j], s);
-      out[i] = s;
-    }
-  }
-}
-
 // Unit k of a row, K from KLO up (compile-time paths for every unit).
 template <int NT, int IG, int KLO, int NU>
 __device__ __forceinline__ void sweep_dispatch(int k, const float (&d)[IG * NT], int type, bool next,
@@ -523,7 +486,10 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) BE[mm * NT + j] = be[j];
   }
-  if (tid < cwc)
+  // one bin per item: each member's terms go straight to the set's
+  // accumulator, so no LDS accumulator bounds the segment
+  const bool direct = a.ngroups > 1 && a.bpg == 1;
+  if (tid < cwc && !direct)
     for (int mm = 0; mm < cnt; ++mm) acc[mm * a.cw + tid] = 0;
   double ap[NT], am[NT];
   series_coeffs<NT>(sp.ax, max(X - rx - 1, 0), ap);
@@ -537,7 +503,14 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const int iXb = col_right(xw + rx + 1), iXa = xw - rx > 0 ? col_left(xw - rx) : -1;
   // an opening row that closes a band adds nothing and is not read
   auto reads = [&](const SweepEv& e) { return on && (e.type != kEvOpen || e.Y % TY != 0); };
-  auto load = [&](float (&d)[IG * NT], const SweepEv& e) {
+  const int lane = tid & 63;
+  auto load = [&](float (&d)[IG * NT], double (&rc)[NT], const SweepEv& e) {
+    if (on && e.k == 0 && e.type != kEvCross && lane <= NT) {
+      // this lane's x term of the tile's row carries at the row (lane NT: term (0, 0))
+      const double* __restrict__ q = a.RC + swih_rc(g, lane < NT ? lane * NT : 0, e.b, tx, e.Y);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) rc[j] = (lane < NT || j == 0) ? q[j] : 0.0;
+    }
     if (!reads(e)) return;
     const int64_t row = (int64_t)(e.k * IG) * ibstride +
                         ((int64_t)e.b * g.NTX * g.tile_stride + (int64_t)e.Y * g.row_stride) * 4;
@@ -566,12 +539,30 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     for (int j = 0; j < NT; ++j) bv[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
   };
   // contract unit e of d; at the end of a boundary row, the member's window phase
-  auto process = [&](const float (&d)[IG * NT], const SweepEv& e) {
+  double qprev = 0.0, rmine = 0.0;  // lanes 0..NT: beta(m) RC[Ya(m)] and the member's R
+  auto process = [&](const float (&d)[IG * NT], const double (&rc)[NT], const SweepEv& e) {
     const bool withL = e.Y % TY != 0;  // as an opening row
     const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
     if (e.k == 0 && e.type == kEvOpen) {
       beta(bcur, 0);
       beta(bnxt, 1);
+    }
+    if (on && e.k == 0 && e.type != kEvCross && lane <= NT) {
+      // row carries: sum_j beta_j RC_ij at this row, for the member it closes
+      // (minus the same at its opening row) and for the one it opens
+      double sc = 0.0, sn = 0.0;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        sc = fma(bcur[j], rc[j], sc);
+        sn = fma(bnxt[j], rc[j], sn);
+      }
+      if (lane == NT) sc = sn = rc[0];
+      if (e.type == kEvBound) {
+        rmine = sc - qprev;
+        qprev = sn;
+      } else {
+        qprev = sc;
+      }
     }
     if (e.k == 0 && (e.type == kEvOpen || e.type == kEvBound)) op = om = on_ = 0.0;
     if (on && (e.type != kEvOpen || withL)) {
@@ -585,15 +576,14 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
       gn = -on_;
     } else if (e.type == kEvBound) {
       if (on) {
-        // the member's contracted row carries (uniform over the wave)
-        const double* __restrict__ R = a.R + swih_rcc(g, e.b, ycb + e.mm * h, tx);
+        // the member's contracted row carries, broadcast from lanes 0..NT
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-          const double ri = R[i];
+          const double ri = readlane(rmine, i);
           gp = fma(ap[i], ri, gp);
           gm = fma(am[i], ri, gm);
         }
-        gn += R[NT];
+        gn += readlane(rmine, NT);
       }
       double* Gp = Gb + par * 3 * nV;
       if (live) {
@@ -607,7 +597,13 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
       if (tid < cwc) {
         const double hp = Gp[iXb], cp = Gp[2 * nV + iXb];
         const double hm = iXa >= 0 ? Gp[nV + iXa] : 0.0, cm = iXa >= 0 ? Gp[2 * nV + iXa] : 0.0;
-        if (cp - cm != 0.0) acc[e.mm * a.cw + tid] += bc_term((hp - hm) * inv_mass, a.tmpl[e.b]);
+        const int64_t v = cp - cm != 0.0 ? bc_term((hp - hm) * inv_mass, a.tmpl[e.b]) : 0;
+        if (!direct) {
+          acc[e.mm * a.cw + tid] += v;
+        } else if (v != 0) {
+          const size_t o = (size_t)(ycb + e.mm * h - a.y0) * (a.x1 - a.x0 + 1) + (xw - a.x0);
+          atomicAdd((unsigned long long*)&a.acc[o], (unsigned long long)v);
+        }
       }
       par ^= 1;
       gp = -op;
@@ -625,19 +621,32 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   e0.Y = e0.Ya = Ya0;
   e0.type = kEvOpen;
   e0.k = 0;
+  // Row-carry values arrive with unit 0 of a row and are used when that unit
+  // is contracted.  With two or more units per row the unit in between
+  // belongs to the previous row's tail, so one buffer serves; with one unit
+  // per row the two register buffers alternate with the plane buffers.
+  constexpr bool kTwoRC = NU == 1;
   float dA[IG * NT], dB[IG * NT];
-  load(dA, e0);
+  double rA[NT], rB[kTwoRC ? NT : 1];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) rA[j] = 0.0;
+  rB[0] = 0.0;
+  auto& rcB = [&]() -> double (&)[NT] {
+    if constexpr (kTwoRC) return rB;
+    else return rA;
+  }();
+  load(dA, rA, e0);
   for (;;) {
     const SweepEv e1 = advance(e0);
-    if (e1.type != kEvEnd) load(dB, e1);
-    process(dA, e0);
+    if (e1.type != kEvEnd) load(dB, rcB, e1);
+    process(dA, rA, e0);
     if (e1.type == kEvEnd) break;
     e0 = advance(e1);
-    if (e0.type != kEvEnd) load(dA, e0);
-    process(dB, e1);
+    if (e0.type != kEvEnd) load(dA, rA, e0);
+    process(dB, rcB, e1);
     if (e0.type == kEvEnd) break;
   }
-  if (tid < cwc) {
+  if (tid < cwc && !direct) {
     const int mw = a.x1 - a.x0 + 1;
     for (int mm = 0; mm < cnt; ++mm) {
       const size_t o = (size_t)(ycb + mm * h - a.y0) * mw + (xw - a.x0);
@@ -732,7 +741,6 @@ hipError_t run_many(const A* items, const int32_t* prefix, int n, unsigned grid,
 template <int K> constexpr void (*int_match)(const MatchArgs&, int) = match_int<K>;
 template <int K> constexpr void (*int_query)(const QueryArgs&, int) = query_int<K>;
 template <int NT> constexpr void (*gauss_match)(const MatchArgs&, int) = match_gauss_sweep<NT>;
-template <int NT> constexpr void (*gauss_rcc)(const MatchArgs&, int) = rc_contract<NT>;
 template <int NT> constexpr void (*gauss_query)(const QueryArgs&, int) = query_gauss<NT>;
 
 // switch over kernel kind (and Gaussian term count) calling CALL(body)
@@ -837,8 +845,12 @@ constexpr int kSweepMaxTiles = 12;     // waves of a sweep block: 768 threads
 constexpr int kSweepBatchS = 16;       // members per segment in batches
 constexpr size_t kLdsMax = 160 * 1024;
 
-size_t sweep_lds(int nt, int S, int NT, int cw) {
-  return sizeof(double) * (6 * 64 * (size_t)nt + (size_t)S * NT) + sizeof(int64_t) * (size_t)S * cw;
+// LDS of a sweep block: G+, G-, N double-buffered, beta of the members, and
+// (unless each item holds one bin of several groups) the (member, window)
+// accumulators.
+size_t sweep_lds(int nt, int S, int NT, int cw, bool direct) {
+  return sizeof(double) * (6 * 64 * (size_t)nt + (size_t)S * NT) +
+         (direct ? 0 : sizeof(int64_t) * (size_t)S * cw);
 }
 
 // Tiles (waves) a chunk of window centres [xs, xe] needs: one contiguous range
@@ -906,29 +918,31 @@ static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int
   const int h = 2 * sp.ry + 1;
   a.ncomb = std::min(h, ny);
   const int Mq = (ny + h - 1) / h;
-  auto smax = [&](int S) {
-    while (S > 1 && sweep_lds(a.nt, S, NT, a.cw) > kLdsMax) --S;
+  auto smax = [&](int S, bool direct) {
+    while (S > 1 && sweep_lds(a.nt, S, NT, a.cw, direct) > kLdsMax) --S;
     return S;
   };
   if (cus <= 0) {
-    a.S = smax(std::min(Mq, kSweepBatchS));
+    a.S = smax(std::min(Mq, kSweepBatchS), false);
     a.nseg = (Mq + a.S - 1) / a.S;
     a.ngroups = 1;
     a.bpg = B;
   } else {
-    const int Slim = smax(Mq);
     const int bpc0 = std::max(1, 12 / a.nt);  // three waves per SIMD (register budget)
     double best = -1.0;
     for (int bpg = B; bpg >= 1; bpg = bpg > 1 ? (bpg + 1) / 2 : 0) {
       const int ng = (B + bpg - 1) / bpg;
+      const bool direct = ng > 1 && bpg == 1;
+      const int Slim = smax(Mq, direct);
       for (int nseg = (Mq + Slim - 1) / Slim; nseg <= Mq; ++nseg) {
         const int S = (Mq + nseg - 1) / nseg;
-        const size_t lds = sweep_lds(a.nt, S, NT, a.cw);
+        const size_t lds = sweep_lds(a.nt, S, NT, a.cw, direct);
         const int bpc = std::max(1, std::min(bpc0, (int)(kLdsMax / lds)));
         const long items = (long)ng * a.nch * nseg * a.ncomb;
         const long rounds = (items + (long)cus * bpc - 1) / ((long)cus * bpc);
         const double rows = S + 1 + 0.25 * S * (double)(h - 1) / 64.0;
-        const double t = (double)rounds * bpc * bpg * a.nt * rows * (ng > 1 ? 1.05 : 1.0);
+        // several bin groups: the accumulator's read-modify-write traffic
+        const double t = (double)rounds * bpc * bpg * a.nt * rows * (ng > 1 ? 1.04 : 1.0);
         if (best < 0 || t < best * 0.999) {
           best = t;
           a.S = S;
@@ -943,7 +957,7 @@ static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int
   }
   ml.blocks = a.ngroups * a.nch * a.nseg * a.ncomb;
   ml.threads = 64 * a.nt;
-  ml.lds = sweep_lds(a.nt, a.S, NT, a.cw);
+  ml.lds = sweep_lds(a.nt, a.S, NT, a.cw, a.ngroups > 1 && a.bpg == 1);
 }
 
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
@@ -972,14 +986,7 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   }
   // Gaussian: the comb sweep, one bin group, segments of up to kSweepBatchS
   // members (the form batches use; a single map picks its own split).
-  a.R = (double*)(sb + L.off_R);
   sweep_plan(sp, L.g.B, L.g.nI, x0, nx, ny, 0, a, ml);
-}
-
-int32_t rc_contract_blocks(const MatchArgs& a) {
-  const int tlo = (std::max(a.x0 - a.sp.rx, 1) - 1) >> 6, thi = (a.x1 + a.sp.rx) >> 6;
-  const long n = (long)a.g.B * (thi - tlo + 1) * (a.y1 - a.y0 + 1) * kRccLanes;
-  return (int32_t)((n + 255) / 256);
 }
 
 void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
@@ -1032,19 +1039,6 @@ hipError_t run_sweep(const MatchArgs& a, const Launch& ml, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t rcc_one(int nt, const MatchArgs& a, const Launch& rl, hipStream_t s) {
-#define SWIH_C(NT) run_one<MatchArgs, gauss_rcc<NT>>(a, rl, s)
-  SWIH_NT_CASES(SWIH_C)
-#undef SWIH_C
-}
-
-hipError_t rcc_many(int nt, const MatchArgs* jobs, const int32_t* prefix, int n, unsigned grid,
-                    const Launch& rl, hipStream_t s) {
-#define SWIH_C(NT) run_many<MatchArgs, gauss_rcc<NT>>(jobs, prefix, n, grid, rl, s)
-  SWIH_NT_CASES(SWIH_C)
-#undef SWIH_C
-}
-
 hipError_t sweep_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s) {
   switch (nt) {
     case 3: return run_sweep<3>(a, ml, s);
@@ -1074,29 +1068,13 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   sweep_plan(sp, L.g.B, L.g.nI, x0, x1 - x0 + 1, y1 - y0 + 1, device_cus(), a, ml);
   if (ml.lds > kLdsMax) return hipErrorInvalidValue;
   a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
-  Launch rl;
-  rl.blocks = rc_contract_blocks(a);
-  rl.threads = 256;
-  rl.lds = 0;
-  hipError_t e = rcc_one(L.g.nI, a, rl, s);
-  if (e != hipSuccess) return e;
-  e = sweep_one(L.g.nI, a, ml, s);
+  hipError_t e = sweep_one(L.g.nI, a, ml, s);
   if (e != hipSuccess || a.ngroups == 1) return e;
   Launch fl;
   fl.threads = 256;
   fl.blocks = (int32_t)(((long)(x1 - x0 + 1) * (y1 - y0 + 1) + 255) / 256);
   fl.lds = 0;
   return run_one<MatchArgs, gauss_fin>(a, fl, s);
-}
-
-hipError_t launch_rcc_batch(int nt, const MatchArgs* jobs, const int32_t* prefix, int njobs,
-                            int32_t total, int grid, hipStream_t s) {
-  if (njobs <= 0 || total <= 0) return hipSuccess;
-  Launch rl;
-  rl.blocks = total;
-  rl.threads = 256;
-  rl.lds = 0;
-  return rcc_many(nt, jobs, prefix, njobs, (unsigned)(total < grid ? total : grid), rl, s);
 }
 
 hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix,
