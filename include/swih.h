@@ -52,7 +52,9 @@
  *
  * Memory and streams
  *   - Every pointer named d_* is a device pointer owned by the caller; the
- *     library never allocates, frees or keeps device memory between calls.
+ *     library never allocates, frees or keeps device memory between calls
+ *     (the one exception is the static scratch of swih_match_noalloc, which
+ *     comes with the code object when the library is loaded).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     All device work is enqueued asynchronously on it; no call synchronises
  *     the device or reads device memory on the host.
@@ -81,6 +83,7 @@ extern "C" {
 #define SWIH_ERR_WORKSPACE (-2)   /* workspace smaller than swih_workspace_bytes */
 #define SWIH_ERR_UNSUPPORTED (-3) /* valid request this kernel cannot serve */
 #define SWIH_ERR_HIP (-4)         /* a HIP launch or runtime call failed */
+#define SWIH_ERR_SCRATCH (-5)     /* swih_match_noalloc: more centres than its static scratch holds */
 
 typedef enum {
   SWIH_UNIFORM = 0,
@@ -198,6 +201,26 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
 int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
                int32_t width, int32_t scale_idx, const float* d_template,
                const uint32_t* d_template_raw, swih_rect centres, float* d_map, void* stream);
+
+/*
+ * swih_match for callers that cannot allocate device memory at the call (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Arguments, results and errors as swih_match; the map equals
+ * swih_match's bit for bit.  A SWIH_GAUSSIAN map whose launch plan splits the
+ * bins into several groups adds their sums into an integer accumulator: here
+ * that accumulator is a static array of the library, one per device, holding
+ * up to 4194304 centres (32 MiB), instead of the workspace's region.  The call
+ * clears the part it uses on `stream` first and allocates nothing.
+ *   SWIH_ERR_SCRATCH  a SWIH_GAUSSIAN rectangle of more than 4194304 centres.
+ * Every call on one device shares that device's array: calls whose Gaussian
+ * maps overlap in time on one device (other streams, other threads) race and
+ * give wrong maps; order them on one stream.  Other kernels use no scratch
+ * and behave exactly as swih_match.
+ */
+int swih_match_noalloc(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+                       int32_t width, int32_t scale_idx, const float* d_template,
+                       const uint32_t* d_template_raw, swih_rect centres, float* d_map,
+                       void* stream);
 
 /* ------------------------------------------------------------------------
  * Baselines the paper compares SWIH with (Sec. 3, Figs. 5 and 6).

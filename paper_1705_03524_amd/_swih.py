@@ -22,12 +22,13 @@ SERIES_KINDS = (GAUSSIAN, GAUSSIAN_SEP)
 # real-valued histograms (no exact integer outputs), one plane set per scale
 REAL_KINDS = (GAUSSIAN, GAUSSIAN_SEP, EXPONENTIAL)
 
-OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP = 0, -1, -2, -3, -4
+OK, ERR_INVALID, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP, ERR_SCRATCH = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_build_planes",
             "swih_query", "swih_match", "swih_batch_table_bytes", "swih_batch_plan",
             "swih_build_batch", "swih_query_batch", "swih_match_batch", "swih_gauss_terms",
-            "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match", "swih_argmax")
+            "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match", "swih_argmax",
+            "swih_match_noalloc")
 
 
 class SwihError(RuntimeError):
@@ -89,8 +90,10 @@ def load():
         f.restype = C.c_int
     lib.swih_query.argtypes = [cfgp, vp, sz, i32, i32, i32, vp, i32, vp, vp, vp]
     lib.swih_query.restype = C.c_int
-    lib.swih_match.argtypes = [cfgp, vp, sz, i32, i32, i32, vp, vp, _Rect, vp, vp]
-    lib.swih_match.restype = C.c_int
+    for name in ("swih_match", "swih_match_noalloc"):
+        f = getattr(lib, name)
+        f.argtypes = [cfgp, vp, sz, i32, i32, i32, vp, vp, _Rect, vp, vp]
+        f.restype = C.c_int
     lib.swih_batch_table_bytes.argtypes = [cfgp, C.POINTER(_FrameDesc), i32, i32, i32]
     lib.swih_batch_table_bytes.restype = C.c_int64
     lib.swih_batch_plan.argtypes = [cfgp, C.POINTER(_FrameDesc), i32, C.POINTER(_QueryDesc), i32,
@@ -219,6 +222,18 @@ def match(cfg: Config, ws, height: int, width: int, scale_idx: int, rect, out, t
                            _ptr(out), _stream(stream))
     if st != OK:
         raise SwihError(st, "swih_match")
+
+
+def match_noalloc(cfg: Config, ws, height: int, width: int, scale_idx: int, rect, out, template=None,
+                  template_raw=None, stream=None):
+    """swih_match_noalloc: swih_match whose Gaussian accumulator is the
+    library's static per-device scratch (nothing is allocated)."""
+    r = _Rect(*[int(v) for v in rect])
+    st = load().swih_match_noalloc(C.byref(cfg.c()), _ptr(ws), ws.numel() * ws.element_size(),
+                                   int(height), int(width), int(scale_idx), _ptr(template),
+                                   _ptr(template_raw), r, _ptr(out), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_match_noalloc")
 
 
 def cake_query(cfg: Config, ws, height: int, width: int, scale_idx: int, rings: int, centres, hist,

@@ -309,9 +309,14 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
              : SWIH_ERR_HIP;
 }
 
-int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+}  // extern "C"
+
+namespace {
+
+int match_impl(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
                int32_t width, int32_t scale_idx, const float* d_template,
-               const uint32_t* d_template_raw, swih_rect r, float* d_map, void* stream) {
+               const uint32_t* d_template_raw, swih_rect r, float* d_map, void* stream,
+               bool noalloc) {
   int st = check_config(cfg, height, width);
   if (st != SWIH_OK) return st;
   if (scale_idx < 0 || scale_idx >= cfg->nscales || !d_ws) return SWIH_ERR_INVALID;
@@ -323,6 +328,9 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
   if (r.x0 < rx || r.y0 < ry || r.x1 > width - 1 - rx || r.y1 > height - 1 - ry)
     return SWIH_ERR_INVALID;
   if (!d_map) return SWIH_ERR_INVALID;
+  if (noalloc && cfg->kernel == SWIH_GAUSSIAN &&
+      (int64_t)(r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1) > kNoallocCentres)
+    return SWIH_ERR_SCRATCH;
   SwihLayout L;
   make_layout(cfg, height, width, L);
   if ((int64_t)ws_bytes < L.total) return SWIH_ERR_WORKSPACE;
@@ -348,10 +356,33 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
     return exp_launch_match(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
   }
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
+  int64_t* acc = nullptr;
+  if (noalloc && cfg->kernel == SWIH_GAUSSIAN) {
+    acc = noalloc_scratch();
+    if (!acc) return SWIH_ERR_HIP;
+  }
   return launch_match(L, sp, set, (const char*)d_ws, d_template, d_template_raw, r.x0, r.y0, r.x1,
-                      r.y1, d_map, (hipStream_t)stream) == hipSuccess
+                      r.y1, d_map, (hipStream_t)stream, acc) == hipSuccess
              ? SWIH_OK
              : SWIH_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+               int32_t width, int32_t scale_idx, const float* d_template,
+               const uint32_t* d_template_raw, swih_rect r, float* d_map, void* stream) {
+  return match_impl(cfg, d_ws, ws_bytes, height, width, scale_idx, d_template, d_template_raw, r,
+                    d_map, stream, false);
+}
+
+int swih_match_noalloc(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
+                       int32_t width, int32_t scale_idx, const float* d_template,
+                       const uint32_t* d_template_raw, swih_rect r, float* d_map, void* stream) {
+  return match_impl(cfg, d_ws, ws_bytes, height, width, scale_idx, d_template, d_template_raw, r,
+                    d_map, stream, true);
 }
 
 }  // extern "C"
@@ -817,6 +848,7 @@ const char* swih_status_string(int status) {
     case SWIH_ERR_WORKSPACE: return "workspace too small";
     case SWIH_ERR_UNSUPPORTED: return "unsupported for this kernel";
     case SWIH_ERR_HIP: return "HIP launch failed";
+    case SWIH_ERR_SCRATCH: return "rectangle larger than the static scratch of swih_match_noalloc";
     default: return "unknown status";
   }
 }

@@ -132,9 +132,17 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
 hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix,
                               int njobs, const Launch& ml, int grid, hipStream_t stream);
 
+// acc: the integer accumulator of a Gaussian map with several bin groups;
+// null = the set's region of the workspace.
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
-                        int32_t x1, int32_t y1, float* map, hipStream_t stream);
+                        int32_t x1, int32_t y1, float* map, hipStream_t stream,
+                        int64_t* acc = nullptr);
+
+// The static scratch of swih_match_noalloc: centres it holds, and its device
+// address on the current device (looked up once per device; null on failure).
+constexpr int64_t kNoallocCentres = (int64_t)1 << 22;
+int64_t* noalloc_scratch();
 
 // ------------------------------------------------------------------------
 // Separable two-pass form of the Gaussian series (kernel SWIH_GAUSSIAN_SEP).

@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "swih_internal.h"
 #include "wave64.h"
@@ -1055,9 +1056,39 @@ hipError_t sweep_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s
 
 }  // namespace
 
+// Scratch of swih_match_noalloc: the integer accumulator of a Gaussian map
+// whose plan has several bin groups, kept with the code object on every
+// device the library runs on, so that the call allocates nothing.
+static __device__ __align__(256) int64_t scratch[kNoallocCentres];
+
+namespace {
+
+std::mutex g_scratch_mu;
+int64_t* g_scratch_ptr[64];  // device address of each device's copy
+
+__global__ void k_zero_i64(int64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+}  // namespace
+
+int64_t* noalloc_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = (int64_t*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
-                        int32_t x1, int32_t y1, float* map, hipStream_t s) {
+                        int32_t x1, int32_t y1, float* map, hipStream_t s, int64_t* acc) {
   if (x1 < x0 || y1 < y0) return hipSuccess;
   MatchArgs a;
   Launch ml;
@@ -1067,7 +1098,15 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   // into the set's accumulator, which the finalising pass turns into the map.
   sweep_plan(sp, L.g.B, L.g.nI, x0, x1 - x0 + 1, y1 - y0 + 1, device_cus(), a, ml);
   if (ml.lds > kLdsMax) return hipErrorInvalidValue;
-  a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
+  if (acc && a.ngroups > 1) {
+    // an outside accumulator must start at zero (the finalising pass leaves it so)
+    const int64_t n = (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);
+    hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256),
+                       0, s, acc, n);
+    a.acc = acc;
+  } else {
+    a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
+  }
   hipError_t e = sweep_one(L.g.nI, a, ml, s);
   if (e != hipSuccess || a.ngroups == 1) return e;
   Launch fl;
