@@ -209,7 +209,7 @@ int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
  * swih_match's bit for bit.  A SWIH_GAUSSIAN map whose launch plan splits the
  * bins into several groups adds their sums into an integer accumulator: here
  * that accumulator is a static array of the library, one per device, holding
- * up to 4194304 centres (32 MiB), instead of the workspace's region.  The call
+ * up to 4194304 centres (16 MiB), instead of the workspace's region.  The call
  * clears the part it uses on `stream` first and allocates nothing.
  *   SWIH_ERR_SCRATCH  a SWIH_GAUSSIAN rectangle of more than 4194304 centres.
  * Every call on one device shares that device's array: calls whose Gaussian

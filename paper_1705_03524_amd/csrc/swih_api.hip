@@ -119,7 +119,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     L.off_vq = off;  // int32 [H][nJ], then double [H][nJ]
     off += swih_align256((int64_t)g.nJ * H * 4) + swih_align256((int64_t)g.nJ * H * 8);
     L.off_acc = off;
-    off += swih_align256((int64_t)H * W * 8);
+    off += swih_align256((int64_t)H * W * 4);
   }
   // build scratch (carries), inside the set so that sets never share it
   const int64_t esz = gauss ? 8 : 4;
@@ -356,7 +356,7 @@ int match_impl(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
     return exp_launch_match(a, nb, (hipStream_t)stream) == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
   }
   const int set = cfg->kernel == SWIH_GAUSSIAN ? scale_idx : 0;
-  int64_t* acc = nullptr;
+  int32_t* acc = nullptr;
   if (noalloc && cfg->kernel == SWIH_GAUSSIAN) {
     acc = noalloc_scratch();
     if (!acc) return SWIH_ERR_HIP;

@@ -756,7 +756,7 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.uq = (int32_t*)(sb + L.off_uq);
     a.vq = (int32_t*)(sb + L.off_vq);
     a.vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
-    a.acc = (int64_t*)(sb + L.off_acc);
+    a.acc = (int32_t*)(sb + L.off_acc);
     a.nacc = (int64_t)g.H * g.W;
     a.ax = *ax;
     a.ay = *ay;

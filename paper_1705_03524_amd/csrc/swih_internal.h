@@ -46,7 +46,7 @@ struct BuildArgs {
   void* z;            // band column sums -> carry rows (integer kernels)
   void* T;            // row-segment sums -> row carries
   void* BT;           // tile totals -> tile-origin values
-  int64_t* acc;       // Gaussian: the map accumulator of the set, cleared by the build
+  int32_t* acc;       // Gaussian: the map accumulator of the set, cleared by the build
   int64_t nacc;
   int32_t agg_hist;   // integer kernels: aggregate by LDS histograms, a block per (band, tile)
   int32_t pad;
@@ -95,7 +95,7 @@ struct MatchArgs {
   int32_t ncomb, nseg, S;  // combs, segments per comb, members per segment
   int32_t ngroups, bpg;    // bin groups, bins per group
   int32_t two;             // 1: a block's waves cover the left-edge and the right-edge tiles apart
-  int64_t* acc;            // ngroups > 1: per-centre integer accumulator (zero between maps)
+  int32_t* acc;            // ngroups > 1: per-centre integer accumulator (zero between maps)
 };
 
 struct Launch {
@@ -137,12 +137,12 @@ hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
                         int32_t x1, int32_t y1, float* map, hipStream_t stream,
-                        int64_t* acc = nullptr);
+                        int32_t* acc = nullptr);
 
 // The static scratch of swih_match_noalloc: centres it holds, and its device
 // address on the current device (looked up once per device; null on failure).
 constexpr int64_t kNoallocCentres = (int64_t)1 << 22;
-int64_t* noalloc_scratch();
+int32_t* noalloc_scratch();
 
 // ------------------------------------------------------------------------
 // Separable two-pass form of the Gaussian series (kernel SWIH_GAUSSIAN_SEP).

@@ -94,7 +94,7 @@ struct SwihLayout {
   int64_t off_RC;        // double [B][NTX][H+1][nP], swih_rc     (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
-  int64_t off_acc;       // int64 [H * W] map accumulator of the map sweep (Gaussian)
+  int64_t off_acc;       // int32 [H * W] map accumulator of the map sweep (Gaussian)
   // build scratch (carries) of the set
   int64_t off_scratch;
   int64_t off_z;         // [nJ][B][NTY][NTX*64] band column sums -> carries (integer)

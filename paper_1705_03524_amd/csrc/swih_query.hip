@@ -251,17 +251,18 @@ __device__ __forceinline__ double uniform(double v) {
 }
 
 // A Gaussian map value is sum_b sqrt(p_b t_b).  Each bin's term is rounded to
-// a multiple of 2^-40 and the terms are added as integers: exact, so the sum
-// is the same whatever the order in which bins arrive (one block per bin and
-// integer atomics, or all bins in one thread); 2^-41 is far below the float
-// resolution of the result.
-constexpr double kBcScale = 1099511627776.0;  // 2^40
+// a multiple of 2^-29 and the terms are added as integers: exact, so the sum
+// is the same whatever the order in which bins arrive (bin groups and integer
+// atomics, or all bins in one block).  The sum is at most 1 (Cauchy-Schwarz;
+// the rounding of p and t moves it by ~1e-6), so it fits an int32 with room
+// to spare, and 2^-30 per bin is far below the float resolution of the result.
+constexpr double kBcScale = 536870912.0;  // 2^29
 
-__device__ __forceinline__ int64_t bc_term(double p, float t) {
-  return (int64_t)__builtin_rint(sqrt(fmax(p, 0.0) * fmax((double)t, 0.0)) * kBcScale);
+__device__ __forceinline__ int32_t bc_term(double p, float t) {
+  return (int32_t)__builtin_rint(sqrt(fmax(p, 0.0) * fmax((double)t, 0.0)) * kBcScale);
 }
 
-__device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q / kBcScale); }
+__device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q / kBcScale); }
 
 // Empty bins.  sqrt is not Lipschitz at 0: a bin with no pixel in the window
 // must give p_b = 0 exactly, or a rounding residue e of the float planes
@@ -296,7 +297,9 @@ __device__ __forceinline__ float bc_value(int64_t q) { return (float)((double)q 
 // each boundary row once and contracting it twice (with beta(yc_m) for the
 // member it closes and beta(yc_m+1) for the one it opens).
 //
-// Work item = (bin group, column chunk, segment, comb); a block has one wave
+// Work item = (bin group, segment, comb, column chunk), chunks fastest so that
+// the tiles two chunks share and the band-closing rows of neighbouring combs
+// are read close together (one XCD's L2, below); a block has one wave
 // per 64-column tile of its chunk (one thread per plane column, every weight
 // term of the column in that thread), loops over the group's bins and walks
 // the segment for each.  Rows are read in load units (IG x terms, all their
@@ -440,12 +443,12 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   constexpr int NU = (NT + IG - 1) / IG;       // load units per row
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
-  const int q = vb % a.ncomb;
-  int r = vb / a.ncomb;
+  const int ch = vb % a.nch;
+  int r = vb / a.nch;
+  const int q = r % a.ncomb;
+  r /= a.ncomb;
   const int sg = r % a.nseg;
-  r /= a.nseg;
-  const int ch = r % a.nch;
-  const int grp = r / a.nch;
+  const int grp = r / a.nseg;
   const int ny = a.y1 - a.y0 + 1, rx = sp.rx, ry = sp.ry, h = 2 * ry + 1;
   const int Mq = q < ny ? (ny - q + h - 1) / h : 0;  // centre rows of comb q
   const int m0 = sg * a.S;
@@ -480,7 +483,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   extern __shared__ double sm[];
   double* Gb = sm;                                  // [2][3][nV]: G+, G-, N
   double* BE = sm + 6 * nV;                         // [S][NT]: beta of the members
-  int64_t* acc = (int64_t*)(BE + (size_t)a.S * NT);  // [S][cw]
+  int32_t* acc = (int32_t*)(BE + (size_t)a.S * NT);  // [S][cw]
   for (int mm = tid; mm < cnt; mm += (int)blockDim.x) {
     double be[NT];
     series_coeffs<NT>(sp.ay, ycb + mm * h, be);
@@ -598,12 +601,12 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
       if (tid < cwc) {
         const double hp = Gp[iXb], cp = Gp[2 * nV + iXb];
         const double hm = iXa >= 0 ? Gp[nV + iXa] : 0.0, cm = iXa >= 0 ? Gp[2 * nV + iXa] : 0.0;
-        const int64_t v = cp - cm != 0.0 ? bc_term((hp - hm) * inv_mass, a.tmpl[e.b]) : 0;
+        const int32_t v = cp - cm != 0.0 ? bc_term((hp - hm) * inv_mass, a.tmpl[e.b]) : 0;
         if (!direct) {
           acc[e.mm * a.cw + tid] += v;
         } else if (v != 0) {
           const size_t o = (size_t)(ycb + e.mm * h - a.y0) * (a.x1 - a.x0 + 1) + (xw - a.x0);
-          atomicAdd((unsigned long long*)&a.acc[o], (unsigned long long)v);
+          atomicAdd((unsigned int*)&a.acc[o], (unsigned int)v);
         }
       }
       par ^= 1;
@@ -651,9 +654,9 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     const int mw = a.x1 - a.x0 + 1;
     for (int mm = 0; mm < cnt; ++mm) {
       const size_t o = (size_t)(ycb + mm * h - a.y0) * mw + (xw - a.x0);
-      const int64_t v = acc[mm * a.cw + tid];
+      const int32_t v = acc[mm * a.cw + tid];
       if (a.ngroups == 1) a.map[o] = bc_value(v);
-      else atomicAdd((unsigned long long*)&a.acc[o], (unsigned long long)v);
+      else atomicAdd((unsigned int*)&a.acc[o], (unsigned int)v);
     }
   }
 }
@@ -851,7 +854,7 @@ constexpr size_t kLdsMax = 160 * 1024;
 // accumulators.
 size_t sweep_lds(int nt, int S, int NT, int cw, bool direct) {
   return sizeof(double) * (6 * 64 * (size_t)nt + (size_t)S * NT) +
-         (direct ? 0 : sizeof(int64_t) * (size_t)S * cw);
+         (direct ? 0 : sizeof(int32_t) * (size_t)S * cw);
 }
 
 // Tiles (waves) a chunk of window centres [xs, xe] needs: one contiguous range
@@ -1059,14 +1062,14 @@ hipError_t sweep_one(int nt, const MatchArgs& a, const Launch& ml, hipStream_t s
 // Scratch of swih_match_noalloc: the integer accumulator of a Gaussian map
 // whose plan has several bin groups, kept with the code object on every
 // device the library runs on, so that the call allocates nothing.
-static __device__ __align__(256) int64_t scratch[kNoallocCentres];
+static __device__ __align__(256) int32_t scratch[kNoallocCentres];
 
 namespace {
 
 std::mutex g_scratch_mu;
-int64_t* g_scratch_ptr[64];  // device address of each device's copy
+int32_t* g_scratch_ptr[64];  // device address of each device's copy
 
-__global__ void k_zero_i64(int64_t* p, int64_t n) {
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -1074,21 +1077,21 @@ __global__ void k_zero_i64(int64_t* p, int64_t n) {
 
 }  // namespace
 
-int64_t* noalloc_scratch() {
+int32_t* noalloc_scratch() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   if (!g_scratch_ptr[dev]) {
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
-    g_scratch_ptr[dev] = (int64_t*)p;
+    g_scratch_ptr[dev] = (int32_t*)p;
   }
   return g_scratch_ptr[dev];
 }
 
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const float* tmpl, const uint32_t* tmpl_raw, int32_t x0, int32_t y0,
-                        int32_t x1, int32_t y1, float* map, hipStream_t s, int64_t* acc) {
+                        int32_t x1, int32_t y1, float* map, hipStream_t s, int32_t* acc) {
   if (x1 < x0 || y1 < y0) return hipSuccess;
   MatchArgs a;
   Launch ml;
@@ -1101,11 +1104,11 @@ hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, con
   if (acc && a.ngroups > 1) {
     // an outside accumulator must start at zero (the finalising pass leaves it so)
     const int64_t n = (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);
-    hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256),
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256),
                        0, s, acc, n);
     a.acc = acc;
   } else {
-    a.acc = (int64_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
+    a.acc = (int32_t*)(ws + (size_t)set * L.set_bytes + L.off_acc);
   }
   hipError_t e = sweep_one(L.g.nI, a, ml, s);
   if (e != hipSuccess || a.ngroups == 1) return e;
