@@ -187,22 +187,29 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_prefix, path=PROFILE_COUNTERS):
-    """HBM bytes per launch of a kernel from a committed counter summary
-    (scaled FETCH_SIZE + WRITE_SIZE), or None if the summary is missing or was
-    taken on different kernel sources."""
+def measured_traffic(prefixes, unit_prefix, path=PROFILE_COUNTERS):
+    """HBM bytes per launch of a phase from a committed counter summary
+    (scaled FETCH_SIZE + WRITE_SIZE): the bytes of every kernel whose name
+    starts with one of `prefixes`, over all its dispatches, divided by the
+    dispatches of the phase's main kernel (`unit_prefix`).  None if the
+    summary is missing or was taken on different kernel sources."""
     try:
         txt = open(path).read()
     except OSError:
         return None
     if kernel_source_hash() not in txt:
         return None
-    total = None
-    for line in txt.splitlines():  # every kernel of the phase (same dispatch count)
+    total, units = 0.0, 0
+    for line in txt.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) == 6 and cells[0].startswith(kernel_prefix):
-            total = (total or 0.0) + (float(cells[4]) + float(cells[5])) * 1e6
-    return total
+        if len(cells) != 6 or not cells[1].isdigit():
+            continue
+        n = int(cells[1])
+        if any(cells[0].startswith(p) for p in prefixes):
+            total += (float(cells[4]) + float(cells[5])) * 1e6 * n
+        if cells[0].startswith(unit_prefix):
+            units += n
+    return total / units if units else None
 
 
 def copy_calibration():
@@ -340,21 +347,23 @@ def run_multiscale(args):
     plane_bytes = 4 * T * B * (N + 1) * (N + 1)
     nsc = len(MS_SCALES)
     kernels = {
-        "build": {"kernel": "k_emit_gauss (Gaussian plane build, %d terms x %d bins, 2048x2048; "
+        "build": {"kernel": "emit_gauss (Gaussian plane build, %d terms x %d bins, 2048x2048; "
                             "average over the 5 scales)" % (T, B),
                   "alg": N * N + plane_bytes,
-                  "ms": sum(per["planes_%d" % w] for w in MS_SCALES) / nsc, "prefix": "k_emit_gauss<"},
-        "match": {"kernel": "k_match_gauss_comb + k_match_gauss_fin (Gaussian dense likelihood map, "
+                  "ms": sum(per["planes_%d" % w] for w in MS_SCALES) / nsc,
+                  "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
+        "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
                             "every valid centre; average over the 5 scales)",
                   "alg": plane_bytes + 4 * sum(nwin) / nsc,
-                  "ms": sum(per["match_%d" % w] for w in MS_SCALES) / nsc, "prefix": "k_match_gauss_"},
+                  "ms": sum(per["match_%d" % w] for w in MS_SCALES) / nsc,
+                  "prefixes": ("k_sweep", "match_gauss_fin"), "unit": "k_sweep"},
     }
 
     def roof(k):
         achieved = k["alg"] / (k["ms"] / 1e3) / 1e9
         return {"bound": "hbm", "kernel": k["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(k["prefix"], PROFILE_COUNTERS_MS),
+                "traffic": measured_traffic(k["prefixes"], k["unit"], PROFILE_COUNTERS_MS),
                 "alg_bytes_per_launch": k["alg"], "avg_launch_ms": k["ms"]}
 
     dominant = max(kernels, key=lambda n: kernels[n]["ms"])
@@ -960,17 +969,20 @@ def run_frame(args, side_kinds=True, builds=True, cpu=True):
     T = (2 * K + 1) ** 2
     plane_bytes = 4 * T * NBINS * (H + 1) * (W + 1)
     kernels = {
-        "build": {"kernel": "k_emit_gauss (Gaussian plane build, %d terms x 16 bins)" % T,
-                  "alg": H * W + plane_bytes, "ms": per["planes_gaussian"], "prefix": "k_emit_gauss<"},
-        "match": {"kernel": "k_match_gauss_comb + k_match_gauss_fin (Gaussian dense likelihood map, "
+        "build": {"kernel": "emit_gauss (Gaussian plane build, %d terms x 16 bins)" % T,
+                  "alg": H * W + plane_bytes, "ms": per["planes_gaussian"],
+                  "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
+        "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
                             "482x482 centres; the finalising pass is ~1% of the phase)",
-                  "alg": plane_bytes + 4 * nwin, "ms": per["match_gaussian"], "prefix": "k_match_gauss_"},
+                  "alg": plane_bytes + 4 * nwin, "ms": per["match_gaussian"],
+                  "prefixes": ("k_sweep", "match_gauss_fin"), "unit": "k_sweep"},
     }
 
     def roof(k):
         achieved = k["alg"] / (k["ms"] / 1e3) / 1e9
         return {"bound": "hbm", "kernel": k["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(k["prefix"]),
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(k["prefixes"], k["unit"]),
                 "alg_bytes_per_launch": k["alg"], "avg_launch_ms": k["ms"]}
 
     dominant = max(kernels, key=lambda n: kernels[n]["ms"])

@@ -257,9 +257,7 @@ def test_gaussian_other_series_lengths(K, kind):
 
 @pytest.mark.parametrize("kind", GAUSS_KINDS)
 def test_gaussian_windows_wider_than_a_block(kind):
-    # windows whose span exceeds half a map block's columns: the 2-D map reads
-    # each chunk's left and right window edges as two column segments
-    # (a map taller than two windows, so the 2-D form takes its comb path)
+    # wide windows on a map taller than two windows (several members per comb)
     H, W = 460, 420
     img = synth.smooth_noise(41, H, W)
     w, h = 161, 151
@@ -270,13 +268,26 @@ def test_gaussian_windows_wider_than_a_block(kind):
                 map_rect=(rx, ry, rx + 40, H - 1 - ry), kind=kind)
 
 
+def test_gaussian_windows_wider_than_a_sweep_block():
+    # windows wider than the twelve tiles of a sweep block: each block covers
+    # its chunk's left-edge tiles and right-edge tiles apart (two tile ranges)
+    H, W = 120, 1400
+    img = synth.smooth_noise(43, H, W)
+    w, h = 801, 15
+    rx, ry = (w - 1) // 2, (h - 1) // 2
+    c = synth.sample_centres(78, H, W, w, h, 256)
+    print("case: gaussian %dx%d window %dx%d (two tile ranges per block)" % (H, W, w, h), flush=True)
+    gauss_check(img, 6, w, h, c, (W // 2, H // 2), "gaussian two-range window",
+                map_rect=(rx, ry, W - 1 - rx, ry + 2))
+
+
 @pytest.mark.parametrize("w", [21, 31, 45, 63, 81])
 def test_gaussian_multiscale_2048(w):
     # The multi-scale precision workload: 2048 x 2048 smooth noise, 32 bins,
     # the Gaussian at each of five scales (26 GB of planes per scale), template
     # at (1024, 1024).  Histograms at 4096 sampled centres (the valid region's
     # corners and edges included); the full valid map, computed as the
-    # benchmark computes it (the comb form), checked on three whole rows of
+    # benchmark computes it (the comb sweep), checked on three whole rows of
     # centres (top, middle, bottom of the valid region) and at the sampled
     # centres, with the GPU's template and with the oracle's.
     H = W = 2048
