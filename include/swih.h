@@ -108,10 +108,12 @@ typedef struct {
   uint32_t flags;           /* reserved, must be 0 */
   int32_t band_rows;        /* rows of a scan tile, the build's band height: 0 = 64,
                                else 16, 32 or 64.  Tiles are 64 columns wide (one lane
-                               per column).  Results do not depend on it; speed does
-                               (more, shorter bands fill the GPU on small frames, at
-                               the price of more carries).  Ignored by
-                               SWIH_GAUSSIAN_SEP, which has no tiles. */
+                               per column).  Integer results do not depend on it; the
+                               real-valued kernels' results change by rounding only
+                               (tile-local origins move; well below their 1e-5 bars).
+                               Speed does depend on it (more, shorter bands fill the
+                               GPU on small frames, at the price of more carries).
+                               Ignored by SWIH_GAUSSIAN_SEP, which has no tiles. */
 } swih_config;
 
 /* Inclusive rectangle of window CENTRES. */
@@ -193,10 +195,11 @@ int swih_query(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_
  *                   order 0..nbins-1, then rounded to float.
  *   d_map           device float [(y1-y0+1)][(x1-x0+1)], row-major.
  * An empty rectangle (x1 < x0 or y1 < y0) is valid and enqueues nothing.
- * SWIH_GAUSSIAN maps use a per-scale accumulator inside d_ws (cleared by the
- * build, left cleared by every map): Gaussian maps of one scale of one
- * workspace must not run concurrently (order them on one stream).  Maps of
- * the other kernels only read d_ws.
+ * SWIH_GAUSSIAN maps may use a per-scale accumulator inside d_ws (when the
+ * launch plan splits the bins into groups; cleared by the build, left cleared
+ * by every map): Gaussian maps of one scale of one workspace must not run
+ * concurrently (order them on one stream).  Maps of the other kernels only
+ * read d_ws.
  */
 int swih_match(const swih_config* cfg, const void* d_ws, size_t ws_bytes, int32_t height,
                int32_t width, int32_t scale_idx, const float* d_template,

@@ -10,8 +10,9 @@ class's size (and, for the 2-D Gaussian, computes one map, since its lookups
 cross band boundaries), the fastest candidate wins, and the choice is cached in
 a JSON file so each class is timed once per device.
 
-Results never depend on the choice (tests/test_gpu_autotune.py); only speed
-does.
+Integer results never depend on the choice; the real-valued kernels' results
+change by rounding only (the tile-local origins move; measured at most 1.8e-7
+on maps, asserted within 1e-5 by tests/test_gpu_autotune.py).
 """
 from __future__ import annotations
 
