@@ -58,6 +58,9 @@ def parse():
                     help="serve workload: request rates (req/s) to sweep")
     ap.add_argument("--seconds", type=float, default=1.0,
                     help="serve workload: arrival span per rate")
+    ap.add_argument("--serve-trace", default=None,
+                    help="serve workload: append each rate's per-request host timeline "
+                         "(continuous server) to this JSONL file")
     ap.add_argument("--gaussian", choices=("2d", "separable"), default="2d",
                     help="batch / serve workloads: the Gaussian as 2-D planes (49 weight terms) "
                          "or in separable form")
@@ -520,6 +523,7 @@ def bench_serve(args):
     cfg = swih.Config(16, "gaussian_sep" if args.gaussian == "separable" else "gaussian", [(15, 15)])
     pool = serving.FramePool(synth.FRAME_SIZES, lambda H, W: synth.smooth_noise(H * 7 + W, H, W))
     cont = serving.ContinuousServer(cfg, pool, budget=24 << 30, max_inflight=3)
+    cont.trace = bool(args.serve_trace)
     ser = serving.SerialServer(cfg, pool, budget=8 << 30)
     # warm up both paths (library load, kernels, allocator, and the weight-term
     # fits of every stream's window sizes: the same seed gives the same streams)
@@ -532,7 +536,11 @@ def bench_serve(args):
         n = max(200, int(rate * args.seconds))   # at least 200 requests, so p99 is not the maximum
         reqs = synth.serving_requests(7, rate, n)
         cont.templates = serving._Templates(cfg.nbins, "cuda")
-        rc = serving.latency_stats(cont.serve(reqs))
+        served = cont.serve(reqs)
+        rc = serving.latency_stats(served)
+        if args.serve_trace:
+            with open(args.serve_trace, "a") as fh:
+                fh.write(json.dumps({"rate": rate, "trace": serving.request_trace(served)}) + "\n")
         ser.templates = serving._Templates(cfg.nbins, "cuda")
         rs = serving.latency_stats(ser.serve(reqs))
         sweep.append({"rate": rate, "continuous": rc, "serial": rs})

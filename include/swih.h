@@ -361,6 +361,19 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream);
  */
 int swih_gauss_terms(int32_t n, int32_t K, double* a_out, double* omega_out, double* err_out);
 
+/*
+ * Copy `bytes` bytes from src to dst on `stream` with a kernel.  Each pointer
+ * is device memory or pinned host memory (hipHostMalloc, torch pin_memory):
+ * the kernel reads and writes pinned host memory directly over the bus, so a
+ * request loop's uploads and downloads do not go through the runtime's copy
+ * engines (Sec. 4's tracking requests, served; see serving.py).  Any
+ * alignment; 16-byte moves where src and dst share their alignment.
+ * Pageable host memory (or any pointer the device cannot reach) gives
+ * SWIH_ERR_INVALID; nothing is enqueued then.  Host memory written by the copy
+ * is complete once the stream has reached the copy (an event after it).
+ */
+int swih_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Static text for a status code. */
 const char* swih_status_string(int status);
 

@@ -28,7 +28,7 @@ EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_bu
             "swih_query", "swih_match", "swih_batch_table_bytes", "swih_batch_plan",
             "swih_build_batch", "swih_query_batch", "swih_match_batch", "swih_gauss_terms",
             "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match", "swih_argmax",
-            "swih_match_noalloc")
+            "swih_match_noalloc", "swih_copy")
 
 
 class SwihError(RuntimeError):
@@ -114,6 +114,8 @@ def load():
     lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
     lib.swih_gauss_terms.restype = C.c_int
+    lib.swih_copy.argtypes = [vp, vp, sz, vp]
+    lib.swih_copy.restype = C.c_int
     lib.swih_status_string.argtypes = [C.c_int]
     lib.swih_status_string.restype = C.c_char_p
     _lib = lib
@@ -234,6 +236,16 @@ def match_noalloc(cfg: Config, ws, height: int, width: int, scale_idx: int, rect
                                    _ptr(template_raw), r, _ptr(out), _stream(stream))
     if st != OK:
         raise SwihError(st, "swih_match_noalloc")
+
+
+def copy(dst, src, nbytes: int, stream=None):
+    """swih_copy: ``nbytes`` bytes from tensor ``src`` to tensor ``dst`` (device
+    or pinned host memory) with a kernel on ``stream``."""
+    if nbytes > dst.numel() * dst.element_size() or nbytes > src.numel() * src.element_size():
+        raise ValueError("copy of %d bytes exceeds a buffer" % nbytes)
+    st = load().swih_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_copy")
 
 
 def cake_query(cfg: Config, ws, height: int, width: int, scale_idx: int, rings: int, centres, hist,

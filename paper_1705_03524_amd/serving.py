@@ -60,12 +60,18 @@ class FramePool:
 
 class Request:
     __slots__ = ("id", "t_arrive", "stream", "hw", "centre", "scales", "search", "crop_box",
-                 "units", "maps", "host_maps", "t_done", "windows")
+                 "units", "maps", "host_maps", "t_done", "windows", "t_seen", "t_launch",
+                 "t_launched", "slot", "batch_size", "marks")
 
     def __init__(self, r):
         self.id, self.t_arrive, self.stream = r["id"], r["t_arrive"], r["stream"]
         self.hw, self.centre, self.scales, self.search = r["frame_hw"], r["centre"], r["scales"], r["search"]
         self.t_done = None
+        # host timestamps (seconds from the run's start): arrival noticed by the
+        # loop, launch started, launch call returned; slot and micro-batch size
+        self.t_seen = self.t_launch = self.t_launched = None
+        self.slot = self.batch_size = None
+        self.marks = None  # (label, host time) of each call inside a traced launch
         H, W = self.hw
         cx, cy = self.centre
         x0, y0, x1, y1 = self.search
@@ -241,6 +247,8 @@ class ContinuousServer:
         self.slots = [_Slot(budget, in_bytes, out_floats, device) for _ in range(max_inflight)]
         self.free = deque(range(max_inflight))
         self.templates = _Templates(cfg.nbins, device)
+        self.trace = False  # record host timestamps of each call inside a launch (Request.marks)
+        self._clock, self._t0 = time.perf_counter, 0.0
 
     def _launch(self, reqs, slot_id):
         cfg, dev = self.cfg, self.device
@@ -264,9 +272,13 @@ class ContinuousServer:
                 cl.append(coff)
                 coff += 2
             cens.append(cl)
+        for r in reqs:
+            self._mark(r, "staged")
         with torch.cuda.stream(st):
-            sl.d_in[:ioff].copy_(sl.h_in[:ioff], non_blocking=True)
-            sl.d_cen[:coff].copy_(sl.h_cen[:coff], non_blocking=True)
+            S.copy(sl.d_in, sl.h_in, ioff, st)  # kernel copies: no copy-engine waits
+            S.copy(sl.d_cen, sl.h_cen, 4 * coff, st)
+            for r in reqs:
+                self._mark(r, "upload")
             if len(reqs) == 1 and self.direct_single:
                 return self._launch_direct(reqs[0], crops[0], cens[0], slot_id)
             for r, (io, h, w), cl in zip(reqs, crops, cens):
@@ -302,12 +314,16 @@ class ContinuousServer:
                 for key in produced:
                     self.templates.produced(key[0], key[1], tev)
             b.match()
-            sl.h_out[:ooff].copy_(sl.d_out[:ooff], non_blocking=True)
+            S.copy(sl.h_out, sl.d_out, 4 * ooff, st)
             ev = torch.cuda.Event()
             ev.record(st)
         mb = _MicroBatch(reqs, slot_id, ev)
         mb.batch = b  # keep the plan table alive until done
         return mb
+
+    def _mark(self, r, label):
+        if self.trace:
+            r.marks.append((label, self._clock() - self._t0))
 
     def _launch_direct(self, r, crop_io, cl, slot_id):
         """One request with single-unit calls on the slot's stream (the current
@@ -326,24 +342,30 @@ class ContinuousServer:
             uc = S.Config(cfg.nbins, cfg.kernel, [(sw, sh)], cfg.gauss_terms, band_rows=cfg.band_rows)
             nb = S.workspace_bytes(uc, view.shape[0], view.shape[1])
             p = Plan(uc, view.shape[0], view.shape[1], ws=sl.ws[:nb])
+            self._mark(r, "plan")
             tmpl, new = self.templates.get(r.stream, (sw, sh))
             if not new:
                 ev = self.templates.event(r.stream, (sw, sh))
                 if ev is not None:  # written by a batch on another stream
                     st.wait_event(ev)
             p.build(view)
+            self._mark(r, "build")
             if new:
                 S.query(uc, p.ws, p.H, p.W, 0, sl.d_cen[co:co + 2].view(1, 2), tmpl)
                 tev = torch.cuda.Event()
                 tev.record(st)
                 self.templates.produced(r.stream, (sw, sh), tev)
+                self._mark(r, "query")
             rows, cols = rect[3] - rect[1] + 1, rect[2] - rect[0] + 1
             p.match(0, template=tmpl[0], rect=rect, out=sl.d_out[ooff:ooff + rows * cols].view(rows, cols))
+            self._mark(r, "match")
             r.maps.append((ooff, rows, cols))
             ooff += rows * cols
-        sl.h_out[:ooff].copy_(sl.d_out[:ooff], non_blocking=True)
+        S.copy(sl.h_out, sl.d_out, 4 * ooff, st)
+        self._mark(r, "download")
         ev = torch.cuda.Event()
         ev.record(st)
+        self._mark(r, "event")
         mb = _MicroBatch([r], slot_id, ev)
         mb.batch = None
         return mb
@@ -361,12 +383,11 @@ class ContinuousServer:
     def _serve(self, requests, clock, keep_maps):
         reqs = [Request(r) for r in requests]
         # one small upload and download on every slot's stream before the
-        # clock starts, so that setting up the asynchronous copies is not
-        # charged to the first requests
+        # clock starts, so that first use of the copy kernel is not charged
+        # to the first requests
         for sl in self.slots:
-            with torch.cuda.stream(sl.stream):
-                sl.d_in[:256].copy_(sl.h_in[:256], non_blocking=True)
-                sl.h_out[:64].copy_(sl.d_out[:64], non_blocking=True)
+            S.copy(sl.d_in, sl.h_in, 256, sl.stream)
+            S.copy(sl.h_out, sl.d_out, 256, sl.stream)
         torch.cuda.synchronize()
         limits = (self.budget, self.in_bytes, self.out_floats, CENTRE_INTS)
         for r in reqs:
@@ -374,10 +395,15 @@ class ContinuousServer:
                 raise ValueError("request %d exceeds a slot's capacity" % r.id)
         pending, inflight = deque(), deque()
         i, done, n = 0, 0, len(reqs)
+        if self.trace:
+            for r in reqs:
+                r.marks = []
         t0 = clock()
+        self._clock, self._t0 = clock, t0
         while done < n:
             now = clock() - t0
             while i < n and reqs[i].t_arrive <= now:
+                reqs[i].t_seen = now
                 pending.append(reqs[i])
                 i += 1
             # every in-flight micro-batch is polled, not just the oldest: the
@@ -403,7 +429,15 @@ class ContinuousServer:
                 k = 0
                 for count in admit(needs, len(self.free), limits, self.max_batch, self.direct_single,
                                    busy, self.work_cap):
-                    mb = self._launch([pending.popleft() for _ in range(count)], self.free.popleft())
+                    batch = [pending.popleft() for _ in range(count)]
+                    slot = self.free.popleft()
+                    t = clock() - t0
+                    for r in batch:
+                        r.t_launch, r.slot, r.batch_size = t, slot, count
+                    mb = self._launch(batch, slot)
+                    t = clock() - t0
+                    for r in batch:
+                        r.t_launched = t
                     mb.work = sum(nd[0] for nd in needs[k:k + count])
                     k += count
                     inflight.append(mb)
@@ -451,6 +485,15 @@ class SerialServer:
                 r.host_maps = host
             r.t_done = clock() - t0
         return reqs
+
+
+def request_trace(reqs):
+    """Per-request host timeline (ms from the run's start) of a served run."""
+    ms = lambda v: None if v is None else round(v * 1e3, 4)
+    return [{"id": r.id, "stream": r.stream, "arrive": ms(r.t_arrive), "seen": ms(r.t_seen),
+             "launch": ms(r.t_launch), "launched": ms(r.t_launched), "done": ms(r.t_done),
+             "slot": r.slot, "batch": r.batch_size, "windows": r.windows,
+             "marks": [(k, ms(t)) for k, t in (r.marks or [])]} for r in reqs]
 
 
 def latency_stats(reqs):
