@@ -184,7 +184,8 @@ def cpu_baseline_multiscale(img, nsample=65536):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha1()
-    for f in ("swih_build.hip", "swih_query.hip", "swih_layout.h", "wave64.h"):
+    for f in ("swih_build.hip", "swih_build_bodies.h", "swih_query.hip", "swih_query_bodies.h",
+              "swih_layout.h", "wave64.h"):
         with open(os.path.join(HERE, "paper_1705_03524_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -426,7 +427,7 @@ def run_batch(args):
     frames = WL.batch_config_frames(4, 64)
     out = {}
     total_windows = 0
-    total_ms = {"per_frame": 0.0, "batched": 0.0, "graph": 0.0}
+    total_ms = {"per_frame": 0.0, "batched": 0.0, "graph": 0.0, "fused": 0.0}
     gname = "gaussian_sep" if args.gaussian == "separable" else "gaussian"
     for name in ("manhattan", gname):
         cfg = swih.Config(16, name, [(15, 15)])
@@ -444,6 +445,14 @@ def run_batch(args):
         bat.run()
         torch.cuda.synchronize()
         same = all(torch.equal(a, j.out) for a, j in zip(ref, (j for u in units for j in u.jobs)))
+        # the one-launch form (one persistent launch per sub-batch)
+        for u in units:
+            for j in u.jobs:
+                j.out.fill_(-1)
+        bat.run_fused()
+        torch.cuda.synchronize()
+        same_fused = bat.fused_status() == 0 and all(
+            torch.equal(a, j.out) for a, j in zip(ref, (j for u in units for j in u.jobs)))
         bat.capture()
 
         def timed(fn, steps):
@@ -462,6 +471,7 @@ def run_batch(args):
         t_per = timed(per.run, steps)
         t_bat = timed(bat.run, steps)
         t_gra = timed(bat.replay, steps)
+        t_fus = timed(bat.run_fused, steps)
         # the same batch with scan tiles picked by the autotuner per unit size class
         from paper_1705_03524_amd.autotune import Autotuner
         tuner = Autotuner()  # cache: $SWIH_AUTOTUNE_CACHE, else ~/.cache/swih_autotune.json
@@ -481,11 +491,14 @@ def run_batch(args):
         total_ms["per_frame"] += t_per
         total_ms["batched"] += t_bat
         total_ms["graph"] += t_gra
+        total_ms["fused"] += t_fus
         out[name] = {"units": len(units), "jobs": sum(len(u.jobs) for u in units),
                      "sub_batches": bat.nbatches, "windows": nw,
                      "plane_gb": WL.plane_bytes(cfg, units) / 1e9,
                      "ms_per_frame_loop": t_per, "ms_batched": t_bat, "ms_graph": t_gra,
                      "windows_per_s_graph": nw / (t_gra / 1e3), "batched_equals_per_frame": same,
+                     "ms_fused": t_fus, "windows_per_s_fused": nw / (t_fus / 1e3),
+                     "fused_equals_per_frame": same_fused,
                      "autotuned": {"band_rows_by_size_class": {"%dx%d" % (c[1], c[0]): r
                                                                for c, r in sorted(chosen.items())},
                                    "ms_batched": t_tun, "ms_graph": t_tgr,
@@ -505,6 +518,8 @@ def run_batch(args):
                    "global_batch": 64, "seq_len": None, "parallelism": "none"},
         "per_frame_windows_per_s": total_windows / (total_ms["per_frame"] / 1e3),
         "speedup_vs_per_frame": total_ms["per_frame"] / best,
+        "fused_windows_per_s": total_windows / (total_ms["fused"] / 1e3),
+        "fused_speedup_vs_per_frame": total_ms["per_frame"] / total_ms["fused"],
         "autotuned_windows_per_s": total_windows / (total_ms["tuned"] / 1e3),
         "detail": out,
     }
@@ -1067,8 +1082,9 @@ def main():
         print("2048x2048 builds done", file=sys.stderr, flush=True)
         bt = run_batch(args)
         line["batch"] = {k: bt[k] for k in ("value", "unit", "ms_per_step", "per_frame_windows_per_s",
-                                            "speedup_vs_per_frame", "autotuned_windows_per_s", "config",
-                                            "detail")}
+                                            "speedup_vs_per_frame", "fused_windows_per_s",
+                                            "fused_speedup_vs_per_frame", "autotuned_windows_per_s",
+                                            "config", "detail")}
         print("batch done", file=sys.stderr, flush=True)
         line["ceilings"] = ceilings()
     if not args.no_cpu_baseline:

@@ -341,6 +341,35 @@ int swih_query_batch(const void* h_table, const void* d_table, void* stream);
 int swih_match_batch(const void* h_table, const void* d_table, void* stream);
 
 /*
+ * The whole batch -- every build, then the template queries, then the maps --
+ * in ONE persistent launch (Sec. 4: many targets over many frames).  Results
+ * are identical, bit for bit, to swih_build_batch + swih_query_batch +
+ * swih_match_batch of the same table.
+ *
+ * Each stage's virtual blocks are tickets taken from one atomic counter in
+ * stage order (basis, aggregate, scan, emit, query, map); a block waits only
+ * until the stage before its ticket is complete for the same plane set (a
+ * map: also until every query of the batch is done, since its template may
+ * be one of them).  Tickets are taken in order, so the launch always drains;
+ * every wait is also bounded: past `wait_ms` milliseconds the block records a
+ * failure and carries on (the results are then not to be used).
+ *   d_table   the device copy of the table; the launch updates counters kept
+ *             in it and leaves them reset, so the table can be launched again.
+ *             Two launches of one table must not overlap.
+ *   d_status  device int32 or NULL: set at the end to 0 if every wait was met,
+ *             1 if one gave up.
+ *   wait_ms   bound on each wait; 0 = 2000 ms.  A negative value makes every
+ *             wait give up at once (a test hook for the failure path: d_status
+ *             becomes 1 and the launch still ends; the next launch of the
+ *             table starts clean).
+ * Kernels: uniform, Manhattan, Euclidean, and the 2-D Gaussian with up to 4
+ * series terms per axis (SWIH_ERR_UNSUPPORTED otherwise: the separable and
+ * exponential forms run with the stage launches).
+ */
+int swih_run_batch(const void* h_table, void* d_table, int32_t* d_status, int32_t wait_ms,
+                   void* stream);
+
+/*
  * The cosine series that stands in for one axis of the Gaussian kernel:
  *   g(t) ~= sum_{k=0..K} a_k cos(w_k t),  t in [-r, r], r = (n-1)/2,
  * with w_0 = 0 < w_1 < ... < w_K, fitted to exp(-t^2 / (2 (n/4)^2)) at the

@@ -28,7 +28,7 @@ EXPORTED = ("swih_workspace_bytes", "swih_build", "swih_build_carries", "swih_bu
             "swih_query", "swih_match", "swih_batch_table_bytes", "swih_batch_plan",
             "swih_build_batch", "swih_query_batch", "swih_match_batch", "swih_gauss_terms",
             "swih_status_string", "swih_cake_query", "swih_cake_match", "swih_brute_match", "swih_argmax",
-            "swih_match_noalloc", "swih_copy")
+            "swih_match_noalloc", "swih_copy", "swih_run_batch")
 
 
 class SwihError(RuntimeError):
@@ -114,6 +114,8 @@ def load():
     lib.swih_gauss_terms.argtypes = [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
     lib.swih_gauss_terms.restype = C.c_int
+    lib.swih_run_batch.argtypes = [vp, vp, vp, C.c_int32, vp]
+    lib.swih_run_batch.restype = C.c_int
     lib.swih_copy.argtypes = [vp, vp, sz, vp]
     lib.swih_copy.restype = C.c_int
     lib.swih_status_string.argtypes = [C.c_int]
@@ -359,6 +361,15 @@ def batch_plan(cfg: Config, frames, queries, matches):
     if st != OK:
         raise SwihError(st, "swih_batch_plan")
     return table
+
+
+def batch_run(h_table, d_table, status=None, wait_ms: int = 0, stream=None):
+    """swih_run_batch: the whole planned batch in one persistent launch;
+    ``status`` (int32 device tensor or None) receives 0 if every wait was met."""
+    st = load().swih_run_batch(h_table.ctypes.data_as(C.c_void_p), C.c_void_p(d_table.data_ptr()),
+                               _ptr(status), int(wait_ms), _stream(stream))
+    if st != OK:
+        raise SwihError(st, "swih_run_batch")
 
 
 def batch_launch(which: str, h_table, d_table, stream=None):

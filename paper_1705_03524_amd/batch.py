@@ -41,6 +41,7 @@ class Batch:
         if self.d_table.data_ptr() % ALIGN:
             raise RuntimeError("device table misaligned")
         self.graph = None
+        self.status = None  # run_fused's status word
 
     def build(self, stream=None):
         S.batch_launch("build", self.h_table, self.d_table, stream)
@@ -55,6 +56,18 @@ class Batch:
         self.build(stream)
         self.query(stream)
         self.match(stream)
+
+    def run_fused(self, stream=None, wait_ms: int = 0):
+        """The whole batch in one persistent launch (swih_run_batch); the
+        results equal ``run``'s bit for bit.  ``fused_status()`` tells whether
+        every wait inside it was met."""
+        if self.status is None:
+            self.status = torch.zeros(1, dtype=torch.int32, device=self.d_table.device)
+        S.batch_run(self.h_table, self.d_table, self.status, wait_ms, stream)
+
+    def fused_status(self) -> int:
+        """0 if every wait of the last run_fused was met (synchronises)."""
+        return int(self.status.item()) if self.status is not None else 0
 
     def capture(self):
         """Capture build + query + match once in a HIP graph (torch.cuda.CUDAGraph)."""

@@ -17,8 +17,8 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libswih.so")
 
 SOURCES = ["swih_build.hip", "swih_query.hip", "swih_sep.hip", "swih_exp.hip", "swih_cake.hip",
-           "swih_argmax.hip", "swih_io.hip", "swih_api.hip", "gauss_terms.cpp"]
-HEADERS = ["swih_layout.h", "swih_internal.h", "wave64.h"]
+           "swih_argmax.hip", "swih_io.hip", "swih_fused.hip", "swih_api.hip", "gauss_terms.cpp"]
+HEADERS = ["swih_layout.h", "swih_internal.h", "wave64.h", "swih_build_bodies.h", "swih_query_bodies.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

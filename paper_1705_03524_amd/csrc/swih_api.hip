@@ -502,7 +502,12 @@ struct BatchHeader {
   int32_t nunits, nq, nm;
   int32_t total[4];   // build-stage virtual blocks
   Launch ql, ml;      // query / map launch shapes (blocks = total virtual blocks)
-  int64_t off_units, off_uprefix, off_q, off_qprefix, off_m, off_mprefix, bytes;
+  int64_t off_units, off_uprefix, off_q, off_qprefix, off_m, off_mprefix;
+  // the fused launch (swih_run_batch): build-stage prefixes in its block
+  // size, the unit each query / map reads, its counters
+  int64_t off_fprefix, off_qunit, off_munit, off_sync, bytes;
+  int32_t fcum[7];    // first ticket of each stage, then the total
+  int32_t fused_ok;   // the kind has a fused form
 };
 
 int32_t frame_units(const swih_config* cfg, const swih_frame_desc& f) {
@@ -532,6 +537,14 @@ BatchHeader table_layout(int32_t kind, int32_t nunits, int32_t nq, int32_t nm) {
   off += swih_align256((int64_t)nm * mb);
   h.off_mprefix = off;
   off += swih_align256((int64_t)(nm + 1) * sizeof(int32_t));
+  h.off_fprefix = off;
+  off += swih_align256((int64_t)4 * (nunits + 1) * sizeof(int32_t));
+  h.off_qunit = off;
+  off += swih_align256((int64_t)nq * sizeof(int32_t));
+  h.off_munit = off;
+  off += swih_align256((int64_t)nm * sizeof(int32_t));
+  h.off_sync = off;
+  off += swih_align256(fused_sync_words(nunits) * (int64_t)sizeof(int32_t));
   h.bytes = off;
   h.nunits = nunits;
   h.nq = nq;
@@ -658,6 +671,19 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     }
   }
   for (int s = 0; s < 4; ++s) h.total[s] = upre[s * (nunits + 1) + nunits];
+  // the fused launch's build prefixes: a virtual block of its size covers
+  // `ratio` 256-thread ones of the same unit
+  h.fused_ok = cfg->kernel <= SWIH_GAUSSIAN && !sep && !ex;
+  {
+    const int ratio = fused_build_ratio(cfg->kernel);
+    int32_t* fpre = (int32_t*)(tb + h.off_fprefix);
+    for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < nunits; ++u) {
+        const int32_t nb = upre[s * (nunits + 1) + u + 1] - upre[s * (nunits + 1) + u];
+        fpre[s * (nunits + 1) + u + 1] = fpre[s * (nunits + 1) + u] + (nb + ratio - 1) / ratio;
+      }
+    for (int s = 0; s < 4; ++s) h.fcum[s + 1] = h.fcum[s] + fpre[s * (nunits + 1) + nunits];
+  }
   // queries
   QueryArgs* qa = (QueryArgs*)(tb + h.off_q);
   int32_t* qpre = (int32_t*)(tb + h.off_qprefix);
@@ -697,6 +723,12 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     if (ql.lds > h.ql.lds) h.ql.lds = ql.lds;
   }
   h.ql.blocks = qpre[nqueries];
+  h.fcum[5] = h.fcum[4] + h.ql.blocks;
+  {
+    int32_t* qu = (int32_t*)(tb + h.off_qunit);
+    for (int q = 0; q < nqueries; ++q)
+      qu[q] = ubase[queries[q].frame] + (per_scale(cfg->kernel) ? queries[q].scale_idx : 0);
+  }
   // maps
   MatchArgs* ma = (MatchArgs*)(tb + h.off_m);
   int32_t* mpre = (int32_t*)(tb + h.off_mprefix);
@@ -751,6 +783,12 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
     if (ml.lds > h.ml.lds) h.ml.lds = ml.lds;
   }
   h.ml.blocks = mpre[nmatches];
+  h.fcum[6] = h.fcum[5] + h.ml.blocks;
+  {
+    int32_t* mu = (int32_t*)(tb + h.off_munit);
+    for (int m = 0; m < nmatches; ++m)
+      mu[m] = ubase[matches[m].frame] + (per_scale(cfg->kernel) ? matches[m].scale_idx : 0);
+  }
   if (h.ml.threads == 0) h.ml.threads = 256;
   if (h.ml.lds > 160 * 1024) return SWIH_ERR_UNSUPPORTED;
   memcpy(tb, &h, sizeof(h));
@@ -826,6 +864,40 @@ int swih_match_batch(const void* h_table, const void* d_table, void* stream) {
                             (hipStream_t)stream) == hipSuccess
              ? SWIH_OK
              : SWIH_ERR_HIP;
+}
+
+int swih_run_batch(const void* h_table, void* d_table, int32_t* d_status, int32_t wait_ms,
+                   void* stream) {
+  const BatchHeader* h = header_of(h_table);
+  if (!h || !d_table || !aligned256(d_table)) return SWIH_ERR_INVALID;
+  if (!h->fused_ok) return SWIH_ERR_UNSUPPORTED;
+  char* db = (char*)d_table;
+  FusedArgs f;
+  memset(&f, 0, sizeof(f));
+  f.units = (const BuildArgs*)(db + h->off_units);
+  f.q = (const QueryArgs*)(db + h->off_q);
+  f.m = (const MatchArgs*)(db + h->off_m);
+  f.upre = (const int32_t*)(db + h->off_fprefix);
+  f.qpre = (const int32_t*)(db + h->off_qprefix);
+  f.mpre = (const int32_t*)(db + h->off_mprefix);
+  f.qunit = (const int32_t*)(db + h->off_qunit);
+  f.munit = (const int32_t*)(db + h->off_munit);
+  f.nunits = h->nunits;
+  f.nq = h->nq;
+  f.nm = h->nm;
+  for (int k = 0; k < 7; ++k) f.cum[k] = h->fcum[k];
+  f.sync = (int32_t*)(db + h->off_sync);
+  f.status = d_status;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return SWIH_ERR_HIP;
+  const int64_t ms = wait_ms == 0 ? 2000 : wait_ms;
+  f.limit = ms < 0 ? -1 : ms * (int64_t)khz;
+  const size_t lds = h->ql.lds > h->ml.lds ? h->ql.lds : h->ml.lds;
+  const hipError_t e = launch_fused(h->kind, h->nt, h->nbins, f, lds, (hipStream_t)stream);
+  if (e == hipErrorInvalidValue) return SWIH_ERR_UNSUPPORTED;
+  return e == hipSuccess ? SWIH_OK : SWIH_ERR_HIP;
 }
 
 int swih_gauss_terms(int32_t n, int32_t K, double* a_out, double* omega_out, double* err_out) {

@@ -132,6 +132,39 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
 hipError_t launch_match_batch(int kind, int nt, const MatchArgs* jobs, const int32_t* prefix,
                               int njobs, const Launch& ml, int grid, hipStream_t stream);
 
+// One persistent launch for a whole planned batch (integer kinds and the 2-D
+// Gaussian): blocks take virtual blocks ("tickets") of every stage from one
+// atomic counter, stages in order (basis, aggregate, scan, emit, query, map),
+// and wait, with a time bound, only for the earlier stage of their own unit.
+struct FusedArgs {
+  const BuildArgs* units;
+  const QueryArgs* q;
+  const MatchArgs* m;
+  const int32_t* upre;   // [4][nunits + 1] prefixes of the build stages' virtual blocks
+  const int32_t* qpre;   // [nq + 1]
+  const int32_t* mpre;   // [nm + 1]
+  const int32_t* qunit;  // [nq] unit (plane set) each query reads
+  const int32_t* munit;  // [nm] unit each map reads
+  int32_t nunits, nq, nm, pad;
+  int32_t cum[7];        // first ticket of each stage; cum[6] = tickets in all
+  int32_t pad2;
+  int32_t* sync;         // kFusedSyncHead words, then [4][nunits] finished tickets,
+                         // then [4][nunits] completion stamps
+  int32_t* status;       // written once at the end (0 = every wait met), or null
+  int64_t limit;         // ticks of the constant-rate clock a wait may take; < 0: none
+};
+
+// next ticket, blocks exited, status, finished query tickets, completion
+// clock, the queries' completion stamp
+constexpr int kFusedSyncHead = 6;
+inline int64_t fused_sync_words(int32_t nunits) { return kFusedSyncHead + 8 * (int64_t)nunits; }
+// Virtual blocks of the fused launch's block size per 256-thread build block.
+inline int fused_build_ratio(int kind) { return kind == 3 ? 3 : 1; }
+
+// dyn_lds: the largest dynamic LDS of the batch's query and map jobs.
+hipError_t launch_fused(int kind, int nt, int nbins, const FusedArgs& f, size_t dyn_lds,
+                        hipStream_t stream);
+
 // acc: the integer accumulator of a Gaussian map with several bin groups;
 // null = the set's region of the workspace.
 hipError_t launch_match(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,

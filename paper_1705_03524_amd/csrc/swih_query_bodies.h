@@ -1,0 +1,675 @@
+// Window histograms from the weighted integral histograms (Sec. 2.1) and the
+// Bhattacharyya likelihood map (Sec. 2 Fig. 3, Sec. 4).
+//
+// Translation (Sec. 2.1): a kernel weight k(x - xc, y - yc) is written as a
+// sum of image-wide weight terms u_i(x) v_j(y) times coefficients that depend
+// only on the centre, so each window histogram is a few O(1) box lookups.
+//
+//   Manhattan, quadrant by quadrant (Fig. 4b), c = rx + ry + 1:
+//     TL [xc-rx, xc] x [yc-ry, yc]      (c - xc - yc) B_1 + B_x + B_y
+//     TR [xc+1, xc+rx] x [yc-ry, yc]    (c + xc - yc) B_1 - B_x + B_y
+//     BL [xc-rx, xc] x [yc+1, yc+ry]    (c - xc + yc) B_1 + B_x - B_y
+//     BR [xc+1, xc+rx] x [yc+1, yc+ry]  (c + xc + yc) B_1 - B_x - B_y
+//   The four quadrants are disjoint, so the centre row and column count once.
+//   Euclidean paraboloid, one box, c = rx^2 + ry^2 + 1:
+//     (c - xc^2 - yc^2) B_1 + 2 xc B_x + 2 yc B_y - B_xx - B_yy
+//   Gaussian, one box: sum_ij alpha_i(xc) beta_j(yc) B_ij with
+//     alpha = (a_0, a_k cos(w_k xc), a_k sin(w_k xc)), w_k the series' frequencies.
+// Integer coefficients are applied modulo 2^32; the true histogram is below
+// 2^32, so the result is exact.  Normalisation divides by the kernel mass S
+// (the same at every location, Sec. 2.1).
+#pragma once
+
+#include <string.h>
+
+#include "swih_internal.h"
+#include "wave64.h"
+
+namespace swih {
+namespace {
+
+// Offsets of a window's corner lookups, the same for every plane and bin:
+// rows {ya, ym, yb} x columns {xa, xm, xb}, ym = yc + 1, xm = xc + 1 (the
+// Manhattan quadrant split; the other kernels use the outer four).  Column
+// X = 0 is not stored and reads as 0: its offset points at column 1 and the
+// value is dropped.
+struct IntCorners {
+  int64_t o[3][3];
+  bool xa0;
+};
+
+__device__ __forceinline__ IntCorners int_corners(const SwihGeom& g, int xc, int yc,
+                                                  const ScaleParams& sp) {
+  IntCorners k;
+  const int xa = xc - sp.rx;
+  const int Ys[3] = {yc - sp.ry, yc + 1, yc + sp.ry + 1};
+  const int64_t Xo[3] = {swih_xoff(g, xa > 0 ? xa : 1), swih_xoff(g, xc + 1),
+                         swih_xoff(g, xc + sp.rx + 1)};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k.o[r][c] = (int64_t)Ys[r] * g.row_stride + Xo[c];
+  k.xa0 = xa == 0;
+  return k;
+}
+
+// P at corner (r, c) of the plane whose base (swih_base) is pl.
+__device__ __forceinline__ uint32_t at_u(const uint32_t* __restrict__ pl, const IntCorners& k,
+                                         int r, int c) {
+  const uint32_t v = pl[k.o[r][c]];
+  return c == 0 && k.xa0 ? 0u : v;
+}
+
+// Exact H_b of an integer kernel at the window of k (uint32 arithmetic modulo 2^32).
+template <int KIND>
+__device__ __forceinline__ uint32_t hist_int(const uint32_t* __restrict__ planes,
+                                             const SwihGeom& g, int b, int xc, int yc,
+                                             const ScaleParams& sp, const IntCorners& k) {
+  const uint32_t* p0 = planes + swih_base(g, 0, b);
+  if (KIND == 0) {
+    return at_u(p0, k, 2, 2) - at_u(p0, k, 0, 2) - at_u(p0, k, 2, 0) + at_u(p0, k, 0, 0);
+  } else if (KIND == 1) {
+    const uint32_t* px = planes + swih_base(g, 1, b);
+    const uint32_t* py = planes + swih_base(g, 2, b);
+    // 3 x 3 corner grid per plane
+    uint32_t c1[3][3], cx[3][3], cy[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        c1[r][c] = at_u(p0, k, r, c);
+        cx[r][c] = at_u(px, k, r, c);
+        cy[r][c] = at_u(py, k, r, c);
+      }
+    auto box = [](const uint32_t (&a)[3][3], int r, int c) {
+      return a[r + 1][c + 1] - a[r][c + 1] - a[r + 1][c] + a[r][c];
+    };
+    const uint32_t c = sp.c_int, X = (uint32_t)xc, Y = (uint32_t)yc;
+    const uint32_t tl = (c - X - Y) * box(c1, 0, 0) + box(cx, 0, 0) + box(cy, 0, 0);
+    const uint32_t tr = (c + X - Y) * box(c1, 0, 1) - box(cx, 0, 1) + box(cy, 0, 1);
+    const uint32_t bl = (c - X + Y) * box(c1, 1, 0) + box(cx, 1, 0) - box(cy, 1, 0);
+    const uint32_t br = (c + X + Y) * box(c1, 1, 1) - box(cx, 1, 1) - box(cy, 1, 1);
+    return tl + tr + bl + br;
+  } else {
+    uint32_t bx[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const uint32_t* pl = planes + swih_base(g, p, b);
+      bx[p] = at_u(pl, k, 2, 2) - at_u(pl, k, 0, 2) - at_u(pl, k, 2, 0) + at_u(pl, k, 0, 0);
+    }
+    const uint32_t X = (uint32_t)xc, Y = (uint32_t)yc;
+    return (sp.c_int - X * X - Y * Y) * bx[0] + 2u * X * bx[1] + 2u * Y * bx[2] - bx[3] - bx[4];
+  }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <int KIND>
+__device__ __forceinline__ void query_int(const QueryArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const uint32_t* __restrict__ planes = (const uint32_t*)a.planes;
+  const int32_t* __restrict__ centres = a.centres;
+  const long t = (long)vb * 256 + threadIdx.x;
+  if (t >= (long)a.n * g.B) return;
+  const int k = (int)(t / g.B), b = (int)(t % g.B);
+  const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
+  const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
+  const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp, int_corners(g, xc, yc, sp));
+  if (a.hist_raw) a.hist_raw[t] = h;
+  if (a.hist) a.hist[t] = (float)((double)h / sp.mass);
+}
+
+template <int KIND>
+__device__ __forceinline__ void match_int(const MatchArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const uint32_t* __restrict__ planes = (const uint32_t*)a.planes;
+  const float* __restrict__ tmpl = a.tmpl;
+  const uint32_t* __restrict__ tmpl_raw = a.tmpl_raw;
+  const int x0 = a.x0, y0 = a.y0, x1 = a.x1, y1 = a.y1;
+  const int bx = vb % a.nbx, by = vb / a.nbx;
+  const int xc = x0 + bx * 64 + (int)(threadIdx.x & 63);
+  const int yc = y0 + by * 4 + (int)(threadIdx.x >> 6);
+  if (xc > x1 || yc > y1) return;
+  const IntCorners k = int_corners(g, xc, yc, sp);
+  double acc = 0.0;
+  for (int b = 0; b < g.B; ++b) {
+    const uint32_t h = hist_int<KIND>(planes, g, b, xc, yc, sp, k);
+    if (tmpl_raw) {
+      acc += sqrt((double)h * (double)tmpl_raw[b]);
+    } else {
+      acc += sqrt(((double)h / sp.mass) * fmax((double)tmpl[b], 0.0));
+    }
+  }
+  if (tmpl_raw) acc = acc / sp.mass;
+  a.map[(size_t)(yc - y0) * (x1 - x0 + 1) + (xc - x0)] = (float)acc;
+}
+
+// ---------------------------------------------------------------- Gaussian
+struct GaussPlanes {
+  const float* L;
+  const double* RC;
+};
+
+__device__ __forceinline__ int tile_of(int X) { return (X > 0 ? X - 1 : 0) >> 6; }
+
+// First band-boundary row (a positive multiple of TY) at or after ya.
+__device__ __forceinline__ int first_cross(int ya, int TY) {
+  const int c = (ya + TY - 1) / TY * TY;
+  return c == 0 ? TY : c;
+}
+
+template <int NT>
+__device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double (&out)[NT]) {
+  out[0] = ax.a[0];
+#pragma unroll
+  for (int k = 1; k <= (NT - 1) / 2; ++k) {
+    double s, co;
+    sincos(ax.om[k] * (double)c, &s, &co);
+    out[2 * k - 1] = ax.a[k] * co;
+    out[2 * k] = ax.a[k] * s;
+  }
+}
+
+// One block per centre; threads over (bin, x term i) pairs compute
+// alpha_i sum_j beta_j B_ij into LDS, then one thread per bin adds the terms
+// in order i = 0..NT-1.  Term (0, 0) is the plain pixel count (u_0 = v_0 = 1
+// exactly), and its box is an exact integer: a bin with no pixel in the
+// window gets p_b = 0 exactly instead of a rounding residue.
+template <int NT>
+__device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const GaussPlanes gp{(const float*)a.planes, a.RC};
+  const int32_t* __restrict__ centres = a.centres;
+  __syncthreads();  // LDS reuse across virtual blocks of one block
+  extern __shared__ double part[];  // [B][NT], then the window's pixel count per bin [B]
+  const int k = vb;
+  const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
+  const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
+  double al[NT], be[NT];
+  series_coeffs<NT>(sp.ax, xc, al);
+  series_coeffs<NT>(sp.ay, yc, be);
+  const int xa = xc - sp.rx, xb = xc + sp.rx + 1, ya = yc - sp.ry, yb = yc + sp.ry + 1;
+  const int64_t rs = g.row_stride;
+  const int txa = tile_of(xa), txb = tile_of(xb);
+  // column X = 0 is not stored (it is zero): its loads go to column 1 and are dropped
+  const bool xa0 = xa == 0;
+  const int64_t oa = swih_xoff(g, xa0 ? 1 : xa), ob = swih_xoff(g, xb);
+  for (int it = threadIdx.x; it < g.B * NT; it += blockDim.x) {
+    const int b = it / NT, i = it - (it / NT) * NT;
+    // the NT y-term planes of x term i sit 64 elements apart within a row
+    const float* lp = gp.L + swih_base(g, i * NT, b);
+    float aA[NT], bA[NT], aB[NT], bB[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const float* q = lp + (size_t)j * 64;
+      aA[j] = xa0 ? 0.0f : q[(size_t)ya * rs + oa];
+      bA[j] = xa0 ? 0.0f : q[(size_t)yb * rs + oa];
+      aB[j] = q[(size_t)ya * rs + ob];
+      bB[j] = q[(size_t)yb * rs + ob];
+    }
+    double d[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      d[j] = ((double)bB[j] - (double)aB[j]) - ((double)bA[j] - (double)aA[j]);
+    for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const float* q = lp + (size_t)j * 64 + (size_t)c * rs;
+        d[j] += (double)q[ob] - (xa0 ? 0.0 : (double)q[oa]);
+      }
+    }
+    double hi = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int p = i * NT + j;
+      d[j] += (gp.RC[swih_rc(g, p, b, txb, yb)] - gp.RC[swih_rc(g, p, b, txb, ya)]) -
+              (gp.RC[swih_rc(g, p, b, txa, yb)] - gp.RC[swih_rc(g, p, b, txa, ya)]);
+      hi = fma(be[j], d[j], hi);
+    }
+    part[it] = al[i] * hi;
+    if (i == 0) part[g.B * NT + b] = d[0];
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
+    double h = 0.0;
+    for (int i = 0; i < NT; ++i) h += part[b * NT + i];
+    if (part[g.B * NT + b] == 0.0) h = 0.0;
+    a.hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
+  }
+}
+
+// A block-uniform double made visibly uniform (kept in scalar registers).
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// A Gaussian map value is sum_b sqrt(p_b t_b).  Each bin's term is rounded to
+// a multiple of 2^-29 and the terms are added as integers: exact, so the sum
+// is the same whatever the order in which bins arrive (bin groups and integer
+// atomics, or all bins in one block).  The sum is at most 1 (Cauchy-Schwarz;
+// the rounding of p and t moves it by ~1e-6), so it fits an int32 with room
+// to spare, and 2^-30 per bin is far below the float resolution of the result.
+constexpr double kBcScale = 536870912.0;  // 2^29
+
+__device__ __forceinline__ int32_t bc_term(double p, float t) {
+  return (int32_t)__builtin_rint(sqrt(fmax(p, 0.0) * fmax((double)t, 0.0)) * kBcScale);
+}
+
+__device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q / kBcScale); }
+
+// Empty bins.  sqrt is not Lipschitz at 0: a bin with no pixel in the window
+// must give p_b = 0 exactly, or a rounding residue e of the float planes
+// turns into sqrt(e t_b), orders of magnitude above e.  The weight term
+// (0, 0) is the plain pixel count (u_0 = v_0 = 1 exactly), and every part of
+// its box is an integer (tile-local float values below 2^24, double carries),
+// so the count is exact and the maps drop a bin's term exactly when it is 0.
+
+// Gaussian maps: the comb sweep.
+//
+// With the y terms contracted at the centre row, V_i(X) = sum_j beta_j(yc)
+// (P_ij[Yb][X] - P_ij[Ya][X]) (Ya = yc - ry, Yb = yc + ry + 1), a window's
+// histogram is H_b(xc) = sum_i alpha_i(xc) (V_i(xc + rx + 1) - V_i(xc - rx)).
+// Each plane column therefore folds its V_i into the two values the windows
+// need from it,
+//   G+(X) = sum_i alpha_i(X - rx - 1) V_i(X)   (X is a window's right edge)
+//   G-(X) = sum_i alpha_i(X + rx) V_i(X)       (X is a window's left edge),
+// and H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).  The box difference of the
+// tile-local storage is
+//   P[Yb] - P[Ya] = L[Yb] - L[Ya] + sum_c L[c] + RC[Yb] - RC[Ya],
+// c the band-closing rows (multiples of TY) in [Ya, Yb).  When Ya itself
+// closes a band its L cancels against the crossing at c = Ya, so both drop.
+// A column's V is a sum of row events, each contracted with beta(yc): the
+// opening row Ya (minus), the crossings, the boundary row Yb (plus).  The
+// row-carry part R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) is the same for
+// every column of a tile: lanes 0..NT of the tile's wave contract one x term
+// each (lane NT the count plane) and the wave broadcasts the results.
+//
+// Combs.  The centre rows yc = y0 + q + m h (h the window height) of comb q
+// follow one another so that member m's boundary row is member m + 1's
+// opening row.  A block walks a segment of S members of one comb, reading
+// each boundary row once and contracting it twice (with beta(yc_m) for the
+// member it closes and beta(yc_m+1) for the one it opens).
+//
+// Work item = (bin group, segment, comb, column chunk), chunks fastest so that
+// the tiles two chunks share and the band-closing rows of neighbouring combs
+// are read close together (one XCD's L2, below); a block has one wave
+// per 64-column tile of its chunk (one thread per plane column, every weight
+// term of the column in that thread), loops over the group's bins and walks
+// the segment for each.  Rows are read in load units (IG x terms, all their
+// y terms) through two register buffers: the next unit's loads are issued
+// before the current unit is contracted, so every wave keeps a unit in
+// flight through the contraction, the barrier and the window phase.  Per
+// member, the column threads put G+, G- and the column's pixel count N (term
+// (0, 0)) into LDS (double-buffered, one barrier) and the window threads add
+// the bin's term sqrt(p_b t_b) to their (member, window) accumulator in LDS.
+// With one bin group the map is stored once at the end; with several, each
+// group adds its sums into the set's integer accumulator and
+// match_gauss_fin writes the map.  A segment of one member is the plain
+// two-row form.  All forms do the same operations in the same order for
+// every (window, bin), so their maps agree bit for bit.
+enum : int { kEvOpen = 0, kEvCross = 1, kEvBound = 2, kEvEnd = 3 };
+
+struct SweepEv {
+  int b, mm, Y, type, Ya, k;  // bin, member, row, kind, the member's opening row, load unit
+};
+
+// The event after e (unit 0 of it) in the walk of a segment of cnt members
+// over bins [., b1).
+__device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1, int h, int TY,
+                                              int Ya0) {
+  SweepEv n = e;
+  n.k = 0;
+  int Ya = e.Ya, mm = e.mm, c;
+  if (e.type == kEvBound) {
+    if (mm + 1 >= cnt) {
+      if (e.b + 1 >= b1) {
+        n.type = kEvEnd;
+        return n;
+      }
+      n.b = e.b + 1;
+      n.mm = 0;
+      n.Y = n.Ya = Ya0;
+      n.type = kEvOpen;
+      return n;
+    }
+    mm += 1;
+    Ya = e.Y;
+    c = (Ya / TY + 1) * TY;
+  } else {
+    c = e.type == kEvOpen ? (Ya / TY + 1) * TY : e.Y + TY;
+  }
+  const int Yb = Ya + h;
+  n.mm = mm;
+  n.Ya = Ya;
+  n.Y = c < Yb ? c : Yb;
+  n.type = c < Yb ? kEvCross : kEvBound;
+  return n;
+}
+
+// x terms per load unit: two units of IG x NT floats stay within the
+// registers of three waves per SIMD.
+template <int NT>
+__host__ __device__ constexpr int sweep_ig() {
+  return NT <= 5 ? NT : (NT <= 7 ? 4 : (NT <= 11 ? 2 : 1));
+}
+
+// One load unit's contraction: x terms [K IG, K IG + IG) of the row in d.
+//   kEvOpen   (op, om) += alpha+-_i sum_j beta_j L_ij (beta of the member it opens)
+//   kEvCross  (gp, gm) += alpha+-_i sum_j beta_j L_ij (beta of its member)
+//   kEvBound  the same into (gp, gm), and, if NEXT, into (op, om) with bn
+//             (beta of the member it opens).
+// Rows that close a band open a member with nothing (their L cancels against
+// the crossing at the same row), so a boundary row that closes a band has
+// NEXT false and an opening row that closes one is not contracted at all.
+template <int NT, int IG, int K, int TYPE, bool NEXT>
+__device__ __forceinline__ void sweep_unit(const float (&d)[IG * NT], const double (&be)[NT],
+                                           const double (&bn)[NT], const double (&ap)[NT],
+                                           const double (&am)[NT], double& gp, double& gm,
+                                           double& op, double& om, double& gn, double& on) {
+#pragma unroll
+  for (int ii = 0; ii < IG; ++ii) {
+    constexpr int i0 = K * IG;
+    const int i = i0 + ii;
+    if (i >= NT) break;
+    double s = 0.0, sn = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const double lv = (double)d[ii * NT + j];
+      if (TYPE == kEvOpen) {
+        sn = fma(be[j], lv, sn);
+      } else {
+        s = fma(be[j], lv, s);
+        if (NEXT) sn = fma(bn[j], lv, sn);
+      }
+    }
+    if (TYPE == kEvOpen || NEXT) {
+      op = fma(ap[i], sn, op);
+      om = fma(am[i], sn, om);
+    }
+    if (TYPE != kEvOpen) {
+      gp = fma(ap[i], s, gp);
+      gm = fma(am[i], s, gm);
+    }
+  }
+  if (K == 0) {  // term (0, 0): the pixel count
+    const double lv = (double)d[0];
+    if (TYPE != kEvOpen) gn += lv;
+    if (TYPE == kEvOpen || NEXT) on = lv;
+  }
+}
+
+// The contraction of unit k of an event of kind type (uniform over the block).
+template <int NT, int IG, int K>
+__device__ __forceinline__ void sweep_unit_k(const float (&d)[IG * NT], int type, bool next,
+                                             const double (&be)[NT], const double (&bn)[NT],
+                                             const double (&ap)[NT], const double (&am)[NT],
+                                             double& gp, double& gm, double& op, double& om,
+                                             double& gn, double& on) {
+  if (type == kEvOpen)
+    sweep_unit<NT, IG, K, kEvOpen, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+  else if (type == kEvCross)
+    sweep_unit<NT, IG, K, kEvCross, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+  else if (next)
+    sweep_unit<NT, IG, K, kEvBound, true>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+  else
+    sweep_unit<NT, IG, K, kEvBound, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
+}
+
+// Unit k of a row, K from KLO up (compile-time paths for every unit).
+template <int NT, int IG, int KLO, int NU>
+__device__ __forceinline__ void sweep_dispatch(int k, const float (&d)[IG * NT], int type, bool next,
+                                               const double (&be)[NT], const double (&bn)[NT],
+                                               const double (&ap)[NT], const double (&am)[NT],
+                                               double& gp, double& gm, double& op, double& om,
+                                               double& gn, double& on) {
+  if constexpr (KLO < NU) {
+    if (k == KLO)
+      sweep_unit_k<NT, IG, KLO>(d, type, next, be, bn, ap, am, gp, gm, op, om, gn, on);
+    else
+      sweep_dispatch<NT, IG, KLO + 1, NU>(k, d, type, next, be, bn, ap, am, gp, gm, op, om, gn, on);
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
+  constexpr int IG = sweep_ig<NT>();           // x terms per load unit
+  constexpr int NU = (NT + IG - 1) / IG;       // load units per row
+  const SwihGeom& g = a.g;
+  const ScaleParams& sp = a.sp;
+  const int ch = vb % a.nch;
+  int r = vb / a.nch;
+  const int q = r % a.ncomb;
+  r /= a.ncomb;
+  const int sg = r % a.nseg;
+  const int grp = r / a.nseg;
+  const int ny = a.y1 - a.y0 + 1, rx = sp.rx, ry = sp.ry, h = 2 * ry + 1;
+  const int Mq = q < ny ? (ny - q + h - 1) / h : 0;  // centre rows of comb q
+  const int m0 = sg * a.S;
+  if (m0 >= Mq) return;  // uniform over the block
+  const int cnt = min(a.S, Mq - m0);
+  const int b0 = grp * a.bpg, b1 = min(b0 + a.bpg, g.B);
+  const int xs = a.x0 + ch * a.cw, cwc = min(a.cw, a.x1 - xs + 1), xe = xs + cwc - 1;
+  // Waves over tiles: tiles ta.. (nl of them) then, in the two-range form,
+  // the right-edge tiles tr...  A column X >= 1 of tile t = (X - 1) / 64 is
+  // thread 64 w + (X - 1) % 64 of wave w.
+  const int ta = (max(xs - rx, 1) - 1) >> 6;
+  const int lastR = (xe + rx) >> 6;  // tile of the last right edge xe + rx + 1
+  const int lastL = a.two ? (max(xe - rx, 1) - 1) >> 6 : lastR;
+  const int nl = a.two ? lastL - ta + 1 : a.nt;
+  const int tr = a.two ? (xs + rx) >> 6 : ta + nl;
+  const int nV = 64 * a.nt;
+  const int tid = (int)threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tx = wv < nl ? ta + wv : tr + (wv - nl);  // the wave's tile
+  // a batch launch may have more waves than this item's tiles
+  const bool live = wv < a.nt, on = live && tx <= (wv < nl ? lastL : lastR);
+  const int X = 64 * tx + 1 + (tid & 63);
+  // LDS index of a left edge / right edge column (>= 1)
+  auto col_left = [&](int Xc) { return 64 * (((Xc - 1) >> 6) - ta) + ((Xc - 1) & 63); };
+  auto col_right = [&](int Xc) {
+    return a.two ? 64 * (nl + ((Xc - 1) >> 6) - tr) + ((Xc - 1) & 63) : col_left(Xc);
+  };
+  const int ycb = a.y0 + q + m0 * h;  // first centre row of the segment
+  const int Ya0 = ycb - ry;
+  const int TY = g.TY;
+  __syncthreads();  // LDS reuse across virtual blocks of one block
+  extern __shared__ double sm[];
+  double* Gb = sm;                                  // [2][3][nV]: G+, G-, N
+  double* BE = sm + 6 * nV;                         // [S][NT]: beta of the members
+  int32_t* acc = (int32_t*)(BE + (size_t)a.S * NT);  // [S][cw]
+  for (int mm = tid; mm < cnt; mm += (int)blockDim.x) {
+    double be[NT];
+    series_coeffs<NT>(sp.ay, ycb + mm * h, be);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) BE[mm * NT + j] = be[j];
+  }
+  // one bin per item: each member's terms go straight to the set's
+  // accumulator, so no LDS accumulator bounds the segment
+  const bool direct = a.ngroups > 1 && a.bpg == 1;
+  if (tid < cwc && !direct)
+    for (int mm = 0; mm < cnt; ++mm) acc[mm * a.cw + tid] = 0;
+  double ap[NT], am[NT];
+  series_coeffs<NT>(sp.ax, max(X - rx - 1, 0), ap);
+  series_coeffs<NT>(sp.ax, X + rx, am);
+  // the column's loads: plane (i, j) of bin b at row Y is at
+  // base(i, b) + Y row_stride + j 64 + the column's offset
+  const char* __restrict__ colp = (const char*)a.planes + swih_xoff(g, X) * 4;
+  const int64_t ibstride = (int64_t)g.B * g.NTX * g.tile_stride * 4;  // bytes from x term i to i + 1
+  const double inv_mass = 1.0 / sp.mass;
+  const int xw = xs + tid;  // this thread's window centre (tid < cwc)
+  const int iXb = col_right(xw + rx + 1), iXa = xw - rx > 0 ? col_left(xw - rx) : -1;
+  // an opening row that closes a band adds nothing and is not read
+  auto reads = [&](const SweepEv& e) { return on && (e.type != kEvOpen || e.Y % TY != 0); };
+  const int lane = tid & 63;
+  auto load = [&](float (&d)[IG * NT], double (&rc)[NT], const SweepEv& e) {
+    if (on && e.k == 0 && e.type != kEvCross && lane <= NT) {
+      // this lane's x term of the tile's row carries at the row (lane NT: term (0, 0))
+      const double* __restrict__ q = a.RC + swih_rc(g, lane < NT ? lane * NT : 0, e.b, tx, e.Y);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) rc[j] = (lane < NT || j == 0) ? q[j] : 0.0;
+    }
+    if (!reads(e)) return;
+    const int64_t row = (int64_t)(e.k * IG) * ibstride +
+                        ((int64_t)e.b * g.NTX * g.tile_stride + (int64_t)e.Y * g.row_stride) * 4;
+#pragma unroll
+    for (int ii = 0; ii < IG; ++ii) {
+      if (e.k * IG + ii >= NT) break;
+      const char* p = colp + (row + (int64_t)ii * ibstride);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) d[ii * NT + j] = *(const float*)(p + j * 256);
+    }
+  };
+  auto advance = [&](const SweepEv& e) {
+    if (e.k + 1 < NU) {
+      SweepEv n = e;
+      n.k = e.k + 1;
+      return n;
+    }
+    return sweep_next(e, cnt, b1, h, TY, Ya0);
+  };
+  double gp = 0.0, gm = 0.0, gn = 0.0;   // the member's G+, G-, N
+  double op = 0.0, om = 0.0, on_ = 0.0;  // the next member's opening sums
+  double bcur[NT], bnxt[NT];             // beta of the current and the next member
+  int par = 0;                           // LDS buffer parity
+  auto beta = [&](double (&bv)[NT], int mm) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) bv[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
+  };
+  // contract unit e of d; at the end of a boundary row, the member's window phase
+  double qprev = 0.0, rmine = 0.0;  // lanes 0..NT: beta(m) RC[Ya(m)] and the member's R
+  auto process = [&](const float (&d)[IG * NT], const double (&rc)[NT], const SweepEv& e) {
+    const bool withL = e.Y % TY != 0;  // as an opening row
+    const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
+    if (e.k == 0 && e.type == kEvOpen) {
+      beta(bcur, 0);
+      beta(bnxt, 1);
+    }
+    if (on && e.k == 0 && e.type != kEvCross && lane <= NT) {
+      // row carries: sum_j beta_j RC_ij at this row, for the member it closes
+      // (minus the same at its opening row) and for the one it opens
+      double sc = 0.0, sn = 0.0;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        sc = fma(bcur[j], rc[j], sc);
+        sn = fma(bnxt[j], rc[j], sn);
+      }
+      if (lane == NT) sc = sn = rc[0];
+      if (e.type == kEvBound) {
+        rmine = sc - qprev;
+        qprev = sn;
+      } else {
+        qprev = sc;
+      }
+    }
+    if (e.k == 0 && (e.type == kEvOpen || e.type == kEvBound)) op = om = on_ = 0.0;
+    if (on && (e.type != kEvOpen || withL)) {
+      static_assert(NU <= 17, "load units");
+      sweep_dispatch<NT, IG, 0, NU>(e.k, d, e.type, next, bcur, bnxt, ap, am, gp, gm, op, om, gn, on_);
+    }
+    if (e.k != NU - 1) return;
+    if (e.type == kEvOpen) {
+      gp = -op;
+      gm = -om;
+      gn = -on_;
+    } else if (e.type == kEvBound) {
+      if (on) {
+        // the member's contracted row carries, broadcast from lanes 0..NT
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+          const double ri = readlane(rmine, i);
+          gp = fma(ap[i], ri, gp);
+          gm = fma(am[i], ri, gm);
+        }
+        gn += readlane(rmine, NT);
+      }
+      double* Gp = Gb + par * 3 * nV;
+      if (live) {
+        Gp[tid] = gp;
+        Gp[nV + tid] = gm;
+        Gp[2 * nV + tid] = gn;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      if (tid < cwc) {
+        const double hp = Gp[iXb], cp = Gp[2 * nV + iXb];
+        const double hm = iXa >= 0 ? Gp[nV + iXa] : 0.0, cm = iXa >= 0 ? Gp[2 * nV + iXa] : 0.0;
+        const int32_t v = cp - cm != 0.0 ? bc_term((hp - hm) * inv_mass, a.tmpl[e.b]) : 0;
+        if (!direct) {
+          acc[e.mm * a.cw + tid] += v;
+        } else if (v != 0) {
+          const size_t o = (size_t)(ycb + e.mm * h - a.y0) * (a.x1 - a.x0 + 1) + (xw - a.x0);
+          atomicAdd((unsigned int*)&a.acc[o], (unsigned int)v);
+        }
+      }
+      par ^= 1;
+      gp = -op;
+      gm = -om;
+      gn = -on_;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bcur[j] = bnxt[j];
+      beta(bnxt, e.mm + 2);
+    }
+  };
+  __syncthreads();  // BE ready
+  SweepEv e0;
+  e0.b = b0;
+  e0.mm = 0;
+  e0.Y = e0.Ya = Ya0;
+  e0.type = kEvOpen;
+  e0.k = 0;
+  // Row-carry values arrive with unit 0 of a row and are used when that unit
+  // is contracted.  With two or more units per row the unit in between
+  // belongs to the previous row's tail, so one buffer serves; with one unit
+  // per row the two register buffers alternate with the plane buffers.
+  constexpr bool kTwoRC = NU == 1;
+  float dA[IG * NT], dB[IG * NT];
+  double rA[NT], rB[kTwoRC ? NT : 1];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) rA[j] = 0.0;
+  rB[0] = 0.0;
+  auto& rcB = [&]() -> double (&)[NT] {
+    if constexpr (kTwoRC) return rB;
+    else return rA;
+  }();
+  load(dA, rA, e0);
+  for (;;) {
+    const SweepEv e1 = advance(e0);
+    if (e1.type != kEvEnd) load(dB, rcB, e1);
+    process(dA, rA, e0);
+    if (e1.type == kEvEnd) break;
+    e0 = advance(e1);
+    if (e0.type != kEvEnd) load(dA, rA, e0);
+    process(dB, rcB, e1);
+    if (e0.type == kEvEnd) break;
+  }
+  if (tid < cwc && !direct) {
+    const int mw = a.x1 - a.x0 + 1;
+    for (int mm = 0; mm < cnt; ++mm) {
+      const size_t o = (size_t)(ycb + mm * h - a.y0) * mw + (xw - a.x0);
+      const int32_t v = acc[mm * a.cw + tid];
+      if (a.ngroups == 1) a.map[o] = bc_value(v);
+      else atomicAdd((unsigned int*)&a.acc[o], (unsigned int)v);
+    }
+  }
+}
+
+// Map from the accumulator of a sweep with several bin groups; the
+// accumulator is left zero.
+__device__ __forceinline__ void match_gauss_fin(const MatchArgs& a, int vb) {
+  const int mw = a.x1 - a.x0 + 1;
+  const long n = (long)mw * (a.y1 - a.y0 + 1);
+  const long t = (long)vb * 256 + threadIdx.x;
+  if (t >= n) return;
+  a.map[t] = bc_value(a.acc[t]);
+  a.acc[t] = 0;
+}
+
+}  // namespace
+}  // namespace swih

@@ -165,6 +165,14 @@ class BatchedRunner:
         for b in self.batches:
             b.run()
 
+    def run_fused(self):
+        """Each sub-batch in one persistent launch (swih_run_batch)."""
+        for b in self.batches:
+            b.run_fused()
+
+    def fused_status(self) -> int:
+        return max(b.fused_status() for b in self.batches)
+
     def capture(self):
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
