@@ -181,6 +181,12 @@ def cpu_baseline_multiscale(img, nsample=65536):
             "host": host_info()}
 
 
+def gauss_rc_bytes(K, B, H, W):
+    """Bytes of the Gaussian row carries a plane build writes: (2K+1)^2 weight
+    terms in FP64 per bin, tile column (64 pixels) and row."""
+    return 8 * (2 * K + 1) ** 2 * B * ((W + 63) // 64) * (H + 1)
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha1()
@@ -347,13 +353,14 @@ def run_multiscale(args):
         for ph in PHASES:
             per["%s_%d" % (ph, w)] = time_launches(lambda: phase(si, ph), reps[ph])
     nwin = [(N - w + 1) ** 2 for w in MS_SCALES]
-    T = (2 * cfgs[0].K + 1) ** 2
+    T = 2 * (2 * cfgs[0].K + 1) + 1
     plane_bytes = 4 * T * B * (N + 1) * (N + 1)
+    rc_bytes = gauss_rc_bytes(cfgs[0].K, B, N, N)
     nsc = len(MS_SCALES)
     kernels = {
-        "build": {"kernel": "emit_gauss (Gaussian plane build, %d terms x %d bins, 2048x2048; "
-                            "average over the 5 scales)" % (T, B),
-                  "alg": N * N + plane_bytes,
+        "build": {"kernel": "emit_gauss (Gaussian plane build, %d planes x %d bins + row carries, "
+                            "2048x2048; average over the 5 scales)" % (T, B),
+                  "alg": N * N + plane_bytes + rc_bytes,
                   "ms": sum(per["planes_%d" % w] for w in MS_SCALES) / nsc,
                   "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
         "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
@@ -378,8 +385,8 @@ def run_multiscale(args):
         per_scale[str(w)] = {
             "windows": nwin[si],
             "ms": build_ms + per["query_%d" % w] + per["match_%d" % w],
-            "ih_build_gbs": (N * N + plane_bytes) / (build_ms / 1e3) / 1e9,
-            "ih_build_frac": (N * N + plane_bytes) / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "ih_build_gbs": (N * N + plane_bytes + rc_bytes) / (build_ms / 1e3) / 1e9,
+            "ih_build_frac": (N * N + plane_bytes + rc_bytes) / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "map_gbs": (plane_bytes + 4 * nwin[si]) / (per["match_%d" % w] / 1e3) / 1e9}
     line = {
         "metric": METRIC,
@@ -623,6 +630,9 @@ def w3_builds(rep_small=10):
             t[ph] = a.elapsed_time(b) / (3 * rep)
             del g
         planes = 4 * bp.nplanes * 32 * (W3 + 1) * (W3 + 1)
+        # the Gaussian's emit also writes its FP64 row carries
+        if kname == "gaussian":
+            planes += gauss_rc_bytes(bp.cfg.K, 32, W3, W3)
         build_ms = t["carries"] + t["planes"]
         w3[kname] = {"ms": t, "plane_bytes": planes,
                      "build_gbs": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9,
@@ -989,11 +999,11 @@ def run_frame(args, side_kinds=True, builds=True, cpu=True):
     # the plane build reads the image once and writes every plane element once;
     # the dense map reads every plane element once and writes one float per centre.
     K = plans["gaussian"].cfg.K
-    T = (2 * K + 1) ** 2
+    T = 2 * (2 * K + 1) + 1
     plane_bytes = 4 * T * NBINS * (H + 1) * (W + 1)
     kernels = {
-        "build": {"kernel": "emit_gauss (Gaussian plane build, %d terms x 16 bins)" % T,
-                  "alg": H * W + plane_bytes, "ms": per["planes_gaussian"],
+        "build": {"kernel": "emit_gauss (Gaussian plane build, %d planes x 16 bins + row carries)" % T,
+                  "alg": H * W + plane_bytes + gauss_rc_bytes(K, NBINS, H, W), "ms": per["planes_gaussian"],
                   "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
         "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
                             "482x482 centres; the finalising pass is ~1% of the phase)",

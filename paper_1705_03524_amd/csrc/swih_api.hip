@@ -73,6 +73,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   g.NTY = (H + g.TY - 1) / g.TY;
   if (c->kernel == SWIH_EXPONENTIAL) {  // four direction planes per bin (swih_exp.hip)
     g.nP = 4;
+    g.nPL = 4;
     g.ppg = 1;
     g.row_stride = SWIH_TX;
     g.tile_stride = (int64_t)(H + 1) * g.row_stride;
@@ -97,20 +98,21 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   if (gauss) {
     g.nI = g.nJ = 2 * gauss_K(c) + 1;
     g.nP = g.nI * g.nJ;
-    g.ppg = g.nJ;
+    g.nPL = 2 * g.nJ + 1;  // edge-contracted planes V+, V-, N
   } else {
     static const int nI[3] = {1, 2, 3}, nP[3] = {1, 3, 5};
     g.nI = g.nJ = nI[c->kernel];
     g.nP = nP[c->kernel];
-    g.ppg = g.nP;
+    g.nPL = g.nP;
   }
+  g.ppg = g.nPL;
   g.row_stride = (int64_t)g.ppg * SWIH_TX;
   g.tile_stride = (int64_t)(H + 1) * g.row_stride;
   const int64_t PB = (int64_t)g.nP * g.B;
   const int64_t NXP = (int64_t)g.NTX * SWIH_TX;
   int64_t off = 0;
   L.off_planes = off;
-  off += swih_align256(PB * g.NTX * (int64_t)(H + 1) * SWIH_TX * 4);
+  off += swih_align256((int64_t)g.nPL * g.B * g.NTX * (int64_t)(H + 1) * SWIH_TX * 4);
   if (gauss) {
     L.off_RC = off;
     off += swih_align256(PB * g.NTX * (int64_t)(H + 1) * 8);
@@ -240,7 +242,7 @@ int build_phases(const swih_config* cfg, const uint8_t* d_img, int32_t height, i
   for (int k = first; k <= last; ++k) {
     ScaleParams sp;
     scale_params(cfg, gauss ? k : 0, sp);
-    if (launch_build(L, cfg->kernel, k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, d_img,
+    if (launch_build(L, cfg->kernel, k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, sp.rx, d_img,
                      pitch, (char*)d_ws, s, phases) != hipSuccess)
       return SWIH_ERR_HIP;
   }
@@ -665,7 +667,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
       ScaleParams sp;
       scale_params(&fc, gauss ? k : 0, sp);
       int32_t nb[4];
-      build_args(layouts[f], k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, fd.d_img,
+      build_args(layouts[f], k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, sp.rx, fd.d_img,
                  fd.pitch, (char*)fd.d_ws, units[u], nb, true);
       for (int s = 0; s < 4; ++s) upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + nb[s];
     }

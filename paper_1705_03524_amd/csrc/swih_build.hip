@@ -85,7 +85,7 @@ hipError_t run_batch(const BuildArgs* units, const int32_t* prefix, int nunits, 
 // chip busy (512 x 512, 16 bins: 5.4 against 5.9 us).
 constexpr int kHistMinTiles = 128;
 
-void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay,
+void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay, int32_t rx,
                 const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4],
                 bool batched) {
   const SwihGeom& g = L.g;
@@ -104,6 +104,7 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.nacc = (int64_t)g.H * g.W;
     a.ax = *ax;
     a.ay = *ay;
+    a.rx = rx;
   }
   a.z = sb + L.off_z;
   a.T = sb + L.off_T;
@@ -118,15 +119,15 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
   a.agg_hist = !g.gauss && int_hist(g.nI - 1, g.B) && (batched || g.NTY * g.NTX >= kHistMinTiles);
   nb[1] = a.agg_hist ? g.NTY * g.NTX : blocks_for_waves(waves);
   nb[2] = a.nb1 + a.nb2 + nb3;
-  nb[3] = blocks_for_waves(waves * (g.gauss ? g.nI + 1 : 1));  // Gaussian: + a row-carry wave
+  nb[3] = blocks_for_waves(waves * (g.gauss ? 2 : 1));  // Gaussian: a plane wave + a row-carry wave
 }
 
 hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,
-                        const GaussAxis* ay, const uint8_t* img, int32_t img_pitch, char* ws,
-                        hipStream_t stream, int phases) {
+                        const GaussAxis* ay, int32_t rx, const uint8_t* img, int32_t img_pitch,
+                        char* ws, hipStream_t stream, int phases) {
   BuildArgs a;
   int32_t nb[4];
-  build_args(L, set, ax, ay, img, img_pitch, ws, a, nb);
+  build_args(L, set, ax, ay, rx, img, img_pitch, ws, a, nb);
 #define SWIH_RUN1(ST) run_single<ST>(a, nb, phases, stream)
   SWIH_STAGE_DISPATCH(kind, L.g.nI, SWIH_RUN1)
 #undef SWIH_RUN1

@@ -600,11 +600,17 @@ __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) 
   }
 }
 
-// Planes of one (band, tile, bin, x term i), rows top to bottom:
-//   L_ij[y + 1] = L_ij[y] + v_j(y) R_i(y),  R_i the row prefix of u_i [Q = b]
-// inside the tile (an exact int32 DPP scan).  The launch interleaves one
-// row-carry wave (rc_gauss) after the NT plane waves of each (band, tile,
-// bin).
+// Planes of one (band, tile, bin), rows top to bottom.  The tile-local sums
+//   L_ij[y + 1] = L_ij[y] + v_j(y) R_i(y)
+// (R_i the row prefix of u_i [Q = b] inside the tile, an exact int32 DPP scan)
+// are contracted over the x terms as they grow, with the coefficients the
+// lane's column X needs as a right and as a left window edge:
+//   V+_j[y + 1] = V+_j[y] + v_j(y) S+(y),  S+(y) = sum_i alpha_i(X - rx - 1) R_i(y)
+//   V-_j[y + 1] = V-_j[y] + v_j(y) S-(y),  S-(y) = sum_i alpha_i(X + rx) R_i(y)
+//   N[y + 1]    = N[y] + (pixels of the bin in the row up to X),
+// so a row stores 2 NT + 1 values per column where the terms would store
+// NT^2.  The launch interleaves one row-carry wave (rc_gauss) after each
+// plane wave.
 template <int NT, int WGT = WG>
 __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
@@ -614,41 +620,64 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const double* __restrict__ vqd = a.vqd;
   float* __restrict__ Lp = (float*)a.planes;
   WaveTile t;
-  int i;
-  if (!wave_tile(g, wave_index<WGT / 64>(vb), NT + 1, t, i)) return;
-  if (i == NT) {
+  int e;
+  if (!wave_tile(g, wave_index<WGT / 64>(vb), 2, t, e)) return;
+  if (e == 1) {
     rc_gauss<NT>(a, t);
     return;
   }
   const int lane = lane_id();
-  const int32_t uqi = uq[(size_t)t.x * NT + i];
-  // the group's NT planes are consecutive 64-element runs of each row
-  float* lrow = Lp + swih_base(g, i * NT, t.b) + t.tx * g.tile_stride + lane;
-  // tile-local running sums in FP64, each rounded once to float when stored:
-  // the row prefix R is an exact integer, so the stored value carries one
-  // half-ulp of rounding and no accumulated error (FP64 FMA issues at the
-  // FP32 rate on gfx950, and the launch is bound by its stores)
-  double L[NT];
+  const int X = t.x + 1;  // this lane's plane column
+  int32_t uqi[NT];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    L[j] = 0.0;
-    if (t.ty == 0) lrow[j * 64] = 0.0f;
+  for (int i = 0; i < NT; ++i) uqi[i] = uq[(size_t)t.x * NT + i];
+  double ap[NT], am[NT];
+  series_coeffs<NT>(a.ax, max(X - a.rx - 1, 0), ap);
+  series_coeffs<NT>(a.ax, X + a.rx, am);
+  // a row's 2 NT + 1 planes are consecutive 64-element runs: V+ (j), V- (NT + j), N (2 NT)
+  float* col = Lp + swih_base(g, 0, t.b) + t.tx * g.tile_stride + lane;
+  constexpr int D = 2 * NT + 1;
+  // running sums in FP64, each rounded once to float when stored
+  double vp[NT], vm[NT];
+  int32_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) vp[j] = vm[j] = 0.0;
+  if (t.ty == 0) {
+#pragma unroll
+    for (int p = 0; p < D; ++p) col[p * 64] = 0.0f;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
     const int y = t.y0 + k;
     const bool m = bit_of(mask, k) != 0;
-    const double Rd = (double)wave_incl_scan(m ? uqi : 0);
+    double sp = 0.0, sm = 0.0;
+    int32_t r0 = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int32_t R = wave_incl_scan(m ? uqi[i] : 0);
+      if (i == 0) r0 = R;
+      sp = fma(ap[i], (double)R, sp);
+      sm = fma(am[i], (double)R, sm);
+    }
+    // u_0 = 1 is 2^24 in fixed point: the row's count up to X, exactly
+    cnt += r0 >> SWIH_FIX_BITS;
     const double* vrow = vqd + (size_t)y * NT;
     double vr[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) vr[j] = vrow[j];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) L[j] = fma(vr[j], Rd, L[j]);
+    for (int j = 0; j < NT; ++j) {
+      vp[j] = fma(vr[j], sp, vp[j]);
+      vm[j] = fma(vr[j], sm, vm[j]);
+    }
     // whole 256-byte runs: lanes past the last column write values never read
-    float* dst = lrow + (size_t)(y + 1) * g.row_stride;
+    float* dst = col + (size_t)(y + 1) * g.row_stride;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) dst[j * 64] = (float)L[j];
+    for (int j = 0; j < NT; ++j) {
+      dst[j * 64] = (float)vp[j];
+      dst[(NT + j) * 64] = (float)vm[j];
+    }
+    dst[2 * NT * 64] = (float)cnt;
   }
 }
 

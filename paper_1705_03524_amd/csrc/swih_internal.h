@@ -23,6 +23,21 @@ struct GaussAxis {
   double om[SWIH_MAX_K + 1];
 };
 
+// The series coefficients of one axis at centre coordinate c: (a_0,
+// a_k cos(w_k c), a_k sin(w_k c)) for k = 1..K, NT = 2K + 1 of them -- the
+// alpha (x) or beta (y) translation coefficients of Sec. 2.1.
+template <int NT>
+__device__ inline void series_coeffs(const GaussAxis& ax, int c, double (&out)[NT]) {
+  out[0] = ax.a[0];
+#pragma unroll
+  for (int k = 1; k <= (NT - 1) / 2; ++k) {
+    double s, co;
+    sincos(ax.om[k] * (double)c, &s, &co);
+    out[2 * k - 1] = ax.a[k] * co;
+    out[2 * k] = ax.a[k] * s;
+  }
+}
+
 // Per-scale constants shared by query and match.
 struct ScaleParams {
   int32_t w, h, rx, ry;
@@ -49,14 +64,14 @@ struct BuildArgs {
   int32_t* acc;       // Gaussian: the map accumulator of the set, cleared by the build
   int64_t nacc;
   int32_t agg_hist;   // integer kernels: aggregate by LDS histograms, a block per (band, tile)
-  int32_t pad;
+  int32_t rx;         // Gaussian: the set's window half-width (edge coefficients of the planes)
   GaussAxis ax, ay;
 };
 
 // Fill the arguments of one plane set; nb = blocks of the basis, aggregate,
 // scan and emit stages.  `batched`: the set is one unit of a batched build
 // (its aggregate may then use the histogram form at any size).
-void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay,
+void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay, int32_t rx,
                 const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4],
                 bool batched = false);
 
@@ -72,8 +87,8 @@ hipError_t launch_build_batch(int kind, int nt, int nbins, const BuildArgs* unit
 // `set` with the axis series of that scale.
 // phase bit 1 = carries (aggregate + scan), bit 2 = planes (emit).
 hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,
-                        const GaussAxis* ay, const uint8_t* img, int32_t img_pitch, char* ws,
-                        hipStream_t stream, int phases = 3);
+                        const GaussAxis* ay, int32_t rx, const uint8_t* img, int32_t img_pitch,
+                        char* ws, hipStream_t stream, int phases = 3);
 
 hipError_t launch_query(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const int32_t* centres, int32_t n, float* hist, uint32_t* hist_raw,

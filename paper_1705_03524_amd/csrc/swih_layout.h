@@ -8,8 +8,7 @@
 // feeds column X = x + 1, so tile tx owns columns X in [64 tx + 1, 64 tx + 64]
 // and band ty owns rows Y in [TY ty + 1, TY ty + TY].
 //
-// Planes come in groups of ppg: the y terms of one x term for the Gaussian,
-// all terms for the integer kernels.  Storage is tile-major: for one (group,
+// Planes come in groups of ppg (all of a bin's stored planes, one group).  Storage is tile-major: for one (group,
 // bin) the tile columns follow one another, each holding rows Y = 0..H, and a
 // row holds the group's ppg planes as consecutive runs of 64 elements:
 //   elem(p, b, Y, X) = ((grp B + b) NTX + tx) tile_stride + Y row_stride
@@ -25,12 +24,20 @@
 //   Manhattan  {1, x, y}                 (i, j) = (0,0) (1,0) (0,1)
 //   Euclidean  {1, x, y, x^2, y^2}       (0,0) (1,0) (0,1) (2,0) (0,2)
 //   Gaussian   all products of {1, cos(w_k x), sin(w_k x)}_{k=1..K}
-//              and the same in y: (2K+1)^2 terms, p = i * (2K+1) + j.
+//              and the same in y: NT^2 terms (NT = 2K+1), p = i * NT + j.
 //
-// Integer kernels store P itself as uint32 (arithmetic modulo 2^32).  The
-// Gaussian stores it split per tile (tile origin Xo = 64 tx, Yo = TY ty):
-//   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X  (float, bounded by the tile)
+// Integer kernels store P itself as uint32 (arithmetic modulo 2^32), one
+// plane per term.  The Gaussian splits P per tile (tile origin Xo = 64 tx,
+// Yo = TY ty):
+//   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X  (bounded by the tile)
 //   RC[tx][Y] = P[Y][Xo]                          (double, per row and tile column)
+// and stores L already contracted over its x terms with the coefficients a
+// window edge at column X needs (the set's window half-width rx fixed):
+//   V+_j[Y][X] = sum_i alpha_i(X - rx - 1) L_ij[Y][X]   (X a right edge)
+//   V-_j[Y][X] = sum_i alpha_i(X + rx) L_ij[Y][X]       (X a left edge)
+//   N[Y][X]    = L_00[Y][X]                           (the pixel count, exact)
+// alpha_i(c) the x series coefficient i at centre column c: 2 NT + 1 float
+// planes per bin (p = j, NT + j, 2 NT), where the terms would take NT^2.
 // RC is stored [bin][Y][tx][plane] (planes fastest): a lookup needs every plane of
 // a few tiles at one row, which is then one contiguous run.
 // with tx = tile of column X, ty = band of row Y, and zeros at row/column 0.
@@ -54,7 +61,8 @@ struct SwihGeom {
   int32_t H, W, B;       // image size, bins
   int32_t TY;            // band height (<= 64)
   int32_t NTX, NTY;      // tiles across, bands down
-  int32_t nP, nI, nJ;    // planes, x terms, y terms
+  int32_t nP, nI, nJ;    // weight terms, x terms, y terms
+  int32_t nPL;           // stored planes per bin (integer kernels: nP; Gaussian: 2 nJ + 1)
   int32_t gauss;         // 1 for the split Gaussian storage
   int32_t ppg;           // planes per interleaved group
   int64_t row_stride;    // 64 ppg: from row Y to row Y + 1 of one plane
@@ -77,7 +85,7 @@ __host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, in
   return swih_base(g, p, b) + (int64_t)Y * g.row_stride + swih_xoff(g, X);
 }
 
-// Element offset of the Gaussian row carry RC[tx][Y] of plane p, bin b:
+// Element offset of the Gaussian row carry RC[tx][Y] of weight term p, bin b:
 // [b][tx][Y][p], planes fastest.  A map step reads all planes of one row and
 // tile as one contiguous run, and the build writes each row of a tile as one.
 __host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int p, int b, int tx, int Y) {

@@ -344,7 +344,7 @@ void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   ql.threads = 256;
   if (L.g.gauss) {
     ql.blocks = n;
-    ql.lds = sizeof(double) * (size_t)L.g.B * (L.g.nI + 1);
+    ql.lds = sizeof(double) * (size_t)L.g.B * (2 * L.g.nJ + 1);
   } else {
     ql.blocks = (int32_t)(((long)n * L.g.B + 255) / 256);
     ql.lds = 0;

@@ -160,31 +160,24 @@ __device__ __forceinline__ int first_cross(int ya, int TY) {
   return c == 0 ? TY : c;
 }
 
-template <int NT>
-__device__ __forceinline__ void series_coeffs(const GaussAxis& ax, int c, double (&out)[NT]) {
-  out[0] = ax.a[0];
-#pragma unroll
-  for (int k = 1; k <= (NT - 1) / 2; ++k) {
-    double s, co;
-    sincos(ax.om[k] * (double)c, &s, &co);
-    out[2 * k - 1] = ax.a[k] * co;
-    out[2 * k] = ax.a[k] * s;
-  }
-}
-
-// One block per centre; threads over (bin, x term i) pairs compute
-// alpha_i sum_j beta_j B_ij into LDS, then one thread per bin adds the terms
-// in order i = 0..NT-1.  Term (0, 0) is the plain pixel count (u_0 = v_0 = 1
-// exactly), and its box is an exact integer: a bin with no pixel in the
-// window gets p_b = 0 exactly instead of a rounding residue.
+// One block per centre; threads over (bin, part) pairs, 2 NT + 1 parts per
+// bin, put the window's terms into LDS, then one thread per bin adds them in
+// order.  With XR = xc + rx + 1 and XL = xc - rx the window's edges,
+//   part j        beta_j (V+_j box at XR - V-_j box at XL)    (j < NT)
+//   part NT + i   alpha_i sum_j beta_j (RC_ij box: tiles of XR and XL)
+//   part 2 NT     the pixel count box (plane N and RC_00: exact integers)
+// where a "box" is the vertical difference at one column, P[yb] - P[ya], with
+// the band-closing rows in between.  A bin with no pixel in the window gets
+// p_b = 0 exactly instead of a rounding residue.
 template <int NT>
 __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
   const GaussPlanes gp{(const float*)a.planes, a.RC};
   const int32_t* __restrict__ centres = a.centres;
+  constexpr int D = 2 * NT + 1;
   __syncthreads();  // LDS reuse across virtual blocks of one block
-  extern __shared__ double part[];  // [B][NT], then the window's pixel count per bin [B]
+  extern __shared__ double part[];  // [B][2 NT + 1]
   const int k = vb;
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
@@ -197,46 +190,42 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   // column X = 0 is not stored (it is zero): its loads go to column 1 and are dropped
   const bool xa0 = xa == 0;
   const int64_t oa = swih_xoff(g, xa0 ? 1 : xa), ob = swih_xoff(g, xb);
-  for (int it = threadIdx.x; it < g.B * NT; it += blockDim.x) {
-    const int b = it / NT, i = it - (it / NT) * NT;
-    // the NT y-term planes of x term i sit 64 elements apart within a row
-    const float* lp = gp.L + swih_base(g, i * NT, b);
-    float aA[NT], bA[NT], aB[NT], bB[NT];
+  // the box at one column of plane pl: rows ya, yb and the band-closing rows between
+  auto box = [&](const float* pl, int64_t o) {
+    double d = (double)pl[(size_t)yb * rs + o] - (double)pl[(size_t)ya * rs + o];
+    for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) d += (double)pl[(size_t)c * rs + o];
+    return d;
+  };
+  auto rcbox = [&](int p, int b) {
+    return (gp.RC[swih_rc(g, p, b, txb, yb)] - gp.RC[swih_rc(g, p, b, txb, ya)]) -
+           (gp.RC[swih_rc(g, p, b, txa, yb)] - gp.RC[swih_rc(g, p, b, txa, ya)]);
+  };
+  for (int it = threadIdx.x; it < g.B * D; it += blockDim.x) {
+    const int b = it / D, r = it - (it / D) * D;
+    const float* pb = gp.L + swih_base(g, 0, b);
+    double v;
+    if (r < NT) {
+      const double dr = box(pb + (size_t)r * 64, ob);
+      const double dl = xa0 ? 0.0 : box(pb + (size_t)(NT + r) * 64, oa);
+      v = be[r] * (dr - dl);
+    } else if (r < 2 * NT) {
+      const int i = r - NT;
+      double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const float* q = lp + (size_t)j * 64;
-      aA[j] = xa0 ? 0.0f : q[(size_t)ya * rs + oa];
-      bA[j] = xa0 ? 0.0f : q[(size_t)yb * rs + oa];
-      aB[j] = q[(size_t)ya * rs + ob];
-      bB[j] = q[(size_t)yb * rs + ob];
+      for (int j = 0; j < NT; ++j) s = fma(be[j], rcbox(i * NT + j, b), s);
+      v = al[i] * s;
+    } else {
+      const double nr = box(pb + (size_t)(2 * NT) * 64, ob);
+      const double nl = xa0 ? 0.0 : box(pb + (size_t)(2 * NT) * 64, oa);
+      v = (nr - nl) + rcbox(0, b);
     }
-    double d[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-      d[j] = ((double)bB[j] - (double)aB[j]) - ((double)bA[j] - (double)aA[j]);
-    for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) {
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const float* q = lp + (size_t)j * 64 + (size_t)c * rs;
-        d[j] += (double)q[ob] - (xa0 ? 0.0 : (double)q[oa]);
-      }
-    }
-    double hi = 0.0;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int p = i * NT + j;
-      d[j] += (gp.RC[swih_rc(g, p, b, txb, yb)] - gp.RC[swih_rc(g, p, b, txb, ya)]) -
-              (gp.RC[swih_rc(g, p, b, txa, yb)] - gp.RC[swih_rc(g, p, b, txa, ya)]);
-      hi = fma(be[j], d[j], hi);
-    }
-    part[it] = al[i] * hi;
-    if (i == 0) part[g.B * NT + b] = d[0];
+    part[it] = v;
   }
   __syncthreads();
   for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
     double h = 0.0;
-    for (int i = 0; i < NT; ++i) h += part[b * NT + i];
-    if (part[g.B * NT + b] == 0.0) h = 0.0;
+    for (int r = 0; r < 2 * NT; ++r) h += part[b * D + r];
+    if (part[b * D + 2 * NT] == 0.0) h = 0.0;
     a.hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
   }
 }
@@ -265,30 +254,32 @@ __device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q 
 
 // Empty bins.  sqrt is not Lipschitz at 0: a bin with no pixel in the window
 // must give p_b = 0 exactly, or a rounding residue e of the float planes
-// turns into sqrt(e t_b), orders of magnitude above e.  The weight term
-// (0, 0) is the plain pixel count (u_0 = v_0 = 1 exactly), and every part of
-// its box is an integer (tile-local float values below 2^24, double carries),
-// so the count is exact and the maps drop a bin's term exactly when it is 0.
+// turns into sqrt(e t_b), orders of magnitude above e.  The plane N holds the
+// plain pixel count (the weight term (0, 0), u_0 = v_0 = 1 exactly), and
+// every part of its box is an integer (tile-local float values below 2^24,
+// double carries), so the count is exact and the maps drop a bin's term
+// exactly when it is 0.
 
 // Gaussian maps: the comb sweep.
 //
-// With the y terms contracted at the centre row, V_i(X) = sum_j beta_j(yc)
-// (P_ij[Yb][X] - P_ij[Ya][X]) (Ya = yc - ry, Yb = yc + ry + 1), a window's
-// histogram is H_b(xc) = sum_i alpha_i(xc) (V_i(xc + rx + 1) - V_i(xc - rx)).
-// Each plane column therefore folds its V_i into the two values the windows
-// need from it,
-//   G+(X) = sum_i alpha_i(X - rx - 1) V_i(X)   (X is a window's right edge)
-//   G-(X) = sum_i alpha_i(X + rx) V_i(X)       (X is a window's left edge),
-// and H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).  The box difference of the
-// tile-local storage is
+// A window's histogram is H_b(xc, yc) = sum_ij alpha_i(xc) beta_j(yc) B_ij,
+// B_ij the box of term (i, j).  The planes hold each column X already
+// contracted over i with the coefficients of the windows that have X as an
+// edge (right edge: xc = X - rx - 1, left edge: xc = X + rx), so with the y
+// terms contracted at the centre row,
+//   G+(X) = sum_j beta_j(yc) (V+_j[Yb][X] - V+_j[Ya][X])   (X a right edge)
+//   G-(X) = sum_j beta_j(yc) (V-_j[Yb][X] - V-_j[Ya][X])   (X a left edge)
+// (Ya = yc - ry, Yb = yc + ry + 1) and H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).
+// The box difference of the tile-local storage is
 //   P[Yb] - P[Ya] = L[Yb] - L[Ya] + sum_c L[c] + RC[Yb] - RC[Ya],
 // c the band-closing rows (multiples of TY) in [Ya, Yb).  When Ya itself
 // closes a band its L cancels against the crossing at c = Ya, so both drop.
-// A column's V is a sum of row events, each contracted with beta(yc): the
+// A column's G+- is a sum of row events, each contracted with beta(yc): the
 // opening row Ya (minus), the crossings, the boundary row Yb (plus).  The
-// row-carry part R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) is the same for
-// every column of a tile: lanes 0..NT of the tile's wave contract one x term
-// each (lane NT the count plane) and the wave broadcasts the results.
+// row carries are not contracted in x (they hold the tile's origin column):
+// R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) is the same for every column of
+// a tile, lanes 0..NT of the tile's wave contract one x term each (lane NT
+// the count) and every column adds sum_i alpha+-_i(X) R_i.
 //
 // Combs.  The centre rows yc = y0 + q + m h (h the window height) of comb q
 // follow one another so that member m's boundary row is member m + 1's
@@ -299,24 +290,23 @@ __device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q 
 // Work item = (bin group, segment, comb, column chunk), chunks fastest so that
 // the tiles two chunks share and the band-closing rows of neighbouring combs
 // are read close together (one XCD's L2, below); a block has one wave
-// per 64-column tile of its chunk (one thread per plane column, every weight
-// term of the column in that thread), loops over the group's bins and walks
-// the segment for each.  Rows are read in load units (IG x terms, all their
-// y terms) through two register buffers: the next unit's loads are issued
-// before the current unit is contracted, so every wave keeps a unit in
+// per 64-column tile of its chunk (one thread per plane column), loops over
+// the group's bins and walks the segment for each.  A row's 2 NT + 1 values
+// at the column come through two register buffers: the next row's loads are
+// issued before the current row is contracted, so every wave keeps a row in
 // flight through the contraction, the barrier and the window phase.  Per
-// member, the column threads put G+, G- and the column's pixel count N (term
-// (0, 0)) into LDS (double-buffered, one barrier) and the window threads add
-// the bin's term sqrt(p_b t_b) to their (member, window) accumulator in LDS.
-// With one bin group the map is stored once at the end; with several, each
-// group adds its sums into the set's integer accumulator and
-// match_gauss_fin writes the map.  A segment of one member is the plain
-// two-row form.  All forms do the same operations in the same order for
-// every (window, bin), so their maps agree bit for bit.
+// member, the column threads put G+, G- and the column's pixel count N into
+// LDS (double-buffered, one barrier) and the window threads add the bin's
+// term sqrt(p_b t_b) to their (member, window) accumulator in LDS.  With one
+// bin group the map is stored once at the end; with several, each group adds
+// its sums into the set's integer accumulator and match_gauss_fin writes the
+// map.  A segment of one member is the plain two-row form.  All forms do the
+// same operations in the same order for every (window, bin), so their maps
+// agree bit for bit.
 enum : int { kEvOpen = 0, kEvCross = 1, kEvBound = 2, kEvEnd = 3 };
 
 struct SweepEv {
-  int b, mm, Y, type, Ya, k;  // bin, member, row, kind, the member's opening row, load unit
+  int b, mm, Y, type, Ya;  // bin, member, row, kind, the member's opening row
 };
 
 // The event after e (unit 0 of it) in the walk of a segment of cnt members
@@ -324,7 +314,6 @@ struct SweepEv {
 __device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1, int h, int TY,
                                               int Ya0) {
   SweepEv n = e;
-  n.k = 0;
   int Ya = e.Ya, mm = e.mm, c;
   if (e.type == kEvBound) {
     if (mm + 1 >= cnt) {
@@ -352,94 +341,55 @@ __device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1,
   return n;
 }
 
-// x terms per load unit: two units of IG x NT floats stay within the
-// registers of three waves per SIMD.
-template <int NT>
-__host__ __device__ constexpr int sweep_ig() {
-  return NT <= 5 ? NT : (NT <= 7 ? 4 : (NT <= 11 ? 2 : 1));
-}
-
-// One load unit's contraction: x terms [K IG, K IG + IG) of the row in d.
-//   kEvOpen   (op, om) += alpha+-_i sum_j beta_j L_ij (beta of the member it opens)
-//   kEvCross  (gp, gm) += alpha+-_i sum_j beta_j L_ij (beta of its member)
-//   kEvBound  the same into (gp, gm), and, if NEXT, into (op, om) with bn
-//             (beta of the member it opens).
+// One row's contraction for the member(s) of event e: d holds the row's 2 NT + 1
+// values at the column (V+_j, V-_j, N).
+//   kEvOpen   (op, om, on) = the row with beta of the member it opens
+//   kEvCross  (gp, gm, gn) += the row with beta of its member
+//   kEvBound  the same, and, if NEXT, (op, om, on) with bn (the member it opens).
 // Rows that close a band open a member with nothing (their L cancels against
 // the crossing at the same row), so a boundary row that closes a band has
 // NEXT false and an opening row that closes one is not contracted at all.
-template <int NT, int IG, int K, int TYPE, bool NEXT>
-__device__ __forceinline__ void sweep_unit(const float (&d)[IG * NT], const double (&be)[NT],
-                                           const double (&bn)[NT], const double (&ap)[NT],
-                                           const double (&am)[NT], double& gp, double& gm,
-                                           double& op, double& om, double& gn, double& on) {
-#pragma unroll
-  for (int ii = 0; ii < IG; ++ii) {
-    constexpr int i0 = K * IG;
-    const int i = i0 + ii;
-    if (i >= NT) break;
-    double s = 0.0, sn = 0.0;
+template <int NT>
+__device__ __forceinline__ void sweep_row(const float (&d)[2 * NT + 1], int type, bool next,
+                                          const double (&be)[NT], const double (&bn)[NT],
+                                          double& gp, double& gm, double& gn, double& op,
+                                          double& om, double& on) {
+  if (type == kEvOpen) {
+    double sp = 0.0, sm = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const double lv = (double)d[ii * NT + j];
-      if (TYPE == kEvOpen) {
-        sn = fma(be[j], lv, sn);
-      } else {
-        s = fma(be[j], lv, s);
-        if (NEXT) sn = fma(bn[j], lv, sn);
-      }
+      sp = fma(be[j], (double)d[j], sp);
+      sm = fma(be[j], (double)d[NT + j], sm);
     }
-    if (TYPE == kEvOpen || NEXT) {
-      op = fma(ap[i], sn, op);
-      om = fma(am[i], sn, om);
-    }
-    if (TYPE != kEvOpen) {
-      gp = fma(ap[i], s, gp);
-      gm = fma(am[i], s, gm);
+    op = sp;
+    om = sm;
+    on = (double)d[2 * NT];
+    return;
+  }
+  double sp = 0.0, sm = 0.0, np = 0.0, nm = 0.0;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const double vpj = (double)d[j], vmj = (double)d[NT + j];
+    sp = fma(be[j], vpj, sp);
+    sm = fma(be[j], vmj, sm);
+    if (next) {
+      np = fma(bn[j], vpj, np);
+      nm = fma(bn[j], vmj, nm);
     }
   }
-  if (K == 0) {  // term (0, 0): the pixel count
-    const double lv = (double)d[0];
-    if (TYPE != kEvOpen) gn += lv;
-    if (TYPE == kEvOpen || NEXT) on = lv;
-  }
-}
-
-// The contraction of unit k of an event of kind type (uniform over the block).
-template <int NT, int IG, int K>
-__device__ __forceinline__ void sweep_unit_k(const float (&d)[IG * NT], int type, bool next,
-                                             const double (&be)[NT], const double (&bn)[NT],
-                                             const double (&ap)[NT], const double (&am)[NT],
-                                             double& gp, double& gm, double& op, double& om,
-                                             double& gn, double& on) {
-  if (type == kEvOpen)
-    sweep_unit<NT, IG, K, kEvOpen, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
-  else if (type == kEvCross)
-    sweep_unit<NT, IG, K, kEvCross, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
-  else if (next)
-    sweep_unit<NT, IG, K, kEvBound, true>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
-  else
-    sweep_unit<NT, IG, K, kEvBound, false>(d, be, bn, ap, am, gp, gm, op, om, gn, on);
-}
-
-// Unit k of a row, K from KLO up (compile-time paths for every unit).
-template <int NT, int IG, int KLO, int NU>
-__device__ __forceinline__ void sweep_dispatch(int k, const float (&d)[IG * NT], int type, bool next,
-                                               const double (&be)[NT], const double (&bn)[NT],
-                                               const double (&ap)[NT], const double (&am)[NT],
-                                               double& gp, double& gm, double& op, double& om,
-                                               double& gn, double& on) {
-  if constexpr (KLO < NU) {
-    if (k == KLO)
-      sweep_unit_k<NT, IG, KLO>(d, type, next, be, bn, ap, am, gp, gm, op, om, gn, on);
-    else
-      sweep_dispatch<NT, IG, KLO + 1, NU>(k, d, type, next, be, bn, ap, am, gp, gm, op, om, gn, on);
+  gp += sp;
+  gm += sm;
+  gn += (double)d[2 * NT];
+  if (next) {
+    op = np;
+    om = nm;
+    on = (double)d[2 * NT];
   }
 }
 
 template <int NT>
 __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
-  constexpr int IG = sweep_ig<NT>();           // x terms per load unit
-  constexpr int NU = (NT + IG - 1) / IG;       // load units per row
+  constexpr int D = 2 * NT + 1;                // planes per row
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
   const int ch = vb % a.nch;
@@ -494,45 +444,34 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const bool direct = a.ngroups > 1 && a.bpg == 1;
   if (tid < cwc && !direct)
     for (int mm = 0; mm < cnt; ++mm) acc[mm * a.cw + tid] = 0;
+  // x coefficients of the column as a right / left edge (for the row carries;
+  // the planes hold them already)
   double ap[NT], am[NT];
   series_coeffs<NT>(sp.ax, max(X - rx - 1, 0), ap);
   series_coeffs<NT>(sp.ax, X + rx, am);
-  // the column's loads: plane (i, j) of bin b at row Y is at
-  // base(i, b) + Y row_stride + j 64 + the column's offset
+  // the column's loads: plane p of bin b at row Y is at
+  // base(0, b) + Y row_stride + p 64 + the column's offset
   const char* __restrict__ colp = (const char*)a.planes + swih_xoff(g, X) * 4;
-  const int64_t ibstride = (int64_t)g.B * g.NTX * g.tile_stride * 4;  // bytes from x term i to i + 1
   const double inv_mass = 1.0 / sp.mass;
   const int xw = xs + tid;  // this thread's window centre (tid < cwc)
   const int iXb = col_right(xw + rx + 1), iXa = xw - rx > 0 ? col_left(xw - rx) : -1;
   // an opening row that closes a band adds nothing and is not read
   auto reads = [&](const SweepEv& e) { return on && (e.type != kEvOpen || e.Y % TY != 0); };
   const int lane = tid & 63;
-  auto load = [&](float (&d)[IG * NT], double (&rc)[NT], const SweepEv& e) {
-    if (on && e.k == 0 && e.type != kEvCross && lane <= NT) {
+  auto load = [&](float (&d)[D], double (&rc)[NT], const SweepEv& e) {
+    if (on && e.type != kEvCross && lane <= NT) {
       // this lane's x term of the tile's row carries at the row (lane NT: term (0, 0))
       const double* __restrict__ q = a.RC + swih_rc(g, lane < NT ? lane * NT : 0, e.b, tx, e.Y);
 #pragma unroll
       for (int j = 0; j < NT; ++j) rc[j] = (lane < NT || j == 0) ? q[j] : 0.0;
     }
     if (!reads(e)) return;
-    const int64_t row = (int64_t)(e.k * IG) * ibstride +
-                        ((int64_t)e.b * g.NTX * g.tile_stride + (int64_t)e.Y * g.row_stride) * 4;
+    const char* p =
+        colp + ((int64_t)e.b * g.NTX * g.tile_stride + (int64_t)e.Y * g.row_stride) * 4;
 #pragma unroll
-    for (int ii = 0; ii < IG; ++ii) {
-      if (e.k * IG + ii >= NT) break;
-      const char* p = colp + (row + (int64_t)ii * ibstride);
-#pragma unroll
-      for (int j = 0; j < NT; ++j) d[ii * NT + j] = *(const float*)(p + j * 256);
-    }
+    for (int q = 0; q < D; ++q) d[q] = *(const float*)(p + q * 256);
   };
-  auto advance = [&](const SweepEv& e) {
-    if (e.k + 1 < NU) {
-      SweepEv n = e;
-      n.k = e.k + 1;
-      return n;
-    }
-    return sweep_next(e, cnt, b1, h, TY, Ya0);
-  };
+  auto advance = [&](const SweepEv& e) { return sweep_next(e, cnt, b1, h, TY, Ya0); };
   double gp = 0.0, gm = 0.0, gn = 0.0;   // the member's G+, G-, N
   double op = 0.0, om = 0.0, on_ = 0.0;  // the next member's opening sums
   double bcur[NT], bnxt[NT];             // beta of the current and the next member
@@ -541,16 +480,16 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) bv[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
   };
-  // contract unit e of d; at the end of a boundary row, the member's window phase
+  // contract row e of d; at a boundary row, the member's window phase
   double qprev = 0.0, rmine = 0.0;  // lanes 0..NT: beta(m) RC[Ya(m)] and the member's R
-  auto process = [&](const float (&d)[IG * NT], const double (&rc)[NT], const SweepEv& e) {
+  auto process = [&](const float (&d)[D], const double (&rc)[NT], const SweepEv& e) {
     const bool withL = e.Y % TY != 0;  // as an opening row
     const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
-    if (e.k == 0 && e.type == kEvOpen) {
+    if (e.type == kEvOpen) {
       beta(bcur, 0);
       beta(bnxt, 1);
     }
-    if (on && e.k == 0 && e.type != kEvCross && lane <= NT) {
+    if (on && e.type != kEvCross && lane <= NT) {
       // row carries: sum_j beta_j RC_ij at this row, for the member it closes
       // (minus the same at its opening row) and for the one it opens
       double sc = 0.0, sn = 0.0;
@@ -567,12 +506,9 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
         qprev = sc;
       }
     }
-    if (e.k == 0 && (e.type == kEvOpen || e.type == kEvBound)) op = om = on_ = 0.0;
-    if (on && (e.type != kEvOpen || withL)) {
-      static_assert(NU <= 17, "load units");
-      sweep_dispatch<NT, IG, 0, NU>(e.k, d, e.type, next, bcur, bnxt, ap, am, gp, gm, op, om, gn, on_);
-    }
-    if (e.k != NU - 1) return;
+    if (e.type == kEvOpen || e.type == kEvBound) op = om = on_ = 0.0;
+    if (on && (e.type != kEvOpen || withL))
+      sweep_row<NT>(d, e.type, next, bcur, bnxt, gp, gm, gn, op, om, on_);
     if (e.type == kEvOpen) {
       gp = -op;
       gm = -om;
@@ -623,30 +559,21 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   e0.mm = 0;
   e0.Y = e0.Ya = Ya0;
   e0.type = kEvOpen;
-  e0.k = 0;
-  // Row-carry values arrive with unit 0 of a row and are used when that unit
-  // is contracted.  With two or more units per row the unit in between
-  // belongs to the previous row's tail, so one buffer serves; with one unit
-  // per row the two register buffers alternate with the plane buffers.
-  constexpr bool kTwoRC = NU == 1;
-  float dA[IG * NT], dB[IG * NT];
-  double rA[NT], rB[kTwoRC ? NT : 1];
+  // two register buffers (planes and row carries) alternate: the next row's
+  // loads are in flight while the current row is contracted
+  float dA[D], dB[D];
+  double rA[NT], rB[NT];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) rA[j] = 0.0;
-  rB[0] = 0.0;
-  auto& rcB = [&]() -> double (&)[NT] {
-    if constexpr (kTwoRC) return rB;
-    else return rA;
-  }();
+  for (int j = 0; j < NT; ++j) rA[j] = rB[j] = 0.0;
   load(dA, rA, e0);
   for (;;) {
     const SweepEv e1 = advance(e0);
-    if (e1.type != kEvEnd) load(dB, rcB, e1);
+    if (e1.type != kEvEnd) load(dB, rB, e1);
     process(dA, rA, e0);
     if (e1.type == kEvEnd) break;
     e0 = advance(e1);
     if (e0.type != kEvEnd) load(dA, rA, e0);
-    process(dB, rcB, e1);
+    process(dB, rB, e1);
     if (e0.type == kEvEnd) break;
   }
   if (tid < cwc && !direct) {

@@ -234,7 +234,7 @@ def plane_bytes(cfg: S.Config, units) -> int:
         if cfg.kernel == S.GAUSSIAN_SEP:
             tot += sum(4 * cfg.nbins * H * (W - w + 1) for w, _ in u.scales)
             continue
-        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4}.get(cfg.kernel, (2 * K + 1) ** 2)
+        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4}.get(cfg.kernel, 2 * (2 * K + 1) + 1)
         nsets = len(u.scales) if cfg.kernel in (S.GAUSSIAN, S.EXPONENTIAL) else 1
         tot += nsets * 4 * T * cfg.nbins * (H + 1) * (W + 1)
     return tot
