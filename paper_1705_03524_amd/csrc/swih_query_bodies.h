@@ -458,12 +458,15 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   // an opening row that closes a band adds nothing and is not read
   auto reads = [&](const SweepEv& e) { return on && (e.type != kEvOpen || e.Y % TY != 0); };
   const int lane = tid & 63;
-  auto load = [&](float (&d)[D], double (&rc)[NT], const SweepEv& e) {
-    if (on && e.type != kEvCross && lane <= NT) {
-      // this lane's x term of the tile's row carries at the row (lane NT: term (0, 0))
-      const double* __restrict__ q = a.RC + swih_rc(g, lane < NT ? lane * NT : 0, e.b, tx, e.Y);
+  // the tile's row carries at a row: NT^2 doubles, one contiguous run, lane l
+  // holding terms l, l + 64, ...
+  constexpr int RCN = (NT * NT + 63) / 64;
+  auto load = [&](float (&d)[D], double (&rc)[RCN], const SweepEv& e) {
+    if (on && e.type != kEvCross) {
+      const double* __restrict__ q = a.RC + swih_rc(g, 0, e.b, tx, e.Y);
 #pragma unroll
-      for (int j = 0; j < NT; ++j) rc[j] = (lane < NT || j == 0) ? q[j] : 0.0;
+      for (int k = 0; k < RCN; ++k)
+        if (lane + 64 * k < NT * NT) rc[k] = q[lane + 64 * k];
     }
     if (!reads(e)) return;
     const char* p =
@@ -482,28 +485,41 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   };
   // contract row e of d; at a boundary row, the member's window phase
   double qprev = 0.0, rmine = 0.0;  // lanes 0..NT: beta(m) RC[Ya(m)] and the member's R
-  auto process = [&](const float (&d)[D], const double (&rc)[NT], const SweepEv& e) {
+  auto process = [&](const float (&d)[D], const double (&rc)[RCN], const SweepEv& e) {
     const bool withL = e.Y % TY != 0;  // as an opening row
     const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
     if (e.type == kEvOpen) {
       beta(bcur, 0);
       beta(bnxt, 1);
     }
-    if (on && e.type != kEvCross && lane <= NT) {
+    if (on && e.type != kEvCross) {
       // row carries: sum_j beta_j RC_ij at this row, for the member it closes
-      // (minus the same at its opening row) and for the one it opens
-      double sc = 0.0, sn = 0.0;
+      // (minus the same at its opening row) and for the one it opens; lane
+      // i < NT gathers its x term's NT values from the lanes holding them,
+      // lane NT the count term (0, 0)
+      const int ib = lane < NT ? lane * NT : 0;
+      double sc = 0.0, sn = 0.0, v0 = 0.0;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        sc = fma(bcur[j], rc[j], sc);
-        sn = fma(bnxt[j], rc[j], sn);
+        const int p = ib + j;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < RCN; ++k) {
+          const double t = __shfl(rc[k], p & 63);
+          if ((p >> 6) == k) v = t;
+        }
+        if (j == 0) v0 = v;
+        sc = fma(bcur[j], v, sc);
+        sn = fma(bnxt[j], v, sn);
       }
-      if (lane == NT) sc = sn = rc[0];
-      if (e.type == kEvBound) {
-        rmine = sc - qprev;
-        qprev = sn;
-      } else {
-        qprev = sc;
+      if (lane == NT) sc = sn = v0;
+      if (lane <= NT) {
+        if (e.type == kEvBound) {
+          rmine = sc - qprev;
+          qprev = sn;
+        } else {
+          qprev = sc;
+        }
       }
     }
     if (e.type == kEvOpen || e.type == kEvBound) op = om = on_ = 0.0;
@@ -562,9 +578,9 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   // two register buffers (planes and row carries) alternate: the next row's
   // loads are in flight while the current row is contracted
   float dA[D], dB[D];
-  double rA[NT], rB[NT];
+  double rA[RCN], rB[RCN];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) rA[j] = rB[j] = 0.0;
+  for (int k = 0; k < RCN; ++k) rA[k] = rB[k] = 0.0;
   load(dA, rA, e0);
   for (;;) {
     const SweepEv e1 = advance(e0);
