@@ -19,19 +19,19 @@ __global__ __launch_bounds__(1024) void k_one(A a) {
   BODY(a, (int)blockIdx.x);
 }
 
-// A single map's sweep: one block per item, renumbered so that each XCD
-// (workgroups go to the 8 XCDs round robin) runs a contiguous range of items,
-// i.e. the combs of one (bin group, chunk, segment) together, and the band-
-// closing rows they share stay in that XCD's L2.  Up to 170 registers: three
-// waves per SIMD, one block of twelve waves per compute unit.
+// A single map's sweep: one block of four waves per item, renumbered so that
+// each XCD (workgroups go to the 8 XCDs round robin) runs a contiguous range
+// of items, i.e. neighbouring chunks of one (bin group, segment, comb)
+// together, and the edge tiles and band-closing rows they share stay in that
+// XCD's L2.
 template <int NT>
-__global__ __launch_bounds__(768, 3) void k_sweep(MatchArgs a) {
+__global__ __launch_bounds__(256, 4) void k_sweep(MatchArgs a) {
   const int n = (int)gridDim.x, base = n >> 3, rem = n & 7;
   const int x = (int)blockIdx.x & 7, k = (int)blockIdx.x >> 3;
   match_gauss_sweep<NT>(a, x * base + (x < rem ? x : rem) + k);
 }
 
-// The batched sweep, with the register budget of k_sweep.
+// The batched sweep: blocks of twelve waves (three per SIMD, up to 170 registers).
 template <void (*BODY)(const MatchArgs&, int)>
 __global__ __launch_bounds__(768, 3) void k_many_sweep(const MatchArgs* __restrict__ items,
                                                        const int32_t* __restrict__ prefix, int n) {
@@ -180,51 +180,16 @@ hipError_t query_many(int kind, int nt, const QueryArgs* jobs, const int32_t* pr
 
 namespace {
 
-constexpr int kSweepMaxTiles = 12;     // waves of a sweep block: 768 threads
+constexpr int kSweepWaves = 4;         // waves of a single map's sweep block
+constexpr int kSweepBatchWaves = 12;   // waves of a batch's sweep block (the fused launch's shape)
+constexpr int kSweepMaxS = 24;         // members per segment, single maps
 constexpr int kSweepBatchS = 16;       // members per segment in batches
 constexpr size_t kLdsMax = 160 * 1024;
 
-// LDS of a sweep block: G+, G-, N double-buffered, beta of the members, and
-// (unless each item holds one bin of several groups) the (member, window)
+// LDS of a sweep block: beta of the members and each wave's (member, window)
 // accumulators.
-size_t sweep_lds(int nt, int S, int NT, int cw, bool direct) {
-  return sizeof(double) * (6 * 64 * (size_t)nt + (size_t)S * NT) +
-         (direct ? 0 : sizeof(int32_t) * (size_t)S * cw);
-}
-
-// Tiles (waves) a chunk of window centres [xs, xe] needs: one contiguous range
-// from the first left edge to the last right edge, or (two) the left-edge
-// tiles and the right-edge tiles apart.
-int sweep_tiles(int xs, int xe, int rx, bool two) {
-  const int ta = (std::max(xs - rx, 1) - 1) >> 6, tb = (xe + rx) >> 6;
-  if (!two) return tb - ta + 1;
-  const int tla = (std::max(xe - rx, 1) - 1) >> 6, trb = (xs + rx) >> 6;
-  return (tla - ta + 1) + (tb - trb + 1);
-}
-
-// Column chunks: the split with the fewest tile reads whose chunks all fit a block.
-void sweep_chunks(int x0, int nx, int rx, MatchArgs& a, int& two) {
-  long best = -1;
-  for (int t = 0; t < 2; ++t) {
-    for (int nch = 1; nch <= nx; ++nch) {
-      const int cw = (nx + nch - 1) / nch, n = (nx + cw - 1) / cw;
-      int nt = 0;
-      for (int c = 0; c < n; ++c) {
-        const int xs = x0 + c * cw, xe = std::min(xs + cw - 1, x0 + nx - 1);
-        nt = std::max(nt, sweep_tiles(xs, xe, rx, t == 1));
-      }
-      if (nt > kSweepMaxTiles) continue;
-      const long cost = (long)n * nt;
-      if (best < 0 || cost < best) {
-        best = cost;
-        a.nch = n;
-        a.cw = cw;
-        a.nt = nt;
-        two = t;
-      }
-      break;  // more chunks only add overlap
-    }
-  }
+size_t sweep_lds(int waves, int S, int NT) {
+  return sizeof(double) * (size_t)S * NT + sizeof(int32_t) * (size_t)waves * S * 64;
 }
 
 int device_cus() {
@@ -242,61 +207,38 @@ int device_cus() {
 
 }  // namespace
 
-// Plan of a Gaussian comb sweep over the centre rectangle: chunks, combs,
-// segments and bin groups, and the launch shape.  cus == 0: the batch form
-// (one bin group, segments of up to kSweepBatchS members).  Otherwise the
-// split that minimises a model of the time on `cus` compute units: rounds of
-// blocks times the work of one block (bins x tiles x rows read, crossings
-// counted at a quarter since neighbouring combs share them in L2), with a
-// small charge for the accumulator pass of several bin groups.
+// Plan of a Gaussian window sweep over the centre rectangle: chunks of 64
+// windows per wave, combs, segments and bin groups, and the launch shape.
+// cus == 0: the batch form (blocks of kSweepBatchWaves waves, one bin group,
+// segments of up to kSweepBatchS members).  Otherwise blocks of kSweepWaves,
+// segments of up to kSweepMaxS members (a segment costs one opening row per
+// bin), then bin groups (powers of two) until the launch has 32 waves per
+// compute unit to hide its loads' latency.
 static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int ny, int cus,
                        MatchArgs& a, Launch& ml) {
-  int two = 0;
-  sweep_chunks(x0, nx, sp.rx, a, two);
-  a.two = two;
   const int h = 2 * sp.ry + 1;
+  const int waves = cus > 0 ? kSweepWaves : kSweepBatchWaves;
+  a.two = 0;
+  a.nt = waves;
+  a.cw = 64 * waves;
+  // chunks start where a wave's right edges begin a tile (the sweep's xo)
+  const int xo = x0 - ((x0 + sp.rx) & 63);
+  a.nch = (x0 + nx - xo + a.cw - 1) / a.cw;
   a.ncomb = std::min(h, ny);
   const int Mq = (ny + h - 1) / h;
-  auto smax = [&](int S, bool direct) {
-    while (S > 1 && sweep_lds(a.nt, S, NT, a.cw, direct) > kLdsMax) --S;
-    return S;
-  };
-  if (cus <= 0) {
-    a.S = smax(std::min(Mq, kSweepBatchS), false);
-    a.nseg = (Mq + a.S - 1) / a.S;
-    a.ngroups = 1;
-    a.bpg = B;
-  } else {
-    const int bpc0 = std::max(1, 12 / a.nt);  // three waves per SIMD (register budget)
-    double best = -1.0;
-    for (int bpg = B; bpg >= 1; bpg = bpg > 1 ? (bpg + 1) / 2 : 0) {
-      const int ng = (B + bpg - 1) / bpg;
-      const bool direct = ng > 1 && bpg == 1;
-      const int Slim = smax(Mq, direct);
-      for (int nseg = (Mq + Slim - 1) / Slim; nseg <= Mq; ++nseg) {
-        const int S = (Mq + nseg - 1) / nseg;
-        const size_t lds = sweep_lds(a.nt, S, NT, a.cw, direct);
-        const int bpc = std::max(1, std::min(bpc0, (int)(kLdsMax / lds)));
-        const long items = (long)ng * a.nch * nseg * a.ncomb;
-        const long rounds = (items + (long)cus * bpc - 1) / ((long)cus * bpc);
-        const double rows = S + 1 + 0.25 * S * (double)(h - 1) / 64.0;
-        // several bin groups: the accumulator's read-modify-write traffic
-        const double t = (double)rounds * bpc * bpg * a.nt * rows * (ng > 1 ? 1.04 : 1.0);
-        if (best < 0 || t < best * 0.999) {
-          best = t;
-          a.S = S;
-          a.nseg = nseg;
-          a.ngroups = ng;
-          a.bpg = bpg;
-        }
-        if (S == 1) break;
-      }
-      if (bpg == 1) break;
-    }
+  const int smax = cus > 0 ? kSweepMaxS : kSweepBatchS;
+  a.nseg = (Mq + smax - 1) / smax;
+  a.S = (Mq + a.nseg - 1) / a.nseg;
+  int ng = 1;
+  if (cus > 0) {
+    const long base = (long)a.nseg * a.ncomb * a.nch * waves;
+    while (ng < B && base * ng < 32L * cus) ng *= 2;
   }
+  a.bpg = (B + ng - 1) / ng;
+  a.ngroups = (B + a.bpg - 1) / a.bpg;
   ml.blocks = a.ngroups * a.nch * a.nseg * a.ncomb;
-  ml.threads = 64 * a.nt;
-  ml.lds = sweep_lds(a.nt, a.S, NT, a.cw, a.ngroups > 1 && a.bpg == 1);
+  ml.threads = 64 * waves;
+  ml.lds = sweep_lds(waves, a.S, NT);
 }
 
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,

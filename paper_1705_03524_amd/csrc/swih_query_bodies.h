@@ -260,49 +260,49 @@ __device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q 
 // double carries), so the count is exact and the maps drop a bin's term
 // exactly when it is 0.
 
-// Gaussian maps: the comb sweep.
+// Gaussian maps: the window sweep.
 //
 // A window's histogram is H_b(xc, yc) = sum_ij alpha_i(xc) beta_j(yc) B_ij,
-// B_ij the box of term (i, j).  The planes hold each column X already
+// B_ij the box of term (i, j).  The planes hold every column X already
 // contracted over i with the coefficients of the windows that have X as an
-// edge (right edge: xc = X - rx - 1, left edge: xc = X + rx), so with the y
-// terms contracted at the centre row,
-//   G+(X) = sum_j beta_j(yc) (V+_j[Yb][X] - V+_j[Ya][X])   (X a right edge)
-//   G-(X) = sum_j beta_j(yc) (V-_j[Yb][X] - V-_j[Ya][X])   (X a left edge)
-// (Ya = yc - ry, Yb = yc + ry + 1) and H_b(xc) = G+(xc + rx + 1) - G-(xc - rx).
-// The box difference of the tile-local storage is
+// edge (right edge: xc = X - rx - 1, left edge: xc = X + rx), so with
+// XR = xc + rx + 1 and XL = xc - rx the window's edges
+//   H_b(xc, yc) = sum_j beta_j(yc) ((V+_j box at XR) - (V-_j box at XL))
+//                 + sum_i alpha_i(xc) sum_j beta_j(yc) (RC_ij box at XR - at XL)
+// where the box at one column is the vertical difference of the tile-local
+// storage,
 //   P[Yb] - P[Ya] = L[Yb] - L[Ya] + sum_c L[c] + RC[Yb] - RC[Ya],
-// c the band-closing rows (multiples of TY) in [Ya, Yb).  When Ya itself
-// closes a band its L cancels against the crossing at c = Ya, so both drop.
-// A column's G+- is a sum of row events, each contracted with beta(yc): the
-// opening row Ya (minus), the crossings, the boundary row Yb (plus).  The
-// row carries are not contracted in x (they hold the tile's origin column):
-// R_i = sum_j beta_j (RC_ij[Yb] - RC_ij[Ya]) is the same for every column of
-// a tile, lanes 0..NT of the tile's wave contract one x term each (lane NT
-// the count) and every column adds sum_i alpha+-_i(X) R_i.
+// (Ya = yc - ry, Yb = yc + ry + 1), c the band-closing rows (multiples of TY)
+// in [Ya, Yb).  When Ya itself closes a band its L cancels against the
+// crossing at c = Ya, so both drop.  The row carries RC hold the tile's origin
+// column and are not contracted in x: the RC box of a tile contracted with
+// beta is one value per x term for every column of the tile.
+//
+// Each lane owns one window centre and reads, per row event, its window's
+// 2 NT + 2 values (V+ and N at XR, V- and N at XL): a wave's 64 windows read
+// 64 consecutive columns at each edge, exactly what they need, and no window
+// waits for any other, so the sweep has no barrier.  A window's sum is a
+// sum of row events, each contracted with beta(yc): the opening row Ya
+// (minus), the crossings, the boundary row Yb (plus).
 //
 // Combs.  The centre rows yc = y0 + q + m h (h the window height) of comb q
 // follow one another so that member m's boundary row is member m + 1's
-// opening row.  A block walks a segment of S members of one comb, reading
-// each boundary row once and contracting it twice (with beta(yc_m) for the
-// member it closes and beta(yc_m+1) for the one it opens).
+// opening row.  A wave walks a segment of S members of one comb, reading each
+// boundary row once and contracting it twice (with beta(yc_m) for the member
+// it closes and beta(yc_m+1) for the one it opens).  Row carries: the wave's
+// right edges lie in at most two tiles and its left edges in two more; for
+// each, lanes 0..NT gather their x term's NT carries from the lanes that
+// loaded the tile's carry row and contract them with beta.
 //
-// Work item = (bin group, segment, comb, column chunk), chunks fastest so that
-// the tiles two chunks share and the band-closing rows of neighbouring combs
-// are read close together (one XCD's L2, below); a block has one wave
-// per 64-column tile of its chunk (one thread per plane column), loops over
-// the group's bins and walks the segment for each.  A row's 2 NT + 1 values
-// at the column come through two register buffers: the next row's loads are
-// issued before the current row is contracted, so every wave keeps a row in
-// flight through the contraction, the barrier and the window phase.  Per
-// member, the column threads put G+, G- and the column's pixel count N into
-// LDS (double-buffered, one barrier) and the window threads add the bin's
-// term sqrt(p_b t_b) to their (member, window) accumulator in LDS.  With one
-// bin group the map is stored once at the end; with several, each group adds
-// its sums into the set's integer accumulator and match_gauss_fin writes the
-// map.  A segment of one member is the plain two-row form.  All forms do the
-// same operations in the same order for every (window, bin), so their maps
-// agree bit for bit.
+// Work item = (bin group, segment, comb, chunk of cw windows, one wave per 64):
+// a wave loops over the group's bins and walks the segment for each, keeping
+// a row's loads in flight while the previous row is contracted, and adds the
+// bin's term sqrt(p_b t_b) to its (member, window) accumulator in LDS (each
+// lane its own entries).  With one bin group the map is stored once at the
+// end; with several, each group adds its sums into the set's integer
+// accumulator and match_gauss_fin writes the map.  Every split does the same
+// operations in the same order for every (window, bin), so maps agree bit for
+// bit.
 enum : int { kEvOpen = 0, kEvCross = 1, kEvBound = 2, kEvEnd = 3 };
 
 struct SweepEv {
@@ -341,55 +341,20 @@ __device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1,
   return n;
 }
 
-// One row's contraction for the member(s) of event e: d holds the row's 2 NT + 1
-// values at the column (V+_j, V-_j, N).
-//   kEvOpen   (op, om, on) = the row with beta of the member it opens
-//   kEvCross  (gp, gm, gn) += the row with beta of its member
-//   kEvBound  the same, and, if NEXT, (op, om, on) with bn (the member it opens).
-// Rows that close a band open a member with nothing (their L cancels against
-// the crossing at the same row), so a boundary row that closes a band has
-// NEXT false and an opening row that closes one is not contracted at all.
+// The window sum of one row event: sum_j beta_j (V+_j at XR - V-_j at XL).
 template <int NT>
-__device__ __forceinline__ void sweep_row(const float (&d)[2 * NT + 1], int type, bool next,
-                                          const double (&be)[NT], const double (&bn)[NT],
-                                          double& gp, double& gm, double& gn, double& op,
-                                          double& om, double& on) {
-  if (type == kEvOpen) {
-    double sp = 0.0, sm = 0.0;
+__device__ __forceinline__ double edge_sum(const float (&d)[2 * NT + 2], const double (&bv)[NT]) {
+  double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      sp = fma(be[j], (double)d[j], sp);
-      sm = fma(be[j], (double)d[NT + j], sm);
-    }
-    op = sp;
-    om = sm;
-    on = (double)d[2 * NT];
-    return;
-  }
-  double sp = 0.0, sm = 0.0, np = 0.0, nm = 0.0;
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const double vpj = (double)d[j], vmj = (double)d[NT + j];
-    sp = fma(be[j], vpj, sp);
-    sm = fma(be[j], vmj, sm);
-    if (next) {
-      np = fma(bn[j], vpj, np);
-      nm = fma(bn[j], vmj, nm);
-    }
-  }
-  gp += sp;
-  gm += sm;
-  gn += (double)d[2 * NT];
-  if (next) {
-    op = np;
-    om = nm;
-    on = (double)d[2 * NT];
-  }
+  for (int j = 0; j < NT; ++j) s = fma(bv[j], (double)d[j] - (double)d[NT + j], s);
+  return s;
 }
 
 template <int NT>
 __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
-  constexpr int D = 2 * NT + 1;                // planes per row
+  constexpr int D = 2 * NT + 2;                // V+ (NT), V- (NT), N at XR, N at XL
+  constexpr int GS = 21;                       // lanes per edge tile (x terms + the count)
+  static_assert(NT + 1 <= GS, "series terms");
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
   const int ch = vb % a.nch;
@@ -404,183 +369,162 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   if (m0 >= Mq) return;  // uniform over the block
   const int cnt = min(a.S, Mq - m0);
   const int b0 = grp * a.bpg, b1 = min(b0 + a.bpg, g.B);
-  const int xs = a.x0 + ch * a.cw, cwc = min(a.cw, a.x1 - xs + 1), xe = xs + cwc - 1;
-  // Waves over tiles: tiles ta.. (nl of them) then, in the two-range form,
-  // the right-edge tiles tr...  A column X >= 1 of tile t = (X - 1) / 64 is
-  // thread 64 w + (X - 1) % 64 of wave w.
-  const int ta = (max(xs - rx, 1) - 1) >> 6;
-  const int lastR = (xe + rx) >> 6;  // tile of the last right edge xe + rx + 1
-  const int lastL = a.two ? (max(xe - rx, 1) - 1) >> 6 : lastR;
-  const int nl = a.two ? lastL - ta + 1 : a.nt;
-  const int tr = a.two ? (xs + rx) >> 6 : ta + nl;
-  const int nV = 64 * a.nt;
-  const int tid = (int)threadIdx.x;
+  const int tid = (int)threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int tx = wv < nl ? ta + wv : tr + (wv - nl);  // the wave's tile
-  // a batch launch may have more waves than this item's tiles
-  const bool live = wv < a.nt, on = live && tx <= (wv < nl ? lastL : lastR);
-  const int X = 64 * tx + 1 + (tid & 63);
-  // LDS index of a left edge / right edge column (>= 1)
-  auto col_left = [&](int Xc) { return 64 * (((Xc - 1) >> 6) - ta) + ((Xc - 1) & 63); };
-  auto col_right = [&](int Xc) {
-    return a.two ? 64 * (nl + ((Xc - 1) >> 6) - tr) + ((Xc - 1) & 63) : col_left(Xc);
-  };
+  // chunks start where a wave's right edges begin a tile: they then lie in
+  // one tile, its left edges in at most two
+  const int xo = a.x0 - ((a.x0 + rx) & 63);
+  const int xs = xo + ch * a.cw + 64 * wv;  // the wave's first window
+  // a launch may have more waves than the item (a batch's largest block)
+  const bool live = 64 * wv < a.cw && xs <= a.x1;
   const int ycb = a.y0 + q + m0 * h;  // first centre row of the segment
   const int Ya0 = ycb - ry;
   const int TY = g.TY;
   __syncthreads();  // LDS reuse across virtual blocks of one block
   extern __shared__ double sm[];
-  double* Gb = sm;                                  // [2][3][nV]: G+, G-, N
-  double* BE = sm + 6 * nV;                         // [S][NT]: beta of the members
-  int32_t* acc = (int32_t*)(BE + (size_t)a.S * NT);  // [S][cw]
+  double* BE = sm;                                            // [S][NT]: beta of the members
+  int32_t* acc = (int32_t*)(BE + (size_t)a.S * NT) + (size_t)wv * a.S * 64;  // [S][64] per wave
   for (int mm = tid; mm < cnt; mm += (int)blockDim.x) {
     double be[NT];
     series_coeffs<NT>(sp.ay, ycb + mm * h, be);
 #pragma unroll
     for (int j = 0; j < NT; ++j) BE[mm * NT + j] = be[j];
   }
-  // one bin per item: each member's terms go straight to the set's
-  // accumulator, so no LDS accumulator bounds the segment
-  const bool direct = a.ngroups > 1 && a.bpg == 1;
-  if (tid < cwc && !direct)
-    for (int mm = 0; mm < cnt; ++mm) acc[mm * a.cw + tid] = 0;
-  // x coefficients of the column as a right / left edge (for the row carries;
-  // the planes hold them already)
-  double ap[NT], am[NT];
-  series_coeffs<NT>(sp.ax, max(X - rx - 1, 0), ap);
-  series_coeffs<NT>(sp.ax, X + rx, am);
-  // the column's loads: plane p of bin b at row Y is at
-  // base(0, b) + Y row_stride + p 64 + the column's offset
-  const char* __restrict__ colp = (const char*)a.planes + swih_xoff(g, X) * 4;
+  if (live)
+    for (int mm = 0; mm < cnt; ++mm) acc[mm * 64 + lane] = 0;
+  __syncthreads();  // BE ready; no barrier after this one
+  if (!live) return;
+  const bool mine = xs + lane >= a.x0 && xs + lane <= a.x1;
+  // lanes outside the rectangle follow its nearest window
+  const int xc = min(max(xs + lane, a.x0), a.x1);
+  const int XR = xc + rx + 1, XL = xc - rx;
+  const bool xl0 = XL == 0;  // column 0 is not stored: its values are 0
+  const int XLc = xl0 ? 1 : XL;
+  double al[NT];
+  series_coeffs<NT>(sp.ax, xc, al);
+  // the edges' tiles: right edges in tR (one tile, or two at the rectangle's
+  // clamped ends), left edges in tL0, tL0 + 1; lanes GS s + i handle x term i
+  // (i = NT: the count) of edge tile s = 0 (right), 1, 2 (left)
+  const int tR0 = __builtin_amdgcn_readfirstlane((XR - 1) >> 6);
+  const int tL0 = __builtin_amdgcn_readfirstlane((XLc - 1) >> 6);
+  const int sR = ((XR - 1) >> 6) - tR0, sL = ((XLc - 1) >> 6) - tL0;
+  const int slot = lane / GS, ti = lane - slot * GS;
+  const int mytile = slot == 0 ? tR0 : tL0 + slot - 1;
+  const bool carries = slot < 3 && ti <= NT && mytile < g.NTX;
+  const float* __restrict__ pl = (const float*)a.planes;
+  const int64_t oR = swih_xoff(g, XR), oL = swih_xoff(g, XLc) + NT * 64;
   const double inv_mass = 1.0 / sp.mass;
-  const int xw = xs + tid;  // this thread's window centre (tid < cwc)
-  const int iXb = col_right(xw + rx + 1), iXa = xw - rx > 0 ? col_left(xw - rx) : -1;
   // an opening row that closes a band adds nothing and is not read
-  auto reads = [&](const SweepEv& e) { return on && (e.type != kEvOpen || e.Y % TY != 0); };
-  const int lane = tid & 63;
-  // the tile's row carries at a row: NT^2 doubles, one contiguous run, lane l
-  // holding terms l, l + 64, ...
-  constexpr int RCN = (NT * NT + 63) / 64;
-  auto load = [&](float (&d)[D], double (&rc)[RCN], const SweepEv& e) {
-    if (on && e.type != kEvCross) {
-      const double* __restrict__ q = a.RC + swih_rc(g, 0, e.b, tx, e.Y);
+  auto reads = [&](const SweepEv& e) { return e.type != kEvOpen || e.Y % TY != 0; };
+  auto load = [&](float (&d)[D], double (&rc)[NT], const SweepEv& e) {
+    if (e.type != kEvCross && carries) {
+      // this lane's x term of its tile's carries at the row (the count: term (0, 0))
+      const double* __restrict__ qr =
+          a.RC + swih_rc(g, ti < NT ? ti * NT : 0, e.b, mytile, e.Y);
 #pragma unroll
-      for (int k = 0; k < RCN; ++k)
-        if (lane + 64 * k < NT * NT) rc[k] = q[lane + 64 * k];
+      for (int j = 0; j < NT; ++j) rc[j] = (ti < NT || j == 0) ? qr[j] : 0.0;
     }
     if (!reads(e)) return;
-    const char* p =
-        colp + ((int64_t)e.b * g.NTX * g.tile_stride + (int64_t)e.Y * g.row_stride) * 4;
+    const float* __restrict__ row = pl + swih_base(g, 0, e.b) + (int64_t)e.Y * g.row_stride;
 #pragma unroll
-    for (int q = 0; q < D; ++q) d[q] = *(const float*)(p + q * 256);
+    for (int j = 0; j < NT; ++j) {
+      d[j] = row[oR + j * 64];
+      d[NT + j] = row[oL + j * 64];
+    }
+    d[2 * NT] = row[oR + 2 * NT * 64];
+    d[2 * NT + 1] = row[oL + NT * 64];
   };
   auto advance = [&](const SweepEv& e) { return sweep_next(e, cnt, b1, h, TY, Ya0); };
-  double gp = 0.0, gm = 0.0, gn = 0.0;   // the member's G+, G-, N
-  double op = 0.0, om = 0.0, on_ = 0.0;  // the next member's opening sums
-  double bcur[NT], bnxt[NT];             // beta of the current and the next member
-  int par = 0;                           // LDS buffer parity
+  double hh = 0.0, nn = 0.0;  // the member's window sum and pixel count so far
+  double oh = 0.0, on = 0.0;  // the next member's opening row
+  double bcur[NT], bnxt[NT];  // beta of the current and the next member
   auto beta = [&](double (&bv)[NT], int mm) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) bv[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
   };
-  // contract row e of d; at a boundary row, the member's window phase
-  double qprev = 0.0, rmine = 0.0;  // lanes 0..NT: beta(m) RC[Ya(m)] and the member's R
-  auto process = [&](const float (&d)[D], const double (&rc)[RCN], const SweepEv& e) {
+  // lanes of an edge tile: beta(m) RC at the member's opening row, and the
+  // member's carry box once it closes
+  double qprev = 0.0, rbox = 0.0;
+  auto process = [&](float (&d)[D], const double (&rc)[NT], const SweepEv& e) {
     const bool withL = e.Y % TY != 0;  // as an opening row
     const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
     if (e.type == kEvOpen) {
       beta(bcur, 0);
       beta(bnxt, 1);
     }
-    if (on && e.type != kEvCross) {
-      // row carries: sum_j beta_j RC_ij at this row, for the member it closes
-      // (minus the same at its opening row) and for the one it opens; lane
-      // i < NT gathers its x term's NT values from the lanes holding them,
-      // lane NT the count term (0, 0)
-      const int ib = lane < NT ? lane * NT : 0;
-      double sc = 0.0, sn = 0.0, v0 = 0.0;
+    if (xl0 && reads(e)) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) d[NT + j] = 0.0f;
+      d[2 * NT + 1] = 0.0f;
+    }
+    if (e.type != kEvCross) {
+      double sc = 0.0, sn = 0.0;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        const int p = ib + j;
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < RCN; ++k) {
-          const double t = __shfl(rc[k], p & 63);
-          if ((p >> 6) == k) v = t;
-        }
-        if (j == 0) v0 = v;
-        sc = fma(bcur[j], v, sc);
-        sn = fma(bnxt[j], v, sn);
+        sc = fma(bcur[j], rc[j], sc);
+        sn = fma(bnxt[j], rc[j], sn);
       }
-      if (lane == NT) sc = sn = v0;
-      if (lane <= NT) {
-        if (e.type == kEvBound) {
-          rmine = sc - qprev;
-          qprev = sn;
-        } else {
-          qprev = sc;
-        }
+      if (ti == NT) sc = sn = rc[0];
+      if (e.type == kEvBound) {
+        rbox = sc - qprev;
+        qprev = sn;
+      } else {
+        qprev = sc;
       }
     }
-    if (e.type == kEvOpen || e.type == kEvBound) op = om = on_ = 0.0;
-    if (on && (e.type != kEvOpen || withL))
-      sweep_row<NT>(d, e.type, next, bcur, bnxt, gp, gm, gn, op, om, on_);
     if (e.type == kEvOpen) {
-      gp = -op;
-      gm = -om;
-      gn = -on_;
-    } else if (e.type == kEvBound) {
-      if (on) {
-        // the member's contracted row carries, broadcast from lanes 0..NT
-#pragma unroll
-        for (int i = 0; i < NT; ++i) {
-          const double ri = readlane(rmine, i);
-          gp = fma(ap[i], ri, gp);
-          gm = fma(am[i], ri, gm);
-        }
-        gn += readlane(rmine, NT);
+      if (withL) {
+        oh = edge_sum<NT>(d, bcur);
+        on = (double)d[2 * NT] - (double)d[2 * NT + 1];
+      } else {
+        oh = on = 0.0;
       }
-      double* Gp = Gb + par * 3 * nV;
-      if (live) {
-        Gp[tid] = gp;
-        Gp[nV + tid] = gm;
-        Gp[2 * nV + tid] = gn;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-      if (tid < cwc) {
-        const double hp = Gp[iXb], cp = Gp[2 * nV + iXb];
-        const double hm = iXa >= 0 ? Gp[nV + iXa] : 0.0, cm = iXa >= 0 ? Gp[2 * nV + iXa] : 0.0;
-        const int32_t v = cp - cm != 0.0 ? bc_term((hp - hm) * inv_mass, a.tmpl[e.b]) : 0;
-        if (!direct) {
-          acc[e.mm * a.cw + tid] += v;
-        } else if (v != 0) {
-          const size_t o = (size_t)(ycb + e.mm * h - a.y0) * (a.x1 - a.x0 + 1) + (xw - a.x0);
-          atomicAdd((unsigned int*)&a.acc[o], (unsigned int)v);
-        }
-      }
-      par ^= 1;
-      gp = -op;
-      gm = -om;
-      gn = -on_;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) bcur[j] = bnxt[j];
-      beta(bnxt, e.mm + 2);
+      hh = -oh;
+      nn = -on;
+      return;
     }
+    hh += edge_sum<NT>(d, bcur);
+    nn += (double)d[2 * NT] - (double)d[2 * NT + 1];
+    if (e.type != kEvBound) return;
+    if (next) {
+      oh = edge_sum<NT>(d, bnxt);
+      on = (double)d[2 * NT] - (double)d[2 * NT + 1];
+    } else {
+      oh = on = 0.0;
+    }
+    // the window's carry part: alpha(xc) . (box of its right-edge tile - left-edge tile)
+    double w[3], c[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) t = fma(al[i], readlane(rbox, GS * s + i), t);
+      w[s] = t;
+      c[s] = readlane(rbox, GS * s + NT);
+    }
+    // right edges share tile tR0 except where lanes were clamped to the rectangle
+    const double wr = sR ? 0.0 : w[0], cr = sR ? 0.0 : c[0];
+    const double H = hh + wr - (xl0 ? 0.0 : (sL ? w[2] : w[1]));
+    const double N = nn + cr - (xl0 ? 0.0 : (sL ? c[2] : c[1]));
+    const int32_t v = N != 0.0 ? bc_term(H * inv_mass, a.tmpl[e.b]) : 0;
+    acc[e.mm * 64 + lane] += v;
+    hh = -oh;
+    nn = -on;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) bcur[j] = bnxt[j];
+    beta(bnxt, e.mm + 2);
   };
-  __syncthreads();  // BE ready
   SweepEv e0;
   e0.b = b0;
   e0.mm = 0;
   e0.Y = e0.Ya = Ya0;
   e0.type = kEvOpen;
-  // two register buffers (planes and row carries) alternate: the next row's
-  // loads are in flight while the current row is contracted
+  // two register buffers alternate: the next row's loads are in flight while
+  // the current row is contracted
   float dA[D], dB[D];
-  double rA[RCN], rB[RCN];
+  double rA[NT], rB[NT];
 #pragma unroll
-  for (int k = 0; k < RCN; ++k) rA[k] = rB[k] = 0.0;
+  for (int j = 0; j < NT; ++j) rA[j] = rB[j] = 0.0;
   load(dA, rA, e0);
   for (;;) {
     const SweepEv e1 = advance(e0);
@@ -592,11 +536,11 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     process(dB, rB, e1);
     if (e0.type == kEvEnd) break;
   }
-  if (tid < cwc && !direct) {
+  if (mine) {
     const int mw = a.x1 - a.x0 + 1;
     for (int mm = 0; mm < cnt; ++mm) {
-      const size_t o = (size_t)(ycb + mm * h - a.y0) * mw + (xw - a.x0);
-      const int32_t v = acc[mm * a.cw + tid];
+      const size_t o = (size_t)(ycb + mm * h - a.y0) * mw + (xc - a.x0);
+      const int32_t v = acc[mm * 64 + lane];
       if (a.ngroups == 1) a.map[o] = bc_value(v);
       else atomicAdd((unsigned int*)&a.acc[o], (unsigned int)v);
     }
