@@ -181,10 +181,15 @@ def cpu_baseline_multiscale(img, nsample=65536):
             "host": host_info()}
 
 
-def gauss_rc_bytes(K, B, H, W):
-    """Bytes of the Gaussian row carries a plane build writes: (2K+1)^2 weight
-    terms in FP64 per bin, tile column (64 pixels) and row."""
-    return 8 * (2 * K + 1) ** 2 * B * ((W + 63) // 64) * (H + 1)
+GAUSS_PLANES = 5  # corner-contracted planes per bin: four corners and the count
+
+
+def gauss_side_bytes(K, B, H, W, TY=64):
+    """Bytes of a Gaussian plane set besides its planes: the row carries (2 (2K+1) + 1
+    FP64 values per bin, tile column of 64 pixels and row) and the band-closing rows
+    (2 (2K+1) floats per bin and column at every multiple of TY below H)."""
+    nt = 2 * K + 1
+    return 8 * (2 * nt + 1) * B * ((W + 63) // 64) * (H + 1) + 4 * 2 * nt * B * W * ((H - 1) // TY)
 
 
 def kernel_source_hash():
@@ -353,9 +358,9 @@ def run_multiscale(args):
         for ph in PHASES:
             per["%s_%d" % (ph, w)] = time_launches(lambda: phase(si, ph), reps[ph])
     nwin = [(N - w + 1) ** 2 for w in MS_SCALES]
-    T = 2 * (2 * cfgs[0].K + 1) + 1
+    T = GAUSS_PLANES
     plane_bytes = 4 * T * B * (N + 1) * (N + 1)
-    rc_bytes = gauss_rc_bytes(cfgs[0].K, B, N, N)
+    rc_bytes = gauss_side_bytes(cfgs[0].K, B, N, N)
     nsc = len(MS_SCALES)
     kernels = {
         "build": {"kernel": "emit_gauss (Gaussian plane build, %d planes x %d bins + row carries, "
@@ -632,7 +637,7 @@ def w3_builds(rep_small=10):
         planes = 4 * bp.nplanes * 32 * (W3 + 1) * (W3 + 1)
         # the Gaussian's emit also writes its FP64 row carries
         if kname == "gaussian":
-            planes += gauss_rc_bytes(bp.cfg.K, 32, W3, W3)
+            planes += gauss_side_bytes(bp.cfg.K, 32, W3, W3)
         build_ms = t["carries"] + t["planes"]
         w3[kname] = {"ms": t, "plane_bytes": planes,
                      "build_gbs": (W3 * W3 + planes) / (build_ms / 1e3) / 1e9,
@@ -999,11 +1004,11 @@ def run_frame(args, side_kinds=True, builds=True, cpu=True):
     # the plane build reads the image once and writes every plane element once;
     # the dense map reads every plane element once and writes one float per centre.
     K = plans["gaussian"].cfg.K
-    T = 2 * (2 * K + 1) + 1
+    T = GAUSS_PLANES
     plane_bytes = 4 * T * NBINS * (H + 1) * (W + 1)
     kernels = {
         "build": {"kernel": "emit_gauss (Gaussian plane build, %d planes x 16 bins + row carries)" % T,
-                  "alg": H * W + plane_bytes + gauss_rc_bytes(K, NBINS, H, W), "ms": per["planes_gaussian"],
+                  "alg": H * W + plane_bytes + gauss_side_bytes(K, NBINS, H, W), "ms": per["planes_gaussian"],
                   "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
         "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
                             "482x482 centres; the finalising pass is ~1% of the phase)",

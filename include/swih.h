@@ -32,17 +32,18 @@
  *                       sy = h/4 (Fig. 1c), evaluated through a K-term cosine
  *                       series per axis (see swih_gauss_terms).  Each scale's
  *                       planes hold, per bin and pixel, the (2K+1)^2 weight
- *                       terms already contracted over x with the coefficients
- *                       a window edge at that column needs (right and left
- *                       edge: 2 (2K+1) values) plus the exact pixel count.
+ *                       terms already contracted with the coefficients of the
+ *                       windows that have the pixel as a corner (its four
+ *                       corner roles: 4 values) plus the exact pixel count;
+ *                       every 64th row also keeps the terms contracted over x
+ *                       only, for the windows that straddle it.
  *       SWIH_GAUSSIAN_SEP  the same series kernel in separable form: one
  *                       1-D weighted integral histogram along x with the
  *                       translated lookups (Sec. 2.1, Eq. 2 per axis) giving
  *                       row results per valid centre column, then one along y
  *                       over those row results.  Same values as SWIH_GAUSSIAN
  *                       up to rounding; the workspace holds H x (W-w+1) x
- *                       nbins floats per scale instead of 2 (2K+1) + 1 planes
- *                       per bin.
+ *                       nbins floats per scale instead of 5 planes per bin.
  *       SWIH_EXPONENTIAL  exp(-|dx|/tx - |dy|/ty), tx = w/4, ty = h/4 (the
  *                       exponential weighting of Sec. 2): four direction-
  *                       weighted integral histograms per bin, one per window

@@ -98,7 +98,8 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   if (gauss) {
     g.nI = g.nJ = 2 * gauss_K(c) + 1;
     g.nP = g.nI * g.nJ;
-    g.nPL = 2 * g.nJ + 1;  // edge-contracted planes V+, V-, N
+    g.nPL = 5;                 // corner-contracted planes C_RB, C_RT, C_LB, C_LT, N
+    g.nRC = 2 * g.nI + 1;      // y-contracted row carries RCB, RCT, count
   } else {
     static const int nI[3] = {1, 2, 3}, nP[3] = {1, 3, 5};
     g.nI = g.nJ = nI[c->kernel];
@@ -115,7 +116,11 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
   off += swih_align256((int64_t)g.nPL * g.B * g.NTX * (int64_t)(H + 1) * SWIH_TX * 4);
   if (gauss) {
     L.off_RC = off;
-    off += swih_align256(PB * g.NTX * (int64_t)(H + 1) * 8);
+    off += swih_align256((int64_t)g.nRC * g.B * g.NTX * (int64_t)(H + 1) * 8);
+    L.off_XC = off;
+    off += swih_align256((int64_t)2 * g.nJ * g.B * g.NTY * g.NTX * SWIH_TX * 4);
+    L.off_beta = off;
+    off += swih_align256((int64_t)2 * g.nJ * (H + 1) * 8);
     L.off_uq = off;
     off += swih_align256((int64_t)g.nI * NXP * 4);
     L.off_vq = off;  // int32 [H][nJ], then double [H][nJ]
@@ -242,7 +247,7 @@ int build_phases(const swih_config* cfg, const uint8_t* d_img, int32_t height, i
   for (int k = first; k <= last; ++k) {
     ScaleParams sp;
     scale_params(cfg, gauss ? k : 0, sp);
-    if (launch_build(L, cfg->kernel, k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, sp.rx, d_img,
+    if (launch_build(L, cfg->kernel, k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, sp.rx, sp.ry, d_img,
                      pitch, (char*)d_ws, s, phases) != hipSuccess)
       return SWIH_ERR_HIP;
   }
@@ -667,7 +672,7 @@ int swih_batch_plan(const swih_config* cfg, const swih_frame_desc* frames, int32
       ScaleParams sp;
       scale_params(&fc, gauss ? k : 0, sp);
       int32_t nb[4];
-      build_args(layouts[f], k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, sp.rx, fd.d_img,
+      build_args(layouts[f], k, gauss ? &sp.ax : nullptr, gauss ? &sp.ay : nullptr, sp.rx, sp.ry, fd.d_img,
                  fd.pitch, (char*)fd.d_ws, units[u], nb, true);
       for (int s = 0; s < 4; ++s) upre[s * (nunits + 1) + u + 1] = upre[s * (nunits + 1) + u] + nb[s];
     }

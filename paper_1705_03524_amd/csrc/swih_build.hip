@@ -86,8 +86,8 @@ hipError_t run_batch(const BuildArgs* units, const int32_t* prefix, int nunits, 
 constexpr int kHistMinTiles = 128;
 
 void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay, int32_t rx,
-                const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4],
-                bool batched) {
+                int32_t ry, const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a,
+                int32_t (&nb)[4], bool batched) {
   const SwihGeom& g = L.g;
   memset(&a, 0, sizeof(a));
   a.g = g;
@@ -97,6 +97,8 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
   a.planes = sb + L.off_planes;
   if (g.gauss) {
     a.RC = (double*)(sb + L.off_RC);
+    a.XC = (float*)(sb + L.off_XC);
+    a.beta = (double*)(sb + L.off_beta);
     a.uq = (int32_t*)(sb + L.off_uq);
     a.vq = (int32_t*)(sb + L.off_vq);
     a.vqd = (double*)(sb + L.off_vq + swih_align256((int64_t)g.nJ * g.H * 4));
@@ -105,6 +107,7 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.ax = *ax;
     a.ay = *ay;
     a.rx = rx;
+    a.ry = ry;
   }
   a.z = sb + L.off_z;
   a.T = sb + L.off_T;
@@ -114,7 +117,8 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
   a.nb2 = blocks_for_threads((long)g.nI * g.B * g.H);
   const int nb3 = blocks_for_waves((long)g.nP * g.B);
   const long waves = (long)g.NTY * g.NTX * g.B;
-  nb[0] = g.gauss ? blocks_for_threads((long)g.nI * NXP + (long)g.nJ * g.H + a.nacc) : 0;
+  nb[0] = g.gauss ? blocks_for_threads((long)g.nI * NXP + (long)g.nJ * g.H + 2L * g.nJ * (g.H + 1) + a.nacc)
+                  : 0;
   // integer kernels with few bins: a block per (band, tile) counts all bins
   a.agg_hist = !g.gauss && int_hist(g.nI - 1, g.B) && (batched || g.NTY * g.NTX >= kHistMinTiles);
   nb[1] = a.agg_hist ? g.NTY * g.NTX : blocks_for_waves(waves);
@@ -123,11 +127,11 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
 }
 
 hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,
-                        const GaussAxis* ay, int32_t rx, const uint8_t* img, int32_t img_pitch,
-                        char* ws, hipStream_t stream, int phases) {
+                        const GaussAxis* ay, int32_t rx, int32_t ry, const uint8_t* img,
+                        int32_t img_pitch, char* ws, hipStream_t stream, int phases) {
   BuildArgs a;
   int32_t nb[4];
-  build_args(L, set, ax, ay, rx, img, img_pitch, ws, a, nb);
+  build_args(L, set, ax, ay, rx, ry, img, img_pitch, ws, a, nb);
 #define SWIH_RUN1(ST) run_single<ST>(a, nb, phases, stream)
   SWIH_STAGE_DISPATCH(kind, L.g.nI, SWIH_RUN1)
 #undef SWIH_RUN1

@@ -461,7 +461,10 @@ __device__ __forceinline__ void emit_int(const BuildArgs& a, int vb) {
 
 // ---------------------------------------------------------------- Gaussian
 // Fixed-point weight terms: uq[x][i] (x < NTX*64, zero beyond W), vq[y][j],
-// and vqd[y][j] = vq * 2^-48 as double (scales the u*v product to real units).
+// and vqd[y][j] = vq * 2^-48 as double (scales the u*v product to real units);
+// the y translation coefficients of each row Y as a window's bottom edge
+// (centre row Y - ry - 1) and as its top edge (centre row Y + ry):
+// beta[Y][j] and beta[Y][NT + j].
 template <int WGT = WG>
 __device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
@@ -472,7 +475,7 @@ __device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
   double* __restrict__ vqd = a.vqd;
   const long t = (long)vb * WGT + threadIdx.x;
   const int NXP = g.NTX * SWIH_TX;
-  const long nu = (long)g.nI * NXP, nv = (long)g.nJ * g.H;
+  const long nu = (long)g.nI * NXP, nv = (long)g.nJ * g.H, nb = 2L * g.nJ * (g.H + 1);
   const double fix = (double)(1 << SWIH_FIX_BITS);
   if (t < nu) {
     const int i = (int)(t / NXP), x = (int)(t % NXP);
@@ -499,8 +502,14 @@ __device__ __forceinline__ void basis(const BuildArgs& a, int vb) {
     const int32_t q = (int32_t)rint(val * fix);
     vq[(size_t)y * g.nJ + j] = q;
     vqd[(size_t)y * g.nJ + j] = ldexp((double)q, -2 * SWIH_FIX_BITS);
-  } else if (t < nu + nv + a.nacc) {
-    a.acc[t - nu - nv] = 0;  // the map accumulator starts at zero
+  } else if (t < nu + nv + nb) {
+    const long r = t - nu - nv;
+    const int Y = (int)(r / (2 * g.nJ)), q = (int)(r % (2 * g.nJ));
+    // rows that are never a bottom edge (Y <= ry) take centre 0: their values are never read
+    a.beta[r] = q < g.nJ ? series_coeff(ay, max(Y - a.ry - 1, 0), q)
+                         : series_coeff(ay, Y + a.ry, q - g.nJ);
+  } else if (t < nu + nv + nb + a.nacc) {
+    a.acc[t - nu - nv - nb] = 0;  // the map accumulator starts at zero
   }
 }
 
@@ -567,35 +576,53 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
   }
 }
 
-// Row carries at the tile origin column, RC_ij[Y] = P_ij[Y][64 tx], of every
-// plane of one (band, tile, bin): one lane per plane p = i NT + j, walking the
-// band's rows,
-//   RC[Y + 1] = RC[Y] + v_j(Y) E_i(Y),   RC[y0] = CTc
-// (CTc the tile-origin value, E_i the row carry of x term i, both in the
-// fixed-point units of the basis).  RC is stored planes fastest (swih_rc), so
-// each row's store is one contiguous run of 8 nP bytes.
+// Row carries at the tile origin column, RC_ij[Y] = P_ij[Y][64 tx], of one
+// (band, tile, bin), contracted in y like the planes.  Lane k takes row
+// Y = y0 + k + 1 of the band: every (i, j) is an inclusive wave scan of the
+// row increments,
+//   RC_ij[y + 1] = RC_ij[y] + v_j(y) E_i(y),   RC_ij[y0] = CT_ij
+// (CT the tile-origin value, E_i the row carry of x term i, both in the
+// fixed-point units of the basis), and the lane stores
+//   RCB_i = sum_j beta_j(Y - ry - 1) RC_ij[Y],  RCT_i = sum_j beta_j(Y + ry) RC_ij[Y]
+// and the count RC_00[Y]: one run of 2 NT + 1 doubles per row (swih_rc).  The
+// count is exact: its increments are integers times 2^48.
 template <int NT>
 __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) {
   const SwihGeom& g = a.g;
-  const int32_t* __restrict__ vq = a.vq;
   const int64_t* __restrict__ E = (const int64_t*)a.T;
   const double* __restrict__ CTc = (const double*)a.BT;
   double* __restrict__ RCp = a.RC;
-  constexpr int NP = NT * NT;
   const double sc48 = ldexp(1.0, -2 * SWIH_FIX_BITS);
-  for (int p0 = 0; p0 < NP; p0 += 64) {
-    const int p = p0 + lane_id();
-    if (p >= NP) break;
-    const int i = p / NT, j = p - (p / NT) * NT;
-    if (t.ty == 0) RCp[swih_rc(g, p, t.b, t.tx, 0)] = 0.0;
-    const int64_t* __restrict__ ei = E + ((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + t.y0;
-    const int32_t* __restrict__ vj = vq + (size_t)t.y0 * NT + j;
-    double* __restrict__ dst = RCp + swih_rc(g, p, t.b, t.tx, t.y0 + 1);
-    double acc = CTc[((size_t)(p * g.B + t.b) * g.NTY + t.ty) * g.NTX + t.tx];
-#pragma unroll 8
-    for (int r = 0; r < t.nrows; ++r) {
-      acc += (double)vj[(size_t)r * NT] * (double)ei[r];
-      dst[(size_t)r * g.nP] = acc * sc48;
+  const int lane = lane_id();
+  const bool row = lane < t.nrows;
+  const int y = t.y0 + (row ? lane : 0);
+  if (t.ty == 0 && lane < g.nRC) RCp[swih_rc(g, lane, t.b, t.tx, 0)] = 0.0;
+  double vj[NT], bB[NT], bT[NT];
+  const int32_t* __restrict__ vr = a.vq + (size_t)y * NT;
+  const double* __restrict__ br = a.beta + (size_t)(y + 1) * 2 * NT;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    vj[j] = row ? (double)vr[j] : 0.0;
+    bB[j] = br[j];
+    bT[j] = br[NT + j];
+  }
+  const size_t ctp = (size_t)g.B * g.NTY * g.NTX;  // from one term's tile values to the next
+  const double* __restrict__ ct = CTc + ((size_t)t.b * g.NTY + t.ty) * g.NTX + t.tx;
+  double* __restrict__ dst = RCp + swih_rc(g, 0, t.b, t.tx, y + 1);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const double ei = row ? (double)E[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + y] : 0.0;
+    double sB = 0.0, sT = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const double r = (ct[(size_t)(i * NT + j) * ctp] + wave_incl_scan(vj[j] * ei)) * sc48;
+      sB = fma(bB[j], r, sB);
+      sT = fma(bT[j], r, sT);
+      if (i == 0 && j == 0 && row) dst[2 * NT] = r;
+    }
+    if (row) {
+      dst[i] = sB;
+      dst[NT + i] = sT;
     }
   }
 }
@@ -608,9 +635,12 @@ __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) 
 //   V+_j[y + 1] = V+_j[y] + v_j(y) S+(y),  S+(y) = sum_i alpha_i(X - rx - 1) R_i(y)
 //   V-_j[y + 1] = V-_j[y] + v_j(y) S-(y),  S-(y) = sum_i alpha_i(X + rx) R_i(y)
 //   N[y + 1]    = N[y] + (pixels of the bin in the row up to X),
-// so a row stores 2 NT + 1 values per column where the terms would store
-// NT^2.  The launch interleaves one row-carry wave (rc_gauss) after each
-// plane wave.
+// and each stored row Y contracts V+ and V- over j with the coefficients of
+// Y as a bottom and as a top edge (the table beta): the four corner values
+// and N, 5 floats per column where the terms would take NT^2.  A band's
+// closing row, which windows cross with any centre row, also keeps V+ and V-
+// (side array XC).  The launch interleaves one row-carry wave (rc_gauss)
+// after each plane wave.
 template <int NT, int WGT = WG>
 __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
@@ -618,6 +648,7 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const int ipitch = a.ipitch;
   const int32_t* __restrict__ uq = a.uq;
   const double* __restrict__ vqd = a.vqd;
+  const double* __restrict__ bet = a.beta;
   float* __restrict__ Lp = (float*)a.planes;
   WaveTile t;
   int e;
@@ -634,9 +665,8 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   double ap[NT], am[NT];
   series_coeffs<NT>(a.ax, max(X - a.rx - 1, 0), ap);
   series_coeffs<NT>(a.ax, X + a.rx, am);
-  // a row's 2 NT + 1 planes are consecutive 64-element runs: V+ (j), V- (NT + j), N (2 NT)
+  // a row's 5 planes are consecutive 64-element runs: C_RB, C_RT, C_LB, C_LT, N
   float* col = Lp + swih_base(g, 0, t.b) + t.tx * g.tile_stride + lane;
-  constexpr int D = 2 * NT + 1;
   // running sums in FP64, each rounded once to float when stored
   double vp[NT], vm[NT];
   int32_t cnt = 0;
@@ -644,7 +674,7 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   for (int j = 0; j < NT; ++j) vp[j] = vm[j] = 0.0;
   if (t.ty == 0) {
 #pragma unroll
-    for (int p = 0; p < D; ++p) col[p * 64] = 0.0f;
+    for (int p = 0; p < 5; ++p) col[p * 64] = 0.0f;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
   for (int k = 0; k < t.nrows; ++k) {
@@ -662,22 +692,37 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     // u_0 = 1 is 2^24 in fixed point: the row's count up to X, exactly
     cnt += r0 >> SWIH_FIX_BITS;
     const double* vrow = vqd + (size_t)y * NT;
+    const double* brow = bet + (size_t)(y + 1) * 2 * NT;
     double vr[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) vr[j] = vrow[j];
+    double rb = 0.0, rt = 0.0, lb = 0.0, lt = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       vp[j] = fma(vr[j], sp, vp[j]);
       vm[j] = fma(vr[j], sm, vm[j]);
+      const double bb = brow[j], bt = brow[NT + j];
+      rb = fma(bb, vp[j], rb);
+      rt = fma(bt, vp[j], rt);
+      lb = fma(bb, vm[j], lb);
+      lt = fma(bt, vm[j], lt);
     }
     // whole 256-byte runs: lanes past the last column write values never read
     float* dst = col + (size_t)(y + 1) * g.row_stride;
+    dst[0] = (float)rb;
+    dst[64] = (float)rt;
+    dst[128] = (float)lb;
+    dst[192] = (float)lt;
+    dst[256] = (float)cnt;
+  }
+  const int Yl = t.y0 + t.nrows;  // the band's last stored row
+  if (Yl % g.TY == 0 && Yl < g.H) {
+    float* xc = a.XC + swih_xc(g, 0, t.b, Yl, X);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      dst[j * 64] = (float)vp[j];
-      dst[(NT + j) * 64] = (float)vm[j];
+      xc[j * 64] = (float)vp[j];
+      xc[(NT + j) * 64] = (float)vm[j];
     }
-    dst[2 * NT * 64] = (float)cnt;
   }
 }
 

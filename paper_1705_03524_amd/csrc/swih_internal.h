@@ -38,6 +38,15 @@ __device__ inline void series_coeffs(const GaussAxis& ax, int c, double (&out)[N
   }
 }
 
+// Coefficient j of series_coeffs at centre c, computed the same way.
+__device__ inline double series_coeff(const GaussAxis& ax, int c, int j) {
+  if (j == 0) return ax.a[0];
+  const int k = (j + 1) / 2;
+  double s, co;
+  sincos(ax.om[k] * (double)c, &s, &co);
+  return ax.a[k] * ((j & 1) ? co : s);
+}
+
 // Per-scale constants shared by query and match.
 struct ScaleParams {
   int32_t w, h, rx, ry;
@@ -54,7 +63,9 @@ struct BuildArgs {
   int32_t ipitch;
   int32_t nb1, nb2;   // scan: blocks of the band-carry and tile-carry roles
   void* planes;       // uint32 (integer kernels) or float tile-local planes (Gaussian)
-  double* RC;         // Gaussian row carries
+  double* RC;         // Gaussian row carries (y-contracted)
+  float* XC;          // Gaussian band-closing rows
+  double* beta;       // Gaussian: [H+1][2 nJ] beta of each row as a bottom / top edge
   int32_t* uq;        // Gaussian x terms [x][i]
   int32_t* vq;        // Gaussian y terms [y][j]
   double* vqd;        // vq * 2^-48
@@ -64,7 +75,8 @@ struct BuildArgs {
   int32_t* acc;       // Gaussian: the map accumulator of the set, cleared by the build
   int64_t nacc;
   int32_t agg_hist;   // integer kernels: aggregate by LDS histograms, a block per (band, tile)
-  int32_t rx;         // Gaussian: the set's window half-width (edge coefficients of the planes)
+  int32_t rx, ry;     // Gaussian: the set's window half-sizes (corner coefficients of the planes)
+  int32_t pad;
   GaussAxis ax, ay;
 };
 
@@ -72,8 +84,8 @@ struct BuildArgs {
 // scan and emit stages.  `batched`: the set is one unit of a batched build
 // (its aggregate may then use the histogram form at any size).
 void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay, int32_t rx,
-                const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a, int32_t (&nb)[4],
-                bool batched = false);
+                int32_t ry, const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a,
+                int32_t (&nb)[4], bool batched = false);
 
 // One batched build: every stage in one grid-stride launch over the units.
 // prefix: 4 arrays of nunits + 1 exclusive block prefixes (device memory, with
@@ -87,8 +99,8 @@ hipError_t launch_build_batch(int kind, int nt, int nbins, const BuildArgs* unit
 // `set` with the axis series of that scale.
 // phase bit 1 = carries (aggregate + scan), bit 2 = planes (emit).
 hipError_t launch_build(const SwihLayout& L, int kind, int set, const GaussAxis* ax,
-                        const GaussAxis* ay, int32_t rx, const uint8_t* img, int32_t img_pitch,
-                        char* ws, hipStream_t stream, int phases = 3);
+                        const GaussAxis* ay, int32_t rx, int32_t ry, const uint8_t* img,
+                        int32_t img_pitch, char* ws, hipStream_t stream, int phases = 3);
 
 hipError_t launch_query(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
                         const int32_t* centres, int32_t n, float* hist, uint32_t* hist_raw,
@@ -100,6 +112,7 @@ struct MatchArgs {
   ScaleParams sp;
   const void* planes;      // uint32 planes or float tile-local planes
   const double* RC;        // Gaussian row carries
+  const float* XC;         // Gaussian band-closing rows
   const float* tmpl;       // normalised template, or null
   const uint32_t* tmpl_raw;  // exact template (integer kernels), or null
   float* map;
@@ -125,6 +138,7 @@ struct QueryArgs {
   ScaleParams sp;
   const void* planes;
   const double* RC;
+  const float* XC;
   const int32_t* centres;  // [n][2]
   int32_t n;
   float* hist;             // [n][B] or null

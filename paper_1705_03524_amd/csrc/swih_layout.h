@@ -31,15 +31,25 @@
 // Yo = TY ty):
 //   L[Y][X]   = sum over Yo <= y < Y, Xo <= x < X  (bounded by the tile)
 //   RC[tx][Y] = P[Y][Xo]                          (double, per row and tile column)
-// and stores L already contracted over its x terms with the coefficients a
-// window edge at column X needs (the set's window half-width rx fixed):
-//   V+_j[Y][X] = sum_i alpha_i(X - rx - 1) L_ij[Y][X]   (X a right edge)
-//   V-_j[Y][X] = sum_i alpha_i(X + rx) L_ij[Y][X]       (X a left edge)
-//   N[Y][X]    = L_00[Y][X]                           (the pixel count, exact)
-// alpha_i(c) the x series coefficient i at centre column c: 2 NT + 1 float
-// planes per bin (p = j, NT + j, 2 NT), where the terms would take NT^2.
-// RC is stored [bin][Y][tx][plane] (planes fastest): a lookup needs every plane of
-// a few tiles at one row, which is then one contiguous run.
+// and, the set's window half-sizes (rx, ry) being fixed, stores L already
+// contracted with the translation coefficients of the windows that have
+// (X, Y) as a corner.  Column X is the right edge of the windows centred at
+// X - rx - 1 and the left edge of those at X + rx; row Y the bottom edge of
+// the windows centred at Y - ry - 1 and the top edge of those at Y + ry:
+//   V+_j[Y][X] = sum_i alpha_i(X - rx - 1) L_ij[Y][X],  V-_j: alpha_i(X + rx)
+//   C_RB = sum_j beta_j(Y - ry - 1) V+_j,  C_RT = sum_j beta_j(Y + ry) V+_j
+//   C_LB = sum_j beta_j(Y - ry - 1) V-_j,  C_LT = sum_j beta_j(Y + ry) V-_j
+//   N[Y][X] = L_00[Y][X]                              (the pixel count, exact)
+// alpha_i / beta_j the x / y series coefficients at a centre coordinate: 5
+// float planes per bin (p = C_RB, C_RT, C_LB, C_LT, N) where the terms would
+// take NT^2.  A window's histogram is then its four corners (plus the
+// crossings and carries below).  The band-closing rows c, crossed by windows
+// whose centre rows vary, keep V+_j and V-_j uncontracted in y in a side
+// array XC[bin][c / TY - 1][tx][q][64] (q = j for V+, NT + j for V-).
+// RC is contracted in y the same way, per (tile, row):
+//   RCB_i = sum_j beta_j(Y - ry - 1) RC_ij,  RCT_i = sum_j beta_j(Y + ry) RC_ij,
+// and RC_00 (the count), 2 NT + 1 doubles stored [bin][tx][Y][q] (q fastest):
+// a lookup needs all of them for one tile and row, one contiguous run.
 // with tx = tile of column X, ty = band of row Y, and zeros at row/column 0.
 // Only window boxes are ever needed, and they follow from vertical
 // differences at fixed X:
@@ -62,7 +72,8 @@ struct SwihGeom {
   int32_t TY;            // band height (<= 64)
   int32_t NTX, NTY;      // tiles across, bands down
   int32_t nP, nI, nJ;    // weight terms, x terms, y terms
-  int32_t nPL;           // stored planes per bin (integer kernels: nP; Gaussian: 2 nJ + 1)
+  int32_t nPL;           // stored planes per bin (integer kernels: nP; Gaussian: 5)
+  int32_t nRC;           // Gaussian row-carry values per (tile, row): 2 nI + 1
   int32_t gauss;         // 1 for the split Gaussian storage
   int32_t ppg;           // planes per interleaved group
   int64_t row_stride;    // 64 ppg: from row Y to row Y + 1 of one plane
@@ -85,11 +96,18 @@ __host__ __device__ inline int64_t swih_elem(const SwihGeom& g, int p, int b, in
   return swih_base(g, p, b) + (int64_t)Y * g.row_stride + swih_xoff(g, X);
 }
 
-// Element offset of the Gaussian row carry RC[tx][Y] of weight term p, bin b:
-// [b][tx][Y][p], planes fastest.  A map step reads all planes of one row and
-// tile as one contiguous run, and the build writes each row of a tile as one.
-__host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int p, int b, int tx, int Y) {
-  return (((int64_t)b * g.NTX + tx) * (g.H + 1) + Y) * g.nP + p;
+// Element offset of the Gaussian row-carry value q (RCB_i: q = i, RCT_i:
+// q = NT + i, the count: q = 2 NT) of tile tx, row Y, bin b: [b][tx][Y][q].
+__host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int q, int b, int tx, int Y) {
+  return (((int64_t)b * g.NTX + tx) * (g.H + 1) + Y) * g.nRC + q;
+}
+
+// Element offset of the Gaussian band-closing row values of row c (a
+// positive multiple of TY below H), value q, bin b, at column X >= 1:
+// XC[b][c / TY - 1][tx][q][64].
+__host__ __device__ inline int64_t swih_xc(const SwihGeom& g, int q, int b, int c, int X) {
+  return (((int64_t)b * g.NTY + (c / g.TY - 1)) * g.NTX + ((X - 1) >> 6)) * (2 * g.nJ * 64) +
+         q * 64 + ((X - 1) & 63);
 }
 
 // Byte offsets inside one workspace.  All regions are 256-byte aligned.
@@ -99,7 +117,9 @@ struct SwihLayout {
   int64_t set_bytes;     // bytes of one plane set (planes [+ RC + tables])
   // inside a set
   int64_t off_planes;    // uint32 or float planes, tile-major (above)
-  int64_t off_RC;        // double [B][NTX][H+1][nP], swih_rc     (Gaussian)
+  int64_t off_RC;        // double [B][NTX][H+1][nRC], swih_rc    (Gaussian)
+  int64_t off_XC;        // float band-closing rows, swih_xc       (Gaussian)
+  int64_t off_beta;      // double [H+1][2 nJ] beta at each row as a bottom / top edge (Gaussian)
   int64_t off_uq;        // int32 [nI][NTX*64]  fixed-point x terms (Gaussian)
   int64_t off_vq;        // int32 [H][nJ] fixed-point y terms, then double [H][nJ] (Gaussian)
   int64_t off_acc;       // int32 [H * W] map accumulator of the map sweep (Gaussian)

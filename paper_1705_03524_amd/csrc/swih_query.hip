@@ -209,8 +209,9 @@ int device_cus() {
 
 // Plan of a Gaussian window sweep over the centre rectangle: chunks of 64
 // windows per wave, combs, segments and bin groups, and the launch shape.
-// cus == 0: the batch form (blocks of kSweepBatchWaves waves, one bin group,
-// segments of up to kSweepBatchS members).  Otherwise blocks of kSweepWaves,
+// cus == 0: the batch form (chunks as wide as the job, up to
+// kSweepBatchWaves waves; one bin group; segments of up to kSweepBatchS
+// members).  Otherwise blocks of kSweepWaves,
 // segments of up to kSweepMaxS members (a segment costs one opening row per
 // bin), then bin groups (powers of two) until the launch has 128 waves per
 // compute unit: many short waves hide the loads' latency and balance the
@@ -219,7 +220,8 @@ int device_cus() {
 static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int ny, int cus,
                        MatchArgs& a, Launch& ml) {
   const int h = 2 * sp.ry + 1;
-  const int waves = cus > 0 ? kSweepWaves : kSweepBatchWaves;
+  // a batch job's chunk is as wide as the job, up to the batch block's waves
+  const int waves = cus > 0 ? kSweepWaves : std::min(kSweepBatchWaves, (nx + 63) / 64 + 1);
   a.two = 0;
   a.nt = waves;
   a.cw = 64 * waves;
@@ -252,6 +254,7 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   const char* sb = ws + (size_t)set * L.set_bytes;
   a.planes = sb + L.off_planes;
   a.RC = L.g.gauss ? (const double*)(sb + L.off_RC) : nullptr;
+  a.XC = L.g.gauss ? (const float*)(sb + L.off_XC) : nullptr;
   a.tmpl = tmpl;
   a.tmpl_raw = tmpl_raw;
   a.map = map;
@@ -281,6 +284,7 @@ void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   const char* sb = ws + (size_t)set * L.set_bytes;
   a.planes = sb + L.off_planes;
   a.RC = L.g.gauss ? (const double*)(sb + L.off_RC) : nullptr;
+  a.XC = L.g.gauss ? (const float*)(sb + L.off_XC) : nullptr;
   a.centres = centres;
   a.n = n;
   a.hist = hist;
@@ -288,7 +292,7 @@ void query_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   ql.threads = 256;
   if (L.g.gauss) {
     ql.blocks = n;
-    ql.lds = sizeof(double) * (size_t)L.g.B * (2 * L.g.nJ + 1);
+    ql.lds = sizeof(double) * (size_t)L.g.B * (L.g.nI + 3);
   } else {
     ql.blocks = (int32_t)(((long)n * L.g.B + 255) / 256);
     ql.lds = 0;

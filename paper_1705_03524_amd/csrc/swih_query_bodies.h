@@ -147,37 +147,30 @@ __device__ __forceinline__ void match_int(const MatchArgs& a, int vb) {
 }
 
 // ---------------------------------------------------------------- Gaussian
-struct GaussPlanes {
-  const float* L;
-  const double* RC;
-};
-
 __device__ __forceinline__ int tile_of(int X) { return (X > 0 ? X - 1 : 0) >> 6; }
 
-// First band-boundary row (a positive multiple of TY) at or after ya.
-__device__ __forceinline__ int first_cross(int ya, int TY) {
-  const int c = (ya + TY - 1) / TY * TY;
-  return c == 0 ? TY : c;
-}
-
-// One block per centre; threads over (bin, part) pairs, 2 NT + 1 parts per
-// bin, put the window's terms into LDS, then one thread per bin adds them in
-// order.  With XR = xc + rx + 1 and XL = xc - rx the window's edges,
-//   part j        beta_j (V+_j box at XR - V-_j box at XL)    (j < NT)
-//   part NT + i   alpha_i sum_j beta_j (RC_ij box: tiles of XR and XL)
-//   part 2 NT     the pixel count box (plane N and RC_00: exact integers)
-// where a "box" is the vertical difference at one column, P[yb] - P[ya], with
-// the band-closing rows in between.  A bin with no pixel in the window gets
-// p_b = 0 exactly instead of a rounding residue.
+// One block per centre; threads over (bin, part) pairs, NT + 3 parts per bin,
+// put the window's terms into LDS, then one thread per bin adds them in
+// order.  With XR = xc + rx + 1, XL = xc - rx, Ya = yc - ry, Yb = yc + ry + 1:
+//   part 0       the corners C_RB(Yb, XR) - C_LB(Yb, XL) - C_RT(Ya, XR) + C_LT(Ya, XL)
+//   part 1       the crossings, sum_c sum_j beta_j(yc) (V+_j(c, XR) - V-_j(c, XL))
+//   part 2 + i   alpha_i(xc) (RCB_i - RCT_i at the tile of XR, minus at the tile of XL)
+//   part NT + 2  the pixel count box (plane N and the count carry: exact integers)
+// c the band-closing rows strictly between Ya and Yb.  When Ya itself closes
+// a band, its top corners cancel against the crossing at c = Ya, so neither
+// is read.  A bin with no pixel in the window gets p_b = 0 exactly instead of
+// a rounding residue.
 template <int NT>
 __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
-  const GaussPlanes gp{(const float*)a.planes, a.RC};
+  const float* __restrict__ pl = (const float*)a.planes;
+  const float* __restrict__ XC = a.XC;
+  const double* __restrict__ RC = a.RC;
   const int32_t* __restrict__ centres = a.centres;
-  constexpr int D = 2 * NT + 1;
+  constexpr int D = NT + 3;
   __syncthreads();  // LDS reuse across virtual blocks of one block
-  extern __shared__ double part[];  // [B][2 NT + 1]
+  extern __shared__ double part[];  // [B][NT + 3]
   const int k = vb;
   const int xc = clampi(centres[2 * k], sp.rx, g.W - 1 - sp.rx);
   const int yc = clampi(centres[2 * k + 1], sp.ry, g.H - 1 - sp.ry);
@@ -189,43 +182,49 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const int txa = tile_of(xa), txb = tile_of(xb);
   // column X = 0 is not stored (it is zero): its loads go to column 1 and are dropped
   const bool xa0 = xa == 0;
+  const bool top = ya % g.TY != 0;
+  const int c0 = (ya / g.TY + 1) * g.TY;  // first crossing
   const int64_t oa = swih_xoff(g, xa0 ? 1 : xa), ob = swih_xoff(g, xb);
-  // the box at one column of plane pl: rows ya, yb and the band-closing rows between
-  auto box = [&](const float* pl, int64_t o) {
-    double d = (double)pl[(size_t)yb * rs + o] - (double)pl[(size_t)ya * rs + o];
-    for (int c = first_cross(ya, g.TY); c < yb; c += g.TY) d += (double)pl[(size_t)c * rs + o];
+  // the count box at one column: rows ya, yb and the crossings
+  auto nbox = [&](const float* pn, int64_t o) {
+    double d = (double)pn[(size_t)yb * rs + o] - (top ? (double)pn[(size_t)ya * rs + o] : 0.0);
+    for (int c = c0; c < yb; c += g.TY) d += (double)pn[(size_t)c * rs + o];
     return d;
   };
-  auto rcbox = [&](int p, int b) {
-    return (gp.RC[swih_rc(g, p, b, txb, yb)] - gp.RC[swih_rc(g, p, b, txb, ya)]) -
-           (gp.RC[swih_rc(g, p, b, txa, yb)] - gp.RC[swih_rc(g, p, b, txa, ya)]);
+  auto rcbox = [&](int qb, int qt, int b) {
+    return (RC[swih_rc(g, qb, b, txb, yb)] - RC[swih_rc(g, qt, b, txb, ya)]) -
+           (RC[swih_rc(g, qb, b, txa, yb)] - RC[swih_rc(g, qt, b, txa, ya)]);
   };
   for (int it = threadIdx.x; it < g.B * D; it += blockDim.x) {
     const int b = it / D, r = it - (it / D) * D;
-    const float* pb = gp.L + swih_base(g, 0, b);
-    double v;
-    if (r < NT) {
-      const double dr = box(pb + (size_t)r * 64, ob);
-      const double dl = xa0 ? 0.0 : box(pb + (size_t)(NT + r) * 64, oa);
-      v = be[r] * (dr - dl);
-    } else if (r < 2 * NT) {
-      const int i = r - NT;
-      double s = 0.0;
+    const float* pb = pl + swih_base(g, 0, b);
+    double v = 0.0;
+    if (r == 0) {
+      v = (double)pb[(size_t)yb * rs + ob] - (top ? (double)pb[(size_t)ya * rs + 64 + ob] : 0.0);
+      if (!xa0)
+        v -= (double)pb[(size_t)yb * rs + 128 + oa] -
+             (top ? (double)pb[(size_t)ya * rs + 192 + oa] : 0.0);
+    } else if (r == 1) {
+      for (int c = c0; c < yb; c += g.TY) {
+        const float* xr = XC + swih_xc(g, 0, b, c, xb);
+        const float* xl = XC + swih_xc(g, NT, b, c, xa0 ? 1 : xa);
 #pragma unroll
-      for (int j = 0; j < NT; ++j) s = fma(be[j], rcbox(i * NT + j, b), s);
-      v = al[i] * s;
+        for (int j = 0; j < NT; ++j)
+          v = fma(be[j], (double)xr[j * 64] - (xa0 ? 0.0 : (double)xl[j * 64]), v);
+      }
+    } else if (r < NT + 2) {
+      const int i = r - 2;
+      v = al[i] * rcbox(i, NT + i, b);
     } else {
-      const double nr = box(pb + (size_t)(2 * NT) * 64, ob);
-      const double nl = xa0 ? 0.0 : box(pb + (size_t)(2 * NT) * 64, oa);
-      v = (nr - nl) + rcbox(0, b);
+      v = nbox(pb + 256, ob) - (xa0 ? 0.0 : nbox(pb + 256, oa)) + rcbox(2 * NT, 2 * NT, b);
     }
     part[it] = v;
   }
   __syncthreads();
   for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
     double h = 0.0;
-    for (int r = 0; r < 2 * NT; ++r) h += part[b * D + r];
-    if (part[b * D + 2 * NT] == 0.0) h = 0.0;
+    for (int r = 0; r < NT + 2; ++r) h += part[b * D + r];
+    if (part[b * D + NT + 2] == 0.0) h = 0.0;
     a.hist[(size_t)k * g.B + b] = (float)(h / sp.mass);
   }
 }
@@ -263,36 +262,35 @@ __device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q 
 // Gaussian maps: the window sweep.
 //
 // A window's histogram is H_b(xc, yc) = sum_ij alpha_i(xc) beta_j(yc) B_ij,
-// B_ij the box of term (i, j).  The planes hold every column X already
-// contracted over i with the coefficients of the windows that have X as an
-// edge (right edge: xc = X - rx - 1, left edge: xc = X + rx), so with
-// XR = xc + rx + 1 and XL = xc - rx the window's edges
-//   H_b(xc, yc) = sum_j beta_j(yc) ((V+_j box at XR) - (V-_j box at XL))
-//                 + sum_i alpha_i(xc) sum_j beta_j(yc) (RC_ij box at XR - at XL)
-// where the box at one column is the vertical difference of the tile-local
-// storage,
-//   P[Yb] - P[Ya] = L[Yb] - L[Ya] + sum_c L[c] + RC[Yb] - RC[Ya],
-// (Ya = yc - ry, Yb = yc + ry + 1), c the band-closing rows (multiples of TY)
-// in [Ya, Yb).  When Ya itself closes a band its L cancels against the
-// crossing at c = Ya, so both drop.  The row carries RC hold the tile's origin
-// column and are not contracted in x: the RC box of a tile contracted with
-// beta is one value per x term for every column of the tile.
+// B_ij the box of term (i, j).  The planes hold, at every (Y, X), the
+// tile-local sums already contracted with the coefficients of the windows
+// that have (Y, X) as a corner, so with XR = xc + rx + 1, XL = xc - rx,
+// Ya = yc - ry, Yb = yc + ry + 1 the window's corners and edges,
+//   H_b = C_RB(Yb, XR) - C_LB(Yb, XL) - C_RT(Ya, XR) + C_LT(Ya, XL)
+//         + sum_c sum_j beta_j(yc) (V+_j(c, XR) - V-_j(c, XL))
+//         + sum_i alpha_i(xc) (RCB_i(Yb) - RCT_i(Ya) at the tile of XR, minus at the tile of XL)
+// c the band-closing rows (multiples of TY) strictly between Ya and Yb: the
+// tile-local sums restart at each band, so the column's full bands in between
+// are added from the side array XC.  When Ya itself closes a band, its top
+// corners cancel against the crossing at c = Ya, so both drop.  The row
+// carries RC hold the tile's origin column, contracted in y: one value per x
+// term for every column of the tile.
 //
 // Each lane owns one window centre and reads, per row event, its window's
-// 2 NT + 2 values (V+ and N at XR, V- and N at XL): a wave's 64 windows read
-// 64 consecutive columns at each edge, exactly what they need, and no window
-// waits for any other, so the sweep has no barrier.  A window's sum is a
-// sum of row events, each contracted with beta(yc): the opening row Ya
-// (minus), the crossings, the boundary row Yb (plus).
+// values at its two edges: a wave's 64 windows read 64 consecutive columns
+// at each edge, exactly what they need, and no window waits for any other, so
+// the sweep has no barrier.  A window's sum is a sum of row events: the
+// opening row Ya (its top corners), the crossings (contracted with
+// beta(yc)), the boundary row Yb (its bottom corners).
 //
 // Combs.  The centre rows yc = y0 + q + m h (h the window height) of comb q
 // follow one another so that member m's boundary row is member m + 1's
-// opening row.  A wave walks a segment of S members of one comb, reading each
-// boundary row once and contracting it twice (with beta(yc_m) for the member
-// it closes and beta(yc_m+1) for the one it opens).  Row carries: the wave's
-// right edges lie in at most two tiles and its left edges in two more; for
-// each, lanes 0..NT gather their x term's NT carries from the lanes that
-// loaded the tile's carry row and contract them with beta.
+// opening row.  A wave walks a segment of S members of one comb and reads
+// each boundary row once, for the member it closes (bottom corners) and the
+// one it opens (top corners).  Row carries: the wave's right edges lie in at
+// most two tiles and its left edges in two more; for each, lanes 0..NT load
+// the carry of their x term (lane NT: the count) at each boundary row, and
+// the windows gather and contract them with alpha(xc) when a member closes.
 //
 // Work item = (bin group, segment, comb, chunk of cw windows, one wave per 64):
 // a wave loops over the group's bins and walks the segment for each, keeping
@@ -341,18 +339,12 @@ __device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1,
   return n;
 }
 
-// The window sum of one row event: sum_j beta_j (V+_j at XR - V-_j at XL).
-template <int NT>
-__device__ __forceinline__ double edge_sum(const float (&d)[2 * NT + 2], const double (&bv)[NT]) {
-  double s = 0.0;
-#pragma unroll
-  for (int j = 0; j < NT; ++j) s = fma(bv[j], (double)d[j] - (double)d[NT + j], s);
-  return s;
-}
-
 template <int NT>
 __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
-  constexpr int D = 2 * NT + 2;                // V+ (NT), V- (NT), N at XR, N at XL
+  // a row's values: at a crossing V+ (NT) and V- (NT), at an opening or a
+  // boundary row the corners C_RB, C_RT at XR and C_LB, C_LT at XL (0..3);
+  // then N at XR and N at XL
+  constexpr int D = 2 * NT + 2;
   constexpr int GS = 21;                       // lanes per edge tile (x terms + the count)
   static_assert(NT + 1 <= GS, "series terms");
   const SwihGeom& g = a.g;
@@ -411,71 +403,67 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const int slot = lane / GS, ti = lane - slot * GS;
   const int mytile = slot == 0 ? tR0 : tL0 + slot - 1;
   const bool carries = slot < 3 && ti <= NT && mytile < g.NTX;
+  const int qB = ti < NT ? ti : 2 * NT, qT = ti < NT ? NT + ti : 2 * NT;
   const float* __restrict__ pl = (const float*)a.planes;
-  const int64_t oR = swih_xoff(g, XR), oL = swih_xoff(g, XLc) + NT * 64;
+  const int64_t oR = swih_xoff(g, XR), oL = swih_xoff(g, XLc);
+  // column parts of the XC offsets: V+ at XR, V- at XL
+  const int64_t xR = (int64_t)((XR - 1) >> 6) * (2 * NT * 64) + ((XR - 1) & 63);
+  const int64_t xL = (int64_t)((XLc - 1) >> 6) * (2 * NT * 64) + NT * 64 + ((XLc - 1) & 63);
   const double inv_mass = 1.0 / sp.mass;
   // an opening row that closes a band adds nothing and is not read
   auto reads = [&](const SweepEv& e) { return e.type != kEvOpen || e.Y % TY != 0; };
-  auto load = [&](float (&d)[D], double (&rc)[NT], const SweepEv& e) {
+  auto load = [&](float (&d)[D], double (&rc)[2], const SweepEv& e) {
     if (e.type != kEvCross && carries) {
-      // this lane's x term of its tile's carries at the row (the count: term (0, 0))
-      const double* __restrict__ qr =
-          a.RC + swih_rc(g, ti < NT ? ti * NT : 0, e.b, mytile, e.Y);
-#pragma unroll
-      for (int j = 0; j < NT; ++j) rc[j] = (ti < NT || j == 0) ? qr[j] : 0.0;
+      // this lane's x term of its tile's carries at the row, as a bottom and as a top row
+      const double* __restrict__ qr = a.RC + swih_rc(g, 0, e.b, mytile, e.Y);
+      rc[0] = qr[qB];
+      rc[1] = qr[qT];
     }
     if (!reads(e)) return;
     const float* __restrict__ row = pl + swih_base(g, 0, e.b) + (int64_t)e.Y * g.row_stride;
+    if (e.type == kEvCross) {
+      const float* __restrict__ xr =
+          a.XC + ((int64_t)e.b * g.NTY + (e.Y / TY - 1)) * g.NTX * (2 * NT * 64);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      d[j] = row[oR + j * 64];
-      d[NT + j] = row[oL + j * 64];
+      for (int j = 0; j < NT; ++j) {
+        d[j] = xr[xR + j * 64];
+        d[NT + j] = xr[xL + j * 64];
+      }
+    } else {
+      if (e.type == kEvBound) {
+        d[0] = row[oR];
+        d[2] = row[oL + 128];
+      }
+      d[1] = row[oR + 64];
+      d[3] = row[oL + 192];
     }
-    d[2 * NT] = row[oR + 2 * NT * 64];
-    d[2 * NT + 1] = row[oL + NT * 64];
+    d[2 * NT] = row[oR + 256];
+    d[2 * NT + 1] = row[oL + 256];
   };
   auto advance = [&](const SweepEv& e) { return sweep_next(e, cnt, b1, h, TY, Ya0); };
   double hh = 0.0, nn = 0.0;  // the member's window sum and pixel count so far
   double oh = 0.0, on = 0.0;  // the next member's opening row
-  double bcur[NT], bnxt[NT];  // beta of the current and the next member
-  auto beta = [&](double (&bv)[NT], int mm) {
+  double bcur[NT];            // beta of the current member
+  auto beta = [&](int mm) {
 #pragma unroll
-    for (int j = 0; j < NT; ++j) bv[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
+    for (int j = 0; j < NT; ++j) bcur[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
   };
-  // lanes of an edge tile: beta(m) RC at the member's opening row, and the
+  // lanes of an edge tile: the carry at the member's opening row, and the
   // member's carry box once it closes
   double qprev = 0.0, rbox = 0.0;
-  auto process = [&](float (&d)[D], const double (&rc)[NT], const SweepEv& e) {
+  auto process = [&](float (&d)[D], const double (&rc)[2], const SweepEv& e) {
     const bool withL = e.Y % TY != 0;  // as an opening row
-    const bool next = e.type == kEvBound && e.mm + 1 < cnt && withL;
-    if (e.type == kEvOpen) {
-      beta(bcur, 0);
-      beta(bnxt, 1);
-    }
-    if (xl0 && reads(e)) {
-#pragma unroll
-      for (int j = 0; j < NT; ++j) d[NT + j] = 0.0f;
-      d[2 * NT + 1] = 0.0f;
-    }
+    // a left-edge value: 0 at column 0
+    auto lv = [&](float v) { return xl0 ? 0.0 : (double)v; };
     if (e.type != kEvCross) {
-      double sc = 0.0, sn = 0.0;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        sc = fma(bcur[j], rc[j], sc);
-        sn = fma(bnxt[j], rc[j], sn);
-      }
-      if (ti == NT) sc = sn = rc[0];
-      if (e.type == kEvBound) {
-        rbox = sc - qprev;
-        qprev = sn;
-      } else {
-        qprev = sc;
-      }
+      if (e.type == kEvBound) rbox = rc[0] - qprev;
+      qprev = rc[1];
     }
     if (e.type == kEvOpen) {
+      beta(0);
       if (withL) {
-        oh = edge_sum<NT>(d, bcur);
-        on = (double)d[2 * NT] - (double)d[2 * NT + 1];
+        oh = (double)d[1] - lv(d[3]);
+        on = (double)d[2 * NT] - lv(d[2 * NT + 1]);
       } else {
         oh = on = 0.0;
       }
@@ -483,36 +471,39 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
       nn = -on;
       return;
     }
-    hh += edge_sum<NT>(d, bcur);
-    nn += (double)d[2 * NT] - (double)d[2 * NT + 1];
-    if (e.type != kEvBound) return;
-    if (next) {
-      oh = edge_sum<NT>(d, bnxt);
-      on = (double)d[2 * NT] - (double)d[2 * NT + 1];
+    const double dn = (double)d[2 * NT] - lv(d[2 * NT + 1]);
+    nn += dn;
+    if (e.type == kEvCross) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) hh = fma(bcur[j], (double)d[j] - lv(d[NT + j]), hh);
+      return;
+    }
+    hh += (double)d[0] - lv(d[2]);
+    if (e.mm + 1 < cnt && withL) {
+      oh = (double)d[1] - lv(d[3]);
+      on = dn;
     } else {
       oh = on = 0.0;
     }
     // the window's carry part: alpha(xc) . (box of its right-edge tile - left-edge tile)
-    double w[3], c[3];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    auto tile_box = [&](int s) {
       double t = 0.0;
 #pragma unroll
       for (int i = 0; i < NT; ++i) t = fma(al[i], readlane(rbox, GS * s + i), t);
-      w[s] = t;
-      c[s] = readlane(rbox, GS * s + NT);
-    }
+      return t;
+    };
+    const double w0 = tile_box(0), w1 = tile_box(1), w2 = tile_box(2);
+    const double c0 = readlane(rbox, NT), c1 = readlane(rbox, GS + NT), c2 = readlane(rbox, 2 * GS + NT);
     // right edges share tile tR0 except where lanes were clamped to the rectangle
-    const double wr = sR ? 0.0 : w[0], cr = sR ? 0.0 : c[0];
-    const double H = hh + wr - (xl0 ? 0.0 : (sL ? w[2] : w[1]));
-    const double N = nn + cr - (xl0 ? 0.0 : (sL ? c[2] : c[1]));
+    const double wr = sR ? 0.0 : w0, cr = sR ? 0.0 : c0;
+    const double wl = xl0 ? 0.0 : (sL ? w2 : w1), cl = xl0 ? 0.0 : (sL ? c2 : c1);
+    const double H = hh + wr - wl;
+    const double N = nn + cr - cl;
     const int32_t v = N != 0.0 ? bc_term(H * inv_mass, a.tmpl[e.b]) : 0;
     acc[e.mm * 64 + lane] += v;
     hh = -oh;
     nn = -on;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) bcur[j] = bnxt[j];
-    beta(bnxt, e.mm + 2);
+    beta(e.mm + 1);
   };
   SweepEv e0;
   e0.b = b0;
@@ -522,9 +513,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   // two register buffers alternate: the next row's loads are in flight while
   // the current row is contracted
   float dA[D], dB[D];
-  double rA[NT], rB[NT];
-#pragma unroll
-  for (int j = 0; j < NT; ++j) rA[j] = rB[j] = 0.0;
+  double rA[2] = {0.0, 0.0}, rB[2] = {0.0, 0.0};
   load(dA, rA, e0);
   for (;;) {
     const SweepEv e1 = advance(e0);

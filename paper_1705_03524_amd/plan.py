@@ -24,11 +24,11 @@ class Plan:
 
     @property
     def nplanes(self) -> int:
-        """Stored planes per bin: 1 uniform, 3 Manhattan, 5 Euclidean, 2 (2K+1) + 1 for the
-        Gaussian (its (2K+1)^2 weight terms contracted at the window edges, plus the count),
+        """Stored planes per bin: 1 uniform, 3 Manhattan, 5 Euclidean, 5 for the Gaussian
+        (its (2K+1)^2 weight terms contracted at the window corners, plus the count),
         2K+1 per axis for the separable Gaussian, 4 directions for the exponential."""
         if self.cfg.kernel == S.GAUSSIAN:
-            return 2 * (2 * self.cfg.K + 1) + 1
+            return 5
         if self.cfg.kernel == S.GAUSSIAN_SEP:
             return 2 * self.cfg.K + 1
         return {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4}[self.cfg.kernel]

@@ -227,14 +227,13 @@ def plane_bytes(cfg: S.Config, units) -> int:
     """Algorithmic bytes the builds write: 4 T B (H+1)(W+1) per plane set, or for
     the separable Gaussian 4 B H (W - w + 1) of row results per scale.  The
     Gaussian and the exponential keep one plane set per scale."""
-    K = cfg.K
     tot = 0
     for u in units:
         H, W = u.img.shape
         if cfg.kernel == S.GAUSSIAN_SEP:
             tot += sum(4 * cfg.nbins * H * (W - w + 1) for w, _ in u.scales)
             continue
-        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4}.get(cfg.kernel, 2 * (2 * K + 1) + 1)
+        T = {S.UNIFORM: 1, S.MANHATTAN: 3, S.EUCLIDEAN: 5, S.EXPONENTIAL: 4, S.GAUSSIAN: 5}[cfg.kernel]
         nsets = len(u.scales) if cfg.kernel in (S.GAUSSIAN, S.EXPONENTIAL) else 1
         tot += nsets * 4 * T * cfg.nbins * (H + 1) * (W + 1)
     return tot
