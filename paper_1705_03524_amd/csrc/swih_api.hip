@@ -69,6 +69,7 @@ int make_layout(const swih_config* c, int32_t H, int32_t W, SwihLayout& L) {
     return SWIH_OK;
   }
   g.TY = c->band_rows ? c->band_rows : kDefaultTY;
+  g.lgTY = g.TY == 16 ? 4 : g.TY == 32 ? 5 : 6;
   g.NTX = (W + SWIH_TX - 1) / SWIH_TX;
   g.NTY = (H + g.TY - 1) / g.TY;
   if (c->kernel == SWIH_EXPONENTIAL) {  // four direction planes per bin (swih_exp.hip)

@@ -716,7 +716,7 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     dst[256] = (float)cnt;
   }
   const int Yl = t.y0 + t.nrows;  // the band's last stored row
-  if (Yl % g.TY == 0 && Yl < g.H) {
+  if ((Yl & (g.TY - 1)) == 0 && Yl < g.H) {
     float* xc = a.XC + swih_xc(g, 0, t.b, Yl, X);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {

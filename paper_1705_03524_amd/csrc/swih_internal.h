@@ -113,6 +113,7 @@ struct MatchArgs {
   const void* planes;      // uint32 planes or float tile-local planes
   const double* RC;        // Gaussian row carries
   const float* XC;         // Gaussian band-closing rows
+  const double* beta;      // Gaussian: [H+1][2 nJ] y coefficients per row (bottom, top edge)
   const float* tmpl;       // normalised template, or null
   const uint32_t* tmpl_raw;  // exact template (integer kernels), or null
   float* map;

@@ -69,7 +69,8 @@
 
 struct SwihGeom {
   int32_t H, W, B;       // image size, bins
-  int32_t TY;            // band height (<= 64)
+  int32_t TY;            // band height: 16, 32 or 64
+  int32_t lgTY;          // log2 TY
   int32_t NTX, NTY;      // tiles across, bands down
   int32_t nP, nI, nJ;    // weight terms, x terms, y terms
   int32_t nPL;           // stored planes per bin (integer kernels: nP; Gaussian: 5)
@@ -106,7 +107,7 @@ __host__ __device__ inline int64_t swih_rc(const SwihGeom& g, int q, int b, int 
 // positive multiple of TY below H), value q, bin b, at column X >= 1:
 // XC[b][c / TY - 1][tx][q][64].
 __host__ __device__ inline int64_t swih_xc(const SwihGeom& g, int q, int b, int c, int X) {
-  return (((int64_t)b * g.NTY + (c / g.TY - 1)) * g.NTX + ((X - 1) >> 6)) * (2 * g.nJ * 64) +
+  return (((int64_t)b * g.NTY + ((c >> g.lgTY) - 1)) * g.NTX + ((X - 1) >> 6)) * (2 * g.nJ * 64) +
          q * 64 + ((X - 1) & 63);
 }
 

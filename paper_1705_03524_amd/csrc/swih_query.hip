@@ -186,10 +186,10 @@ constexpr int kSweepMaxS = 32;         // members per segment, single maps
 constexpr int kSweepBatchS = 16;       // members per segment in batches
 constexpr size_t kLdsMax = 160 * 1024;
 
-// LDS of a sweep block: beta of the members and each wave's (member, window)
-// accumulators.
-size_t sweep_lds(int waves, int S, int NT) {
-  return sizeof(double) * (size_t)S * NT + sizeof(int32_t) * (size_t)waves * S * 64;
+// LDS of a sweep block: each wave's carry boxes of its three edge tiles (3 x 21
+// doubles) and its (member, window) accumulators.
+size_t sweep_lds(int waves, int S) {
+  return sizeof(double) * (size_t)waves * 3 * 21 + sizeof(int32_t) * (size_t)waves * S * 64;
 }
 
 int device_cus() {
@@ -242,7 +242,7 @@ static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int
   a.ngroups = (B + a.bpg - 1) / a.bpg;
   ml.blocks = a.ngroups * a.nch * a.nseg * a.ncomb;
   ml.threads = 64 * waves;
-  ml.lds = sweep_lds(waves, a.S, NT);
+  ml.lds = sweep_lds(waves, a.S);
 }
 
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,
@@ -255,6 +255,7 @@ void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char*
   a.planes = sb + L.off_planes;
   a.RC = L.g.gauss ? (const double*)(sb + L.off_RC) : nullptr;
   a.XC = L.g.gauss ? (const float*)(sb + L.off_XC) : nullptr;
+  a.beta = L.g.gauss ? (const double*)(sb + L.off_beta) : nullptr;
   a.tmpl = tmpl;
   a.tmpl_raw = tmpl_raw;
   a.map = map;

@@ -182,8 +182,8 @@ __device__ __forceinline__ void query_gauss(const QueryArgs& a, int vb) {
   const int txa = tile_of(xa), txb = tile_of(xb);
   // column X = 0 is not stored (it is zero): its loads go to column 1 and are dropped
   const bool xa0 = xa == 0;
-  const bool top = ya % g.TY != 0;
-  const int c0 = (ya / g.TY + 1) * g.TY;  // first crossing
+  const bool top = (ya & (g.TY - 1)) != 0;
+  const int c0 = ((ya >> g.lgTY) + 1) << g.lgTY;  // first crossing
   const int64_t oa = swih_xoff(g, xa0 ? 1 : xa), ob = swih_xoff(g, xb);
   // the count box at one column: rows ya, yb and the crossings
   auto nbox = [&](const float* pn, int64_t o) {
@@ -309,7 +309,7 @@ struct SweepEv {
 
 // The event after e (unit 0 of it) in the walk of a segment of cnt members
 // over bins [., b1).
-__device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1, int h, int TY,
+__device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1, int h, int lgTY,
                                               int Ya0) {
   SweepEv n = e;
   int Ya = e.Ya, mm = e.mm, c;
@@ -327,9 +327,9 @@ __device__ __forceinline__ SweepEv sweep_next(const SweepEv& e, int cnt, int b1,
     }
     mm += 1;
     Ya = e.Y;
-    c = (Ya / TY + 1) * TY;
+    c = ((Ya >> lgTY) + 1) << lgTY;
   } else {
-    c = e.type == kEvOpen ? (Ya / TY + 1) * TY : e.Y + TY;
+    c = e.type == kEvOpen ? ((Ya >> lgTY) + 1) << lgTY : e.Y + (1 << lgTY);
   }
   const int Yb = Ya + h;
   n.mm = mm;
@@ -371,21 +371,16 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const bool live = 64 * wv < a.cw && xs <= a.x1;
   const int ycb = a.y0 + q + m0 * h;  // first centre row of the segment
   const int Ya0 = ycb - ry;
-  const int TY = g.TY;
-  __syncthreads();  // LDS reuse across virtual blocks of one block
-  extern __shared__ double sm[];
-  double* BE = sm;                                            // [S][NT]: beta of the members
-  int32_t* acc = (int32_t*)(BE + (size_t)a.S * NT) + (size_t)wv * a.S * 64;  // [S][64] per wave
-  for (int mm = tid; mm < cnt; mm += (int)blockDim.x) {
-    double be[NT];
-    series_coeffs<NT>(sp.ay, ycb + mm * h, be);
-#pragma unroll
-    for (int j = 0; j < NT; ++j) BE[mm * NT + j] = be[j];
-  }
-  if (live)
-    for (int mm = 0; mm < cnt; ++mm) acc[mm * 64 + lane] = 0;
-  __syncthreads();  // BE ready; no barrier after this one
+  const int lgTY = g.lgTY, ymask = g.TY - 1;
+  // the waves' LDS regions move with the item's S: every wave has left the
+  // previous virtual block of its block before any reuses it; no barrier after
+  // this one (each lane touches only its own entries)
+  __syncthreads();
+  extern __shared__ double slds[];
+  double* rcs = slds + wv * 3 * GS;  // [3 GS] per wave: the edge tiles' carry boxes
+  int32_t* acc = (int32_t*)(slds + a.nt * 3 * GS) + (size_t)wv * a.S * 64;  // [S][64] per wave
   if (!live) return;
+  for (int mm = 0; mm < cnt; ++mm) acc[mm * 64 + lane] = 0;
   const bool mine = xs + lane >= a.x0 && xs + lane <= a.x1;
   // lanes outside the rectangle follow its nearest window
   const int xc = min(max(xs + lane, a.x0), a.x1);
@@ -400,6 +395,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const int tR0 = __builtin_amdgcn_readfirstlane((XR - 1) >> 6);
   const int tL0 = __builtin_amdgcn_readfirstlane((XLc - 1) >> 6);
   const int sR = ((XR - 1) >> 6) - tR0, sL = ((XLc - 1) >> 6) - tL0;
+  const int ls = GS * (1 + sL);  // first lane of this lane's left edge tile
   const int slot = lane / GS, ti = lane - slot * GS;
   const int mytile = slot == 0 ? tR0 : tL0 + slot - 1;
   const bool carries = slot < 3 && ti <= NT && mytile < g.NTX;
@@ -411,7 +407,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const int64_t xL = (int64_t)((XLc - 1) >> 6) * (2 * NT * 64) + NT * 64 + ((XLc - 1) & 63);
   const double inv_mass = 1.0 / sp.mass;
   // an opening row that closes a band adds nothing and is not read
-  auto reads = [&](const SweepEv& e) { return e.type != kEvOpen || e.Y % TY != 0; };
+  auto reads = [&](const SweepEv& e) { return e.type != kEvOpen || (e.Y & ymask) != 0; };
   auto load = [&](float (&d)[D], double (&rc)[2], const SweepEv& e) {
     if (e.type != kEvCross && carries) {
       // this lane's x term of its tile's carries at the row, as a bottom and as a top row
@@ -423,7 +419,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     const float* __restrict__ row = pl + swih_base(g, 0, e.b) + (int64_t)e.Y * g.row_stride;
     if (e.type == kEvCross) {
       const float* __restrict__ xr =
-          a.XC + ((int64_t)e.b * g.NTY + (e.Y / TY - 1)) * g.NTX * (2 * NT * 64);
+          a.XC + ((int64_t)e.b * g.NTY + ((e.Y >> lgTY) - 1)) * g.NTX * (2 * NT * 64);
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         d[j] = xr[xR + j * 64];
@@ -440,19 +436,22 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     d[2 * NT] = row[oR + 256];
     d[2 * NT + 1] = row[oL + 256];
   };
-  auto advance = [&](const SweepEv& e) { return sweep_next(e, cnt, b1, h, TY, Ya0); };
+  auto advance = [&](const SweepEv& e) { return sweep_next(e, cnt, b1, h, lgTY, Ya0); };
   double hh = 0.0, nn = 0.0;  // the member's window sum and pixel count so far
   double oh = 0.0, on = 0.0;  // the next member's opening row
   double bcur[NT];            // beta of the current member
+  // beta(yc) of member mm: the build's row table holds it at row yc - ry as a top edge
+  const double* __restrict__ btab = a.beta + (size_t)(ycb - ry) * 2 * NT + NT;
   auto beta = [&](int mm) {
+    const int m = min(mm, cnt - 1);  // past the last member: never used
 #pragma unroll
-    for (int j = 0; j < NT; ++j) bcur[j] = mm < cnt ? uniform(BE[mm * NT + j]) : 0.0;
+    for (int j = 0; j < NT; ++j) bcur[j] = btab[(size_t)m * h * 2 * NT + j];
   };
   // lanes of an edge tile: the carry at the member's opening row, and the
   // member's carry box once it closes
   double qprev = 0.0, rbox = 0.0;
   auto process = [&](float (&d)[D], const double (&rc)[2], const SweepEv& e) {
-    const bool withL = e.Y % TY != 0;  // as an opening row
+    const bool withL = (e.Y & ymask) != 0;  // as an opening row
     // a left-edge value: 0 at column 0
     auto lv = [&](float v) { return xl0 ? 0.0 : (double)v; };
     if (e.type != kEvCross) {
@@ -486,19 +485,21 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
       oh = on = 0.0;
     }
     // the window's carry part: alpha(xc) . (box of its right-edge tile - left-edge tile)
-    auto tile_box = [&](int s) {
-      double t = 0.0;
+    // every lane's right edge tile is the wave's (lanes GS s + i hold tile s's boxes),
+    // its left edge tile one of two
+    // (passed through the wave's LDS slots: a wave's LDS accesses complete in order)
+    if (carries) rcs[lane] = rbox;
+    const double* __restrict__ rl = rcs + ls;
+    double wr = 0.0, wl = 0.0;
 #pragma unroll
-      for (int i = 0; i < NT; ++i) t = fma(al[i], readlane(rbox, GS * s + i), t);
-      return t;
-    };
-    const double w0 = tile_box(0), w1 = tile_box(1), w2 = tile_box(2);
-    const double c0 = readlane(rbox, NT), c1 = readlane(rbox, GS + NT), c2 = readlane(rbox, 2 * GS + NT);
+    for (int i = 0; i < NT; ++i) {
+      wr = fma(al[i], rcs[i], wr);
+      wl = fma(al[i], rl[i], wl);
+    }
+    const double cr = rcs[NT], cl = rl[NT];
     // right edges share tile tR0 except where lanes were clamped to the rectangle
-    const double wr = sR ? 0.0 : w0, cr = sR ? 0.0 : c0;
-    const double wl = xl0 ? 0.0 : (sL ? w2 : w1), cl = xl0 ? 0.0 : (sL ? c2 : c1);
-    const double H = hh + wr - wl;
-    const double N = nn + cr - cl;
+    const double H = hh + (sR ? 0.0 : wr) - (xl0 ? 0.0 : wl);
+    const double N = nn + (sR ? 0.0 : cr) - (xl0 ? 0.0 : cl);
     const int32_t v = N != 0.0 ? bc_term(H * inv_mass, a.tmpl[e.b]) : 0;
     acc[e.mm * 64 + lane] += v;
     hh = -oh;

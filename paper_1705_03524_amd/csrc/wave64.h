@@ -81,6 +81,14 @@ __device__ __forceinline__ double readlane(double v, int lane) {
   return __builtin_bit_cast(double, (uint64_t)readlane(__builtin_bit_cast(int64_t, v), lane));
 }
 
+// The value v of lane src (src may differ from lane to lane).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Put a wave-uniform value into one lane of a per-lane register.
 template <typename T>
 __device__ __forceinline__ T put_lane(T reg, T val, int lane) {
