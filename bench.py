@@ -370,7 +370,7 @@ def run_multiscale(args):
                   "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
         "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
                             "every valid centre; average over the 5 scales)",
-                  "alg": plane_bytes + 4 * sum(nwin) / nsc,
+                  "alg": plane_bytes + rc_bytes + 4 * sum(nwin) / nsc,
                   "ms": sum(per["match_%d" % w] for w in MS_SCALES) / nsc,
                   "prefixes": ("k_sweep", "match_gauss_fin"), "unit": "k_sweep"},
     }
@@ -1000,9 +1000,10 @@ def run_frame(args, side_kinds=True, builds=True, cpu=True):
 
     nwin = (H - WIN + 1) * (W - WIN + 1)
     value = len(KERNELS) * nwin / (ms / 1e3)
-    # Algorithmic bytes of the two Gaussian kernels ((2K+1)^2 weight terms x 16 bins):
-    # the plane build reads the image once and writes every plane element once;
-    # the dense map reads every plane element once and writes one float per centre.
+    # Algorithmic bytes of the two Gaussian kernels (5 corner-contracted planes x 16
+    # bins, plus the row carries and band-closing rows): the plane build reads the
+    # image once and writes every stored element once; the dense map reads every
+    # stored element once and writes one float per centre.
     K = plans["gaussian"].cfg.K
     T = GAUSS_PLANES
     plane_bytes = 4 * T * NBINS * (H + 1) * (W + 1)
@@ -1012,7 +1013,7 @@ def run_frame(args, side_kinds=True, builds=True, cpu=True):
                   "prefixes": ("emit_gauss",), "unit": "emit_gauss"},
         "match": {"kernel": "k_sweep + match_gauss_fin (Gaussian dense likelihood map, "
                             "482x482 centres; the finalising pass is ~1% of the phase)",
-                  "alg": plane_bytes + 4 * nwin, "ms": per["match_gaussian"],
+                  "alg": plane_bytes + gauss_side_bytes(K, NBINS, H, W) + 4 * nwin, "ms": per["match_gaussian"],
                   "prefixes": ("k_sweep", "match_gauss_fin"), "unit": "k_sweep"},
     }
 
