@@ -186,10 +186,10 @@ constexpr int kSweepMaxS = 32;         // members per segment, single maps
 constexpr int kSweepBatchS = 16;       // members per segment in batches
 constexpr size_t kLdsMax = 160 * 1024;
 
-// LDS of a sweep block: each wave's carry boxes of its three edge tiles (3 x 21
-// doubles) and its (member, window) accumulators.
+// LDS of a sweep block: each wave's carry boxes of its three edge tiles (a
+// double per lane) and its (member, window) accumulators.
 size_t sweep_lds(int waves, int S) {
-  return sizeof(double) * (size_t)waves * 3 * 21 + sizeof(int32_t) * (size_t)waves * S * 64;
+  return sizeof(double) * (size_t)waves * 64 + sizeof(int32_t) * (size_t)waves * S * 64;
 }
 
 int device_cus() {

@@ -377,8 +377,8 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   // this one (each lane touches only its own entries)
   __syncthreads();
   extern __shared__ double slds[];
-  double* rcs = slds + wv * 3 * GS;  // [3 GS] per wave: the edge tiles' carry boxes
-  int32_t* acc = (int32_t*)(slds + a.nt * 3 * GS) + (size_t)wv * a.S * 64;  // [S][64] per wave
+  double* rcs = slds + wv * 64;  // [64] per wave: lane GS s + i holds edge tile s's box of term i
+  int32_t* acc = (int32_t*)(slds + a.nt * 64) + (size_t)wv * a.S * 64;  // [S][64] per wave
   if (!live) return;
   for (int mm = 0; mm < cnt; ++mm) acc[mm * 64 + lane] = 0;
   const bool mine = xs + lane >= a.x0 && xs + lane <= a.x1;
@@ -408,18 +408,31 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   const double inv_mass = 1.0 / sp.mass;
   // an opening row that closes a band adds nothing and is not read
   auto reads = [&](const SweepEv& e) { return e.type != kEvOpen || (e.Y & ymask) != 0; };
+  // the bin's bases, recomputed when the walk reaches the next bin (loads run in
+  // event order); within a bin a row costs one 32-bit product per base
+  const int rs = (int)g.row_stride, xrs = g.NTX * (2 * NT * 64), nrc = g.nRC;
+  const int ctile = min(mytile, g.NTX - 1);
+  int lb = -1;
+  const float* pbin = pl;     // the bin's planes
+  int64_t xbin = 0;           // the bin's band-closing rows in XC
+  const double* rcl = a.RC;   // this lane's carry tile of the bin, row 0
   auto load = [&](float (&d)[D], double (&rc)[2], const SweepEv& e) {
+    if (e.b != lb) {
+      lb = e.b;
+      pbin = pl + swih_base(g, 0, e.b);
+      xbin = (int64_t)e.b * g.NTY * xrs;
+      rcl = a.RC + swih_rc(g, 0, e.b, ctile, 0);
+    }
     if (e.type != kEvCross && carries) {
       // this lane's x term of its tile's carries at the row, as a bottom and as a top row
-      const double* __restrict__ qr = a.RC + swih_rc(g, 0, e.b, mytile, e.Y);
+      const double* __restrict__ qr = rcl + e.Y * nrc;
       rc[0] = qr[qB];
       rc[1] = qr[qT];
     }
     if (!reads(e)) return;
-    const float* __restrict__ row = pl + swih_base(g, 0, e.b) + (int64_t)e.Y * g.row_stride;
+    const float* __restrict__ row = pbin + e.Y * rs;
     if (e.type == kEvCross) {
-      const float* __restrict__ xr =
-          a.XC + ((int64_t)e.b * g.NTY + ((e.Y >> lgTY) - 1)) * g.NTX * (2 * NT * 64);
+      const float* __restrict__ xr = a.XC + xbin + ((e.Y >> lgTY) - 1) * xrs;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         d[j] = xr[xR + j * 64];
@@ -488,7 +501,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     // every lane's right edge tile is the wave's (lanes GS s + i hold tile s's boxes),
     // its left edge tile one of two
     // (passed through the wave's LDS slots: a wave's LDS accesses complete in order)
-    if (carries) rcs[lane] = rbox;
+    rcs[lane] = rbox;  // read back only from carry lanes
     const double* __restrict__ rl = rcs + ls;
     double wr = 0.0, wl = 0.0;
 #pragma unroll
