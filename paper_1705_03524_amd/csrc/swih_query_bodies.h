@@ -452,14 +452,17 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   auto advance = [&](const SweepEv& e) { return sweep_next(e, cnt, b1, h, lgTY, Ya0); };
   double hh = 0.0, nn = 0.0;  // the member's window sum and pixel count so far
   double oh = 0.0, on = 0.0;  // the next member's opening row
-  double bcur[NT];            // beta of the current member
-  // beta(yc) of member mm: the build's row table holds it at row yc - ry as a top edge
+  // beta(yc) of the current member: the build's row table holds it at row
+  // yc - ry as a top edge, members h rows apart.
+  double bcur[NT];
   const double* __restrict__ btab = a.beta + (size_t)(ycb - ry) * 2 * NT + NT;
+  const int bstep = h * 2 * NT;
   auto beta = [&](int mm) {
-    const int m = min(mm, cnt - 1);  // past the last member: never used
+    const double* __restrict__ br = btab + min(mm, cnt - 1) * bstep;  // past the last: never used
 #pragma unroll
-    for (int j = 0; j < NT; ++j) bcur[j] = btab[(size_t)m * h * 2 * NT + j];
+    for (int j = 0; j < NT; ++j) bcur[j] = br[j];
   };
+  float tb = 0.0f;  // the bin's template value
   // lanes of an edge tile: the carry at the member's opening row, and the
   // member's carry box once it closes
   double qprev = 0.0, rbox = 0.0;
@@ -473,6 +476,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     }
     if (e.type == kEvOpen) {
       beta(0);
+      tb = a.tmpl[e.b];
       if (withL) {
         oh = (double)d[1] - lv(d[3]);
         on = (double)d[2 * NT] - lv(d[2 * NT + 1]);
@@ -513,7 +517,7 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
     // right edges share tile tR0 except where lanes were clamped to the rectangle
     const double H = hh + (sR ? 0.0 : wr) - (xl0 ? 0.0 : wl);
     const double N = nn + (sR ? 0.0 : cr) - (xl0 ? 0.0 : cl);
-    const int32_t v = N != 0.0 ? bc_term(H * inv_mass, a.tmpl[e.b]) : 0;
+    const int32_t v = N != 0.0 ? bc_term(H * inv_mass, tb) : 0;
     acc[e.mm * 64 + lane] += v;
     hh = -oh;
     nn = -on;
