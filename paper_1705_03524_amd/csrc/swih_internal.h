@@ -119,11 +119,11 @@ struct MatchArgs {
   float* map;
   int32_t x0, y0, x1, y1;  // inclusive centre rectangle
   int32_t nbx;             // integer kernels: virtual blocks per row of blocks
-  // Gaussian comb sweep: items = ngroups x nch x nseg x ncomb
-  int32_t nch, cw, nt;     // column chunks, centres per chunk, tiles (waves) per block
+  // Gaussian comb sweep: items = ngroups x nseg x (comb groups of cpb) x nch
+  int32_t nch, cw, nt;     // column chunks, centres per chunk, waves per chunk
   int32_t ncomb, nseg, S;  // combs, segments per comb, members per segment
   int32_t ngroups, bpg;    // bin groups, bins per group
-  int32_t two;             // 1: a block's waves cover the left-edge and the right-edge tiles apart
+  int32_t cpb;             // combs per block (each nt waves)
   int32_t* acc;            // ngroups > 1: per-centre integer accumulator (zero between maps)
 };
 

@@ -209,9 +209,9 @@ int device_cus() {
 
 // Plan of a Gaussian window sweep over the centre rectangle: chunks of 64
 // windows per wave, combs, segments and bin groups, and the launch shape.
-// cus == 0: the batch form (chunks as wide as the job, up to
-// kSweepBatchWaves waves; one bin group; segments of up to kSweepBatchS
-// members).  Otherwise blocks of kSweepWaves,
+// cus == 0: the batch form (blocks of kSweepBatchWaves waves; chunks as wide
+// as the job, and as many combs per block as such chunks fit; one bin group;
+// segments of up to kSweepBatchS members).  Otherwise blocks of kSweepWaves,
 // segments of up to kSweepMaxS members (a segment costs one opening row per
 // bin), then bin groups (powers of two) until the launch has 128 waves per
 // compute unit: many short waves hide the loads' latency and balance the
@@ -220,10 +220,11 @@ int device_cus() {
 static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int ny, int cus,
                        MatchArgs& a, Launch& ml) {
   const int h = 2 * sp.ry + 1;
-  // a batch job's chunk is as wide as the job, up to the batch block's waves
+  // a batch job's chunk is as wide as the job, up to the batch block's waves;
+  // a narrower job packs several combs into the block
   const int waves = cus > 0 ? kSweepWaves : std::min(kSweepBatchWaves, (nx + 63) / 64 + 1);
-  a.two = 0;
   a.nt = waves;
+  a.cpb = cus > 0 ? 1 : kSweepBatchWaves / waves;
   a.cw = 64 * waves;
   // chunks start where a wave's right edges begin a tile (the sweep's xo)
   const int xo = x0 - ((x0 + sp.rx) & 63);
@@ -240,9 +241,12 @@ static void sweep_plan(const ScaleParams& sp, int B, int NT, int x0, int nx, int
   }
   a.bpg = (B + ng - 1) / ng;
   a.ngroups = (B + a.bpg - 1) / a.bpg;
-  ml.blocks = a.ngroups * a.nch * a.nseg * a.ncomb;
-  ml.threads = 64 * waves;
-  ml.lds = sweep_lds(waves, a.S);
+  ml.blocks = a.ngroups * a.nch * a.nseg * ((a.ncomb + a.cpb - 1) / a.cpb);
+  // batch items take the batch block whatever their width: the body lays its
+  // LDS out by the launch's block size
+  const int bw = cus > 0 ? waves : kSweepBatchWaves;
+  ml.threads = 64 * bw;
+  ml.lds = sweep_lds(bw, a.S);
 }
 
 void match_args(const SwihLayout& L, const ScaleParams& sp, int set, const char* ws,

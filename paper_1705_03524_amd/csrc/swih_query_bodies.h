@@ -349,26 +349,31 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   static_assert(NT + 1 <= GS, "series terms");
   const SwihGeom& g = a.g;
   const ScaleParams& sp = a.sp;
+  // item = (bin group, segment, comb group, chunk); a block's waves cover the
+  // chunk's nt sub-chunks of 64 windows for each of cpb combs (batches pack
+  // the combs of narrow jobs into one block)
+  const int ncg = (a.ncomb + a.cpb - 1) / a.cpb;
   const int ch = vb % a.nch;
   int r = vb / a.nch;
-  const int q = r % a.ncomb;
-  r /= a.ncomb;
+  const int qg = r % ncg;
+  r /= ncg;
   const int sg = r % a.nseg;
   const int grp = r / a.nseg;
+  const int tid = (int)threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int sub = wv / a.nt, wsub = wv - sub * a.nt;
+  const int q = qg * a.cpb + sub;
   const int ny = a.y1 - a.y0 + 1, rx = sp.rx, ry = sp.ry, h = 2 * ry + 1;
   const int Mq = q < ny ? (ny - q + h - 1) / h : 0;  // centre rows of comb q
   const int m0 = sg * a.S;
-  if (m0 >= Mq) return;  // uniform over the block
   const int cnt = min(a.S, Mq - m0);
   const int b0 = grp * a.bpg, b1 = min(b0 + a.bpg, g.B);
-  const int tid = (int)threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   // chunks start where a wave's right edges begin a tile: they then lie in
   // one tile, its left edges in at most two
   const int xo = a.x0 - ((a.x0 + rx) & 63);
-  const int xs = xo + ch * a.cw + 64 * wv;  // the wave's first window
+  const int xs = xo + ch * a.cw + 64 * wsub;  // the wave's first window
   // a launch may have more waves than the item (a batch's largest block)
-  const bool live = 64 * wv < a.cw && xs <= a.x1;
+  const bool live = sub < a.cpb && q < a.ncomb && m0 < Mq && xs <= a.x1;
   const int ycb = a.y0 + q + m0 * h;  // first centre row of the segment
   const int Ya0 = ycb - ry;
   const int lgTY = g.lgTY, ymask = g.TY - 1;
@@ -377,8 +382,9 @@ __device__ __forceinline__ void match_gauss_sweep(const MatchArgs& a, int vb) {
   // this one (each lane touches only its own entries)
   __syncthreads();
   extern __shared__ double slds[];
+  const int nwb = (int)(blockDim.x >> 6);
   double* rcs = slds + wv * 64;  // [64] per wave: lane GS s + i holds edge tile s's box of term i
-  int32_t* acc = (int32_t*)(slds + a.nt * 64) + (size_t)wv * a.S * 64;  // [S][64] per wave
+  int32_t* acc = (int32_t*)(slds + nwb * 64) + (size_t)wv * a.S * 64;  // [S][64] per wave
   if (!live) return;
   for (int mm = 0; mm < cnt; ++mm) acc[mm * 64 + lane] = 0;
   const bool mine = xs + lane >= a.x0 && xs + lane <= a.x1;
