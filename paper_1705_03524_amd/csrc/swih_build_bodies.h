@@ -1,10 +1,12 @@
 // Weighted integral histogram build for gfx950 (Sec. 2.1, Eq. 2).
 //
-// One plane per (weight term p = (i, j), bin b):
+// Per weight term p = (i, j) and bin b, the prefix sums
 //   P[Y][X] = sum_{x < X, y < Y} [Q(f(x, y)) = b] u_i(x) v_j(y).
-// Every u_i v_j product is a weight image w_dir of Eq. 2; the window-centre
-// translation of Sec. 2.1 is applied later, at query time, through per-centre
-// coefficients (see swih_query_bodies.h).
+// Every u_i v_j product is a weight image w_dir of Eq. 2.  The integer kernels
+// store one plane per term and apply the window-centre translation of
+// Sec. 2.1 at query time; the Gaussian stores its terms already contracted
+// with the translation coefficients of the windows each point is a corner of
+// (swih_layout.h; the lookups in swih_query_bodies.h).
 //
 // The 2-D prefix is computed in three launches over a grid of 64-column tiles
 // (one wave64 lane per pixel column) and TY-row bands:
@@ -16,14 +18,14 @@
 //   2. scan: exclusive prefix of z over bands (the carry row above a band),
 //      of T over tiles (the carry column left of a tile), and a 2-D exclusive
 //      prefix of the tile totals (the value at each tile's origin corner).
-//   3. emit: per (band, tile, bin[, i]) wave, rows top to bottom: a wave64 DPP
+//   3. emit: per (band, tile, bin) wave, rows top to bottom: a wave64 DPP
 //      inclusive scan of u_i m gives the row prefix inside the tile, the carries
 //      complete it, and v_j(y) times it accumulates into each plane's column
 //      running sum, stored once per element with coalesced 256-byte rows.
 // Integer kernels accumulate modulo 2^32.  The Gaussian runs its horizontal
 // scans in int32 fixed point (exact), accumulates each tile's columns in
-// double relative to the tile's own origin and stores them as float, and
-// keeps the cross-tile row carries in double.
+// double relative to the tile's own origin, contracts them and stores the
+// result as float, and keeps the cross-tile row carries in double.
 #pragma once
 
 #include <string.h>

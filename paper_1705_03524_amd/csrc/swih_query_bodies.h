@@ -287,20 +287,23 @@ __device__ __forceinline__ float bc_value(int32_t q) { return (float)((double)q 
 // follow one another so that member m's boundary row is member m + 1's
 // opening row.  A wave walks a segment of S members of one comb and reads
 // each boundary row once, for the member it closes (bottom corners) and the
-// one it opens (top corners).  Row carries: the wave's right edges lie in at
-// most two tiles and its left edges in two more; for each, lanes 0..NT load
-// the carry of their x term (lane NT: the count) at each boundary row, and
-// the windows gather and contract them with alpha(xc) when a member closes.
+// one it opens (top corners).  Row carries: the wave's right edges lie in one
+// tile and its left edges in at most two (chunks start where right edges
+// begin a tile); lanes 21 s + i load term i (i = NT: the count) of edge tile
+// s's carries at each opening and boundary row, keep the member's carry box,
+// and pass it to every lane through the wave's LDS slots when the member
+// closes, where each window contracts its two tiles' boxes with alpha(xc).
 //
-// Work item = (bin group, segment, comb, chunk of cw windows, one wave per 64):
-// a wave loops over the group's bins and walks the segment for each, keeping
-// a row's loads in flight while the previous row is contracted, and adds the
-// bin's term sqrt(p_b t_b) to its (member, window) accumulator in LDS (each
-// lane its own entries).  With one bin group the map is stored once at the
-// end; with several, each group adds its sums into the set's integer
-// accumulator and match_gauss_fin writes the map.  Every split does the same
-// operations in the same order for every (window, bin), so maps agree bit for
-// bit.
+// Work item = (bin group, segment, comb group, chunk of cw windows; nt waves
+// of 64 windows per comb, cpb combs per block -- batches pack the combs of a
+// narrow job into one block): a wave loops over the group's bins and walks
+// the segment for each, keeping a row's loads in flight while the previous
+// row is contracted, and adds the bin's term sqrt(p_b t_b) to its (member,
+// window) accumulator in LDS (each lane its own entries).  With one bin group
+// the map is stored once at the end; with several, each group adds its sums
+// into the set's integer accumulator and match_gauss_fin writes the map.
+// Every split does the same operations in the same order for every (window,
+// bin), so maps agree bit for bit.
 enum : int { kEvOpen = 0, kEvCross = 1, kEvBound = 2, kEvEnd = 3 };
 
 struct SweepEv {
