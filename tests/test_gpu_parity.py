@@ -244,9 +244,10 @@ def test_gaussian_ragged(HW, nb, wh, kind):
 
 
 @pytest.mark.parametrize("kind", GAUSS_KINDS)
-@pytest.mark.parametrize("K", [4, 6])
+@pytest.mark.parametrize("K", [4, 6, 8])
 def test_gaussian_other_series_lengths(K, kind):
-    # K is a build parameter: longer series than the default (3) are just as exact
+    # K is a build parameter: longer series than the default (3), up to the
+    # maximum (8), are just as exact
     H, W = 65, 129
     img = synth.uniform_noise(17 + K, H, W)
     c = all_centres(H, W, 15, 21)
