@@ -588,7 +588,7 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
 //   RCB_i = sum_j beta_j(Y - ry - 1) RC_ij[Y],  RCT_i = sum_j beta_j(Y + ry) RC_ij[Y]
 // and the count RC_00[Y]: one run of 2 NT + 1 doubles per row (swih_rc).  The
 // count is exact: its increments are integers times 2^48.
-template <int NT>
+template <int NT, int WGT>
 __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) {
   const SwihGeom& g = a.g;
   const int64_t* __restrict__ E = (const int64_t*)a.T;
@@ -610,23 +610,43 @@ __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) 
   }
   const size_t ctp = (size_t)g.B * g.NTY * g.NTX;  // from one term's tile values to the next
   const double* __restrict__ ct = CTc + ((size_t)t.b * g.NTY + t.ty) * g.NTX + t.tx;
-  double* __restrict__ dst = RCp + swih_rc(g, 0, t.b, t.tx, y + 1);
+  // the tile-origin values, one term per lane (vector loads: the plane waves'
+  // row tables keep the scalar cache)
+  constexpr int NCT = (NT * NT + 63) / 64;
+  double ctv[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) {
+    const int q = c * 64 + lane;
+    ctv[c] = q < NT * NT ? ct[(size_t)q * ctp] : 0.0;
+  }
+  // the band's rows are one contiguous run of 64 nRC doubles in the carry array:
+  // staged in LDS ([row][q], the array's order) so that every store writes 512
+  // consecutive bytes.  The row-carry waves are the odd waves of a block.
+  constexpr int NRC = 2 * NT + 1;
+  __shared__ double stage[WGT / 128][64 * NRC];
+  double* __restrict__ st = stage[threadIdx.x >> 7] + lane * NRC;
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
     const double ei = row ? (double)E[((size_t)(i * g.B + t.b) * g.NTX + t.tx) * g.H + y] : 0.0;
     double sB = 0.0, sT = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const double r = (ct[(size_t)(i * NT + j) * ctp] + wave_incl_scan(vj[j] * ei)) * sc48;
+      const int q = i * NT + j;
+      const double r = (readlane(ctv[q >> 6], q & 63) + wave_incl_scan(vj[j] * ei)) * sc48;
       sB = fma(bB[j], r, sB);
       sT = fma(bT[j], r, sT);
-      if (i == 0 && j == 0 && row) dst[2 * NT] = r;
+      if (i == 0 && j == 0) st[2 * NT] = r;
     }
-    if (row) {
-      dst[i] = sB;
-      dst[NT + i] = sT;
-    }
+    st[i] = sB;
+    st[NT + i] = sT;
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const double* __restrict__ sw = stage[threadIdx.x >> 7];
+  double* __restrict__ dst = RCp + swih_rc(g, 0, t.b, t.tx, t.y0 + 1);
+  const int n = t.nrows * NRC;
+  for (int k = lane; k < n; k += 64) dst[k] = sw[k];
 }
 
 // Planes of one (band, tile, bin), rows top to bottom.  The tile-local sums
@@ -656,7 +676,7 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   int e;
   if (!wave_tile(g, wave_index<WGT / 64>(vb), 2, t, e)) return;
   if (e == 1) {
-    rc_gauss<NT>(a, t);
+    rc_gauss<NT, WGT>(a, t);
     return;
   }
   const int lane = lane_id();
