@@ -699,6 +699,20 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     for (int p = 0; p < 5; ++p) col[p * 64] = 0.0f;
   }
   const uint64_t mask = band_mask(img, ipitch, g.W, t.x, t.y0, t.nrows, g.B, t.b);
+  // the row's y terms and beta rows are loaded one row ahead (scalar loads issued
+  // as the previous row's values die, so they arrive during the row's scans)
+  double vr[NT], bb[NT], bt[NT];
+  auto row_terms = [&](int y) {
+    const double* vrow = vqd + (size_t)y * NT;
+    const double* brow = bet + (size_t)(y + 1) * 2 * NT;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      vr[j] = vrow[j];
+      bb[j] = brow[j];
+      bt[j] = brow[NT + j];
+    }
+  };
+  row_terms(t.y0);
   for (int k = 0; k < t.nrows; ++k) {
     const int y = t.y0 + k;
     const bool m = bit_of(mask, k) != 0;
@@ -713,22 +727,17 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     }
     // u_0 = 1 is 2^24 in fixed point: the row's count up to X, exactly
     cnt += r0 >> SWIH_FIX_BITS;
-    const double* vrow = vqd + (size_t)y * NT;
-    const double* brow = bet + (size_t)(y + 1) * 2 * NT;
-    double vr[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) vr[j] = vrow[j];
     double rb = 0.0, rt = 0.0, lb = 0.0, lt = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       vp[j] = fma(vr[j], sp, vp[j]);
       vm[j] = fma(vr[j], sm, vm[j]);
-      const double bb = brow[j], bt = brow[NT + j];
-      rb = fma(bb, vp[j], rb);
-      rt = fma(bt, vp[j], rt);
-      lb = fma(bb, vm[j], lb);
-      lt = fma(bt, vm[j], lt);
+      rb = fma(bb[j], vp[j], rb);
+      rt = fma(bt[j], vp[j], rt);
+      lb = fma(bb[j], vm[j], lb);
+      lt = fma(bt[j], vm[j], lt);
     }
+    row_terms(min(y + 1, g.H - 1));  // the last row reloads a row in range
     // whole 256-byte runs: lanes past the last column write values never read
     float* dst = col + (size_t)(y + 1) * g.row_stride;
     dst[0] = (float)rb;
