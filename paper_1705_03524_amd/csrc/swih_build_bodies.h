@@ -60,20 +60,23 @@ __device__ __forceinline__ bool in_bin(uint32_t v, int B, int b) {
 
 // Bit k = [pixel (x, y0 + k) falls in bin b] for the band's rows.  All the
 // band's pixel loads of a lane are issued together (row index clamped, so no
-// branch separates them) and masked afterwards.
+// branch separates them) and masked afterwards.  Each load addresses the
+// band's first row (wave-uniform) plus a 32-bit offset: the row's, uniform,
+// and the lane's column.
 __device__ __forceinline__ uint64_t band_mask(const uint8_t* __restrict__ img, int ipitch, int W,
                                               int x, int y0, int nrows, int B, int b) {
-  const uint8_t* col = img + (size_t)y0 * ipitch + (x < W ? x : W - 1);
+  const uint8_t* band = img + (size_t)y0 * ipitch;
+  const uint32_t xo = (uint32_t)(x < W ? x : W - 1);
   uint32_t lo = 0, hi = 0;
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int kk = k < nrows ? k : nrows - 1;
-    lo |= (uint32_t)in_bin(col[(size_t)kk * ipitch], B, b) << k;
+    lo |= (uint32_t)in_bin(band[(uint32_t)(kk * ipitch) + xo], B, b) << k;
   }
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int kk = k + 32 < nrows ? k + 32 : nrows - 1;
-    hi |= (uint32_t)in_bin(col[(size_t)kk * ipitch], B, b) << k;
+    hi |= (uint32_t)in_bin(band[(uint32_t)(kk * ipitch) + xo], B, b) << k;
   }
   uint64_t m = ((uint64_t)hi << 32) | lo;
   if (nrows < 64) m &= ((uint64_t)1 << nrows) - 1;
@@ -215,13 +218,15 @@ __device__ __forceinline__ void aggregate_int_hist(const BuildArgs& a, int vb) {
   unsigned char* tile = hist_lds;
   W* colh = (W*)(hist_lds + 64 * kHistRow);
   W* rowh = colh + B * 64;
-  // wave w loads rows 16 w .. 16 w + 15 of the band (clamped into the image)
-  const uint8_t* col = a.img + (size_t)y0 * a.ipitch + (x < g.W ? x : g.W - 1);
+  // wave w loads rows 16 w .. 16 w + 15 of the band (clamped into the image),
+  // each at the band's first row plus a 32-bit offset
+  const uint8_t* band = a.img + (size_t)y0 * a.ipitch;
+  const uint32_t xo = (uint32_t)(x < g.W ? x : g.W - 1);
   uint32_t v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int k = 16 * w + i;
-    v[i] = col[(size_t)(k < nrows ? k : nrows - 1) * a.ipitch];
+    v[i] = band[(uint32_t)((k < nrows ? k : nrows - 1) * a.ipitch) + xo];
   }
   __syncthreads();  // an earlier virtual block of this block is done with the counters
   {

@@ -150,8 +150,12 @@ __device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const E
   const bool valid = xm < g.W;
   const int xo = valid ? ((t.d & 1) ? g.W - 1 - xm : xm) : 0;
   const bool my = (t.d & 2) != 0;
-  const long step = my ? -(long)a.ipitch : (long)a.ipitch;
-  const uint8_t* col = a.img + (long)(my ? g.H - 1 - t.y0 : t.y0) * a.ipitch + xo;
+  // the band's rows in memory start at its lowest image row; mirrored row
+  // y0 + kk sits (nrows - 1 - kk) rows above it when rows are mirrored
+  const uint8_t* band = a.img + (long)(my ? g.H - t.y0 - t.nrows : t.y0) * a.ipitch;
+  auto row = [&](int kk) {
+    return (uint32_t)((my ? t.nrows - 1 - kk : kk) * a.ipitch) + (uint32_t)xo;
+  };
   // [Q(v) = b] exactly when ceil(256 b / B) <= v < ceil(256 (b + 1) / B)
   const uint32_t B = (uint32_t)g.B, b = (uint32_t)t.b;
   const uint32_t vlo = (256u * b + B - 1) / B, span = (256u * (b + 1) + B - 1) / B - vlo;
@@ -159,12 +163,12 @@ __device__ __forceinline__ uint64_t exp_band_mask(const ExpBuildArgs& a, const E
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int kk = k < t.nrows ? k : t.nrows - 1;
-    lo |= (uint32_t)((uint32_t)col[kk * step] - vlo < span) << k;
+    lo |= (uint32_t)((uint32_t)band[row(kk)] - vlo < span) << k;
   }
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int kk = k + 32 < t.nrows ? k + 32 : t.nrows - 1;
-    hi |= (uint32_t)((uint32_t)col[kk * step] - vlo < span) << k;
+    hi |= (uint32_t)((uint32_t)band[row(kk)] - vlo < span) << k;
   }
   uint64_t m = ((uint64_t)hi << 32) | lo;
   if (t.nrows < 64) m &= ((uint64_t)1 << t.nrows) - 1;
@@ -209,13 +213,15 @@ __device__ __forceinline__ void exp_aggregate_hist(const ExpBuildArgs& a, int vb
   const bool xok = xm < g.W;
   const int xo = xok ? ((d & 1) ? g.W - 1 - xm : xm) : 0;
   const bool my = (d & 2) != 0;
-  const long step = my ? -(long)a.ipitch : (long)a.ipitch;
-  const uint8_t* col = a.img + (long)(my ? g.H - 1 - y0 : y0) * a.ipitch + xo;
+  // the band's lowest image row plus a 32-bit offset per load (mirrored row
+  // y0 + kk sits nrows - 1 - kk rows above it when rows are mirrored)
+  const uint8_t* band = a.img + (long)(my ? g.H - y0 - nrows : y0) * a.ipitch;
   uint32_t v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int k = 16 * w + i;
-    v[i] = col[(long)(k < nrows ? k : nrows - 1) * step];
+    const int kk = k < nrows ? k : nrows - 1;
+    v[i] = band[(uint32_t)((my ? nrows - 1 - kk : kk) * a.ipitch) + (uint32_t)xo];
   }
   __syncthreads();  // an earlier virtual block of this block is done with LDS
   {
