@@ -54,7 +54,7 @@ hipError_t run_batch(const BuildArgs* units, const int32_t* prefix, int nunits, 
     hipLaunchKernelGGL(k_batch<ST::basis>, g(0), dim3(WG), 0, s, units, pre[0], nunits);
   hipLaunchKernelGGL(k_batch<ST::agg>, g(1), dim3(WG), ST::agg_lds(nbins), s, units, pre[1], nunits);
   hipLaunchKernelGGL(k_batch<ST::scan>, g(2), dim3(WG), 0, s, units, pre[2], nunits);
-  hipLaunchKernelGGL(k_batch<ST::emit>, g(3), dim3(WG), 0, s, units, pre[3], nunits);
+  hipLaunchKernelGGL(k_batch<ST::emit_batch>, g(3), dim3(WG), 0, s, units, pre[3], nunits);
   return hipGetLastError();
 }
 
@@ -84,6 +84,9 @@ hipError_t run_batch(const BuildArgs* units, const int32_t* prefix, int nunits, 
 // blocks up; below it the wave per (band, tile, bin) form keeps more of the
 // chip busy (512 x 512, 16 bins: 5.4 against 5.9 us).
 constexpr int kHistMinTiles = 128;
+// Gaussian plane sets from this size on are stored non-temporally (about the
+// device's last-level cache, 256 MB).
+constexpr int64_t kNtPlaneBytes = 256ll << 20;
 
 void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAxis* ay, int32_t rx,
                 int32_t ry, const uint8_t* img, int32_t img_pitch, char* ws, BuildArgs& a,
@@ -108,6 +111,11 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.ay = *ay;
     a.rx = rx;
     a.ry = ry;
+    // planes larger than the last-level cache stream to HBM past it: left in
+    // it, their write-back competes with the next launches' reads (batched
+    // builds keep plain stores: their emit has one loop)
+    const int64_t plane_bytes = (int64_t)g.nPL * g.B * g.NTX * (g.H + 1) * SWIH_TX * 4;
+    a.nt_planes = !batched && plane_bytes >= kNtPlaneBytes;
   }
   a.z = sb + L.off_z;
   a.T = sb + L.off_T;
