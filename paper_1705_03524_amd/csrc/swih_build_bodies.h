@@ -595,7 +595,8 @@ __device__ __forceinline__ void aggregate_gauss(const BuildArgs& a, int vb) {
 //   RCB_i = sum_j beta_j(Y - ry - 1) RC_ij[Y],  RCT_i = sum_j beta_j(Y + ry) RC_ij[Y]
 // and the count RC_00[Y]: one run of 2 NT + 1 doubles per row (swih_rc).  The
 // count is exact: its increments are integers times 2^48.
-template <int NT, int WGT>
+// NTS: non-temporal stores (large plane sets, as the planes).
+template <int NT, int WGT, bool NTS>
 __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) {
   const SwihGeom& g = a.g;
   const int64_t* __restrict__ E = (const int64_t*)a.T;
@@ -653,7 +654,12 @@ __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) 
   const double* __restrict__ sw = stage[threadIdx.x >> 7];
   double* __restrict__ dst = RCp + swih_rc(g, 0, t.b, t.tx, t.y0 + 1);
   const int n = t.nrows * NRC;
-  for (int k = lane; k < n; k += 64) dst[k] = sw[k];
+  for (int k = lane; k < n; k += 64) {
+    if constexpr (NTS)
+      __builtin_nontemporal_store(sw[k], dst + k);
+    else
+      dst[k] = sw[k];
+  }
 }
 
 // Planes of one (band, tile, bin), rows top to bottom.  The tile-local sums
@@ -684,7 +690,10 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   int e;
   if (!wave_tile(g, wave_index<WGT / 64>(vb), 2, t, e)) return;
   if (e == 1) {
-    rc_gauss<NT, WGT>(a, t);
+    if (NTOK && a.nt_planes)
+      rc_gauss<NT, WGT, NTOK>(a, t);
+    else
+      rc_gauss<NT, WGT, false>(a, t);
     return;
   }
   const int lane = lane_id();
