@@ -40,7 +40,12 @@ hipError_t run_single(const BuildArgs& a, const int32_t (&nb)[4], int phases, hi
                        s, a);
     hipLaunchKernelGGL(k_single<ST::scan>, dim3(nb[2]), dim3(WG), 0, s, a);
   }
-  if (phases & 2) hipLaunchKernelGGL(k_single<ST::emit>, dim3(nb[3]), dim3(WG), 0, s, a);
+  if (phases & 2) {
+    if (a.nt_planes)
+      hipLaunchKernelGGL(k_single<ST::emit_nt>, dim3(nb[3]), dim3(WG), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_single<ST::emit>, dim3(nb[3]), dim3(WG), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -111,12 +116,12 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.ay = *ay;
     a.rx = rx;
     a.ry = ry;
-    // planes larger than the last-level cache stream to HBM past it: left in
-    // it, their write-back competes with the next launches' reads (batched
-    // builds keep plain stores: their emit has one loop)
-    const int64_t plane_bytes = (int64_t)g.nPL * g.B * g.NTX * (g.H + 1) * SWIH_TX * 4;
-    a.nt_planes = !batched && plane_bytes >= kNtPlaneBytes;
   }
+  // planes larger than the last-level cache stream to HBM past it: left in it,
+  // their write-back competes with the next launches' reads (batched builds
+  // keep plain stores)
+  const int64_t plane_bytes = (int64_t)g.nPL * g.B * g.NTX * (g.H + 1) * SWIH_TX * 4;
+  a.nt_planes = !batched && plane_bytes >= kNtPlaneBytes;
   a.z = sb + L.off_z;
   a.T = sb + L.off_T;
   a.BT = sb + L.off_CT;

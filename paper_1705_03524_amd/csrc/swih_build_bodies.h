@@ -416,7 +416,8 @@ __device__ __forceinline__ void scan_carries(const BuildArgs& a, int vb) {
   }
 }
 
-template <int KIND>
+// NTS: non-temporal plane stores (plane sets from the last-level cache's size on).
+template <int KIND, bool NTS = false>
 __device__ __forceinline__ void emit_int(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
   const uint8_t* __restrict__ img = a.img;
@@ -464,7 +465,12 @@ __device__ __forceinline__ void emit_int(const BuildArgs& a, int vb) {
     for (int p = 0; p < TT::nP; ++p) acc[p] += poly_term(plane_j(p), y) * s[plane_i(p)];
     const size_t row = (size_t)(y + 1) * g.row_stride;
 #pragma unroll
-    for (int p = 0; p < TT::nP; ++p) planes[pbase[p] + row] = acc[p];
+    for (int p = 0; p < TT::nP; ++p) {
+      if constexpr (NTS)
+        __builtin_nontemporal_store(acc[p], planes + pbase[p] + row);
+      else
+        planes[pbase[p] + row] = acc[p];
+    }
   }
 }
 
@@ -802,6 +808,7 @@ template <int KIND> struct IntStages {
   static constexpr Body agg = aggregate_int<KIND>;
   static constexpr Body scan = scan_carries<uint32_t, uint32_t, uint32_t>;
   static constexpr Body emit = emit_int<KIND>;
+  static constexpr Body emit_nt = emit_int<KIND, true>;
   static constexpr Body emit_batch = emit_int<KIND>;
 };
 template <int NT> struct GaussStages {
@@ -809,7 +816,8 @@ template <int NT> struct GaussStages {
   static constexpr Body basis = ::swih::basis<>;
   static constexpr Body agg = aggregate_gauss<NT>;
   static constexpr Body scan = scan_carries<int64_t, int64_t, double>;
-  static constexpr Body emit = emit_gauss<NT, WG, true>;
+  static constexpr Body emit = emit_gauss<NT, WG, true>;  // chooses by a.nt_planes itself
+  static constexpr Body emit_nt = emit_gauss<NT, WG, true>;
   static constexpr Body emit_batch = emit_gauss<NT>;
 };
 

@@ -409,7 +409,9 @@ __device__ __forceinline__ void exp_scan(const ExpBuildArgs& a, int vb) {
 //   E(X, y + 1) = qy (E(X, y) + qx s_l + qx^(l + 1) C(y)),
 // s the leaky scan of the row's [Q = b] across the tile and C(y) the row value
 // at the tile's left edge.  Every lane stores, so a wave writes whole 256-byte
-// rows (lanes past the last column hold values never read).
+// rows (lanes past the last column hold values never read).  NTS: non-temporal
+// plane stores.
+template <bool NTS>
 __device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
   ExpTile t;
@@ -430,7 +432,11 @@ __device__ __forceinline__ void exp_emit(const ExpBuildArgs& a, int vb) {
     const double s = (double)leaky_scan((float)((uint32_t)(mask >> k) & 1u), Lx);
     const double R = fma(qx, s, pw * readlane(creg, k));
     e = qy * (e + R);
-    P[(long)(t.y0 + k + 1) * g.row_stride] = (float)e;
+    float* dst = P + (long)(t.y0 + k + 1) * g.row_stride;
+    if constexpr (NTS)
+      __builtin_nontemporal_store((float)e, dst);
+    else
+      *dst = (float)e;
   }
 }
 
@@ -654,7 +660,10 @@ void exp_match_args(const SwihLayout& L, const ExpScale& s, int set, const char*
 namespace {
 constexpr void (*agg_body)(const ExpBuildArgs&, int) = exp_aggregate;
 constexpr void (*scan_body)(const ExpBuildArgs&, int) = exp_scan;
-constexpr void (*emit_body)(const ExpBuildArgs&, int) = exp_emit;
+constexpr void (*emit_body)(const ExpBuildArgs&, int) = exp_emit<false>;
+// plane sets from about the last-level cache's size on: non-temporal stores
+constexpr void (*emit_body_nt)(const ExpBuildArgs&, int) = exp_emit<true>;
+constexpr int64_t kExpNtPlaneBytes = 256ll << 20;
 constexpr void (*query_body)(const ExpQueryArgs&, int) = exp_query;
 constexpr void (*match_body)(const ExpMatchArgs&, int) = exp_match;
 }  // namespace
@@ -666,7 +675,11 @@ hipError_t exp_launch_build(const ExpBuildArgs& a, const int32_t (&nb)[4], int p
     e = one<ExpBuildArgs, agg_body>(a, nb[1], s, a.agg_hist ? exp_hist_lds_bytes(a.g.B) : 0);
     if (e == hipSuccess) e = one<ExpBuildArgs, scan_body>(a, nb[2], s);
   }
-  if (e == hipSuccess && (phases & 2)) e = one<ExpBuildArgs, emit_body>(a, nb[3], s);
+  const SwihGeom& g = a.g;
+  const int64_t plane_bytes = (int64_t)g.nPL * g.B * g.NTX * (g.H + 1) * SWIH_TX * 4;
+  if (e == hipSuccess && (phases & 2))
+    e = plane_bytes >= kExpNtPlaneBytes ? one<ExpBuildArgs, emit_body_nt>(a, nb[3], s)
+                                        : one<ExpBuildArgs, emit_body>(a, nb[3], s);
   return e;
 }
 
