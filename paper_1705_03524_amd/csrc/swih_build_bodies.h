@@ -85,8 +85,6 @@ __device__ __forceinline__ uint64_t band_mask(const uint8_t* __restrict__ img, i
 
 __device__ __forceinline__ uint32_t bit_of(uint64_t m, int k) { return (uint32_t)(m >> k) & 1u; }
 
-template <bool B> struct BoolTag { static constexpr bool value = B; };
-
 struct WaveTile {
   int b, tx, ty, x, y0, nrows;
   bool valid;
@@ -681,9 +679,10 @@ __device__ __forceinline__ void rc_gauss(const BuildArgs& a, const WaveTile& t) 
 // and N, 5 floats per column where the terms would take NT^2.  A band's
 // closing row, which windows cross with any centre row, also keeps V+ and V-
 // (side array XC).  The launch interleaves one row-carry wave (rc_gauss)
-// after each plane wave.  NTOK: the launch may store the planes non-temporally
-// (a.nt_planes; single plane sets only, batches keep the one loop's registers).
-template <int NT, int WGT = WG, bool NTOK = false>
+// after each plane wave.  NTS: non-temporal stores of the planes, the row
+// carries and the band-closing rows (plane sets from the last-level cache's
+// size on).
+template <int NT, int WGT = WG, bool NTS = false>
 __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   const SwihGeom& g = a.g;
   const uint8_t* __restrict__ img = a.img;
@@ -696,10 +695,7 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
   int e;
   if (!wave_tile(g, wave_index<WGT / 64>(vb), 2, t, e)) return;
   if (e == 1) {
-    if (NTOK && a.nt_planes)
-      rc_gauss<NT, WGT, NTOK>(a, t);
-    else
-      rc_gauss<NT, WGT, false>(a, t);
+    rc_gauss<NT, WGT, NTS>(a, t);
     return;
   }
   const int lane = lane_id();
@@ -736,62 +732,59 @@ __device__ __forceinline__ void emit_gauss(const BuildArgs& a, int vb) {
     }
   };
   row_terms(t.y0);
-  // the row loop, with plain or non-temporal plane stores (one loop each: the
-  // two store forms differ only in their cache policy)
-  auto rows = [&](auto nts) {
-    for (int k = 0; k < t.nrows; ++k) {
-      const int y = t.y0 + k;
-      const bool m = bit_of(mask, k) != 0;
-      double sp = 0.0, sm = 0.0;
-      int32_t r0 = 0;
+  for (int k = 0; k < t.nrows; ++k) {
+    const int y = t.y0 + k;
+    const bool m = bit_of(mask, k) != 0;
+    double sp = 0.0, sm = 0.0;
+    int32_t r0 = 0;
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const int32_t R = wave_incl_scan(m ? uqi[i] : 0);
-        if (i == 0) r0 = R;
-        sp = fma(ap[i], (double)R, sp);
-        sm = fma(am[i], (double)R, sm);
-      }
-      // u_0 = 1 is 2^24 in fixed point: the row's count up to X, exactly
-      cnt += r0 >> SWIH_FIX_BITS;
-      double rb = 0.0, rt = 0.0, lb = 0.0, lt = 0.0;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        vp[j] = fma(vr[j], sp, vp[j]);
-        vm[j] = fma(vr[j], sm, vm[j]);
-        rb = fma(bb[j], vp[j], rb);
-        rt = fma(bt[j], vp[j], rt);
-        lb = fma(bb[j], vm[j], lb);
-        lt = fma(bt[j], vm[j], lt);
-      }
-      row_terms(min(y + 1, g.H - 1));  // the last row reloads a row in range
-      // whole 256-byte runs: lanes past the last column write values never read
-      float* dst = col + (size_t)(y + 1) * g.row_stride;
-      if constexpr (decltype(nts)::value) {
-        __builtin_nontemporal_store((float)rb, dst);
-        __builtin_nontemporal_store((float)rt, dst + 64);
-        __builtin_nontemporal_store((float)lb, dst + 128);
-        __builtin_nontemporal_store((float)lt, dst + 192);
-        __builtin_nontemporal_store((float)cnt, dst + 256);
-      } else {
-        dst[0] = (float)rb;
-        dst[64] = (float)rt;
-        dst[128] = (float)lb;
-        dst[192] = (float)lt;
-        dst[256] = (float)cnt;
-      }
+    for (int i = 0; i < NT; ++i) {
+      const int32_t R = wave_incl_scan(m ? uqi[i] : 0);
+      if (i == 0) r0 = R;
+      sp = fma(ap[i], (double)R, sp);
+      sm = fma(am[i], (double)R, sm);
     }
-  };
-  if (NTOK && a.nt_planes)
-    rows(BoolTag<NTOK>{});
-  else
-    rows(BoolTag<false>{});
+    // u_0 = 1 is 2^24 in fixed point: the row's count up to X, exactly
+    cnt += r0 >> SWIH_FIX_BITS;
+    double rb = 0.0, rt = 0.0, lb = 0.0, lt = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      vp[j] = fma(vr[j], sp, vp[j]);
+      vm[j] = fma(vr[j], sm, vm[j]);
+      rb = fma(bb[j], vp[j], rb);
+      rt = fma(bt[j], vp[j], rt);
+      lb = fma(bb[j], vm[j], lb);
+      lt = fma(bt[j], vm[j], lt);
+    }
+    row_terms(min(y + 1, g.H - 1));  // the last row reloads a row in range
+    // whole 256-byte runs: lanes past the last column write values never read
+    float* dst = col + (size_t)(y + 1) * g.row_stride;
+    if constexpr (NTS) {
+      __builtin_nontemporal_store((float)rb, dst);
+      __builtin_nontemporal_store((float)rt, dst + 64);
+      __builtin_nontemporal_store((float)lb, dst + 128);
+      __builtin_nontemporal_store((float)lt, dst + 192);
+      __builtin_nontemporal_store((float)cnt, dst + 256);
+    } else {
+      dst[0] = (float)rb;
+      dst[64] = (float)rt;
+      dst[128] = (float)lb;
+      dst[192] = (float)lt;
+      dst[256] = (float)cnt;
+    }
+  }
   const int Yl = t.y0 + t.nrows;  // the band's last stored row
   if ((Yl & (g.TY - 1)) == 0 && Yl < g.H) {
     float* xc = a.XC + swih_xc(g, 0, t.b, Yl, X);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      xc[j * 64] = (float)vp[j];
-      xc[(NT + j) * 64] = (float)vm[j];
+      if constexpr (NTS) {
+        __builtin_nontemporal_store((float)vp[j], xc + j * 64);
+        __builtin_nontemporal_store((float)vm[j], xc + (NT + j) * 64);
+      } else {
+        xc[j * 64] = (float)vp[j];
+        xc[(NT + j) * 64] = (float)vm[j];
+      }
     }
   }
 }
@@ -816,7 +809,7 @@ template <int NT> struct GaussStages {
   static constexpr Body basis = ::swih::basis<>;
   static constexpr Body agg = aggregate_gauss<NT>;
   static constexpr Body scan = scan_carries<int64_t, int64_t, double>;
-  static constexpr Body emit = emit_gauss<NT, WG, true>;  // chooses by a.nt_planes itself
+  static constexpr Body emit = emit_gauss<NT>;
   static constexpr Body emit_nt = emit_gauss<NT, WG, true>;
   static constexpr Body emit_batch = emit_gauss<NT>;
 };
