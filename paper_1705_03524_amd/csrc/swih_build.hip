@@ -118,10 +118,11 @@ void build_args(const SwihLayout& L, int set, const GaussAxis* ax, const GaussAx
     a.ry = ry;
   }
   // planes larger than the last-level cache stream to HBM past it: left in it,
-  // their write-back competes with the next launches' reads (batched builds
-  // keep plain stores)
+  // their write-back competes with the next launches' reads.  A single set's
+  // launch picks its emit by this; batched builds always stream (a batch is
+  // planned to fill the device's memory).
   const int64_t plane_bytes = (int64_t)g.nPL * g.B * g.NTX * (g.H + 1) * SWIH_TX * 4;
-  a.nt_planes = !batched && plane_bytes >= kNtPlaneBytes;
+  a.nt_planes = plane_bytes >= kNtPlaneBytes;
   a.z = sb + L.off_z;
   a.T = sb + L.off_T;
   a.BT = sb + L.off_CT;

@@ -802,7 +802,7 @@ template <int KIND> struct IntStages {
   static constexpr Body scan = scan_carries<uint32_t, uint32_t, uint32_t>;
   static constexpr Body emit = emit_int<KIND>;
   static constexpr Body emit_nt = emit_int<KIND, true>;
-  static constexpr Body emit_batch = emit_int<KIND>;
+  static constexpr Body emit_batch = emit_int<KIND, true>;
 };
 template <int NT> struct GaussStages {
   static int agg_lds(int) { return 0; }
@@ -811,7 +811,7 @@ template <int NT> struct GaussStages {
   static constexpr Body scan = scan_carries<int64_t, int64_t, double>;
   static constexpr Body emit = emit_gauss<NT>;
   static constexpr Body emit_nt = emit_gauss<NT, WG, true>;
-  static constexpr Body emit_batch = emit_gauss<NT>;
+  static constexpr Body emit_batch = emit_gauss<NT, WG, true>;
 };
 
 // The Gaussian stages with virtual blocks of WGT threads (a multiple of 256):

@@ -699,7 +699,8 @@ hipError_t exp_launch_build_batch(const ExpBuildArgs* units, const int32_t* pref
   hipError_t e = many<ExpBuildArgs, agg_body>(units, pre[1], nunits, total[1], grid, s,
                                               nbins <= kExpHistMaxB ? exp_hist_lds_bytes(nbins) : 0);
   if (e == hipSuccess) e = many<ExpBuildArgs, scan_body>(units, pre[2], nunits, total[2], grid, s);
-  if (e == hipSuccess) e = many<ExpBuildArgs, emit_body>(units, pre[3], nunits, total[3], grid, s);
+  // a batch streams its planes past the last-level cache, as large single sets do
+  if (e == hipSuccess) e = many<ExpBuildArgs, emit_body_nt>(units, pre[3], nunits, total[3], grid, s);
   return e;
 }
 

@@ -76,7 +76,7 @@ struct BuildArgs {
   int64_t nacc;
   int32_t agg_hist;   // integer kernels: aggregate by LDS histograms, a block per (band, tile)
   int32_t rx, ry;     // Gaussian: the set's window half-sizes (corner coefficients of the planes)
-  int32_t nt_planes;  // store the planes non-temporally (single sets of 256 MB and more)
+  int32_t nt_planes;  // single-set launch: store the planes non-temporally (256 MB and more)
   GaussAxis ax, ay;
 };
 
